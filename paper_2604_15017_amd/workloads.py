@@ -1,0 +1,270 @@
+"""Seeded synthetic workloads: scene, probe, transmit and pixel-grid descriptions.
+
+This module only *describes* inputs. It holds none of the method's arithmetic
+(no transport, no Fresnel, no pulse, no beamforming); both the HIP path and the
+FP64 oracle take their inputs from here, so it must stay free of either's code.
+
+Units everywhere: metres, seconds, hertz, m/s for sound speed, MRayl for
+acoustic impedance, dB/cm/MHz for attenuation, radians for angles.
+
+Parameter vector theta (flat float64), in this order:
+  regions  : (c, Z, alpha) for each region
+  planes   : depth z for each horizontal interface plane
+  spheres  : (cx, cy, cz, r) for each sphere
+The layout is what the C-ABI reports from scene upload as well.
+
+Workloads (Sec. 3 of the paper sets the problem; the sizes below are the
+synthetic phantoms the build is measured on):
+  two_layer()      : water over tissue, flat interface at 30 mm, 64 elements,
+                     one 0 deg plane wave, 2^14 rays per element, 4 bounces.
+  layered_phantom(): three drawn layers at 10/25/45 mm under a water slab,
+                     five drawn diffuse spherical inclusions, 128 elements,
+                     11 plane waves over [-10, 10] deg, 2^20 rays per transmit,
+                     8 bounces, 4096 samples, 256 x 512 pixels.
+  layered_phantom_target(): the same scene with 34 of its parameters moved by
+                     a seeded +-5 %, used as the reference image for the
+                     forward+backward workload.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+# stream tag used for drawing scene parameters (the ray streams use tag 0)
+SCENE_STREAM_TAG = 1
+TARGET_STREAM_TAG = 2
+
+
+@dataclasses.dataclass
+class Probe:
+    """Linear array at z = 0 facing +z (Sec. 2.3.1: aperture, N_e elements, pitch p)."""
+    n_elem: int
+    pitch: float
+    elem_width: float
+    elem_height: float
+    f0: float
+    n_cycles: float
+    fs: float
+    n_t: int
+    c_ref: float
+    alpha_main: float = math.radians(20.0)   # receive main-lobe angle (Eq. cutoff)
+    alpha_cut: float = math.radians(60.0)    # receive cutoff angle (Eq. cutoff)
+
+
+@dataclasses.dataclass
+class Scene:
+    """Regions of homogeneous media bounded by planes z = d and spheres."""
+    regions: np.ndarray          # (R, 3) float64: c [m/s], Z [MRayl], alpha [dB/cm/MHz]
+    planes: np.ndarray           # (Pl,) float64 depth [m]
+    plane_regions: np.ndarray    # (Pl, 2) int32: region above (smaller z), region below
+    plane_kd: np.ndarray         # (Pl,) float64 diffuse fraction of reflected energy
+    spheres: np.ndarray          # (S, 4) float64: cx, cy, cz, r [m]
+    sphere_regions: np.ndarray   # (S, 2) int32: region inside, region outside
+    sphere_kd: np.ndarray        # (S,) float64
+    start_region: int = 0        # region just below the array face
+
+    @property
+    def n_regions(self) -> int:
+        return int(self.regions.shape[0])
+
+    @property
+    def n_planes(self) -> int:
+        return int(self.planes.shape[0])
+
+    @property
+    def n_spheres(self) -> int:
+        return int(self.spheres.shape[0])
+
+    @property
+    def n_params(self) -> int:
+        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres
+
+    def theta(self) -> np.ndarray:
+        return np.concatenate([self.regions.reshape(-1), self.planes.reshape(-1),
+                               self.spheres.reshape(-1)]).astype(np.float64)
+
+    def with_theta(self, theta: np.ndarray) -> "Scene":
+        theta = np.asarray(theta, dtype=np.float64)
+        assert theta.shape == (self.n_params,)
+        r, p, s = self.n_regions, self.n_planes, self.n_spheres
+        return dataclasses.replace(
+            self,
+            regions=theta[:3 * r].reshape(r, 3).copy(),
+            planes=theta[3 * r:3 * r + p].copy(),
+            spheres=theta[3 * r + p:].reshape(s, 4).copy())
+
+    # index helpers for the flat parameter vector
+    def idx_region(self, k: int, which: str) -> int:
+        return 3 * k + {"c": 0, "Z": 1, "alpha": 2}[which]
+
+    def idx_plane(self, k: int) -> int:
+        return 3 * self.n_regions + k
+
+    def idx_sphere(self, k: int, which: str) -> int:
+        return 3 * self.n_regions + self.n_planes + 4 * k + {"x": 0, "y": 1, "z": 2, "r": 3}[which]
+
+
+@dataclasses.dataclass
+class Grid:
+    """Pixel centres x_a = x0 + a*dx, z_b = z0 + b*dz; images are [n_x][n_z]."""
+    n_x: int
+    n_z: int
+    x0: float
+    dx: float
+    z0: float
+    dz: float
+
+    @staticmethod
+    def span(n_x: int, n_z: int, x_min: float, x_max: float, z_min: float, z_max: float) -> "Grid":
+        dx = (x_max - x_min) / n_x
+        dz = (z_max - z_min) / n_z
+        return Grid(n_x, n_z, x_min + 0.5 * dx, dx, z_min + 0.5 * dz, dz)
+
+    @property
+    def n_px(self) -> int:
+        return self.n_x * self.n_z
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    scene: Scene
+    probe: Probe
+    angles: np.ndarray            # (n_tx,) steering angles [rad]
+    tx_ids: np.ndarray            # (n_tx,) uint32 ids used in the ray counters
+    grid: Grid
+    seed: int
+    rays_per_elem: int
+    max_bounces: int
+    dr_db: float = 60.0
+
+    @property
+    def n_tx(self) -> int:
+        return int(self.angles.shape[0])
+
+    @property
+    def rays_per_tx(self) -> int:
+        return self.probe.n_elem * self.rays_per_elem
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def _water():
+    return [1480.0, 1.48, 0.0]
+
+
+def two_layer(rays_per_elem: int = 1 << 14) -> Workload:
+    """Water (1480 m/s, 1.48 MRayl) over tissue (1540 m/s, 1.63 MRayl, 0.5 dB/cm/MHz)."""
+    scene = Scene(
+        regions=np.array([_water(), [1540.0, 1.63, 0.5]], dtype=np.float64),
+        planes=np.array([30e-3]),
+        plane_regions=np.array([[0, 1]], dtype=np.int32),
+        plane_kd=np.array([0.0]),
+        spheres=np.zeros((0, 4)),
+        sphere_regions=np.zeros((0, 2), dtype=np.int32),
+        sphere_kd=np.zeros((0,)),
+    )
+    probe = Probe(n_elem=64, pitch=0.3e-3, elem_width=0.3e-3, elem_height=5e-3, f0=5e6,
+                  n_cycles=2.0, fs=40e6, n_t=2048, c_ref=1480.0)
+    grid = Grid.span(128, 256, -19.2e-3, 19.2e-3, 0.0, 40e-3)
+    return Workload("two_layer", scene, probe, np.array([0.0]), np.array([0], dtype=np.uint32),
+                    grid, seed=0, rays_per_elem=rays_per_elem, max_bounces=4)
+
+
+def _layered_scene(seed: int) -> Scene:
+    rng = np.random.Generator(np.random.Philox(key=[seed, SCENE_STREAM_TAG]))
+    depths = [10e-3, 25e-3, 45e-3]
+    layer_span = [(10e-3, 25e-3), (25e-3, 45e-3), (45e-3, 58e-3)]
+
+    def draw_medium():
+        return [rng.uniform(1450.0, 1600.0), rng.uniform(1.3, 1.8), rng.uniform(0.3, 1.0)]
+
+    regions = [_water()] + [draw_medium() for _ in range(3)]
+    spheres, sph_regions = [], []
+    while len(spheres) < 5:
+        r = rng.uniform(2e-3, 6e-3)
+        layer = int(rng.integers(0, 3))
+        lo, hi = layer_span[layer]
+        lo, hi = lo + r + 0.5e-3, hi - r - 0.5e-3
+        if hi <= lo:
+            continue
+        cx, cz = rng.uniform(-15e-3, 15e-3), rng.uniform(lo, hi)
+        if any(math.hypot(cx - s[0], cz - s[2]) < r + s[3] + 0.5e-3 for s in spheres):
+            continue
+        spheres.append([cx, 0.0, cz, r])
+        sph_regions.append([4 + len(sph_regions), 1 + layer])
+        regions.append(draw_medium())
+    return Scene(
+        regions=np.array(regions, dtype=np.float64),
+        planes=np.array(depths),
+        plane_regions=np.array([[0, 1], [1, 2], [2, 3]], dtype=np.int32),
+        plane_kd=np.zeros(3),
+        spheres=np.array(spheres, dtype=np.float64),
+        sphere_regions=np.array(sph_regions, dtype=np.int32),
+        sphere_kd=np.full(5, 0.2),
+    )
+
+
+def layered_probe() -> Probe:
+    return Probe(n_elem=128, pitch=0.3e-3, elem_width=0.3e-3, elem_height=5e-3, f0=5e6,
+                 n_cycles=2.0, fs=40e6, n_t=4096, c_ref=1540.0)
+
+
+def layered_phantom(seed: int = 1, rays_per_tx: int = 1 << 20, n_tx: int = 11) -> Workload:
+    probe = layered_probe()
+    angles = np.radians(np.linspace(-10.0, 10.0, n_tx))
+    grid = Grid.span(256, 512, -19.2e-3, 19.2e-3, 0.0, 60e-3)
+    return Workload("layered_phantom", _layered_scene(seed), probe, angles,
+                    np.arange(n_tx, dtype=np.uint32), grid, seed=0,
+                    rays_per_elem=rays_per_tx // probe.n_elem, max_bounces=8)
+
+
+def perturbed_indices(scene: Scene) -> List[int]:
+    """The 34 perturbed parameters: (c, Z, alpha) of every non-water region, then
+    every sphere's depth and radius."""
+    idx = [scene.idx_region(k, w) for k in range(1, scene.n_regions) for w in ("c", "Z", "alpha")]
+    idx += [scene.idx_sphere(k, "z") for k in range(scene.n_spheres)]
+    idx += [scene.idx_sphere(k, "r") for k in range(scene.n_spheres)]
+    return idx
+
+
+def layered_phantom_target(wl: Workload, seed: int = 1) -> Scene:
+    """theta_target_j = theta_j * (1 + 0.05 (2u_j - 1)) on the perturbed set; redrawn
+    if a sphere would leave its layer or touch another sphere."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, TARGET_STREAM_TAG]))
+    sc = wl.scene
+    theta0 = sc.theta()
+    idx = perturbed_indices(sc)
+    bounds = {1: (10e-3, 25e-3), 2: (25e-3, 45e-3), 3: (45e-3, 58e-3)}
+    while True:
+        theta = theta0.copy()
+        theta[idx] *= 1.0 + 0.05 * (2.0 * rng.random(len(idx)) - 1.0)
+        cand = sc.with_theta(theta)
+        ok = True
+        for k in range(cand.n_spheres):
+            cx, _, cz, r = cand.spheres[k]
+            lo, hi = bounds[int(cand.sphere_regions[k, 1])]
+            if cz - r < lo + 0.25e-3 or cz + r > hi - 0.25e-3:
+                ok = False
+            for j in range(k):
+                d = math.hypot(cx - cand.spheres[j, 0], cz - cand.spheres[j, 2])
+                if d < r + cand.spheres[j, 3] + 0.25e-3:
+                    ok = False
+        if ok:
+            return cand
+
+
+def tiny(workload: Workload, rays_per_elem: int, n_elem: Optional[int] = None,
+         n_t: Optional[int] = None, grid: Optional[Grid] = None) -> Workload:
+    """A reduced copy of a workload (fewer rays/elements/samples) for fast parity runs."""
+    probe = workload.probe
+    if n_elem is not None:
+        probe = dataclasses.replace(probe, n_elem=n_elem)
+    if n_t is not None:
+        probe = dataclasses.replace(probe, n_t=n_t)
+    return workload.replace(probe=probe, rays_per_elem=rays_per_elem,
+                            grid=grid if grid is not None else workload.grid)
