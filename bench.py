@@ -1,0 +1,167 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one B-mode frame of the layered phantom (11 plane waves x 2^20
+rays, 8 interactions, 128 elements x 4096 samples, 256 x 512 pixels): transport
+and RF synthesis, beamforming, envelope and log compression, all through the
+C-ABI with inputs and buffers resident in HBM. Prints one JSON line with the
+throughput in ray-segments/s (a segment is one closest-hit query, primary or
+secondary), frames/s, per-kernel timings from HIP events recorded on the
+launch stream inside the timed region, the roofline of the dominant kernel and
+the FP64 oracle timed on the host cores as a reported baseline.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6    # MI355X vector fp64
+
+
+def kernel_bytes(name, wl, counts, n_px):
+    """Algorithmic HBM bytes of one frame for each kernel (what it must read
+    and write at least once), from the frame's event counts."""
+    p = wl.probe
+    rays = wl.n_tx * wl.rays_per_tx
+    seg_p, seg_s, dep, inter, sec = counts
+    row_samples = wl.n_tx * p.n_elem * p.n_t
+    state = 8 * 8 + 2 * 4          # ray state in the queue [B]
+    sec_rec = 5 * 8 + 3 * 4        # secondary-ray record [B]
+    return {
+        # every primary segment after the first reads a queued state, every
+        # surviving ray writes one, every diffuse hit writes a secondary record
+        "bounce": 2 * state * (seg_p - rays) + sec_rec * sec,
+        # each secondary record is read once; each deposit updates two fp32 bins
+        "secondary": sec_rec * sec + 8 * dep,
+        "pulse": 8 * row_samples,
+        "analytic": 12 * row_samples,
+        "das": 8 * row_samples + 8 * n_px,
+        "bmode": 20 * n_px,
+    }.get(name)
+
+
+def cpu_baseline(wl):
+    """The FP64 oracle on the host: the whole frame's transport (all rays)."""
+    import numpy as np
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    tr = oracle.trace(wl.scene, wl.probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                      wl.max_bounces, n_threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": tr.segments / dt, "unit": "ray-segments/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"full frame transport, {wl.n_tx} x {wl.rays_per_tx} rays, FP64, "
+                      f"{tr.segments} segments in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2604_15017_amd import _lib as L
+    from paper_2604_15017_amd import workloads as W
+
+    wl = W.layered_phantom()
+    p, g = wl.probe, wl.grid
+    ctx = L.Context(0)
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    dev = ctx.torch_device
+    rf = torch.empty((wl.n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=dev)
+    iq = torch.empty((g.n_x, g.n_z, 2), dtype=torch.float32, device=dev)
+    bm = torch.empty((g.n_x, g.n_z), dtype=torch.float32, device=dev)
+    ws_t = L._workspace(L.us_simulate_rf_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx,
+                                                        wl.max_bounces), dev)
+    ws_b = L._workspace(L.load().us_beamform_workspace_size(probe.handle, wl.n_tx), dev)
+    ws_m = L._workspace(L.load().us_bmode_workspace_size(g.n_px), dev)
+    counters = torch.zeros(5, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(cnt=None):
+        L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                         wl.max_bounces, rf=rf, counters=cnt, workspace=ws_t, stream=stream)
+        L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf, iq=iq, workspace=ws_b, stream=stream)
+        L.us_bmode(ctx, iq, wl.dr_db, out=bm, workspace=ws_m, stream=stream)
+
+    step(counters)                      # event counts of one frame (deterministic)
+    torch.cuda.synchronize()
+    counts = [int(v) for v in counters.cpu().numpy()]
+    segments = counts[0] + counts[1]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    L.us_profile_enable(ctx, True)
+    L.us_profile_read(ctx)              # clear
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        step()
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    prof = L.us_profile_read(ctx)
+    L.us_profile_enable(ctx, False)
+
+    ms_per_step = total_ms / args.steps
+    kernels = {}
+    for name, (ms, launches) in prof.items():
+        per_step_ms = ms / args.steps
+        nbytes = kernel_bytes(name, wl, counts, g.n_px)
+        kernels[name] = {"ms_per_step": round(per_step_ms, 4), "launches_per_step": launches // args.steps,
+                         "avg_launch_us": round(1e3 * ms / launches, 2),
+                         "algorithmic_GBps": round(nbytes / (per_step_ms * 1e-3) / 1e9, 1) if nbytes else None}
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms = prof[dom][0] / args.steps
+    dom_bytes = kernel_bytes(dom, wl, counts, g.n_px)
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    launches = prof[dom][1] // args.steps
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(dom_bytes / max(1, launches)),
+                "avg_launch_us": round(1e3 * dom_ms / max(1, launches), 2)}
+
+    out = {
+        "metric": "ray-segments/s and B-mode frames/s (fwd)",
+        "value": segments / (ms_per_step * 1e-3),
+        "unit": "ray-segments/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 transport + f32 image chain",
+        "data": "synthetic",
+        "config": {"workload": "layered_phantom", "n_tx": wl.n_tx, "rays_per_tx": wl.rays_per_tx,
+                   "max_bounces": wl.max_bounces, "n_elem": p.n_elem, "n_t": p.n_t,
+                   "grid": [g.n_x, g.n_z], "pass": "forward"},
+        "frames_per_s": round(1e3 / ms_per_step, 2),
+        "segments_per_frame": segments,
+        "frame_counts": {"primary_segments": counts[0], "secondary_segments": counts[1],
+                         "deposits": counts[2], "interactions": counts[3], "secondary_rays": counts[4]},
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * usrt.h — C-ABI of the MI355X (gfx950) library for differentiable full-path
+ * Monte-Carlo ultrasound ray tracing ("Fully Differentiable Ultrasound
+ * Simulation Utilizing Ray-Tracing", arXiv 2604.15017).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: 0 (US_OK) on success, a negative US_E* code otherwise; the
+ *    message of the last failure on the calling thread is us_last_error().
+ *    Argument errors are detected on the host before anything is launched.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as a
+ *    plain pointer; NULL = the device's null stream). Device faults surface on
+ *    a later call or on stream synchronisation.
+ *  - Pointers named *_dev are device memory owned by the caller; the library
+ *    never frees them. Descriptors and host arrays are read during the call
+ *    only. Handles (us_ctx, us_probe, us_scene) are owned by the library until
+ *    their destroy call; they hold resident device copies of what was uploaded.
+ *  - Scratch: every compute entry point takes a caller-allocated device
+ *    workspace `ws_dev` of `ws_bytes`, whose required size the matching
+ *    *_workspace_size() call returns; the library allocates nothing during
+ *    compute calls. Calls sharing a workspace must be ordered on one stream.
+ *  - Units: metres, seconds, hertz, m/s, MRayl, dB/cm/MHz, radians.
+ *  - Layouts (row-major, last index fastest):
+ *      rf        float  [n_tx][n_elem][n_t]
+ *      iq        float  [n_x][n_z][2]  (real, imaginary)
+ *      bmode     float  [n_x][n_z]     (dB, in [-dr_db, 0])
+ *      theta     double [n_params]: (c, Z, alpha) per region, then plane
+ *                depths, then (cx, cy, cz, r) per sphere
+ */
+#ifndef USRT_H
+#define USRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  US_OK = 0,
+  US_EINVAL = -1,   /* bad argument (sizes, layout, pointers) */
+  US_ENOMEM = -2,   /* device allocation failed (handle creation only) */
+  US_EDEVICE = -3,  /* a HIP runtime call failed */
+  US_ETOOBIG = -4,  /* workspace smaller than required */
+};
+
+typedef struct us_ctx us_ctx;
+typedef struct us_probe us_probe;
+typedef struct us_scene us_scene;
+
+/* Linear array on z = 0 facing +z (Sec. 2.3.1): element e centred at
+ * x_e = (e - (n_elem - 1)/2) pitch; receive directivity of Eq. cutoff with
+ * main-lobe angle alpha_main and cutoff alpha_cut; pulse of Eq. axial_sig at
+ * f0 with an envelope n_cycles / f0 wide at half maximum; n_t samples at fs;
+ * c_ref is the sound speed of the steering and beamforming delays. */
+typedef struct us_probe_desc {
+  int32_t n_elem;
+  double pitch, elem_width, elem_height;
+  double f0, n_cycles, fs;
+  int32_t n_t;
+  double c_ref, alpha_main, alpha_cut;
+} us_probe_desc;
+
+/* Scene of homogeneous regions bounded by planes z = d and spheres
+ * (Sec. 2.3.2). theta holds the continuous parameters (layout above);
+ * plane_regions[k] = {region above, region below}; sphere_regions[k] =
+ * {inside, outside}; kd = fraction of the reflected energy scattered into the
+ * Lambertian lobe; start_region = region at the array face. Host arrays. */
+typedef struct us_scene_desc {
+  int32_t n_regions, n_planes, n_spheres;
+  const double* theta;
+  const int32_t* plane_regions;
+  const double* plane_kd;
+  const int32_t* sphere_regions;
+  const double* sphere_kd;
+  int32_t start_region;
+} us_scene_desc;
+
+/* One plane-wave transmit: steering angle and the id that seeds its rays. */
+typedef struct us_tx_desc {
+  double angle;
+  uint32_t id;
+} us_tx_desc;
+
+/* Pixel centres x_a = x0 + a dx, z_b = z0 + b dz (z > 0 below the array). */
+typedef struct us_grid_desc {
+  int32_t n_x, n_z;
+  double x0, dx, z0, dz;
+} us_grid_desc;
+
+/* Last error message of the calling thread ("" if none). */
+const char* us_last_error(void);
+
+/* Context bound to one HIP device. */
+int us_create(int device, us_ctx** out);
+int us_destroy(us_ctx* ctx);
+
+/* Uploads a probe (resident pulse taps and FFT twiddles). */
+int us_probe_upload(us_ctx* ctx, const us_probe_desc* desc, us_probe** out);
+int us_probe_destroy(us_probe* probe);
+
+/* Uploads a scene; *n_params receives the length of theta. */
+int us_scene_upload(us_ctx* ctx, const us_scene_desc* desc, us_scene** out, int32_t* n_params);
+int us_scene_destroy(us_scene* scene);
+/* Replaces the scene's resident theta with n_params doubles from device
+ * memory theta_dev (asynchronous copy on stream). */
+int us_scene_set_params(us_scene* scene, const double* theta_dev, int32_t n_params, void* stream);
+
+/* Forward transport, Sec. 2.3 (emission, traversal with Snell reflection /
+ * refraction / Lambertian backscatter, attenuation, receiver-directed
+ * secondary rays, time-of-flight deposit with a linear tent, Eq. axial_sig
+ * pulse filter). Traces rays [ray_begin, ray_begin + ray_count) of each of
+ * the n_tx transmits (ray id = element * rays_per_elem + j, Philox4x64-10
+ * counter (ray id, tx.id, event, 0), key (seed, 0)); each ray has weight
+ * 1/rays_per_elem so disjoint ray ranges add up.
+ *   rf_dev        out: float [n_tx][n_elem][n_t] (overwritten)
+ *   counters_dev  optional (NULL): int64 [5], accumulated: primary segments,
+ *                 secondary-ray segments, deposits, interactions, secondary
+ *                 rays traced (a segment is one closest-hit query)
+ *   ray_hash_dev  optional (NULL): uint64 [n_tx][ray_count], overwritten with
+ *                 each ray's decision hash (sum over its events of SplitMix64
+ *                 of (tag, event, word)), for auditing branch agreement
+ *   max_bounces   at most this many interactions per path (>= 0) */
+size_t us_simulate_rf_workspace_size(const us_scene* scene, const us_probe* probe, int32_t n_tx,
+                                     int64_t ray_count, int32_t max_bounces);
+int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
+                   const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                   int64_t ray_begin, int64_t ray_count, int32_t max_bounces, float* rf_dev,
+                   int64_t* counters_dev, uint64_t* ray_hash_dev, void* ws_dev, size_t ws_bytes,
+                   void* stream);
+
+/* Plane-wave delay-and-sum, Eq. das: analytic signal of each RF channel along
+ * time (demodulation, Sec. 2.3.4), then I(x, z) = sum over transmits and
+ * elements of the linearly interpolated analytic sample at
+ * fs (x sin th + z cos th + |(x, z) - (x_e, 0)|) / c_ref, unit weights,
+ * samples outside [0, n_t) read as zero. n_t must be a power of two in
+ * [64, 8192].
+ *   rf_dev in: float [n_tx][n_elem][n_t]; iq_dev out: float [n_x][n_z][2] */
+size_t us_beamform_workspace_size(const us_probe* probe, int32_t n_tx);
+int us_beamform(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
+                const us_tx_desc* tx, int32_t n_tx, const float* rf_dev, float* iq_dev,
+                void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Envelope and log compression (Sec. 2.3.4, Sec. 3.1):
+ * bmode = max(20 log10(|iq| / max|iq|), -dr_db). */
+size_t us_bmode_workspace_size(int64_t n_px);
+int us_bmode(us_ctx* ctx, const float* iq_dev, int64_t n_px, float dr_db, float* bmode_dev,
+             void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian products (Sec. 3.2-3.3). */
+/* g_iq = (d bmode / d iq)^T g_bmode, including the normalisation by the
+ * frame maximum (first largest pixel); clipped pixels contribute nothing.
+ *   g_iq_dev out: float [n_x][n_z][2] (d/dRe, d/dIm) */
+int us_bmode_vjp(us_ctx* ctx, const float* iq_dev, const float* g_bmode_dev, int64_t n_px,
+                 float dr_db, float* g_iq_dev, void* ws_dev, size_t ws_bytes, void* stream);
+/* g_rf = adjoint of us_beamform (Eq. das_adjoint, then the self-adjoint
+ * analytic-signal map, real part). Computed per RF sample as a gather over
+ * the pixels that interpolate from it; no atomics.
+ *   g_iq_dev in: float [n_x][n_z][2]; g_rf_dev out: float [n_tx][n_elem][n_t] */
+size_t us_beamform_vjp_workspace_size(const us_probe* probe, int32_t n_tx);
+int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
+                    const us_tx_desc* tx, int32_t n_tx, const float* g_iq_dev, float* g_rf_dev,
+                    void* ws_dev, size_t ws_bytes, void* stream);
+/* g_theta += (d rf / d theta)^T g_rf at fixed ray realizations (Sec. 3.2,
+ * Eq. chain_rule): the paths of the same rays as us_simulate_rf are replayed
+ * from their Philox counters (nothing stored between the calls); discrete
+ * choices are frozen and branch probabilities are not differentiated.
+ *   g_rf_dev in: float [n_tx][n_elem][n_t]; g_theta_dev in/out: double [n_params] */
+size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* probe,
+                                         int32_t n_tx, int64_t ray_count, int32_t max_bounces);
+int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
+                       const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                       int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
+                       const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
+                       void* stream);
+
+/* Kernel timing for measurement. While enabled on a context, every kernel the
+ * library launches for that context is bracketed by a pair of HIP events
+ * recorded on the kernel's own stream. us_profile_read waits for the pending
+ * events and returns, per kernel name, the summed duration in milliseconds and
+ * the launch count, then clears the totals. names: caller buffer of
+ * max_kernels * 32 chars (NUL-terminated names); *n_kernels receives the count
+ * (kernels beyond max_kernels are dropped). Not thread-safe per context. */
+int us_profile_enable(us_ctx* ctx, int enable);
+int us_profile_read(us_ctx* ctx, int32_t max_kernels, char* names, double* total_ms,
+                    int64_t* launches, int32_t* n_kernels);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* USRT_H */

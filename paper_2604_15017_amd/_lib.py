@@ -1,0 +1,334 @@
+"""ctypes binding of libusrt.so (include/usrt.h), same names as the C-ABI.
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+the library. PyTorch provides device memory (outputs and workspaces) and
+streams. If the library is not built, every call raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libusrt.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "usrt.h")
+
+US_OK, US_EINVAL, US_ENOMEM, US_EDEVICE, US_ETOOBIG = 0, -1, -2, -3, -4
+
+
+class USError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class us_probe_desc(ctypes.Structure):
+    _fields_ = [("n_elem", ctypes.c_int32), ("pitch", ctypes.c_double),
+                ("elem_width", ctypes.c_double), ("elem_height", ctypes.c_double),
+                ("f0", ctypes.c_double), ("n_cycles", ctypes.c_double), ("fs", ctypes.c_double),
+                ("n_t", ctypes.c_int32), ("c_ref", ctypes.c_double),
+                ("alpha_main", ctypes.c_double), ("alpha_cut", ctypes.c_double)]
+
+
+class us_scene_desc(ctypes.Structure):
+    _fields_ = [("n_regions", ctypes.c_int32), ("n_planes", ctypes.c_int32),
+                ("n_spheres", ctypes.c_int32), ("theta", ctypes.c_void_p),
+                ("plane_regions", ctypes.c_void_p), ("plane_kd", ctypes.c_void_p),
+                ("sphere_regions", ctypes.c_void_p), ("sphere_kd", ctypes.c_void_p),
+                ("start_region", ctypes.c_int32)]
+
+
+class us_tx_desc(ctypes.Structure):
+    _fields_ = [("angle", ctypes.c_double), ("id", ctypes.c_uint32)]
+
+
+class us_grid_desc(ctypes.Structure):
+    _fields_ = [("n_x", ctypes.c_int32), ("n_z", ctypes.c_int32), ("x0", ctypes.c_double),
+                ("dx", ctypes.c_double), ("z0", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+_lib = None
+vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+
+_SIGNATURES = {
+    "us_last_error": (ctypes.c_char_p, []),
+    "us_create": (ctypes.c_int, [ctypes.c_int, vp]),
+    "us_destroy": (ctypes.c_int, [vp]),
+    "us_probe_upload": (ctypes.c_int, [vp, vp, vp]),
+    "us_probe_destroy": (ctypes.c_int, [vp]),
+    "us_scene_upload": (ctypes.c_int, [vp, vp, vp, vp]),
+    "us_scene_destroy": (ctypes.c_int, [vp]),
+    "us_scene_set_params": (ctypes.c_int, [vp, vp, i32, vp]),
+    "us_simulate_rf_workspace_size": (sz, [vp, vp, i32, i64, i32]),
+    "us_simulate_rf": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp, vp,
+                                      vp, sz, vp]),
+    "us_beamform_workspace_size": (sz, [vp, i32]),
+    "us_beamform": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
+    "us_bmode_workspace_size": (sz, [i64]),
+    "us_bmode": (ctypes.c_int, [vp, vp, i64, ctypes.c_float, vp, vp, sz, vp]),
+    "us_bmode_vjp": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_float, vp, vp, sz, vp]),
+    "us_beamform_vjp_workspace_size": (sz, [vp, i32]),
+    "us_beamform_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
+    "us_simulate_rf_vjp_workspace_size": (sz, [vp, vp, i32, i64, i32]),
+    "us_simulate_rf_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
+                                          vp, sz, vp]),
+    "us_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
+    "us_profile_read": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
+}
+
+
+def header_symbols():
+    """Function names declared in include/usrt.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(us_[a-z_]+)\s*\(", text)) - {"us_probe_desc", "us_scene_desc"})
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, name: str):
+    if rc != US_OK:
+        msg = load().us_last_error().decode()
+        raise USError(rc, f"{name}: {msg}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a visible GPU")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _tx_array(angles, tx_ids):
+    angles = np.asarray(angles, dtype=np.float64).reshape(-1)
+    ids = np.asarray(tx_ids if tx_ids is not None else np.arange(len(angles)), dtype=np.uint32)
+    arr = (us_tx_desc * len(angles))()
+    for i, (a, k) in enumerate(zip(angles, ids)):
+        arr[i].angle = float(a)
+        arr[i].id = int(k)
+    return arr, len(angles)
+
+
+class Context:
+    """us_create / us_destroy."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(load().us_create(device, ctypes.byref(h)), "us_create")
+        self.handle, self.device = h, device
+        self.torch_device = _torch().device("cuda", device)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.us_destroy(self.handle)
+            self.handle = None
+
+
+class Probe:
+    """us_probe_upload of a workloads.Probe-like object."""
+
+    def __init__(self, ctx: Context, p):
+        d = us_probe_desc(int(p.n_elem), float(p.pitch), float(p.elem_width),
+                          float(p.elem_height), float(p.f0), float(p.n_cycles), float(p.fs),
+                          int(p.n_t), float(p.c_ref), float(p.alpha_main), float(p.alpha_cut))
+        h = ctypes.c_void_p()
+        _check(load().us_probe_upload(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "us_probe_upload")
+        self.ctx, self.handle, self.desc = ctx, h, p
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.us_probe_destroy(self.handle)
+            self.handle = None
+
+
+class Scene:
+    """us_scene_upload of a workloads.Scene-like object."""
+
+    def __init__(self, ctx: Context, s, theta: Optional[np.ndarray] = None):
+        th = np.ascontiguousarray(s.theta() if theta is None else theta, dtype=np.float64)
+        pr = np.ascontiguousarray(s.plane_regions, dtype=np.int32)
+        pk = np.ascontiguousarray(s.plane_kd, dtype=np.float64)
+        sr = np.ascontiguousarray(s.sphere_regions, dtype=np.int32)
+        sk = np.ascontiguousarray(s.sphere_kd, dtype=np.float64)
+        d = us_scene_desc(int(s.regions.shape[0]), int(s.planes.shape[0]),
+                          int(s.spheres.shape[0]), th.ctypes.data, pr.ctypes.data, pk.ctypes.data,
+                          sr.ctypes.data, sk.ctypes.data, int(s.start_region))
+        h = ctypes.c_void_p()
+        n = ctypes.c_int32()
+        _check(load().us_scene_upload(ctx.handle, ctypes.byref(d), ctypes.byref(h), ctypes.byref(n)),
+               "us_scene_upload")
+        self.ctx, self.handle, self.n_params, self.desc = ctx, h, n.value, s
+
+    def set_params(self, theta_dev, stream=None):
+        """us_scene_set_params from a float64 device tensor."""
+        _check(load().us_scene_set_params(self.handle, _ptr(theta_dev), int(theta_dev.numel()),
+                                          _stream(stream)), "us_scene_set_params")
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.us_scene_destroy(self.handle)
+            self.handle = None
+
+
+def us_simulate_rf_workspace_size(scene: Scene, probe: Probe, n_tx: int, ray_count: int,
+                                  max_bounces: int) -> int:
+    return int(load().us_simulate_rf_workspace_size(scene.handle, probe.handle, n_tx, ray_count,
+                                                    max_bounces))
+
+
+def us_simulate_rf(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, seed: int,
+                   rays_per_elem: int, max_bounces: int, ray_begin: int = 0,
+                   ray_count: Optional[int] = None, rf=None, counters=None, ray_hash=None,
+                   workspace=None, stream=None):
+    torch = _torch()
+    p = probe.desc
+    tx, n_tx = _tx_array(angles, tx_ids)
+    if ray_count is None:
+        ray_count = int(p.n_elem) * int(rays_per_elem) - ray_begin
+    if rf is None:
+        rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
+    if workspace is None:
+        workspace = _workspace(us_simulate_rf_workspace_size(scene, probe, n_tx, ray_count,
+                                                             max_bounces), ctx.torch_device)
+    _check(load().us_simulate_rf(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
+                                 int(rays_per_elem), int(ray_begin), int(ray_count),
+                                 int(max_bounces), _ptr(rf), _ptr(counters), _ptr(ray_hash),
+                                 _ptr(workspace), workspace.numel(), _stream(stream)),
+           "us_simulate_rf")
+    return rf
+
+
+def _grid(g) -> us_grid_desc:
+    return us_grid_desc(int(g.n_x), int(g.n_z), float(g.x0), float(g.dx), float(g.z0), float(g.dz))
+
+
+def us_beamform(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, iq=None, workspace=None,
+                stream=None):
+    torch = _torch()
+    tx, n_tx = _tx_array(angles, tx_ids)
+    g = _grid(grid)
+    if iq is None:
+        iq = torch.empty((g.n_x, g.n_z, 2), dtype=torch.float32, device=ctx.torch_device)
+    if workspace is None:
+        workspace = _workspace(load().us_beamform_workspace_size(probe.handle, n_tx), ctx.torch_device)
+    _check(load().us_beamform(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf),
+                              _ptr(iq), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "us_beamform")
+    return iq
+
+
+def us_bmode(ctx: Context, iq, dr_db: float, out=None, workspace=None, stream=None):
+    torch = _torch()
+    n_px = iq.numel() // 2
+    if out is None:
+        out = torch.empty(iq.shape[:-1], dtype=torch.float32, device=ctx.torch_device)
+    if workspace is None:
+        workspace = _workspace(load().us_bmode_workspace_size(n_px), ctx.torch_device)
+    _check(load().us_bmode(ctx.handle, _ptr(iq), n_px, float(dr_db), _ptr(out), _ptr(workspace),
+                           workspace.numel(), _stream(stream)), "us_bmode")
+    return out
+
+
+def us_bmode_vjp(ctx: Context, iq, g_bmode, dr_db: float, g_iq=None, workspace=None, stream=None):
+    torch = _torch()
+    n_px = iq.numel() // 2
+    if g_iq is None:
+        g_iq = torch.empty_like(iq)
+    if workspace is None:
+        workspace = _workspace(load().us_bmode_workspace_size(n_px), ctx.torch_device)
+    _check(load().us_bmode_vjp(ctx.handle, _ptr(iq), _ptr(g_bmode), n_px, float(dr_db), _ptr(g_iq),
+                               _ptr(workspace), workspace.numel(), _stream(stream)), "us_bmode_vjp")
+    return g_iq
+
+
+def us_beamform_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, g_iq, g_rf=None,
+                    workspace=None, stream=None):
+    torch = _torch()
+    tx, n_tx = _tx_array(angles, tx_ids)
+    g = _grid(grid)
+    p = probe.desc
+    if g_rf is None:
+        g_rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
+    if workspace is None:
+        workspace = _workspace(load().us_beamform_vjp_workspace_size(probe.handle, n_tx),
+                               ctx.torch_device)
+    _check(load().us_beamform_vjp(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(g_iq),
+                                  _ptr(g_rf), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "us_beamform_vjp")
+    return g_rf
+
+
+def us_simulate_rf_vjp_workspace_size(scene: Scene, probe: Probe, n_tx: int, ray_count: int,
+                                      max_bounces: int) -> int:
+    return int(load().us_simulate_rf_vjp_workspace_size(scene.handle, probe.handle, n_tx,
+                                                        ray_count, max_bounces))
+
+
+def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, seed: int,
+                       rays_per_elem: int, max_bounces: int, g_rf, g_theta=None,
+                       ray_begin: int = 0, ray_count: Optional[int] = None, workspace=None,
+                       stream=None):
+    torch = _torch()
+    p = probe.desc
+    tx, n_tx = _tx_array(angles, tx_ids)
+    if ray_count is None:
+        ray_count = int(p.n_elem) * int(rays_per_elem) - ray_begin
+    if g_theta is None:
+        g_theta = torch.zeros(scene.n_params, dtype=torch.float64, device=ctx.torch_device)
+    if workspace is None:
+        workspace = _workspace(us_simulate_rf_vjp_workspace_size(scene, probe, n_tx, ray_count,
+                                                                 max_bounces), ctx.torch_device)
+    _check(load().us_simulate_rf_vjp(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
+                                     int(rays_per_elem), int(ray_begin), int(ray_count),
+                                     int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(workspace),
+                                     workspace.numel(), _stream(stream)), "us_simulate_rf_vjp")
+    return g_theta
+
+
+def us_profile_enable(ctx: Context, enable: bool = True):
+    _check(load().us_profile_enable(ctx.handle, 1 if enable else 0), "us_profile_enable")
+
+
+def us_profile_read(ctx: Context, max_kernels: int = 64):
+    """{kernel name: (total ms, launches)} since the last read."""
+    names = ctypes.create_string_buffer(32 * max_kernels)
+    ms = (ctypes.c_double * max_kernels)()
+    cnt = (ctypes.c_int64 * max_kernels)()
+    n = ctypes.c_int32()
+    _check(load().us_profile_read(ctx.handle, max_kernels, names, ms, cnt, ctypes.byref(n)),
+           "us_profile_read")
+    out = {}
+    for i in range(n.value):
+        name = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[name] = (ms[i], cnt[i])
+    return out

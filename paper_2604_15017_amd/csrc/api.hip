@@ -1,0 +1,631 @@
+// C-ABI of the library (declared in include/usrt.h): argument checks on the
+// host, workspace slicing, and the launch sequence of each entry point.
+#include "usrt.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace usrt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define US_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail(US_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define US_CHECK(cond, msg)                    \
+  do {                                         \
+    if (!(cond)) return fail(US_EINVAL, msg);  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Carves aligned sub-buffers out of a workspace.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T> T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+}  // namespace
+
+// Optional per-kernel timing: event pairs recorded around launches.
+struct ProfileLog {
+  bool on = false;
+  struct Pending { std::string name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<std::string, std::pair<double, long>>> totals;
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
+struct us_ctx {
+  int device;
+  ProfileLog prof;
+};
+
+namespace {
+
+// Brackets the launches issued in its scope with events when profiling is on.
+struct Timed {
+  ProfileLog* log;
+  const char* name;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timed(us_ctx* ctx, const char* n, hipStream_t st) : log(&ctx->prof), name(n), s(st) {
+    if (log->on) { a = log->get(); (void)hipEventRecord(a, s); }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = log->get();
+    (void)hipEventRecord(b, s);
+    log->pending.push_back({name, a, b});
+  }
+};
+
+}  // namespace
+
+struct us_probe {
+  us_ctx* ctx;
+  us_probe_desc d;
+  ProbeView pv;
+  int M;
+  float* taps;          // s[m], m = -M..M
+  float* taps_rev;      // s[-m]
+  float2* twiddle;      // exp(-2 pi i j / n_t), j < n_t / 2 (power-of-two n_t only)
+};
+
+struct us_scene {
+  us_ctx* ctx;
+  int n_regions, n_planes, n_spheres, start_region, n_params;
+  bool any_diffuse;
+  double* theta;
+  int* plane_regions;
+  double* plane_kd;
+  int* sphere_regions;
+  double* sphere_kd;
+};
+
+extern "C" {
+
+const char* us_last_error(void) { return g_err.c_str(); }
+
+int us_create(int device, us_ctx** out) {
+  US_CHECK(out != nullptr, "us_create: out is NULL");
+  int n = 0;
+  US_HIP(hipGetDeviceCount(&n));
+  US_CHECK(device >= 0 && device < n, "us_create: no such device");
+  US_HIP(hipSetDevice(device));
+  *out = new us_ctx{device};
+  return US_OK;
+}
+
+int us_destroy(us_ctx* ctx) {
+  delete ctx;
+  return US_OK;
+}
+
+int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
+  US_CHECK(ctx && d && out, "us_probe_upload: NULL argument");
+  US_CHECK(d->n_elem >= 1 && d->n_elem <= 65535, "us_probe_upload: n_elem must be in [1, 65535]");
+  US_CHECK(d->pitch > 0 && d->elem_width > 0 && d->elem_height > 0, "us_probe_upload: element geometry must be positive");
+  US_CHECK(d->f0 > 0 && d->n_cycles > 0 && d->fs > 0 && d->c_ref > 0, "us_probe_upload: f0, n_cycles, fs, c_ref must be positive");
+  US_CHECK(d->n_t >= 2 && d->n_t <= (1 << 20), "us_probe_upload: n_t must be in [2, 2^20]");
+  US_CHECK(d->alpha_main >= 0 && d->alpha_main < d->alpha_cut && d->alpha_cut <= M_PI, "us_probe_upload: need 0 <= alpha_main < alpha_cut <= pi");
+  // Eq. axial_sig: envelope FWHM n_cycles / f0; taps until the envelope falls to 1e-7
+  const double sigma = std::pow(d->n_cycles / (2.0 * d->f0), 2) / std::log(2.0);
+  const int M = (int)std::ceil(d->fs * std::sqrt(sigma * std::log(1e7)));
+  US_CHECK(M >= 0 && M <= 511, "us_probe_upload: pulse longer than 1023 taps");
+  std::vector<float> taps(2 * M + 1), rev(2 * M + 1);
+  for (int m = -M; m <= M; ++m) {
+    const double t = m / d->fs;
+    taps[m + M] = (float)(std::sin(2.0 * M_PI * d->f0 * t) * std::exp(-t * t / sigma));
+  }
+  for (int i = 0; i < 2 * M + 1; ++i) rev[i] = taps[2 * M - i];
+  US_HIP(hipSetDevice(ctx->device));
+  us_probe* p = new us_probe{};
+  p->ctx = ctx;
+  p->d = *d;
+  p->M = M;
+  p->pv = ProbeView{d->n_elem, d->n_t, d->pitch, d->elem_width, d->elem_height, d->f0, d->fs,
+                    d->c_ref, d->alpha_main, d->alpha_cut};
+  const bool pow2 = (d->n_t & (d->n_t - 1)) == 0;
+  if (hipMalloc(&p->taps, taps.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(&p->taps_rev, rev.size() * sizeof(float)) != hipSuccess ||
+      (pow2 && hipMalloc(&p->twiddle, (d->n_t / 2) * sizeof(float2)) != hipSuccess)) {
+    us_probe_destroy(p);
+    return fail(US_ENOMEM, "us_probe_upload: hipMalloc failed");
+  }
+  US_HIP(hipMemcpy(p->taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice));
+  US_HIP(hipMemcpy(p->taps_rev, rev.data(), rev.size() * sizeof(float), hipMemcpyHostToDevice));
+  if (pow2) {
+    std::vector<float2> tw(d->n_t / 2);
+    for (int j = 0; j < d->n_t / 2; ++j) {
+      const double ang = -2.0 * M_PI * j / d->n_t;
+      tw[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    US_HIP(hipMemcpy(p->twiddle, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+  }
+  *out = p;
+  return US_OK;
+}
+
+int us_probe_destroy(us_probe* p) {
+  if (!p) return US_OK;
+  (void)hipSetDevice(p->ctx->device);
+  (void)hipFree(p->taps);
+  (void)hipFree(p->taps_rev);
+  (void)hipFree(p->twiddle);
+  delete p;
+  return US_OK;
+}
+
+int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t* n_params) {
+  US_CHECK(ctx && d && out && d->theta, "us_scene_upload: NULL argument");
+  US_CHECK(d->n_regions >= 1 && d->n_regions <= kMaxRegions, "us_scene_upload: n_regions must be in [1, 64]");
+  US_CHECK(d->n_planes >= 0 && d->n_planes <= kMaxPlanes, "us_scene_upload: at most 16 planes");
+  US_CHECK(d->n_spheres >= 0 && d->n_spheres <= kMaxSpheres, "us_scene_upload: at most 32 spheres");
+  US_CHECK(d->n_planes == 0 || (d->plane_regions && d->plane_kd), "us_scene_upload: plane arrays missing");
+  US_CHECK(d->n_spheres == 0 || (d->sphere_regions && d->sphere_kd), "us_scene_upload: sphere arrays missing");
+  US_CHECK(d->start_region >= 0 && d->start_region < d->n_regions, "us_scene_upload: start_region out of range");
+  const int np = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
+  for (int r = 0; r < d->n_regions; ++r)
+    US_CHECK(d->theta[3 * r] > 0 && d->theta[3 * r + 1] > 0 && d->theta[3 * r + 2] >= 0,
+             "us_scene_upload: region needs c > 0, Z > 0, alpha >= 0");
+  bool diffuse = false;
+  for (int k = 0; k < d->n_planes; ++k) {
+    for (int j = 0; j < 2; ++j)
+      US_CHECK(d->plane_regions[2 * k + j] >= 0 && d->plane_regions[2 * k + j] < d->n_regions, "us_scene_upload: plane region out of range");
+    US_CHECK(d->plane_kd[k] >= 0 && d->plane_kd[k] <= 1, "us_scene_upload: kd must be in [0, 1]");
+    diffuse |= d->plane_kd[k] > 0;
+  }
+  for (int k = 0; k < d->n_spheres; ++k) {
+    for (int j = 0; j < 2; ++j)
+      US_CHECK(d->sphere_regions[2 * k + j] >= 0 && d->sphere_regions[2 * k + j] < d->n_regions, "us_scene_upload: sphere region out of range");
+    US_CHECK(d->sphere_kd[k] >= 0 && d->sphere_kd[k] <= 1, "us_scene_upload: kd must be in [0, 1]");
+    US_CHECK(d->theta[3 * d->n_regions + d->n_planes + 4 * k + 3] > 0, "us_scene_upload: sphere radius must be positive");
+    diffuse |= d->sphere_kd[k] > 0;
+  }
+  US_HIP(hipSetDevice(ctx->device));
+  us_scene* s = new us_scene{};
+  s->ctx = ctx;
+  s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
+  s->start_region = d->start_region; s->n_params = np; s->any_diffuse = diffuse;
+  bool ok = hipMalloc(&s->theta, np * sizeof(double)) == hipSuccess &&
+            hipMalloc(&s->plane_regions, (2 * d->n_planes + 1) * sizeof(int)) == hipSuccess &&
+            hipMalloc(&s->plane_kd, (d->n_planes + 1) * sizeof(double)) == hipSuccess &&
+            hipMalloc(&s->sphere_regions, (2 * d->n_spheres + 1) * sizeof(int)) == hipSuccess &&
+            hipMalloc(&s->sphere_kd, (d->n_spheres + 1) * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    us_scene_destroy(s);
+    return fail(US_ENOMEM, "us_scene_upload: hipMalloc failed");
+  }
+  US_HIP(hipMemcpy(s->theta, d->theta, np * sizeof(double), hipMemcpyHostToDevice));
+  if (d->n_planes) {
+    US_HIP(hipMemcpy(s->plane_regions, d->plane_regions, 2 * d->n_planes * sizeof(int), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy(s->plane_kd, d->plane_kd, d->n_planes * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (d->n_spheres) {
+    US_HIP(hipMemcpy(s->sphere_regions, d->sphere_regions, 2 * d->n_spheres * sizeof(int), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy(s->sphere_kd, d->sphere_kd, d->n_spheres * sizeof(double), hipMemcpyHostToDevice));
+  }
+  *out = s;
+  if (n_params) *n_params = np;
+  return US_OK;
+}
+
+int us_scene_destroy(us_scene* s) {
+  if (!s) return US_OK;
+  (void)hipSetDevice(s->ctx->device);
+  (void)hipFree(s->theta);
+  (void)hipFree(s->plane_regions);
+  (void)hipFree(s->plane_kd);
+  (void)hipFree(s->sphere_regions);
+  (void)hipFree(s->sphere_kd);
+  delete s;
+  return US_OK;
+}
+
+int us_scene_set_params(us_scene* s, const double* theta_dev, int32_t n_params, void* stream) {
+  US_CHECK(s && theta_dev, "us_scene_set_params: NULL argument");
+  US_CHECK(n_params == s->n_params, "us_scene_set_params: n_params does not match the scene");
+  US_HIP(hipSetDevice(s->ctx->device));
+  US_HIP(hipMemcpyAsync(s->theta, theta_dev, n_params * sizeof(double), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return US_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+SceneView scene_view(const us_scene* s, const us_probe* p) {
+  SceneView v;
+  v.theta = s->theta;
+  v.plane_regions = s->plane_regions;
+  v.plane_kd = s->plane_kd;
+  v.sphere_regions = s->sphere_regions;
+  v.sphere_kd = s->sphere_kd;
+  v.n_regions = s->n_regions;
+  v.n_planes = s->n_planes;
+  v.n_spheres = s->n_spheres;
+  v.start_region = s->start_region;
+  // amplitude attenuation at f0: alpha [dB/cm/MHz] * f0 [MHz] * 100 cm/m / (20 / ln 10)
+  v.np_per_m = (p->d.f0 * 1e-6) * 100.0 * std::log(10.0) / 20.0;
+  return v;
+}
+
+int fill_tx(TxTable& t, const us_tx_desc* tx, int first, int count) {
+  std::memset(&t, 0, sizeof(t));
+  t.n = count;
+  for (int i = 0; i < count; ++i) {
+    const double a = tx[first + i].angle;
+    if (!(std::fabs(a) < 0.5 * M_PI)) return -1;
+    t.sin_a[i] = std::sin(a);
+    t.cos_a[i] = std::cos(a);
+    t.id[i] = tx[first + i].id;
+  }
+  return 0;
+}
+
+// Rays per chunk when the caller sizes the workspace with
+// us_simulate_rf_workspace_size (about 200 bytes of queue per ray).
+constexpr long kDefaultChunk = 1L << 24;
+
+size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {
+  Carver c{nullptr};
+  c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
+  c.take<unsigned long long>((size_t)max_bounces + 4);
+  return c.off;
+}
+
+size_t trace_per_ray_bytes() { return 2 * kRayQueueBytesPerRay + kSecondaryBytesPerRay; }
+
+void carve_queues(Carver& c, long cap, RayQueue* q0, RayQueue* q1, SecondaryQueue* nq) {
+  for (RayQueue* q : {q0, q1}) {
+    q->ox = c.take<double>(cap); q->oy = c.take<double>(cap); q->oz = c.take<double>(cap);
+    q->dx = c.take<double>(cap); q->dy = c.take<double>(cap); q->dz = c.take<double>(cap);
+    q->t = c.take<double>(cap); q->w = c.take<double>(cap);
+    q->rid = c.take<uint32_t>(cap); q->meta = c.take<uint32_t>(cap);
+  }
+  nq->x = c.take<double>(cap); nq->y = c.take<double>(cap); nq->z = c.take<double>(cap);
+  nq->t = c.take<double>(cap); nq->amp = c.take<double>(cap);
+  nq->rid = c.take<uint32_t>(cap); nq->meta = c.take<uint32_t>(cap); nq->txk = c.take<uint32_t>(cap);
+}
+
+size_t queue_bytes(long cap) {
+  Carver c{nullptr};
+  RayQueue a, b;
+  SecondaryQueue n;
+  carve_queues(c, cap, &a, &b, &n);
+  return c.off;
+}
+
+int check_trace_args(const us_scene* scene, const us_probe* probe, const us_tx_desc* tx, int n_tx,
+                     int rays_per_elem, int64_t ray_begin, int64_t ray_count, int max_bounces) {
+  US_CHECK(scene && probe && tx, "simulate_rf: NULL scene, probe or tx");
+  US_CHECK(scene->ctx == probe->ctx, "simulate_rf: scene and probe belong to different contexts");
+  US_CHECK(n_tx >= 1, "simulate_rf: n_tx must be >= 1");
+  US_CHECK(rays_per_elem >= 1, "simulate_rf: rays_per_elem must be >= 1");
+  const int64_t total = (int64_t)probe->d.n_elem * rays_per_elem;
+  US_CHECK(total < (int64_t(1) << 32), "simulate_rf: n_elem * rays_per_elem must be < 2^32");
+  US_CHECK(ray_begin >= 0 && ray_count >= 0 && ray_begin + ray_count <= total,
+           "simulate_rf: ray range outside [0, n_elem * rays_per_elem)");
+  US_CHECK(max_bounces >= 0 && max_bounces <= 1000, "simulate_rf: max_bounces must be in [0, 1000]");
+  for (int i = 0; i < n_tx; ++i)
+    US_CHECK(std::fabs(tx[i].angle) < 0.5 * M_PI, "simulate_rf: steering angle must be in (-pi/2, pi/2)");
+  return US_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t us_simulate_rf_workspace_size(const us_scene* scene, const us_probe* probe, int32_t n_tx,
+                                     int64_t ray_count, int32_t max_bounces) {
+  if (!scene || !probe || n_tx < 1 || ray_count < 0 || max_bounces < 0) return 0;
+  const int group = n_tx < kMaxTxPerLaunch ? n_tx : kMaxTxPerLaunch;
+  long chunk = (long)std::min<int64_t>((int64_t)group * ray_count, kDefaultChunk);
+  if (chunk < 256) chunk = 256;
+  return trace_fixed_bytes(n_tx, probe, max_bounces) + queue_bytes(chunk);
+}
+
+int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
+                   int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                   int64_t ray_count, int32_t max_bounces, float* rf_dev, int64_t* counters_dev,
+                   uint64_t* ray_hash_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && rf_dev && ws_dev, "us_simulate_rf: NULL ctx, rf or workspace");
+  int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
+  if (rc) return rc;
+  const size_t fixed = trace_fixed_bytes(n_tx, probe, max_bounces);
+  // largest chunk whose queues fit in the workspace
+  long cap = 0;
+  {
+    long lo = 0, hi = (long)std::max<int64_t>(256, (int64_t)std::min(n_tx, kMaxTxPerLaunch) * ray_count);
+    while (lo < hi) {
+      const long mid = (lo + hi + 1) / 2;
+      if (fixed + queue_bytes(mid) <= ws_bytes) lo = mid; else hi = mid - 1;
+    }
+    cap = lo;
+  }
+  if (cap < std::min<int64_t>(256, (int64_t)n_tx * ray_count) || (ray_count > 0 && cap < 1))
+    return fail(US_ETOOBIG, "us_simulate_rf: workspace too small (see us_simulate_rf_workspace_size)");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const us_probe_desc& pd = probe->d;
+  Carver c{(char*)ws_dev};
+  float* h = c.take<float>((size_t)n_tx * pd.n_elem * pd.n_t);
+  unsigned long long* counts = c.take<unsigned long long>((size_t)max_bounces + 4);
+  TraceArgs a{};
+  carve_queues(c, cap, &a.qin, &a.qout, &a.nee);
+  const RayQueue q0 = a.qin, q1 = a.qout;
+  a.scene = scene_view(scene, probe);
+  a.probe = probe->pv;
+  a.seed = seed;
+  a.rays_per_elem = rays_per_elem;
+  a.max_bounces = max_bounces;
+  a.ray_begin = ray_begin;
+  a.ray_count = ray_count;
+  a.counts = counts;
+  a.h = h;
+  a.counters = (unsigned long long*)counters_dev;
+  a.hash = (unsigned long long*)ray_hash_dev;
+  const bool audit = ray_hash_dev != nullptr;
+  launch_fill_u32((uint32_t*)h, (long)n_tx * pd.n_elem * pd.n_t, 0u, s);
+  if (audit) launch_fill_u32((uint32_t*)ray_hash_dev, 2L * n_tx * ray_count, 0u, s);
+  for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    fill_tx(a.tx, tx, t0, ng);
+    a.tx_base = t0;
+    const long total = (long)ng * ray_count;
+    for (long g0 = 0; g0 < total; g0 += cap) {
+      const long n = std::min(cap, total - g0);
+      a.g0 = g0;
+      a.n_chunk = n;
+      launch_fill_u32((uint32_t*)counts, 2L * (max_bounces + 4), 0u, s);
+      a.qin = q0;
+      a.qout = q1;
+      for (int k = 1; k <= max_bounces + 1; ++k) {
+        {
+          Timed tm(ctx, "bounce", s);
+          launch_bounce(a, k, n, audit, s);
+        }
+        if (k <= max_bounces && scene->any_diffuse) {
+          Timed tm(ctx, "secondary", s);
+          launch_secondary(a, k, n, audit, s);
+        }
+        std::swap(a.qin, a.qout);
+      }
+    }
+  }
+  {
+    Timed tm(ctx, "pulse", s);
+    if (launch_pulse(h, rf_dev, probe->taps, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
+      return fail(US_EINVAL, "us_simulate_rf: pulse too long");
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+GridView grid_view(const us_grid_desc* g) {
+  return GridView{g->n_x, g->n_z, g->x0, g->dx, g->z0, g->dz};
+}
+
+int check_beamform(const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx, int n_tx) {
+  US_CHECK(probe && grid && tx, "beamform: NULL probe, grid or tx");
+  US_CHECK(n_tx >= 1, "beamform: n_tx must be >= 1");
+  US_CHECK(probe->twiddle != nullptr && probe->d.n_t >= 64 && probe->d.n_t <= 8192,
+           "beamform: n_t must be a power of two in [64, 8192]");
+  US_CHECK(grid->n_x >= 1 && grid->n_z >= 1 && (int64_t)grid->n_x * grid->n_z < (int64_t(1) << 31),
+           "beamform: grid size out of range");
+  US_CHECK(grid->dx > 0 && grid->dz > 0 && grid->z0 >= 0, "beamform: need dx, dz > 0 and z0 >= 0");
+  for (int i = 0; i < n_tx; ++i)
+    US_CHECK(std::fabs(tx[i].angle) < 0.5 * M_PI, "beamform: steering angle must be in (-pi/2, pi/2)");
+  return US_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t us_beamform_workspace_size(const us_probe* probe, int32_t n_tx) {
+  if (!probe || n_tx < 1) return 0;
+  return align_up((size_t)n_tx * probe->d.n_elem * probe->d.n_t * sizeof(float2));
+}
+
+int us_beamform(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx,
+                int32_t n_tx, const float* rf_dev, float* iq_dev, void* ws_dev, size_t ws_bytes,
+                void* stream) {
+  US_CHECK(ctx && rf_dev && iq_dev && ws_dev, "us_beamform: NULL argument");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  if (ws_bytes < us_beamform_workspace_size(probe, n_tx))
+    return fail(US_ETOOBIG, "us_beamform: workspace too small");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  float2* A = (float2*)ws_dev;
+  const long rows = (long)n_tx * probe->d.n_elem;
+  {
+    Timed tm(ctx, "analytic", s);
+    if (launch_analytic(rf_dev, A, probe->twiddle, probe->d.n_t, rows, s))
+      return fail(US_EINVAL, "us_beamform: unsupported n_t");
+  }
+  const GridView g = grid_view(grid);
+  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    TxTable tt;
+    fill_tx(tt, tx, t0, ng);
+    Timed tm(ctx, "das", s);
+    launch_das(A, (float2*)iq_dev, probe->pv, g, tt, ng, t0, t0 > 0, s);
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+size_t us_bmode_workspace_size(int64_t n_px) {
+  (void)n_px;
+  return 2 * kAlign;
+}
+
+int us_bmode(us_ctx* ctx, const float* iq_dev, int64_t n_px, float dr_db, float* bmode_dev,
+             void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && iq_dev && bmode_dev && ws_dev, "us_bmode: NULL argument");
+  US_CHECK(n_px >= 1 && n_px < (int64_t(1) << 32) - 1, "us_bmode: n_px out of range");
+  US_CHECK(dr_db > 0, "us_bmode: dr_db must be positive");
+  if (ws_bytes < us_bmode_workspace_size(n_px)) return fail(US_ETOOBIG, "us_bmode: workspace too small");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* key = (unsigned long long*)ws_dev;
+  launch_fill_u32((uint32_t*)key, 2, 0u, s);
+  {
+    Timed tm(ctx, "bmode", s);
+    launch_env_max((const float2*)iq_dev, n_px, key, s);
+    launch_bmode((const float2*)iq_dev, n_px, dr_db, key, bmode_dev, s);
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+int us_bmode_vjp(us_ctx* ctx, const float* iq_dev, const float* g_bmode_dev, int64_t n_px,
+                 float dr_db, float* g_iq_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && iq_dev && g_bmode_dev && g_iq_dev && ws_dev, "us_bmode_vjp: NULL argument");
+  US_CHECK(n_px >= 1 && n_px < (int64_t(1) << 32) - 1, "us_bmode_vjp: n_px out of range");
+  US_CHECK(dr_db > 0, "us_bmode_vjp: dr_db must be positive");
+  if (ws_bytes < us_bmode_workspace_size(n_px)) return fail(US_ETOOBIG, "us_bmode_vjp: workspace too small");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* key = (unsigned long long*)ws_dev;
+  double* sum = (double*)((char*)ws_dev + kAlign);
+  launch_fill_u32((uint32_t*)key, 2, 0u, s);
+  launch_fill_u32((uint32_t*)sum, 2, 0u, s);
+  {
+    Timed tm(ctx, "bmode_vjp", s);
+    launch_env_max((const float2*)iq_dev, n_px, key, s);
+    launch_bmode_vjp((const float2*)iq_dev, g_bmode_dev, n_px, dr_db, key, sum, (float2*)g_iq_dev, s);
+    launch_bmode_vjp_fix((const float2*)iq_dev, n_px, key, sum, (float2*)g_iq_dev, s);
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+size_t us_beamform_vjp_workspace_size(const us_probe* probe, int32_t n_tx) {
+  return us_beamform_workspace_size(probe, n_tx);
+}
+
+int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
+                    const us_tx_desc* tx, int32_t n_tx, const float* g_iq_dev, float* g_rf_dev,
+                    void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && g_iq_dev && g_rf_dev && ws_dev, "us_beamform_vjp: NULL argument");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  if (ws_bytes < us_beamform_vjp_workspace_size(probe, n_tx))
+    return fail(US_ETOOBIG, "us_beamform_vjp: workspace too small");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  float2* gA = (float2*)ws_dev;
+  const GridView g = grid_view(grid);
+  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    TxTable tt;
+    fill_tx(tt, tx, t0, ng);
+    Timed tm(ctx, "das_adjoint", s);
+    launch_das_adjoint((const float2*)g_iq_dev, gA, probe->pv, g, tt, ng, t0, s);
+  }
+  {
+    Timed tm(ctx, "analytic_adjoint", s);
+    if (launch_analytic_adjoint(gA, g_rf_dev, probe->twiddle, probe->d.n_t,
+                                (long)n_tx * probe->d.n_elem, s))
+      return fail(US_EINVAL, "us_beamform_vjp: unsupported n_t");
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* probe,
+                                         int32_t n_tx, int64_t ray_count, int32_t max_bounces) {
+  (void)ray_count; (void)max_bounces;
+  if (!scene || !probe || n_tx < 1) return 0;
+  return align_up((size_t)n_tx * probe->d.n_elem * probe->d.n_t * sizeof(float));
+}
+
+int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
+                       const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                       int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
+                       const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
+                       void* stream) {
+  (void)ctx; (void)scene; (void)probe; (void)tx; (void)n_tx; (void)seed; (void)rays_per_elem;
+  (void)ray_begin; (void)ray_count; (void)max_bounces; (void)g_rf_dev; (void)g_theta_dev;
+  (void)ws_dev; (void)ws_bytes; (void)stream;
+  return fail(US_EINVAL, "us_simulate_rf_vjp: not available in this build");
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int us_profile_enable(us_ctx* ctx, int enable) {
+  US_CHECK(ctx, "us_profile_enable: NULL ctx");
+  ctx->prof.on = enable != 0;
+  return US_OK;
+}
+
+int us_profile_read(us_ctx* ctx, int32_t max_kernels, char* names, double* total_ms,
+                    int64_t* launches, int32_t* n_kernels) {
+  US_CHECK(ctx && n_kernels && (max_kernels == 0 || (names && total_ms && launches)),
+           "us_profile_read: NULL argument");
+  US_HIP(hipSetDevice(ctx->device));
+  ProfileLog& L = ctx->prof;
+  for (auto& p : L.pending) {
+    US_HIP(hipEventSynchronize(p.b));
+    float ms = 0.0f;
+    US_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    bool found = false;
+    for (auto& t : L.totals)
+      if (t.first == p.name) { t.second.first += ms; t.second.second += 1; found = true; }
+    if (!found) L.totals.push_back({p.name, {ms, 1}});
+    L.pool.push_back(p.a);
+    L.pool.push_back(p.b);
+  }
+  L.pending.clear();
+  int n = 0;
+  for (auto& t : L.totals) {
+    if (n >= max_kernels) break;
+    std::strncpy(names + 32 * n, t.first.c_str(), 31);
+    names[32 * n + 31] = 0;
+    total_ms[n] = t.second.first;
+    launches[n] = t.second.second;
+    ++n;
+  }
+  *n_kernels = n;
+  L.totals.clear();
+  return US_OK;
+}
+
+}  // extern "C"

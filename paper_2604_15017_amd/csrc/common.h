@@ -1,0 +1,188 @@
+// Device-side building blocks for the gfx950 kernels: counter-based RNG,
+// fp64 3-vectors, scene/probe views and the per-ray decision hash.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace usrt {
+
+constexpr int kMaxRegions = 64;
+constexpr int kMaxPlanes = 16;
+constexpr int kMaxSpheres = 32;
+constexpr int kMaxTxPerLaunch = 64;
+constexpr double kTMin = 1e-6;          // self-intersection guard [m]
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11). key = (seed, 0),
+// counter = (ray id, transmit id, event, 0). The 64x64 -> 128 products are
+// formed from 32-bit halves by the compiler (__umul64hi).
+// ---------------------------------------------------------------------------
+struct U64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                               uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t lo0 = 0xD2E7470EE14C6C93ULL * c0;
+    const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ULL, c0);
+    const uint64_t lo1 = 0xCA5A826395121157ULL * c2;
+    const uint64_t hi1 = __umul64hi(0xCA5A826395121157ULL, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B97F4A7C15ULL;
+    k1 += 0xBB67AE8584CAA73BULL;
+  }
+  return U64x4{{c0, c1, c2, c3}};
+}
+
+// 23 random bits as the odd multiple (2 m + 1) 2^-24: exact in fp32 and fp64.
+__device__ __forceinline__ double unit_uniform(uint64_t x) {
+  return ((double)(x >> 41) + 0.5) * 0x1.0p-23;
+}
+
+struct Draw { double u0, u1, u2, u3; };
+
+__device__ __forceinline__ Draw draw(uint64_t seed, uint32_t ray, uint32_t tx_id, uint32_t event) {
+  const U64x4 o = philox4x64_10(ray, tx_id, event, 0, seed, 0);
+  return Draw{unit_uniform(o.v[0]), unit_uniform(o.v[1]), unit_uniform(o.v[2]),
+              unit_uniform(o.v[3])};
+}
+
+// Decision hash event: SplitMix64 finaliser of (tag, event index, word).
+__device__ __forceinline__ uint64_t event_mix(uint32_t tag, uint32_t k, uint32_t word) {
+  uint64_t z = ((uint64_t)tag << 60) | ((uint64_t)(k & 0xFFFu) << 48) | (uint64_t)word;
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+enum : uint32_t { kEvHit = 1, kEvArray = 2, kEvBranch = 3, kEvNee = 4 };
+enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3 };
+
+struct d3 { double x, y, z; };
+__device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ d3 operator*(d3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// Probe as the kernels see it.
+struct ProbeView {
+  int n_elem, n_t;
+  double pitch, elem_w, elem_h, f0, fs, c_ref, alpha_m, alpha_c;
+};
+
+// Scene as the kernels see it (device pointers; copied to LDS per block).
+struct SceneView {
+  const double* theta;
+  const int* plane_regions;
+  const double* plane_kd;
+  const int* sphere_regions;
+  const double* sphere_kd;
+  int n_regions, n_planes, n_spheres, start_region;
+  double np_per_m;       // amplitude attenuation [Np/m] per dB/cm/MHz at f0
+};
+
+// Per-block copy of the scene in LDS.
+struct SceneLDS {
+  double c[kMaxRegions], Z[kMaxRegions], a[kMaxRegions];
+  double pd[kMaxPlanes], pkd[kMaxPlanes];
+  int pr[kMaxPlanes][2];
+  double sx[kMaxSpheres], sy[kMaxSpheres], sz[kMaxSpheres], sr[kMaxSpheres], skd[kMaxSpheres];
+  int sreg[kMaxSpheres][2];
+  int n_planes, n_spheres, start_region;
+  bool any_diffuse;
+};
+
+__device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
+  const int t = threadIdx.x;
+  const int nr = v.n_regions;
+  for (int i = t; i < nr; i += blockDim.x) {
+    s.c[i] = v.theta[3 * i];
+    s.Z[i] = v.theta[3 * i + 1];
+    s.a[i] = v.theta[3 * i + 2] * v.np_per_m;
+  }
+  const int op = 3 * nr, os = op + v.n_planes;
+  for (int i = t; i < v.n_planes; i += blockDim.x) {
+    s.pd[i] = v.theta[op + i];
+    s.pkd[i] = v.plane_kd[i];
+    s.pr[i][0] = v.plane_regions[2 * i];
+    s.pr[i][1] = v.plane_regions[2 * i + 1];
+  }
+  for (int i = t; i < v.n_spheres; i += blockDim.x) {
+    s.sx[i] = v.theta[os + 4 * i];
+    s.sy[i] = v.theta[os + 4 * i + 1];
+    s.sz[i] = v.theta[os + 4 * i + 2];
+    s.sr[i] = v.theta[os + 4 * i + 3];
+    s.skd[i] = v.sphere_kd[i];
+    s.sreg[i][0] = v.sphere_regions[2 * i];
+    s.sreg[i][1] = v.sphere_regions[2 * i + 1];
+  }
+  if (t == 0) {
+    s.n_planes = v.n_planes;
+    s.n_spheres = v.n_spheres;
+    s.start_region = v.start_region;
+    bool d = false;
+    for (int i = 0; i < v.n_planes; ++i) d |= v.plane_kd[i] > 0.0;
+    for (int i = 0; i < v.n_spheres; ++i) d |= v.sphere_kd[i] > 0.0;
+    s.any_diffuse = d;
+  }
+  __syncthreads();
+}
+
+// Transmit table passed by value.
+struct TxTable {
+  double sin_a[kMaxTxPerLaunch], cos_a[kMaxTxPerLaunch];
+  uint32_t id[kMaxTxPerLaunch];
+  int n;
+};
+
+// Receive directivity (Eq. cutoff) as a function of the cosine of the angle
+// between the element normal and the direction the wave comes from.
+__device__ __forceinline__ double rx_directivity(const ProbeView& p, double cos_a) {
+  const double c = fmin(1.0, fmax(-1.0, cos_a));
+  const double al = acos(c);
+  if (al <= p.alpha_m) return 1.0;
+  if (al > p.alpha_c) return 0.0;
+  return (p.alpha_c - al) / (p.alpha_c - p.alpha_m);
+}
+
+// Block-aggregated append to two queues at once. Each lane with keep_a
+// (keep_b) receives a distinct slot in queue A (B). The two running counts
+// share one 64-bit word (A in the low half, B in the high half), so a block
+// takes all its slots with a single atomic. Must be called by every thread of
+// the block (it contains barriers); `scratch` is 2 * (waves per block) + 1
+// words of LDS.
+struct Slots { long a, b; };
+
+__device__ __forceinline__ Slots block_append2(bool keep_a, bool keep_b,
+                                               unsigned long long* counts,
+                                               unsigned long long* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+  const unsigned long long ma = __ballot(keep_a), mb = __ballot(keep_b);
+  if (lane == 0) scratch[wave] = ((unsigned long long)__popcll(mb) << 32) | (unsigned)__popcll(ma);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int w = 0; w < n_waves; ++w) {   // exclusive scan over the waves
+      const unsigned long long c = scratch[w];
+      scratch[w] = run;
+      run += c;
+    }
+    scratch[n_waves] = run ? atomicAdd(counts, run) : 0ull;
+  }
+  __syncthreads();
+  const unsigned long long base = scratch[n_waves] + scratch[wave];
+  __syncthreads();   // scratch is reused by the next call
+  const unsigned below_a =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(ma >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ma, 0u));
+  const unsigned below_b =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+  Slots s;
+  s.a = keep_a ? (long)(uint32_t)base + below_a : -1;
+  s.b = keep_b ? (long)(base >> 32) + below_b : -1;
+  return s;
+}
+
+}  // namespace usrt

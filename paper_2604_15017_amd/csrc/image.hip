@@ -1,0 +1,340 @@
+// Image formation on gfx950 (paper Sec. 2.3.4 and Sec. 3.3): analytic signal
+// of every RF channel (FFT in LDS), plane-wave delay-and-sum (Eq. das),
+// envelope and log compression, and the adjoints of all three (Eq.
+// das_adjoint as a per-sample gather, no atomics).
+#include "kernels.h"
+
+namespace usrt {
+
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) {
+  return __brev(v) >> (32 - bits);
+}
+
+constexpr int kFftThreads = 256;
+constexpr int kMaxFft = 8192;
+
+// In LDS: forward DIT on bit-reversed input -> natural-order spectrum.
+__device__ void fft_dit(float2* x, const float2* w, int n, int logn) {
+  for (int s = 1; s <= logn; ++s) {
+    const int half = 1 << (s - 1);
+    const int tw_stride = n >> s;
+    for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
+      const int pos = b & (half - 1);
+      const int i0 = ((b >> (s - 1)) << s) + pos;
+      const int i1 = i0 + half;
+      const float2 t = cmul(w[pos * tw_stride], x[i1]);
+      const float2 u = x[i0];
+      x[i0] = make_float2(u.x + t.x, u.y + t.y);
+      x[i1] = make_float2(u.x - t.x, u.y - t.y);
+    }
+    __syncthreads();
+  }
+}
+
+// In LDS: forward DIF on natural-order input -> bit-reversed spectrum.
+__device__ void fft_dif(float2* x, const float2* w, int n, int logn) {
+  for (int s = logn; s >= 1; --s) {
+    const int half = 1 << (s - 1);
+    const int tw_stride = n >> s;
+    for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
+      const int pos = b & (half - 1);
+      const int i0 = ((b >> (s - 1)) << s) + pos;
+      const int i1 = i0 + half;
+      const float2 u = x[i0], v = x[i1];
+      x[i0] = make_float2(u.x + v.x, u.y + v.y);
+      x[i1] = cmul(make_float2(u.x - v.x, u.y - v.y), w[pos * tw_stride]);
+    }
+    __syncthreads();
+  }
+}
+
+// Analytic-signal map T = F^-1 diag(H) F along one row, H = 1, 2..2, 1, 0..0.
+// kRealIn: input row is real (forward) or complex (adjoint); kRealOut: keep
+// the real part (adjoint: T is self-adjoint, g_rf = Re(T g_A)).
+template <bool kRealIn, bool kRealOut>
+__global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* out,
+                                                          const float2* twiddle, int n, int logn) {
+  extern __shared__ float2 lds[];
+  float2* x = lds;            // n
+  float2* w = lds + n;        // n / 2 twiddles exp(-2 pi i j / n)
+  const long row = blockIdx.x;
+  for (int j = threadIdx.x; j < (n >> 1); j += blockDim.x) w[j] = twiddle[j];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    float2 v;
+    if (kRealIn) v = make_float2(((const float*)in)[row * n + j], 0.0f);
+    else v = ((const float2*)in)[row * n + j];
+    x[bitrev((unsigned)j, logn)] = v;
+  }
+  __syncthreads();
+  fft_dit(x, w, n, logn);
+  // X * H, conjugated so that a forward transform computes the inverse
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const float hm = (j == 0 || j == (n >> 1)) ? 1.0f : (j < (n >> 1) ? 2.0f : 0.0f);
+    const float2 v = x[j];
+    x[j] = make_float2(hm * v.x, -hm * v.y);
+  }
+  __syncthreads();
+  fft_dif(x, w, n, logn);
+  const float inv_n = 1.0f / (float)n;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const float2 v = x[bitrev((unsigned)j, logn)];
+    if (kRealOut) ((float*)out)[row * n + j] = v.x * inv_n;
+    else ((float2*)out)[row * n + j] = make_float2(v.x * inv_n, -v.y * inv_n);
+  }
+}
+
+// Delay-and-sum, one pixel per thread, threads along z. The fractional
+// sample index is formed in fp64 (an fp32 index near 4000 carries 2.4e-4
+// samples of rounding, i.e. 2e-4 rad of phase per tap at 5 MHz / 40 MHz);
+// interpolation and accumulation are fp32.
+__global__ __launch_bounds__(256) void k_das(const float2* __restrict__ A, float2* __restrict__ iq,
+                                             ProbeView p, GridView g, TxTable tx, int n_tx,
+                                             int tx_base, int accumulate) {
+  const long px = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (px >= (long)g.n_x * g.n_z) return;
+  const int a = (int)(px / g.n_z), b = (int)(px % g.n_z);
+  const double x = g.x0 + a * g.dx, z = g.z0 + b * g.dz;
+  const double s_per_m = p.fs / p.c_ref;
+  float2 acc = accumulate ? iq[px] : make_float2(0.0f, 0.0f);
+  const double half = 0.5 * (double)(p.n_elem - 1);
+  for (int e = 0; e < p.n_elem; ++e) {
+    const double dxe = x - ((double)e - half) * p.pitch;
+    const double krx = sqrt(dxe * dxe + z * z) * s_per_m;
+    for (int i = 0; i < n_tx; ++i) {
+      const double k = (x * tx.sin_a[i] + z * tx.cos_a[i]) * s_per_m + krx;
+      const double k0d = floor(k);
+      if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
+      const int k0 = (int)k0d;
+      const float f = (float)(k - k0d);
+      const float2* row = A + ((long)(tx_base + i) * p.n_elem + e) * p.n_t;
+      const float2 v0 = k0 >= 0 ? row[k0] : make_float2(0.0f, 0.0f);
+      const float2 v1 = k0 + 1 < p.n_t ? row[k0 + 1] : make_float2(0.0f, 0.0f);
+      acc.x += (1.0f - f) * v0.x + f * v1.x;
+      acc.y += (1.0f - f) * v0.y + f * v1.y;
+    }
+  }
+  iq[px] = acc;
+}
+
+// Frame maximum of |I|^2 with the first index among equals, packed as
+// (float bits << 32) | (~index) for a 64-bit atomic max.
+__global__ __launch_bounds__(256) void k_env_max(const float2* __restrict__ iq, long n,
+                                                 unsigned long long* key) {
+  __shared__ unsigned long long best;
+  if (threadIdx.x == 0) best = 0;
+  __syncthreads();
+  unsigned long long local = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float2 v = iq[i];
+    const float pw = v.x * v.x + v.y * v.y;
+    const unsigned long long kk = ((unsigned long long)__float_as_uint(pw) << 32) |
+                                  (unsigned long long)(0xFFFFFFFFu - (unsigned)i);
+    local = kk > local ? kk : local;
+  }
+  atomicMax(&best, local);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(key, best);
+}
+
+__device__ __forceinline__ float key_power(unsigned long long key) {
+  return __uint_as_float((unsigned)(key >> 32));
+}
+__device__ __forceinline__ long key_index(unsigned long long key) {
+  return (long)(0xFFFFFFFFu - (unsigned)(key & 0xFFFFFFFFu));
+}
+
+constexpr float kLog10Scale = 10.0f;                 // 20 log10 |I| = 10 log10 |I|^2
+constexpr double kDbPerNeper = 8.685889638065037;    // 20 / ln 10
+
+__global__ __launch_bounds__(256) void k_bmode(const float2* __restrict__ iq, long n, float dr,
+                                               const unsigned long long* key, float* out) {
+  const float m2 = key_power(*key);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float2 v = iq[i];
+    const float pw = v.x * v.x + v.y * v.y;
+    float b = pw > 0.0f ? kLog10Scale * log10f(pw / m2) : -dr;
+    out[i] = fmaxf(b, -dr);
+  }
+}
+
+// g_I = g_B (20/ln10) I / |I|^2 on unclipped pixels; the sum of g_B over
+// them feeds the normalisation term added at the arg-max pixel afterwards.
+__global__ __launch_bounds__(256) void k_bmode_vjp(const float2* __restrict__ iq,
+                                                   const float* __restrict__ gb, long n, float dr,
+                                                   const unsigned long long* key, double* sum,
+                                                   float2* __restrict__ giq) {
+  __shared__ double bsum;
+  if (threadIdx.x == 0) bsum = 0.0;
+  __syncthreads();
+  const float m2 = key_power(*key);
+  double local = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const float2 v = iq[i];
+    const float pw = v.x * v.x + v.y * v.y;
+    const bool live = pw > 0.0f && kLog10Scale * log10f(pw / m2) > -dr;
+    float2 gi = make_float2(0.0f, 0.0f);
+    if (live) {
+      const float s = gb[i] * (float)kDbPerNeper / pw;
+      gi = make_float2(s * v.x, s * v.y);
+      local += gb[i];
+    }
+    giq[i] = gi;
+  }
+  atomicAdd(&bsum, local);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(sum, bsum);
+}
+
+__global__ void k_bmode_vjp_fix(const float2* __restrict__ iq, const unsigned long long* key,
+                                const double* sum, float2* giq) {
+  const long am = key_index(*key);
+  const float m2 = key_power(*key);
+  const float2 v = iq[am];
+  const float s = (float)(-kDbPerNeper * *sum / (double)m2);
+  giq[am].x += s * v.x;
+  giq[am].y += s * v.y;
+}
+
+// Adjoint of DAS for one RF row (transmit, element): each thread owns kS
+// consecutive samples k and gathers, column by column, the pixels whose
+// interpolation reads them with weight max(0, 1 - |kappa - k|). kappa(z) is
+// increasing in z, so the first pixel of interest follows from the inverse
+// z(kappa) = (T^2 - dx^2) / (T cos th + sqrt(T^2 - dx^2 sin^2 th)),
+// T = kappa c / fs - x sin th; weights are recomputed exactly per pixel, so
+// rounding in the inverse only shifts where the walk starts.
+template <int kS>
+__global__ __launch_bounds__(256) void k_das_adjoint(const float2* __restrict__ giq,
+                                                     float2* __restrict__ gA, ProbeView p,
+                                                     GridView g, TxTable tx, int tx_base) {
+  const int txl = blockIdx.x / p.n_elem;
+  const int e = blockIdx.x % p.n_elem;
+  const int k_a = threadIdx.x * kS;
+  float2 acc[kS];
+#pragma unroll
+  for (int s = 0; s < kS; ++s) acc[s] = make_float2(0.0f, 0.0f);
+  const double sa = tx.sin_a[txl], ca = tx.cos_a[txl];
+  const double s_per_m = p.fs / p.c_ref, m_per_s = p.c_ref / p.fs;
+  const double xe = ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
+  if (k_a < p.n_t) {
+    for (int a = 0; a < g.n_x; ++a) {
+      const double x = g.x0 + a * g.dx;
+      const double dx = x - xe;
+      // first pixel with kappa > k_a - 1
+      const double T = (double)(k_a - 1) * m_per_s - x * sa;
+      const double disc = T * T - dx * dx * sa * sa;
+      int b = 0;
+      if (T > 0.0 && disc >= 0.0) {
+        const double zs = (T * T - dx * dx) / (T * ca + sqrt(disc));
+        const double bd = floor((zs - g.z0) / g.dz) - 1.0;
+        b = bd > 0.0 ? (bd < (double)g.n_z ? (int)bd : g.n_z) : 0;
+      }
+      const float2* col = giq + (long)a * g.n_z;
+      for (; b < g.n_z; ++b) {
+        const double z = g.z0 + b * g.dz;
+        const double kap = (x * sa + z * ca + sqrt(dx * dx + z * z)) * s_per_m;
+        if (kap >= (double)(k_a + kS)) break;
+        const double rel = kap - (double)k_a;
+        if (rel <= -1.0) continue;
+        const float2 gv = col[b];
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+          const float wt = fmaxf(0.0f, 1.0f - fabsf((float)(rel - (double)s)));
+          acc[s].x = fmaf(wt, gv.x, acc[s].x);
+          acc[s].y = fmaf(wt, gv.y, acc[s].y);
+        }
+      }
+    }
+    float2* row = gA + ((long)(tx_base + txl) * p.n_elem + e) * p.n_t;
+#pragma unroll
+    for (int s = 0; s < kS; ++s)
+      if (k_a + s < p.n_t) row[k_a + s] = acc[s];
+  }
+}
+
+int grid_for(long n, int per_block, int cap) {
+  long gsz = (n + per_block - 1) / per_block;
+  if (gsz < 1) gsz = 1;
+  return (int)(gsz < cap ? gsz : cap);
+}
+
+int log2_exact(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return (1 << l) == n ? l : -1;
+}
+
+}  // namespace
+
+int launch_analytic(const float* rf, float2* A, const float2* twiddle, int n_t, long n_rows,
+                    hipStream_t s) {
+  const int logn = log2_exact(n_t);
+  if (logn < 6 || n_t > kMaxFft) return -1;
+  const size_t lds = (size_t)(n_t + n_t / 2) * sizeof(float2);
+  hipLaunchKernelGGL((k_analytic<true, false>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
+                     (const void*)rf, (void*)A, twiddle, n_t, logn);
+  return 0;
+}
+
+int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddle, int n_t,
+                            long n_rows, hipStream_t s) {
+  const int logn = log2_exact(n_t);
+  if (logn < 6 || n_t > kMaxFft) return -1;
+  const size_t lds = (size_t)(n_t + n_t / 2) * sizeof(float2);
+  hipLaunchKernelGGL((k_analytic<false, true>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
+                     (const void*)g_A, (void*)g_rf, twiddle, n_t, logn);
+  return 0;
+}
+
+void launch_das(const float2* A, float2* iq, const ProbeView& p, const GridView& g,
+                const TxTable& tx, int n_tx_group, int tx_base, bool accumulate, hipStream_t s) {
+  const long n_px = (long)g.n_x * g.n_z;
+  hipLaunchKernelGGL(k_das, dim3((unsigned)((n_px + 255) / 256)), dim3(256), 0, s, A, iq, p, g, tx,
+                     n_tx_group, tx_base, accumulate ? 1 : 0);
+}
+
+void launch_env_max(const float2* iq, long n_px, unsigned long long* key, hipStream_t s) {
+  hipLaunchKernelGGL(k_env_max, dim3(grid_for(n_px, 256, 1024)), dim3(256), 0, s, iq, n_px, key);
+}
+
+void launch_bmode(const float2* iq, long n_px, float dr_db, const unsigned long long* key,
+                  float* bmode, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmode, dim3(grid_for(n_px, 256, 4096)), dim3(256), 0, s, iq, n_px, dr_db,
+                     key, bmode);
+}
+
+void launch_bmode_vjp(const float2* iq, const float* g_b, long n_px, float dr_db,
+                      const unsigned long long* key, double* sum, float2* g_iq, hipStream_t s) {
+  hipLaunchKernelGGL(k_bmode_vjp, dim3(grid_for(n_px, 256, 1024)), dim3(256), 0, s, iq, g_b, n_px,
+                     dr_db, key, sum, g_iq);
+}
+
+void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long* key,
+                          const double* sum, float2* g_iq, hipStream_t s) {
+  (void)n_px;
+  hipLaunchKernelGGL(k_bmode_vjp_fix, dim3(1), dim3(1), 0, s, iq, key, sum, g_iq);
+}
+
+void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, const GridView& g,
+                        const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s) {
+  const dim3 grid((unsigned)(n_tx_group * p.n_elem)), block(256);
+  const int per_thread = (p.n_t + 255) / 256;
+  if (per_thread <= 8)
+    hipLaunchKernelGGL(k_das_adjoint<8>, grid, block, 0, s, g_iq, g_A, p, g, tx, tx_base);
+  else if (per_thread <= 16)
+    hipLaunchKernelGGL(k_das_adjoint<16>, grid, block, 0, s, g_iq, g_A, p, g, tx, tx_base);
+  else
+    hipLaunchKernelGGL(k_das_adjoint<32>, grid, block, 0, s, g_iq, g_A, p, g, tx, tx_base);
+}
+
+int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps_reversed, int M, int n_t,
+                         long n_rows, hipStream_t s) {
+  return launch_pulse(g_rf, g_h, taps_reversed, M, n_t, n_rows, s);
+}
+
+}  // namespace usrt

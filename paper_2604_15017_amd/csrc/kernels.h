@@ -1,0 +1,75 @@
+// Internal interface between the C-ABI (api.hip) and the kernels.
+#pragma once
+
+#include "common.h"
+
+namespace usrt {
+
+// Live-ray queue, structure of arrays (coalesced per field).
+struct RayQueue {
+  double *ox, *oy, *oz, *dx, *dy, *dz, *t, *w;
+  uint32_t* rid;
+  uint32_t* meta;   // region (8 bits) | last event not diffuse << 8 | transmit (local) << 12
+};
+constexpr size_t kRayQueueBytesPerRay = 8 * sizeof(double) + 2 * sizeof(uint32_t);
+
+// Secondary-ray queue.
+struct SecondaryQueue {
+  double *x, *y, *z, *t, *amp;
+  uint32_t* rid;
+  uint32_t* meta;   // region (8 bits) | element << 8
+  uint32_t* txk;    // transmit (local, 16 bits) | interaction index << 16
+};
+constexpr size_t kSecondaryBytesPerRay = 5 * sizeof(double) + 3 * sizeof(uint32_t);
+
+struct TraceArgs {
+  SceneView scene;
+  ProbeView probe;
+  TxTable tx;             // the transmits of this launch group
+  uint64_t seed;
+  int rays_per_elem;
+  int max_bounces;
+  long ray_begin, ray_count;
+  long g0, n_chunk;       // chunk of the flattened (local transmit, ray) index space
+  int tx_base;            // index of the group's first transmit in the caller's list
+  RayQueue qin, qout;
+  SecondaryQueue nee;
+  // counts[k], k = 1..max_bounces + 1: rays alive after interaction k (low 32
+  // bits) and secondary rays spawned at interaction k (high 32 bits)
+  unsigned long long* counts;
+  float* h;               // deposit histogram [n_tx][n_elem][n_t]
+  unsigned long long* counters;   // optional int64[5]
+  unsigned long long* hash;       // optional [n_tx][ray_count]
+};
+
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
+void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
+void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
+int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,
+                 hipStream_t s);
+
+// ---------------------------------------------------------------- image chain
+struct GridView {
+  int n_x, n_z;
+  double x0, dx, z0, dz;
+};
+
+int launch_analytic(const float* rf, float2* A, const float2* twiddle, int n_t, long n_rows,
+                    hipStream_t s);
+void launch_das(const float2* A, float2* iq, const ProbeView& p, const GridView& g,
+                const TxTable& tx, int n_tx_group, int tx_base, bool accumulate, hipStream_t s);
+void launch_env_max(const float2* iq, long n_px, unsigned long long* key, hipStream_t s);
+void launch_bmode(const float2* iq, long n_px, float dr_db, const unsigned long long* key,
+                  float* bmode, hipStream_t s);
+void launch_bmode_vjp(const float2* iq, const float* g_b, long n_px, float dr_db,
+                      const unsigned long long* key, double* sum, float2* g_iq, hipStream_t s);
+void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long* key,
+                          const double* sum, float2* g_iq, hipStream_t s);
+void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, const GridView& g,
+                        const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s);
+int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddle, int n_t,
+                            long n_rows, hipStream_t s);
+int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps, int M, int n_t,
+                         long n_rows, hipStream_t s);
+
+}  // namespace usrt

@@ -1,0 +1,417 @@
+// Forward Monte-Carlo transport for gfx950 (paper Sec. 2.3), wavefront style:
+// one launch per interaction index k, each consuming a compacted queue of
+// live rays in HBM and producing the next one, plus one launch per k for the
+// receiver-directed secondary rays spawned at diffuse-capable hits. Deposits
+// are splatted with a linear tent into an fp32 histogram h[tx][elem][sample]
+// with hardware fp32 atomics; a final FIR applies the pulse of Eq. axial_sig.
+//
+// Precision: positions, directions, times and weights are fp64 (MI355X runs
+// fp64 vector math at half the fp32 rate). A time error dt costs 2 pi f0 dt of
+// phase, and the parity bound on RF needs dt of a few ps over paths tens of
+// millimetres long, which fp32 geometry cannot hold.
+#include "kernels.h"
+
+namespace usrt {
+
+namespace {
+
+struct Hit { int kind; int index; double t; };
+
+// Closest surface along o + t d with t > kTMin among the planes, the spheres
+// and, when `with_array` and the ray moves up, the array face z = 0.
+__device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool with_array) {
+  Hit h{kHitNone, -1, 0.0};
+  double best = INFINITY;
+  if (d.z != 0.0) {
+    const double inv = 1.0 / d.z;
+    for (int k = 0; k < s.n_planes; ++k) {
+      const double t = (s.pd[k] - o.z) * inv;
+      if (t > kTMin && t < best) { best = t; h = Hit{kHitPlane, k, t}; }
+    }
+    if (with_array && d.z < 0.0) {
+      const double t = -o.z * inv;
+      if (t > kTMin && t < best) { best = t; h = Hit{kHitArray, -1, t}; }
+    }
+  }
+  for (int k = 0; k < s.n_spheres; ++k) {
+    const d3 oc{o.x - s.sx[k], o.y - s.sy[k], o.z - s.sz[k]};
+    const double b = dot(oc, d);
+    const double disc = b * b - (dot(oc, oc) - s.sr[k] * s.sr[k]);
+    if (disc < 0.0) continue;
+    const double q = sqrt(disc);
+    const double t1 = -b - q;
+    const double t = t1 > kTMin ? t1 : -b + q;
+    if (t > kTMin && t < best) { best = t; h = Hit{kHitSphere, k, t}; }
+  }
+  return h;
+}
+
+struct Surface { d3 n; int other; double kd; };
+
+__device__ __forceinline__ Surface surface_of(const SceneLDS& s, const Hit& h, d3 x, int region) {
+  Surface f;
+  if (h.kind == kHitPlane) {
+    f.n = d3{0.0, 0.0, 1.0};
+    f.other = region == s.pr[h.index][0] ? s.pr[h.index][1] : s.pr[h.index][0];
+    f.kd = s.pkd[h.index];
+  } else {
+    const double ir = 1.0 / s.sr[h.index];
+    f.n = d3{(x.x - s.sx[h.index]) * ir, (x.y - s.sy[h.index]) * ir, (x.z - s.sz[h.index]) * ir};
+    f.other = region == s.sreg[h.index][0] ? s.sreg[h.index][1] : s.sreg[h.index][0];
+    f.kd = s.skd[h.index];
+  }
+  return f;
+}
+
+// Interface coefficients for direction d across normal n (any orientation),
+// from medium (c1, Z1) into (c2, Z2): n_r faces the incident side; Snell from
+// the sound-speed ratio; pressure coefficients from the impedances.
+struct Coef { d3 nr; double ci, ct, Ar, At, RE; bool tir; };
+
+__device__ __forceinline__ Coef coefficients(d3 d, d3 n, double c1, double Z1, double c2, double Z2) {
+  Coef f;
+  const double dn = dot(n, d);
+  f.nr = dn > 0.0 ? d3{-n.x, -n.y, -n.z} : n;
+  f.ci = dn > 0.0 ? dn : -dn;
+  const double eta = c2 / c1;
+  const double s2 = eta * eta * (1.0 - f.ci * f.ci);
+  if (s2 >= 1.0) {
+    f.tir = true; f.ct = 0.0; f.Ar = 1.0; f.At = 0.0; f.RE = 1.0;
+    return f;
+  }
+  f.tir = false;
+  f.ct = sqrt(1.0 - s2);
+  const double zi = Z2 * f.ci, zt = Z1 * f.ct;
+  const double inv = 1.0 / (zi + zt);
+  f.Ar = (zi - zt) * inv;
+  f.At = 2.0 * zi * inv;
+  f.RE = f.Ar * f.Ar;
+  return f;
+}
+
+__device__ __forceinline__ void splat(float* h, long row, int n_t, double fs, double t, double a) {
+  const double x = t * fs;
+  if (!(x > -1.0 && x < (double)n_t)) return;   // also rejects NaN
+  const double j0d = floor(x);
+  const double f = x - j0d;
+  const int j0 = (int)j0d;
+  float* r = h + row * (long)n_t;
+  if (j0 >= 0) unsafeAtomicAdd(r + j0, (float)(a * (1.0 - f)));
+  if (j0 + 1 < n_t) unsafeAtomicAdd(r + j0 + 1, (float)(a * f));
+}
+
+__device__ __forceinline__ double elem_x(const ProbeView& p, int e) {
+  return ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
+}
+
+// Block-level reduction of the event counters into the global int64[5]:
+// primary segments, secondary segments, deposits, interactions, secondary rays.
+__device__ __forceinline__ void flush_counters(unsigned long long* g, unsigned long long c0,
+                                               unsigned long long c1, unsigned long long c2,
+                                               unsigned long long c3, unsigned long long c4) {
+  __shared__ unsigned long long acc[5];
+  if (threadIdx.x < 5) acc[threadIdx.x] = 0;
+  __syncthreads();
+  if (c0) atomicAdd(&acc[0], c0);
+  if (c1) atomicAdd(&acc[1], c1);
+  if (c2) atomicAdd(&acc[2], c2);
+  if (c3) atomicAdd(&acc[3], c3);
+  if (c4) atomicAdd(&acc[4], c4);
+  __syncthreads();
+  if (threadIdx.x < 5 && acc[threadIdx.x]) atomicAdd(&g[threadIdx.x], acc[threadIdx.x]);
+}
+
+}  // namespace
+
+// One interaction step for every live ray (k = 1 fuses the emission).
+template <bool kAudit>
+__global__ __launch_bounds__(256) void k_bounce(TraceArgs a, int k) {
+  const long n_in = k == 1 ? a.n_chunk : (long)(uint32_t)a.counts[k - 1];
+  if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
+  __shared__ SceneLDS S;
+  __shared__ unsigned long long scan[8];
+  load_scene(S, a.scene);
+  const ProbeView& P = a.probe;
+  const long stride = (long)gridDim.x * blockDim.x;
+  unsigned long long n_seg = 0, n_dep = 0, n_int = 0;
+
+  // block-uniform loop: the queue append below synchronises the block
+  for (long base = (long)blockIdx.x * blockDim.x; base < n_in; base += stride) {
+    const long i = base + threadIdx.x;
+    const bool active = i < n_in;
+    d3 o{0, 0, 0}, d{0, 0, 1};
+    double t = 0.0, w = 0.0;
+    uint32_t rid = 0, meta = 0;
+    if (active) {
+      if (k == 1) {
+        const long g = a.g0 + i;
+        const int txl = (int)(g / a.ray_count);
+        rid = (uint32_t)(a.ray_begin + g % a.ray_count);
+        const int e = (int)(rid / (uint32_t)a.rays_per_elem);
+        const Draw u = draw(a.seed, rid, a.tx.id[txl], 0);
+        const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
+        o = d3{elem_x(P, e) + (u.u0 - 0.5) * P.elem_w, (u.u1 - 0.5) * P.elem_h, 0.0};
+        d = d3{sa, 0.0, ca};
+        t = o.x * (sa / P.c_ref);
+        w = fmax(0.0, ca) / (double)a.rays_per_elem;
+        meta = (uint32_t)S.start_region | (1u << 8) | ((uint32_t)txl << 12);
+      } else {
+        o = d3{a.qin.ox[i], a.qin.oy[i], a.qin.oz[i]};
+        d = d3{a.qin.dx[i], a.qin.dy[i], a.qin.dz[i]};
+        t = a.qin.t[i];
+        w = a.qin.w[i];
+        rid = a.qin.rid[i];
+        meta = a.qin.meta[i];
+      }
+    }
+    int region = meta & 0xFF;
+    bool delta = (meta >> 8) & 1u;
+    const int txl = (int)(meta >> 12);
+    bool keep = false, push_nee = false;
+    d3 x{0, 0, 0};
+    double nee_amp = 0.0;
+    int nee_e = 0;
+    const int incident_region = region;   // the secondary ray starts in this medium
+    uint64_t hsum = 0;
+
+    if (active) {
+      const Hit h = closest_hit(S, o, d, true);
+      ++n_seg;
+      if (kAudit) hsum += event_mix(kEvHit, k, ((uint32_t)h.kind << 24) | ((uint32_t)(h.index + 1) & 0xFFFFFFu));
+      if (h.kind != kHitNone) {
+        t += h.t / S.c[region];
+        w *= exp(-(S.a[region] * h.t));
+        x = o + d * h.t;
+        if (h.kind == kHitArray) {
+          const double half = 0.5 * (double)P.n_elem * P.pitch;
+          if (delta && fabs(x.x) < half && fabs(x.y) < 0.5 * P.elem_h) {
+            int e = (int)floor((x.x + half) / P.pitch);
+            e = min(max(e, 0), P.n_elem - 1);
+            if (kAudit) hsum += event_mix(kEvArray, k, (uint32_t)e);
+            const double fd = rx_directivity(P, -d.z);
+            if (fd > 0.0) {
+              splat(a.h, (long)(a.tx_base + txl) * P.n_elem + e, P.n_t, P.fs, t, w * fd);
+              ++n_dep;
+            }
+          } else if (kAudit) {
+            hsum += event_mix(kEvArray, k, 0xFFFFFFu);
+          }
+        } else if (k <= a.max_bounces) {
+          ++n_int;
+          const Surface sf = surface_of(S, h, x, region);
+          const Coef f = coefficients(d, sf.n, S.c[region], S.Z[region], S.c[sf.other], S.Z[sf.other]);
+          const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
+          if (sf.kd > 0.0) {
+            // receiver-directed secondary ray: weight of everything but the
+            // crossings; the march runs in k_secondary
+            nee_e = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
+            const d3 dv = d3{elem_x(P, nee_e), 0.0, 0.0} - x;
+            const double r = sqrt(dot(dv, dv));
+            const d3 we = dv * (1.0 / r);
+            const double cos_o = dot(f.nr, we);
+            if (cos_o <= 0.0) {
+              if (kAudit) hsum += event_mix(kEvNee, k, (uint32_t)nee_e | (1u << 16));
+            } else {
+              const double cos_el = -we.z;
+              const double fd = rx_directivity(P, cos_el);
+              if (fd == 0.0) {
+                if (kAudit) hsum += event_mix(kEvNee, k, (uint32_t)nee_e | (2u << 16));
+              } else {
+                nee_amp = w * f.Ar * (sf.kd / kPi) * cos_o *
+                          (P.elem_w * P.elem_h * cos_el / (r * r)) * (double)P.n_elem * fd;
+                push_nee = true;
+              }
+            }
+          }
+          // branch on the energy split; weight times coefficient / probability
+          const double p_spec = (1.0 - sf.kd) * f.RE;
+          uint32_t branch;
+          if (v.u0 < p_spec) {
+            d = d + f.nr * (2.0 * f.ci);
+            w *= f.Ar / f.RE;
+            delta = true; branch = 0;
+          } else if (v.u0 < f.RE) {
+            // cosine lobe about n_r in the frame of Duff et al. (JCGT 2017)
+            const d3 n = f.nr;
+            const double sg = n.z >= 0.0 ? 1.0 : -1.0;
+            const double aa = -1.0 / (sg + n.z);
+            const double bb = n.x * n.y * aa;
+            const d3 b1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
+            const d3 b2{bb, sg + n.y * n.y * aa, -n.y};
+            const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
+            const double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(1.0 - v.u2);
+            d = b1 * lx + b2 * ly + n * lz;
+            w *= f.Ar / f.RE;
+            delta = false; branch = 1;
+          } else {
+            const double eta = S.c[sf.other] / S.c[region];
+            d = d * eta + f.nr * (eta * f.ci - f.ct);
+            w *= f.At / (1.0 - f.RE);
+            region = sf.other;
+            delta = true; branch = 2;
+          }
+          if (kAudit) hsum += event_mix(kEvBranch, k, branch | (f.tir ? 0x10u : 0u));
+          keep = true;
+        }
+      }
+      if (kAudit && hsum) atomicAdd(a.hash + (long)(a.tx_base + txl) * a.ray_count + (rid - a.ray_begin), (unsigned long long)hsum);
+    }
+
+    const Slots sl = block_append2(keep, push_nee, &a.counts[k], scan);
+    const long slot = sl.a;
+    if (slot >= 0) {
+      a.qout.ox[slot] = x.x; a.qout.oy[slot] = x.y; a.qout.oz[slot] = x.z;
+      a.qout.dx[slot] = d.x; a.qout.dy[slot] = d.y; a.qout.dz[slot] = d.z;
+      a.qout.t[slot] = t; a.qout.w[slot] = w;
+      a.qout.rid[slot] = rid;
+      a.qout.meta[slot] = (uint32_t)region | ((uint32_t)delta << 8) | ((uint32_t)txl << 12);
+    }
+    const long ns = sl.b;
+    if (ns >= 0) {
+      a.nee.x[ns] = x.x; a.nee.y[ns] = x.y; a.nee.z[ns] = x.z;
+      a.nee.t[ns] = t; a.nee.amp[ns] = nee_amp;
+      a.nee.rid[ns] = rid;
+      a.nee.meta[ns] = (uint32_t)incident_region | ((uint32_t)nee_e << 8);
+      a.nee.txk[ns] = (uint32_t)txl | ((uint32_t)k << 16);
+    }
+  }
+  if (a.counters) flush_counters(a.counters, n_seg, 0, n_dep, n_int, 0);
+}
+
+// Receiver-directed secondary rays spawned at interaction k: straight to the
+// element centre through every crossed interface (transmission coefficient
+// each, zero on total internal reflection), attenuation and travel time per
+// medium, then the deposit.
+template <bool kAudit>
+__global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
+  const long n_in = (long)(a.counts[k] >> 32);
+  if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
+  __shared__ SceneLDS S;
+  load_scene(S, a.scene);
+  const ProbeView& P = a.probe;
+  unsigned long long n_seg = 0, n_dep = 0, n_rays = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n_in;
+       i += (long)gridDim.x * blockDim.x) {
+    ++n_rays;
+    const d3 x{a.nee.x[i], a.nee.y[i], a.nee.z[i]};
+    double tof = a.nee.t[i], amp = a.nee.amp[i];
+    const uint32_t meta = a.nee.meta[i], txk = a.nee.txk[i];
+    int reg = meta & 0xFF;
+    const int e2 = (int)(meta >> 8);
+    const int txl = (int)(txk & 0xFFFF);
+    const d3 dv = d3{elem_x(P, e2), 0.0, 0.0} - x;
+    const double r = sqrt(dot(dv, dv));
+    const d3 we = dv * (1.0 / r);
+    d3 p = x;
+    double remaining = r;
+    uint32_t crossings = 0;
+    bool blocked = false;
+    // a straight segment crosses each plane once and each sphere twice; the
+    // cap only guards against non-finite geometry
+    const int max_legs = S.n_planes + 2 * S.n_spheres + 1;
+    for (int leg = 0; leg <= max_legs; ++leg) {
+      const Hit h = closest_hit(S, p, we, false);
+      ++n_seg;
+      if (h.kind == kHitNone || h.t >= remaining) {
+        tof += remaining / S.c[reg];
+        amp *= exp(-(S.a[reg] * remaining));
+        break;
+      }
+      tof += h.t / S.c[reg];
+      amp *= exp(-(S.a[reg] * h.t));
+      remaining -= h.t;
+      p = p + we * h.t;
+      const Surface sf = surface_of(S, h, p, reg);
+      const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[sf.other], S.Z[sf.other]);
+      ++crossings;
+      if (g.tir) { blocked = true; break; }
+      amp *= g.At;
+      reg = sf.other;
+    }
+    if (!blocked) {
+      splat(a.h, (long)(a.tx_base + txl) * P.n_elem + e2, P.n_t, P.fs, tof, amp);
+      ++n_dep;
+    }
+    if (kAudit) {
+      const uint32_t word = blocked ? ((uint32_t)e2 | (3u << 16) | (crossings << 20))
+                                    : ((uint32_t)e2 | (crossings << 20));
+      atomicAdd(a.hash + (long)(a.tx_base + txl) * a.ray_count + (a.nee.rid[i] - a.ray_begin),
+                (unsigned long long)event_mix(kEvNee, txk >> 16, word));
+    }
+  }
+  if (a.counters) flush_counters(a.counters, 0, n_seg, n_dep, 0, n_rays);
+}
+
+// rf[row][k] = sum_{|m| <= M} h[row][k - m] s[m]  (Eq. axial_sig as a FIR on
+// the deposit histogram; h is zero outside [0, n_t)). One block computes a
+// tile of kPulseTile outputs of one row from an LDS copy of the tile + halo.
+constexpr int kPulseTile = 1024;
+constexpr int kMaxTaps = 512;
+
+__global__ __launch_bounds__(256) void k_pulse(const float* __restrict__ h, float* __restrict__ rf,
+                                               const float* __restrict__ taps, int M, int n_t,
+                                               int tiles_per_row) {
+  __shared__ float sh[kPulseTile + 2 * kMaxTaps];
+  __shared__ float st[2 * kMaxTaps + 1];
+  const long row = blockIdx.x / tiles_per_row;
+  const int k0 = (blockIdx.x % tiles_per_row) * kPulseTile;
+  const float* hr = h + row * (long)n_t;
+  const int span = kPulseTile + 2 * M;
+  for (int j = threadIdx.x; j < span; j += blockDim.x) {
+    const int src = k0 - M + j;
+    sh[j] = (src >= 0 && src < n_t) ? hr[src] : 0.0f;
+  }
+  for (int j = threadIdx.x; j < 2 * M + 1; j += blockDim.x) st[j] = taps[j];
+  __syncthreads();
+  for (int j = threadIdx.x; j < kPulseTile; j += blockDim.x) {
+    const int kk = k0 + j;
+    if (kk >= n_t) break;
+    // output kk reads h[kk - m] = sh[j + M - m], m = -M..M
+    float acc = 0.0f;
+    for (int m = 0; m <= 2 * M; ++m) acc = fmaf(sh[j + 2 * M - m], st[m], acc);
+    rf[row * (long)n_t + kk] = acc;
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+static int grid_for(long n, int per_block, int cap) {
+  long g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  return (int)(g < cap ? g : cap);
+}
+
+void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+}
+
+// Grids are capped at a few blocks per compute unit; the kernels loop.
+constexpr int kMaxBlocks = 2048;
+
+void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {
+  const dim3 grid(grid_for(max_rays, 256, kMaxBlocks)), block(256);
+  if (audit) hipLaunchKernelGGL(k_bounce<true>, grid, block, 0, s, a, k);
+  else hipLaunchKernelGGL(k_bounce<false>, grid, block, 0, s, a, k);
+}
+
+void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {
+  const dim3 grid(grid_for(max_rays, 256, kMaxBlocks)), block(256);
+  if (audit) hipLaunchKernelGGL(k_secondary<true>, grid, block, 0, s, a, k);
+  else hipLaunchKernelGGL(k_secondary<false>, grid, block, 0, s, a, k);
+}
+
+int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,
+                 hipStream_t s) {
+  if (M > kMaxTaps - 1) return -1;
+  const int tiles = (n_t + kPulseTile - 1) / kPulseTile;
+  hipLaunchKernelGGL(k_pulse, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, h, rf, taps, M,
+                     n_t, tiles);
+  return 0;
+}
+
+}  // namespace usrt

@@ -1,0 +1,214 @@
+"""GPU parity of the forward path through the C-ABI against the FP64 oracle.
+
+Tolerances: RF relative L2 <= 1e-4; B-mode <= 0.05 dB wherever either image
+is above the -60 dB floor; paths whose discrete decisions differ (per-ray
+decision hashes) <= 1e-5 of all rays; segment counts identical."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_15017_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RF_TOL = 1e-4
+DB_TOL = 0.05
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2604_15017_amd import _lib
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    return L.Context(0)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def db_err(a, b, dr=60.0):
+    live = (a > -dr) | (b > -dr)
+    return float(np.abs(a - b)[live].max()) if live.any() else 0.0
+
+
+def gpu_trace(L, ctx, wl, audit=False, ray_begin=0, ray_count=None, workspace=None):
+    import torch
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    if ray_count is None:
+        ray_count = wl.rays_per_tx - ray_begin
+    counters = torch.zeros(5, dtype=torch.int64, device="cuda")
+    hashes = torch.zeros((wl.n_tx, ray_count), dtype=torch.int64, device="cuda") if audit else None
+    rf = L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                          wl.max_bounces, ray_begin=ray_begin, ray_count=ray_count,
+                          counters=counters, ray_hash=hashes, workspace=workspace)
+    torch.cuda.synchronize()
+    out = dict(rf=rf.cpu().numpy().astype(np.float64), counters=counters.cpu().numpy())
+    if audit:
+        out["hashes"] = hashes.cpu().numpy().view(np.uint64)
+    return out
+
+
+def check_transport(L, ctx, wl, **kw):
+    g = gpu_trace(L, ctx, wl, audit=True, **kw)
+    rf, h, tr = oracle.simulate_rf(wl, want_hashes=True, **kw)
+    rel = rel_l2(g["rf"], rf)
+    flips = int(np.count_nonzero(g["hashes"] != tr.hashes))
+    frac = flips / tr.hashes.size
+    print(f"{wl.name}: rf rel-L2 {rel:.3e}, flipped paths {flips}/{tr.hashes.size}, "
+          f"segments gpu {g['counters'][0] + g['counters'][1]} oracle {tr.segments}", flush=True)
+    assert frac <= 1e-5
+    assert rel <= RF_TOL
+    if flips == 0:
+        assert g["counters"][0] + g["counters"][1] == tr.segments
+        assert g["counters"][2] == tr.t.shape[0]
+    return g, rf
+
+
+def test_two_layer_full_size(L, ctx):
+    check_transport(L, ctx, W.two_layer())
+
+
+def test_layered_phantom_reduced_rays(L, ctx):
+    wl = W.layered_phantom()
+    check_transport(L, ctx, wl.replace(rays_per_elem=128))
+
+
+def test_layered_phantom_full_size(L, ctx):
+    """The benchmark workload itself: 11 transmits x 2^20 rays, 8 bounces."""
+    check_transport(L, ctx, W.layered_phantom())
+
+
+def test_ragged_ray_range_and_subsets_add_up(L, ctx):
+    wl = W.layered_phantom().replace(rays_per_elem=64, angles=np.radians([-7.0, 3.0]),
+                                     tx_ids=np.array([4, 9], dtype=np.uint32))
+    n = wl.rays_per_tx
+    # a ragged range that is not a multiple of the block or wave size
+    check_transport(L, ctx, wl, ray_begin=37, ray_count=n - 37 - 1001)
+    a = gpu_trace(L, ctx, wl, ray_begin=0, ray_count=3001)["rf"]
+    b = gpu_trace(L, ctx, wl, ray_begin=3001, ray_count=n - 3001)["rf"]
+    full = gpu_trace(L, ctx, wl)["rf"]
+    assert rel_l2(a + b, full) <= 1e-6
+
+
+def test_empty_ray_range_and_zero_bounces(L, ctx):
+    wl = W.layered_phantom().replace(rays_per_elem=16, angles=np.radians([0.0]),
+                                     tx_ids=np.array([0], dtype=np.uint32))
+    g = gpu_trace(L, ctx, wl, ray_begin=5, ray_count=0)
+    assert not g["rf"].any() and g["counters"].sum() == 0
+    wl0 = wl.replace(max_bounces=0)
+    g0 = gpu_trace(L, ctx, wl0)
+    rf0, _, tr0 = oracle.simulate_rf(wl0)
+    assert not g0["rf"].any() and not rf0.any()
+    assert g0["counters"][0] == tr0.segments
+
+
+def test_small_workspace_forces_chunks(L, ctx):
+    import torch
+    wl = W.layered_phantom().replace(rays_per_elem=96, angles=np.radians([-10.0, 0.0, 10.0]),
+                                     tx_ids=np.arange(3, dtype=np.uint32))
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    need = L.us_simulate_rf_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx, wl.max_bounces)
+    hist = wl.n_tx * wl.probe.n_elem * wl.probe.n_t * 4 + 4096   # histogram + counters
+    small = hist + (need - hist) // 7                             # queues for ~1/7 of the rays
+    ws = torch.empty(small, dtype=torch.uint8, device="cuda")
+    g_small = gpu_trace(L, ctx, wl, workspace=ws)["rf"]
+    g_full = gpu_trace(L, ctx, wl)["rf"]
+    assert rel_l2(g_small, g_full) <= 1e-6
+    rf, _, _ = oracle.simulate_rf(wl)
+    assert rel_l2(g_small, rf) <= RF_TOL
+
+
+def test_invalid_arguments_are_rejected(L, ctx):
+    import torch
+    wl = W.two_layer(rays_per_elem=64)
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    with pytest.raises(L.USError) as e:
+        L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, 0, 64, 4, ray_begin=0,
+                         ray_count=wl.rays_per_tx + 1)
+    assert e.value.code == L.US_EINVAL
+    with pytest.raises(L.USError) as e:
+        L.us_simulate_rf(ctx, scene, probe, [np.pi / 2], [0], 0, 64, 4)
+    assert e.value.code == L.US_EINVAL
+    with pytest.raises(L.USError) as e:
+        L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, 0, 64, 4,
+                         workspace=torch.empty(1024, dtype=torch.uint8, device="cuda"))
+    assert e.value.code == L.US_ETOOBIG
+    bad = W.Scene(regions=np.array([[1480.0, 1.48, 0.0]]), planes=np.array([0.01]),
+                  plane_regions=np.array([[0, 3]], np.int32), plane_kd=np.zeros(1),
+                  spheres=np.zeros((0, 4)), sphere_regions=np.zeros((0, 2), np.int32),
+                  sphere_kd=np.zeros(0))
+    with pytest.raises(L.USError):
+        L.Scene(ctx, bad)
+
+
+# ------------------------------------------------------------------ image chain
+def _gpu_image(L, ctx, wl, rf_np):
+    import torch
+    probe = L.Probe(ctx, wl.probe)
+    rf = torch.tensor(rf_np, dtype=torch.float32, device="cuda")
+    iq = L.us_beamform(ctx, probe, wl.grid, wl.angles, wl.tx_ids, rf)
+    bm = L.us_bmode(ctx, iq, wl.dr_db)
+    torch.cuda.synchronize()
+    iq = iq.cpu().numpy().astype(np.float64)
+    return iq[..., 0] + 1j * iq[..., 1], bm.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("which", ["two_layer", "layered"])
+def test_beamform_and_bmode_on_oracle_rf(L, ctx, which):
+    """Each stage fed the oracle's own input, so a failure points at the stage."""
+    wl = W.two_layer() if which == "two_layer" else W.layered_phantom().replace(rays_per_elem=128)
+    rf, _, _ = oracle.simulate_rf(wl)
+    A = oracle.analytic(rf)
+    I = oracle.das(A, wl.probe, wl.grid, wl.angles)
+    B = oracle.bmode(I, wl.dr_db)
+    Ig, Bg = _gpu_image(L, ctx, wl, rf)
+    rel = rel_l2(Ig, I)
+    err = db_err(Bg, B)
+    print(f"{which}: iq rel-L2 {rel:.3e}, B-mode max dB error {err:.3e}", flush=True)
+    assert rel <= 1e-5
+    assert err <= DB_TOL
+
+
+def test_end_to_end_bmode_full_size(L, ctx):
+    wl = W.two_layer()
+    out = oracle.render(wl)
+    g = gpu_trace(L, ctx, wl)
+    _, Bg = _gpu_image(L, ctx, wl, g["rf"])
+    assert db_err(Bg, out["B"]) <= DB_TOL
+
+
+def test_bmode_vjp_against_oracle(L, ctx):
+    import torch
+    rng = np.random.default_rng(0)
+    wl = W.layered_phantom().replace(rays_per_elem=64)
+    out = oracle.render(wl)
+    I = out["I"]
+    g_B = rng.standard_normal(I.shape)
+    ref = oracle.bmode_vjp(I, g_B, 60.0)
+    iq = torch.tensor(np.stack([I.real, I.imag], -1), dtype=torch.float32, device="cuda")
+    gb = torch.tensor(g_B, dtype=torch.float32, device="cuda")
+    g = L.us_bmode_vjp(ctx, iq, gb, 60.0)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    gc = g[..., 0] + 1j * g[..., 1]
+    assert rel_l2(gc, ref) <= 1e-4
+
+
+def test_beamform_vjp_against_oracle(L, ctx):
+    import torch
+    rng = np.random.default_rng(1)
+    wl = W.layered_phantom().replace(angles=np.radians([-10.0, 2.0, 10.0]),
+                                     tx_ids=np.arange(3, dtype=np.uint32))
+    gI = rng.standard_normal((wl.grid.n_x, wl.grid.n_z)) + 1j * rng.standard_normal((wl.grid.n_x, wl.grid.n_z))
+    ref = oracle.analytic_vjp(oracle.das_vjp(gI, wl.probe, wl.grid, wl.angles, wl.probe.n_t))
+    probe = L.Probe(ctx, wl.probe)
+    giq = torch.tensor(np.stack([gI.real, gI.imag], -1), dtype=torch.float32, device="cuda")
+    g = L.us_beamform_vjp(ctx, probe, wl.grid, wl.angles, wl.tx_ids, giq)
+    torch.cuda.synchronize()
+    assert rel_l2(g.cpu().numpy().astype(np.float64), ref) <= 1e-5

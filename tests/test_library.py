@@ -1,0 +1,35 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, and it
+exports every entry point the header declares."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2604_15017_amd import _lib as L
+
+
+def test_header_declares_the_boundary():
+    names = L.header_symbols()
+    for required in ["us_create", "us_destroy", "us_last_error", "us_probe_upload",
+                     "us_scene_upload", "us_scene_set_params", "us_simulate_rf", "us_beamform",
+                     "us_bmode", "us_bmode_vjp", "us_beamform_vjp", "us_simulate_rf_vjp"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libusrt.so not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in L.header_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(L._SIGNATURES) == set(L.header_symbols())
+
+
+def test_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libusrt.so not built")
+    with pytest.raises(Exception):
+        L.Context(0)
