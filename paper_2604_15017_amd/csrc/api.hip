@@ -316,6 +316,19 @@ void carve_queues(Carver& c, long cap, RayQueue* q0, RayQueue* q1, SecondaryQueu
   nq->rid = c.take<uint32_t>(cap); nq->meta = c.take<uint32_t>(cap); nq->txk = c.take<uint32_t>(cap);
 }
 
+constexpr long kMaxReplayBlocks = 1024;
+
+// Workspace of the replay backward: dL/dh plus one checkpoint per interaction
+// for every thread of the grid.
+size_t replay_bytes(int n_tx, const us_probe* p, int max_bounces, long blocks) {
+  Carver c{nullptr};
+  c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
+  const size_t n = (size_t)blocks * 256 * (max_bounces + 1);
+  for (int f = 0; f < 8; ++f) c.take<double>(n);
+  c.take<uint32_t>(n);
+  return c.off;
+}
+
 size_t queue_bytes(long cap) {
   Carver c{nullptr};
   RayQueue a, b;
@@ -570,9 +583,11 @@ int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid
 
 size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* probe,
                                          int32_t n_tx, int64_t ray_count, int32_t max_bounces) {
-  (void)ray_count; (void)max_bounces;
-  if (!scene || !probe || n_tx < 1) return 0;
-  return align_up((size_t)n_tx * probe->d.n_elem * probe->d.n_t * sizeof(float));
+  if (!scene || !probe || n_tx < 1 || ray_count < 0 || max_bounces < 0) return 0;
+  const int group = n_tx < kMaxTxPerLaunch ? n_tx : kMaxTxPerLaunch;
+  long blocks = (long)(((int64_t)group * ray_count + 255) / 256);
+  blocks = std::max(1L, std::min(blocks, kMaxReplayBlocks));
+  return replay_bytes(n_tx, probe, max_bounces, blocks);
 }
 
 int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
@@ -580,10 +595,53 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
                        int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
                        const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
                        void* stream) {
-  (void)ctx; (void)scene; (void)probe; (void)tx; (void)n_tx; (void)seed; (void)rays_per_elem;
-  (void)ray_begin; (void)ray_count; (void)max_bounces; (void)g_rf_dev; (void)g_theta_dev;
-  (void)ws_dev; (void)ws_bytes; (void)stream;
-  return fail(US_EINVAL, "us_simulate_rf_vjp: not available in this build");
+  US_CHECK(ctx && g_rf_dev && g_theta_dev && ws_dev, "us_simulate_rf_vjp: NULL argument");
+  int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
+  if (rc) return rc;
+  long blocks = 0;
+  while (blocks < kMaxReplayBlocks && replay_bytes(n_tx, probe, max_bounces, blocks + 1) <= ws_bytes)
+    ++blocks;
+  if (blocks < 1) return fail(US_ETOOBIG, "us_simulate_rf_vjp: workspace too small");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const us_probe_desc& pd = probe->d;
+  const long cap = blocks * 256;
+  Carver c{(char*)ws_dev};
+  float* gh = c.take<float>((size_t)n_tx * pd.n_elem * pd.n_t);
+  ReplayArgs a{};
+  ReplayStack& k = a.stk;
+  const size_t n = (size_t)cap * (max_bounces + 1);
+  k.ox = c.take<double>(n); k.oy = c.take<double>(n); k.oz = c.take<double>(n);
+  k.dx = c.take<double>(n); k.dy = c.take<double>(n); k.dz = c.take<double>(n);
+  k.t = c.take<double>(n); k.w = c.take<double>(n);
+  k.meta = c.take<uint32_t>(n);
+  {
+    Timed tm(ctx, "pulse_adjoint", s);
+    if (launch_pulse_adjoint(g_rf_dev, gh, probe->taps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
+      return fail(US_EINVAL, "us_simulate_rf_vjp: pulse too long");
+  }
+  a.scene = scene_view(scene, probe);
+  a.probe = probe->pv;
+  a.seed = seed;
+  a.rays_per_elem = rays_per_elem;
+  a.max_bounces = max_bounces;
+  a.ray_begin = ray_begin;
+  a.ray_count = ray_count;
+  a.n_params = scene->n_params;
+  a.gh = gh;
+  a.g_theta = g_theta_dev;
+  for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    fill_tx(a.tx, tx, t0, ng);
+    a.tx_base = t0;
+    a.g0 = 0;
+    a.n_chunk = (long)ng * ray_count;
+    const int nb = (int)std::min<long>(blocks, (a.n_chunk + 255) / 256);
+    Timed tm(ctx, "replay", s);
+    launch_replay(a, nb, s);
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
 }
 
 }  // extern "C"

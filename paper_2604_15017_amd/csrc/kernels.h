@@ -42,6 +42,30 @@ struct TraceArgs {
   unsigned long long* hash;       // optional [n_tx][ray_count]
 };
 
+// Per-thread checkpoint stack of the replay: field[step * capacity + slot].
+struct ReplayStack {
+  double *ox, *oy, *oz, *dx, *dy, *dz, *t, *w;
+  uint32_t* meta;   // region | last event not diffuse << 8
+};
+constexpr size_t kReplayBytesPerStep = 8 * sizeof(double) + sizeof(uint32_t);
+
+struct ReplayArgs {
+  SceneView scene;
+  ProbeView probe;
+  TxTable tx;
+  uint64_t seed;
+  int rays_per_elem;
+  int max_bounces;
+  long ray_begin, ray_count;
+  long g0, n_chunk;
+  int tx_base;
+  int n_params;
+  const float* gh;        // dL/dh [n_tx][n_elem][n_t]
+  double* g_theta;        // accumulated
+  ReplayStack stk;
+};
+
+void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s);
 void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);

@@ -1,0 +1,463 @@
+// Backward of the transport by path replay (paper Sec. 3.2, Eq. chain_rule):
+// for fixed random numbers, every ray's path is traced again from its Philox
+// counters with exactly the forward's decisions, and the gradient of
+//   L = sum over deposits of <dL/dh, tent(t fs) a>
+// with respect to the scene parameters is accumulated by reverse-mode
+// differentiation along the path. Nothing is stored between the forward and
+// the backward call; inside this call each thread keeps the exact fp64 state
+// before every interaction of its current path in a private stack in the
+// workspace (structure of arrays, coalesced across threads), then sweeps it
+// backwards. Discrete choices (branch, hit surface, element, total internal
+// reflection, sample index) are frozen; branch probabilities are sampling
+// densities and carry no derivative.
+//
+// Parameter adjoints are summed per block in LDS (fp64 LDS atomics) and
+// flushed with one global fp64 atomic per block and parameter.
+#include "geometry.h"
+#include "kernels.h"
+
+namespace usrt {
+
+namespace {
+
+// Per-block gradient accumulator over the flat parameter vector.
+struct GradAcc {
+  double* g;
+  int n_regions, n_planes;
+  double np_per_m;
+  __device__ void c(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r], v); }
+  __device__ void Z(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 1], v); }
+  // v is the adjoint of the amplitude attenuation a [Np/m]; a = alpha * np_per_m
+  __device__ void a(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 2], v * np_per_m); }
+  __device__ void plane(int k, double v) { if (v != 0.0) atomicAdd(&g[3 * n_regions + k], v); }
+  __device__ void sphere(int k, d3 cbar, double rbar) {
+    double* s = g + 3 * n_regions + n_planes + 4 * k;
+    if (cbar.x != 0.0) atomicAdd(s + 0, cbar.x);
+    if (cbar.y != 0.0) atomicAdd(s + 1, cbar.y);
+    if (cbar.z != 0.0) atomicAdd(s + 2, cbar.z);
+    if (rbar != 0.0) atomicAdd(s + 3, rbar);
+  }
+};
+
+__device__ __forceinline__ d3 operator-(d3 a) { return {-a.x, -a.y, -a.z}; }
+
+// d/dc of the receive directivity (Eq. cutoff) at cosine c; zero outside the ramp.
+__device__ __forceinline__ double rx_directivity_deriv(const ProbeView& p, double cos_a) {
+  const double c = fmin(1.0, fmax(-1.0, cos_a));
+  const double al = acos(c);
+  if (al <= p.alpha_m || al > p.alpha_c) return 0.0;
+  const double s = sqrt(fmax(0.0, 1.0 - c * c));
+  return s > 0.0 ? 1.0 / ((p.alpha_c - p.alpha_m) * s) : 0.0;
+}
+
+// Adjoints (g_a, g_t) of a deposit (t, a) given dL/dh on its row: the tent
+// deposits a (1 - f) at j0 = floor(t fs) and a f at j0 + 1.
+__device__ __forceinline__ void tent_adjoint(const float* row, int n_t, double fs, double t,
+                                             double a, double* ga, double* gt) {
+  const double x = t * fs;
+  if (!(x > -1.0 && x < (double)n_t)) { *ga = 0.0; *gt = 0.0; return; }
+  const double j0d = floor(x);
+  const double f = x - j0d;
+  const int j0 = (int)j0d;
+  const double g0 = j0 >= 0 ? (double)row[j0] : 0.0;
+  const double g1 = j0 + 1 < n_t ? (double)row[j0 + 1] : 0.0;
+  *ga = g0 * (1.0 - f) + g1 * f;
+  *gt = a * fs * (g1 - g0);
+}
+
+// Adjoint of a distance s along (o, d) to the surface of `h`, for a plane
+// s = (z_p - o.z) / d.z, the array face s = -o.z / d.z, or a sphere
+// s = -b + sig sqrt(b^2 - cc), b = (o - C).d, cc = |o - C|^2 - R^2.
+__device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, int idx, double sig,
+                                                  d3 o, d3 d, double s, double sbar, d3& obar,
+                                                  d3& dbar, GradAcc& G) {
+  if (sbar == 0.0) return;
+  if (kind == kHitPlane || kind == kHitArray) {
+    const double inv = 1.0 / d.z;
+    if (kind == kHitPlane) G.plane(idx, sbar * inv);
+    obar.z -= sbar * inv;
+    dbar.z -= sbar * s * inv;
+  } else {
+    const d3 oc{o.x - S.sx[idx], o.y - S.sy[idx], o.z - S.sz[idx]};
+    const double b = dot(oc, d);
+    const double cc = dot(oc, oc) - S.sr[idx] * S.sr[idx];
+    const double q = sqrt(fmax(b * b - cc, 0.0));
+    if (q == 0.0) return;   // tangent ray: measure zero
+    const double bbar = sbar * (-1.0 + sig * b / q);
+    const double ccbar = sbar * (-sig / (2.0 * q));
+    const d3 ocbar = d * bbar + oc * (2.0 * ccbar);
+    dbar = dbar + oc * bbar;
+    obar = obar + ocbar;
+    G.sphere(idx, -ocbar, -2.0 * ccbar * S.sr[idx]);
+  }
+}
+
+// Root sign of the primary intersection, as the forward chose it.
+__device__ __forceinline__ double primary_root(const SceneLDS& S, int idx, d3 o, d3 d) {
+  const d3 oc{o.x - S.sx[idx], o.y - S.sy[idx], o.z - S.sz[idx]};
+  const double b = dot(oc, d);
+  const double disc = b * b - (dot(oc, oc) - S.sr[idx] * S.sr[idx]);
+  const double q = sqrt(disc);
+  return (-b - q > kTMin) ? -1.0 : 1.0;
+}
+
+// Adjoint of the geometric normal at x on the hit surface (plane: constant;
+// sphere: n = (x - C) / R). nbar is the adjoint of n; adds to xbar.
+__device__ __forceinline__ void normal_backward(const SceneLDS& S, int kind, int idx, d3 n,
+                                                d3 nbar, d3& xbar, GradAcc& G) {
+  if (kind != kHitSphere) return;
+  const double ir = 1.0 / S.sr[idx];
+  const d3 t = nbar * ir;
+  xbar = xbar + t;
+  G.sphere(idx, -t, -dot(nbar, n) * ir);
+}
+
+// Adjoint of the pressure coefficients and of cos theta_t: given Abar (total
+// adjoint on A_r and A_t, which differ by the constant 1), ctbar and etabar,
+// returns cibar and adds the impedance and sound-speed adjoints.
+__device__ __forceinline__ double interface_backward(const Coef& f, double eta, int r1, int r2,
+                                                     double Z1, double Z2, double c1, double Abar,
+                                                     double ctbar, double etabar, GradAcc& G) {
+  double cibar = 0.0;
+  if (!f.tir) {
+    const double u = Z2 * f.ci, v = Z1 * f.ct, D = u + v;
+    const double ubar = Abar * 2.0 * v / (D * D);
+    const double vbar = -Abar * 2.0 * u / (D * D);
+    G.Z(r2, ubar * f.ci);
+    cibar += ubar * Z2;
+    G.Z(r1, vbar * f.ct);
+    ctbar += vbar * Z1;
+    if (f.ct > 0.0 && ctbar != 0.0) {   // ct = sqrt(1 - eta^2 (1 - ci^2))
+      const double s2bar = -ctbar / (2.0 * f.ct);
+      etabar += s2bar * 2.0 * eta * (1.0 - f.ci * f.ci);
+      cibar += s2bar * (-2.0 * eta * eta * f.ci);
+    }
+  }
+  if (etabar != 0.0) {   // eta = c2 / c1
+    G.c(r2, etabar / c1);
+    G.c(r1, -etabar * eta / c1);
+  }
+  return cibar;
+}
+
+struct ReplayCtx {
+  const SceneLDS& S;
+  const ProbeView& P;
+  const float* gh;      // dL/dh rows [n_tx][n_elem][n_t]
+  long row_base;        // (tx_base + txl) * n_elem
+  GradAcc& G;
+};
+
+// Secondary ray of interaction k at x (weight watt, time tp, interface f):
+// adds its adjoints to xbar, nrbar, Arbar, wattbar, tpbar and the parameters.
+__device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f, double kd,
+                                   double watt, double tp, int e2, d3& xbar, d3& nrbar,
+                                   double& Arbar, double& wattbar, double& tpbar) {
+  const SceneLDS& S = C.S;
+  const ProbeView& P = C.P;
+  const double xe = ((double)e2 - 0.5 * (double)(P.n_elem - 1)) * P.pitch;
+  const d3 dv = d3{xe, 0.0, 0.0} - x;
+  const double r = sqrt(dot(dv, dv));
+  const d3 we = dv * (1.0 / r);
+  const double co = dot(f.nr, we);
+  if (co <= 0.0) return;
+  const double cel = -we.z;
+  const double fd = rx_directivity(P, cel);
+  if (fd == 0.0) return;
+  const double K = (kd / kPi) * P.elem_w * P.elem_h * (double)P.n_elem;
+  const double amp0 = watt * f.Ar * (kd / kPi) * co * (P.elem_w * P.elem_h * cel / (r * r)) *
+                      (double)P.n_elem * fd;
+  // pass 1: the march as the forward did it
+  const int max_legs = S.n_planes + 2 * S.n_spheres + 1;
+  double tof = tp, rest = 1.0;
+  {
+    d3 p = x;
+    double remaining = r;
+    int reg = region;
+    for (int leg = 0; leg <= max_legs; ++leg) {
+      const Hit h = closest_hit(S, p, we, false);
+      if (h.kind == kHitNone || h.t >= remaining) {
+        tof += remaining / S.c[reg];
+        rest *= exp(-(S.a[reg] * remaining));
+        break;
+      }
+      tof += h.t / S.c[reg];
+      rest *= exp(-(S.a[reg] * h.t));
+      remaining -= h.t;
+      p = p + we * h.t;
+      const Surface sf = surface_of(S, h, p, reg);
+      const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[sf.other], S.Z[sf.other]);
+      if (g.tir) return;   // blocked: no deposit
+      rest *= g.At;
+      reg = sf.other;
+    }
+  }
+  const double amp = amp0 * rest;
+  double GA, GT;
+  tent_adjoint(C.gh + (C.row_base + e2) * (long)P.n_t, P.n_t, P.fs, tof, amp, &GA, &GT);
+  if (GA == 0.0 && GT == 0.0) return;
+  tpbar += GT;
+  const double AA = GA * amp;   // adjoint of log(amplitude)
+  // pass 2: every leg and crossing, with s_j the distance from x
+  d3 webar{0, 0, 0}, xb{0, 0, 0};
+  double rbar = 0.0;
+  {
+    d3 p = x;
+    double remaining = r, s_cum = 0.0;
+    int reg = region;
+    for (int leg = 0; leg <= max_legs; ++leg) {
+      const Hit h = closest_hit(S, p, we, false);
+      if (h.kind == kHitNone || h.t >= remaining) {
+        const double ell = remaining;   // = r - s_J
+        C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
+        C.G.a(reg, -AA * ell);
+        rbar += GT / S.c[reg] - AA * S.a[reg];
+        break;
+      }
+      const double ell = h.t;
+      C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
+      C.G.a(reg, -AA * ell);
+      s_cum += ell;
+      remaining -= ell;
+      p = p + we * ell;
+      const Surface sf = surface_of(S, h, p, reg);
+      const int other = sf.other;
+      const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[other], S.Z[other]);
+      const double eta = S.c[other] / S.c[reg];
+      // distance s_j: the time and attenuation switch medium there
+      double sbar = GT * (1.0 / S.c[reg] - 1.0 / S.c[other]) + AA * (S.a[other] - S.a[reg]);
+      // transmission coefficient of the crossing: d log(amp) / d At = 1 / At
+      const double cibar = interface_backward(g, eta, reg, other, S.Z[reg], S.Z[other], S.c[reg],
+                                              AA / g.At, 0.0, 0.0, C.G);
+      // ci = -nr . we
+      const d3 nrb = we * (-cibar);
+      webar = webar - g.nr * cibar;
+      const double sgn = dot(sf.n, we) > 0.0 ? -1.0 : 1.0;
+      d3 pbar{0, 0, 0};
+      normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, pbar, C.G);
+      // p_j = x + we s_j
+      xb = xb + pbar;
+      webar = webar + pbar * s_cum;
+      sbar += dot(pbar, we);
+      // s_j as a function of (x, we): entering a sphere takes the near root
+      double sig = -1.0;
+      if (h.kind == kHitSphere) sig = (reg == S.sreg[h.index][1]) ? -1.0 : 1.0;
+      distance_backward(S, h.kind, h.index, sig, x, we, s_cum, sbar, xb, webar, C.G);
+      reg = other;
+    }
+  }
+  // amp0 = watt * Ar * (kd/pi) * co * (A_el cel / r^2) * N_e * fd
+  const double A0bar = GA * rest;
+  const double base = K * co * cel * fd / (r * r);
+  wattbar += A0bar * f.Ar * base;
+  Arbar += A0bar * watt * base;
+  const double common = A0bar * watt * f.Ar * K / (r * r);
+  const double cobar = common * cel * fd;
+  const double celbar = common * co * (fd + cel * rx_directivity_deriv(P, cel));
+  rbar += A0bar * watt * f.Ar * base * (-2.0 / r);
+  nrbar = nrbar + we * cobar;
+  webar = webar + f.nr * cobar;
+  webar.z -= celbar;
+  // we = dv / r, r = |dv|, dv = y - x
+  const d3 dvbar = (webar - we * dot(webar, we)) * (1.0 / r) + we * rbar;
+  xbar = xbar + xb - dvbar;
+}
+
+}  // namespace
+
+// One thread per ray: forward replay with checkpoints, then the reverse sweep.
+__global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
+  if ((long)blockIdx.x * blockDim.x >= a.n_chunk) return;
+  __shared__ SceneLDS S;
+  extern __shared__ double gsh[];
+  load_scene(S, a.scene);
+  for (int i = threadIdx.x; i < a.n_params; i += blockDim.x) gsh[i] = 0.0;
+  __syncthreads();
+  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m};
+  const ProbeView& P = a.probe;
+  const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long cap = (long)gridDim.x * blockDim.x;
+  const int B = a.max_bounces;
+
+  for (long i = slot; i < a.n_chunk; i += cap) {
+    const long g = a.g0 + i;
+    const int txl = (int)(g / a.ray_count);
+    const uint32_t rid = (uint32_t)(a.ray_begin + g % a.ray_count);
+    const uint32_t tx_id = a.tx.id[txl];
+    ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G};
+
+    // ---- forward replay, checkpointing the state before each step
+    d3 o, d;
+    double t, w;
+    int region;
+    bool delta;
+    {
+      const int e = (int)(rid / (uint32_t)a.rays_per_elem);
+      const Draw u = draw(a.seed, rid, tx_id, 0);
+      const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
+      o = d3{((double)e - 0.5 * (double)(P.n_elem - 1)) * P.pitch + (u.u0 - 0.5) * P.elem_w,
+             (u.u1 - 0.5) * P.elem_h, 0.0};
+      d = d3{sa, 0.0, ca};
+      t = o.x * (sa / P.c_ref);
+      w = fmax(0.0, ca) / (double)a.rays_per_elem;
+      region = S.start_region;
+      delta = true;
+    }
+    int last = 0;   // last step that can carry a deposit
+    for (int k = 1; k <= B + 1; ++k) {
+      const long at = (long)(k - 1) * cap + slot;
+      a.stk.ox[at] = o.x; a.stk.oy[at] = o.y; a.stk.oz[at] = o.z;
+      a.stk.dx[at] = d.x; a.stk.dy[at] = d.y; a.stk.dz[at] = d.z;
+      a.stk.t[at] = t; a.stk.w[at] = w;
+      a.stk.meta[at] = (uint32_t)region | ((uint32_t)delta << 8);
+      const Hit h = closest_hit(S, o, d, true);
+      if (h.kind == kHitNone) break;
+      if (h.kind == kHitArray) { last = k; break; }
+      if (k > B) break;
+      t += h.t / S.c[region];
+      w *= exp(-(S.a[region] * h.t));
+      const d3 x = o + d * h.t;
+      const Surface sf = surface_of(S, h, x, region);
+      const Coef f = coefficients(d, sf.n, S.c[region], S.Z[region], S.c[sf.other], S.Z[sf.other]);
+      const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
+      const double p_spec = (1.0 - sf.kd) * f.RE;
+      if (v.u0 < p_spec) {
+        d = d + f.nr * (2.0 * f.ci);
+        w *= f.Ar / f.RE;
+        delta = true;
+      } else if (v.u0 < f.RE) {
+        const d3 n = f.nr;
+        const double sg = n.z >= 0.0 ? 1.0 : -1.0;
+        const double aa = -1.0 / (sg + n.z);
+        const double bb = n.x * n.y * aa;
+        const d3 b1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
+        const d3 b2{bb, sg + n.y * n.y * aa, -n.y};
+        const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
+        d = b1 * (rr * cos(phi)) + b2 * (rr * sin(phi)) + n * sqrt(1.0 - v.u2);
+        w *= f.Ar / f.RE;
+        delta = false;
+      } else {
+        const double eta = S.c[sf.other] / S.c[region];
+        d = d * eta + f.nr * (eta * f.ci - f.ct);
+        w *= f.At / (1.0 - f.RE);
+        region = sf.other;
+        delta = true;
+      }
+      o = x;
+      last = k;
+    }
+
+    // ---- reverse sweep
+    d3 ob{0, 0, 0}, db{0, 0, 0};
+    double tb = 0.0, wb = 0.0;
+    for (int k = last; k >= 1; --k) {
+      const long at = (long)(k - 1) * cap + slot;
+      const d3 o0{a.stk.ox[at], a.stk.oy[at], a.stk.oz[at]};
+      const d3 d0{a.stk.dx[at], a.stk.dy[at], a.stk.dz[at]};
+      const double t0 = a.stk.t[at], w0 = a.stk.w[at];
+      const uint32_t meta = a.stk.meta[at];
+      const int reg = meta & 0xFF;
+      const bool dl = (meta >> 8) & 1u;
+      const Hit h = closest_hit(S, o0, d0, true);
+      const double L = h.t, c1 = S.c[reg], ar = S.a[reg];
+      const double E = exp(-(ar * L));
+      const double tp = t0 + L / c1, watt = w0 * E;
+      const d3 x = o0 + d0 * L;
+      d3 xb{0, 0, 0}, d0b{0, 0, 0};
+      double tpb = 0.0, wattb = 0.0;
+      if (h.kind == kHitArray) {
+        const double half = 0.5 * (double)P.n_elem * P.pitch;
+        if (dl && fabs(x.x) < half && fabs(x.y) < 0.5 * P.elem_h) {
+          int e = (int)floor((x.x + half) / P.pitch);
+          e = min(max(e, 0), P.n_elem - 1);
+          const double fd = rx_directivity(P, -d0.z);
+          if (fd > 0.0) {
+            double ga, gt;
+            tent_adjoint(a.gh + (C.row_base + e) * (long)P.n_t, P.n_t, P.fs, tp, watt * fd, &ga, &gt);
+            wattb += ga * fd;
+            d0b.z -= ga * watt * rx_directivity_deriv(P, -d0.z);
+            tpb += gt;
+          }
+        }
+      } else {
+        const Surface sf = surface_of(S, h, x, reg);
+        const int r2 = sf.other;
+        const Coef f = coefficients(d0, sf.n, c1, S.Z[reg], S.c[r2], S.Z[r2]);
+        const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
+        const double eta = S.c[r2] / c1;
+        xb = ob;
+        tpb = tb;
+        d3 nrb{0, 0, 0};
+        double cib = 0.0, ctb = 0.0, etab = 0.0, Ab = 0.0;
+        const double p_spec = (1.0 - sf.kd) * f.RE;
+        if (v.u0 < p_spec) {          // d' = d + 2 ci nr, w' = watt Ar / R_E
+          d0b = d0b + db;
+          cib += 2.0 * dot(db, f.nr);
+          nrb = nrb + db * (2.0 * f.ci);
+          wattb += wb * f.Ar / f.RE;
+          Ab += wb * watt / f.RE;
+        } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
+          const d3 n = f.nr;
+          const double sg = n.z >= 0.0 ? 1.0 : -1.0;
+          const double aa = -1.0 / (sg + n.z);
+          const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
+          const double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(1.0 - v.u2);
+          const double a2 = aa * aa;
+          // Jacobian of d' with respect to (nx, ny, nz), applied transposed to db
+          const double j_xx = lx * 2.0 * sg * n.x * aa + ly * n.y * aa + lz;
+          const double j_xy = ly * n.x * aa;
+          const double j_xz = lx * sg * n.x * n.x * a2 + ly * n.x * n.y * a2;
+          const double j_yx = lx * sg * n.y * aa;
+          const double j_yy = lx * sg * n.x * aa + ly * 2.0 * n.y * aa + lz;
+          const double j_yz = lx * sg * n.x * n.y * a2 + ly * n.y * n.y * a2;
+          const double j_zx = -lx * sg, j_zy = -ly, j_zz = lz;
+          nrb.x += db.x * j_xx + db.y * j_yx + db.z * j_zx;
+          nrb.y += db.x * j_xy + db.y * j_yy + db.z * j_zy;
+          nrb.z += db.x * j_xz + db.y * j_yz + db.z * j_zz;
+          wattb += wb * f.Ar / f.RE;
+          Ab += wb * watt / f.RE;
+        } else {                      // d' = eta d + (eta ci - ct) nr, w' = watt At / (1 - R_E)
+          const double dn = dot(db, f.nr);
+          d0b = d0b + db * eta;
+          etab += dot(db, d0) + f.ci * dn;
+          cib += eta * dn;
+          ctb -= dn;
+          nrb = nrb + db * (eta * f.ci - f.ct);
+          wattb += wb * f.At / (1.0 - f.RE);
+          Ab += wb * watt / (1.0 - f.RE);
+        }
+        if (sf.kd > 0.0) {
+          const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
+          secondary_backward(C, reg, x, f, sf.kd, watt, tp, e2, xb, nrb, Ab, wattb, tpb);
+        }
+        cib += interface_backward(f, eta, reg, r2, S.Z[reg], S.Z[r2], c1, Ab, ctb, etab, G);
+        // ci = -nr . d
+        nrb = nrb - d0 * cib;
+        d0b = d0b - f.nr * cib;
+        const double sgn = dot(sf.n, d0) > 0.0 ? -1.0 : 1.0;
+        normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, xb, G);
+      }
+      // t' = t + L / c, w_att = w exp(-a L), x = o + d L, L = distance(o, d)
+      double Lb = tpb / c1 - wattb * watt * ar + dot(xb, d0);
+      G.c(reg, -tpb * L / (c1 * c1));
+      G.a(reg, -wattb * watt * L);
+      d3 o0b = xb;
+      d0b = d0b + xb * L;
+      const double sig = h.kind == kHitSphere ? primary_root(S, h.index, o0, d0) : -1.0;
+      distance_backward(S, h.kind, h.index, sig, o0, d0, L, Lb, o0b, d0b, G);
+      ob = o0b;
+      db = d0b;
+      tb = tpb;
+      wb = wattb * E;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.n_params; i += blockDim.x)
+    if (gsh[i] != 0.0) atomicAdd(&a.g_theta[i], gsh[i]);
+}
+
+void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay, dim3(blocks), dim3(256), (size_t)a.n_params * sizeof(double), s, a);
+}
+
+}  // namespace usrt
