@@ -42,6 +42,14 @@ def kernel_bytes(name, wl, counts, n_px):
         # each secondary record is read once; each deposit updates two fp32 bins
         "secondary": sec_rec * sec + 8 * dep,
         "pulse": 8 * row_samples,
+        "pulse_adjoint": 8 * row_samples,
+        "analytic_adjoint": 12 * row_samples,
+        "das_adjoint": 8 * row_samples + 8 * n_px,
+        "bmode_vjp": 28 * n_px,
+        "image_loss": 12 * n_px,
+        # the replay reads dL/dh at every deposit (two fp32 bins) and writes and
+        # reads one checkpoint per interaction
+        "replay": 8 * dep + 2 * (8 * 8 + 4) * inter,
         "analytic": 12 * row_samples,
         "das": 8 * row_samples + 8 * n_px,
         "bmode": 20 * n_px,
@@ -100,6 +108,34 @@ def main():
         L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf, iq=iq, workspace=ws_b, stream=stream)
         L.us_bmode(ctx, iq, wl.dr_db, out=bm, workspace=ws_m, stream=stream)
 
+    # forward + backward: B-mode MSE against a target rendered from the
+    # seeded +-5 % perturbation of 34 parameters, gradient for all parameters
+    target = W.layered_phantom_target(wl)
+    scene_t = L.Scene(ctx, target)
+    L.us_simulate_rf(ctx, scene_t, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                     wl.max_bounces, rf=rf, workspace=ws_t, stream=stream)
+    L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf, iq=iq, workspace=ws_b, stream=stream)
+    b_ref = L.us_bmode(ctx, iq, wl.dr_db, workspace=ws_m, stream=stream).clone()
+    del scene_t
+    ws_r = L._workspace(L.us_simulate_rf_vjp_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx,
+                                                            wl.max_bounces), dev)
+    ws_bv = L._workspace(L.load().us_beamform_vjp_workspace_size(probe.handle, wl.n_tx), dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    g_b = torch.empty_like(bm)
+    g_iq = torch.empty_like(iq)
+    g_rf = torch.empty_like(rf)
+    g_theta = torch.zeros(scene.n_params, dtype=torch.float64, device=dev)
+
+    def step_fb():
+        step()
+        L.us_image_loss(ctx, bm, b_ref, 0.0, 1.0, loss=loss, g_bmode=g_b, stream=stream)
+        L.us_bmode_vjp(ctx, iq, g_b, wl.dr_db, g_iq=g_iq, workspace=ws_m, stream=stream)
+        L.us_beamform_vjp(ctx, probe, g, wl.angles, wl.tx_ids, g_iq, g_rf=g_rf, workspace=ws_bv,
+                          stream=stream)
+        g_theta.zero_()
+        L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                             wl.max_bounces, g_rf, g_theta=g_theta, workspace=ws_r, stream=stream)
+
     step(counters)                      # event counts of one frame (deterministic)
     torch.cuda.synchronize()
     counts = [int(v) for v in counters.cpu().numpy()]
@@ -121,6 +157,33 @@ def main():
     prof = L.us_profile_read(ctx)
     L.us_profile_enable(ctx, False)
 
+    # forward + backward, same protocol
+    for _ in range(args.warmup):
+        step_fb()
+    torch.cuda.synchronize()
+    L.us_profile_enable(ctx, True)
+    L.us_profile_read(ctx)
+    start.record(stream)
+    for _ in range(args.steps):
+        step_fb()
+    end.record(stream)
+    torch.cuda.synchronize()
+    fb_ms = start.elapsed_time(end) / args.steps
+    prof_fb = L.us_profile_read(ctx)
+    L.us_profile_enable(ctx, False)
+    fb_kernels = {}
+    for name, (ms, launches) in prof_fb.items():
+        per_step_ms = ms / args.steps
+        nbytes = kernel_bytes(name, wl, counts, g.n_px)
+        fb_kernels[name] = {"ms_per_step": round(per_step_ms, 4),
+                            "launches_per_step": launches // args.steps,
+                            "algorithmic_GBps": round(nbytes / (per_step_ms * 1e-3) / 1e9, 1) if nbytes else None}
+    fwd_bwd = {"workload": "layered_phantom forward + backward, B-mode MSE vs +-5 % target, "
+                           f"gradient of all {scene.n_params} parameters",
+               "ms_per_step": round(fb_ms, 4), "frames_per_s": round(1e3 / fb_ms, 2),
+               "ray_segments_per_s": segments / (fb_ms * 1e-3),
+               "loss": float(loss.item()), "kernels": fb_kernels}
+
     ms_per_step = total_ms / args.steps
     kernels = {}
     for name, (ms, launches) in prof.items():
@@ -140,7 +203,7 @@ def main():
                 "avg_launch_us": round(1e3 * dom_ms / max(1, launches), 2)}
 
     out = {
-        "metric": "ray-segments/s and B-mode frames/s (fwd)",
+        "metric": "ray-segments/s and B-mode frames/s (fwd, fwd+bwd)",
         "value": segments / (ms_per_step * 1e-3),
         "unit": "ray-segments/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -157,6 +220,7 @@ def main():
                          "deposits": counts[2], "interactions": counts[3], "secondary_rays": counts[4]},
         "kernels": kernels,
         "roofline": roofline,
+        "fwd_bwd": fwd_bwd,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -76,6 +76,9 @@ _SIGNATURES = {
     "us_simulate_rf_vjp_workspace_size": (sz, [vp, vp, i32, i64, i32]),
     "us_simulate_rf_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                           vp, sz, vp]),
+    "us_image_loss_workspace_size": (sz, [i64]),
+    "us_image_loss": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp,
+                                     vp, sz, vp]),
     "us_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
     "us_profile_read": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
 }
@@ -257,6 +260,21 @@ def us_bmode(ctx: Context, iq, dr_db: float, out=None, workspace=None, stream=No
     _check(load().us_bmode(ctx.handle, _ptr(iq), n_px, float(dr_db), _ptr(out), _ptr(workspace),
                            workspace.numel(), _stream(stream)), "us_bmode")
     return out
+
+
+def us_image_loss(ctx: Context, bmode, ref, lambda1: float = 0.0, lambda2: float = 1.0,
+                  loss=None, g_bmode=None, want_grad: bool = True, stream=None):
+    """Returns (loss as a 1-element float64 device tensor, dL/dB or None)."""
+    torch = _torch()
+    n_px = bmode.numel()
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=ctx.torch_device)
+    if want_grad and g_bmode is None:
+        g_bmode = torch.empty_like(bmode)
+    _check(load().us_image_loss(ctx.handle, _ptr(bmode), _ptr(ref), n_px, float(lambda1),
+                                float(lambda2), _ptr(loss), _ptr(g_bmode if want_grad else None),
+                                ctypes.c_void_p(0), 0, _stream(stream)), "us_image_loss")
+    return loss, (g_bmode if want_grad else None)
 
 
 def us_bmode_vjp(ctx: Context, iq, g_bmode, dr_db: float, g_iq=None, workspace=None, stream=None):

@@ -548,6 +548,27 @@ int us_bmode_vjp(us_ctx* ctx, const float* iq_dev, const float* g_bmode_dev, int
   return US_OK;
 }
 
+size_t us_image_loss_workspace_size(int64_t n_px) {
+  (void)n_px;
+  return kAlign;
+}
+
+int us_image_loss(us_ctx* ctx, const float* bmode_dev, const float* ref_dev, int64_t n_px,
+                  double lambda1, double lambda2, double* loss_dev, float* g_bmode_dev,
+                  void* ws_dev, size_t ws_bytes, void* stream) {
+  (void)ws_dev; (void)ws_bytes;
+  US_CHECK(ctx && bmode_dev && ref_dev && loss_dev, "us_image_loss: NULL argument");
+  US_CHECK(n_px >= 1, "us_image_loss: n_px must be >= 1");
+  US_CHECK(lambda1 >= 0 && lambda2 >= 0, "us_image_loss: weights must be non-negative");
+  US_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  Timed tm(ctx, "image_loss", s);
+  launch_fill_u32((uint32_t*)loss_dev, 2, 0u, s);
+  launch_image_loss(bmode_dev, ref_dev, n_px, lambda1, lambda2, loss_dev, g_bmode_dev, s);
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
 size_t us_beamform_vjp_workspace_size(const us_probe* probe, int32_t n_tx) {
   return us_beamform_workspace_size(probe, n_tx);
 }

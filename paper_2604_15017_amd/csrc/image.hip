@@ -257,6 +257,29 @@ __global__ __launch_bounds__(256) void k_das_adjoint(const float2* __restrict__ 
   }
 }
 
+// L = (1/n) sum [l1 |d| + l2 d^2], d = B - R; dL/dB = (l1 sign(d) + 2 l2 d) / n.
+__global__ __launch_bounds__(256) void k_image_loss(const float* __restrict__ b,
+                                                    const float* __restrict__ ref, long n,
+                                                    double l1, double l2, double* loss,
+                                                    float* __restrict__ gb) {
+  __shared__ double bsum;
+  if (threadIdx.x == 0) bsum = 0.0;
+  __syncthreads();
+  const double inv_n = 1.0 / (double)n;
+  double local = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double d = (double)b[i] - (double)ref[i];
+    local += l1 * fabs(d) + l2 * d * d;
+    if (gb) {
+      const double sg = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+      gb[i] = (float)((l1 * sg + 2.0 * l2 * d) * inv_n);
+    }
+  }
+  atomicAdd(&bsum, local * inv_n);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, bsum);
+}
+
 int grid_for(long n, int per_block, int cap) {
   long gsz = (n + per_block - 1) / per_block;
   if (gsz < 1) gsz = 1;
@@ -337,4 +360,12 @@ int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps_revers
   return launch_pulse(g_rf, g_h, taps_reversed, M, n_t, n_rows, s);
 }
 
+}  // namespace usrt
+
+namespace usrt {
+void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2, double* loss,
+                       float* gb, hipStream_t s) {
+  hipLaunchKernelGGL(k_image_loss, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, b, ref, n, l1, l2,
+                     loss, gb);
+}
 }  // namespace usrt

@@ -93,6 +93,8 @@ void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, con
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s);
 int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddle, int n_t,
                             long n_rows, hipStream_t s);
+void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2, double* loss,
+                       float* gb, hipStream_t s);
 int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps, int M, int n_t,
                          long n_rows, hipStream_t s);
 

@@ -161,3 +161,64 @@ def test_full_chain_gradient_against_oracle(L, ctx):
     assert loss == pytest.approx(ref["loss"], rel=1e-3)
     compare_grads(g.cpu().numpy(), ref["g_theta"], wl.scene.theta(), "full chain (34 perturbed)", idx)
     compare_grads(g.cpu().numpy(), ref["g_theta"], wl.scene.theta(), "full chain (all 50)")
+
+
+def test_autograd_matches_explicit_chain(L, ctx):
+    """loss.backward() through the Functions equals the explicit chain of C-ABI
+    VJP calls on the same forward tensors (only the order of fp64 atomic
+    additions in the replay may differ)."""
+    import torch
+    from paper_2604_15017_amd import autograd as A
+    wl = W.layered_phantom().replace(rays_per_elem=32, angles=np.radians([-8.0, 0.0, 8.0]),
+                                     tx_ids=np.arange(3, dtype=np.uint32))
+    r = A.Renderer(wl, ctx)
+    target = W.layered_phantom_target(wl)
+    with torch.no_grad():
+        b_ref = r.render(torch.tensor(target.theta(), device="cuda")).clone()
+    theta = r.theta0.clone().requires_grad_(True)
+    rf = r.simulate_rf(theta)
+    iq = r.beamform(rf)
+    b = r.bmode(iq)
+    loss = A.mse(b, b_ref, r)
+    loss.backward()
+    torch.cuda.synchronize()
+    l2, g_b = L.us_image_loss(ctx, b.detach(), b_ref, 0.0, 1.0)
+    g_iq = L.us_bmode_vjp(ctx, iq.detach(), g_b, wl.dr_db)
+    g_rf = L.us_beamform_vjp(ctx, r.probe, wl.grid, wl.angles, wl.tx_ids, g_iq)
+    g_theta = L.us_simulate_rf_vjp(ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
+                                   wl.rays_per_elem, wl.max_bounces, g_rf)
+    torch.cuda.synchronize()
+    assert float(loss.detach()) == pytest.approx(float(l2[0]), rel=1e-12)
+    assert float(loss.detach()) == pytest.approx(float(((b.detach() - b_ref) ** 2).mean()), rel=1e-5)
+    a, e = theta.grad.cpu().numpy(), g_theta.cpu().numpy()
+    assert np.allclose(a, e, rtol=1e-9, atol=1e-12 * np.abs(e).max())
+
+
+def test_full_size_gradient_on_ray_sample(L, ctx):
+    """The forward+backward workload at full size (11 x 2^20 rays): dL/drf from
+    the full-size image chain on the GPU; the transport VJP of a sampled ray
+    range (rays of every element) checked against the oracle on that range."""
+    import torch
+    wl = W.layered_phantom()
+    target = W.layered_phantom_target(wl)
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    scene_t = L.Scene(ctx, target)
+    def frame(sc):
+        rf = L.us_simulate_rf(ctx, sc, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces)
+        iq = L.us_beamform(ctx, probe, wl.grid, wl.angles, wl.tx_ids, rf)
+        return iq, L.us_bmode(ctx, iq, wl.dr_db)
+    _, b_ref = frame(scene_t)
+    iq, b = frame(scene)
+    _, g_b = L.us_image_loss(ctx, b, b_ref, 0.0, 1.0)
+    g_rf = L.us_beamform_vjp(ctx, probe, wl.grid, wl.angles, wl.tx_ids, L.us_bmode_vjp(ctx, iq, g_b, wl.dr_db))
+    begin, count = 123457, 6000
+    g = L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                             wl.max_bounces, g_rf, ray_begin=begin, ray_count=count)
+    torch.cuda.synchronize()
+    p = wl.probe
+    _, s = oracle.pulse_taps(p.f0, p.n_cycles, p.fs)
+    g_h = oracle.pulse_vjp(g_rf.cpu().numpy().astype(np.float64), s)
+    tr = oracle.trace(wl.scene, p, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                      ray_begin=begin, ray_count=count, g_h=g_h,
+                      grad_params=list(range(wl.scene.n_params)))
+    compare_grads(g.cpu().numpy(), tr.g_theta, wl.scene.theta(), "full size, ray sample")
