@@ -71,12 +71,73 @@ def cpu_baseline(wl):
                       f"{tr.segments} segments in {dt:.2f} s"}
 
 
+def serving(ctx, n_requests):
+    """Serving stream: Poisson arrivals at 80 % of the measured one-at-a-time
+    throughput, scenes 40/40/20 from the two-layer and two layered-phantom
+    draws, 2^14..2^24 rays, grids 128x256..512x1024, 30 % gradient requests,
+    200 GB admission cap; one slot (plain) against eight slots (continuous
+    batching) on the same arrivals."""
+    import torch
+    from paper_2604_15017_amd import serve as S
+    from paper_2604_15017_amd import workloads as W
+    specs = W.serving_requests(n_requests, seed=4)
+    ex1 = S.GpuExecutor(ctx, n_slots=1)
+    reqs = S.build_requests(ex1, specs)
+
+    def fresh():
+        return [S.Request(r.rid, r.workload, r.want_grad, r.b_ref) for r in reqs]
+
+    # warm-up: every distinct scene and shape once
+    srv = S.Server(ex1, n_slots=1)
+    for r in fresh()[:16]:
+        srv.submit(r)
+    srv.run(16)
+    torch.cuda.synchronize()
+    # plain throughput: all requests queued at once, one at a time
+    srv = S.Server(ex1, n_slots=1)
+    batch = fresh()
+    for r in batch:
+        srv.submit(r)
+    t0 = time.perf_counter()
+    srv.run(len(batch))
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    # the same closed loop with eight overlapping slots
+    ex8 = S.GpuExecutor(ctx, n_slots=8)
+    srv = S.Server(ex8, n_slots=8)
+    for r in fresh():
+        srv.submit(r)
+    t0 = time.perf_counter()
+    srv.run(len(batch))
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - t0
+    rate = 0.8 * len(batch) / plain_s
+    offsets = S.poisson_arrivals(len(batch), rate, seed=4)
+    out = {"requests": len(batch), "grad_requests": int(sum(r.want_grad for r in batch)),
+           "arrival_rate_hz": round(rate, 2),
+           "plain_closed_loop_s": round(plain_s, 3),
+           "batched_closed_loop_s": round(batched_s, 3),
+           "closed_loop_speedup": round(plain_s / batched_s, 3)}
+    for name, slots in (("plain_one_at_a_time", 1), ("continuous_batching", 8)):
+        ex = ex1 if slots == 1 else ex8
+        srv = S.Server(ex, n_slots=slots, mem_cap_bytes=200 * 10**9)
+        res = S.replay_stream(srv, fresh(), offsets)
+        torch.cuda.synchronize()
+        st = S.latency_stats(res)
+        st.update({"slots": slots, "max_concurrent": srv.max_concurrent,
+                   "peak_reserved_GB": round(srv.max_reserved / 1e9, 2)})
+        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -222,6 +283,8 @@ def main():
         "roofline": roofline,
         "fwd_bwd": fwd_bwd,
     }
+    if not args.no_serving:
+        out["serving"] = serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -268,3 +268,60 @@ def tiny(workload: Workload, rays_per_elem: int, n_elem: Optional[int] = None,
         probe = dataclasses.replace(probe, n_t=n_t)
     return workload.replace(probe=probe, rays_per_elem=rays_per_elem,
                             grid=grid if grid is not None else workload.grid)
+
+
+def with_grid(wl: Workload, n_x: int, n_z: int) -> Workload:
+    """Same field of view, another pixel count."""
+    g = wl.grid
+    x_min, x_max = g.x0 - 0.5 * g.dx, g.x0 + (g.n_x - 0.5) * g.dx
+    z_min, z_max = g.z0 - 0.5 * g.dz, g.z0 + (g.n_z - 0.5) * g.dz
+    return wl.replace(grid=Grid.span(n_x, n_z, x_min, x_max, z_min, z_max))
+
+
+@dataclasses.dataclass
+class ServingRequestSpec:
+    workload: Workload
+    want_grad: bool
+    target: Optional[Scene]      # scene of the reference image for gradient requests
+    total_rays: int
+
+
+def serving_requests(n: int = 512, seed: int = 4, generators=None, min_log2_rays: int = 14,
+                     max_log2_rays: int = 24) -> List[ServingRequestSpec]:
+    """Serving stream: scenes drawn 40/40/20 from the generators (default: the
+    two-layer, layered-phantom and a second layered-phantom draw), ray counts
+    2^U{min..max} per frame, grids from {128x256, 256x512, 512x1024}, 30 % of
+    the requests ask for the gradient of the B-mode MSE against the image of a
+    seeded +-5 % perturbation of their scene. Scene descriptions are shared
+    between requests of the same draw, so a server keeps them resident."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, 5]))
+    if generators is None:
+        base = [two_layer(), layered_phantom(seed=1), layered_phantom(seed=2)]
+    else:
+        base = generators
+    weights = np.array([0.4, 0.4, 0.2])[:len(base)]
+    weights = weights / weights.sum()
+    targets = {}
+    grids = [(128, 256), (256, 512), (512, 1024)]
+    out = []
+    for i in range(n):
+        k = int(rng.choice(len(base), p=weights))
+        wl = base[k]
+        total = 1 << int(rng.integers(min_log2_rays, max_log2_rays + 1))
+        rpe = max(1, total // (wl.probe.n_elem * wl.n_tx))
+        gx, gz = grids[int(rng.integers(0, len(grids)))]
+        want_grad = bool(rng.random() < 0.3)
+        target = None
+        if want_grad:
+            if k not in targets:
+                if wl.scene.n_spheres:
+                    targets[k] = layered_phantom_target(wl, seed=seed + k)
+                else:   # perturb every region's (c, Z, alpha) and the plane depths
+                    r2 = np.random.Generator(np.random.Philox(key=[seed + k, TARGET_STREAM_TAG]))
+                    th = wl.scene.theta()
+                    th = th * (1.0 + 0.05 * (2.0 * r2.random(th.shape[0]) - 1.0))
+                    targets[k] = wl.scene.with_theta(th)
+            target = targets[k]
+        out.append(ServingRequestSpec(with_grid(wl.replace(rays_per_elem=rpe), gx, gz), want_grad,
+                                      target, rpe * wl.probe.n_elem * wl.n_tx))
+    return out
