@@ -48,7 +48,13 @@ class _Scene(ctypes.Structure):
                 ("n_spheres", ctypes.c_int),
                 ("plane_regions", ctypes.c_void_p), ("plane_kd", ctypes.c_void_p),
                 ("sphere_regions", ctypes.c_void_p), ("sphere_kd", ctypes.c_void_p),
-                ("start_region", ctypes.c_int)]
+                ("start_region", ctypes.c_int),
+                ("n_meshes", ctypes.c_int), ("n_basis", ctypes.c_int),
+                ("mesh_regions", ctypes.c_void_p), ("mesh_kd", ctypes.c_void_p),
+                ("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
+                ("vrest", ctypes.c_void_p), ("vnormal", ctypes.c_void_p), ("vbasis", ctypes.c_void_p),
+                ("vmesh", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("tmesh", ctypes.c_void_p),
+                ("mesh_bruteforce", ctypes.c_int)]
 
 
 class _Probe(ctypes.Structure):
@@ -131,7 +137,7 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
           nee_mode: int = 0, g_h: Optional[np.ndarray] = None,
           grad_params: Optional[Sequence[int]] = None, want_hashes: bool = False,
           n_threads: int = 0, probs: Optional[np.ndarray] = None,
-          record_probs: bool = False) -> TraceResult:
+          record_probs: bool = False, mesh_bruteforce: bool = False) -> TraceResult:
     """FP64 transport of rays [ray_begin, ray_begin + ray_count) of every transmit.
 
     scene: attributes regions (R,3), planes (P,), plane_regions (P,2), plane_kd (P,),
@@ -141,6 +147,10 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
     record_probs / probs: record the branch probabilities of this call
            (returned as .probs), or reuse given ones; finite differences of the
            estimator with its sampling density held fixed need this.
+    scene.meshes (optional): closed triangle meshes with attributes vertices,
+           triangles, normals, basis, region_in, region_out, kd; their
+           displacement coefficients follow the spheres in theta.
+    mesh_bruteforce: test every triangle instead of walking the hierarchy.
     """
     lib = _load()
     th = np.ascontiguousarray(scene.theta() if theta is None else theta, dtype=np.float64)
@@ -148,9 +158,28 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
     pk = np.ascontiguousarray(scene.plane_kd, dtype=np.float64)
     sr = np.ascontiguousarray(scene.sphere_regions, dtype=np.int32).reshape(-1)
     sk = np.ascontiguousarray(scene.sphere_kd, dtype=np.float64)
+    meshes = list(getattr(scene, "meshes", []) or [])
+    keep = [pr, pk, sr, sk]
+    if meshes:
+        vs, ns, bs, vm, ts, tm, off = [], [], [], [], [], [], 0
+        for k, mm in enumerate(meshes):
+            vs.append(mm.vertices); ns.append(mm.normals); bs.append(mm.basis)
+            vm.append(np.full(len(mm.vertices), k, np.int32))
+            ts.append(np.asarray(mm.triangles) + off); tm.append(np.full(len(mm.triangles), k, np.int32))
+            off += len(mm.vertices)
+        arr = [np.ascontiguousarray(np.concatenate(x), dtype=dt) for x, dt in
+               ((vs, np.float64), (ns, np.float64), (bs, np.float64), (vm, np.int32), (ts, np.int32), (tm, np.int32))]
+        mreg = np.ascontiguousarray([[mm.region_in, mm.region_out] for mm in meshes], dtype=np.int32)
+        mkd = np.ascontiguousarray([mm.kd for mm in meshes], dtype=np.float64)
+        keep += arr + [mreg, mkd]
+        nb = int(arr[2].shape[1])
+        mesh_fields = (len(meshes), nb, _ptr(mreg), _ptr(mkd), int(arr[0].shape[0]), int(arr[4].shape[0]),
+                       _ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), _ptr(arr[3]), _ptr(arr[4]), _ptr(arr[5]))
+    else:
+        mesh_fields = (0, 0, None, None, 0, 0, None, None, None, None, None, None)
     sd = _Scene(int(scene.regions.shape[0]), int(scene.planes.shape[0]),
                 int(scene.spheres.shape[0]), _ptr(pr), _ptr(pk), _ptr(sr), _ptr(sk),
-                int(scene.start_region))
+                int(scene.start_region), *mesh_fields, 1 if mesh_bruteforce else 0)
     pd = _probe_struct(probe)
     ang = np.ascontiguousarray(angles, dtype=np.float64)
     ids = np.ascontiguousarray(tx_ids, dtype=np.uint32)

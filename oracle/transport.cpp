@@ -162,6 +162,18 @@ struct OrSceneDesc {
   const int32_t* sphere_regions;  // [n_spheres][2]: inside, outside
   const double* sphere_kd;        // [n_spheres]
   int start_region;
+  // closed triangle meshes; vertex v moves as vrest + sum_j q_j basis[v][j] vnormal[v]
+  int n_meshes, n_basis;
+  const int32_t* mesh_regions;    // [n_meshes][2]: inside, outside
+  const double* mesh_kd;          // [n_meshes]
+  int64_t n_vertices, n_triangles;
+  const double* vrest;            // [V][3]
+  const double* vnormal;          // [V][3]
+  const double* vbasis;           // [V][n_basis]
+  const int32_t* vmesh;           // [V]
+  const int32_t* tris;            // [T][3]
+  const int32_t* tmesh;           // [T]
+  int mesh_bruteforce;            // test hook: 1 = test every triangle instead of the BVH
 };
 
 struct OrProbeDesc {
@@ -200,7 +212,59 @@ namespace {
 constexpr double TMIN = 1e-6;   // reading: self-intersection guard of 1 um
 constexpr double PI = 3.14159265358979323846;
 
-enum HitKind { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_ARRAY = 3 };
+enum HitKind { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_ARRAY = 3, HIT_MESH = 4 };
+
+// Bounding-volume hierarchy over the mesh triangles (median split along the
+// longest axis of the centroids, at most 4 triangles per leaf). It only
+// accelerates the closest-hit search; the hit is the same as a linear scan.
+struct BNode { double lo[3], hi[3]; int left, right, first, count; };
+
+struct Bvh {
+  std::vector<BNode> nodes;
+  std::vector<int> order;   // triangle ids in leaf order
+  void build(const std::vector<double>& vp, const int32_t* tris, int64_t n_tri) {
+    order.resize(n_tri);
+    for (int64_t i = 0; i < n_tri; ++i) order[i] = (int)i;
+    std::vector<double> cen(3 * n_tri);
+    for (int64_t i = 0; i < n_tri; ++i)
+      for (int k = 0; k < 3; ++k)
+        cen[3 * i + k] = (vp[3 * tris[3 * i] + k] + vp[3 * tris[3 * i + 1] + k] + vp[3 * tris[3 * i + 2] + k]) / 3.0;
+    nodes.clear();
+    if (n_tri) split(vp, tris, cen, 0, (int)n_tri);
+  }
+  int split(const std::vector<double>& vp, const int32_t* tris, const std::vector<double>& cen,
+            int first, int count) {
+    int id = (int)nodes.size();
+    nodes.push_back(BNode{});
+    BNode nd;
+    for (int k = 0; k < 3; ++k) { nd.lo[k] = INFINITY; nd.hi[k] = -INFINITY; }
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = first; i < first + count; ++i) {
+      int t = order[i];
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) {
+          double x = vp[3 * tris[3 * t + j] + k];
+          nd.lo[k] = std::min(nd.lo[k], x); nd.hi[k] = std::max(nd.hi[k], x);
+        }
+      for (int k = 0; k < 3; ++k) { clo[k] = std::min(clo[k], cen[3 * t + k]); chi[k] = std::max(chi[k], cen[3 * t + k]); }
+    }
+    if (count <= 4) {
+      nd.left = nd.right = -1; nd.first = first; nd.count = count;
+      nodes[id] = nd;
+      return id;
+    }
+    int ax = 0;
+    for (int k = 1; k < 3; ++k) if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+    int mid = first + count / 2;
+    std::nth_element(order.begin() + first, order.begin() + mid, order.begin() + first + count,
+                     [&](int a, int b) { return cen[3 * a + ax] < cen[3 * b + ax]; });
+    nd.first = first; nd.count = 0;
+    nd.left = split(vp, tris, cen, first, mid - first);
+    nd.right = split(vp, tris, cen, mid, first + count - mid);
+    nodes[id] = nd;
+    return id;
+  }
+};
 
 template <class T>
 struct Model {
@@ -210,7 +274,102 @@ struct Model {
   std::vector<T> c, Z, a;               // per region: speed, impedance, amplitude attenuation [Np/m]
   std::vector<T> pz;                    // plane depths
   std::vector<V3<T>> sc; std::vector<T> sr;  // sphere centres, radii
+  std::vector<T> q;                     // mesh displacement coefficients [n_meshes][n_basis]
+  std::vector<double> vpos;             // current vertex positions (values) [V][3]
+  Bvh bvh;
 };
+
+// Current position of mesh vertex v as a function of the displacement coefficients.
+template <class T>
+V3<T> vertex(const Model<T>& m, int v) {
+  const OrSceneDesc* sd = m.sd;
+  const int mesh = sd->vmesh[v];
+  T s(0.0);
+  for (int j = 0; j < sd->n_basis; ++j) s = s + m.q[mesh * sd->n_basis + j] * sd->vbasis[(int64_t)v * sd->n_basis + j];
+  return V3<T>{sd->vrest[3 * v] + s * sd->vnormal[3 * v], sd->vrest[3 * v + 1] + s * sd->vnormal[3 * v + 1],
+               sd->vrest[3 * v + 2] + s * sd->vnormal[3 * v + 2]};
+}
+
+// Moller-Trumbore on values, edges included; returns the distance or -1.
+double tri_hit_value(const Model<double>* dummy, const std::vector<double>& vp, const int32_t* tri,
+                     const double* o, const double* d) {
+  (void)dummy;
+  const double* p0 = &vp[3 * tri[0]];
+  const double* p1 = &vp[3 * tri[1]];
+  const double* p2 = &vp[3 * tri[2]];
+  double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+  double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+  double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+  double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+  if (det == 0.0) return -1.0;
+  double inv = 1.0 / det;
+  double sv[3] = {o[0] - p0[0], o[1] - p0[1], o[2] - p0[2]};
+  double u = (sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2]) * inv;
+  if (u < 0.0 || u > 1.0) return -1.0;
+  double qv[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
+  double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
+  if (v < 0.0 || u + v > 1.0) return -1.0;
+  return (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+}
+
+// Closest triangle with distance in (TMIN, best): linear scan or BVH walk.
+template <class T>
+void mesh_closest(const Model<T>& m, const double* o, const double* d, double* best, int* best_tri) {
+  const OrSceneDesc* sd = m.sd;
+  if (sd->mesh_bruteforce) {
+    for (int64_t t = 0; t < sd->n_triangles; ++t) {
+      double tt = tri_hit_value(nullptr, m.vpos, sd->tris + 3 * t, o, d);
+      if (tt > TMIN && tt < *best) { *best = tt; *best_tri = (int)t; }
+    }
+    return;
+  }
+  if (m.bvh.nodes.empty()) return;
+  std::vector<int> stack;
+  stack.push_back(0);
+  while (!stack.empty()) {
+    const BNode& nd = m.bvh.nodes[stack.back()];
+    stack.pop_back();
+    // slab test of the node box
+    double t0 = 0.0, t1 = *best;
+    bool hit = true;
+    for (int k = 0; k < 3 && hit; ++k) {
+      if (d[k] == 0.0) {
+        if (o[k] < nd.lo[k] || o[k] > nd.hi[k]) hit = false;
+        continue;
+      }
+      double ta = (nd.lo[k] - o[k]) / d[k], tb = (nd.hi[k] - o[k]) / d[k];
+      if (ta > tb) std::swap(ta, tb);
+      t0 = std::max(t0, ta); t1 = std::min(t1, tb);
+      if (t0 > t1) hit = false;
+    }
+    if (!hit) continue;
+    if (nd.left < 0) {
+      for (int i = nd.first; i < nd.first + nd.count; ++i) {
+        int t = m.bvh.order[i];
+        double tt = tri_hit_value(nullptr, m.vpos, sd->tris + 3 * t, o, d);
+        if (tt > TMIN && tt < *best) { *best = tt; *best_tri = t; }
+      }
+    } else {
+      stack.push_back(nd.left);
+      stack.push_back(nd.right);
+    }
+  }
+}
+
+// Distance to the plane of triangle t along (o, w), and its unit normal, as
+// functions of the displacement coefficients.
+template <class T>
+void tri_geometry(const Model<T>& m, int t, const V3<T>& o, const V3<T>& w, T* dist, V3<T>* n) {
+  const int32_t* tr = m.sd->tris + 3 * t;
+  V3<T> p0 = vertex(m, tr[0]), p1 = vertex(m, tr[1]), p2 = vertex(m, tr[2]);
+  V3<T> e1 = p1 - p0, e2 = p2 - p0;
+  V3<T> nu{e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x};
+  if (dist) *dist = dot(nu, p0 - o) / dot(nu, w);
+  if (n) {
+    T len = sqrt(dot(nu, nu));
+    *n = nu * (1.0 / len);
+  }
+}
 
 template <class T>
 struct Hit { int kind; int index; T t; };
@@ -238,6 +397,18 @@ Hit<T> closest_hit(const Model<T>& m, const V3<T>& o, const V3<T>& w, bool with_
     T t = val(t1) > TMIN ? t1 : t2;
     if (val(t) > TMIN && val(t) < best_t) { best = {HIT_SPHERE, k, t}; best_t = val(t); }
   }
+  if (m.sd->n_meshes > 0) {
+    double ov[3] = {val(o.x), val(o.y), val(o.z)}, wv[3] = {val(w.x), val(w.y), val(w.z)};
+    double bt = best_t;
+    int tri = -1;
+    mesh_closest(m, ov, wv, &bt, &tri);
+    if (tri >= 0) {
+      T t;
+      tri_geometry(m, tri, o, w, &t, (V3<T>*)nullptr);
+      best = {HIT_MESH, tri, t};
+      best_t = bt;
+    }
+  }
   if (with_array && val(w.z) < 0.0) {
     T t = -o.z / w.z;
     if (val(t) > TMIN && val(t) < best_t) { best = {HIT_ARRAY, -1, t}; best_t = val(t); }
@@ -254,12 +425,19 @@ void surface_at(const Model<T>& m, const Hit<T>& h, const V3<T>& x, int region,
     const int32_t* pr = m.sd->plane_regions + 2 * h.index;
     *other = region == pr[0] ? pr[1] : pr[0];
     *kd = m.sd->plane_kd[h.index];
-  } else {
+  } else if (h.kind == HIT_SPHERE) {
     T inv_r = 1.0 / m.sr[h.index];
     *n = (x - m.sc[h.index]) * inv_r;
     const int32_t* sr = m.sd->sphere_regions + 2 * h.index;
     *other = region == sr[0] ? sr[1] : sr[0];
     *kd = m.sd->sphere_kd[h.index];
+  } else {   // mesh triangle: flat face normal
+    V3<T> zero{T(0.0), T(0.0), T(1.0)};
+    tri_geometry(m, h.index, x, zero, (T*)nullptr, n);
+    const int mesh = m.sd->tmesh[h.index];
+    const int32_t* mr = m.sd->mesh_regions + 2 * mesh;
+    *other = region == mr[0] ? mr[1] : mr[0];
+    *kd = m.sd->mesh_kd[mesh];
   }
 }
 
@@ -537,9 +715,21 @@ void build_model(Model<T>& m, const OrSceneDesc* sd, const OrProbeDesc* pd, cons
     m.sc.push_back({th[off + 4 * s], th[off + 4 * s + 1], th[off + 4 * s + 2]});
     m.sr.push_back(th[off + 4 * s + 3]);
   }
+  off += 4 * sd->n_spheres;
+  if (sd->n_meshes > 0) {
+    for (int j = 0; j < sd->n_meshes * sd->n_basis; ++j) m.q.push_back(th[off + j]);
+    m.vpos.resize(3 * sd->n_vertices);
+    for (int64_t v = 0; v < sd->n_vertices; ++v) {
+      V3<T> p = vertex(m, (int)v);
+      m.vpos[3 * v] = val(p.x); m.vpos[3 * v + 1] = val(p.y); m.vpos[3 * v + 2] = val(p.z);
+    }
+    m.bvh.build(m.vpos, sd->tris, sd->n_triangles);
+  }
 }
 
-int n_params_of(const OrSceneDesc* sd) { return 3 * sd->n_regions + sd->n_planes + 4 * sd->n_spheres; }
+int n_params_of(const OrSceneDesc* sd) {
+  return 3 * sd->n_regions + sd->n_planes + 4 * sd->n_spheres + sd->n_meshes * sd->n_basis;
+}
 
 struct Result {
   std::vector<OrContrib> contribs;

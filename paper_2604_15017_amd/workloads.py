@@ -65,6 +65,21 @@ class Scene:
     sphere_regions: np.ndarray   # (S, 2) int32: region inside, region outside
     sphere_kd: np.ndarray        # (S,) float64
     start_region: int = 0        # region just below the array face
+    meshes: list = dataclasses.field(default_factory=list)   # closed triangle meshes (Mesh)
+    mesh_q: Optional[np.ndarray] = None   # (n_meshes, n_basis) displacement coefficients [m]
+
+    @property
+    def n_meshes(self) -> int:
+        return len(self.meshes)
+
+    @property
+    def n_basis(self) -> int:
+        return int(self.meshes[0].basis.shape[1]) if self.meshes else 0
+
+    def q(self) -> np.ndarray:
+        if self.mesh_q is not None:
+            return np.asarray(self.mesh_q, dtype=np.float64).reshape(self.n_meshes, self.n_basis)
+        return np.zeros((self.n_meshes, self.n_basis))
 
     @property
     def n_regions(self) -> int:
@@ -80,21 +95,26 @@ class Scene:
 
     @property
     def n_params(self) -> int:
-        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres
+        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres + self.n_meshes * self.n_basis
 
     def theta(self) -> np.ndarray:
         return np.concatenate([self.regions.reshape(-1), self.planes.reshape(-1),
-                               self.spheres.reshape(-1)]).astype(np.float64)
+                               self.spheres.reshape(-1), self.q().reshape(-1)]).astype(np.float64)
 
     def with_theta(self, theta: np.ndarray) -> "Scene":
         theta = np.asarray(theta, dtype=np.float64)
         assert theta.shape == (self.n_params,)
         r, p, s = self.n_regions, self.n_planes, self.n_spheres
+        o = 3 * r + p + 4 * s
         return dataclasses.replace(
             self,
             regions=theta[:3 * r].reshape(r, 3).copy(),
             planes=theta[3 * r:3 * r + p].copy(),
-            spheres=theta[3 * r + p:].reshape(s, 4).copy())
+            spheres=theta[3 * r + p:o].reshape(s, 4).copy(),
+            mesh_q=theta[o:].reshape(self.n_meshes, self.n_basis).copy() if self.meshes else None)
+
+    def idx_mesh(self, m: int, j: int) -> int:
+        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres + m * self.n_basis + j
 
     # index helpers for the flat parameter vector
     def idx_region(self, k: int, which: str) -> int:
@@ -325,3 +345,183 @@ def serving_requests(n: int = 512, seed: int = 4, generators=None, min_log2_rays
         out.append(ServingRequestSpec(with_grid(wl.replace(rays_per_elem=rpe), gx, gz), want_grad,
                                       target, rpe * wl.probe.n_elem * wl.n_tx))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Triangle meshes: closed, outward-oriented, each with a displacement basis.
+# A vertex moves as v = v_rest + sum_j q_j phi_j(v_rest) n_rest, where q (one
+# coefficient per basis function and mesh, in metres) is part of theta.
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Mesh:
+    vertices: np.ndarray      # (V, 3) float64 rest positions [m]
+    triangles: np.ndarray     # (T, 3) int32, counter-clockwise seen from outside
+    normals: np.ndarray       # (V, 3) float64 unit displacement directions
+    basis: np.ndarray         # (V, nb) float64 basis weights phi_j(v)
+    region_in: int
+    region_out: int
+    kd: float
+
+
+def _orient_outward(v, f, inside_point):
+    c = v[f].mean(axis=1)
+    n = np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]])
+    flip = np.einsum("ij,ij->i", n, c - inside_point) < 0
+    f = f.copy()
+    f[flip] = f[flip][:, [0, 2, 1]]
+    return f
+
+
+def _vertex_normals(v, f):
+    n = np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]])   # area-weighted
+    vn = np.zeros_like(v)
+    for k in range(3):
+        np.add.at(vn, f[:, k], n)
+    return vn / np.linalg.norm(vn, axis=1, keepdims=True)
+
+
+def icosphere(level: int):
+    """Unit icosphere: 20 * 4^level faces."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    v = [[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t], [0, -1, -t],
+         [0, 1, -t], [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]]
+    f = [[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9], [5, 11, 4],
+         [11, 10, 2], [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+         [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]]
+    v = [np.array(p, dtype=np.float64) / np.linalg.norm(p) for p in v]
+    faces = np.array(f, dtype=np.int64)
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                m = v[a] + v[b]
+                v.append(m / np.linalg.norm(m))
+                cache[key] = len(v) - 1
+            return cache[key]
+        nf = []
+        for a, b, c in faces.tolist():
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [[a, ab, ca], [b, bc, ab], [c, ca, bc], [ab, bc, ca]]
+        faces = np.array(nf, dtype=np.int64)
+    V = np.array(v)
+    return V, _orient_outward(V, faces, np.zeros(3)).astype(np.int32)
+
+
+def _fibonacci_sphere(n):
+    i = np.arange(n) + 0.5
+    phi = np.arccos(1 - 2 * i / n)
+    th = np.pi * (1 + 5 ** 0.5) * i
+    return np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+
+
+def blob_mesh(center, radius, level, rng, noise=0.08, n_basis=16, region_in=1, region_out=0,
+              kd=0.2, basis_width=0.35) -> Mesh:
+    """Icosphere displaced radially by smooth seeded noise (a few Gaussian bumps)."""
+    u, f = icosphere(level)
+    bumps = _fibonacci_sphere(8) @ np.linalg.qr(rng.standard_normal((3, 3)))[0]
+    amp = noise * (2 * rng.random(8) - 1)
+    r = 1.0 + sum(a * np.exp(-np.sum((u - b) ** 2, 1) / (2 * 0.4 ** 2)) for a, b in zip(amp, bumps))
+    v = np.asarray(center) + radius * r[:, None] * u
+    centres = _fibonacci_sphere(n_basis)
+    basis = np.exp(-((u[:, None, :] - centres[None, :, :]) ** 2).sum(-1) / (2 * basis_width ** 2))
+    return Mesh(v, f, _vertex_normals(v, f), basis, region_in, region_out, kd)
+
+
+def tube_mesh(center, radius, half_length, n_around, n_along, n_basis=16, region_in=1, region_out=0,
+              kd=0.2) -> Mesh:
+    """Closed tube along y (a vessel crossing the image plane) with flat caps."""
+    ang = 2 * np.pi * np.arange(n_around) / n_around
+    ys = np.linspace(-half_length, half_length, n_along + 1)
+    cx, cy, cz = center
+    ring = np.stack([np.cos(ang), np.sin(ang)], 1)
+    v = [[cx + radius * c, cy + y, cz + radius * s] for y in ys for c, s in ring]
+    f = []
+    for i in range(n_along):
+        for j in range(n_around):
+            a, b = i * n_around + j, i * n_around + (j + 1) % n_around
+            c, d = a + n_around, b + n_around
+            f += [[a, b, d], [a, d, c]]
+    base = len(v)
+    v += [[cx, cy - half_length, cz], [cx, cy + half_length, cz]]
+    top = n_along * n_around
+    for j in range(n_around):
+        f.append([base, (j + 1) % n_around, j])
+        f.append([base + 1, top + j, top + (j + 1) % n_around])
+    V = np.array(v, dtype=np.float64)
+    F = _orient_outward(V, np.array(f), np.asarray(center, dtype=np.float64))
+    rel = V - np.asarray(center)
+    ay, az = np.meshgrid(np.linspace(-half_length, half_length, 4), np.arange(4) * np.pi / 2, indexing="ij")
+    angle = np.arctan2(rel[:, 2], rel[:, 0])
+    basis = np.stack([np.exp(-(rel[:, 1] - y0) ** 2 / (2 * (half_length / 3) ** 2)
+                             - (1 - np.cos(angle - a0)) / (2 * 0.5 ** 2))
+                      for y0, a0 in zip(ay.ravel(), az.ravel())], 1)[:, :n_basis]
+    return Mesh(V, F.astype(np.int32), _vertex_normals(V, F), basis, region_in, region_out, kd)
+
+
+def mesh_arrays(scene: Scene) -> dict:
+    """The scene's meshes concatenated: rest vertices, displacement normals,
+    basis weights, per-vertex and per-triangle mesh ids, global triangles."""
+    if not scene.meshes:
+        z = np.zeros
+        return dict(vertices=z((0, 3)), normals=z((0, 3)), basis=z((0, 0)), vmesh=z(0, np.int32),
+                    triangles=z((0, 3), np.int32), tmesh=z(0, np.int32),
+                    regions=z((0, 2), np.int32), kd=z(0))
+    vs, ns, bs, vm, ts, tm = [], [], [], [], [], []
+    off = 0
+    for k, m in enumerate(scene.meshes):
+        vs.append(m.vertices); ns.append(m.normals); bs.append(m.basis)
+        vm.append(np.full(len(m.vertices), k, np.int32))
+        ts.append(m.triangles + off); tm.append(np.full(len(m.triangles), k, np.int32))
+        off += len(m.vertices)
+    return dict(vertices=np.concatenate(vs), normals=np.concatenate(ns), basis=np.concatenate(bs),
+                vmesh=np.concatenate(vm), triangles=np.concatenate(ts).astype(np.int32),
+                tmesh=np.concatenate(tm),
+                regions=np.array([[m.region_in, m.region_out] for m in scene.meshes], np.int32),
+                kd=np.array([m.kd for m in scene.meshes]))
+
+
+def anatomy_probe() -> Probe:
+    return Probe(n_elem=192, pitch=0.2e-3, elem_width=0.2e-3, elem_height=5e-3, f0=7.5e6,
+                 n_cycles=2.0, fs=60e6, n_t=8192, c_ref=1540.0)
+
+
+def anatomy_scene(seed: int = 3, level_organ: int = 6, level_lesion: int = 5,
+                  tube_around: int = 128, tube_along: int = 190) -> Scene:
+    """Nested closed meshes: an organ (noise-displaced icosphere, radius 14 mm,
+    centre 40 mm deep) holding a lesion (icosphere, 4 mm) and a vessel (capped
+    tube across the image plane, 1.5 mm), and a second vessel (2.5 mm) below
+    the organ in the background tissue. Defaults give 200,192 triangles."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, SCENE_STREAM_TAG]))
+
+    def medium(c, z, a):
+        return [rng.uniform(*c), rng.uniform(*z), rng.uniform(*a)]
+
+    regions = [[1540.0, 1.63, 0.5],                                   # background tissue
+               medium((1560, 1600), (1.60, 1.75), (0.5, 0.9)),        # organ
+               medium((1450, 1520), (1.35, 1.50), (0.3, 0.6)),        # lesion
+               medium((1560, 1590), (1.58, 1.65), (0.1, 0.2)),        # vessel in the organ
+               medium((1560, 1590), (1.58, 1.65), (0.1, 0.2))]        # vessel in the background
+    meshes = [
+        blob_mesh([0.0, 0.0, 40e-3], 14e-3, level_organ, rng, noise=0.06, region_in=1, region_out=0),
+        blob_mesh([-5e-3, 0.0, 44e-3], 4e-3, level_lesion, rng, noise=0.08, region_in=2, region_out=1),
+        tube_mesh([6e-3, 0.0, 35e-3], 1.5e-3, 6e-3, tube_around, tube_along, region_in=3, region_out=1),
+        tube_mesh([-12e-3, 0.0, 64e-3], 2.5e-3, 8e-3, tube_around, tube_along, region_in=4, region_out=0),
+    ]
+    return Scene(regions=np.array(regions, dtype=np.float64), planes=np.zeros(0),
+                 plane_regions=np.zeros((0, 2), np.int32), plane_kd=np.zeros(0),
+                 spheres=np.zeros((0, 4)), sphere_regions=np.zeros((0, 2), np.int32),
+                 sphere_kd=np.zeros(0), meshes=meshes)
+
+
+def anatomy_phantom(seed: int = 3, rays_per_elem: int = 4161, **mesh_kw) -> Workload:
+    """Triangle-mesh anatomy: 192 elements x 0.2 mm, 7.5 MHz, 60 MHz, 21 plane
+    waves over [-10, 10] deg, 4161 rays per element and transmit (16,777,152 per
+    frame), 12 interactions, 8192 samples, 512 x 1024 pixels over 38.4 x 76.8 mm."""
+    probe = anatomy_probe()
+    angles = np.radians(np.linspace(-10.0, 10.0, 21))
+    grid = Grid.span(512, 1024, -19.2e-3, 19.2e-3, 0.0, 76.8e-3)
+    return Workload("anatomy_phantom", anatomy_scene(seed, **mesh_kw), probe, angles,
+                    np.arange(21, dtype=np.uint32), grid, seed=0, rays_per_elem=rays_per_elem,
+                    max_bounces=12)
