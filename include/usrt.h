@@ -24,7 +24,8 @@
  *      iq        float  [n_x][n_z][2]  (real, imaginary)
  *      bmode     float  [n_x][n_z]     (dB, in [-dr_db, 0])
  *      theta     double [n_params]: (c, Z, alpha) per region, then plane
- *                depths, then (cx, cy, cz, r) per sphere
+ *                depths, then (cx, cy, cz, r) per sphere, then the
+ *                displacement coefficients q[mesh][j] of the meshes
  */
 #ifndef USRT_H
 #define USRT_H
@@ -61,11 +62,22 @@ typedef struct us_probe_desc {
   double c_ref, alpha_main, alpha_cut;
 } us_probe_desc;
 
-/* Scene of homogeneous regions bounded by planes z = d and spheres
- * (Sec. 2.3.2). theta holds the continuous parameters (layout above);
- * plane_regions[k] = {region above, region below}; sphere_regions[k] =
+/* Scene of homogeneous regions bounded by planes z = d, spheres and closed
+ * triangle meshes (Sec. 2.3.2; meshes as in the anatomy scenes of Sec. 4).
+ * theta holds the continuous parameters (layout above); plane_regions[k] =
+ * {region above, region below}; sphere_regions[k] and mesh_regions[m] =
  * {inside, outside}; kd = fraction of the reflected energy scattered into the
- * Lambertian lobe; start_region = region at the array face. Host arrays. */
+ * Lambertian lobe; start_region = region at the array face. Host arrays.
+ *
+ * Meshes (n_meshes = 0: none, and the mesh pointers may be NULL): the
+ * vertices of all meshes are concatenated ([n_vertices][3] rest positions,
+ * owning mesh vmesh[v]), and so are the triangles ([n_triangles][3] global
+ * vertex ids, counter-clockwise seen from outside, owning mesh tmesh[t], all
+ * three vertices of that mesh). Vertex v moves along its unit direction
+ * vnormal[v] by sum_j q[vmesh[v]][j] vbasis[v][j]; faces are flat. At most
+ * 32 meshes; zero-area triangles are rejected. The library builds a
+ * bounding-volume hierarchy on upload (rejected with US_EINVAL if deeper than
+ * 38 levels) and refits it on every us_scene_set_params. */
 typedef struct us_scene_desc {
   int32_t n_regions, n_planes, n_spheres;
   const double* theta;
@@ -74,6 +86,16 @@ typedef struct us_scene_desc {
   const int32_t* sphere_regions;
   const double* sphere_kd;
   int32_t start_region;
+  int32_t n_meshes, n_basis;
+  const int32_t* mesh_regions;   /* [n_meshes][2] */
+  const double* mesh_kd;         /* [n_meshes] */
+  int64_t n_vertices, n_triangles;
+  const double* vertices;        /* [n_vertices][3] */
+  const double* vnormal;         /* [n_vertices][3] */
+  const double* vbasis;          /* [n_vertices][n_basis] */
+  const int32_t* vmesh;          /* [n_vertices] */
+  const int32_t* triangles;      /* [n_triangles][3] */
+  const int32_t* tmesh;          /* [n_triangles] */
 } us_scene_desc;
 
 /* One plane-wave transmit: steering angle and the id that seeds its rays. */
@@ -103,7 +125,8 @@ int us_probe_destroy(us_probe* probe);
 int us_scene_upload(us_ctx* ctx, const us_scene_desc* desc, us_scene** out, int32_t* n_params);
 int us_scene_destroy(us_scene* scene);
 /* Replaces the scene's resident theta with n_params doubles from device
- * memory theta_dev (asynchronous copy on stream). */
+ * memory theta_dev (asynchronous copy on stream); with meshes, also moves
+ * the vertices and refits the hierarchy on stream. */
 int us_scene_set_params(us_scene* scene, const double* theta_dev, int32_t n_params, void* stream);
 
 /* Forward transport, Sec. 2.3 (emission, traversal with Snell reflection /

@@ -39,7 +39,13 @@ class us_scene_desc(ctypes.Structure):
                 ("n_spheres", ctypes.c_int32), ("theta", ctypes.c_void_p),
                 ("plane_regions", ctypes.c_void_p), ("plane_kd", ctypes.c_void_p),
                 ("sphere_regions", ctypes.c_void_p), ("sphere_kd", ctypes.c_void_p),
-                ("start_region", ctypes.c_int32)]
+                ("start_region", ctypes.c_int32),
+                ("n_meshes", ctypes.c_int32), ("n_basis", ctypes.c_int32),
+                ("mesh_regions", ctypes.c_void_p), ("mesh_kd", ctypes.c_void_p),
+                ("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
+                ("vertices", ctypes.c_void_p), ("vnormal", ctypes.c_void_p),
+                ("vbasis", ctypes.c_void_p), ("vmesh", ctypes.c_void_p),
+                ("triangles", ctypes.c_void_p), ("tmesh", ctypes.c_void_p)]
 
 
 class us_tx_desc(ctypes.Structure):
@@ -186,6 +192,28 @@ class Scene:
         d = us_scene_desc(int(s.regions.shape[0]), int(s.planes.shape[0]),
                           int(s.spheres.shape[0]), th.ctypes.data, pr.ctypes.data, pk.ctypes.data,
                           sr.ctypes.data, sk.ctypes.data, int(s.start_region))
+        meshes = list(getattr(s, "meshes", None) or [])
+        if meshes:
+            # concatenate the meshes: global vertex ids, owning mesh per vertex / triangle
+            offs = np.cumsum([0] + [len(m.vertices) for m in meshes])
+            arr = dict(
+                regions=np.array([[m.region_in, m.region_out] for m in meshes], np.int32),
+                kd=np.array([m.kd for m in meshes], np.float64),
+                v=np.concatenate([m.vertices for m in meshes]).astype(np.float64),
+                n=np.concatenate([m.normals for m in meshes]).astype(np.float64),
+                b=np.concatenate([m.basis for m in meshes]).astype(np.float64),
+                vm=np.concatenate([np.full(len(m.vertices), k, np.int32) for k, m in enumerate(meshes)]),
+                t=np.concatenate([np.asarray(m.triangles) + offs[k] for k, m in enumerate(meshes)]).astype(np.int32),
+                tm=np.concatenate([np.full(len(m.triangles), k, np.int32) for k, m in enumerate(meshes)]))
+            arr = {k: np.ascontiguousarray(v) for k, v in arr.items()}
+            nb = {m.basis.shape[1] for m in meshes}
+            if len(nb) != 1:
+                raise ValueError("all meshes need the same number of basis functions")
+            d.n_meshes, d.n_basis = len(meshes), nb.pop()
+            d.mesh_regions, d.mesh_kd = arr["regions"].ctypes.data, arr["kd"].ctypes.data
+            d.n_vertices, d.n_triangles = len(arr["v"]), len(arr["t"])
+            d.vertices, d.vnormal, d.vbasis = arr["v"].ctypes.data, arr["n"].ctypes.data, arr["b"].ctypes.data
+            d.vmesh, d.triangles, d.tmesh = arr["vm"].ctypes.data, arr["t"].ctypes.data, arr["tm"].ctypes.data
         h = ctypes.c_void_p()
         n = ctypes.c_int32()
         _check(load().us_scene_upload(ctx.handle, ctypes.byref(d), ctypes.byref(h), ctypes.byref(n)),

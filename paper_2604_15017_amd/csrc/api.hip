@@ -107,6 +107,12 @@ struct us_scene {
   double* plane_kd;
   int* sphere_regions;
   double* sphere_kd;
+  // meshes
+  int n_meshes, n_basis, q_offset;
+  int* mesh_regions;
+  double* mesh_kd;
+  int* tri_orig;
+  MeshDevice mesh;   // owns vrest, vnormal, vbasis, vmesh, vcur, nodes, tri
 };
 
 extern "C" {
@@ -191,7 +197,18 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
   US_CHECK(d->n_planes == 0 || (d->plane_regions && d->plane_kd), "us_scene_upload: plane arrays missing");
   US_CHECK(d->n_spheres == 0 || (d->sphere_regions && d->sphere_kd), "us_scene_upload: sphere arrays missing");
   US_CHECK(d->start_region >= 0 && d->start_region < d->n_regions, "us_scene_upload: start_region out of range");
-  const int np = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
+  US_CHECK(d->n_meshes >= 0 && d->n_meshes <= kMaxMeshes, "us_scene_upload: at most 32 meshes");
+  const int nm = d->n_meshes;
+  if (nm > 0) {
+    US_CHECK(d->n_basis >= 0 && d->n_basis <= 4096, "us_scene_upload: n_basis must be in [0, 4096]");
+    US_CHECK(d->mesh_regions && d->mesh_kd && d->vertices && d->vnormal && d->vmesh && d->triangles &&
+                 d->tmesh && (d->n_basis == 0 || d->vbasis),
+             "us_scene_upload: mesh arrays missing");
+    US_CHECK(d->n_vertices >= 3 && d->n_vertices < (1L << 30), "us_scene_upload: n_vertices must be in [3, 2^30)");
+    US_CHECK(d->n_triangles >= 1 && d->n_triangles < (1L << 30), "us_scene_upload: n_triangles must be in [1, 2^30)");
+  }
+  const int q_offset = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
+  const int np = q_offset + (nm > 0 ? nm * d->n_basis : 0);
   for (int r = 0; r < d->n_regions; ++r)
     US_CHECK(d->theta[3 * r] > 0 && d->theta[3 * r + 1] > 0 && d->theta[3 * r + 2] >= 0,
              "us_scene_upload: region needs c > 0, Z > 0, alpha >= 0");
@@ -209,19 +226,84 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_CHECK(d->theta[3 * d->n_regions + d->n_planes + 4 * k + 3] > 0, "us_scene_upload: sphere radius must be positive");
     diffuse |= d->sphere_kd[k] > 0;
   }
+  MeshHierarchy H;
+  const long nv = nm > 0 ? (long)d->n_vertices : 0, nt = nm > 0 ? (long)d->n_triangles : 0;
+  const int nb = nm > 0 ? d->n_basis : 0;
+  if (nm > 0) {
+    for (int m = 0; m < nm; ++m) {
+      for (int j = 0; j < 2; ++j)
+        US_CHECK(d->mesh_regions[2 * m + j] >= 0 && d->mesh_regions[2 * m + j] < d->n_regions, "us_scene_upload: mesh region out of range");
+      US_CHECK(d->mesh_kd[m] >= 0 && d->mesh_kd[m] <= 1, "us_scene_upload: kd must be in [0, 1]");
+      diffuse |= d->mesh_kd[m] > 0;
+    }
+    for (long v = 0; v < nv; ++v) {
+      US_CHECK(d->vmesh[v] >= 0 && d->vmesh[v] < nm, "us_scene_upload: vmesh out of range");
+      for (int k = 0; k < 3; ++k)
+        US_CHECK(std::isfinite(d->vertices[3 * v + k]) && std::isfinite(d->vnormal[3 * v + k]),
+                 "us_scene_upload: vertices and vnormal must be finite");
+    }
+    for (long t = 0; t < nt; ++t) {
+      const int32_t* tv = d->triangles + 3 * t;
+      US_CHECK(d->tmesh[t] >= 0 && d->tmesh[t] < nm, "us_scene_upload: tmesh out of range");
+      for (int j = 0; j < 3; ++j)
+        US_CHECK(tv[j] >= 0 && tv[j] < nv && d->vmesh[tv[j]] == d->tmesh[t],
+                 "us_scene_upload: triangle vertex out of range or of another mesh");
+      const double* a = d->vertices + 3 * (long)tv[0];
+      const double* b = d->vertices + 3 * (long)tv[1];
+      const double* c = d->vertices + 3 * (long)tv[2];
+      const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+      const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+      const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                   cz = e1[0] * e2[1] - e1[1] * e2[0];
+      US_CHECK(cx * cx + cy * cy + cz * cz > 0.0, "us_scene_upload: zero-area triangle");
+    }
+    US_CHECK(build_mesh_bvh(d->vertices, nv, d->triangles, d->tmesh, nt, H) == 0,
+             "us_scene_upload: mesh hierarchy deeper than 38 levels");
+  }
   US_HIP(hipSetDevice(ctx->device));
   us_scene* s = new us_scene{};
   s->ctx = ctx;
   s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
   s->start_region = d->start_region; s->n_params = np; s->any_diffuse = diffuse;
+  s->n_meshes = nm; s->n_basis = nb; s->q_offset = q_offset;
   bool ok = hipMalloc(&s->theta, np * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->plane_regions, (2 * d->n_planes + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc(&s->plane_kd, (d->n_planes + 1) * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->sphere_regions, (2 * d->n_spheres + 1) * sizeof(int)) == hipSuccess &&
-            hipMalloc(&s->sphere_kd, (d->n_spheres + 1) * sizeof(double)) == hipSuccess;
+            hipMalloc(&s->sphere_kd, (d->n_spheres + 1) * sizeof(double)) == hipSuccess &&
+            hipMalloc(&s->mesh_regions, (2 * nm + 1) * sizeof(int)) == hipSuccess &&
+            hipMalloc(&s->mesh_kd, (nm + 1) * sizeof(double)) == hipSuccess;
+  MeshDevice& md = s->mesh;
+  if (ok && nm > 0) {
+    md.n_vertices = nv; md.n_triangles = nt; md.n_basis = nb;
+    md.level_begin = H.level_begin;
+    double *vrest = nullptr, *vnormal = nullptr, *vbasis = nullptr;
+    int* vmesh = nullptr;
+    int4* tri = nullptr;
+    ok = hipMalloc(&vrest, 3 * nv * sizeof(double)) == hipSuccess &&
+         hipMalloc(&vnormal, 3 * nv * sizeof(double)) == hipSuccess &&
+         hipMalloc(&vbasis, (nv * nb + 1) * sizeof(double)) == hipSuccess &&
+         hipMalloc(&vmesh, nv * sizeof(int)) == hipSuccess &&
+         hipMalloc(&md.vcur, 3 * nv * sizeof(double)) == hipSuccess &&
+         hipMalloc(&md.nodes, H.nodes.size() * sizeof(BvhNode)) == hipSuccess &&
+         hipMalloc(&tri, nt * sizeof(int4)) == hipSuccess &&
+         hipMalloc(&s->tri_orig, nt * sizeof(int)) == hipSuccess;
+    md.vrest = vrest; md.vnormal = vnormal; md.vbasis = vbasis; md.vmesh = vmesh; md.tri = tri;
+  }
   if (!ok) {
     us_scene_destroy(s);
     return fail(US_ENOMEM, "us_scene_upload: hipMalloc failed");
+  }
+  if (nm > 0) {
+    US_HIP(hipMemcpy(s->mesh_regions, d->mesh_regions, 2 * nm * sizeof(int), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy(s->mesh_kd, d->mesh_kd, nm * sizeof(double), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy((void*)md.vrest, d->vertices, 3 * nv * sizeof(double), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy((void*)md.vnormal, d->vnormal, 3 * nv * sizeof(double), hipMemcpyHostToDevice));
+    if (nb > 0) US_HIP(hipMemcpy((void*)md.vbasis, d->vbasis, nv * nb * sizeof(double), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy((void*)md.vmesh, d->vmesh, nv * sizeof(int), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy(md.nodes, H.nodes.data(), H.nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy((void*)md.tri, H.tri.data(), nt * sizeof(int4), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy(s->tri_orig, H.tri_orig.data(), nt * sizeof(int), hipMemcpyHostToDevice));
   }
   US_HIP(hipMemcpy(s->theta, d->theta, np * sizeof(double), hipMemcpyHostToDevice));
   if (d->n_planes) {
@@ -231,6 +313,11 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
   if (d->n_spheres) {
     US_HIP(hipMemcpy(s->sphere_regions, d->sphere_regions, 2 * d->n_spheres * sizeof(int), hipMemcpyHostToDevice));
     US_HIP(hipMemcpy(s->sphere_kd, d->sphere_kd, d->n_spheres * sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (nm > 0) {
+    launch_mesh_refit(md, s->theta + q_offset, nullptr);
+    US_HIP(hipGetLastError());
+    US_HIP(hipDeviceSynchronize());
   }
   *out = s;
   if (n_params) *n_params = np;
@@ -245,6 +332,16 @@ int us_scene_destroy(us_scene* s) {
   (void)hipFree(s->plane_kd);
   (void)hipFree(s->sphere_regions);
   (void)hipFree(s->sphere_kd);
+  (void)hipFree(s->mesh_regions);
+  (void)hipFree(s->mesh_kd);
+  (void)hipFree(s->tri_orig);
+  (void)hipFree((void*)s->mesh.vrest);
+  (void)hipFree((void*)s->mesh.vnormal);
+  (void)hipFree((void*)s->mesh.vbasis);
+  (void)hipFree((void*)s->mesh.vmesh);
+  (void)hipFree(s->mesh.vcur);
+  (void)hipFree(s->mesh.nodes);
+  (void)hipFree((void*)s->mesh.tri);
   delete s;
   return US_OK;
 }
@@ -255,6 +352,10 @@ int us_scene_set_params(us_scene* s, const double* theta_dev, int32_t n_params, 
   US_HIP(hipSetDevice(s->ctx->device));
   US_HIP(hipMemcpyAsync(s->theta, theta_dev, n_params * sizeof(double), hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));
+  if (s->n_meshes > 0) {
+    launch_mesh_refit(s->mesh, s->theta + s->q_offset, (hipStream_t)stream);
+    US_HIP(hipGetLastError());
+  }
   return US_OK;
 }
 
@@ -263,7 +364,7 @@ int us_scene_set_params(us_scene* s, const double* theta_dev, int32_t n_params, 
 namespace {
 
 SceneView scene_view(const us_scene* s, const us_probe* p) {
-  SceneView v;
+  SceneView v{};
   v.theta = s->theta;
   v.plane_regions = s->plane_regions;
   v.plane_kd = s->plane_kd;
@@ -273,6 +374,16 @@ SceneView scene_view(const us_scene* s, const us_probe* p) {
   v.n_planes = s->n_planes;
   v.n_spheres = s->n_spheres;
   v.start_region = s->start_region;
+  v.n_meshes = s->n_meshes;
+  v.n_basis = s->n_basis;
+  v.mesh_regions = s->mesh_regions;
+  v.mesh_kd = s->mesh_kd;
+  v.nodes = s->mesh.nodes;
+  v.tri = s->mesh.tri;
+  v.tri_orig = s->tri_orig;
+  v.vcur = s->mesh.vcur;
+  v.vnormal = s->mesh.vnormal;
+  v.vbasis = s->mesh.vbasis;
   // amplitude attenuation at f0: alpha [dB/cm/MHz] * f0 [MHz] * 100 cm/m / (20 / ln 10)
   v.np_per_m = (p->d.f0 * 1e-6) * 100.0 * std::log(10.0) / 20.0;
   return v;

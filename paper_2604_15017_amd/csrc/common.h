@@ -11,6 +11,9 @@ constexpr int kMaxRegions = 64;
 constexpr int kMaxPlanes = 16;
 constexpr int kMaxSpheres = 32;
 constexpr int kMaxTxPerLaunch = 64;
+constexpr int kMaxMeshes = 32;
+constexpr int kBvhStack = 40;           // per-thread LDS stack entries
+constexpr int kMaxBvhDepth = kBvhStack - 2;   // leaves at depth <= 38 keep the stack within 40
 constexpr double kTMin = 1e-6;          // self-intersection guard [m]
 constexpr double kPi = 3.14159265358979323846;
 
@@ -59,7 +62,17 @@ __device__ __forceinline__ uint64_t event_mix(uint32_t tag, uint32_t k, uint32_t
   return z ^ (z >> 31);
 }
 enum : uint32_t { kEvHit = 1, kEvArray = 2, kEvBranch = 3, kEvNee = 4 };
-enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3 };
+enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3, kHitMesh = 4 };
+
+// Bounding-volume hierarchy node (32 B): fp32 box rounded outward; inner
+// node: a = left child, b = right child; leaf: a = first triangle (leaf
+// order), b = -count.
+struct BvhNode {
+  float lo[3];
+  int a;
+  float hi[3];
+  int b;
+};
 
 struct d3 { double x, y, z; };
 __device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
@@ -82,6 +95,16 @@ struct SceneView {
   const double* sphere_kd;
   int n_regions, n_planes, n_spheres, start_region;
   double np_per_m;       // amplitude attenuation [Np/m] per dB/cm/MHz at f0
+  // triangle meshes (all null / zero without meshes)
+  int n_meshes, n_basis;
+  const int* mesh_regions;     // [n_meshes][2]: inside, outside
+  const double* mesh_kd;       // [n_meshes]
+  const BvhNode* nodes;
+  const int4* tri;             // leaf order: vertex ids (x, y, z), mesh id (w)
+  const int* tri_orig;         // leaf order -> triangle id of the description
+  const double* vcur;          // [V][3] current vertex positions
+  const double* vnormal;       // [V][3] displacement directions
+  const double* vbasis;        // [V][n_basis]
 };
 
 // Per-block copy of the scene in LDS.
@@ -91,8 +114,14 @@ struct SceneLDS {
   int pr[kMaxPlanes][2];
   double sx[kMaxSpheres], sy[kMaxSpheres], sz[kMaxSpheres], sr[kMaxSpheres], skd[kMaxSpheres];
   int sreg[kMaxSpheres][2];
-  int n_planes, n_spheres, start_region;
+  int mreg[kMaxMeshes][2];
+  double mkd[kMaxMeshes];
+  int n_planes, n_spheres, n_meshes, start_region;
   bool any_diffuse;
+  const BvhNode* nodes;
+  const int4* tri;
+  const int* tri_orig;
+  const double* vcur;
 };
 
 __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
@@ -119,14 +148,25 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
     s.sreg[i][0] = v.sphere_regions[2 * i];
     s.sreg[i][1] = v.sphere_regions[2 * i + 1];
   }
+  for (int i = t; i < v.n_meshes; i += blockDim.x) {
+    s.mreg[i][0] = v.mesh_regions[2 * i];
+    s.mreg[i][1] = v.mesh_regions[2 * i + 1];
+    s.mkd[i] = v.mesh_kd[i];
+  }
   if (t == 0) {
     s.n_planes = v.n_planes;
     s.n_spheres = v.n_spheres;
+    s.n_meshes = v.n_meshes;
     s.start_region = v.start_region;
     bool d = false;
     for (int i = 0; i < v.n_planes; ++i) d |= v.plane_kd[i] > 0.0;
     for (int i = 0; i < v.n_spheres; ++i) d |= v.sphere_kd[i] > 0.0;
+    for (int i = 0; i < v.n_meshes; ++i) d |= v.mesh_kd[i] > 0.0;
     s.any_diffuse = d;
+    s.nodes = v.nodes;
+    s.tri = v.tri;
+    s.tri_orig = v.tri_orig;
+    s.vcur = v.vcur;
   }
   __syncthreads();
 }

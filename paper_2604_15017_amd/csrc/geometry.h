@@ -8,9 +8,70 @@ namespace usrt {
 
 struct Hit { int kind; int index; double t; };
 
+__device__ __forceinline__ d3 vtx(const double* v, int i) {
+  return d3{v[3 * i], v[3 * i + 1], v[3 * i + 2]};
+}
+__device__ __forceinline__ d3 cross(d3 a, d3 b) {
+  return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// Moller-Trumbore in fp64, edges included; distance or -1.
+__device__ __forceinline__ double tri_distance(d3 p0, d3 p1, d3 p2, d3 o, d3 d) {
+  const d3 e1 = p1 - p0, e2 = p2 - p0;
+  const d3 pv = cross(d, e2);
+  const double det = dot(e1, pv);
+  if (det == 0.0) return -1.0;
+  const double inv = 1.0 / det;
+  const d3 sv = o - p0;
+  const double u = dot(sv, pv) * inv;
+  if (u < 0.0 || u > 1.0) return -1.0;
+  const d3 qv = cross(sv, e1);
+  const double v = dot(d, qv) * inv;
+  if (v < 0.0 || u + v > 1.0) return -1.0;
+  return dot(e2, qv) * inv;
+}
+
+// Closest triangle in (kTMin, best) by walking the hierarchy; the node stack
+// lives in LDS, interleaved across the block's threads (entry i of this
+// thread at stk[i * blockDim.x]). Boxes are tested in fp32, padded by 1 um
+// to absorb the rounding of the ray to fp32; triangles in fp64.
+__device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, double& best, int& best_tri,
+                                             int* stk) {
+  constexpr float kPad = 1e-6f;
+  const float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
+  const float ix = fabs(d.x) > 1e-30 ? (float)(1.0 / d.x) : copysignf(1e30f, (float)d.x);
+  const float iy = fabs(d.y) > 1e-30 ? (float)(1.0 / d.y) : copysignf(1e30f, (float)d.y);
+  const float iz = fabs(d.z) > 1e-30 ? (float)(1.0 / d.z) : copysignf(1e30f, (float)d.z);
+  const int step = blockDim.x;
+  int sp = 1;
+  stk[0] = 0;
+  while (sp > 0) {
+    --sp;
+    const BvhNode nd = s.nodes[stk[sp * step]];
+    const float ax = (nd.lo[0] - kPad - ox) * ix, bx = (nd.hi[0] + kPad - ox) * ix;
+    const float ay = (nd.lo[1] - kPad - oy) * iy, by = (nd.hi[1] + kPad - oy) * iy;
+    const float az = (nd.lo[2] - kPad - oz) * iz, bz = (nd.hi[2] + kPad - oz) * iz;
+    const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+    const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+    if (tmin > tmax || tmin > (float)best * 1.0001f + kPad) continue;
+    if (nd.b < 0) {
+      for (int i = nd.a; i < nd.a - nd.b; ++i) {
+        const int4 tv = s.tri[i];
+        const double t = tri_distance(vtx(s.vcur, tv.x), vtx(s.vcur, tv.y), vtx(s.vcur, tv.z), o, d);
+        if (t > kTMin && t < best) { best = t; best_tri = i; }
+      }
+    } else if (sp + 2 <= kBvhStack) {   // the build bounds the depth, so this always holds
+      stk[sp * step] = nd.b;
+      stk[(sp + 1) * step] = nd.a;
+      sp += 2;
+    }
+  }
+}
+
 // Closest surface along o + t d with t > kTMin among the planes, the spheres
 // and, when `with_array` and the ray moves up, the array face z = 0.
-__device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool with_array) {
+__device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool with_array,
+                                           int* stk) {
   Hit h{kHitNone, -1, 0.0};
   double best = INFINITY;
   if (d.z != 0.0) {
@@ -34,7 +95,28 @@ __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool w
     const double t = t1 > kTMin ? t1 : -b + q;
     if (t > kTMin && t < best) { best = t; h = Hit{kHitSphere, k, t}; }
   }
+  if (s.n_meshes > 0) {
+    int tri = -1;
+    mesh_closest(s, o, d, best, tri, stk);
+    if (tri >= 0) h = Hit{kHitMesh, tri, best};
+  }
   return h;
+}
+
+// Upper bound on the legs of a straight receiver segment: each plane is
+// crossed once, each sphere twice, each closed mesh a few times (a segment
+// that needs more is treated as blocked).
+constexpr int kMeshLegs = 16;
+__device__ __forceinline__ int max_legs(const SceneLDS& s) {
+  return s.n_planes + 2 * s.n_spheres + kMeshLegs * s.n_meshes + 1;
+}
+
+// Unit face normal of leaf-order triangle i, from the current vertices.
+__device__ __forceinline__ d3 tri_normal(const SceneLDS& s, int i) {
+  const int4 tv = s.tri[i];
+  const d3 p0 = vtx(s.vcur, tv.x);
+  const d3 nu = cross(vtx(s.vcur, tv.y) - p0, vtx(s.vcur, tv.z) - p0);
+  return nu * (1.0 / sqrt(dot(nu, nu)));
 }
 
 struct Surface { d3 n; int other; double kd; };
@@ -45,13 +127,23 @@ __device__ __forceinline__ Surface surface_of(const SceneLDS& s, const Hit& h, d
     f.n = d3{0.0, 0.0, 1.0};
     f.other = region == s.pr[h.index][0] ? s.pr[h.index][1] : s.pr[h.index][0];
     f.kd = s.pkd[h.index];
-  } else {
+  } else if (h.kind == kHitSphere) {
     const double ir = 1.0 / s.sr[h.index];
     f.n = d3{(x.x - s.sx[h.index]) * ir, (x.y - s.sy[h.index]) * ir, (x.z - s.sz[h.index]) * ir};
     f.other = region == s.sreg[h.index][0] ? s.sreg[h.index][1] : s.sreg[h.index][0];
     f.kd = s.skd[h.index];
+  } else {
+    const int m = s.tri[h.index].w;
+    f.n = tri_normal(s, h.index);
+    f.other = region == s.mreg[m][0] ? s.mreg[m][1] : s.mreg[m][0];
+    f.kd = s.mkd[m];
   }
   return f;
+}
+
+// Index of the hit primitive as the scene description numbers it (hash words).
+__device__ __forceinline__ int hit_id(const SceneLDS& s, const Hit& h) {
+  return h.kind == kHitMesh ? s.tri_orig[h.index] : h.index;
 }
 
 // Interface coefficients for direction d across normal n (any orientation),

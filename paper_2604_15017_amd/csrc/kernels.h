@@ -1,6 +1,8 @@
 // Internal interface between the C-ABI (api.hip) and the kernels.
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace usrt {
@@ -66,6 +68,36 @@ struct ReplayArgs {
 };
 
 void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s);
+
+// ---------------------------------------------------------------- meshes
+// Hierarchy as built on the host (breadth-first nodes, leaf-order triangles).
+struct MeshHierarchy {
+  std::vector<BvhNode> nodes;
+  std::vector<int4> tri;
+  std::vector<int> tri_orig;
+  std::vector<int> level_begin;   // nodes of depth l: [level_begin[l], level_begin[l + 1])
+  int depth = 0;
+};
+// Returns 0, or -1 if the tree would exceed kMaxBvhDepth.
+int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
+                   const int32_t* tmesh, long n_tri, MeshHierarchy& out);
+
+// Device arrays of a scene's meshes.
+struct MeshDevice {
+  long n_vertices = 0, n_triangles = 0;
+  int n_basis = 0;
+  const double* vrest = nullptr;
+  const double* vnormal = nullptr;
+  const double* vbasis = nullptr;
+  const int* vmesh = nullptr;
+  double* vcur = nullptr;
+  BvhNode* nodes = nullptr;
+  const int4* tri = nullptr;
+  std::vector<int> level_begin;
+};
+// Current vertices from the displacement coefficients q (device,
+// [n_meshes][n_basis]), then the boxes, deepest level first.
+void launch_mesh_refit(const MeshDevice& m, const double* q, hipStream_t s);
 void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);

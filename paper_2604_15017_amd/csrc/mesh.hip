@@ -1,0 +1,265 @@
+// Closed triangle meshes (the anatomy scenes of Sec. 4): bounding-volume
+// hierarchy built once on the host from the rest shape (binned surface-area
+// heuristic), then refitted on the device whenever the displacement
+// coefficients change, so that the topology stays fixed and only the boxes
+// move. Nodes are numbered breadth first: the nodes of one depth form a
+// contiguous range and a refit is one launch per depth, deepest first.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "kernels.h"
+
+namespace usrt {
+
+namespace {
+
+struct Box {
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  void add(const double* p) {
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], p[k]); hi[k] = std::max(hi[k], p[k]); }
+  }
+  void add(const Box& b) {
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], b.lo[k]); hi[k] = std::max(hi[k], b.hi[k]); }
+  }
+  double area() const {
+    const double x = hi[0] - lo[0], y = hi[1] - lo[1], z = hi[2] - lo[2];
+    return (x < 0 || y < 0 || z < 0) ? 0.0 : 2.0 * (x * y + y * z + z * x);
+  }
+};
+
+struct TmpNode {
+  int left = -1, right = -1;   // children (temporary numbering), -1 for a leaf
+  int first = 0, count = 0;    // leaf range in the permutation
+  int depth = 0;
+};
+
+constexpr int kLeafMax = 4;
+constexpr int kBins = 16;
+
+struct Builder {
+  const double* v;
+  const int32_t* tris;
+  std::vector<Box> tbox;
+  std::vector<double> cen;      // [T][3]
+  std::vector<int> perm;
+  std::vector<TmpNode> nodes;
+  int max_depth_seen = 0;
+
+  // Split [first, first + count) at the best binned SAH plane; returns the
+  // size of the left part (0 = make a leaf). *halve is set when no plane
+  // separates the triangles and the range must be halved by the caller.
+  int split(int first, int count, const Box& bounds, int depth, bool* halve) {
+    *halve = false;
+    if (count <= kLeafMax || depth >= kMaxBvhDepth) return 0;
+    Box cb;
+    for (int i = first; i < first + count; ++i) cb.add(&cen[3 * (size_t)perm[i]]);
+    int axis = 0;
+    double ext = cb.hi[0] - cb.lo[0];
+    for (int k = 1; k < 3; ++k)
+      if (cb.hi[k] - cb.lo[k] > ext) { ext = cb.hi[k] - cb.lo[k]; axis = k; }
+    int* p = perm.data() + first;
+    if (!(ext > 0.0)) {   // coincident centroids: halve by index
+      *halve = true;
+      return count / 2;
+    }
+    const double scale = kBins / ext;
+    auto bin_of = [&](int t) {
+      const int b = (int)((cen[3 * (size_t)t + axis] - cb.lo[axis]) * scale);
+      return std::min(std::max(b, 0), kBins - 1);
+    };
+    int cnt[kBins] = {0};
+    Box bb[kBins];
+    for (int i = 0; i < count; ++i) {
+      const int b = bin_of(p[i]);
+      ++cnt[b];
+      bb[b].add(tbox[p[i]]);
+    }
+    double right_area[kBins];
+    int right_cnt[kBins];
+    Box acc;
+    int n = 0;
+    for (int b = kBins - 1; b > 0; --b) {
+      acc.add(bb[b]); n += cnt[b];
+      right_area[b] = acc.area(); right_cnt[b] = n;
+    }
+    Box lacc;
+    int ln = 0, best_b = -1;
+    double best = INFINITY;
+    for (int b = 1; b < kBins; ++b) {
+      lacc.add(bb[b - 1]); ln += cnt[b - 1];
+      if (ln == 0 || right_cnt[b] == 0) continue;
+      const double c = lacc.area() * ln + right_area[b] * right_cnt[b];
+      if (c < best) { best = c; best_b = b; }
+    }
+    if (best_b < 0) { *halve = true; return count / 2; }
+    // cost model: one box test costs about one triangle test
+    const double leaf_cost = bounds.area() * count;
+    if (count <= 16 && best + bounds.area() >= leaf_cost) return 0;
+    int* mid = std::partition(p, p + count, [&](int t) { return bin_of(t) < best_b; });
+    const int nl = (int)(mid - p);
+    if (nl == 0 || nl == count) { *halve = true; return count / 2; }
+    return nl;
+  }
+
+  int build(int first, int count, int depth) {
+    const int id = (int)nodes.size();
+    nodes.push_back(TmpNode{});
+    nodes[id].depth = depth;
+    max_depth_seen = std::max(max_depth_seen, depth);
+    Box bounds;
+    for (int i = first; i < first + count; ++i) bounds.add(tbox[perm[i]]);
+    bool halve = false;
+    const int nl = split(first, count, bounds, depth, &halve);
+    if (halve) {
+      // halving: order by centroid along the widest axis first so the halves are compact
+      Box cb;
+      for (int i = first; i < first + count; ++i) cb.add(&cen[3 * (size_t)perm[i]]);
+      int axis = 0;
+      for (int k = 1; k < 3; ++k)
+        if (cb.hi[k] - cb.lo[k] > cb.hi[axis] - cb.lo[axis]) axis = k;
+      int* p = perm.data() + first;
+      std::nth_element(p, p + nl, p + count, [&](int a, int b) {
+        return cen[3 * (size_t)a + axis] < cen[3 * (size_t)b + axis];
+      });
+    }
+    if (nl == 0) {
+      nodes[id].first = first;
+      nodes[id].count = count;
+      return id;
+    }
+    const int l = build(first, nl, depth + 1);
+    const int r = build(first + nl, count - nl, depth + 1);
+    nodes[id].left = l;
+    nodes[id].right = r;
+    return id;
+  }
+};
+
+}  // namespace
+
+int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
+                   const int32_t* tmesh, long n_tri, MeshHierarchy& out) {
+  (void)n_vertices;
+  Builder b{vertices, tris};
+  b.tbox.resize(n_tri);
+  b.cen.resize(3 * (size_t)n_tri);
+  b.perm.resize(n_tri);
+  for (long t = 0; t < n_tri; ++t) {
+    Box& bx = b.tbox[t];
+    for (int j = 0; j < 3; ++j) bx.add(vertices + 3 * (size_t)tris[3 * t + j]);
+    for (int k = 0; k < 3; ++k) b.cen[3 * t + k] = 0.5 * (bx.lo[k] + bx.hi[k]);
+    b.perm[t] = (int)t;
+  }
+  b.nodes.reserve(2 * (size_t)n_tri / kLeafMax + 16);
+  b.build(0, (int)n_tri, 0);
+  if (b.max_depth_seen > kMaxBvhDepth) return -1;
+
+  // breadth-first renumbering; every depth becomes a contiguous range
+  const int n = (int)b.nodes.size();
+  std::vector<int> order;
+  order.reserve(n);
+  order.push_back(0);
+  std::vector<int> newid(n, -1);
+  out.level_begin.assign(1, 0);
+  for (size_t head = 0; head < order.size(); ++head) {
+    const int i = order[head];
+    newid[i] = (int)head;
+    if (b.nodes[i].left >= 0) {
+      order.push_back(b.nodes[i].left);
+      order.push_back(b.nodes[i].right);
+    }
+  }
+  for (int i = 1; i < n; ++i)
+    if (b.nodes[order[i]].depth != b.nodes[order[i - 1]].depth) out.level_begin.push_back(i);
+  out.level_begin.push_back(n);
+  out.nodes.resize(n);
+  for (int k = 0; k < n; ++k) {
+    const TmpNode& t = b.nodes[order[k]];
+    BvhNode& nd = out.nodes[k];
+    for (int j = 0; j < 3; ++j) { nd.lo[j] = 0.0f; nd.hi[j] = 0.0f; }
+    if (t.left >= 0) { nd.a = newid[t.left]; nd.b = newid[t.right]; }
+    else { nd.a = t.first; nd.b = -t.count; }
+  }
+  out.tri.resize(n_tri);
+  out.tri_orig.resize(n_tri);
+  for (long i = 0; i < n_tri; ++i) {
+    const int t = b.perm[i];
+    out.tri[i] = make_int4(tris[3 * (size_t)t], tris[3 * (size_t)t + 1], tris[3 * (size_t)t + 2], tmesh[t]);
+    out.tri_orig[i] = t;
+  }
+  out.depth = b.max_depth_seen;
+  return 0;
+}
+
+namespace {
+
+// v = v_rest + (sum_j q[mesh(v)][j] phi_j(v)) n(v)
+__global__ __launch_bounds__(256) void k_mesh_vertices(long n_v, const double* __restrict__ vrest,
+                                                       const double* __restrict__ vnormal,
+                                                       const double* __restrict__ vbasis,
+                                                       const int* __restrict__ vmesh, int n_basis,
+                                                       const double* __restrict__ q,
+                                                       double* __restrict__ vcur) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_v) return;
+  const double* qm = q + (long)vmesh[v] * n_basis;
+  const double* phi = vbasis + v * n_basis;
+  double s = 0.0;
+  for (int j = 0; j < n_basis; ++j) s += qm[j] * phi[j];
+  for (int k = 0; k < 3; ++k) vcur[3 * v + k] = vrest[3 * v + k] + s * vnormal[3 * v + k];
+}
+
+__device__ __forceinline__ float round_down(double x) {
+  const float f = (float)x;
+  return (double)f > x ? nextafterf(f, -INFINITY) : f;
+}
+__device__ __forceinline__ float round_up(double x) {
+  const float f = (float)x;
+  return (double)f < x ? nextafterf(f, INFINITY) : f;
+}
+
+// Boxes of the nodes [begin, end) of one depth: a leaf from its triangles'
+// current vertices (fp64, rounded outward to fp32), an inner node as the union
+// of its children, which belong to deeper levels and are already refitted.
+__global__ __launch_bounds__(256) void k_refit(BvhNode* __restrict__ nodes, int begin, int end,
+                                               const int4* __restrict__ tri,
+                                               const double* __restrict__ vcur) {
+  const int i = begin + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= end) return;
+  BvhNode nd = nodes[i];
+  if (nd.b < 0) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int t = nd.a; t < nd.a - nd.b; ++t) {
+      const int4 tv = tri[t];
+      const int id[3] = {tv.x, tv.y, tv.z};
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) {
+          const double c = vcur[3 * (long)id[j] + k];
+          lo[k] = fmin(lo[k], c);
+          hi[k] = fmax(hi[k], c);
+        }
+    }
+    for (int k = 0; k < 3; ++k) { nd.lo[k] = round_down(lo[k]); nd.hi[k] = round_up(hi[k]); }
+  } else {
+    const BvhNode l = nodes[nd.a], r = nodes[nd.b];
+    for (int k = 0; k < 3; ++k) { nd.lo[k] = fminf(l.lo[k], r.lo[k]); nd.hi[k] = fmaxf(l.hi[k], r.hi[k]); }
+  }
+  nodes[i] = nd;
+}
+
+}  // namespace
+
+void launch_mesh_refit(const MeshDevice& m, const double* q, hipStream_t s) {
+  if (m.n_vertices > 0)
+    hipLaunchKernelGGL(k_mesh_vertices, dim3((unsigned)((m.n_vertices + 255) / 256)), dim3(256), 0, s,
+                       m.n_vertices, m.vrest, m.vnormal, m.vbasis, m.vmesh, m.n_basis, q, m.vcur);
+  for (int lv = (int)m.level_begin.size() - 2; lv >= 0; --lv) {
+    const int b = m.level_begin[lv], e = m.level_begin[lv + 1];
+    hipLaunchKernelGGL(k_refit, dim3((unsigned)((e - b + 255) / 256)), dim3(256), 0, s, m.nodes, b, e,
+                       m.tri, m.vcur);
+  }
+}
+
+}  // namespace usrt

@@ -25,6 +25,18 @@ struct GradAcc {
   double* g;
   int n_regions, n_planes;
   double np_per_m;
+  int q_offset, n_basis;          // mesh displacement coefficients in theta
+  const double* vnormal;
+  const double* vbasis;
+  // adjoint vbar of mesh vertex v (mesh m): v = v_rest + sum_j q_j phi_j n
+  __device__ void mesh_vertex(int v, int m, d3 vbar) {
+    const double s = vbar.x * vnormal[3 * v] + vbar.y * vnormal[3 * v + 1] + vbar.z * vnormal[3 * v + 2];
+    if (s == 0.0) return;
+    double* q = g + q_offset + m * n_basis;
+    const double* phi = vbasis + (long)v * n_basis;
+    for (int j = 0; j < n_basis; ++j)
+      if (phi[j] != 0.0) atomicAdd(q + j, s * phi[j]);
+  }
   __device__ void c(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r], v); }
   __device__ void Z(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 1], v); }
   // v is the adjoint of the amplitude attenuation a [Np/m]; a = alpha * np_per_m
@@ -40,6 +52,17 @@ struct GradAcc {
 };
 
 __device__ __forceinline__ d3 operator-(d3 a) { return {-a.x, -a.y, -a.z}; }
+
+// Adjoint through nu = (p1 - p0) x (p2 - p0) into the three vertices.
+__device__ __forceinline__ void tri_nu_backward(const SceneLDS& S, int i, d3 nub, d3 p0b_extra,
+                                                GradAcc& G) {
+  const int4 tv = S.tri[i];
+  const d3 p0 = vtx(S.vcur, tv.x), e1 = vtx(S.vcur, tv.y) - p0, e2 = vtx(S.vcur, tv.z) - p0;
+  const d3 e1b = cross(e2, nub), e2b = cross(nub, e1);
+  G.mesh_vertex(tv.x, tv.w, p0b_extra - e1b - e2b);
+  G.mesh_vertex(tv.y, tv.w, e1b);
+  G.mesh_vertex(tv.z, tv.w, e2b);
+}
 
 // d/dc of the receive directivity (Eq. cutoff) at cosine c; zero outside the ramp.
 __device__ __forceinline__ double rx_directivity_deriv(const ProbeView& p, double cos_a) {
@@ -72,6 +95,17 @@ __device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, i
                                                   d3 o, d3 d, double s, double sbar, d3& obar,
                                                   d3& dbar, GradAcc& G) {
   if (sbar == 0.0) return;
+  if (kind == kHitMesh) {   // s = nu.(p0 - o) / nu.d
+    const int4 tv = S.tri[idx];
+    const d3 p0 = vtx(S.vcur, tv.x);
+    const d3 nu = cross(vtx(S.vcur, tv.y) - p0, vtx(S.vcur, tv.z) - p0);
+    const double den = dot(nu, d);
+    const double numb = sbar / den, denb = -sbar * s / den;
+    obar = obar - nu * numb;
+    dbar = dbar + nu * denb;
+    tri_nu_backward(S, idx, (p0 - o) * numb + d * denb, nu * numb, G);
+    return;
+  }
   if (kind == kHitPlane || kind == kHitArray) {
     const double inv = 1.0 / d.z;
     if (kind == kHitPlane) G.plane(idx, sbar * inv);
@@ -105,6 +139,14 @@ __device__ __forceinline__ double primary_root(const SceneLDS& S, int idx, d3 o,
 // sphere: n = (x - C) / R). nbar is the adjoint of n; adds to xbar.
 __device__ __forceinline__ void normal_backward(const SceneLDS& S, int kind, int idx, d3 n,
                                                 d3 nbar, d3& xbar, GradAcc& G) {
+  if (kind == kHitMesh) {   // n = nu / |nu|
+    const int4 tv = S.tri[idx];
+    const d3 p0 = vtx(S.vcur, tv.x);
+    const d3 nu = cross(vtx(S.vcur, tv.y) - p0, vtx(S.vcur, tv.z) - p0);
+    const d3 nub = (nbar - n * dot(nbar, n)) * (1.0 / sqrt(dot(nu, nu)));
+    tri_nu_backward(S, idx, nub, d3{0, 0, 0}, G);
+    return;
+  }
   if (kind != kHitSphere) return;
   const double ir = 1.0 / S.sr[idx];
   const d3 t = nbar * ir;
@@ -146,6 +188,7 @@ struct ReplayCtx {
   const float* gh;      // dL/dh rows [n_tx][n_elem][n_t]
   long row_base;        // (tx_base + txl) * n_elem
   GradAcc& G;
+  int* stk;             // this thread's hierarchy stack in LDS
 };
 
 // Secondary ray of interaction k at x (weight watt, time tp, interface f):
@@ -168,17 +211,19 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   const double amp0 = watt * f.Ar * (kd / kPi) * co * (P.elem_w * P.elem_h * cel / (r * r)) *
                       (double)P.n_elem * fd;
   // pass 1: the march as the forward did it
-  const int max_legs = S.n_planes + 2 * S.n_spheres + 1;
+  const int legs = max_legs(S);
   double tof = tp, rest = 1.0;
   {
     d3 p = x;
     double remaining = r;
     int reg = region;
-    for (int leg = 0; leg <= max_legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false);
+    bool reached = false;
+    for (int leg = 0; leg < legs; ++leg) {
+      const Hit h = closest_hit(S, p, we, false, C.stk);
       if (h.kind == kHitNone || h.t >= remaining) {
         tof += remaining / S.c[reg];
         rest *= exp(-(S.a[reg] * remaining));
+        reached = true;
         break;
       }
       tof += h.t / S.c[reg];
@@ -191,6 +236,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
       rest *= g.At;
       reg = sf.other;
     }
+    if (!reached) return;   // the forward dropped this deposit
   }
   const double amp = amp0 * rest;
   double GA, GT;
@@ -205,8 +251,8 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
     d3 p = x;
     double remaining = r, s_cum = 0.0;
     int reg = region;
-    for (int leg = 0; leg <= max_legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false);
+    for (int leg = 0; leg < legs; ++leg) {
+      const Hit h = closest_hit(S, p, we, false, C.stk);
       if (h.kind == kHitNone || h.t >= remaining) {
         const double ell = remaining;   // = r - s_J
         C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
@@ -269,11 +315,14 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
 __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
   if ((long)blockIdx.x * blockDim.x >= a.n_chunk) return;
   __shared__ SceneLDS S;
-  extern __shared__ double gsh[];
+  extern __shared__ double gsh[];      // n_params gradient sums, then the hierarchy stacks
   load_scene(S, a.scene);
   for (int i = threadIdx.x; i < a.n_params; i += blockDim.x) gsh[i] = 0.0;
   __syncthreads();
-  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m};
+  int* stk = (int*)(gsh + ((a.n_params + 1) & ~1)) + threadIdx.x;
+  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m,
+            3 * a.scene.n_regions + a.scene.n_planes + 4 * a.scene.n_spheres, a.scene.n_basis,
+            a.scene.vnormal, a.scene.vbasis};
   const ProbeView& P = a.probe;
   const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long cap = (long)gridDim.x * blockDim.x;
@@ -284,7 +333,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
     const int txl = (int)(g / a.ray_count);
     const uint32_t rid = (uint32_t)(a.ray_begin + g % a.ray_count);
     const uint32_t tx_id = a.tx.id[txl];
-    ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G};
+    ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk};
 
     // ---- forward replay, checkpointing the state before each step
     d3 o, d;
@@ -310,7 +359,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
       a.stk.dx[at] = d.x; a.stk.dy[at] = d.y; a.stk.dz[at] = d.z;
       a.stk.t[at] = t; a.stk.w[at] = w;
       a.stk.meta[at] = (uint32_t)region | ((uint32_t)delta << 8);
-      const Hit h = closest_hit(S, o, d, true);
+      const Hit h = closest_hit(S, o, d, true, stk);
       if (h.kind == kHitNone) break;
       if (h.kind == kHitArray) { last = k; break; }
       if (k > B) break;
@@ -358,7 +407,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
       const uint32_t meta = a.stk.meta[at];
       const int reg = meta & 0xFF;
       const bool dl = (meta >> 8) & 1u;
-      const Hit h = closest_hit(S, o0, d0, true);
+      const Hit h = closest_hit(S, o0, d0, true, stk);
       const double L = h.t, c1 = S.c[reg], ar = S.a[reg];
       const double E = exp(-(ar * L));
       const double tp = t0 + L / c1, watt = w0 * E;
@@ -457,7 +506,9 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
 }
 
 void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_replay, dim3(blocks), dim3(256), (size_t)a.n_params * sizeof(double), s, a);
+  const size_t lds = (size_t)((a.n_params + 1) & ~1) * sizeof(double) +
+                     (a.scene.n_meshes > 0 ? (size_t)kBvhStack * 256 * sizeof(int) : 0);
+  hipLaunchKernelGGL(k_replay, dim3(blocks), dim3(256), lds, s, a);
 }
 
 }  // namespace usrt

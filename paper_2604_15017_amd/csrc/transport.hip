@@ -42,7 +42,9 @@ __global__ __launch_bounds__(256) void k_bounce(TraceArgs a, int k) {
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
   __shared__ unsigned long long scan[8];
+  extern __shared__ int bvh_stack[];   // kBvhStack entries per thread when the scene has meshes
   load_scene(S, a.scene);
+  int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
   const long stride = (long)gridDim.x * blockDim.x;
   unsigned long long n_seg = 0, n_dep = 0, n_int = 0;
@@ -87,9 +89,9 @@ __global__ __launch_bounds__(256) void k_bounce(TraceArgs a, int k) {
     uint64_t hsum = 0;
 
     if (active) {
-      const Hit h = closest_hit(S, o, d, true);
+      const Hit h = closest_hit(S, o, d, true, stk);
       ++n_seg;
-      if (kAudit) hsum += event_mix(kEvHit, k, ((uint32_t)h.kind << 24) | ((uint32_t)(h.index + 1) & 0xFFFFFFu));
+      if (kAudit) hsum += event_mix(kEvHit, k, ((uint32_t)h.kind << 24) | ((uint32_t)(hit_id(S, h) + 1) & 0xFFFFFFu));
       if (h.kind != kHitNone) {
         t += h.t / S.c[region];
         w *= exp(-(S.a[region] * h.t));
@@ -199,7 +201,9 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
   const long n_in = (long)(a.counts[k] >> 32);
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
+  extern __shared__ int bvh_stack[];
   load_scene(S, a.scene);
+  int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
   unsigned long long n_seg = 0, n_dep = 0, n_rays = 0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n_in;
@@ -217,16 +221,15 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
     d3 p = x;
     double remaining = r;
     uint32_t crossings = 0;
-    bool blocked = false;
-    // a straight segment crosses each plane once and each sphere twice; the
-    // cap only guards against non-finite geometry
-    const int max_legs = S.n_planes + 2 * S.n_spheres + 1;
-    for (int leg = 0; leg <= max_legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false);
+    bool blocked = true;
+    const int legs = max_legs(S);
+    for (int leg = 0; leg < legs; ++leg) {
+      const Hit h = closest_hit(S, p, we, false, stk);
       ++n_seg;
       if (h.kind == kHitNone || h.t >= remaining) {
         tof += remaining / S.c[reg];
         amp *= exp(-(S.a[reg] * remaining));
+        blocked = false;
         break;
       }
       tof += h.t / S.c[reg];
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
       const Surface sf = surface_of(S, h, p, reg);
       const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[sf.other], S.Z[sf.other]);
       ++crossings;
-      if (g.tir) { blocked = true; break; }
+      if (g.tir) break;
       amp *= g.At;
       reg = sf.other;
     }
@@ -305,16 +308,20 @@ void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
 // Grids are capped at a few blocks per compute unit; the kernels loop.
 constexpr int kMaxBlocks = 2048;
 
+static size_t stack_bytes(const TraceArgs& a) {
+  return a.scene.n_meshes > 0 ? (size_t)kBvhStack * 256 * sizeof(int) : 0;
+}
+
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {
   const dim3 grid(grid_for(max_rays, 256, kMaxBlocks)), block(256);
-  if (audit) hipLaunchKernelGGL(k_bounce<true>, grid, block, 0, s, a, k);
-  else hipLaunchKernelGGL(k_bounce<false>, grid, block, 0, s, a, k);
+  if (audit) hipLaunchKernelGGL(k_bounce<true>, grid, block, stack_bytes(a), s, a, k);
+  else hipLaunchKernelGGL(k_bounce<false>, grid, block, stack_bytes(a), s, a, k);
 }
 
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {
   const dim3 grid(grid_for(max_rays, 256, kMaxBlocks)), block(256);
-  if (audit) hipLaunchKernelGGL(k_secondary<true>, grid, block, 0, s, a, k);
-  else hipLaunchKernelGGL(k_secondary<false>, grid, block, 0, s, a, k);
+  if (audit) hipLaunchKernelGGL(k_secondary<true>, grid, block, stack_bytes(a), s, a, k);
+  else hipLaunchKernelGGL(k_secondary<false>, grid, block, stack_bytes(a), s, a, k);
 }
 
 int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,

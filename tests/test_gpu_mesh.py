@@ -1,0 +1,208 @@
+"""GPU parity of the triangle-mesh path (hierarchy walk with an LDS stack,
+refit on parameter change, flat-face interface physics, displacement-basis
+gradients) through the C-ABI against the FP64 oracle.
+
+Tolerances as for the analytic scenes: RF relative L2 <= 1e-4, flipped paths
+<= 1e-5 of the rays, gradients <= 1e-3 relative on every parameter above
+1e-3 of the largest (scaled units)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_15017_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RF_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2604_15017_amd import _lib
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    return L.Context(0)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def mesh_scene(meshes, regions, planes=(), plane_regions=()):
+    return W.Scene(regions=np.array(regions, dtype=np.float64), planes=np.array(planes, np.float64),
+                   plane_regions=np.array(plane_regions, np.int32).reshape(-1, 2),
+                   plane_kd=np.zeros(len(planes)), spheres=np.zeros((0, 4)),
+                   sphere_regions=np.zeros((0, 2), np.int32), sphere_kd=np.zeros(0), meshes=meshes)
+
+
+def small_anatomy(rays_per_elem=64, kd=0.2, seed=0):
+    """An organ-like blob (1280 faces) holding a capped vessel tube, 2 transmits."""
+    rng = np.random.default_rng(seed)
+    meshes = [W.blob_mesh([0, 0, 25e-3], 8e-3, 3, rng, region_in=1, region_out=0, kd=kd),
+              W.tube_mesh([3e-3, 0, 26e-3], 1.5e-3, 4e-3, 24, 10, region_in=2, region_out=1, kd=kd)]
+    sc = mesh_scene(meshes, [[1540, 1.63, 0.5], [1580, 1.75, 0.7], [1500, 1.45, 0.4]])
+    return W.anatomy_phantom(level_organ=1, level_lesion=1, tube_around=8, tube_along=2).replace(
+        scene=sc, rays_per_elem=rays_per_elem, angles=np.radians([-6.0, 4.0]),
+        tx_ids=np.arange(2, dtype=np.uint32), max_bounces=6)
+
+
+def gpu_rf(L, ctx, wl, theta=None, ray_begin=0, ray_count=None, set_params=None):
+    import torch
+    scene, probe = L.Scene(ctx, wl.scene, theta=theta), L.Probe(ctx, wl.probe)
+    if set_params is not None:
+        scene.set_params(torch.tensor(set_params, dtype=torch.float64, device="cuda"))
+    if ray_count is None:
+        ray_count = wl.rays_per_tx - ray_begin
+    counters = torch.zeros(5, dtype=torch.int64, device="cuda")
+    hashes = torch.zeros((wl.n_tx, ray_count), dtype=torch.int64, device="cuda")
+    rf = L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                          wl.max_bounces, ray_begin=ray_begin, ray_count=ray_count,
+                          counters=counters, ray_hash=hashes)
+    torch.cuda.synchronize()
+    return (rf.cpu().numpy().astype(np.float64), counters.cpu().numpy(),
+            hashes.cpu().numpy().view(np.uint64))
+
+
+def check(L, ctx, wl, label, theta=None, set_params=None, **kw):
+    rf, cnt, hashes = gpu_rf(L, ctx, wl, theta=theta, set_params=set_params, **kw)
+    th = set_params if set_params is not None else theta
+    ref, _, tr = oracle.simulate_rf(wl, theta=th, want_hashes=True, **kw)
+    rel = rel_l2(rf, ref)
+    flips = int(np.count_nonzero(hashes != tr.hashes))
+    print(f"{label}: rf rel-L2 {rel:.3e}, flipped paths {flips}/{tr.hashes.size}, "
+          f"segments gpu {cnt[0] + cnt[1]} oracle {tr.segments}, deposits {cnt[2]}", flush=True)
+    assert flips / tr.hashes.size <= 1e-5
+    assert rel <= RF_TOL
+    if flips == 0:
+        assert cnt[0] + cnt[1] == tr.segments and cnt[2] == tr.t.shape[0]
+    return rf, ref
+
+
+def test_small_mesh_scene_forward(L, ctx):
+    check(L, ctx, small_anatomy(), "blob + tube")
+
+
+def test_specular_mesh_forward(L, ctx):
+    check(L, ctx, small_anatomy(kd=0.0, seed=1), "specular blob + tube")
+
+
+def box_mesh(z0, z1, half=0.5):
+    v = np.array([[x, y, z] for z in (z0, z1) for y in (-half, half) for x in (-half, half)], dtype=np.float64)
+    f = np.array([[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1],
+                  [2, 3, 7], [2, 7, 6], [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]])
+    f = W._orient_outward(v, f, np.array([0.0, 0.0, 0.5 * (z0 + z1)])).astype(np.int32)
+    basis = (np.abs(v[:, 2] - z0) < 1e-12).astype(np.float64)[:, None]
+    return W.Mesh(v, f, np.tile([0.0, 0.0, -1.0], (8, 1)), basis, 1, 0, 0.0)
+
+
+def test_box_mesh_matches_planes_on_gpu(L, ctx):
+    """A closed box whose top and bottom faces coincide with two planes gives
+    the planes' RF (same paths, same decisions) on the GPU."""
+    z0, z1 = 12e-3, 31e-3
+    regions = [[1480.0, 1.48, 0.0], [1560.0, 1.7, 0.6]]
+    wl = W.layered_phantom().replace(rays_per_elem=64, angles=np.radians([-8.0, 3.0]),
+                                     tx_ids=np.arange(2, dtype=np.uint32), max_bounces=5)
+    planes = mesh_scene([], regions, [z0, z1], [[0, 1], [1, 0]])
+    rf_p, _, h_p = gpu_rf(L, ctx, wl.replace(scene=planes))
+    box = wl.replace(scene=mesh_scene([box_mesh(z0, z1)], regions))
+    rf_b, _ = check(L, ctx, box, "box mesh")
+    assert rel_l2(rf_b, rf_p) <= 1e-6
+
+
+def test_refit_after_set_params(L, ctx):
+    """Displacement coefficients move the surfaces: uploading at theta_q and
+    uploading at rest then us_scene_set_params(theta_q) both match the oracle
+    at theta_q."""
+    wl = small_anatomy(rays_per_elem=32, seed=2)
+    theta = wl.scene.theta()
+    rng = np.random.default_rng(7)
+    tq = theta.copy()
+    for m in range(2):
+        for j in range(wl.scene.meshes[m].basis.shape[1]):
+            tq[wl.scene.idx_mesh(m, j)] = rng.uniform(-0.4e-3, 0.4e-3)
+    a, ref = check(L, ctx, wl, "displaced, uploaded", theta=tq)
+    b, _ = check(L, ctx, wl, "displaced, set_params", set_params=tq)
+    assert rel_l2(a, b) <= 1e-6   # fp32 atomic deposits: equal up to summation order
+    rest, _, _ = gpu_rf(L, ctx, wl)
+    assert rel_l2(rest, ref) > 1e-2   # the displacement changed the image
+
+
+def test_anatomy_phantom_ray_sample(L, ctx):
+    """The 200,192-triangle anatomy phantom at full size and every transmit: a
+    ray range covering several elements against the oracle on that range."""
+    wl = W.anatomy_phantom()
+    check(L, ctx, wl, "anatomy phantom sample", ray_begin=400_003, ray_count=6000)
+
+
+def smooth_field(shape, seed):
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(shape)
+    k = np.exp(-0.5 * (np.arange(-30, 31) / 10.0) ** 2)
+    return np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), -1, g)
+
+
+def compare_grads(g_gpu, g_ref, theta, label):
+    unit = np.where(theta != 0, np.abs(theta), 1e-3)
+    sg, sr = g_gpu * unit, g_ref * unit
+    scale = np.abs(sr).max()
+    assert scale > 0
+    big = np.abs(sr) >= 1e-3 * scale
+    rel = np.abs(sg - sr) / np.maximum(np.abs(sr), 1e-300)
+    worst = float(rel[big].max())
+    small_err = float((np.abs(sg - sr)[~big]).max() / scale) if (~big).any() else 0.0
+    print(f"{label}: {big.sum()} significant parameters, worst relative error {worst:.2e}, "
+          f"others {small_err:.2e} of the largest", flush=True)
+    bad = np.flatnonzero(big & (rel > 1e-3))
+    assert worst <= 1e-3, [(int(j), float(g_gpu[j]), float(g_ref[j])) for j in bad]
+    assert small_err <= 1e-6
+    return big
+
+
+def mesh_vjp(L, ctx, wl, label, theta=None, ray_begin=0, ray_count=None):
+    import torch
+    p = wl.probe
+    g_rf = smooth_field((wl.n_tx, p.n_elem, p.n_t), 3).astype(np.float32)
+    _, s = oracle.pulse_taps(p.f0, p.n_cycles, p.fs)
+    g_h = oracle.pulse_vjp(g_rf.astype(np.float64), s)
+    th = wl.scene.theta() if theta is None else theta
+    ref = np.zeros_like(th)
+    for c0 in range(0, th.shape[0], 64):
+        sel = list(range(c0, min(th.shape[0], c0 + 64)))
+        ref += oracle.trace(wl.scene, p, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                            wl.max_bounces, ray_begin=ray_begin, ray_count=ray_count, theta=th,
+                            g_h=g_h, grad_params=sel).g_theta
+    scene, probe = L.Scene(ctx, wl.scene, theta=th), L.Probe(ctx, wl.probe)
+    if ray_count is None:
+        ray_count = wl.rays_per_tx - ray_begin
+    g = L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                             wl.max_bounces, torch.tensor(g_rf, device="cuda"),
+                             ray_begin=ray_begin, ray_count=ray_count)
+    torch.cuda.synchronize()
+    return compare_grads(g.cpu().numpy(), ref, th, label)
+
+
+def test_mesh_vjp_small_scene(L, ctx):
+    wl = small_anatomy(rays_per_elem=48)
+    big = mesh_vjp(L, ctx, wl, "blob + tube VJP")
+    q0 = wl.scene.idx_mesh(0, 0)
+    assert big[q0:].sum() >= 8   # the displacement coefficients carry real gradient
+
+
+def test_mesh_vjp_displaced_specular(L, ctx):
+    wl = small_anatomy(rays_per_elem=48, kd=0.0, seed=3)
+    tq = wl.scene.theta()
+    rng = np.random.default_rng(11)
+    for m in range(2):
+        for j in range(16):
+            tq[wl.scene.idx_mesh(m, j)] = rng.uniform(-0.3e-3, 0.3e-3)
+    mesh_vjp(L, ctx, wl, "displaced specular VJP", theta=tq)
+
+
+def test_anatomy_phantom_vjp_ray_sample(L, ctx):
+    wl = W.anatomy_phantom()
+    mesh_vjp(L, ctx, wl, "anatomy phantom VJP sample", ray_begin=300_001, ray_count=3000)
