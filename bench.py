@@ -3,7 +3,9 @@
 One step = one B-mode frame of the layered phantom (11 plane waves x 2^20
 rays, 8 interactions, 128 elements x 4096 samples, 256 x 512 pixels): transport
 and RF synthesis, beamforming, envelope and log compression, all through the
-C-ABI with inputs and buffers resident in HBM. Prints one JSON line with the
+C-ABI with inputs and buffers resident in HBM. The same protocol is repeated
+for forward + backward, and for the triangle-mesh anatomy phantom (200k
+triangles, 21 x 798,912 rays, 12 interactions), reported beside it. Prints one JSON line with the
 throughput in ray-segments/s (a segment is one closest-hit query, primary or
 secondary), frames/s, per-kernel timings from HIP events recorded on the
 launch stream inside the timed region, the roofline of the dominant kernel and
@@ -73,8 +75,8 @@ def cpu_baseline(wl):
 
 def serving(ctx, n_requests):
     """Serving stream: Poisson arrivals at 80 % of the measured one-at-a-time
-    throughput, scenes 40/40/20 from the two-layer and two layered-phantom
-    draws, 2^14..2^24 rays, grids 128x256..512x1024, 30 % gradient requests,
+    throughput, scenes 40/40/20 from the two-layer, layered-phantom and mesh
+    anatomy generators, 2^14..2^24 rays, grids 128x256..512x1024, 30 % gradient requests,
     200 GB admission cap; one slot (plain) against eight slots (continuous
     batching) on the same arrivals."""
     import torch
@@ -102,6 +104,7 @@ def serving(ctx, n_requests):
     srv.run(len(batch))
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
+    print(f"serving: plain closed loop {plain_s:.2f} s", file=sys.stderr, flush=True)
     # the same closed loop with eight overlapping slots
     ex8 = S.GpuExecutor(ctx, n_slots=8)
     srv = S.Server(ex8, n_slots=8)
@@ -111,6 +114,7 @@ def serving(ctx, n_requests):
     srv.run(len(batch))
     torch.cuda.synchronize()
     batched_s = time.perf_counter() - t0
+    print(f"serving: batched closed loop {batched_s:.2f} s", file=sys.stderr, flush=True)
     rate = 0.8 * len(batch) / plain_s
     offsets = S.poisson_arrivals(len(batch), rate, seed=4)
     out = {"requests": len(batch), "grad_requests": int(sum(r.want_grad for r in batch)),
@@ -127,30 +131,19 @@ def serving(ctx, n_requests):
         st.update({"slots": slots, "max_concurrent": srv.max_concurrent,
                    "peak_reserved_GB": round(srv.max_reserved / 1e9, 2)})
         out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+        print(f"serving: {name} p50 {st.get('p50_ms')} ms p99 {st.get('p99_ms')} ms", file=sys.stderr,
+              flush=True)
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=512)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
-        sys.exit(2)
-
-    import numpy as np
+def frame_legs(ctx, wl, target, steps, warmup):
+    """Forward (one B-mode frame) and forward + backward (B-mode MSE against
+    the image of `target`, gradient of every parameter) of one workload, each
+    timed over `steps` frames after `warmup` untimed ones with HIP events on the
+    launch stream; per-kernel times from the library's own event log."""
     import torch
     from paper_2604_15017_amd import _lib as L
-    from paper_2604_15017_amd import workloads as W
-
-    wl = W.layered_phantom()
     p, g = wl.probe, wl.grid
-    ctx = L.Context(0)
     scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
     dev = ctx.torch_device
     rf = torch.empty((wl.n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=dev)
@@ -163,20 +156,15 @@ def main():
     counters = torch.zeros(5, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step(cnt=None):
-        L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+    def step(sc=scene, cnt=None):
+        L.us_simulate_rf(ctx, sc, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
                          wl.max_bounces, rf=rf, counters=cnt, workspace=ws_t, stream=stream)
         L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf, iq=iq, workspace=ws_b, stream=stream)
         L.us_bmode(ctx, iq, wl.dr_db, out=bm, workspace=ws_m, stream=stream)
 
-    # forward + backward: B-mode MSE against a target rendered from the
-    # seeded +-5 % perturbation of 34 parameters, gradient for all parameters
-    target = W.layered_phantom_target(wl)
     scene_t = L.Scene(ctx, target)
-    L.us_simulate_rf(ctx, scene_t, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
-                     wl.max_bounces, rf=rf, workspace=ws_t, stream=stream)
-    L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf, iq=iq, workspace=ws_b, stream=stream)
-    b_ref = L.us_bmode(ctx, iq, wl.dr_db, workspace=ws_m, stream=stream).clone()
+    step(scene_t)
+    b_ref = bm.clone()
     del scene_t
     ws_r = L._workspace(L.us_simulate_rf_vjp_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx,
                                                             wl.max_bounces), dev)
@@ -197,62 +185,71 @@ def main():
         L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
                              wl.max_bounces, g_rf, g_theta=g_theta, workspace=ws_r, stream=stream)
 
-    step(counters)                      # event counts of one frame (deterministic)
+    step(cnt=counters)                  # event counts of one frame (deterministic)
     torch.cuda.synchronize()
     counts = [int(v) for v in counters.cpu().numpy()]
-    segments = counts[0] + counts[1]
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    L.us_profile_enable(ctx, True)
-    L.us_profile_read(ctx)              # clear
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    for _ in range(args.steps):
-        step()
-    end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
-    prof = L.us_profile_read(ctx)
-    L.us_profile_enable(ctx, False)
 
-    # forward + backward, same protocol
-    for _ in range(args.warmup):
-        step_fb()
-    torch.cuda.synchronize()
-    L.us_profile_enable(ctx, True)
-    L.us_profile_read(ctx)
-    start.record(stream)
-    for _ in range(args.steps):
-        step_fb()
-    end.record(stream)
-    torch.cuda.synchronize()
-    fb_ms = start.elapsed_time(end) / args.steps
-    prof_fb = L.us_profile_read(ctx)
-    L.us_profile_enable(ctx, False)
-    fb_kernels = {}
-    for name, (ms, launches) in prof_fb.items():
-        per_step_ms = ms / args.steps
-        nbytes = kernel_bytes(name, wl, counts, g.n_px)
-        fb_kernels[name] = {"ms_per_step": round(per_step_ms, 4),
-                            "launches_per_step": launches // args.steps,
-                            "algorithmic_GBps": round(nbytes / (per_step_ms * 1e-3) / 1e9, 1) if nbytes else None}
-    fwd_bwd = {"workload": "layered_phantom forward + backward, B-mode MSE vs +-5 % target, "
-                           f"gradient of all {scene.n_params} parameters",
-               "ms_per_step": round(fb_ms, 4), "frames_per_s": round(1e3 / fb_ms, 2),
-               "ray_segments_per_s": segments / (fb_ms * 1e-3),
-               "loss": float(loss.item()), "kernels": fb_kernels}
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        L.us_profile_enable(ctx, True)
+        L.us_profile_read(ctx)          # clear
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(steps):
+            fn()
+        end.record(stream)
+        torch.cuda.synchronize()
+        prof = L.us_profile_read(ctx)
+        L.us_profile_enable(ctx, False)
+        return start.elapsed_time(end) / steps, prof
 
-    ms_per_step = total_ms / args.steps
-    kernels = {}
-    for name, (ms, launches) in prof.items():
-        per_step_ms = ms / args.steps
-        nbytes = kernel_bytes(name, wl, counts, g.n_px)
-        kernels[name] = {"ms_per_step": round(per_step_ms, 4), "launches_per_step": launches // args.steps,
-                         "avg_launch_us": round(1e3 * ms / launches, 2),
+    def kernel_table(prof):
+        out = {}
+        for name, (ms, launches) in prof.items():
+            per_step_ms = ms / steps
+            nbytes = kernel_bytes(name, wl, counts, g.n_px)
+            out[name] = {"ms_per_step": round(per_step_ms, 4), "launches_per_step": launches // steps,
+                         "avg_launch_us": round(1e3 * ms / max(1, launches), 2),
                          "algorithmic_GBps": round(nbytes / (per_step_ms * 1e-3) / 1e9, 1) if nbytes else None}
+        return out
+
+    fwd_ms, prof = timed(step)
+    fb_ms, prof_fb = timed(step_fb)
+    segments = counts[0] + counts[1]
+    return {"counts": counts, "segments": segments, "n_params": scene.n_params,
+            "fwd_ms": fwd_ms, "prof": prof, "kernels": kernel_table(prof),
+            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb), "loss": float(loss.item())}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-anatomy", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    from paper_2604_15017_amd import _lib as L
+    from paper_2604_15017_amd import workloads as W
+
+    ctx = L.Context(0)
+    wl = W.layered_phantom()
+    p, g = wl.probe, wl.grid
+    r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup)
+    counts, segments, prof = r["counts"], r["segments"], r["prof"]
+    ms_per_step = r["fwd_ms"]
+    print(f"layered phantom: forward {ms_per_step:.3f} ms/frame, forward+backward "
+          f"{r['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
+
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms = prof[dom][0] / args.steps
     dom_bytes = kernel_bytes(dom, wl, counts, g.n_px)
@@ -279,10 +276,32 @@ def main():
         "segments_per_frame": segments,
         "frame_counts": {"primary_segments": counts[0], "secondary_segments": counts[1],
                          "deposits": counts[2], "interactions": counts[3], "secondary_rays": counts[4]},
-        "kernels": kernels,
+        "kernels": r["kernels"],
         "roofline": roofline,
-        "fwd_bwd": fwd_bwd,
+        "fwd_bwd": {"workload": "layered_phantom forward + backward, B-mode MSE vs +-5 % target, "
+                                f"gradient of all {r['n_params']} parameters",
+                    "ms_per_step": round(r["fb_ms"], 4), "frames_per_s": round(1e3 / r["fb_ms"], 2),
+                    "ray_segments_per_s": segments / (r["fb_ms"] * 1e-3),
+                    "loss": r["loss"], "kernels": r["fb_kernels"]},
     }
+    if not args.no_anatomy:
+        wa = W.anatomy_phantom()
+        a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup)
+        print(f"anatomy phantom: forward {a['fwd_ms']:.3f} ms/frame, forward+backward "
+              f"{a['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
+        out["anatomy"] = {
+            "workload": f"anatomy_phantom: {sum(len(m.triangles) for m in wa.scene.meshes)} triangles "
+                        f"in {len(wa.scene.meshes)} closed meshes, {wa.n_tx} x {wa.rays_per_tx} rays, "
+                        f"{wa.max_bounces} interactions, {wa.probe.n_elem} x {wa.probe.n_t} samples, "
+                        f"{wa.grid.n_x} x {wa.grid.n_z} pixels",
+            "forward": {"ms_per_step": round(a["fwd_ms"], 4), "frames_per_s": round(1e3 / a["fwd_ms"], 2),
+                        "ray_segments_per_s": a["segments"] / (a["fwd_ms"] * 1e-3),
+                        "segments_per_frame": a["segments"], "kernels": a["kernels"]},
+            "fwd_bwd": {"ms_per_step": round(a["fb_ms"], 4), "frames_per_s": round(1e3 / a["fb_ms"], 2),
+                        "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
+                        "gradient_parameters": a["n_params"], "loss": a["loss"],
+                        "kernels": a["fb_kernels"]},
+        }
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:

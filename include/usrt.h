@@ -75,7 +75,7 @@ typedef struct us_probe_desc {
  * vertex ids, counter-clockwise seen from outside, owning mesh tmesh[t], all
  * three vertices of that mesh). Vertex v moves along its unit direction
  * vnormal[v] by sum_j q[vmesh[v]][j] vbasis[v][j]; faces are flat. At most
- * 32 meshes; zero-area triangles are rejected. The library builds a
+ * 32 meshes and 2^27 - 1 triangles; zero-area triangles are rejected. The library builds a
  * bounding-volume hierarchy on upload (rejected with US_EINVAL if deeper than
  * 38 levels) and refits it on every us_scene_set_params. */
 typedef struct us_scene_desc {

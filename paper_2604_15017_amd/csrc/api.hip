@@ -108,7 +108,7 @@ struct us_scene {
   int* sphere_regions;
   double* sphere_kd;
   // meshes
-  int n_meshes, n_basis, q_offset;
+  int n_meshes, n_basis, q_offset, stack_cap;
   int* mesh_regions;
   double* mesh_kd;
   int* tri_orig;
@@ -205,7 +205,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
                  d->tmesh && (d->n_basis == 0 || d->vbasis),
              "us_scene_upload: mesh arrays missing");
     US_CHECK(d->n_vertices >= 3 && d->n_vertices < (1L << 30), "us_scene_upload: n_vertices must be in [3, 2^30)");
-    US_CHECK(d->n_triangles >= 1 && d->n_triangles < (1L << 30), "us_scene_upload: n_triangles must be in [1, 2^30)");
+    US_CHECK(d->n_triangles >= 1 && d->n_triangles < (1L << 27), "us_scene_upload: n_triangles must be in [1, 2^27)");
   }
   const int q_offset = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
   const int np = q_offset + (nm > 0 ? nm * d->n_basis : 0);
@@ -258,14 +258,14 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
       US_CHECK(cx * cx + cy * cy + cz * cz > 0.0, "us_scene_upload: zero-area triangle");
     }
     US_CHECK(build_mesh_bvh(d->vertices, nv, d->triangles, d->tmesh, nt, H) == 0,
-             "us_scene_upload: mesh hierarchy deeper than 38 levels");
+             "us_scene_upload: mesh hierarchy deeper than 38 levels (degenerate triangle set)");
   }
   US_HIP(hipSetDevice(ctx->device));
   us_scene* s = new us_scene{};
   s->ctx = ctx;
   s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
   s->start_region = d->start_region; s->n_params = np; s->any_diffuse = diffuse;
-  s->n_meshes = nm; s->n_basis = nb; s->q_offset = q_offset;
+  s->n_meshes = nm; s->n_basis = nb; s->q_offset = q_offset; s->stack_cap = nm > 0 ? H.depth : 0;
   bool ok = hipMalloc(&s->theta, np * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->plane_regions, (2 * d->n_planes + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc(&s->plane_kd, (d->n_planes + 1) * sizeof(double)) == hipSuccess &&
@@ -285,6 +285,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
          hipMalloc(&vbasis, (nv * nb + 1) * sizeof(double)) == hipSuccess &&
          hipMalloc(&vmesh, nv * sizeof(int)) == hipSuccess &&
          hipMalloc(&md.vcur, 3 * nv * sizeof(double)) == hipSuccess &&
+         hipMalloc(&md.trec, nt * sizeof(TriRec)) == hipSuccess &&
          hipMalloc(&md.nodes, H.nodes.size() * sizeof(BvhNode)) == hipSuccess &&
          hipMalloc(&tri, nt * sizeof(int4)) == hipSuccess &&
          hipMalloc(&s->tri_orig, nt * sizeof(int)) == hipSuccess;
@@ -340,6 +341,7 @@ int us_scene_destroy(us_scene* s) {
   (void)hipFree((void*)s->mesh.vbasis);
   (void)hipFree((void*)s->mesh.vmesh);
   (void)hipFree(s->mesh.vcur);
+  (void)hipFree(s->mesh.trec);
   (void)hipFree(s->mesh.nodes);
   (void)hipFree((void*)s->mesh.tri);
   delete s;
@@ -376,9 +378,11 @@ SceneView scene_view(const us_scene* s, const us_probe* p) {
   v.start_region = s->start_region;
   v.n_meshes = s->n_meshes;
   v.n_basis = s->n_basis;
+  v.stack_cap = s->stack_cap;
   v.mesh_regions = s->mesh_regions;
   v.mesh_kd = s->mesh_kd;
   v.nodes = s->mesh.nodes;
+  v.trec = s->mesh.trec;
   v.tri = s->mesh.tri;
   v.tri_orig = s->tri_orig;
   v.vcur = s->mesh.vcur;

@@ -12,8 +12,8 @@ constexpr int kMaxPlanes = 16;
 constexpr int kMaxSpheres = 32;
 constexpr int kMaxTxPerLaunch = 64;
 constexpr int kMaxMeshes = 32;
-constexpr int kBvhStack = 40;           // per-thread LDS stack entries
-constexpr int kMaxBvhDepth = kBvhStack - 2;   // leaves at depth <= 38 keep the stack within 40
+constexpr int kMaxBvhDepth = 38;        // inner levels of the hierarchy; the walk's LDS
+                                        // stack holds at most one entry per inner level
 constexpr double kTMin = 1e-6;          // self-intersection guard [m]
 constexpr double kPi = 3.14159265358979323846;
 
@@ -64,14 +64,21 @@ __device__ __forceinline__ uint64_t event_mix(uint32_t tag, uint32_t k, uint32_t
 enum : uint32_t { kEvHit = 1, kEvArray = 2, kEvBranch = 3, kEvNee = 4 };
 enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3, kHitMesh = 4 };
 
-// Bounding-volume hierarchy node (32 B): fp32 box rounded outward; inner
-// node: a = left child, b = right child; leaf: a = first triangle (leaf
-// order), b = -count.
+// Inner node of the bounding-volume hierarchy (64 B): the fp32 boxes of both
+// children (rounded outward) and the child references. A reference c >= 0 is
+// an inner node; c < 0 is a leaf holding the n = (~c) & 15 triangles starting
+// at (~c) >> 4 in leaf order (n = 0: empty).
 struct BvhNode {
-  float lo[3];
-  int a;
-  float hi[3];
-  int b;
+  float lo_l[3], hi_l[3];
+  float lo_r[3], hi_r[3];
+  int left, right, pad0, pad1;
+};
+constexpr int kLeafCap = 15;
+
+// Leaf-order triangle as the walk reads it: p0 and the edges p1 - p0,
+// p2 - p0 in fp64 (80 B, 16-B aligned), rewritten by every refit.
+struct TriRec {
+  double p0[3], e1[3], e2[3], pad;
 };
 
 struct d3 { double x, y, z; };
@@ -97,9 +104,11 @@ struct SceneView {
   double np_per_m;       // amplitude attenuation [Np/m] per dB/cm/MHz at f0
   // triangle meshes (all null / zero without meshes)
   int n_meshes, n_basis;
+  int stack_cap;               // LDS stack entries per thread (>= inner levels)
   const int* mesh_regions;     // [n_meshes][2]: inside, outside
   const double* mesh_kd;       // [n_meshes]
   const BvhNode* nodes;
+  const TriRec* trec;          // leaf order: current geometry
   const int4* tri;             // leaf order: vertex ids (x, y, z), mesh id (w)
   const int* tri_orig;         // leaf order -> triangle id of the description
   const double* vcur;          // [V][3] current vertex positions
@@ -116,9 +125,10 @@ struct SceneLDS {
   int sreg[kMaxSpheres][2];
   int mreg[kMaxMeshes][2];
   double mkd[kMaxMeshes];
-  int n_planes, n_spheres, n_meshes, start_region;
+  int n_planes, n_spheres, n_meshes, start_region, stack_cap;
   bool any_diffuse;
   const BvhNode* nodes;
+  const TriRec* trec;
   const int4* tri;
   const int* tri_orig;
   const double* vcur;
@@ -157,6 +167,7 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
     s.n_planes = v.n_planes;
     s.n_spheres = v.n_spheres;
     s.n_meshes = v.n_meshes;
+    s.stack_cap = v.stack_cap;
     s.start_region = v.start_region;
     bool d = false;
     for (int i = 0; i < v.n_planes; ++i) d |= v.plane_kd[i] > 0.0;
@@ -164,6 +175,7 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
     for (int i = 0; i < v.n_meshes; ++i) d |= v.mesh_kd[i] > 0.0;
     s.any_diffuse = d;
     s.nodes = v.nodes;
+    s.trec = v.trec;
     s.tri = v.tri;
     s.tri_orig = v.tri_orig;
     s.vcur = v.vcur;

@@ -15,14 +15,29 @@ __device__ __forceinline__ d3 cross(d3 a, d3 b) {
   return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
-// Moller-Trumbore in fp64, edges included; distance or -1.
-__device__ __forceinline__ double tri_distance(d3 p0, d3 p1, d3 p2, d3 o, d3 d) {
-  const d3 e1 = p1 - p0, e2 = p2 - p0;
+// Ray against one fp32 child box padded by kPad (absorbs the rounding of the
+// ray to fp32); entry distance in *t0, culled beyond lim.
+__device__ __forceinline__ bool slab(const float* lo, const float* hi, float ox, float oy, float oz,
+                                     float ix, float iy, float iz, float lim, float* t0) {
+  constexpr float kPad = 1e-6f;
+  const float ax = (lo[0] - kPad - ox) * ix, bx = (hi[0] + kPad - ox) * ix;
+  const float ay = (lo[1] - kPad - oy) * iy, by = (hi[1] + kPad - oy) * iy;
+  const float az = (lo[2] - kPad - oz) * iz, bz = (hi[2] + kPad - oz) * iz;
+  const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+  const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+  *t0 = tmin;
+  return tmin <= tmax && tmin <= lim;
+}
+
+// Moller-Trumbore in fp64 on a leaf-order triangle record, edges included;
+// distance or -1.
+__device__ __forceinline__ double rec_distance(const TriRec& r, d3 o, d3 d) {
+  const d3 e1{r.e1[0], r.e1[1], r.e1[2]}, e2{r.e2[0], r.e2[1], r.e2[2]};
   const d3 pv = cross(d, e2);
   const double det = dot(e1, pv);
   if (det == 0.0) return -1.0;
   const double inv = 1.0 / det;
-  const d3 sv = o - p0;
+  const d3 sv = o - d3{r.p0[0], r.p0[1], r.p0[2]};
   const double u = dot(sv, pv) * inv;
   if (u < 0.0 || u > 1.0) return -1.0;
   const d3 qv = cross(sv, e1);
@@ -31,10 +46,12 @@ __device__ __forceinline__ double tri_distance(d3 p0, d3 p1, d3 p2, d3 o, d3 d) 
   return dot(e2, qv) * inv;
 }
 
-// Closest triangle in (kTMin, best) by walking the hierarchy; the node stack
-// lives in LDS, interleaved across the block's threads (entry i of this
-// thread at stk[i * blockDim.x]). Boxes are tested in fp32, padded by 1 um
-// to absorb the rounding of the ray to fp32; triangles in fp64.
+// Closest triangle in (kTMin, best) by walking the hierarchy near child
+// first. One step handles one inner node (both child boxes tested against the
+// ray in fp32; the farther of two hit children is pushed) or one leaf (its
+// triangles intersected in fp64). The stack lives in LDS, interleaved across
+// the block's threads (entry i of this thread at stk[i * blockDim.x]); it
+// holds at most one entry per inner level.
 __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, double& best, int& best_tri,
                                              int* stk) {
   constexpr float kPad = 1e-6f;
@@ -43,37 +60,43 @@ __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, doub
   const float iy = fabs(d.y) > 1e-30 ? (float)(1.0 / d.y) : copysignf(1e30f, (float)d.y);
   const float iz = fabs(d.z) > 1e-30 ? (float)(1.0 / d.z) : copysignf(1e30f, (float)d.z);
   const int step = blockDim.x;
-  int sp = 1;
-  stk[0] = 0;
-  while (sp > 0) {
-    --sp;
-    const BvhNode nd = s.nodes[stk[sp * step]];
-    const float ax = (nd.lo[0] - kPad - ox) * ix, bx = (nd.hi[0] + kPad - ox) * ix;
-    const float ay = (nd.lo[1] - kPad - oy) * iy, by = (nd.hi[1] + kPad - oy) * iy;
-    const float az = (nd.lo[2] - kPad - oz) * iz, bz = (nd.hi[2] + kPad - oz) * iz;
-    const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
-    const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
-    if (tmin > tmax || tmin > (float)best * 1.0001f + kPad) continue;
-    if (nd.b < 0) {
-      for (int i = nd.a; i < nd.a - nd.b; ++i) {
-        const int4 tv = s.tri[i];
-        const double t = tri_distance(vtx(s.vcur, tv.x), vtx(s.vcur, tv.y), vtx(s.vcur, tv.z), o, d);
+  int sp = 0, cur = 0;
+  for (;;) {
+    if (cur >= 0) {
+      const BvhNode n = s.nodes[cur];
+      const float lim = (float)best * 1.0001f + kPad;
+      float tl, tr;
+      const bool hl = slab(n.lo_l, n.hi_l, ox, oy, oz, ix, iy, iz, lim, &tl);
+      const bool hr = slab(n.lo_r, n.hi_r, ox, oy, oz, ix, iy, iz, lim, &tr);
+      if (hl && hr) {
+        const bool left_first = tl <= tr;
+        // the build bounds the inner depth by stack_cap, so the push always fits
+        if (sp < s.stack_cap) { stk[sp * step] = left_first ? n.right : n.left; ++sp; }
+        cur = left_first ? n.left : n.right;
+        continue;
+      }
+      if (hl) { cur = n.left; continue; }
+      if (hr) { cur = n.right; continue; }
+    } else {
+      const int first = (~cur) >> 4, cnt = (~cur) & 15;
+      for (int i = first; i < first + cnt; ++i) {
+        const double t = rec_distance(s.trec[i], o, d);
         if (t > kTMin && t < best) { best = t; best_tri = i; }
       }
-    } else if (sp + 2 <= kBvhStack) {   // the build bounds the depth, so this always holds
-      stk[sp * step] = nd.b;
-      stk[(sp + 1) * step] = nd.a;
-      sp += 2;
     }
+    if (sp == 0) break;
+    --sp;
+    cur = stk[sp * step];
   }
 }
 
-// Closest surface along o + t d with t > kTMin among the planes, the spheres
-// and, when `with_array` and the ray moves up, the array face z = 0.
+// Closest surface along o + t d with kTMin < t < tmax among the planes, the
+// spheres, the meshes and, when `with_array` and the ray moves up, the array
+// face z = 0.
 __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool with_array,
-                                           int* stk) {
+                                           int* stk, double tmax = INFINITY) {
   Hit h{kHitNone, -1, 0.0};
-  double best = INFINITY;
+  double best = tmax;
   if (d.z != 0.0) {
     const double inv = 1.0 / d.z;
     for (int k = 0; k < s.n_planes; ++k) {
@@ -111,11 +134,10 @@ __device__ __forceinline__ int max_legs(const SceneLDS& s) {
   return s.n_planes + 2 * s.n_spheres + kMeshLegs * s.n_meshes + 1;
 }
 
-// Unit face normal of leaf-order triangle i, from the current vertices.
+// Unit face normal of leaf-order triangle i, from the current geometry.
 __device__ __forceinline__ d3 tri_normal(const SceneLDS& s, int i) {
-  const int4 tv = s.tri[i];
-  const d3 p0 = vtx(s.vcur, tv.x);
-  const d3 nu = cross(vtx(s.vcur, tv.y) - p0, vtx(s.vcur, tv.z) - p0);
+  const TriRec& r = s.trec[i];
+  const d3 nu = cross(d3{r.e1[0], r.e1[1], r.e1[2]}, d3{r.e2[0], r.e2[1], r.e2[2]});
   return nu * (1.0 / sqrt(dot(nu, nu)));
 }
 

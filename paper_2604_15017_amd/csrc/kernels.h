@@ -75,10 +75,11 @@ struct MeshHierarchy {
   std::vector<BvhNode> nodes;
   std::vector<int4> tri;
   std::vector<int> tri_orig;
-  std::vector<int> level_begin;   // nodes of depth l: [level_begin[l], level_begin[l + 1])
-  int depth = 0;
+  std::vector<int> level_begin;   // inner nodes of depth l: [level_begin[l], level_begin[l + 1])
+  int depth = 0;                  // number of inner levels
 };
-// Returns 0, or -1 if the tree would exceed kMaxBvhDepth.
+// Returns 0, or -1 if the tree would exceed kMaxBvhDepth (or a leaf at that
+// depth would hold more than kLeafCap triangles).
 int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
                    const int32_t* tmesh, long n_tri, MeshHierarchy& out);
 
@@ -91,6 +92,7 @@ struct MeshDevice {
   const double* vbasis = nullptr;
   const int* vmesh = nullptr;
   double* vcur = nullptr;
+  TriRec* trec = nullptr;
   BvhNode* nodes = nullptr;
   const int4* tri = nullptr;
   std::vector<int> level_begin;

@@ -50,9 +50,15 @@ struct Builder {
   // Split [first, first + count) at the best binned SAH plane; returns the
   // size of the left part (0 = make a leaf). *halve is set when no plane
   // separates the triangles and the range must be halved by the caller.
+  bool too_deep = false;   // a leaf at the depth limit would exceed kLeafCap
+
   int split(int first, int count, const Box& bounds, int depth, bool* halve) {
     *halve = false;
-    if (count <= kLeafMax || depth >= kMaxBvhDepth) return 0;
+    if (count <= kLeafMax) return 0;
+    if (depth >= kMaxBvhDepth) {
+      too_deep |= count > kLeafCap;
+      return 0;
+    }
     Box cb;
     for (int i = first; i < first + count; ++i) cb.add(&cen[3 * (size_t)perm[i]]);
     int axis = 0;
@@ -96,7 +102,7 @@ struct Builder {
     if (best_b < 0) { *halve = true; return count / 2; }
     // cost model: one box test costs about one triangle test
     const double leaf_cost = bounds.area() * count;
-    if (count <= 16 && best + bounds.area() >= leaf_cost) return 0;
+    if (count <= kLeafCap && best + bounds.area() >= leaf_cost) return 0;
     int* mid = std::partition(p, p + count, [&](int t) { return bin_of(t) < best_b; });
     const int nl = (int)(mid - p);
     if (nl == 0 || nl == count) { *halve = true; return count / 2; }
@@ -154,34 +160,48 @@ int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
   }
   b.nodes.reserve(2 * (size_t)n_tri / kLeafMax + 16);
   b.build(0, (int)n_tri, 0);
-  if (b.max_depth_seen > kMaxBvhDepth) return -1;
+  if (b.max_depth_seen > kMaxBvhDepth || b.too_deep) return -1;
 
-  // breadth-first renumbering; every depth becomes a contiguous range
-  const int n = (int)b.nodes.size();
-  std::vector<int> order;
-  order.reserve(n);
-  order.push_back(0);
-  std::vector<int> newid(n, -1);
-  out.level_begin.assign(1, 0);
-  for (size_t head = 0; head < order.size(); ++head) {
-    const int i = order[head];
-    newid[i] = (int)head;
-    if (b.nodes[i].left >= 0) {
-      order.push_back(b.nodes[i].left);
-      order.push_back(b.nodes[i].right);
-    }
+  // inner nodes in breadth-first order, so that every depth is a contiguous
+  // range; leaves become references held by their parents
+  std::vector<TmpNode>& T = b.nodes;
+  std::vector<int> order;   // temporary ids of the inner nodes, breadth first
+  if (T[0].left < 0) {      // a single leaf: wrap it in a root with an empty sibling
+    TmpNode empty;
+    empty.first = 0; empty.count = 0; empty.depth = 1;
+    T[0].depth = 1;
+    TmpNode root;
+    root.left = 0; root.right = (int)T.size() + 1; root.depth = 0;
+    T.push_back(root);
+    T.push_back(empty);
+    order.push_back((int)T.size() - 2);
+  } else {
+    order.push_back(0);
   }
+  std::vector<int> newid(T.size(), -1);
+  for (size_t head = 0; head < order.size(); ++head) {
+    const TmpNode& t = T[order[head]];
+    newid[order[head]] = (int)head;
+    if (T[t.left].left >= 0) order.push_back(t.left);
+    if (T[t.right].left >= 0) order.push_back(t.right);
+  }
+  const int n = (int)order.size();
+  out.level_begin.assign(1, 0);
   for (int i = 1; i < n; ++i)
-    if (b.nodes[order[i]].depth != b.nodes[order[i - 1]].depth) out.level_begin.push_back(i);
+    if (T[order[i]].depth != T[order[i - 1]].depth) out.level_begin.push_back(i);
   out.level_begin.push_back(n);
   out.nodes.resize(n);
   for (int k = 0; k < n; ++k) {
-    const TmpNode& t = b.nodes[order[k]];
+    const TmpNode& t = T[order[k]];
     BvhNode& nd = out.nodes[k];
-    for (int j = 0; j < 3; ++j) { nd.lo[j] = 0.0f; nd.hi[j] = 0.0f; }
-    if (t.left >= 0) { nd.a = newid[t.left]; nd.b = newid[t.right]; }
-    else { nd.a = t.first; nd.b = -t.count; }
+    for (int j = 0; j < 3; ++j) { nd.lo_l[j] = nd.hi_l[j] = nd.lo_r[j] = nd.hi_r[j] = 0.0f; }
+    nd.pad0 = nd.pad1 = 0;
+    const TmpNode& l = T[t.left];
+    const TmpNode& r = T[t.right];
+    nd.left = l.left >= 0 ? newid[t.left] : ~((l.first << 4) | l.count);
+    nd.right = r.left >= 0 ? newid[t.right] : ~((r.first << 4) | r.count);
   }
+  out.depth = (int)out.level_begin.size() - 1;   // inner levels = stack entries needed
   out.tri.resize(n_tri);
   out.tri_orig.resize(n_tri);
   for (long i = 0; i < n_tri; ++i) {
@@ -189,7 +209,6 @@ int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
     out.tri[i] = make_int4(tris[3 * (size_t)t], tris[3 * (size_t)t + 1], tris[3 * (size_t)t + 2], tmesh[t]);
     out.tri_orig[i] = t;
   }
-  out.depth = b.max_depth_seen;
   return 0;
 }
 
@@ -220,33 +239,58 @@ __device__ __forceinline__ float round_up(double x) {
   return (double)f < x ? nextafterf(f, INFINITY) : f;
 }
 
-// Boxes of the nodes [begin, end) of one depth: a leaf from its triangles'
-// current vertices (fp64, rounded outward to fp32), an inner node as the union
-// of its children, which belong to deeper levels and are already refitted.
+// Child boxes of the inner nodes [begin, end) of one depth: a leaf child's
+// from its triangles' current vertices (fp64, rounded outward to fp32), an
+// inner child's as the union of its own two boxes, which belong to a deeper
+// level and are already refitted.
+__device__ __forceinline__ void child_box(const BvhNode* nodes, int ref, const int4* tri,
+                                          const double* vcur, float* lo, float* hi) {
+  if (ref >= 0) {
+    const BvhNode c = nodes[ref];
+    for (int k = 0; k < 3; ++k) { lo[k] = fminf(c.lo_l[k], c.lo_r[k]); hi[k] = fmaxf(c.hi_l[k], c.hi_r[k]); }
+    return;
+  }
+  double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const int first = (~ref) >> 4, cnt = (~ref) & 15;
+  for (int t = first; t < first + cnt; ++t) {
+    const int4 tv = tri[t];
+    const int id[3] = {tv.x, tv.y, tv.z};
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        const double c = vcur[3 * (long)id[j] + k];
+        l[k] = fmin(l[k], c);
+        h[k] = fmax(h[k], c);
+      }
+  }
+  for (int k = 0; k < 3; ++k) { lo[k] = round_down(l[k]); hi[k] = round_up(h[k]); }
+}
+
 __global__ __launch_bounds__(256) void k_refit(BvhNode* __restrict__ nodes, int begin, int end,
                                                const int4* __restrict__ tri,
                                                const double* __restrict__ vcur) {
   const int i = begin + (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= end) return;
   BvhNode nd = nodes[i];
-  if (nd.b < 0) {
-    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int t = nd.a; t < nd.a - nd.b; ++t) {
-      const int4 tv = tri[t];
-      const int id[3] = {tv.x, tv.y, tv.z};
-      for (int j = 0; j < 3; ++j)
-        for (int k = 0; k < 3; ++k) {
-          const double c = vcur[3 * (long)id[j] + k];
-          lo[k] = fmin(lo[k], c);
-          hi[k] = fmax(hi[k], c);
-        }
-    }
-    for (int k = 0; k < 3; ++k) { nd.lo[k] = round_down(lo[k]); nd.hi[k] = round_up(hi[k]); }
-  } else {
-    const BvhNode l = nodes[nd.a], r = nodes[nd.b];
-    for (int k = 0; k < 3; ++k) { nd.lo[k] = fminf(l.lo[k], r.lo[k]); nd.hi[k] = fmaxf(l.hi[k], r.hi[k]); }
-  }
+  child_box(nodes, nd.left, tri, vcur, nd.lo_l, nd.hi_l);
+  child_box(nodes, nd.right, tri, vcur, nd.lo_r, nd.hi_r);
   nodes[i] = nd;
+}
+
+// Leaf-order triangle records from the current vertices.
+__global__ __launch_bounds__(256) void k_trec(long n_tri, const int4* __restrict__ tri,
+                                              const double* __restrict__ vcur, TriRec* __restrict__ rec) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tri) return;
+  const int4 tv = tri[i];
+  TriRec r;
+  for (int k = 0; k < 3; ++k) {
+    const double p0 = vcur[3 * (long)tv.x + k];
+    r.p0[k] = p0;
+    r.e1[k] = vcur[3 * (long)tv.y + k] - p0;
+    r.e2[k] = vcur[3 * (long)tv.z + k] - p0;
+  }
+  r.pad = 0.0;
+  rec[i] = r;
 }
 
 }  // namespace
@@ -255,6 +299,9 @@ void launch_mesh_refit(const MeshDevice& m, const double* q, hipStream_t s) {
   if (m.n_vertices > 0)
     hipLaunchKernelGGL(k_mesh_vertices, dim3((unsigned)((m.n_vertices + 255) / 256)), dim3(256), 0, s,
                        m.n_vertices, m.vrest, m.vnormal, m.vbasis, m.vmesh, m.n_basis, q, m.vcur);
+  if (m.n_triangles > 0)
+    hipLaunchKernelGGL(k_trec, dim3((unsigned)((m.n_triangles + 255) / 256)), dim3(256), 0, s,
+                       m.n_triangles, m.tri, m.vcur, m.trec);
   for (int lv = (int)m.level_begin.size() - 2; lv >= 0; --lv) {
     const int b = m.level_begin[lv], e = m.level_begin[lv + 1];
     hipLaunchKernelGGL(k_refit, dim3((unsigned)((e - b + 255) / 256)), dim3(256), 0, s, m.nodes, b, e,

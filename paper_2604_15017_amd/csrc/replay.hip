@@ -219,7 +219,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
     int reg = region;
     bool reached = false;
     for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false, C.stk);
+      const Hit h = closest_hit(S, p, we, false, C.stk, remaining);
       if (h.kind == kHitNone || h.t >= remaining) {
         tof += remaining / S.c[reg];
         rest *= exp(-(S.a[reg] * remaining));
@@ -252,7 +252,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
     double remaining = r, s_cum = 0.0;
     int reg = region;
     for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false, C.stk);
+      const Hit h = closest_hit(S, p, we, false, C.stk, remaining);
       if (h.kind == kHitNone || h.t >= remaining) {
         const double ell = remaining;   // = r - s_J
         C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
 
 void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s) {
   const size_t lds = (size_t)((a.n_params + 1) & ~1) * sizeof(double) +
-                     (a.scene.n_meshes > 0 ? (size_t)kBvhStack * 256 * sizeof(int) : 0);
+                     (a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0);
   hipLaunchKernelGGL(k_replay, dim3(blocks), dim3(256), lds, s, a);
 }
 

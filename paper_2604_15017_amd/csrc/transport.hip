@@ -42,7 +42,7 @@ __global__ __launch_bounds__(256) void k_bounce(TraceArgs a, int k) {
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
   __shared__ unsigned long long scan[8];
-  extern __shared__ int bvh_stack[];   // kBvhStack entries per thread when the scene has meshes
+  extern __shared__ int bvh_stack[];   // stack_cap entries per thread when the scene has meshes
   load_scene(S, a.scene);
   int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
     bool blocked = true;
     const int legs = max_legs(S);
     for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false, stk);
+      const Hit h = closest_hit(S, p, we, false, stk, remaining);
       ++n_seg;
       if (h.kind == kHitNone || h.t >= remaining) {
         tof += remaining / S.c[reg];
@@ -309,7 +309,7 @@ void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
 constexpr int kMaxBlocks = 2048;
 
 static size_t stack_bytes(const TraceArgs& a) {
-  return a.scene.n_meshes > 0 ? (size_t)kBvhStack * 256 * sizeof(int) : 0;
+  return a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0;
 }
 
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {

@@ -309,14 +309,14 @@ class ServingRequestSpec:
 def serving_requests(n: int = 512, seed: int = 4, generators=None, min_log2_rays: int = 14,
                      max_log2_rays: int = 24) -> List[ServingRequestSpec]:
     """Serving stream: scenes drawn 40/40/20 from the generators (default: the
-    two-layer, layered-phantom and a second layered-phantom draw), ray counts
+    two-layer, layered-phantom and mesh anatomy generators), ray counts
     2^U{min..max} per frame, grids from {128x256, 256x512, 512x1024}, 30 % of
     the requests ask for the gradient of the B-mode MSE against the image of a
     seeded +-5 % perturbation of their scene. Scene descriptions are shared
     between requests of the same draw, so a server keeps them resident."""
     rng = np.random.Generator(np.random.Philox(key=[seed, 5]))
     if generators is None:
-        base = [two_layer(), layered_phantom(seed=1), layered_phantom(seed=2)]
+        base = [two_layer(), layered_phantom(seed=1), anatomy_phantom()]
     else:
         base = generators
     weights = np.array([0.4, 0.4, 0.2])[:len(base)]
@@ -334,7 +334,9 @@ def serving_requests(n: int = 512, seed: int = 4, generators=None, min_log2_rays
         target = None
         if want_grad:
             if k not in targets:
-                if wl.scene.n_spheres:
+                if wl.scene.meshes:
+                    targets[k] = anatomy_phantom_target(wl, seed=seed + k)
+                elif wl.scene.n_spheres:
                     targets[k] = layered_phantom_target(wl, seed=seed + k)
                 else:   # perturb every region's (c, Z, alpha) and the plane depths
                     r2 = np.random.Generator(np.random.Philox(key=[seed + k, TARGET_STREAM_TAG]))
@@ -525,3 +527,18 @@ def anatomy_phantom(seed: int = 3, rays_per_elem: int = 4161, **mesh_kw) -> Work
     return Workload("anatomy_phantom", anatomy_scene(seed, **mesh_kw), probe, angles,
                     np.arange(21, dtype=np.uint32), grid, seed=0, rays_per_elem=rays_per_elem,
                     max_bounces=12)
+
+
+def anatomy_phantom_target(wl: Workload, seed: int = 3, dq: float = 0.3e-3) -> Scene:
+    """Target scene of the mesh workload: every region's (c, Z, alpha) times
+    (1 + 0.05 (2u - 1)) and every displacement coefficient moved by
+    dq (2u - 1) metres (u uniform from the target stream)."""
+    rng = np.random.Generator(np.random.Philox(key=[seed, TARGET_STREAM_TAG]))
+    sc = wl.scene
+    theta = sc.theta().copy()
+    nr = 3 * sc.n_regions
+    theta[:nr] *= 1.0 + 0.05 * (2.0 * rng.random(nr) - 1.0)
+    if sc.meshes:
+        q0 = sc.idx_mesh(0, 0)
+        theta[q0:] += dq * (2.0 * rng.random(theta.shape[0] - q0) - 1.0)
+    return sc.with_theta(theta)
