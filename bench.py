@@ -49,9 +49,13 @@ def kernel_bytes(name, wl, counts, n_px):
         "das_adjoint": 8 * row_samples + 8 * n_px,
         "bmode_vjp": 28 * n_px,
         "image_loss": 12 * n_px,
-        # the replay reads dL/dh at every deposit (two fp32 bins) and writes and
-        # reads one checkpoint per interaction
-        "replay": 8 * dep + 2 * (8 * 8 + 4) * inter,
+        # replay: the forward phase writes one 80-byte step record per primary
+        # segment and queues the diffuse interactions; the secondary phase
+        # reads a step record, dL/dh at its deposit and writes 72 bytes of
+        # adjoints; the reverse phase reads the step records and those adjoints
+        "replay_forward": 80 * seg_p + 8 * sec,
+        "replay_secondary": (80 + 8 + 72) * sec,
+        "replay_reverse": 80 * seg_p + 72 * sec + 8 * (dep - sec),
         "analytic": 12 * row_samples,
         "das": 8 * row_samples + 8 * n_px,
         "bmode": 20 * n_px,

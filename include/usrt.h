@@ -70,8 +70,9 @@ typedef struct us_probe_desc {
  * Lambertian lobe; start_region = region at the array face. Host arrays.
  *
  * Meshes (n_meshes = 0: none, and the mesh pointers may be NULL): the
- * vertices of all meshes are concatenated ([n_vertices][3] rest positions,
- * owning mesh vmesh[v]), and so are the triangles ([n_triangles][3] global
+ * vertices of all meshes are concatenated in mesh order ([n_vertices][3]
+ * rest positions, owning mesh vmesh[v], non-decreasing), and so are the
+ * triangles ([n_triangles][3] global
  * vertex ids, counter-clockwise seen from outside, owning mesh tmesh[t], all
  * three vertices of that mesh). Vertex v moves along its unit direction
  * vnormal[v] by sum_j q[vmesh[v]][j] vbasis[v][j]; faces are flat. At most

@@ -238,6 +238,8 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     }
     for (long v = 0; v < nv; ++v) {
       US_CHECK(d->vmesh[v] >= 0 && d->vmesh[v] < nm, "us_scene_upload: vmesh out of range");
+      US_CHECK(v == 0 || d->vmesh[v] >= d->vmesh[v - 1],
+               "us_scene_upload: vertices must be concatenated in mesh order");
       for (int k = 0; k < 3; ++k)
         US_CHECK(std::isfinite(d->vertices[3 * v + k]) && std::isfinite(d->vnormal[3 * v + k]),
                  "us_scene_upload: vertices and vnormal must be finite");
@@ -280,6 +282,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     double *vrest = nullptr, *vnormal = nullptr, *vbasis = nullptr;
     int* vmesh = nullptr;
     int4* tri = nullptr;
+    long* vbeg = nullptr;
     ok = hipMalloc(&vrest, 3 * nv * sizeof(double)) == hipSuccess &&
          hipMalloc(&vnormal, 3 * nv * sizeof(double)) == hipSuccess &&
          hipMalloc(&vbasis, (nv * nb + 1) * sizeof(double)) == hipSuccess &&
@@ -288,8 +291,10 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
          hipMalloc(&md.trec, nt * sizeof(TriRec)) == hipSuccess &&
          hipMalloc(&md.nodes, H.nodes.size() * sizeof(BvhNode)) == hipSuccess &&
          hipMalloc(&tri, nt * sizeof(int4)) == hipSuccess &&
-         hipMalloc(&s->tri_orig, nt * sizeof(int)) == hipSuccess;
+         hipMalloc(&s->tri_orig, nt * sizeof(int)) == hipSuccess &&
+         hipMalloc(&vbeg, (nm + 1) * sizeof(long)) == hipSuccess;
     md.vrest = vrest; md.vnormal = vnormal; md.vbasis = vbasis; md.vmesh = vmesh; md.tri = tri;
+    md.vbeg = vbeg;
   }
   if (!ok) {
     us_scene_destroy(s);
@@ -305,6 +310,10 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_HIP(hipMemcpy(md.nodes, H.nodes.data(), H.nodes.size() * sizeof(BvhNode), hipMemcpyHostToDevice));
     US_HIP(hipMemcpy((void*)md.tri, H.tri.data(), nt * sizeof(int4), hipMemcpyHostToDevice));
     US_HIP(hipMemcpy(s->tri_orig, H.tri_orig.data(), nt * sizeof(int), hipMemcpyHostToDevice));
+    std::vector<long> vb(nm + 1, nv);
+    for (long v = nv - 1; v >= 0; --v) vb[d->vmesh[v]] = v;
+    for (int m = nm - 1; m >= 0; --m) vb[m] = std::min(vb[m], vb[m + 1]);   // meshes without vertices
+    US_HIP(hipMemcpy((void*)md.vbeg, vb.data(), (nm + 1) * sizeof(long), hipMemcpyHostToDevice));
   }
   US_HIP(hipMemcpy(s->theta, d->theta, np * sizeof(double), hipMemcpyHostToDevice));
   if (d->n_planes) {
@@ -344,6 +353,7 @@ int us_scene_destroy(us_scene* s) {
   (void)hipFree(s->mesh.trec);
   (void)hipFree(s->mesh.nodes);
   (void)hipFree((void*)s->mesh.tri);
+  (void)hipFree((void*)s->mesh.vbeg);
   delete s;
   return US_OK;
 }
@@ -431,16 +441,31 @@ void carve_queues(Carver& c, long cap, RayQueue* q0, RayQueue* q1, SecondaryQueu
   nq->rid = c.take<uint32_t>(cap); nq->meta = c.take<uint32_t>(cap); nq->txk = c.take<uint32_t>(cap);
 }
 
-constexpr long kMaxReplayBlocks = 1024;
+// Rays per chunk of the replay backward when the caller sizes the workspace
+// with us_simulate_rf_vjp_workspace_size (about 160 bytes per ray and step).
+constexpr long kReplayChunk = 1L << 21;
 
-// Workspace of the replay backward: dL/dh plus one checkpoint per interaction
-// for every thread of the grid.
-size_t replay_bytes(int n_tx, const us_probe* p, int max_bounces, long blocks) {
-  Carver c{nullptr};
-  c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
-  const size_t n = (size_t)blocks * 256 * (max_bounces + 1);
-  for (int f = 0; f < 8; ++f) c.take<double>(n);
-  c.take<uint32_t>(n);
+// Workspace of the replay backward for chunks of `cap` rays: dL/dh, then the
+// per-ray steps, the secondary-ray adjoints and the queue of diffuse
+// interactions.
+size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_bounces, long cap,
+                    ReplayStack* k = nullptr, char* base = nullptr, float** gh = nullptr,
+                    double** vadj = nullptr) {
+  Carver c{base};
+  float* g = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
+  if (gh) *gh = g;
+  double* va = c.take<double>((size_t)scene->mesh.n_vertices + 1);
+  if (vadj) *vadj = va;
+  ReplayStack tmp;
+  ReplayStack& r = k ? *k : tmp;
+  const size_t n = (size_t)cap * (max_bounces + 1);
+  r.n = (long)n;
+  r.f = c.take<double>(n * kReplayFields);
+  r.meta = c.take<uint32_t>(n);
+  r.hidx = c.take<int>(n);
+  r.last = c.take<int>((size_t)cap);
+  r.queue = c.take<unsigned long long>((size_t)cap * (max_bounces > 0 ? max_bounces : 1));
+  r.queue_count = c.take<unsigned long long>(1);
   return c.off;
 }
 
@@ -721,9 +746,8 @@ size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* 
                                          int32_t n_tx, int64_t ray_count, int32_t max_bounces) {
   if (!scene || !probe || n_tx < 1 || ray_count < 0 || max_bounces < 0) return 0;
   const int group = n_tx < kMaxTxPerLaunch ? n_tx : kMaxTxPerLaunch;
-  long blocks = (long)(((int64_t)group * ray_count + 255) / 256);
-  blocks = std::max(1L, std::min(blocks, kMaxReplayBlocks));
-  return replay_bytes(n_tx, probe, max_bounces, blocks);
+  const long cap = std::max(1L, std::min((long)group * (long)ray_count, kReplayChunk));
+  return replay_bytes(scene, n_tx, probe, max_bounces, cap);
 }
 
 int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
@@ -734,23 +758,22 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   US_CHECK(ctx && g_rf_dev && g_theta_dev && ws_dev, "us_simulate_rf_vjp: NULL argument");
   int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
-  long blocks = 0;
-  while (blocks < kMaxReplayBlocks && replay_bytes(n_tx, probe, max_bounces, blocks + 1) <= ws_bytes)
-    ++blocks;
-  if (blocks < 1) return fail(US_ETOOBIG, "us_simulate_rf_vjp: workspace too small");
+  // largest chunk that fits the workspace
+  if (replay_bytes(scene, n_tx, probe, max_bounces, 1) > ws_bytes)
+    return fail(US_ETOOBIG, "us_simulate_rf_vjp: workspace too small");
+  long lo = 1, hi = kReplayChunk;
+  while (lo < hi) {
+    const long mid = lo + (hi - lo + 1) / 2;
+    if (replay_bytes(scene, n_tx, probe, max_bounces, mid) <= ws_bytes) lo = mid; else hi = mid - 1;
+  }
+  const long cap = lo;
   US_HIP(hipSetDevice(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const us_probe_desc& pd = probe->d;
-  const long cap = blocks * 256;
-  Carver c{(char*)ws_dev};
-  float* gh = c.take<float>((size_t)n_tx * pd.n_elem * pd.n_t);
   ReplayArgs a{};
-  ReplayStack& k = a.stk;
-  const size_t n = (size_t)cap * (max_bounces + 1);
-  k.ox = c.take<double>(n); k.oy = c.take<double>(n); k.oz = c.take<double>(n);
-  k.dx = c.take<double>(n); k.dy = c.take<double>(n); k.dz = c.take<double>(n);
-  k.t = c.take<double>(n); k.w = c.take<double>(n);
-  k.meta = c.take<uint32_t>(n);
+  float* gh = nullptr;
+  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &a.vadj);
+  if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2 * scene->mesh.n_vertices, 0u, s);
   {
     Timed tm(ctx, "pulse_adjoint", s);
     if (launch_pulse_adjoint(g_rf_dev, gh, probe->taps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
@@ -766,15 +789,34 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   a.n_params = scene->n_params;
   a.gh = gh;
   a.g_theta = g_theta_dev;
+  a.cap = cap;
   for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
     const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
     fill_tx(a.tx, tx, t0, ng);
     a.tx_base = t0;
-    a.g0 = 0;
-    a.n_chunk = (long)ng * ray_count;
-    const int nb = (int)std::min<long>(blocks, (a.n_chunk + 255) / 256);
-    Timed tm(ctx, "replay", s);
-    launch_replay(a, nb, s);
+    const long n_group = (long)ng * ray_count;
+    for (long g0 = 0; g0 < n_group; g0 += cap) {
+      const long n = std::min(cap, n_group - g0);
+      a.g0 = g0;
+      launch_fill_u32((uint32_t*)a.stk.queue_count, 2, 0u, s);
+      {
+        Timed tm(ctx, "replay_forward", s);
+        launch_replay_forward(a, n, s);
+      }
+      {
+        Timed tm(ctx, "replay_secondary", s);
+        launch_replay_secondary(a, n * std::max(1, max_bounces), s);
+      }
+      {
+        Timed tm(ctx, "replay_reverse", s);
+        launch_replay_reverse(a, n, s);
+      }
+    }
+  }
+  if (scene->n_meshes > 0) {
+    Timed tm(ctx, "basis_gather", s);
+    launch_basis_gather(a.vadj, scene->mesh.vbasis, scene->mesh.vbeg, scene->n_meshes, scene->n_basis,
+                        g_theta_dev + scene->q_offset, s);
   }
   US_HIP(hipGetLastError());
   return US_OK;

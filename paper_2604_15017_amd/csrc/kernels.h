@@ -45,12 +45,25 @@ struct TraceArgs {
 };
 
 // Per-thread checkpoint stack of the replay: field[step * capacity + slot].
-struct ReplayStack {
-  double *ox, *oy, *oz, *dx, *dy, *dz, *t, *w;
-  uint32_t* meta;   // region | last event not diffuse << 8
+// Per-ray replay state of one chunk of rays: fp64 field F of step k of chunk
+// ray i at f[F * n + (k - 1) * cap + i] (coalesced across rays), n = cap *
+// (max_bounces + 1).
+enum ReplayField : int {
+  kFOx, kFOy, kFOz, kFDx, kFDy, kFDz, kFT, kFW,   // state before step k
+  kFL,                                           // distance to the surface step k hits
+  // adjoints of the inputs of the secondary ray of interaction k: x, n_r, A_r, w_att, t'
+  kFXb, kFYb, kFZb, kFNxb, kFNyb, kFNzb, kFAb, kFWb, kFTb,
+  kReplayFields
 };
-constexpr size_t kReplayBytesPerStep = 8 * sizeof(double) + sizeof(uint32_t);
-
+struct ReplayStack {
+  double* f;
+  long n;
+  uint32_t* meta;                                // region | delta << 8 | hit kind << 12
+  int* hidx;                                     // hit index (leaf-order triangle for meshes)
+  int* last;                                     // [cap] last step that can carry a deposit
+  unsigned long long* queue;                     // (k << 32) | i of the diffuse interactions
+  unsigned long long* queue_count;
+};
 struct ReplayArgs {
   SceneView scene;
   ProbeView probe;
@@ -59,15 +72,23 @@ struct ReplayArgs {
   int rays_per_elem;
   int max_bounces;
   long ray_begin, ray_count;
-  long g0, n_chunk;
+  long g0;                // first ray of the chunk within the transmit group
+  long cap;               // chunk capacity (rays)
   int tx_base;
   int n_params;
   const float* gh;        // dL/dh [n_tx][n_elem][n_t]
   double* g_theta;        // accumulated
+  double* vadj;           // [n_vertices] mesh vertex adjoints along vnormal (zeroed per call)
   ReplayStack stk;
 };
-
-void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s);
+// The three phases of the replay over chunk rays [0, n); the queue count must
+// be zero before the forward phase.
+void launch_replay_forward(const ReplayArgs& a, long n, hipStream_t s);
+void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s);
+void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
+// g_q[m * n_basis + j] += sum_{v in mesh m} vadj[v] vbasis[v][j].
+void launch_basis_gather(const double* vadj, const double* vbasis, const long* vbeg, int n_meshes,
+                         int n_basis, double* g_q, hipStream_t s);
 
 // ---------------------------------------------------------------- meshes
 // Hierarchy as built on the host (breadth-first nodes, leaf-order triangles).
@@ -95,6 +116,7 @@ struct MeshDevice {
   TriRec* trec = nullptr;
   BvhNode* nodes = nullptr;
   const int4* tri = nullptr;
+  const long* vbeg = nullptr;     // [n_meshes + 1] vertex range of each mesh
   std::vector<int> level_begin;
 };
 // Current vertices from the displacement coefficients q (device,

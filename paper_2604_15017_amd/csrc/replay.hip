@@ -25,17 +25,15 @@ struct GradAcc {
   double* g;
   int n_regions, n_planes;
   double np_per_m;
-  int q_offset, n_basis;          // mesh displacement coefficients in theta
   const double* vnormal;
-  const double* vbasis;
-  // adjoint vbar of mesh vertex v (mesh m): v = v_rest + sum_j q_j phi_j n
+  double* vadj;                   // per-vertex adjoint along the displacement direction (HBM)
+  // adjoint vbar of mesh vertex v: v = v_rest + (sum_j q_j phi_j(v)) n(v), so
+  // the vertex contributes (vbar . n(v)) phi_j(v) to q_j; the scalar is summed
+  // per vertex here and projected onto the basis once per call
   __device__ void mesh_vertex(int v, int m, d3 vbar) {
+    (void)m;
     const double s = vbar.x * vnormal[3 * v] + vbar.y * vnormal[3 * v + 1] + vbar.z * vnormal[3 * v + 2];
-    if (s == 0.0) return;
-    double* q = g + q_offset + m * n_basis;
-    const double* phi = vbasis + (long)v * n_basis;
-    for (int j = 0; j < n_basis; ++j)
-      if (phi[j] != 0.0) atomicAdd(q + j, s * phi[j]);
+    if (s != 0.0) unsafeAtomicAdd(vadj + v, s);
   }
   __device__ void c(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r], v); }
   __device__ void Z(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 1], v); }
@@ -182,6 +180,11 @@ __device__ __forceinline__ double interface_backward(const Coef& f, double eta, 
   return cibar;
 }
 
+// Crossings of a receiver segment remembered between the two passes of its
+// adjoint (in LDS, interleaved across the block's threads); further
+// crossings are found again.
+constexpr int kLegCache = 8;
+
 struct ReplayCtx {
   const SceneLDS& S;
   const ProbeView& P;
@@ -189,6 +192,8 @@ struct ReplayCtx {
   long row_base;        // (tx_base + txl) * n_elem
   GradAcc& G;
   int* stk;             // this thread's hierarchy stack in LDS
+  double* leg_t;        // this thread's crossing cache in LDS: distance ...
+  int* leg_h;           // ... and kind << 28 | index
 };
 
 // Secondary ray of interaction k at x (weight watt, time tp, interface f):
@@ -213,11 +218,13 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   // pass 1: the march as the forward did it
   const int legs = max_legs(S);
   double tof = tp, rest = 1.0;
+  int n_cross = 0;
   {
     d3 p = x;
     double remaining = r;
     int reg = region;
     bool reached = false;
+    const int step = blockDim.x;
     for (int leg = 0; leg < legs; ++leg) {
       const Hit h = closest_hit(S, p, we, false, C.stk, remaining);
       if (h.kind == kHitNone || h.t >= remaining) {
@@ -226,6 +233,11 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
         reached = true;
         break;
       }
+      if (leg < kLegCache) {
+        C.leg_t[leg * step] = h.t;
+        C.leg_h[leg * step] = (h.kind << 28) | h.index;
+      }
+      ++n_cross;
       tof += h.t / S.c[reg];
       rest *= exp(-(S.a[reg] * h.t));
       remaining -= h.t;
@@ -251,8 +263,20 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
     d3 p = x;
     double remaining = r, s_cum = 0.0;
     int reg = region;
+    const int step = blockDim.x;
     for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false, C.stk, remaining);
+      // the crossings of pass 1 in order, then the final stretch to the element
+      Hit h;
+      if (leg < kLegCache) {
+        if (leg < n_cross) {
+          const int id = C.leg_h[leg * step];
+          h = Hit{id >> 28, id & 0x0FFFFFFF, C.leg_t[leg * step]};
+        } else {
+          h = Hit{kHitNone, -1, 0.0};
+        }
+      } else {
+        h = closest_hit(S, p, we, false, C.stk, remaining);
+      }
       if (h.kind == kHitNone || h.t >= remaining) {
         const double ell = remaining;   // = r - s_J
         C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
@@ -309,37 +333,77 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   xbar = xbar + xb - dvbar;
 }
 
+// Appends one entry per active lane whose `want` is set, with one atomic per
+// wave; usable in divergent code (only the active lanes take part).
+__device__ __forceinline__ long wave_append(bool want, unsigned long long* count) {
+  const unsigned long long m = __ballot(want);
+  if (!want) return -1;
+  const int leader = __ffsll((long long)m) - 1;
+  const unsigned below =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  unsigned long long base = 0;
+  if (below == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+  return (long)((((unsigned long long)hi << 32) | lo) + below);
+}
+
+// Ray of chunk slot i: transmit (local index) and ray id.
+__device__ __forceinline__ void ray_of(const ReplayArgs& a, long i, int* txl, uint32_t* rid) {
+  const long g = a.g0 + i;
+  *txl = (int)(g / a.ray_count);
+  *rid = (uint32_t)(a.ray_begin + g % a.ray_count);
+}
+
+// State after the interaction at x, given the draw v (same decisions as the
+// forward); returns false when the path ends.
+struct Step {
+  Hit h;
+  Surface sf;
+  Coef f;
+  double L, E, tp, watt;
+  d3 x;
+};
+
+__device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t, double w, int region,
+                                        const Hit& h) {
+  Step st;
+  st.h = h;
+  st.L = h.t;
+  st.E = exp(-(S.a[region] * h.t));
+  st.tp = t + h.t / S.c[region];
+  st.watt = w * st.E;
+  st.x = o + d * h.t;
+  if (h.kind != kHitArray && h.kind != kHitNone) {
+    st.sf = surface_of(S, h, st.x, region);
+    st.f = coefficients(d, st.sf.n, S.c[region], S.Z[region], S.c[st.sf.other], S.Z[st.sf.other]);
+  }
+  return st;
+}
+
 }  // namespace
 
-// One thread per ray: forward replay with checkpoints, then the reverse sweep.
-__global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
-  if ((long)blockIdx.x * blockDim.x >= a.n_chunk) return;
+// Phase 1 (one thread per ray of the chunk): the forward path again, keeping
+// the state before every step and the surface it hits; every interaction on
+// a diffuse surface is queued for phase 2.
+__global__ __launch_bounds__(256) void k_replay_forward(ReplayArgs a, long n) {
+  if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
-  extern __shared__ double gsh[];      // n_params gradient sums, then the hierarchy stacks
+  extern __shared__ int bvh_stack[];
   load_scene(S, a.scene);
-  for (int i = threadIdx.x; i < a.n_params; i += blockDim.x) gsh[i] = 0.0;
-  __syncthreads();
-  int* stk = (int*)(gsh + ((a.n_params + 1) & ~1)) + threadIdx.x;
-  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m,
-            3 * a.scene.n_regions + a.scene.n_planes + 4 * a.scene.n_spheres, a.scene.n_basis,
-            a.scene.vnormal, a.scene.vbasis};
+  int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
-  const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long cap = (long)gridDim.x * blockDim.x;
   const int B = a.max_bounces;
-
-  for (long i = slot; i < a.n_chunk; i += cap) {
-    const long g = a.g0 + i;
-    const int txl = (int)(g / a.ray_count);
-    const uint32_t rid = (uint32_t)(a.ray_begin + g % a.ray_count);
+  const long cap = a.cap;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    int txl;
+    uint32_t rid;
+    ray_of(a, i, &txl, &rid);
     const uint32_t tx_id = a.tx.id[txl];
-    ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk};
-
-    // ---- forward replay, checkpointing the state before each step
     d3 o, d;
     double t, w;
-    int region;
-    bool delta;
+    int region = S.start_region;
+    bool delta = true;
     {
       const int e = (int)(rid / (uint32_t)a.rays_per_elem);
       const Draw u = draw(a.seed, rid, tx_id, 0);
@@ -349,69 +413,141 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
       d = d3{sa, 0.0, ca};
       t = o.x * (sa / P.c_ref);
       w = fmax(0.0, ca) / (double)a.rays_per_elem;
-      region = S.start_region;
-      delta = true;
     }
-    int last = 0;   // last step that can carry a deposit
+    int last = 0;
     for (int k = 1; k <= B + 1; ++k) {
-      const long at = (long)(k - 1) * cap + slot;
-      a.stk.ox[at] = o.x; a.stk.oy[at] = o.y; a.stk.oz[at] = o.z;
-      a.stk.dx[at] = d.x; a.stk.dy[at] = d.y; a.stk.dz[at] = d.z;
-      a.stk.t[at] = t; a.stk.w[at] = w;
-      a.stk.meta[at] = (uint32_t)region | ((uint32_t)delta << 8);
+      const long at = (long)(k - 1) * cap + i;
       const Hit h = closest_hit(S, o, d, true, stk);
+      double* F = a.stk.f + at;
+      const long fs = a.stk.n;
+      F[kFOx * fs] = o.x; F[kFOy * fs] = o.y; F[kFOz * fs] = o.z;
+      F[kFDx * fs] = d.x; F[kFDy * fs] = d.y; F[kFDz * fs] = d.z;
+      F[kFT * fs] = t; F[kFW * fs] = w; F[kFL * fs] = h.t;
+      a.stk.meta[at] = (uint32_t)region | ((uint32_t)delta << 8) | ((uint32_t)h.kind << 12);
+      a.stk.hidx[at] = h.index;
       if (h.kind == kHitNone) break;
       if (h.kind == kHitArray) { last = k; break; }
       if (k > B) break;
-      t += h.t / S.c[region];
-      w *= exp(-(S.a[region] * h.t));
-      const d3 x = o + d * h.t;
-      const Surface sf = surface_of(S, h, x, region);
-      const Coef f = coefficients(d, sf.n, S.c[region], S.Z[region], S.c[sf.other], S.Z[sf.other]);
+      const Step st = step_at(S, o, d, t, w, region, h);
+      t = st.tp;
+      w = st.watt;
       const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
-      const double p_spec = (1.0 - sf.kd) * f.RE;
+      const double p_spec = (1.0 - st.sf.kd) * st.f.RE;
       if (v.u0 < p_spec) {
-        d = d + f.nr * (2.0 * f.ci);
-        w *= f.Ar / f.RE;
+        d = d + st.f.nr * (2.0 * st.f.ci);
+        w *= st.f.Ar / st.f.RE;
         delta = true;
-      } else if (v.u0 < f.RE) {
-        const d3 n = f.nr;
-        const double sg = n.z >= 0.0 ? 1.0 : -1.0;
-        const double aa = -1.0 / (sg + n.z);
-        const double bb = n.x * n.y * aa;
-        const d3 b1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
-        const d3 b2{bb, sg + n.y * n.y * aa, -n.y};
+      } else if (v.u0 < st.f.RE) {
+        const d3 nn = st.f.nr;
+        const double sg = nn.z >= 0.0 ? 1.0 : -1.0;
+        const double aa = -1.0 / (sg + nn.z);
+        const double bb = nn.x * nn.y * aa;
+        const d3 b1{1.0 + sg * nn.x * nn.x * aa, sg * bb, -sg * nn.x};
+        const d3 b2{bb, sg + nn.y * nn.y * aa, -nn.y};
         const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
-        d = b1 * (rr * cos(phi)) + b2 * (rr * sin(phi)) + n * sqrt(1.0 - v.u2);
-        w *= f.Ar / f.RE;
+        d = b1 * (rr * cos(phi)) + b2 * (rr * sin(phi)) + nn * sqrt(1.0 - v.u2);
+        w *= st.f.Ar / st.f.RE;
         delta = false;
       } else {
-        const double eta = S.c[sf.other] / S.c[region];
-        d = d * eta + f.nr * (eta * f.ci - f.ct);
-        w *= f.At / (1.0 - f.RE);
-        region = sf.other;
+        const double eta = S.c[st.sf.other] / S.c[region];
+        d = d * eta + st.f.nr * (eta * st.f.ci - st.f.ct);
+        w *= st.f.At / (1.0 - st.f.RE);
+        region = st.sf.other;
         delta = true;
       }
-      o = x;
+      const long q = wave_append(st.sf.kd > 0.0, a.stk.queue_count);
+      if (q >= 0) a.stk.queue[q] = ((unsigned long long)k << 32) | (unsigned long long)i;
+      o = st.x;
       last = k;
     }
+    a.stk.last[i] = last;
+  }
+}
 
-    // ---- reverse sweep
+// Phase 2 (one thread per queued interaction): the secondary ray towards
+// the element the interaction picked, with its parameter adjoints, and the
+// adjoints of its inputs (x, n_r, A_r, w_att, t') kept for phase 3.
+__global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
+  const long n_q = (long)*a.stk.queue_count;
+  if ((long)blockIdx.x * blockDim.x >= n_q) return;
+  __shared__ SceneLDS S;
+  extern __shared__ double gsh[];      // n_params gradient sums, then the hierarchy stacks
+  load_scene(S, a.scene);
+  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x) gsh[j] = 0.0;
+  __syncthreads();
+  double* leg_t = gsh + ((a.n_params + 1) & ~1) + threadIdx.x;
+  int* leg_h = (int*)(gsh + ((a.n_params + 1) & ~1) + kLegCache * blockDim.x) + threadIdx.x;
+  int* stk = leg_h + kLegCache * blockDim.x;
+  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+  const ProbeView& P = a.probe;
+  const long cap = a.cap;
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
+    const unsigned long long e = a.stk.queue[q];
+    const long i = (long)(e & 0xFFFFFFFFull);
+    const int k = (int)(e >> 32);
+    int txl;
+    uint32_t rid;
+    ray_of(a, i, &txl, &rid);
+    const long at = (long)(k - 1) * cap + i;
+    double* F = a.stk.f + at;
+    const long fs = a.stk.n;
+    const d3 o{F[kFOx * fs], F[kFOy * fs], F[kFOz * fs]};
+    const d3 d{F[kFDx * fs], F[kFDy * fs], F[kFDz * fs]};
+    const uint32_t meta = a.stk.meta[at];
+    const int reg = meta & 0xFF;
+    const Hit h{(int)(meta >> 12), a.stk.hidx[at], F[kFL * fs]};
+    const Step st = step_at(S, o, d, F[kFT * fs], F[kFW * fs], reg, h);
+    const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
+    const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
+    ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
+    d3 xb{0, 0, 0}, nrb{0, 0, 0};
+    double Ab = 0.0, wb = 0.0, tb = 0.0;
+    secondary_backward(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb);
+    F[kFXb * fs] = xb.x; F[kFYb * fs] = xb.y; F[kFZb * fs] = xb.z;
+    F[kFNxb * fs] = nrb.x; F[kFNyb * fs] = nrb.y; F[kFNzb * fs] = nrb.z;
+    F[kFAb * fs] = Ab; F[kFWb * fs] = wb; F[kFTb * fs] = tb;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x)
+    if (gsh[j] != 0.0) atomicAdd(&a.g_theta[j], gsh[j]);
+}
+
+// Phase 3 (one thread per ray): the reverse sweep over the kept steps, with
+// the secondary-ray adjoints of phase 2 added at their interactions; no
+// intersection queries.
+__global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
+  if ((long)blockIdx.x * blockDim.x >= n) return;
+  __shared__ SceneLDS S;
+  extern __shared__ double gsh[];
+  load_scene(S, a.scene);
+  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x) gsh[j] = 0.0;
+  __syncthreads();
+  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+  const ProbeView& P = a.probe;
+  const long cap = a.cap;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    int txl;
+    uint32_t rid;
+    ray_of(a, i, &txl, &rid);
+    const uint32_t tx_id = a.tx.id[txl];
+    const long row_base = (long)(a.tx_base + txl) * P.n_elem;
     d3 ob{0, 0, 0}, db{0, 0, 0};
     double tb = 0.0, wb = 0.0;
-    for (int k = last; k >= 1; --k) {
-      const long at = (long)(k - 1) * cap + slot;
-      const d3 o0{a.stk.ox[at], a.stk.oy[at], a.stk.oz[at]};
-      const d3 d0{a.stk.dx[at], a.stk.dy[at], a.stk.dz[at]};
-      const double t0 = a.stk.t[at], w0 = a.stk.w[at];
+    for (int k = a.stk.last[i]; k >= 1; --k) {
+      const long at = (long)(k - 1) * cap + i;
+      const double* F = a.stk.f + at;
+      const long fs = a.stk.n;
+      const d3 o0{F[kFOx * fs], F[kFOy * fs], F[kFOz * fs]};
+      const d3 d0{F[kFDx * fs], F[kFDy * fs], F[kFDz * fs]};
+      const double t0 = F[kFT * fs], w0 = F[kFW * fs];
       const uint32_t meta = a.stk.meta[at];
       const int reg = meta & 0xFF;
       const bool dl = (meta >> 8) & 1u;
-      const Hit h = closest_hit(S, o0, d0, true, stk);
-      const double L = h.t, c1 = S.c[reg], ar = S.a[reg];
-      const double E = exp(-(ar * L));
-      const double tp = t0 + L / c1, watt = w0 * E;
-      const d3 x = o0 + d0 * L;
+      const Hit h{(int)(meta >> 12), a.stk.hidx[at], F[kFL * fs]};
+      const Step st = step_at(S, o0, d0, t0, w0, reg, h);
+      const double L = st.L, c1 = S.c[reg], ar = S.a[reg];
+      const double watt = st.watt;
+      const d3 x = st.x;
       d3 xb{0, 0, 0}, d0b{0, 0, 0};
       double tpb = 0.0, wattb = 0.0;
       if (h.kind == kHitArray) {
@@ -422,16 +558,16 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
           const double fd = rx_directivity(P, -d0.z);
           if (fd > 0.0) {
             double ga, gt;
-            tent_adjoint(a.gh + (C.row_base + e) * (long)P.n_t, P.n_t, P.fs, tp, watt * fd, &ga, &gt);
+            tent_adjoint(a.gh + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, watt * fd, &ga, &gt);
             wattb += ga * fd;
             d0b.z -= ga * watt * rx_directivity_deriv(P, -d0.z);
             tpb += gt;
           }
         }
       } else {
-        const Surface sf = surface_of(S, h, x, reg);
+        const Surface sf = st.sf;
+        const Coef f = st.f;
         const int r2 = sf.other;
-        const Coef f = coefficients(d0, sf.n, c1, S.Z[reg], S.c[r2], S.Z[r2]);
         const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
         const double eta = S.c[r2] / c1;
         xb = ob;
@@ -446,19 +582,19 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
           wattb += wb * f.Ar / f.RE;
           Ab += wb * watt / f.RE;
         } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
-          const d3 n = f.nr;
-          const double sg = n.z >= 0.0 ? 1.0 : -1.0;
-          const double aa = -1.0 / (sg + n.z);
+          const d3 nn = f.nr;
+          const double sg = nn.z >= 0.0 ? 1.0 : -1.0;
+          const double aa = -1.0 / (sg + nn.z);
           const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
           const double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(1.0 - v.u2);
           const double a2 = aa * aa;
           // Jacobian of d' with respect to (nx, ny, nz), applied transposed to db
-          const double j_xx = lx * 2.0 * sg * n.x * aa + ly * n.y * aa + lz;
-          const double j_xy = ly * n.x * aa;
-          const double j_xz = lx * sg * n.x * n.x * a2 + ly * n.x * n.y * a2;
-          const double j_yx = lx * sg * n.y * aa;
-          const double j_yy = lx * sg * n.x * aa + ly * 2.0 * n.y * aa + lz;
-          const double j_yz = lx * sg * n.x * n.y * a2 + ly * n.y * n.y * a2;
+          const double j_xx = lx * 2.0 * sg * nn.x * aa + ly * nn.y * aa + lz;
+          const double j_xy = ly * nn.x * aa;
+          const double j_xz = lx * sg * nn.x * nn.x * a2 + ly * nn.x * nn.y * a2;
+          const double j_yx = lx * sg * nn.y * aa;
+          const double j_yy = lx * sg * nn.x * aa + ly * 2.0 * nn.y * aa + lz;
+          const double j_yz = lx * sg * nn.x * nn.y * a2 + ly * nn.y * nn.y * a2;
           const double j_zx = -lx * sg, j_zy = -ly, j_zz = lz;
           nrb.x += db.x * j_xx + db.y * j_yx + db.z * j_zx;
           nrb.y += db.x * j_xy + db.y * j_yy + db.z * j_zy;
@@ -475,9 +611,12 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
           wattb += wb * f.At / (1.0 - f.RE);
           Ab += wb * watt / (1.0 - f.RE);
         }
-        if (sf.kd > 0.0) {
-          const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
-          secondary_backward(C, reg, x, f, sf.kd, watt, tp, e2, xb, nrb, Ab, wattb, tpb);
+        if (sf.kd > 0.0) {   // adjoints of the secondary ray's inputs (phase 2)
+          xb = xb + d3{F[kFXb * fs], F[kFYb * fs], F[kFZb * fs]};
+          nrb = nrb + d3{F[kFNxb * fs], F[kFNyb * fs], F[kFNzb * fs]};
+          Ab += F[kFAb * fs];
+          wattb += F[kFWb * fs];
+          tpb += F[kFTb * fs];
         }
         cib += interface_backward(f, eta, reg, r2, S.Z[reg], S.Z[r2], c1, Ab, ctb, etab, G);
         // ci = -nr . d
@@ -487,7 +626,7 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
         normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, xb, G);
       }
       // t' = t + L / c, w_att = w exp(-a L), x = o + d L, L = distance(o, d)
-      double Lb = tpb / c1 - wattb * watt * ar + dot(xb, d0);
+      const double Lb = tpb / c1 - wattb * watt * ar + dot(xb, d0);
       G.c(reg, -tpb * L / (c1 * c1));
       G.a(reg, -wattb * watt * L);
       d3 o0b = xb;
@@ -497,18 +636,65 @@ __global__ __launch_bounds__(256) void k_replay(ReplayArgs a) {
       ob = o0b;
       db = d0b;
       tb = tpb;
-      wb = wattb * E;
+      wb = wattb * st.E;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < a.n_params; i += blockDim.x)
-    if (gsh[i] != 0.0) atomicAdd(&a.g_theta[i], gsh[i]);
+  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x)
+    if (gsh[j] != 0.0) atomicAdd(&a.g_theta[j], gsh[j]);
 }
 
-void launch_replay(const ReplayArgs& a, int blocks, hipStream_t s) {
-  const size_t lds = (size_t)((a.n_params + 1) & ~1) * sizeof(double) +
-                     (a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0);
-  hipLaunchKernelGGL(k_replay, dim3(blocks), dim3(256), lds, s, a);
+// g_theta[q(m, j)] += sum over the vertices v of mesh m of vadj[v] phi_j(v):
+// one block per (mesh, basis function), vertices of mesh m in [vbeg[m], vbeg[m + 1]).
+__global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__ vadj,
+                                                      const double* __restrict__ vbasis,
+                                                      const long* __restrict__ vbeg, int n_basis,
+                                                      double* __restrict__ g_q) {
+  const int m = blockIdx.x / n_basis, j = blockIdx.x % n_basis;
+  double acc = 0.0;
+  for (long v = vbeg[m] + threadIdx.x; v < vbeg[m + 1]; v += blockDim.x)
+    acc += vadj[v] * vbasis[v * n_basis + j];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(g_q + blockIdx.x, red[0]);
+}
+
+namespace {
+constexpr int kMaxReplayGrid = 2048;
+unsigned replay_grid(long n) {
+  const long b = (n + 255) / 256;
+  return (unsigned)(b < 1 ? 1 : (b > kMaxReplayGrid ? kMaxReplayGrid : b));
+}
+size_t stack_lds(const ReplayArgs& a) {
+  return a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0;
+}
+size_t grad_lds(const ReplayArgs& a) { return (size_t)((a.n_params + 1) & ~1) * sizeof(double); }
+}  // namespace
+
+void launch_replay_forward(const ReplayArgs& a, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_forward, dim3(replay_grid(n)), dim3(256), stack_lds(a), s, a, n);
+}
+
+void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s) {
+  const size_t legs = (size_t)kLegCache * 256 * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(k_replay_secondary, dim3(replay_grid(max_entries)), dim3(256),
+                     grad_lds(a) + legs + stack_lds(a), s, a);
+}
+
+void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a), s, a, n);
+}
+
+void launch_basis_gather(const double* vadj, const double* vbasis, const long* vbeg, int n_meshes,
+                         int n_basis, double* g_q, hipStream_t s) {
+  if (n_meshes > 0 && n_basis > 0)
+    hipLaunchKernelGGL(k_basis_gather, dim3(n_meshes * n_basis), dim3(256), 0, s, vadj, vbasis, vbeg,
+                       n_basis, g_q);
 }
 
 }  // namespace usrt
