@@ -420,10 +420,22 @@ int fill_tx(TxTable& t, const us_tx_desc* tx, int first, int count) {
 // us_simulate_rf_workspace_size (about 200 bytes of queue per ray).
 constexpr long kDefaultChunk = 1L << 24;
 
+// Deposits recorded for the binned splat per ray of a chunk (more spill to
+// direct atomics).
+constexpr long kDepositsPerRay = 2;
+
+// Rows of the widest transmit group when their deposits can be binned, else 0.
+int bin_rows(int n_tx, const us_probe* p) {
+  const long rows = (long)std::min(n_tx, kMaxTxPerLaunch) * p->d.n_elem;
+  return rows <= kMaxBinRows && p->d.n_t < kMaxBinSamples ? (int)rows : 0;
+}
+
 size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {
   Carver c{nullptr};
   c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
-  c.take<unsigned long long>((size_t)max_bounces + 4);
+  c.take<unsigned long long>((size_t)max_bounces + 4 + kDepShards);
+  const int rows = bin_rows(n_tx, p);
+  if (rows > 0) c.take<char>(splat_scratch_bytes(rows));
   return c.off;
 }
 
@@ -474,6 +486,8 @@ size_t queue_bytes(long cap) {
   RayQueue a, b;
   SecondaryQueue n;
   carve_queues(c, cap, &a, &b, &n);
+  c.take<uint32_t>((size_t)kDepositsPerRay * cap);
+  c.take<float2>((size_t)kDepositsPerRay * cap);
   return c.off;
 }
 
@@ -531,10 +545,27 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   const us_probe_desc& pd = probe->d;
   Carver c{(char*)ws_dev};
   float* h = c.take<float>((size_t)n_tx * pd.n_elem * pd.n_t);
-  unsigned long long* counts = c.take<unsigned long long>((size_t)max_bounces + 4);
+  unsigned long long* counts = c.take<unsigned long long>((size_t)max_bounces + 4 + kDepShards);
+  const int rows = bin_rows(n_tx, probe);
+  void* bin_scratch = rows > 0 ? (void*)c.take<char>(splat_scratch_bytes(rows)) : nullptr;
   TraceArgs a{};
   carve_queues(c, cap, &a.qin, &a.qout, &a.nee);
   const RayQueue q0 = a.qin, q1 = a.qout;
+  a.dep.key = c.take<uint32_t>((size_t)kDepositsPerRay * cap);
+  a.dep.w = c.take<float2>((size_t)kDepositsPerRay * cap);
+  a.dep_count = counts + max_bounces + 4;
+  // the binned order is written over the first ray queue, which is dead by
+  // then (72 bytes per ray hold the 2 x 12 bytes per ray)
+  DepositList sorted{};
+  {
+    char* dead = reinterpret_cast<char*>(q0.ox);
+    const size_t key_bytes = align_up((size_t)kDepositsPerRay * cap * sizeof(uint32_t));
+    sorted.key = reinterpret_cast<uint32_t*>(dead);
+    sorted.w = reinterpret_cast<float2*>(dead + key_bytes);
+    US_CHECK(key_bytes + (size_t)kDepositsPerRay * cap * sizeof(float2) <=
+                 (size_t)(reinterpret_cast<char*>(q1.ox) - dead),
+             "us_simulate_rf: internal workspace layout");
+  }
   a.scene = scene_view(scene, probe);
   a.probe = probe->pv;
   a.seed = seed;
@@ -554,11 +585,14 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
     fill_tx(a.tx, tx, t0, ng);
     a.tx_base = t0;
     const long total = (long)ng * ray_count;
+    const int n_rows = ng * pd.n_elem;
+    a.dep_cap = (bin_scratch && n_rows <= rows) ? kDepositsPerRay * cap : 0;   // split in kDepShards
+    a.dep.row0 = (uint32_t)t0 * (uint32_t)pd.n_elem;
     for (long g0 = 0; g0 < total; g0 += cap) {
       const long n = std::min(cap, total - g0);
       a.g0 = g0;
       a.n_chunk = n;
-      launch_fill_u32((uint32_t*)counts, 2L * (max_bounces + 4), 0u, s);
+      launch_fill_u32((uint32_t*)counts, 2L * (max_bounces + 4 + kDepShards), 0u, s);
       a.qin = q0;
       a.qout = q1;
       for (int k = 1; k <= max_bounces + 1; ++k) {
@@ -571,6 +605,14 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
           launch_secondary(a, k, n, audit, s);
         }
         std::swap(a.qin, a.qout);
+      }
+      if (a.dep_cap > 0) {
+        {
+          Timed tm(ctx, "splat_bin", s);
+          launch_splat_bin(a.dep, a.dep_count, a.dep_cap / kDepShards, n_rows, sorted, bin_scratch, s);
+        }
+        Timed tm(ctx, "splat_accumulate", s);
+        launch_splat_accumulate(sorted, bin_scratch, a.dep.row0, n_rows, pd.n_t, h, s);
       }
     }
   }

@@ -237,4 +237,84 @@ __device__ __forceinline__ Slots block_append2(bool keep_a, bool keep_b,
   return s;
 }
 
+// Block-aggregated append to one queue; same contract as block_append2.
+__device__ __forceinline__ long block_append1(bool keep, unsigned long long* count,
+                                              unsigned long long* scratch) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = blockDim.x >> 6;
+  const unsigned long long m = __ballot(keep);
+  if (lane == 0) scratch[wave] = (unsigned long long)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int w = 0; w < n_waves; ++w) {
+      const unsigned long long c = scratch[w];
+      scratch[w] = run;
+      run += c;
+    }
+    scratch[n_waves] = run ? atomicAdd(count, run) : 0ull;
+  }
+  __syncthreads();
+  const unsigned long long base = scratch[n_waves] + scratch[wave];
+  __syncthreads();
+  const unsigned below =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  return keep ? (long)(base + below) : -1;
+}
+
+// Appends one entry per active lane whose `want` is set, with one atomic per
+// wave; usable in divergent code (only the active lanes take part).
+__device__ __forceinline__ long wave_append(bool want, unsigned long long* count) {
+  const unsigned long long m = __ballot(want);
+  if (!want) return -1;
+  const int leader = __ffsll((long long)m) - 1;
+  const unsigned below =
+      __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  unsigned long long base = 0;
+  if (below == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
+  return (long)((((unsigned long long)hi << 32) | lo) + below);
+}
+
+// One path contribution of amplitude a at time t on RF row `row`, split by
+// the linear tent: a (1 - f) at bin j0 = floor(t fs), a f at j0 + 1 (bins
+// outside [0, n_t) are dropped when the deposit is added).
+struct Deposit {
+  uint32_t row;
+  int32_t j0;
+  float w0, w1;
+};
+
+__device__ __forceinline__ bool make_deposit(uint32_t row, int n_t, double fs, double t, double a,
+                                             Deposit* d) {
+  const double x = t * fs;
+  if (!(x > -1.0 && x < (double)n_t)) return false;   // also rejects NaN
+  const double j0d = floor(x);
+  const double f = x - j0d;
+  d->row = row;
+  d->j0 = (int)j0d;
+  d->w0 = (float)(a * (1.0 - f));
+  d->w1 = (float)(a * f);
+  return true;
+}
+
+// Recorded deposits, structure of arrays: key = (row - row0) << kDepBinBits |
+// (j0 + 1), w = (w0, w1).
+constexpr int kDepBinBits = 19;
+constexpr int kMaxBinRows = 8192;                          // rows of one binned group
+constexpr int kMaxBinSamples = (1 << kDepBinBits) - 1;     // n_t below this
+constexpr int kDepShards = 64;   // record buffer shards, each with its own counter
+struct DepositList {
+  uint32_t* key;
+  float2* w;
+  uint32_t row0;
+};
+
+// Adds a deposit straight into the histogram with global atomics.
+__device__ __forceinline__ void add_deposit(float* h, int n_t, const Deposit& d) {
+  float* r = h + (long)d.row * n_t;
+  if (d.j0 >= 0) unsafeAtomicAdd(r + d.j0, d.w0);
+  if (d.j0 + 1 < n_t) unsafeAtomicAdd(r + d.j0 + 1, d.w1);
+}
+
 }  // namespace usrt

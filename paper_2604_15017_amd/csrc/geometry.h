@@ -194,17 +194,6 @@ __device__ __forceinline__ Coef coefficients(d3 d, d3 n, double c1, double Z1, d
   return f;
 }
 
-__device__ __forceinline__ void splat(float* h, long row, int n_t, double fs, double t, double a) {
-  const double x = t * fs;
-  if (!(x > -1.0 && x < (double)n_t)) return;   // also rejects NaN
-  const double j0d = floor(x);
-  const double f = x - j0d;
-  const int j0 = (int)j0d;
-  float* r = h + row * (long)n_t;
-  if (j0 >= 0) unsafeAtomicAdd(r + j0, (float)(a * (1.0 - f)));
-  if (j0 + 1 < n_t) unsafeAtomicAdd(r + j0 + 1, (float)(a * f));
-}
-
 __device__ __forceinline__ double elem_x(const ProbeView& p, int e) {
   return ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
 }

@@ -40,6 +40,13 @@ struct TraceArgs {
   // bits) and secondary rays spawned at interaction k (high 32 bits)
   unsigned long long* counts;
   float* h;               // deposit histogram [n_tx][n_elem][n_t]
+  // deposits of the secondary rays recorded for the binned splat in
+  // kDepShards shards of dep_cap / kDepShards records (shard = block index
+  // mod kDepShards, count dep_count[shard]); beyond a shard's capacity (or
+  // with dep_cap = 0) they are added to h directly
+  DepositList dep;
+  long dep_cap;
+  unsigned long long* dep_count;
   unsigned long long* counters;   // optional int64[5]
   unsigned long long* hash;       // optional [n_tx][ray_count]
 };
@@ -123,6 +130,16 @@ struct MeshDevice {
 // [n_meshes][n_basis]), then the boxes, deepest level first.
 void launch_mesh_refit(const MeshDevice& m, const double* q, hipStream_t s);
 void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
+
+// Binned splat of the recorded deposits of rows [row0, row0 + n_rows)
+// (n_rows <= kMaxBinRows, n_t < kMaxBinSamples): counting sort by row into
+// `sorted`, then one block per row and time tile sums the row's deposits in
+// LDS and adds the tile to h.
+size_t splat_scratch_bytes(int n_rows);
+void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_count, long shard_cap,
+                      int n_rows, const DepositList& sorted, void* scratch, hipStream_t s);
+void launch_splat_accumulate(const DepositList& sorted, const void* scratch, uint32_t row0, int n_rows,
+                             int n_t, float* h, hipStream_t s);
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,

@@ -333,21 +333,6 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   xbar = xbar + xb - dvbar;
 }
 
-// Appends one entry per active lane whose `want` is set, with one atomic per
-// wave; usable in divergent code (only the active lanes take part).
-__device__ __forceinline__ long wave_append(bool want, unsigned long long* count) {
-  const unsigned long long m = __ballot(want);
-  if (!want) return -1;
-  const int leader = __ffsll((long long)m) - 1;
-  const unsigned below =
-      __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-  unsigned long long base = 0;
-  if (below == 0) base = atomicAdd(count, (unsigned long long)__popcll(m));
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)base, leader);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(base >> 32), leader);
-  return (long)((((unsigned long long)hi << 32) | lo) + below);
-}
-
 // Ray of chunk slot i: transmit (local index) and ray id.
 __device__ __forceinline__ void ray_of(const ReplayArgs& a, long i, int* txl, uint32_t* rid) {
   const long g = a.g0 + i;

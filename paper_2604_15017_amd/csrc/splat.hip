@@ -1,0 +1,178 @@
+// Binned splat of the RF deposit histogram (time-of-flight deposits with the
+// linear tent of the path contributions, Sec. 2.3.4): the secondary-ray kernel
+// records each deposit (row and bin in one key, the two tent weights); here
+// the records are grouped by RF row with a counting sort whose per-block
+// histograms and cursors live in LDS, and then one block per row and time tile
+// sums its deposits in an LDS copy of the tile (LDS atomics) and adds the tile
+// to the histogram in HBM with plain coalesced accesses. Global atomics are
+// left to deposits that did not fit the record buffer.
+#include "kernels.h"
+
+namespace usrt {
+
+namespace {
+
+constexpr int kBinBlocks = 256;    // blocks of the counting and scatter passes
+constexpr int kBinThreads = 1024;
+constexpr int kAccTile = 8192;     // samples per accumulation block (32 KB of LDS)
+
+struct BinScratch {
+  uint32_t* hist;       // [n_rows][kBinBlocks]: counts, then row start + prefix over blocks
+  uint32_t* total;      // [n_rows]
+  uint32_t* row_begin;  // [n_rows + 1]
+};
+
+inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+inline BinScratch carve(void* base, int n_rows) {
+  char* p = (char*)base;
+  BinScratch b;
+  b.hist = (uint32_t*)p;
+  p += align256((size_t)kBinBlocks * n_rows * sizeof(uint32_t));
+  b.total = (uint32_t*)p;
+  p += align256((size_t)n_rows * sizeof(uint32_t));
+  b.row_begin = (uint32_t*)p;
+  return b;
+}
+
+// Records [b0, b1) of this block: kBinBlocks / kDepShards blocks split each
+// shard's recorded records evenly.
+constexpr int kBlocksPerShard = kBinBlocks / kDepShards;
+static_assert(kBinBlocks % kDepShards == 0, "blocks per shard");
+
+__device__ __forceinline__ void block_range(const unsigned long long* shard_count, long shard_cap, long* b0,
+                                            long* b1) {
+  const int shard = blockIdx.x / kBlocksPerShard, part = blockIdx.x % kBlocksPerShard;
+  const long n = min((long)shard_count[shard], shard_cap);
+  const long per = (n + kBlocksPerShard - 1) / kBlocksPerShard;
+  const long base = (long)shard * shard_cap;
+  *b0 = base + min(n, (long)part * per);
+  *b1 = base + min(n, (long)(part + 1) * per);
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_dep_count(const uint32_t* __restrict__ key,
+                                                           const unsigned long long* count, long shard_cap,
+                                                           int n_rows, BinScratch bs) {
+  __shared__ uint32_t lh[kMaxBinRows];
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) lh[r] = 0;
+  __syncthreads();
+  long b0, b1;
+  block_range(count, shard_cap, &b0, &b1);
+  for (long i = b0 + threadIdx.x; i < b1; i += blockDim.x) atomicAdd(&lh[key[i] >> kDepBinBits], 1u);
+  __syncthreads();
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x) bs.hist[(long)r * kBinBlocks + blockIdx.x] = lh[r];
+}
+
+// Block per row: exclusive prefix of the row's block counts (in place) and
+// the row total.
+__global__ __launch_bounds__(kBinBlocks) void k_dep_colscan(BinScratch bs) {
+  __shared__ uint32_t v[kBinBlocks];
+  const int r = blockIdx.x;
+  uint32_t* h = bs.hist + (long)r * kBinBlocks;
+  const uint32_t c = h[threadIdx.x];
+  v[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < kBinBlocks; off <<= 1) {   // inclusive Hillis-Steele scan
+    const uint32_t x = threadIdx.x >= (unsigned)off ? v[threadIdx.x - off] : 0u;
+    __syncthreads();
+    v[threadIdx.x] += x;
+    __syncthreads();
+  }
+  h[threadIdx.x] = v[threadIdx.x] - c;
+  if (threadIdx.x == kBinBlocks - 1) bs.total[r] = v[threadIdx.x];
+}
+
+// Exclusive scan of the row totals (one block of 1024 threads).
+__global__ __launch_bounds__(1024) void k_dep_rowscan(int n_rows, BinScratch bs) {
+  __shared__ uint32_t part[1024];
+  const int per = (n_rows + 1023) / 1024;
+  const int r0 = min(n_rows, (int)threadIdx.x * per), r1 = min(n_rows, r0 + per);
+  uint32_t s = 0;
+  for (int r = r0; r < r1; ++r) s += bs.total[r];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - s;
+  for (int r = r0; r < r1; ++r) {
+    bs.row_begin[r] = run;
+    run += bs.total[r];
+  }
+  if (threadIdx.x == 1023) bs.row_begin[n_rows] = part[1023];
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_dep_scatter(DepositList dep, const unsigned long long* count,
+                                                             long shard_cap, int n_rows, BinScratch bs,
+                                                             DepositList sorted) {
+  __shared__ uint32_t cur[kMaxBinRows];
+  for (int r = threadIdx.x; r < n_rows; r += blockDim.x)
+    cur[r] = bs.row_begin[r] + bs.hist[(long)r * kBinBlocks + blockIdx.x];
+  __syncthreads();
+  long b0, b1;
+  block_range(count, shard_cap, &b0, &b1);
+  for (long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+    const uint32_t k = dep.key[i];
+    const uint32_t pos = atomicAdd(&cur[k >> kDepBinBits], 1u);
+    sorted.key[pos] = k;
+    sorted.w[pos] = dep.w[i];
+  }
+}
+
+// Block (row, tile): the row's deposits summed into an LDS tile of samples
+// [t0, t0 + kAccTile), then added to h.
+__global__ __launch_bounds__(512) void k_dep_accumulate(DepositList sorted, BinScratch bs, uint32_t row0,
+                                                        int n_t, int tiles, float* __restrict__ h) {
+  __shared__ float acc[kAccTile];
+  const int r = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const uint32_t i0 = bs.row_begin[r], i1 = bs.row_begin[r + 1];
+  if (i0 == i1) return;   // nothing to add
+  const int t0 = tile * kAccTile, len = min(kAccTile, n_t - t0);
+  for (int j = threadIdx.x; j < len; j += blockDim.x) acc[j] = 0.0f;
+  __syncthreads();
+  const uint32_t mask = (1u << kDepBinBits) - 1u;
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const int j0 = (int)(sorted.key[i] & mask) - 1;   // bin of w0; w1 goes to j0 + 1
+    const float2 w = sorted.w[i];
+    const int j = j0 - t0;
+    if (j0 >= 0 && j >= 0 && j < len) atomicAdd(&acc[j], w.x);
+    if (j0 + 1 < n_t && j + 1 >= 0 && j + 1 < len) atomicAdd(&acc[j + 1], w.y);
+  }
+  __syncthreads();
+  float* out = h + (long)(row0 + r) * n_t + t0;
+  for (int j = threadIdx.x; j < len; j += blockDim.x) {
+    const float v = acc[j];
+    if (v != 0.0f) out[j] += v;
+  }
+}
+
+}  // namespace
+
+size_t splat_scratch_bytes(int n_rows) {
+  return align256((size_t)kBinBlocks * n_rows * sizeof(uint32_t)) + align256((size_t)n_rows * sizeof(uint32_t)) +
+         align256((size_t)(n_rows + 1) * sizeof(uint32_t));
+}
+
+void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_count, long shard_cap,
+                      int n_rows, const DepositList& sorted, void* scratch, hipStream_t s) {
+  const BinScratch bs = carve(scratch, n_rows);
+  hipLaunchKernelGGL(k_dep_count, dim3(kBinBlocks), dim3(kBinThreads), 0, s, dep.key, shard_count, shard_cap,
+                     n_rows, bs);
+  hipLaunchKernelGGL(k_dep_colscan, dim3(n_rows), dim3(kBinBlocks), 0, s, bs);
+  hipLaunchKernelGGL(k_dep_rowscan, dim3(1), dim3(1024), 0, s, n_rows, bs);
+  hipLaunchKernelGGL(k_dep_scatter, dim3(kBinBlocks), dim3(kBinThreads), 0, s, dep, shard_count, shard_cap,
+                     n_rows, bs, sorted);
+}
+
+void launch_splat_accumulate(const DepositList& sorted, const void* scratch, uint32_t row0, int n_rows,
+                             int n_t, float* h, hipStream_t s) {
+  const BinScratch bs = carve(const_cast<void*>(scratch), n_rows);
+  const int tiles = (n_t + kAccTile - 1) / kAccTile;
+  hipLaunchKernelGGL(k_dep_accumulate, dim3((unsigned)((long)n_rows * tiles)), dim3(512), 0, s, sorted, bs,
+                     row0, n_t, tiles, h);
+}
+
+}  // namespace usrt

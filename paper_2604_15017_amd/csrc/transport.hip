@@ -37,7 +37,7 @@ __device__ __forceinline__ void flush_counters(unsigned long long* g, unsigned l
 
 // One interaction step for every live ray (k = 1 fuses the emission).
 template <bool kAudit>
-__global__ __launch_bounds__(256) void k_bounce(TraceArgs a, int k) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_bounce(TraceArgs a, int k) {
   const long n_in = k == 1 ? a.n_chunk : (long)(uint32_t)a.counts[k - 1];
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
@@ -103,9 +103,11 @@ __global__ __launch_bounds__(256) void k_bounce(TraceArgs a, int k) {
             e = min(max(e, 0), P.n_elem - 1);
             if (kAudit) hsum += event_mix(kEvArray, k, (uint32_t)e);
             const double fd = rx_directivity(P, -d.z);
-            if (fd > 0.0) {
-              splat(a.h, (long)(a.tx_base + txl) * P.n_elem + e, P.n_t, P.fs, t, w * fd);
+            Deposit dp;
+            if (fd > 0.0) {   // few per launch: added to the histogram directly
               ++n_dep;
+              if (make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e), P.n_t, P.fs, t, w * fd, &dp))
+                add_deposit(a.h, P.n_t, dp);
             }
           } else if (kAudit) {
             hsum += event_mix(kEvArray, k, 0xFFFFFFu);
@@ -206,8 +208,7 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
   int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
   unsigned long long n_seg = 0, n_dep = 0, n_rays = 0;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)n_in;
-       i += (long)gridDim.x * blockDim.x) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += (long)gridDim.x * blockDim.x) {
     ++n_rays;
     const d3 x{a.nee.x[i], a.nee.y[i], a.nee.z[i]};
     double tof = a.nee.t[i], amp = a.nee.amp[i];
@@ -243,9 +244,23 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
       amp *= g.At;
       reg = sf.other;
     }
+    Deposit dp;
+    bool rec = false;
     if (!blocked) {
-      splat(a.h, (long)(a.tx_base + txl) * P.n_elem + e2, P.n_t, P.fs, tof, amp);
       ++n_dep;
+      rec = make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, tof, amp, &dp);
+    }
+    // record for the binned splat (one atomic per wave on this block's shard
+    // of the record buffer), else add directly
+    const int shard = blockIdx.x % kDepShards;
+    const long shard_cap = a.dep_cap / kDepShards;
+    const long slot = wave_append(rec && shard_cap > 0, a.dep_count + shard);
+    if (slot >= 0 && slot < shard_cap) {
+      const long at = (long)shard * shard_cap + slot;
+      a.dep.key[at] = ((dp.row - a.dep.row0) << kDepBinBits) | (uint32_t)(dp.j0 + 1);
+      a.dep.w[at] = make_float2(dp.w0, dp.w1);
+    } else if (rec) {
+      add_deposit(a.h, P.n_t, dp);
     }
     if (kAudit) {
       const uint32_t word = blocked ? ((uint32_t)e2 | (3u << 16) | (crossings << 20))

@@ -124,6 +124,35 @@ def test_small_workspace_forces_chunks(L, ctx):
     assert rel_l2(g_small, rf) <= RF_TOL
 
 
+def test_deposits_beyond_the_record_buffer(L, ctx):
+    """Twelve weakly reflecting, half-diffuse layers of equal sound speed: each
+    ray crosses them all and sends a secondary ray at every crossing, about 10
+    deposits per ray, more than the binned splat records (2 per ray); the rest
+    take the direct path and the RF still matches the oracle."""
+    n = 12
+    regions = np.array([[1540.0, 1.5 + 0.05 * (i % 2), 0.3] for i in range(n + 1)])
+    sc = W.Scene(regions=regions, planes=np.linspace(2e-3, 24e-3, n),
+                 plane_regions=np.array([[i, i + 1] for i in range(n)], np.int32),
+                 plane_kd=np.full(n, 0.5), spheres=np.zeros((0, 4)),
+                 sphere_regions=np.zeros((0, 2), np.int32), sphere_kd=np.zeros(0))
+    wl = W.two_layer().replace(scene=sc, rays_per_elem=64, max_bounces=12)
+    g, rf = check_transport(L, ctx, wl)
+    assert g["counters"][2] > 4 * wl.n_tx * wl.rays_per_tx   # more deposits than records
+
+
+def test_wide_transmit_groups_splat_directly(L, ctx):
+    """65 transmits of a 130-element array: the first launch group has 64 x 130
+    rows, beyond what the binned splat sorts in LDS, and deposits directly;
+    the second (one transmit) is binned."""
+    import dataclasses
+    wl = W.two_layer()
+    probe = dataclasses.replace(wl.probe, n_elem=130)
+    sc = dataclasses.replace(wl.scene, plane_kd=np.full_like(wl.scene.plane_kd, 0.3))
+    wl = wl.replace(scene=sc, probe=probe, rays_per_elem=4, angles=np.radians(np.linspace(-10, 10, 65)),
+                    tx_ids=np.arange(65, dtype=np.uint32))
+    check_transport(L, ctx, wl)
+
+
 def test_invalid_arguments_are_rejected(L, ctx):
     import torch
     wl = W.two_layer(rays_per_elem=64)
