@@ -93,9 +93,13 @@ __global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* 
 // sample index is formed in fp64 (an fp32 index near 4000 carries 2.4e-4
 // samples of rounding, i.e. 2e-4 rad of phase per tap at 5 MHz / 40 MHz);
 // interpolation and accumulation are fp32.
-__global__ __launch_bounds__(256) void k_das(const float2* __restrict__ A, float2* __restrict__ iq,
-                                             ProbeView p, GridView g, TxTable tx, int n_tx,
-                                             int tx_base, int accumulate) {
+// One thread per pixel, reading the two samples of every (element,
+// transmit) pair straight from HBM through the caches; used for grids too
+// small to fill the chip with pixel tiles. Same sums in the same order as
+// k_das_tiled.
+__global__ __launch_bounds__(256) void k_das_gather(const float2* __restrict__ A, float2* __restrict__ iq,
+                                                    ProbeView p, GridView g, TxTable tx, int n_tx,
+                                                    int tx_base, int accumulate) {
   const long px = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (px >= (long)g.n_x * g.n_z) return;
   const int a = (int)(px / g.n_z), b = (int)(px % g.n_z);
@@ -120,6 +124,98 @@ __global__ __launch_bounds__(256) void k_das(const float2* __restrict__ A, float
     }
   }
   iq[px] = acc;
+}
+
+// One block per tile of kDasTx x kDasTz pixels. The (element, transmit)
+// pairs are taken kDasPairs at a time, element-major like the plain sum: for
+// each pair the window of samples any pixel of the tile can touch is bounded
+// from the tile's corners (the transmit term is linear in x and z; the
+// receive distance lies between the distance from the element to the tile
+// and to its farthest corner), that window of the pair's analytic signal is
+// loaded into LDS with coalesced reads, and every pixel interpolates from it.
+// A window wider than kDasSpan is read from HBM instead.
+constexpr int kDasTx = 16, kDasTz = 16;      // 256 threads, z fastest
+constexpr int kDasPairs = 8;
+constexpr int kDasSpan = 256;
+constexpr long kDasMinTiles = 1024;          // below this the grid cannot fill the chip: gather
+
+__global__ __launch_bounds__(256) void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq,
+                                                   ProbeView p, GridView g, TxTable tx, int n_tx,
+                                                   int tx_base, int accumulate, int tiles_z) {
+  __shared__ float2 seg[kDasPairs][kDasSpan];
+  __shared__ int seg_lo[kDasPairs], seg_n[kDasPairs];
+  const int a0 = (blockIdx.x / tiles_z) * kDasTx, b0 = (blockIdx.x % tiles_z) * kDasTz;
+  const int a = a0 + (int)threadIdx.x / kDasTz, b = b0 + (int)threadIdx.x % kDasTz;
+  const bool inside = a < g.n_x && b < g.n_z;
+  const long px = (long)a * g.n_z + b;
+  const double x = g.x0 + a * g.dx, z = g.z0 + b * g.dz;
+  // the tile's extent (clipped to the grid)
+  const double xa = g.x0 + a0 * g.dx, xb = g.x0 + (min(a0 + kDasTx, g.n_x) - 1) * g.dx;
+  const double za = g.z0 + b0 * g.dz, zb = g.z0 + (min(b0 + kDasTz, g.n_z) - 1) * g.dz;
+  const double s_per_m = p.fs / p.c_ref;
+  const double half = 0.5 * (double)(p.n_elem - 1);
+  float2 acc = (accumulate && inside) ? iq[px] : make_float2(0.0f, 0.0f);
+  const int n_pairs = p.n_elem * n_tx;
+  int krx_e = -1;
+  double krx = 0.0;
+  for (int q0 = 0; q0 < n_pairs; q0 += kDasPairs) {
+    const int nq = min(kDasPairs, n_pairs - q0);
+    if ((int)threadIdx.x < nq) {
+      const int q = q0 + threadIdx.x, e = q / n_tx, i = q % n_tx;
+      const double xe = ((double)e - half) * p.pitch;
+      const double sa = tx.sin_a[i], ca = tx.cos_a[i];
+      const double l1 = xa * sa + za * ca, l2 = xb * sa + za * ca, l3 = xa * sa + zb * ca, l4 = xb * sa + zb * ca;
+      const double lmin = fmin(fmin(l1, l2), fmin(l3, l4)), lmax = fmax(fmax(l1, l2), fmax(l3, l4));
+      const double dx_near = xe < xa ? xa - xe : (xe > xb ? xe - xb : 0.0);
+      const double dx_far = fmax(fabs(xe - xa), fabs(xe - xb));
+      const double rmin = sqrt(dx_near * dx_near + za * za), rmax = sqrt(dx_far * dx_far + zb * zb);
+      const double klo = floor((lmin + rmin) * s_per_m) - 1.0, khi = floor((lmax + rmax) * s_per_m) + 2.0;
+      const double lo = fmax(klo, -1.0), hi = fmin(khi, (double)p.n_t);   // samples [lo, hi]
+      seg_lo[threadIdx.x] = (int)lo;
+      seg_n[threadIdx.x] = hi >= lo ? (int)(hi - lo) + 1 : 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nq; ++j) {
+      const int n = seg_n[j];
+      if (n > kDasSpan) continue;   // read from HBM below
+      const int q = q0 + j;
+      const float2* row = A + ((long)(tx_base + q % n_tx) * p.n_elem + q / n_tx) * p.n_t;
+      for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int k = seg_lo[j] + t;
+        seg[j][t] = (k >= 0 && k < p.n_t) ? row[k] : make_float2(0.0f, 0.0f);
+      }
+    }
+    __syncthreads();
+    if (inside) {
+      for (int j = 0; j < nq; ++j) {
+        const int q = q0 + j, e = q / n_tx, i = q % n_tx;
+        if (e != krx_e) {   // receive delay once per element
+          const double dxe = x - ((double)e - half) * p.pitch;
+          krx = sqrt(dxe * dxe + z * z) * s_per_m;
+          krx_e = e;
+        }
+        const double k = (x * tx.sin_a[i] + z * tx.cos_a[i]) * s_per_m + krx;
+        const double k0d = floor(k);
+        if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
+        const int k0 = (int)k0d;
+        const float f = (float)(k - k0d);
+        float2 v0, v1;
+        if (seg_n[j] <= kDasSpan) {
+          const int o = k0 - seg_lo[j];   // within [0, n - 2] by the window bound
+          v0 = seg[j][o];
+          v1 = seg[j][o + 1];
+        } else {
+          const float2* row = A + ((long)(tx_base + i) * p.n_elem + e) * p.n_t;
+          v0 = k0 >= 0 ? row[k0] : make_float2(0.0f, 0.0f);
+          v1 = k0 + 1 < p.n_t ? row[k0 + 1] : make_float2(0.0f, 0.0f);
+        }
+        acc.x += (1.0f - f) * v0.x + f * v1.x;
+        acc.y += (1.0f - f) * v0.y + f * v1.y;
+      }
+    }
+    __syncthreads();
+  }
+  if (inside) iq[px] = acc;
 }
 
 // Frame maximum of |I|^2 with the first index among equals, packed as
@@ -316,9 +412,16 @@ int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddl
 
 void launch_das(const float2* A, float2* iq, const ProbeView& p, const GridView& g,
                 const TxTable& tx, int n_tx_group, int tx_base, bool accumulate, hipStream_t s) {
-  const long n_px = (long)g.n_x * g.n_z;
-  hipLaunchKernelGGL(k_das, dim3((unsigned)((n_px + 255) / 256)), dim3(256), 0, s, A, iq, p, g, tx,
-                     n_tx_group, tx_base, accumulate ? 1 : 0);
+  const int tiles_x = (g.n_x + kDasTx - 1) / kDasTx, tiles_z = (g.n_z + kDasTz - 1) / kDasTz;
+  const long tiles = (long)tiles_x * tiles_z;
+  if (tiles >= kDasMinTiles) {
+    hipLaunchKernelGGL(k_das_tiled, dim3((unsigned)tiles), dim3(kDasTx * kDasTz), 0, s, A, iq, p, g, tx,
+                       n_tx_group, tx_base, accumulate ? 1 : 0, tiles_z);
+  } else {
+    const long n_px = (long)g.n_x * g.n_z;
+    hipLaunchKernelGGL(k_das_gather, dim3((unsigned)((n_px + 255) / 256)), dim3(256), 0, s, A, iq, p, g, tx,
+                       n_tx_group, tx_base, accumulate ? 1 : 0);
+  }
 }
 
 void launch_env_max(const float2* iq, long n_px, unsigned long long* key, hipStream_t s) {

@@ -204,6 +204,36 @@ def test_beamform_and_bmode_on_oracle_rf(L, ctx, which):
     assert err <= DB_TOL
 
 
+def test_tiled_and_gather_beamformers_on_a_large_grid(L, ctx):
+    """The 512 x 1024 anatomy grid (192 elements, 21 transmits) is beamformed
+    by the LDS-tiled kernel; a ragged 61 x 133 window of it, beamformed alone,
+    is small enough for the per-pixel gather kernel. Both match the oracle on
+    that window (to 1e-5, as for the full pipeline), and each other."""
+    import torch
+    wl = W.anatomy_phantom(level_organ=1, level_lesion=1, tube_around=8, tube_along=2)
+    p, g = wl.probe, wl.grid
+    rng = np.random.default_rng(9)
+    k = np.exp(-0.5 * (np.arange(-12, 13) / 4.0) ** 2)
+    rf = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), -1,
+                             rng.standard_normal((wl.n_tx, p.n_elem, p.n_t))).astype(np.float32)
+    probe = L.Probe(ctx, p)
+    rf_t = torch.tensor(rf, device="cuda")
+    big = L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf_t)
+    a0, b0 = 203, 301
+    sub = W.Grid(61, 133, g.x0 + a0 * g.dx, g.dx, g.z0 + b0 * g.dz, g.dz)
+    small = L.us_beamform(ctx, probe, sub, wl.angles, wl.tx_ids, rf_t)
+    torch.cuda.synchronize()
+    big = big.cpu().numpy().astype(np.float64)
+    small = small.cpu().numpy().astype(np.float64)
+    win = big[a0:a0 + sub.n_x, b0:b0 + sub.n_z]
+    I = oracle.das(oracle.analytic(rf.astype(np.float64)), p, sub, wl.angles)
+    r_tiled = rel_l2(win[..., 0] + 1j * win[..., 1], I)
+    r_gather = rel_l2(small[..., 0] + 1j * small[..., 1], I)
+    print(f"tiled {r_tiled:.3e}, gather {r_gather:.3e}, between {rel_l2(win, small):.3e}", flush=True)
+    assert r_tiled <= 1e-5 and r_gather <= 1e-5
+    assert rel_l2(win, small) <= 1e-6
+
+
 def test_end_to_end_bmode_full_size(L, ctx):
     wl = W.two_layer()
     out = oracle.render(wl)
