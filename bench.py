@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+CALIBRATION_BYTES = 512 << 20
 FP64_PEAK_TFLOPS = 78.6    # MI355X vector fp64
 
 
@@ -62,19 +63,49 @@ def kernel_bytes(name, wl, counts, n_px):
     }.get(name)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
+    summary is missing or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "transport_layered_phantom_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals, srcs, sha = {}, [], None
+    for line in text.splitlines():
+        t = line.split()
+        if len(t) == 3 and t[0] == "traffic_bytes_per_launch":
+            vals[t[1]] = float(t[2])
+        elif len(t) == 2 and t[0] == "sources_sha256":
+            sha = t[1]
+        elif t and t[0] == "sources":
+            srcs = t[1:]
+    h = hashlib.sha256()
+    try:
+        for f in srcs:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    if sha is None or h.hexdigest() != sha:
+        return None
+    return vals.get(kernel)
+
+
 def cpu_baseline(wl):
-    """The FP64 oracle on the host: the whole frame's transport (all rays)."""
-    import numpy as np
+    """The FP64 oracle on the host cores: the transport of one whole frame
+    (every ray of every transmit; a few seconds of CPU work), segments/s."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
     tr = oracle.trace(wl.scene, wl.probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
                       wl.max_bounces, n_threads=cores)
     dt = time.perf_counter() - t0
-    return {"value": tr.segments / dt, "unit": "ray-segments/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"full frame transport, {wl.n_tx} x {wl.rays_per_tx} rays, FP64, "
-                      f"{tr.segments} segments in {dt:.2f} s"}
+    return {"value": tr.segments / dt, "unit": "ray-segments/s", "cores": cores, "kind": "oracle",
+            "sample": f"one whole frame: {wl.n_tx} x {wl.rays_per_tx} rays, FP64 transport "
+                      f"(no image chain), {tr.segments} segments in {dt:.2f} s"}
 
 
 def serving(ctx, n_requests):
@@ -140,7 +171,7 @@ def serving(ctx, n_requests):
     return out
 
 
-def frame_legs(ctx, wl, target, steps, warmup):
+def frame_legs(ctx, wl, target, steps, warmup, backward=True):
     """Forward (one B-mode frame) and forward + backward (B-mode MSE against
     the image of `target`, gradient of every parameter) of one workload, each
     timed over `steps` frames after `warmup` untimed ones with HIP events on the
@@ -221,22 +252,27 @@ def frame_legs(ctx, wl, target, steps, warmup):
         return out
 
     fwd_ms, prof = timed(step)
-    fb_ms, prof_fb = timed(step_fb)
+    fb_ms, prof_fb = timed(step_fb) if backward else (float("nan"), {})
     segments = counts[0] + counts[1]
     return {"counts": counts, "segments": segments, "n_params": scene.n_params,
             "fwd_ms": fwd_ms, "prof": prof, "kernels": kernel_table(prof),
-            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb), "loss": float(loss.item())}
+            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb),
+            "loss": float(loss.item()) if backward else None}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-anatomy", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--no-backward", action="store_true",
+                    help="forward legs only (for short profiler runs)")
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="first copy 512 MiB device to device, the reference for HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -246,9 +282,17 @@ def main():
     from paper_2604_15017_amd import workloads as W
 
     ctx = L.Context(0)
+    if args.pmc_calibration:
+        import torch
+        src = torch.ones(CALIBRATION_BYTES // 4, dtype=torch.float32, device=ctx.torch_device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = W.layered_phantom()
     p, g = wl.probe, wl.grid
-    r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup)
+    r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup,
+                   backward=not args.no_backward)
     counts, segments, prof = r["counts"], r["segments"], r["prof"]
     ms_per_step = r["fwd_ms"]
     print(f"layered phantom: forward {ms_per_step:.3f} ms/frame, forward+backward "
@@ -259,8 +303,10 @@ def main():
     dom_bytes = kernel_bytes(dom, wl, counts, g.n_px)
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
     launches = prof[dom][1] // args.steps
+    traffic = measured_traffic(dom)
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": int(traffic) if traffic is not None else None,
                 "bytes_per_launch": int(dom_bytes / max(1, launches)),
                 "avg_launch_us": round(1e3 * dom_ms / max(1, launches), 2)}
 
@@ -282,15 +328,17 @@ def main():
                          "deposits": counts[2], "interactions": counts[3], "secondary_rays": counts[4]},
         "kernels": r["kernels"],
         "roofline": roofline,
-        "fwd_bwd": {"workload": "layered_phantom forward + backward, B-mode MSE vs +-5 % target, "
-                                f"gradient of all {r['n_params']} parameters",
-                    "ms_per_step": round(r["fb_ms"], 4), "frames_per_s": round(1e3 / r["fb_ms"], 2),
-                    "ray_segments_per_s": segments / (r["fb_ms"] * 1e-3),
-                    "loss": r["loss"], "kernels": r["fb_kernels"]},
+        "fwd_bwd": None if args.no_backward else {
+            "workload": "layered_phantom forward + backward, B-mode MSE vs +-5 % target, "
+                        f"gradient of all {r['n_params']} parameters",
+            "ms_per_step": round(r["fb_ms"], 4), "frames_per_s": round(1e3 / r["fb_ms"], 2),
+            "ray_segments_per_s": segments / (r["fb_ms"] * 1e-3),
+            "loss": r["loss"], "kernels": r["fb_kernels"]},
     }
     if not args.no_anatomy:
         wa = W.anatomy_phantom()
-        a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup)
+        a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup,
+                       backward=not args.no_backward)
         print(f"anatomy phantom: forward {a['fwd_ms']:.3f} ms/frame, forward+backward "
               f"{a['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
         out["anatomy"] = {
@@ -301,10 +349,11 @@ def main():
             "forward": {"ms_per_step": round(a["fwd_ms"], 4), "frames_per_s": round(1e3 / a["fwd_ms"], 2),
                         "ray_segments_per_s": a["segments"] / (a["fwd_ms"] * 1e-3),
                         "segments_per_frame": a["segments"], "kernels": a["kernels"]},
-            "fwd_bwd": {"ms_per_step": round(a["fb_ms"], 4), "frames_per_s": round(1e3 / a["fb_ms"], 2),
-                        "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
-                        "gradient_parameters": a["n_params"], "loss": a["loss"],
-                        "kernels": a["fb_kernels"]},
+            "fwd_bwd": None if args.no_backward else {
+                "ms_per_step": round(a["fb_ms"], 4), "frames_per_s": round(1e3 / a["fb_ms"], 2),
+                "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
+                "gradient_parameters": a["n_params"], "loss": a["loss"],
+                "kernels": a["fb_kernels"]},
         }
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests)
