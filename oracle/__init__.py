@@ -11,6 +11,9 @@ Pieces:
   chain.py       - splat, pulse filter (Eq. axial_sig), analytic signal,
                    delay-and-sum (Eq. das) and its adjoint (Eq. das_adjoint),
                    envelope / log compression and their adjoints, numpy FP64
+  optim.py       - the inverse loop: clip parameterisation (Eq. clip01,
+                   scale_phys, clip_grad), Adam (Eq. adam), the weighted
+                   L1 + L2 image loss, one micro-batched iteration
 
 Parity status: every function here is pinned by a `-m "not gpu"` test against
 a closed form, an invariant, a library routine, brute force or finite
@@ -267,3 +270,4 @@ def directivity(probe, cos_a: float) -> float:
 
 
 from .chain import *  # noqa: E402,F401,F403
+from . import optim  # noqa: E402,F401
