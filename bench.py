@@ -5,7 +5,8 @@ rays, 8 interactions, 128 elements x 4096 samples, 256 x 512 pixels): transport
 and RF synthesis, beamforming, envelope and log compression, all through the
 C-ABI with inputs and buffers resident in HBM. The same protocol is repeated
 for forward + backward, and for the triangle-mesh anatomy phantom (200k
-triangles, 21 x 798,912 rays, 12 interactions), reported beside it. Prints one JSON line with the
+triangles, 21 x 798,912 rays, 12 interactions), reported beside it, followed
+by iterations of the inverse loop and the serving stream. Prints one JSON line with the
 throughput in ray-segments/s (a segment is one closest-hit query, primary or
 secondary), frames/s, per-kernel timings from HIP events recorded on the
 launch stream inside the timed region, the roofline of the dominant kernel and
@@ -106,6 +107,43 @@ def cpu_baseline(wl):
     return {"value": tr.segments / dt, "unit": "ray-segments/s", "cores": cores, "kind": "oracle",
             "sample": f"one whole frame: {wl.n_tx} x {wl.rays_per_tx} rays, FP64 transport "
                       f"(no image chain), {tr.segments} segments in {dt:.2f} s"}
+
+
+def inverse_leg(ctx, steps, warmup):
+    """Algorithm opt on the layered phantom: the 34 perturbed parameters free
+    within +-10 % (material and geometry learning-rate groups), the other 16
+    fixed, three micro-batches of transmits (4, 4, 3 plane waves), MSE against
+    the image of the seeded +-5 % target; iterations per second."""
+    import numpy as np
+    import torch
+    from paper_2604_15017_amd import workloads as W
+    from paper_2604_15017_amd.inverse import InverseLoop, MicroBatch, unconstrained_start
+    wl = W.layered_phantom()
+    sc = wl.scene
+    theta0 = sc.theta()
+    idx = W.perturbed_indices(sc)
+    lo, hi = theta0.copy(), theta0.copy()
+    lo[idx] = theta0[idx] - 0.1 * np.abs(theta0[idx])
+    hi[idx] = theta0[idx] + 0.1 * np.abs(theta0[idx])
+    lr = np.zeros_like(theta0)
+    n_mat = 3 * (sc.n_regions - 1)
+    lr[idx[:n_mat]], lr[idx[n_mat:]] = 0.02, 0.03
+    batches = [MicroBatch(list(range(i, min(i + 4, wl.n_tx)))) for i in range(0, wl.n_tx, 4)]
+    loop = InverseLoop(ctx, wl, lo, hi, lr, unconstrained_start(theta0, lo, hi), batches,
+                       target=W.layered_phantom_target(wl), max_norm=1e3)
+    losses = [float(loop.iterate().item()) for _ in range(warmup)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(loop.stream)
+    out = [loop.iterate() for _ in range(steps)]
+    end.record(loop.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    losses += [float(x.item()) for x in out]
+    return {"workload": f"layered_phantom, {len(idx)} free parameters, {len(batches)} transmit "
+                        f"micro-batches, MSE vs the +-5 % target, Adam (lr 0.02 material / 0.03 geometry)",
+            "ms_per_iteration": round(ms, 4), "iterations_per_s": round(1e3 / ms, 2),
+            "loss_first": losses[0], "loss_last": losses[-1], "iterations": len(losses)}
 
 
 def serving(ctx, n_requests):
@@ -355,6 +393,10 @@ def main():
                 "gradient_parameters": a["n_params"], "loss": a["loss"],
                 "kernels": a["fb_kernels"]},
         }
+    if not args.no_backward:
+        out["inverse"] = inverse_leg(ctx, args.steps, args.warmup)
+        print(f"inverse loop: {out['inverse']['ms_per_iteration']:.3f} ms/iteration", file=sys.stderr,
+              flush=True)
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:

@@ -208,6 +208,29 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
                        const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
                        void* stream);
 
+/* Inverse loop (Sec. "Parameterization and constraints", Sec. "Optimization
+ * procedure", Algorithm opt). All arrays are device doubles of length n.
+ *
+ * us_param_map: theta[j] = lo[j] + clip(u[j], 0, 1) (hi[j] - lo[j])
+ * (Eq. clip01, Eq. scale_phys); a parameter with lo[j] == hi[j] is fixed at
+ * lo[j]. Requires lo[j] <= hi[j] (not checked on the device). */
+int us_param_map(us_ctx* ctx, const double* u_dev, const double* lo_dev, const double* hi_dev,
+                 int32_t n, double* theta_dev, void* stream);
+/* us_adam_step: one Adam update (Eq. adam) of the unconstrained variables u
+ * from the gradient with respect to theta (as accumulated by the VJPs):
+ *   g_u[j] = g_theta[j] (hi[j] - lo[j]) if 0 < u[j] < 1 and lo[j] < hi[j],
+ *            else 0                                       (Eq. clip_grad)
+ *   if max_norm > 0 and |g_u|_2 > max_norm: g_u *= max_norm / |g_u|_2
+ *   m = beta1 m + (1 - beta1) g_u;  v = beta2 v + (1 - beta2) g_u^2
+ *   u -= lr[j] (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps)
+ * step >= 1 counts the updates (bias correction); lr holds one learning rate
+ * per parameter, so parameter groups are runs of equal values. u, m and v
+ * are updated in place; m and v start at zero. */
+int us_adam_step(us_ctx* ctx, double* u_dev, double* m_dev, double* v_dev,
+                 const double* g_theta_dev, const double* lo_dev, const double* hi_dev,
+                 const double* lr_dev, int32_t n, int32_t step, double beta1, double beta2,
+                 double eps, double max_norm, void* stream);
+
 /* Kernel timing for measurement. While enabled on a context, every kernel the
  * library launches for that context is bracketed by a pair of HIP events
  * recorded on the kernel's own stream. us_profile_read waits for the pending

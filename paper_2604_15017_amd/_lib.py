@@ -85,6 +85,9 @@ _SIGNATURES = {
     "us_image_loss_workspace_size": (sz, [i64]),
     "us_image_loss": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp,
                                      vp, sz, vp]),
+    "us_param_map": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp]),
+    "us_adam_step": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, i32, i32, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]),
     "us_profile_enable": (ctypes.c_int, [vp, ctypes.c_int]),
     "us_profile_read": (ctypes.c_int, [vp, i32, vp, vp, vp, vp]),
 }
@@ -362,6 +365,26 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
                                      int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(workspace),
                                      workspace.numel(), _stream(stream)), "us_simulate_rf_vjp")
     return g_theta
+
+
+def us_param_map(ctx: Context, u, lo, hi, theta=None, stream=None):
+    """theta = lo + clip(u, 0, 1) (hi - lo) on float64 device tensors."""
+    torch = _torch()
+    n = u.numel()
+    if theta is None:
+        theta = torch.empty(n, dtype=torch.float64, device=ctx.torch_device)
+    _check(load().us_param_map(ctx.handle, _ptr(u), _ptr(lo), _ptr(hi), n, _ptr(theta),
+                               _stream(stream)), "us_param_map")
+    return theta
+
+
+def us_adam_step(ctx: Context, u, m, v, g_theta, lo, hi, lr, step: int, beta1: float = 0.9,
+                 beta2: float = 0.999, eps: float = 1e-8, max_norm: float = 0.0, stream=None):
+    """One Adam step on u (float64 device tensors, updated in place with m, v)."""
+    _check(load().us_adam_step(ctx.handle, _ptr(u), _ptr(m), _ptr(v), _ptr(g_theta), _ptr(lo),
+                               _ptr(hi), _ptr(lr), u.numel(), int(step), float(beta1),
+                               float(beta2), float(eps), float(max_norm), _stream(stream)),
+           "us_adam_step")
 
 
 def us_profile_enable(ctx: Context, enable: bool = True):

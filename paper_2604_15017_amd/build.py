@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libusrt.so")
-SOURCES = ["api.hip", "transport.hip", "image.hip", "replay.hip", "mesh.hip", "splat.hip"]
+SOURCES = ["api.hip", "transport.hip", "image.hip", "replay.hip", "mesh.hip", "splat.hip", "optim.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

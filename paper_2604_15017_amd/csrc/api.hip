@@ -868,6 +868,35 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
 
 extern "C" {
 
+int us_param_map(us_ctx* ctx, const double* u_dev, const double* lo_dev, const double* hi_dev,
+                 int32_t n, double* theta_dev, void* stream) {
+  US_CHECK(ctx && u_dev && lo_dev && hi_dev && theta_dev, "us_param_map: NULL argument");
+  US_CHECK(n >= 1, "us_param_map: n must be >= 1");
+  US_HIP(hipSetDevice(ctx->device));
+  Timed tm(ctx, "param_map", (hipStream_t)stream);
+  launch_param_map(u_dev, lo_dev, hi_dev, n, theta_dev, (hipStream_t)stream);
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+int us_adam_step(us_ctx* ctx, double* u_dev, double* m_dev, double* v_dev,
+                 const double* g_theta_dev, const double* lo_dev, const double* hi_dev,
+                 const double* lr_dev, int32_t n, int32_t step, double beta1, double beta2,
+                 double eps, double max_norm, void* stream) {
+  US_CHECK(ctx && u_dev && m_dev && v_dev && g_theta_dev && lo_dev && hi_dev && lr_dev,
+           "us_adam_step: NULL argument");
+  US_CHECK(n >= 1, "us_adam_step: n must be >= 1");
+  US_CHECK(step >= 1, "us_adam_step: step counts from 1");
+  US_CHECK(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0,
+           "us_adam_step: need 0 <= beta1, beta2 < 1 and eps > 0");
+  US_HIP(hipSetDevice(ctx->device));
+  Timed tm(ctx, "adam_step", (hipStream_t)stream);
+  launch_adam(u_dev, m_dev, v_dev, g_theta_dev, lo_dev, hi_dev, lr_dev, n, step, beta1, beta2, eps,
+              max_norm, (hipStream_t)stream);
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
 int us_profile_enable(us_ctx* ctx, int enable) {
   US_CHECK(ctx, "us_profile_enable: NULL ctx");
   ctx->prof.on = enable != 0;

@@ -97,6 +97,13 @@ void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
 void launch_basis_gather(const double* vadj, const double* vbasis, const long* vbeg, int n_meshes,
                          int n_basis, double* g_q, hipStream_t s);
 
+// ---------------------------------------------------------------- inverse loop
+void launch_param_map(const double* u, const double* lo, const double* hi, int n, double* theta,
+                      hipStream_t s);
+void launch_adam(double* u, double* m, double* v, const double* g, const double* lo, const double* hi,
+                 const double* lr, int n, int step, double b1, double b2, double eps, double max_norm,
+                 hipStream_t s);
+
 // ---------------------------------------------------------------- meshes
 // Hierarchy as built on the host (breadth-first nodes, leaf-order triangles).
 struct MeshHierarchy {

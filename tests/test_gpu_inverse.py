@@ -1,0 +1,123 @@
+"""GPU parity of the inverse loop (Algorithm opt): the clip-and-scale map and
+the Adam step through the C-ABI against the oracle's numpy versions, whole
+micro-batched iterations against oracle.optim.iteration, and a sim-to-sim
+recovery on the layered phantom."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import optim
+from paper_2604_15017_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    from paper_2604_15017_amd import _lib
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return _lib
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    return L.Context(0)
+
+
+def test_param_map_and_adam_kernels(L, ctx):
+    import torch
+    rng = np.random.default_rng(0)
+    n = 3000   # more than one block's threads
+    lo = rng.uniform(-2.0, 0.0, n)
+    hi = lo + rng.uniform(0.5, 3.0, n)
+    hi[::17] = lo[::17]                      # fixed parameters
+    u = rng.uniform(-0.3, 1.3, n)
+    u[5], u[6] = 0.0, 1.0                    # exactly on the bounds
+    g = rng.standard_normal(n)
+    lr = np.where(np.arange(n) < n // 2, 0.01, 0.05)   # two parameter groups
+    m0, v0 = 0.1 * rng.standard_normal(n), rng.uniform(0.0, 0.1, n)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    theta = L.us_param_map(ctx, t(u), t(lo), t(hi))
+    torch.cuda.synchronize()
+    # equal up to the rounding of a fused multiply-add on the device
+    assert np.allclose(theta.cpu().numpy(), optim.param_map(u, lo, hi), rtol=1e-15, atol=1e-15)
+    for max_norm in (0.0, 0.5):
+        ud, md, vd = t(u), t(m0), t(v0)
+        L.us_adam_step(ctx, ud, md, vd, t(g), t(lo), t(hi), t(lr), 3, 0.9, 0.999, 1e-8, max_norm)
+        torch.cuda.synchronize()
+        g_u = optim.clip_norm(optim.unconstrained_grad(g, u, lo, hi), max_norm)
+        ur, mr, vr = optim.adam_update(u, m0, v0, g_u, lr, 3, 0.9, 0.999, 1e-8)
+        for a, b in ((ud, ur), (md, mr), (vd, vr)):
+            assert np.allclose(a.cpu().numpy(), b, rtol=1e-13, atol=1e-15)
+        if max_norm > 0:
+            assert np.linalg.norm(optim.unconstrained_grad(g, u, lo, hi)) > max_norm   # clipping active
+
+
+def _small_problem():
+    wl = W.with_grid(W.layered_phantom(), 96, 192).replace(
+        rays_per_elem=16, angles=np.radians([-10.0, 0.0, 10.0]), tx_ids=np.arange(3, dtype=np.uint32))
+    sc = wl.scene
+    theta0 = sc.theta()
+    # the four parameters this configuration is most sensitive to
+    idx = [sc.idx_region(1, "c"), sc.idx_region(2, "Z"), sc.idx_sphere(0, "r"), sc.idx_sphere(3, "z")]
+    target = theta0.copy()
+    target[idx] *= np.array([1.01, 1.04, 1.05, 0.98])
+    lo, hi = theta0.copy(), theta0.copy()
+    lo[idx], hi[idx] = theta0[idx] * 0.9, theta0[idx] * 1.1
+    lr = np.zeros_like(theta0)
+    lr[idx] = [0.02, 0.02, 0.03, 0.03]   # two parameter groups (material, geometry)
+    return wl, idx, theta0, target, lo, hi, lr
+
+
+def test_iterations_match_the_oracle(L, ctx):
+    """Three iterations with two micro-batches (transmits {0, 1}; transmit 2 on
+    half of its rays), weighted L1 + L2 loss and gradient clipping: the GPU
+    loop and oracle.optim.iteration fed the same reference images."""
+    import torch
+    from paper_2604_15017_amd.inverse import InverseLoop, MicroBatch, unconstrained_start
+    wl, idx, theta0, target, lo, hi, lr = _small_problem()
+    half = wl.rays_per_tx // 2
+    batches = [MicroBatch([0, 1]), MicroBatch([2], ray_begin=101, ray_count=half)]
+    subs = [(wl.replace(angles=wl.angles[[0, 1]], tx_ids=wl.tx_ids[[0, 1]]), 0, None),
+            (wl.replace(angles=wl.angles[[2]], tx_ids=wl.tx_ids[[2]]), 101, half)]
+    refs = [oracle.render(sw, theta=target, ray_begin=rb, ray_count=rc)["B"] for sw, rb, rc in subs]
+    u0 = unconstrained_start(theta0, lo, hi)
+    kw = dict(lambda1=0.2, lambda2=1.0, max_norm=5.0)
+    loop = InverseLoop(ctx, wl, lo, hi, lr, u0, batches,
+                       refs=[torch.tensor(r, dtype=torch.float32, device="cuda") for r in refs], **kw)
+    u, m, v = u0.copy(), np.zeros_like(u0), np.zeros_like(u0)
+    for k in range(1, 4):
+        loss_gpu = float(loop.iterate().item())
+        u, m, v, loss_orc, g = optim.iteration(subs, refs, u, m, v, lo, hi, lr, k, l1=0.2, l2=1.0,
+                                               max_norm=5.0)
+        ug = loop.u.cpu().numpy()
+        print(f"iteration {k}: loss gpu {loss_gpu:.6f} oracle {loss_orc:.6f}; "
+              f"u gpu {ug[idx]} oracle {u[idx]}", flush=True)
+        assert loss_gpu == pytest.approx(loss_orc, rel=1e-3)
+        assert np.all(np.abs(ug[idx] - u[idx]) <= 0.05 * lr[idx])
+        fixed = np.setdiff1d(np.arange(u.shape[0]), idx)
+        assert np.array_equal(loop.theta.cpu().numpy()[fixed], theta0[fixed])
+
+
+def test_recovery_on_the_layered_phantom(L, ctx):
+    """Sim-to-sim: four parameters perturbed by 2-5 % are pulled back towards
+    the target by 30 iterations of the loop (one micro-batch per transmit
+    pair, MSE)."""
+    import torch
+    from paper_2604_15017_amd import _lib
+    from paper_2604_15017_amd.inverse import InverseLoop, MicroBatch, unconstrained_start
+    wl, idx, theta0, target, lo, hi, lr = _small_problem()
+    wl = W.layered_phantom().replace(rays_per_elem=128)
+    sc = wl.scene
+    target_scene = sc.with_theta(target)
+    batches = [MicroBatch(list(range(i, min(i + 4, wl.n_tx)))) for i in range(0, wl.n_tx, 4)]
+    loop = InverseLoop(ctx, wl, lo, hi, lr, unconstrained_start(theta0, lo, hi), batches,
+                       target=target_scene)
+    losses = [float(loop.iterate().item()) for _ in range(30)]
+    th = loop.theta.cpu().numpy()
+    err0 = np.abs(theta0[idx] - target[idx]) / np.abs(target[idx])
+    err1 = np.abs(th[idx] - target[idx]) / np.abs(target[idx])
+    print(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}; relative parameter error {err0} -> {err1}", flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    assert err1.mean() < 0.5 * err0.mean()
