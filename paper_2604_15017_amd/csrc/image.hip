@@ -311,9 +311,12 @@ __global__ __launch_bounds__(256) void k_das_adjoint(const float2* __restrict__ 
   const int txl = blockIdx.x / p.n_elem;
   const int e = blockIdx.x % p.n_elem;
   const int k_a = threadIdx.x * kS;
-  float2 acc[kS];
-#pragma unroll
-  for (int s = 0; s < kS; ++s) acc[s] = make_float2(0.0f, 0.0f);
+  // this thread's kS accumulators, private, interleaved across the block's
+  // threads (entry s at acc[s * blockDim.x]): a pixel adds to two of them
+  extern __shared__ float2 acc_lds[];
+  float2* acc = acc_lds + threadIdx.x;
+  const int step = blockDim.x;
+  for (int s = 0; s < kS; ++s) acc[s * step] = make_float2(0.0f, 0.0f);
   const double sa = tx.sin_a[txl], ca = tx.cos_a[txl];
   const double s_per_m = p.fs / p.c_ref, m_per_s = p.c_ref / p.fs;
   const double xe = ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
@@ -338,18 +341,27 @@ __global__ __launch_bounds__(256) void k_das_adjoint(const float2* __restrict__ 
         const double rel = kap - (double)k_a;
         if (rel <= -1.0) continue;
         const float2 gv = col[b];
-#pragma unroll
-        for (int s = 0; s < kS; ++s) {
-          const float wt = fmaxf(0.0f, 1.0f - fabsf((float)(rel - (double)s)));
-          acc[s].x = fmaf(wt, gv.x, acc[s].x);
-          acc[s].y = fmaf(wt, gv.y, acc[s].y);
+        // the forward reads sample floor(kap) with weight 1 - f and the next with f
+        const double j0d = floor(rel);
+        const int j0 = (int)j0d;
+        const float f = (float)(rel - j0d);
+        if (j0 >= 0) {
+          float2 v = acc[j0 * step];
+          v.x = fmaf(1.0f - f, gv.x, v.x);
+          v.y = fmaf(1.0f - f, gv.y, v.y);
+          acc[j0 * step] = v;
+        }
+        if (j0 + 1 < kS) {
+          float2 v = acc[(j0 + 1) * step];
+          v.x = fmaf(f, gv.x, v.x);
+          v.y = fmaf(f, gv.y, v.y);
+          acc[(j0 + 1) * step] = v;
         }
       }
     }
     float2* row = gA + ((long)(tx_base + txl) * p.n_elem + e) * p.n_t;
-#pragma unroll
     for (int s = 0; s < kS; ++s)
-      if (k_a + s < p.n_t) row[k_a + s] = acc[s];
+      if (k_a + s < p.n_t) row[k_a + s] = acc[s * step];
   }
 }
 
@@ -450,12 +462,14 @@ void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, con
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s) {
   const dim3 grid((unsigned)(n_tx_group * p.n_elem)), block(256);
   const int per_thread = (p.n_t + 255) / 256;
+  const int k_s = per_thread <= 8 ? 8 : (per_thread <= 16 ? 16 : 32);
+  const size_t lds = (size_t)k_s * 256 * sizeof(float2);   // 64 KB at most
   if (per_thread <= 8)
-    hipLaunchKernelGGL(k_das_adjoint<8>, grid, block, 0, s, g_iq, g_A, p, g, tx, tx_base);
+    hipLaunchKernelGGL(k_das_adjoint<8>, grid, block, lds, s, g_iq, g_A, p, g, tx, tx_base);
   else if (per_thread <= 16)
-    hipLaunchKernelGGL(k_das_adjoint<16>, grid, block, 0, s, g_iq, g_A, p, g, tx, tx_base);
+    hipLaunchKernelGGL(k_das_adjoint<16>, grid, block, lds, s, g_iq, g_A, p, g, tx, tx_base);
   else
-    hipLaunchKernelGGL(k_das_adjoint<32>, grid, block, 0, s, g_iq, g_A, p, g, tx, tx_base);
+    hipLaunchKernelGGL(k_das_adjoint<32>, grid, block, lds, s, g_iq, g_A, p, g, tx, tx_base);
 }
 
 int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps_reversed, int M, int n_t,
