@@ -441,43 +441,55 @@ size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {
 
 size_t trace_per_ray_bytes() { return 2 * kRayQueueBytesPerRay + kSecondaryBytesPerRay; }
 
+void carve_ray_queue(Carver& c, long cap, RayQueue* q) {
+  q->ox = c.take<double>(cap); q->oy = c.take<double>(cap); q->oz = c.take<double>(cap);
+  q->dx = c.take<double>(cap); q->dy = c.take<double>(cap); q->dz = c.take<double>(cap);
+  q->t = c.take<double>(cap); q->w = c.take<double>(cap);
+  q->rid = c.take<uint32_t>(cap); q->meta = c.take<uint32_t>(cap);
+}
+
 void carve_queues(Carver& c, long cap, RayQueue* q0, RayQueue* q1, SecondaryQueue* nq) {
-  for (RayQueue* q : {q0, q1}) {
-    q->ox = c.take<double>(cap); q->oy = c.take<double>(cap); q->oz = c.take<double>(cap);
-    q->dx = c.take<double>(cap); q->dy = c.take<double>(cap); q->dz = c.take<double>(cap);
-    q->t = c.take<double>(cap); q->w = c.take<double>(cap);
-    q->rid = c.take<uint32_t>(cap); q->meta = c.take<uint32_t>(cap);
-  }
+  carve_ray_queue(c, cap, q0);
+  carve_ray_queue(c, cap, q1);
   nq->x = c.take<double>(cap); nq->y = c.take<double>(cap); nq->z = c.take<double>(cap);
   nq->t = c.take<double>(cap); nq->amp = c.take<double>(cap);
   nq->rid = c.take<uint32_t>(cap); nq->meta = c.take<uint32_t>(cap); nq->txk = c.take<uint32_t>(cap);
 }
 
 // Rays per chunk of the replay backward when the caller sizes the workspace
-// with us_simulate_rf_vjp_workspace_size (about 160 bytes per ray and step).
-constexpr long kReplayChunk = 1L << 21;
+// with us_simulate_rf_vjp_workspace_size: about 160 bytes per ray and step
+// plus 150 per ray, so some 20 GB for twelve interactions, and few enough
+// chunks that the per-step launches stay long.
+constexpr long kReplayChunk = 1L << 23;
 
-// Workspace of the replay backward for chunks of `cap` rays: dL/dh, then the
-// per-ray steps, the secondary-ray adjoints and the queue of diffuse
-// interactions.
+// Workspace of the replay backward for chunks of `cap` rays: dL/dh, the mesh
+// vertex adjoints, the per-block gradient rows, the step records, the queue
+// of diffuse interactions with its step offsets, the per-step counts and the
+// two live-ray queues.
 size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_bounces, long cap,
                     ReplayStack* k = nullptr, char* base = nullptr, float** gh = nullptr,
-                    double** vadj = nullptr) {
+                    double** vadj = nullptr, double** g_part = nullptr, RayQueue* q0 = nullptr,
+                    RayQueue* q1 = nullptr, unsigned long long** counts = nullptr) {
   Carver c{base};
   float* g = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   if (gh) *gh = g;
   double* va = c.take<double>((size_t)scene->mesh.n_vertices + 1);
   if (vadj) *vadj = va;
+  double* gp = c.take<double>((size_t)kMaxReplayBlocks * scene->q_offset);
+  if (g_part) *g_part = gp;
   ReplayStack tmp;
   ReplayStack& r = k ? *k : tmp;
   const size_t n = (size_t)cap * (max_bounces + 1);
-  r.n = (long)n;
-  r.f = c.take<double>(n * kReplayFields);
-  r.meta = c.take<uint32_t>(n);
-  r.hidx = c.take<int>(n);
+  r.rec = c.take<StepRec>(n);
+  r.adj = c.take<StepAdj>(n);
   r.last = c.take<int>((size_t)cap);
-  r.queue = c.take<unsigned long long>((size_t)cap * (max_bounces > 0 ? max_bounces : 1));
-  r.queue_count = c.take<unsigned long long>(1);
+  r.queue = c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1));
+  r.queue_begin = c.take<unsigned long long>((size_t)max_bounces + 1);
+  unsigned long long* cn = c.take<unsigned long long>((size_t)max_bounces + 2);
+  if (counts) *counts = cn;
+  RayQueue ta, tb;
+  carve_ray_queue(c, cap, q0 ? q0 : &ta);
+  carve_ray_queue(c, cap, q1 ? q1 : &tb);
   return c.off;
 }
 
@@ -814,8 +826,11 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   const us_probe_desc& pd = probe->d;
   ReplayArgs a{};
   float* gh = nullptr;
-  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &a.vadj);
+  RayQueue q0, q1;
+  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &a.vadj, &a.g_part,
+               &q0, &q1, &a.counts);
   if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2 * scene->mesh.n_vertices, 0u, s);
+  launch_fill_u32((uint32_t*)a.g_part, 2L * kMaxReplayBlocks * scene->q_offset, 0u, s);
   {
     Timed tm(ctx, "pulse_adjoint", s);
     if (launch_pulse_adjoint(g_rf_dev, gh, probe->taps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
@@ -829,8 +844,11 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   a.ray_begin = ray_begin;
   a.ray_count = ray_count;
   a.n_params = scene->n_params;
+  a.n_grad = scene->q_offset;
+  a.grad_copies = 16;   // keep the copies within 16 KB of LDS
+  while (a.grad_copies > 1 && (size_t)a.grad_copies * ((a.n_grad + 1) & ~1) * sizeof(double) > 16384)
+    a.grad_copies >>= 1;
   a.gh = gh;
-  a.g_theta = g_theta_dev;
   a.cap = cap;
   for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
     const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
@@ -840,13 +858,18 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
     for (long g0 = 0; g0 < n_group; g0 += cap) {
       const long n = std::min(cap, n_group - g0);
       a.g0 = g0;
-      launch_fill_u32((uint32_t*)a.stk.queue_count, 2, 0u, s);
+      launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);
       {
         Timed tm(ctx, "replay_forward", s);
-        launch_replay_forward(a, n, s);
+        for (int k = 1; k <= max_bounces + 1; ++k) {
+          a.qout = (k & 1) ? q0 : q1;
+          a.qin = (k & 1) ? q1 : q0;
+          launch_replay_forward(a, k, n, s);
+        }
       }
       {
         Timed tm(ctx, "replay_secondary", s);
+        launch_replay_prefix(a, s);
         launch_replay_secondary(a, n * std::max(1, max_bounces), s);
       }
       {
@@ -855,6 +878,7 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
       }
     }
   }
+  launch_grad_reduce(a.g_part, a.n_grad, g_theta_dev, s);
   if (scene->n_meshes > 0) {
     Timed tm(ctx, "basis_gather", s);
     launch_basis_gather(a.vadj, scene->mesh.vbasis, scene->mesh.vbeg, scene->n_meshes, scene->n_basis,

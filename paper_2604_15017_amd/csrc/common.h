@@ -204,8 +204,8 @@ __device__ __forceinline__ double rx_directivity(const ProbeView& p, double cos_
 // (keep_b) receives a distinct slot in queue A (B). The two running counts
 // share one 64-bit word (A in the low half, B in the high half), so a block
 // takes all its slots with a single atomic. Must be called by every thread of
-// the block (it contains barriers); `scratch` is 2 * (waves per block) + 1
-// words of LDS.
+// the block (it contains barriers); `scratch` is (waves per block) + 1 words
+// of LDS.
 struct Slots { long a, b; };
 
 __device__ __forceinline__ Slots block_append2(bool keep_a, bool keep_b,

@@ -51,26 +51,31 @@ struct TraceArgs {
   unsigned long long* hash;       // optional [n_tx][ray_count]
 };
 
-// Per-thread checkpoint stack of the replay: field[step * capacity + slot].
-// Per-ray replay state of one chunk of rays: fp64 field F of step k of chunk
-// ray i at f[F * n + (k - 1) * cap + i] (coalesced across rays), n = cap *
-// (max_bounces + 1).
-enum ReplayField : int {
-  kFOx, kFOy, kFOz, kFDx, kFDy, kFDz, kFT, kFW,   // state before step k
-  kFL,                                           // distance to the surface step k hits
-  // adjoints of the inputs of the secondary ray of interaction k: x, n_r, A_r, w_att, t'
-  kFXb, kFYb, kFZb, kFNxb, kFNyb, kFNzb, kFAb, kFWb, kFTb,
-  kReplayFields
+// Step record of the replay: the exact state before step k of a ray and the
+// surface the step hits (80 bytes, written and read as five 16-byte pieces,
+// so that records scattered by chunk ray still move whole sectors).
+struct alignas(16) StepRec {
+  double ox, oy, oz, dx, dy, dz, t, w;
+  double L;          // distance to the surface hit
+  uint32_t meta;     // region | last event not diffuse << 8 | hit kind << 12
+  int hidx;          // hit index (leaf-order triangle for meshes)
 };
+// Adjoints of the inputs of the secondary ray of a diffuse interaction:
+// x, n_r, A_r, w_att, t' (80 bytes with the padding).
+struct alignas(16) StepAdj {
+  double xb, yb, zb, nxb, nyb, nzb, Ab, wb, tb, pad;
+};
+static_assert(sizeof(StepRec) == 80 && sizeof(StepAdj) == 80, "replay record layout");
+
+// Records of one chunk of rays: step k of chunk ray i at [(k - 1) * cap + i].
 struct ReplayStack {
-  double* f;
-  long n;
-  uint32_t* meta;                                // region | delta << 8 | hit kind << 12
-  int* hidx;                                     // hit index (leaf-order triangle for meshes)
+  StepRec* rec;
+  StepAdj* adj;
   int* last;                                     // [cap] last step that can carry a deposit
-  unsigned long long* queue;                     // (k << 32) | i of the diffuse interactions
-  unsigned long long* queue_count;
+  uint32_t* queue;          // [max_bounces][cap]: chunk rays of the diffuse interactions of step k
+  unsigned long long* queue_begin;   // [max_bounces + 1]: exclusive prefix of the step sizes
 };
+constexpr int kMaxReplayBlocks = 2048;
 struct ReplayArgs {
   SceneView scene;
   ProbeView probe;
@@ -83,16 +88,27 @@ struct ReplayArgs {
   long cap;               // chunk capacity (rays)
   int tx_base;
   int n_params;
+  int n_grad;             // leading theta entries summed in LDS (regions, planes, spheres)
+  int grad_copies;        // interleaved LDS copies of those sums (power of two, <= 16)
   const float* gh;        // dL/dh [n_tx][n_elem][n_t]
-  double* g_theta;        // accumulated
+  double* g_part;         // [kMaxReplayBlocks][n_grad] per-block partial sums (zeroed per call)
   double* vadj;           // [n_vertices] mesh vertex adjoints along vnormal (zeroed per call)
   ReplayStack stk;
+  RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
+  unsigned long long* counts;   // [max_bounces + 2]: survivors of step k | diffuse interactions << 32
 };
-// The three phases of the replay over chunk rays [0, n); the queue count must
-// be zero before the forward phase.
-void launch_replay_forward(const ReplayArgs& a, long n, hipStream_t s);
+// The three phases of the replay over chunk rays [0, n): the forward phase
+// once per step k = 1..max_bounces + 1 (queues swapped in between), the
+// prefix over the per-step interaction counts, the secondary phase, then the
+// reverse sweep. The counts must be zero before the forward step k = 1. The
+// analytic gradient collects in g_part; add it to g_theta with
+// launch_grad_reduce once all chunks are done.
+void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s);
+void launch_replay_prefix(const ReplayArgs& a, hipStream_t s);
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s);
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
+// g_theta[j] += sum over b of g_part[b * n_grad + j], j < n_grad.
+void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, hipStream_t s);
 // g_q[m * n_basis + j] += sum_{v in mesh m} vadj[v] vbasis[v][j].
 void launch_basis_gather(const double* vadj, const double* vbasis, const long* vbeg, int n_meshes,
                          int n_basis, double* g_q, hipStream_t s);

@@ -4,21 +4,47 @@
 //   L = sum over deposits of <dL/dh, tent(t fs) a>
 // with respect to the scene parameters is accumulated by reverse-mode
 // differentiation along the path. Nothing is stored between the forward and
-// the backward call; inside this call each thread keeps the exact fp64 state
-// before every interaction of its current path in a private stack in the
-// workspace (structure of arrays, coalesced across threads), then sweeps it
-// backwards. Discrete choices (branch, hit surface, element, total internal
-// reflection, sample index) are frozen; branch probabilities are sampling
-// densities and carry no derivative.
+// the backward call. Inside this call the rays of a chunk are traced again as
+// a wavefront (one launch per step, survivors compacted), each step leaving
+// the exact fp64 state before it in an 80-byte record of its ray; the
+// secondary rays of the diffuse interactions are differentiated next, and
+// one thread per ray finally sweeps its records backwards. Discrete choices
+// (branch, hit surface, element, total internal reflection, sample index)
+// are frozen; branch probabilities are sampling densities and carry no
+// derivative.
 //
 // Parameter adjoints are summed per block in LDS (fp64 LDS atomics) and
-// flushed with one global fp64 atomic per block and parameter.
+// folded into a per-block row in HBM; the rows are reduced once per call.
 #include "geometry.h"
 #include "kernels.h"
 
 namespace usrt {
 
 namespace {
+
+// Per-block sums of the region, plane and sphere adjoints (the first n_grad
+// entries of theta; mesh coefficients go through the per-vertex scalars) are
+// kept in LDS in grad_copies interleaved copies: a lane adds to copy
+// lane % grad_copies, so lanes adding to the same parameter contend at most
+// 64 / grad_copies ways. The copies are folded when the block flushes.
+__device__ __forceinline__ int grad_stride(int n_grad) { return (n_grad + 1) & ~1; }
+
+__device__ __forceinline__ void grad_clear(double* gsh, int n_grad, int copies) {
+  for (int j = threadIdx.x; j < copies * grad_stride(n_grad); j += blockDim.x) gsh[j] = 0.0;
+}
+
+// Folds the copies into the block's own row of partial sums: one block with
+// this index runs at a time, so plain read-modify-writes suffice and no
+// global atomics contend on the few gradient entries.
+__device__ __forceinline__ void grad_flush(const double* gsh, int n_grad, int copies, double* g_part) {
+  const int st = grad_stride(n_grad);
+  double* row = g_part + (long)blockIdx.x * n_grad;
+  for (int j = threadIdx.x; j < n_grad; j += blockDim.x) {
+    double v = 0.0;
+    for (int c = 0; c < copies; ++c) v += gsh[c * st + j];
+    if (v != 0.0) row[j] += v;
+  }
+}
 
 // Per-block gradient accumulator over the flat parameter vector.
 struct GradAcc {
@@ -368,133 +394,177 @@ __device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t,
 
 }  // namespace
 
-// Phase 1 (one thread per ray of the chunk): the forward path again, keeping
-// the state before every step and the surface it hits; every interaction on
-// a diffuse surface is queued for phase 2.
-__global__ __launch_bounds__(256) void k_replay_forward(ReplayArgs a, long n) {
-  if ((long)blockIdx.x * blockDim.x >= n) return;
+// Phase 1, one launch per step k as in the forward transport: the live rays
+// of the chunk (all of them at k = 1, emitted here) take their step k again,
+// keeping the state before it and the surface it hits in the step record of
+// their chunk index; the survivors are compacted into the next queue and
+// every interaction on a diffuse surface is queued for phase 2.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+void k_replay_forward(ReplayArgs a, int k, long n) {
+  const long n_in = k == 1 ? n : (long)(uint32_t)a.counts[k - 1];   // survivors of step k - 1
+  if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
+  __shared__ unsigned long long scan[8];
   extern __shared__ int bvh_stack[];
   load_scene(S, a.scene);
   int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
   const int B = a.max_bounces;
   const long cap = a.cap;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    int txl;
-    uint32_t rid;
-    ray_of(a, i, &txl, &rid);
-    const uint32_t tx_id = a.tx.id[txl];
-    d3 o, d;
-    double t, w;
-    int region = S.start_region;
-    bool delta = true;
-    {
-      const int e = (int)(rid / (uint32_t)a.rays_per_elem);
-      const Draw u = draw(a.seed, rid, tx_id, 0);
-      const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
-      o = d3{((double)e - 0.5 * (double)(P.n_elem - 1)) * P.pitch + (u.u0 - 0.5) * P.elem_w,
-             (u.u1 - 0.5) * P.elem_h, 0.0};
-      d = d3{sa, 0.0, ca};
-      t = o.x * (sa / P.c_ref);
-      w = fmax(0.0, ca) / (double)a.rays_per_elem;
-    }
-    int last = 0;
-    for (int k = 1; k <= B + 1; ++k) {
-      const long at = (long)(k - 1) * cap + i;
-      const Hit h = closest_hit(S, o, d, true, stk);
-      double* F = a.stk.f + at;
-      const long fs = a.stk.n;
-      F[kFOx * fs] = o.x; F[kFOy * fs] = o.y; F[kFOz * fs] = o.z;
-      F[kFDx * fs] = d.x; F[kFDy * fs] = d.y; F[kFDz * fs] = d.z;
-      F[kFT * fs] = t; F[kFW * fs] = w; F[kFL * fs] = h.t;
-      a.stk.meta[at] = (uint32_t)region | ((uint32_t)delta << 8) | ((uint32_t)h.kind << 12);
-      a.stk.hidx[at] = h.index;
-      if (h.kind == kHitNone) break;
-      if (h.kind == kHitArray) { last = k; break; }
-      if (k > B) break;
-      const Step st = step_at(S, o, d, t, w, region, h);
-      t = st.tp;
-      w = st.watt;
-      const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
-      const double p_spec = (1.0 - st.sf.kd) * st.f.RE;
-      if (v.u0 < p_spec) {
-        d = d + st.f.nr * (2.0 * st.f.ci);
-        w *= st.f.Ar / st.f.RE;
-        delta = true;
-      } else if (v.u0 < st.f.RE) {
-        const d3 nn = st.f.nr;
-        const double sg = nn.z >= 0.0 ? 1.0 : -1.0;
-        const double aa = -1.0 / (sg + nn.z);
-        const double bb = nn.x * nn.y * aa;
-        const d3 b1{1.0 + sg * nn.x * nn.x * aa, sg * bb, -sg * nn.x};
-        const d3 b2{bb, sg + nn.y * nn.y * aa, -nn.y};
-        const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
-        d = b1 * (rr * cos(phi)) + b2 * (rr * sin(phi)) + nn * sqrt(1.0 - v.u2);
-        w *= st.f.Ar / st.f.RE;
-        delta = false;
+  const long stride = (long)gridDim.x * blockDim.x;
+  // block-uniform loop: the queue append below synchronises the block
+  for (long base = (long)blockIdx.x * blockDim.x; base < n_in; base += stride) {
+    const long iq = base + threadIdx.x;
+    const bool active = iq < n_in;
+    d3 o{0, 0, 0}, d{0, 0, 1};
+    double t = 0.0, w = 0.0;
+    uint32_t ci = 0;   // chunk index of the ray
+    int region = 0;
+    bool delta = true, keep = false, diffuse = false;
+    if (active) {
+      if (k == 1) {
+        ci = (uint32_t)iq;
+        int txl;
+        uint32_t rid;
+        ray_of(a, ci, &txl, &rid);
+        const int e = (int)(rid / (uint32_t)a.rays_per_elem);
+        const Draw u = draw(a.seed, rid, a.tx.id[txl], 0);
+        const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
+        o = d3{((double)e - 0.5 * (double)(P.n_elem - 1)) * P.pitch + (u.u0 - 0.5) * P.elem_w,
+               (u.u1 - 0.5) * P.elem_h, 0.0};
+        d = d3{sa, 0.0, ca};
+        t = o.x * (sa / P.c_ref);
+        w = fmax(0.0, ca) / (double)a.rays_per_elem;
+        region = S.start_region;
+        a.stk.last[ci] = 0;
       } else {
-        const double eta = S.c[st.sf.other] / S.c[region];
-        d = d * eta + st.f.nr * (eta * st.f.ci - st.f.ct);
-        w *= st.f.At / (1.0 - st.f.RE);
-        region = st.sf.other;
-        delta = true;
+        o = d3{a.qin.ox[iq], a.qin.oy[iq], a.qin.oz[iq]};
+        d = d3{a.qin.dx[iq], a.qin.dy[iq], a.qin.dz[iq]};
+        t = a.qin.t[iq];
+        w = a.qin.w[iq];
+        ci = a.qin.rid[iq];
+        const uint32_t m = a.qin.meta[iq];
+        region = m & 0xFF;
+        delta = (m >> 8) & 1u;
       }
-      const long q = wave_append(st.sf.kd > 0.0, a.stk.queue_count);
-      if (q >= 0) a.stk.queue[q] = ((unsigned long long)k << 32) | (unsigned long long)i;
-      o = st.x;
-      last = k;
+      const long at = (long)(k - 1) * cap + ci;
+      const Hit h = closest_hit(S, o, d, true, stk);
+      a.stk.rec[at] = StepRec{o.x, o.y, o.z, d.x, d.y, d.z, t, w, h.t,
+                              (uint32_t)region | ((uint32_t)delta << 8) | ((uint32_t)h.kind << 12),
+                              h.index};
+      if (h.kind == kHitArray) {
+        a.stk.last[ci] = k;
+      } else if (h.kind != kHitNone && k <= B) {
+        int txl;
+        uint32_t rid;
+        ray_of(a, ci, &txl, &rid);
+        const Step st = step_at(S, o, d, t, w, region, h);
+        t = st.tp;
+        w = st.watt;
+        const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
+        const double p_spec = (1.0 - st.sf.kd) * st.f.RE;
+        if (v.u0 < p_spec) {
+          d = d + st.f.nr * (2.0 * st.f.ci);
+          w *= st.f.Ar / st.f.RE;
+          delta = true;
+        } else if (v.u0 < st.f.RE) {
+          const d3 nn = st.f.nr;
+          const double sg = nn.z >= 0.0 ? 1.0 : -1.0;
+          const double aa = -1.0 / (sg + nn.z);
+          const double bb = nn.x * nn.y * aa;
+          const d3 b1{1.0 + sg * nn.x * nn.x * aa, sg * bb, -sg * nn.x};
+          const d3 b2{bb, sg + nn.y * nn.y * aa, -nn.y};
+          const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
+          d = b1 * (rr * cos(phi)) + b2 * (rr * sin(phi)) + nn * sqrt(1.0 - v.u2);
+          w *= st.f.Ar / st.f.RE;
+          delta = false;
+        } else {
+          const double eta = S.c[st.sf.other] / S.c[region];
+          d = d * eta + st.f.nr * (eta * st.f.ci - st.f.ct);
+          w *= st.f.At / (1.0 - st.f.RE);
+          region = st.sf.other;
+          delta = true;
+        }
+        o = st.x;
+        a.stk.last[ci] = k;
+        keep = true;
+        diffuse = st.sf.kd > 0.0;
+      }
     }
-    a.stk.last[i] = last;
+    const Slots sl = block_append2(keep, diffuse, &a.counts[k], scan);
+    const long slot = sl.a;
+    if (sl.b >= 0) a.stk.queue[(long)(k - 1) * cap + sl.b] = ci;
+    if (slot >= 0) {
+      a.qout.ox[slot] = o.x; a.qout.oy[slot] = o.y; a.qout.oz[slot] = o.z;
+      a.qout.dx[slot] = d.x; a.qout.dy[slot] = d.y; a.qout.dz[slot] = d.z;
+      a.qout.t[slot] = t; a.qout.w[slot] = w;
+      a.qout.rid[slot] = ci;
+      a.qout.meta[slot] = (uint32_t)region | ((uint32_t)delta << 8);
+    }
   }
 }
 
 // Phase 2 (one thread per queued interaction): the secondary ray towards
 // the element the interaction picked, with its parameter adjoints, and the
 // adjoints of its inputs (x, n_r, A_r, w_att, t') kept for phase 3.
+// Exclusive prefix over the diffuse interactions of the steps (high halves
+// of the counts): step k's entries are number queue_begin[k - 1] onwards.
+__global__ void k_replay_prefix(ReplayArgs a) {
+  if (threadIdx.x != 0) return;
+  unsigned long long run = 0;
+  a.stk.queue_begin[0] = 0;
+  for (int k = 1; k <= a.max_bounces; ++k) {
+    run += a.counts[k] >> 32;
+    a.stk.queue_begin[k] = run;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
-  const long n_q = (long)*a.stk.queue_count;
+  const int B = a.max_bounces;
+  const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
   if ((long)blockIdx.x * blockDim.x >= n_q) return;
   __shared__ SceneLDS S;
-  extern __shared__ double gsh[];      // n_params gradient sums, then the hierarchy stacks
+  extern __shared__ double gsh[];      // gradient sums (kGradCopies copies), crossing caches, hierarchy stacks
   load_scene(S, a.scene);
-  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x) gsh[j] = 0.0;
+  grad_clear(gsh, a.n_grad, a.grad_copies);
   __syncthreads();
-  double* leg_t = gsh + ((a.n_params + 1) & ~1) + threadIdx.x;
-  int* leg_h = (int*)(gsh + ((a.n_params + 1) & ~1) + kLegCache * blockDim.x) + threadIdx.x;
+  double* legs = gsh + a.grad_copies * grad_stride(a.n_grad);
+  double* leg_t = legs + threadIdx.x;
+  int* leg_h = (int*)(legs + kLegCache * blockDim.x) + threadIdx.x;
   int* stk = leg_h + kLegCache * blockDim.x;
-  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+  GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
+            a.scene.np_per_m, a.scene.vnormal, a.vadj};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
-    const unsigned long long e = a.stk.queue[q];
-    const long i = (long)(e & 0xFFFFFFFFull);
-    const int k = (int)(e >> 32);
+    // the step k with queue_begin[k - 1] <= q < queue_begin[k]
+    int k = 1, hi = B;
+    while (k < hi) {
+      const int mid = (k + hi + 1) >> 1;
+      if ((long)a.stk.queue_begin[mid - 1] <= q) k = mid; else hi = mid - 1;
+    }
+    const uint32_t i = a.stk.queue[(long)(k - 1) * cap + (q - (long)a.stk.queue_begin[k - 1])];
+    const long at = (long)(k - 1) * cap + i;
     int txl;
     uint32_t rid;
     ray_of(a, i, &txl, &rid);
-    const long at = (long)(k - 1) * cap + i;
-    double* F = a.stk.f + at;
-    const long fs = a.stk.n;
-    const d3 o{F[kFOx * fs], F[kFOy * fs], F[kFOz * fs]};
-    const d3 d{F[kFDx * fs], F[kFDy * fs], F[kFDz * fs]};
-    const uint32_t meta = a.stk.meta[at];
+    const StepRec R = a.stk.rec[at];
+    const d3 o{R.ox, R.oy, R.oz};
+    const d3 d{R.dx, R.dy, R.dz};
+    const uint32_t meta = R.meta;
     const int reg = meta & 0xFF;
-    const Hit h{(int)(meta >> 12), a.stk.hidx[at], F[kFL * fs]};
-    const Step st = step_at(S, o, d, F[kFT * fs], F[kFW * fs], reg, h);
+    const Hit h{(int)(meta >> 12), R.hidx, R.L};
+    const Step st = step_at(S, o, d, R.t, R.w, reg, h);
     const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
     const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
     ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
     d3 xb{0, 0, 0}, nrb{0, 0, 0};
     double Ab = 0.0, wb = 0.0, tb = 0.0;
     secondary_backward(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb);
-    F[kFXb * fs] = xb.x; F[kFYb * fs] = xb.y; F[kFZb * fs] = xb.z;
-    F[kFNxb * fs] = nrb.x; F[kFNyb * fs] = nrb.y; F[kFNzb * fs] = nrb.z;
-    F[kFAb * fs] = Ab; F[kFWb * fs] = wb; F[kFTb * fs] = tb;
+    a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x)
-    if (gsh[j] != 0.0) atomicAdd(&a.g_theta[j], gsh[j]);
+  grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
 }
 
 // Phase 3 (one thread per ray): the reverse sweep over the kept steps, with
@@ -503,11 +573,12 @@ __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
 __global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
   if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
-  extern __shared__ double gsh[];
+  extern __shared__ double gsh[];      // gradient sums, kGradCopies copies
   load_scene(S, a.scene);
-  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x) gsh[j] = 0.0;
+  grad_clear(gsh, a.n_grad, a.grad_copies);
   __syncthreads();
-  GradAcc G{gsh, a.scene.n_regions, a.scene.n_planes, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+  GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
+            a.scene.np_per_m, a.scene.vnormal, a.vadj};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -520,15 +591,14 @@ __global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
     double tb = 0.0, wb = 0.0;
     for (int k = a.stk.last[i]; k >= 1; --k) {
       const long at = (long)(k - 1) * cap + i;
-      const double* F = a.stk.f + at;
-      const long fs = a.stk.n;
-      const d3 o0{F[kFOx * fs], F[kFOy * fs], F[kFOz * fs]};
-      const d3 d0{F[kFDx * fs], F[kFDy * fs], F[kFDz * fs]};
-      const double t0 = F[kFT * fs], w0 = F[kFW * fs];
-      const uint32_t meta = a.stk.meta[at];
+      const StepRec R = a.stk.rec[at];
+      const uint32_t meta = R.meta;
+      const d3 o0{R.ox, R.oy, R.oz};
+      const d3 d0{R.dx, R.dy, R.dz};
+      const double t0 = R.t, w0 = R.w;
       const int reg = meta & 0xFF;
       const bool dl = (meta >> 8) & 1u;
-      const Hit h{(int)(meta >> 12), a.stk.hidx[at], F[kFL * fs]};
+      const Hit h{(int)(meta >> 12), R.hidx, R.L};
       const Step st = step_at(S, o0, d0, t0, w0, reg, h);
       const double L = st.L, c1 = S.c[reg], ar = S.a[reg];
       const double watt = st.watt;
@@ -597,11 +667,12 @@ __global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
           Ab += wb * watt / (1.0 - f.RE);
         }
         if (sf.kd > 0.0) {   // adjoints of the secondary ray's inputs (phase 2)
-          xb = xb + d3{F[kFXb * fs], F[kFYb * fs], F[kFZb * fs]};
-          nrb = nrb + d3{F[kFNxb * fs], F[kFNyb * fs], F[kFNzb * fs]};
-          Ab += F[kFAb * fs];
-          wattb += F[kFWb * fs];
-          tpb += F[kFTb * fs];
+          const StepAdj Q = a.stk.adj[at];
+          xb = xb + d3{Q.xb, Q.yb, Q.zb};
+          nrb = nrb + d3{Q.nxb, Q.nyb, Q.nzb};
+          Ab += Q.Ab;
+          wattb += Q.wb;
+          tpb += Q.tb;
         }
         cib += interface_backward(f, eta, reg, r2, S.Z[reg], S.Z[r2], c1, Ab, ctb, etab, G);
         // ci = -nr . d
@@ -625,8 +696,7 @@ __global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < a.n_params; j += blockDim.x)
-    if (gsh[j] != 0.0) atomicAdd(&a.g_theta[j], gsh[j]);
+  grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
 }
 
 // g_theta[q(m, j)] += sum over the vertices v of mesh m of vadj[v] phi_j(v):
@@ -649,26 +719,46 @@ __global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__
   if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(g_q + blockIdx.x, red[0]);
 }
 
+// g_theta[j] += sum of the kMaxReplayBlocks partial rows, one thread per entry.
+__global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ g_part, int n_grad,
+                                                     double* __restrict__ g_theta) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_grad) return;
+  double v = 0.0;
+  for (int b = 0; b < kMaxReplayBlocks; ++b) v += g_part[(long)b * n_grad + j];
+  g_theta[j] += v;
+}
+
 namespace {
-constexpr int kMaxReplayGrid = 2048;
 unsigned replay_grid(long n) {
   const long b = (n + 255) / 256;
-  return (unsigned)(b < 1 ? 1 : (b > kMaxReplayGrid ? kMaxReplayGrid : b));
+  return (unsigned)(b < 1 ? 1 : (b > kMaxReplayBlocks ? kMaxReplayBlocks : b));
 }
 size_t stack_lds(const ReplayArgs& a) {
   return a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0;
 }
-size_t grad_lds(const ReplayArgs& a) { return (size_t)((a.n_params + 1) & ~1) * sizeof(double); }
+size_t grad_lds(const ReplayArgs& a) {
+  return (size_t)a.grad_copies * ((a.n_grad + 1) & ~1) * sizeof(double);
+}
 }  // namespace
 
-void launch_replay_forward(const ReplayArgs& a, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_replay_forward, dim3(replay_grid(n)), dim3(256), stack_lds(a), s, a, n);
+void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_forward, dim3(replay_grid(n)), dim3(256), stack_lds(a), s, a, k, n);
 }
 
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s) {
   const size_t legs = (size_t)kLegCache * 256 * (sizeof(double) + sizeof(int));
   hipLaunchKernelGGL(k_replay_secondary, dim3(replay_grid(max_entries)), dim3(256),
                      grad_lds(a) + legs + stack_lds(a), s, a);
+}
+
+void launch_replay_prefix(const ReplayArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_replay_prefix, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, hipStream_t s) {
+  if (n_grad > 0)
+    hipLaunchKernelGGL(k_grad_reduce, dim3((n_grad + 255) / 256), dim3(256), 0, s, g_part, n_grad, g_theta);
 }
 
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s) {

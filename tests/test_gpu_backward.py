@@ -137,6 +137,29 @@ def test_vjp_ray_subsets_add_up(L, ctx):
     assert np.allclose(a, f, rtol=1e-9, atol=1e-12 * np.abs(f).max())
 
 
+def test_vjp_chunked_workspace(L, ctx):
+    """A workspace sized for 400 rays per transmit splits the replay into
+    chunks of 1200 rays (the last one ragged) whose per-step queues, records and gradient rows restart per
+    chunk: the result equals the one-chunk call up to the fp64 summation
+    order, on the layered phantom (planes and partly diffuse spheres)."""
+    import torch
+    wl = W.layered_phantom().replace(rays_per_elem=24, angles=np.radians([-7.0, 2.0, 9.0]),
+                                     tx_ids=np.arange(3, dtype=np.uint32))
+    p = wl.probe
+    g_rf = torch.tensor(smooth_field((wl.n_tx, p.n_elem, p.n_t), 11).astype(np.float32), device="cuda")
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    args = (ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces, g_rf)
+    one = L.us_simulate_rf_vjp(*args)
+    ws = L._workspace(L.us_simulate_rf_vjp_workspace_size(scene, probe, wl.n_tx, 400, wl.max_bounces), "cuda")
+    assert ws.numel() < L.us_simulate_rf_vjp_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx,
+                                                            wl.max_bounces)
+    chunked = L.us_simulate_rf_vjp(*args, workspace=ws)
+    torch.cuda.synchronize()
+    a, e = chunked.cpu().numpy(), one.cpu().numpy()
+    assert np.abs(e).max() > 0
+    assert np.allclose(a, e, rtol=1e-9, atol=1e-12 * np.abs(e).max())
+
+
 def test_full_chain_gradient_against_oracle(L, ctx):
     """Gradient of the B-mode MSE against a target rendered from seeded +-5 %
     parameters (34 perturbed), through bmode, beamform and the transport VJPs."""
