@@ -12,81 +12,187 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__device__ __forceinline__ unsigned bitrev(unsigned v, int bits) {
-  return __brev(v) >> (32 - bits);
-}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 
 constexpr int kFftThreads = 256;
 constexpr int kMaxFft = 8192;
+constexpr int kFftLoBits = 7;   // two-level twiddle table: 128 low and up to 64 high entries
 
-// In LDS: forward DIT on bit-reversed input -> natural-order spectrum.
-__device__ void fft_dit(float2* x, const float2* w, int n, int logn) {
-  for (int s = 1; s <= logn; ++s) {
-    const int half = 1 << (s - 1);
-    const int tw_stride = n >> s;
-    for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
-      const int pos = b & (half - 1);
-      const int i0 = ((b >> (s - 1)) << s) + pos;
-      const int i1 = i0 + half;
-      const float2 t = cmul(w[pos * tw_stride], x[i1]);
-      const float2 u = x[i0];
-      x[i0] = make_float2(u.x + t.x, u.y + t.y);
-      x[i1] = make_float2(u.x - t.x, u.y - t.y);
+// LDS index of element i: one float2 of padding every 16, so that the
+// stride-R writes of the first pass spread over the banks.
+__device__ __forceinline__ int fpad(int i) { return i + (i >> 4); }
+
+constexpr int brev_c(int i, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+constexpr int log2_c(int r) { return r <= 1 ? 0 : 1 + log2_c(r >> 1); }
+
+// w_n^e = exp(-2 pi i e / n), 0 <= e < n, as hi[e >> 7] * lo[e & 127].
+__device__ __forceinline__ float2 twid(const float2* lo, const float2* hi, int e) {
+  return cmul(hi[e >> kFftLoBits], lo[e & ((1 << kFftLoBits) - 1)]);
+}
+
+// In-register R-point DFT, b_s = sum_r a_r w_R^(r s): radix-2 DIT on the
+// bit-reversed registers, natural order out; w[t] = w_R^t, t < R / 2.
+template <int R>
+__device__ __forceinline__ void dft_regs(float2 (&a)[R], const float2 (&w)[R / 2 > 0 ? R / 2 : 1]) {
+  constexpr int kLog = log2_c(R);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = brev_c(i, kLog);
+    if (i < j) {
+      const float2 t = a[i];
+      a[i] = a[j];
+      a[j] = t;
     }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int half = 1; half < R; half <<= 1)
+#pragma unroll
+    for (int base = 0; base < R; base += 2 * half)
+#pragma unroll
+      for (int q = 0; q < half; ++q) {
+        const float2 t = q == 0 ? a[base + half] : cmul(a[base + q + half], w[q * (R / (2 * half))]);
+        const float2 u = a[base + q];
+        a[base + q] = cadd(u, t);
+        a[base + q + half] = csub(u, t);
+      }
+}
+
+enum FftIo : int {
+  kIoLds,          // LDS buffer (padded)
+  kIoRealIn,       // global real row
+  kIoComplexIn,    // global complex row
+  kIoLdsH,         // LDS, multiplied by the analytic-signal mask H and conjugated
+  kIoComplexOut,   // global complex row: conj(v) / n
+  kIoRealOut       // global real row: Re(v) / n
+};
+
+// One Stockham radix-R pass (decimation in time, natural order in and out)
+// over n points with L = product of the previous radices: butterfly j takes
+// x[j + r n / R], twists it by w_(L R)^(r k), k = j mod L, transforms and
+// writes y[(j / L) L R + k + s L]. Every thread first loads all its
+// butterflies, so the pass can run in place in LDS.
+template <int R, int kSrc, int kDst>
+__device__ __forceinline__ void fft_pass(float2* x, const void* gin, void* gout, int n, int L,
+                                         const float2* lo, const float2* hi) {
+  constexpr int kB = 32 / R > 0 ? 32 / R : 1;   // butterflies per thread (n <= 8192, 256 threads)
+  const int m = n / R, Ls = L * R, tw_step = n / Ls;
+  float2 a[kB][R];
+#pragma unroll
+  for (int bi = 0; bi < kB; ++bi) {
+    const int j = threadIdx.x + bi * kFftThreads;
+    if (j < m) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = j + r * m;
+        if (kSrc == kIoRealIn) a[bi][r] = make_float2(((const float*)gin)[i], 0.0f);
+        else if (kSrc == kIoComplexIn) a[bi][r] = ((const float2*)gin)[i];
+        else a[bi][r] = x[fpad(i)];
+      }
+    }
+  }
+  if (kSrc == kIoLds) __syncthreads();   // every read before the in-place writes
+  float2 w[R / 2 > 0 ? R / 2 : 1];
+#pragma unroll
+  for (int t = 0; t < R / 2; ++t) w[t] = twid(lo, hi, t * (n / R));
+  const float inv_n = 1.0f / (float)n;
+#pragma unroll
+  for (int bi = 0; bi < kB; ++bi) {
+    const int j = threadIdx.x + bi * kFftThreads;
+    if (j < m) {
+      const int k = j & (L - 1);
+      if (L > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) a[bi][r] = cmul(a[bi][r], twid(lo, hi, r * k * tw_step));
+      }
+      dft_regs<R>(a[bi], w);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        const int o = base + s * L;
+        const float2 v = a[bi][s];
+        if (kDst == kIoLds) {
+          x[fpad(o)] = v;
+        } else if (kDst == kIoLdsH) {
+          const float hm = (o == 0 || o == (n >> 1)) ? 1.0f : (o < (n >> 1) ? 2.0f : 0.0f);
+          x[fpad(o)] = make_float2(hm * v.x, -hm * v.y);
+        } else if (kDst == kIoComplexOut) {
+          ((float2*)gout)[o] = make_float2(v.x * inv_n, -v.y * inv_n);
+        } else {
+          ((float*)gout)[o] = v.x * inv_n;
+        }
+      }
+    }
+  }
+  if (kDst == kIoLds || kDst == kIoLdsH) __syncthreads();
+}
+
+template <int kSrc, int kDst>
+__device__ __forceinline__ void fft_pass_bits(int bits, float2* x, const void* gin, void* gout, int n, int L,
+                                              const float2* lo, const float2* hi) {
+  switch (bits) {   // 64 <= n <= 8192 split into two or three passes: 3 to 5 bits each
+    case 3: fft_pass<8, kSrc, kDst>(x, gin, gout, n, L, lo, hi); break;
+    case 4: fft_pass<16, kSrc, kDst>(x, gin, gout, n, L, lo, hi); break;
+    default: fft_pass<32, kSrc, kDst>(x, gin, gout, n, L, lo, hi); break;
   }
 }
 
-// In LDS: forward DIF on natural-order input -> bit-reversed spectrum.
-__device__ void fft_dif(float2* x, const float2* w, int n, int logn) {
-  for (int s = logn; s >= 1; --s) {
-    const int half = 1 << (s - 1);
-    const int tw_stride = n >> s;
-    for (int b = threadIdx.x; b < (n >> 1); b += blockDim.x) {
-      const int pos = b & (half - 1);
-      const int i0 = ((b >> (s - 1)) << s) + pos;
-      const int i1 = i0 + half;
-      const float2 u = x[i0], v = x[i1];
-      x[i0] = make_float2(u.x + v.x, u.y + v.y);
-      x[i1] = cmul(make_float2(u.x - v.x, u.y - v.y), w[pos * tw_stride]);
-    }
-    __syncthreads();
-  }
-}
-
-// Analytic-signal map T = F^-1 diag(H) F along one row, H = 1, 2..2, 1, 0..0.
-// kRealIn: input row is real (forward) or complex (adjoint); kRealOut: keep
-// the real part (adjoint: T is self-adjoint, g_rf = Re(T g_A)).
+// Analytic-signal map T = F^-1 diag(H) F along one row, H = 1, 2..2, 1, 0..0,
+// the inverse taken as a forward transform of the conjugate. kRealIn: input
+// row is real (forward) or complex (adjoint); kRealOut: keep the real part
+// (adjoint: T is self-adjoint, g_rf = Re(T g_A)). n = 2^logn is split into
+// two or three passes of radix <= 32, smallest first.
 template <bool kRealIn, bool kRealOut>
 __global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* out,
                                                           const float2* twiddle, int n, int logn) {
   extern __shared__ float2 lds[];
-  float2* x = lds;            // n
-  float2* w = lds + n;        // n / 2 twiddles exp(-2 pi i j / n)
+  float2* lo = lds;                          // w_n^i, i < 128
+  float2* hi = lds + (1 << kFftLoBits);       // w_n^(128 i), i < 64
+  float2* x = hi + 64;
   const long row = blockIdx.x;
-  for (int j = threadIdx.x; j < (n >> 1); j += blockDim.x) w[j] = twiddle[j];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    float2 v;
-    if (kRealIn) v = make_float2(((const float*)in)[row * n + j], 0.0f);
-    else v = ((const float2*)in)[row * n + j];
-    x[bitrev((unsigned)j, logn)] = v;
+  const int half = n >> 1;
+  // w_n^e from the table of the first half: w_n^(e + n/2) = -w_n^e
+  for (int i = threadIdx.x; i < (1 << kFftLoBits) + 64; i += blockDim.x) {
+    const bool is_lo = i < (1 << kFftLoBits);
+    const int e = is_lo ? i : (i - (1 << kFftLoBits)) << kFftLoBits;
+    float2 v = make_float2(1.0f, 0.0f);
+    if (e < n) {
+      v = twiddle[e < half ? e : e - half];
+      if (e >= half) v = make_float2(-v.x, -v.y);
+    }
+    lds[i] = v;
   }
   __syncthreads();
-  fft_dit(x, w, n, logn);
-  // X * H, conjugated so that a forward transform computes the inverse
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const float hm = (j == 0 || j == (n >> 1)) ? 1.0f : (j < (n >> 1) ? 2.0f : 0.0f);
-    const float2 v = x[j];
-    x[j] = make_float2(hm * v.x, -hm * v.y);
+  const int n_pass = (logn + 4) / 5;
+  int bits[3];
+  for (int p = 0, left = logn; p < n_pass; ++p) {   // even split, smallest first
+    bits[p] = left / (n_pass - p);
+    left -= bits[p];
   }
-  __syncthreads();
-  fft_dif(x, w, n, logn);
-  const float inv_n = 1.0f / (float)n;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const float2 v = x[bitrev((unsigned)j, logn)];
-    if (kRealOut) ((float*)out)[row * n + j] = v.x * inv_n;
-    else ((float2*)out)[row * n + j] = make_float2(v.x * inv_n, -v.y * inv_n);
+  const void* src = kRealIn ? (const void*)((const float*)in + row * n) : (const void*)((const float2*)in + row * n);
+  void* dst = kRealOut ? (void*)((float*)out + row * n) : (void*)((float2*)out + row * n);
+  constexpr int kIn = kRealIn ? kIoRealIn : kIoComplexIn;
+  constexpr int kOut = kRealOut ? kIoRealOut : kIoComplexOut;
+  // forward transform, mask and conjugate on the last write
+  int L = 1;
+  fft_pass_bits<kIn, kIoLds>(bits[0], x, src, nullptr, n, L, lo, hi);
+  L <<= bits[0];
+  if (n_pass == 3) {
+    fft_pass_bits<kIoLds, kIoLds>(bits[1], x, nullptr, nullptr, n, L, lo, hi);
+    L <<= bits[1];
   }
+  fft_pass_bits<kIoLds, kIoLdsH>(bits[n_pass - 1], x, nullptr, nullptr, n, L, lo, hi);
+  // transform of the conjugate, conjugated and scaled on the way out
+  L = 1;
+  for (int p = 0; p < n_pass - 1; ++p) {
+    fft_pass_bits<kIoLds, kIoLds>(bits[p], x, nullptr, nullptr, n, L, lo, hi);
+    L <<= bits[p];
+  }
+  fft_pass_bits<kIoLds, kOut>(bits[n_pass - 1], x, nullptr, dst, n, L, lo, hi);
 }
 
 // Delay-and-sum, one pixel per thread, threads along z. The fractional
@@ -402,11 +508,15 @@ int log2_exact(int n) {
 
 }  // namespace
 
+size_t analytic_lds(int n_t) {
+  return (size_t)((1 << kFftLoBits) + 64 + n_t + n_t / 16 + 1) * sizeof(float2);
+}
+
 int launch_analytic(const float* rf, float2* A, const float2* twiddle, int n_t, long n_rows,
                     hipStream_t s) {
   const int logn = log2_exact(n_t);
   if (logn < 6 || n_t > kMaxFft) return -1;
-  const size_t lds = (size_t)(n_t + n_t / 2) * sizeof(float2);
+  const size_t lds = analytic_lds(n_t);
   hipLaunchKernelGGL((k_analytic<true, false>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
                      (const void*)rf, (void*)A, twiddle, n_t, logn);
   return 0;
@@ -416,7 +526,7 @@ int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddl
                             long n_rows, hipStream_t s) {
   const int logn = log2_exact(n_t);
   if (logn < 6 || n_t > kMaxFft) return -1;
-  const size_t lds = (size_t)(n_t + n_t / 2) * sizeof(float2);
+  const size_t lds = analytic_lds(n_t);
   hipLaunchKernelGGL((k_analytic<false, true>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
                      (const void*)g_A, (void*)g_rf, twiddle, n_t, logn);
   return 0;

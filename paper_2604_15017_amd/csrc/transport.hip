@@ -274,32 +274,61 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
 
 // rf[row][k] = sum_{|m| <= M} h[row][k - m] s[m]  (Eq. axial_sig as a FIR on
 // the deposit histogram; h is zero outside [0, n_t)). One block computes a
-// tile of kPulseTile outputs of one row from an LDS copy of the tile + halo.
-constexpr int kPulseTile = 1024;
+// tile of kPulseTile outputs of one row from an LDS copy of the tile + halo;
+// each thread keeps kPulseR consecutive outputs in registers and slides a
+// window of 2 kPulseR inputs over the taps, so that one LDS read feeds
+// kPulseR multiply-adds (the FIR is then bound by fp32 FMA issue, not LDS).
+constexpr int kPulseR = 8;
+constexpr int kPulseTile = 256 * kPulseR;
 constexpr int kMaxTaps = 512;
 
+template <bool kVec>
 __global__ __launch_bounds__(256) void k_pulse(const float* __restrict__ h, float* __restrict__ rf,
                                                const float* __restrict__ taps, int M, int n_t,
                                                int tiles_per_row) {
-  __shared__ float sh[kPulseTile + 2 * kMaxTaps];
-  __shared__ float st[2 * kMaxTaps + 1];
+  // x[i] = h[k0 - M + i]; c[q] = s[M - q] = taps[2M - q], zero-padded to Tp
+  __shared__ __align__(16) float x[kPulseTile + 2 * kMaxTaps];
+  __shared__ __align__(16) float c[2 * kMaxTaps];
   const long row = blockIdx.x / tiles_per_row;
   const int k0 = (blockIdx.x % tiles_per_row) * kPulseTile;
   const float* hr = h + row * (long)n_t;
-  const int span = kPulseTile + 2 * M;
-  for (int j = threadIdx.x; j < span; j += blockDim.x) {
+  const int T = 2 * M + 1, Tp = (T + kPulseR - 1) / kPulseR * kPulseR;
+  for (int j = threadIdx.x; j < kPulseTile + Tp; j += blockDim.x) {
     const int src = k0 - M + j;
-    sh[j] = (src >= 0 && src < n_t) ? hr[src] : 0.0f;
+    x[j] = (src >= 0 && src < n_t) ? hr[src] : 0.0f;
   }
-  for (int j = threadIdx.x; j < 2 * M + 1; j += blockDim.x) st[j] = taps[j];
+  for (int j = threadIdx.x; j < Tp; j += blockDim.x) c[j] = j < T ? taps[2 * M - j] : 0.0f;
   __syncthreads();
-  for (int j = threadIdx.x; j < kPulseTile; j += blockDim.x) {
-    const int kk = k0 + j;
-    if (kk >= n_t) break;
-    // output kk reads h[kk - m] = sh[j + M - m], m = -M..M
-    float acc = 0.0f;
-    for (int m = 0; m <= 2 * M; ++m) acc = fmaf(sh[j + 2 * M - m], st[m], acc);
-    rf[row * (long)n_t + kk] = acc;
+  // output k0 + b + r = sum_q x[b + r + q] c[q]
+  const int b = threadIdx.x * kPulseR;
+  float acc[kPulseR], v[2 * kPulseR];
+#pragma unroll
+  for (int r = 0; r < kPulseR; ++r) {
+    acc[r] = 0.0f;
+    v[r] = x[b + r];
+  }
+  for (int q0 = 0; q0 < Tp; q0 += kPulseR) {
+#pragma unroll
+    for (int r = 0; r < kPulseR; ++r) v[kPulseR + r] = x[b + q0 + kPulseR + r];
+#pragma unroll
+    for (int qq = 0; qq < kPulseR; ++qq) {
+      const float cq = c[q0 + qq];
+#pragma unroll
+      for (int r = 0; r < kPulseR; ++r) acc[r] = fmaf(v[r + qq], cq, acc[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < kPulseR; ++r) v[r] = v[kPulseR + r];
+  }
+  const int kk = k0 + b;
+  float* out = rf + row * (long)n_t + kk;
+  if (kVec && kk + kPulseR <= n_t) {
+#pragma unroll
+    for (int r = 0; r < kPulseR; r += 4)
+      *reinterpret_cast<float4*>(out + r) = make_float4(acc[r], acc[r + 1], acc[r + 2], acc[r + 3]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kPulseR; ++r)
+      if (kk + r < n_t) out[r] = acc[r];
   }
 }
 
@@ -343,8 +372,14 @@ int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, l
                  hipStream_t s) {
   if (M > kMaxTaps - 1) return -1;
   const int tiles = (n_t + kPulseTile - 1) / kPulseTile;
-  hipLaunchKernelGGL(k_pulse, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, h, rf, taps, M,
-                     n_t, tiles);
+  // 16-byte stores when every row starts 16-byte aligned
+  const bool vec = n_t % 4 == 0 && ((uintptr_t)rf & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_pulse<true>, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, h, rf, taps, M,
+                       n_t, tiles);
+  else
+    hipLaunchKernelGGL(k_pulse<false>, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, h, rf, taps, M,
+                       n_t, tiles);
   return 0;
 }
 

@@ -204,6 +204,28 @@ def test_beamform_and_bmode_on_oracle_rf(L, ctx, which):
     assert err <= DB_TOL
 
 
+@pytest.mark.parametrize("n_t", [64, 128, 256, 512, 1024, 2048, 8192])
+def test_analytic_signal_at_every_transform_size(L, ctx, n_t):
+    """The analytic signal splits n_t = 2^6..2^13 into two or three register
+    passes of radix 8-32; each split is checked through us_beamform on seeded
+    random channels (3 transmits, 2 rows of pixels near the bottom of the
+    record so that late samples are read) against the oracle."""
+    import dataclasses
+    wl = W.two_layer()
+    p = dataclasses.replace(wl.probe, n_t=n_t)
+    depth = 0.45 * n_t / p.fs * p.c_ref   # pixels reach the last quarter of the record
+    g = W.Grid.span(32, 24, -4e-3, 4e-3, 0.2 * depth, depth)
+    wl = wl.replace(probe=p, grid=g, angles=np.radians([-6.0, 0.0, 5.0]),
+                    tx_ids=np.arange(3, dtype=np.uint32))
+    rng = np.random.default_rng(n_t)
+    rf = rng.standard_normal((3, p.n_elem, n_t)).astype(np.float32)
+    I = oracle.das(oracle.analytic(rf.astype(np.float64)), p, g, wl.angles)
+    Ig, _ = _gpu_image(L, ctx, wl, rf)
+    rel = rel_l2(Ig, I)
+    print(f"n_t {n_t}: iq rel-L2 {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
 def test_tiled_and_gather_beamformers_on_a_large_grid(L, ctx):
     """The 512 x 1024 anatomy grid (192 elements, 21 transmits) is beamformed
     by the LDS-tiled kernel; a ragged 61 x 133 window of it, beamformed alone,
