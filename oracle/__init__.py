@@ -102,6 +102,7 @@ def _load():
         lib.oracle_cosine_dir.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
         lib.oracle_directivity.restype = ctypes.c_double
         lib.oracle_directivity.argtypes = [vp, ctypes.c_double]
+        lib.oracle_glossy.argtypes = [vp, vp] + [ctypes.c_double] * 7 + [vp]
         _lib = lib
     return _lib
 
@@ -151,8 +152,10 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
            (returned as .probs), or reuse given ones; finite differences of the
            estimator with its sampling density held fixed need this.
     scene.meshes (optional): closed triangle meshes with attributes vertices,
-           triangles, normals, basis, region_in, region_out, kd; their
-           displacement coefficients follow the spheres in theta.
+           triangles, normals, basis, region_in, region_out, kd.
+    theta layout: (c, Z, alpha) per region, plane depths, (x, y, z, r) per
+           sphere, GGX roughness per plane, per sphere and per mesh, then the
+           mesh displacement coefficients [mesh][basis].
     mesh_bruteforce: test every triangle instead of walking the hierarchy.
     """
     lib = _load()
@@ -180,6 +183,12 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
                        _ptr(arr[0]), _ptr(arr[1]), _ptr(arr[2]), _ptr(arr[3]), _ptr(arr[4]), _ptr(arr[5]))
     else:
         mesh_fields = (0, 0, None, None, 0, 0, None, None, None, None, None, None)
+    n_m = len(meshes)
+    n_b = int(meshes[0].basis.shape[1]) if meshes else 0
+    n_exp = (3 * scene.regions.shape[0] + 2 * scene.planes.shape[0] + 5 * scene.spheres.shape[0]
+             + n_m + n_m * n_b)
+    if th.shape != (n_exp,):
+        raise ValueError(f"theta has {th.shape} entries, the scene needs {n_exp}")
     sd = _Scene(int(scene.regions.shape[0]), int(scene.planes.shape[0]),
                 int(scene.spheres.shape[0]), _ptr(pr), _ptr(pk), _ptr(sr), _ptr(sk),
                 int(scene.start_region), *mesh_fields, 1 if mesh_bruteforce else 0)
@@ -262,6 +271,15 @@ def cosine_dir(n, u1, u2):
     out = np.zeros(3)
     _load().oracle_cosine_dir(_ptr(n), float(u1), float(u2), _ptr(out))
     return out
+
+
+def glossy(w, n, c1, Z1, c2, Z2, rho, u1, u2):
+    """Rough (GGX) reflection of w at normal n: (direction, estimator factor, ok)."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    out = np.zeros(5)
+    _load().oracle_glossy(_ptr(w), _ptr(n), c1, Z1, c2, Z2, float(rho), float(u1), float(u2), _ptr(out))
+    return out[:3], out[3], bool(out[4])
 
 
 def directivity(probe, cos_a: float) -> float:

@@ -274,6 +274,7 @@ struct Model {
   std::vector<T> c, Z, a;               // per region: speed, impedance, amplitude attenuation [Np/m]
   std::vector<T> pz;                    // plane depths
   std::vector<V3<T>> sc; std::vector<T> sr;  // sphere centres, radii
+  std::vector<T> rho_p, rho_s, rho_m;   // GGX roughness of planes, spheres, meshes
   std::vector<T> q;                     // mesh displacement coefficients [n_meshes][n_basis]
   std::vector<double> vpos;             // current vertex positions (values) [V][3]
   Bvh bvh;
@@ -419,18 +420,20 @@ Hit<T> closest_hit(const Model<T>& m, const V3<T>& o, const V3<T>& w, bool with_
 // Geometric normal of the surface that was hit, and the region across it.
 template <class T>
 void surface_at(const Model<T>& m, const Hit<T>& h, const V3<T>& x, int region,
-                V3<T>* n, int* other, double* kd) {
+                V3<T>* n, int* other, double* kd, T* rho = nullptr) {
   if (h.kind == HIT_PLANE) {
     *n = {T(0.0), T(0.0), T(1.0)};
     const int32_t* pr = m.sd->plane_regions + 2 * h.index;
     *other = region == pr[0] ? pr[1] : pr[0];
     *kd = m.sd->plane_kd[h.index];
+    if (rho) *rho = m.rho_p[h.index];
   } else if (h.kind == HIT_SPHERE) {
     T inv_r = 1.0 / m.sr[h.index];
     *n = (x - m.sc[h.index]) * inv_r;
     const int32_t* sr = m.sd->sphere_regions + 2 * h.index;
     *other = region == sr[0] ? sr[1] : sr[0];
     *kd = m.sd->sphere_kd[h.index];
+    if (rho) *rho = m.rho_s[h.index];
   } else {   // mesh triangle: flat face normal
     V3<T> zero{T(0.0), T(0.0), T(1.0)};
     tri_geometry(m, h.index, x, zero, (T*)nullptr, n);
@@ -438,6 +441,7 @@ void surface_at(const Model<T>& m, const Hit<T>& h, const V3<T>& x, int region,
     const int32_t* mr = m.sd->mesh_regions + 2 * mesh;
     *other = region == mr[0] ? mr[1] : mr[0];
     *kd = m.sd->mesh_kd[mesh];
+    if (rho) *rho = m.rho_m[mesh];
   }
 }
 
@@ -498,6 +502,48 @@ V3<T> cosine_dir(const V3<T>& n, double u1, double u2) {
   double phi = 2.0 * PI * u1, rr = std::sqrt(u2);
   double lx = rr * std::cos(phi), ly = rr * std::sin(phi), lz = std::sqrt(1.0 - u2);
   return b1 * T(lx) + b2 * T(ly) + n * T(lz);
+}
+
+// Rough specular reflection (Eq. GGX_PDF). Reading: the specular share of
+// the reflection is mirrored about a microfacet normal h drawn with density
+// D(h) (n.h) (GGX with roughness rho: tan^2 theta_h = rho^2 u1 / (1 - u1),
+// azimuth 2 pi u2, in the same orthonormal frame about n_r as the
+// Lambertian lobe); the path weight takes the microfacet estimator factor
+//   G1(n.i) G1(n.o) |i.h| / ((n.i) (n.h)),
+//   G1(c) = 2 c / (c + sqrt(rho^2 + (1 - rho^2) c^2))   (Smith, separable),
+// i = -w the direction towards the source, o the reflected direction. The
+// Fresnel amplitude and the reflect / refract / diffuse choice stay those of
+// the macroscopic normal. A microfacet facing away from i, or an o below the
+// surface, ends the path (factor 0). rho = 0 gives h = n_r and the mirror.
+template <class T>
+struct Glossy { V3<T> dir; T g; bool ok; };
+
+template <class T>
+T smith_g1(const T& c, const T& rho) {
+  return 2.0 * c / (c + sqrt(rho * rho + (1.0 - rho * rho) * c * c));
+}
+
+template <class T>
+Glossy<T> glossy_reflect(const V3<T>& w, const Interface<T>& f, const T& rho, double u1, double u2) {
+  const V3<T>& n = f.n_r;
+  double sgn = val(n.z) >= 0.0 ? 1.0 : -1.0;
+  T a = -1.0 / (sgn + n.z);
+  T b = n.x * n.y * a;
+  V3<T> b1{1.0 + sgn * n.x * n.x * a, sgn * b, -sgn * n.x};
+  V3<T> b2{b, sgn + n.y * n.y * a, -n.y};
+  T tan_h = rho * std::sqrt(u1 / (1.0 - u1));   // rho >= 0; smooth in rho at 0
+  T cos_h = 1.0 / sqrt(1.0 + tan_h * tan_h);
+  T sin_h = tan_h * cos_h;
+  double phi = 2.0 * PI * u2;
+  V3<T> h = b1 * (sin_h * std::cos(phi)) + b2 * (sin_h * std::sin(phi)) + n * cos_h;
+  Glossy<T> out;
+  T wh = dot(w, h);
+  out.dir = w - h * (2.0 * wh);
+  T cos_o = dot(n, out.dir);
+  out.ok = val(wh) < 0.0 && val(cos_o) > 0.0;
+  if (!out.ok) { out.g = T(0.0); return out; }
+  out.g = smith_g1(f.cos_i, rho) * smith_g1(cos_o, rho) * (-wh) / (f.cos_i * cos_h);
+  return out;
 }
 
 // Receive directivity (Eq. cutoff), angle alpha = acos(n . w_i).
@@ -650,8 +696,8 @@ void trace_path(const Model<T>& m, Sink<T>& sink, int txi, int64_t ray, uint64_t
     }
     if (k > rd->max_bounces) break;         // only an array hit counts after the last interaction
 
-    V3<T> n; int other; double kd;
-    surface_at(m, h, x, region, &n, &other, &kd);
+    V3<T> n; int other; double kd; T rho;
+    surface_at(m, h, x, region, &n, &other, &kd, &rho);
     Interface<T> f = interface_at(w, n, m.c[region], m.Z[region], m.c[other], m.Z[other]);
     U4 v = draw(rd->seed, (uint64_t)ray, tx_id, (uint32_t)k);
 
@@ -672,10 +718,15 @@ void trace_path(const Model<T>& m, Sink<T>& sink, int txi, int64_t ray, uint64_t
     }
     double p_spec = (1.0 - kd) * RE;
     uint32_t branch;
+    bool ends = false;
     if (v.u[0] < p_spec) {
-      w = reflect_dir(w, f);
-      wt = wt * f.Ar / RE;
-      last_delta = true; branch = 0;
+      // glossy about a GGX microfacet (the mirror when rho = 0); a glossy
+      // path deposits on the array like a specular one
+      Glossy<T> gl = glossy_reflect(w, f, rho, v.u[1], v.u[2]);
+      w = gl.dir;
+      wt = wt * f.Ar / RE * gl.g;
+      ends = !gl.ok;
+      last_delta = true; branch = ends ? 3 : 0;
     } else if (v.u[0] < RE) {
       w = cosine_dir(f.n_r, v.u[1], v.u[2]);
       wt = wt * f.Ar / RE;
@@ -688,6 +739,7 @@ void trace_path(const Model<T>& m, Sink<T>& sink, int txi, int64_t ray, uint64_t
       last_delta = true; branch = 2;
     }
     ph.add(EV_BRANCH, k, branch | (f.tir ? 0x10u : 0u));
+    if (ends) break;
     o = x;
   }
   if (hash_out) *hash_out = ph.h;
@@ -716,6 +768,12 @@ void build_model(Model<T>& m, const OrSceneDesc* sd, const OrProbeDesc* pd, cons
     m.sr.push_back(th[off + 4 * s + 3]);
   }
   off += 4 * sd->n_spheres;
+  for (int p = 0; p < sd->n_planes; ++p) m.rho_p.push_back(th[off + p]);
+  off += sd->n_planes;
+  for (int s = 0; s < sd->n_spheres; ++s) m.rho_s.push_back(th[off + s]);
+  off += sd->n_spheres;
+  for (int j = 0; j < sd->n_meshes; ++j) m.rho_m.push_back(th[off + j]);
+  off += sd->n_meshes;
   if (sd->n_meshes > 0) {
     for (int j = 0; j < sd->n_meshes * sd->n_basis; ++j) m.q.push_back(th[off + j]);
     m.vpos.resize(3 * sd->n_vertices);
@@ -727,8 +785,11 @@ void build_model(Model<T>& m, const OrSceneDesc* sd, const OrProbeDesc* pd, cons
   }
 }
 
+// theta = [(c, Z, alpha) per region, plane depths, (x, y, z, r) per sphere,
+//          roughness per plane, per sphere, per mesh, mesh basis coefficients]
 int n_params_of(const OrSceneDesc* sd) {
-  return 3 * sd->n_regions + sd->n_planes + 4 * sd->n_spheres + sd->n_meshes * sd->n_basis;
+  return 3 * sd->n_regions + sd->n_planes + 4 * sd->n_spheres +
+         (sd->n_planes + sd->n_spheres + sd->n_meshes) + sd->n_meshes * sd->n_basis;
 }
 
 struct Result {
@@ -870,5 +931,15 @@ void oracle_cosine_dir(const double* n, double u1, double u2, double* out) {
 }
 
 double oracle_directivity(const OrProbeDesc* pd, double cos_a) { return directivity(pd, cos_a); }
+
+// Rough reflection of w at normal n between media (c1, Z1) and (c2, Z2):
+// out = reflected direction (3), estimator factor g, ok flag.
+void oracle_glossy(const double* w, const double* n, double c1, double Z1, double c2, double Z2,
+                   double rho, double u1, double u2, double* out) {
+  V3<double> wv{w[0], w[1], w[2]}, nv{n[0], n[1], n[2]};
+  Interface<double> f = interface_at(wv, nv, c1, Z1, c2, Z2);
+  Glossy<double> g = glossy_reflect(wv, f, rho, u1, u2);
+  out[0] = g.dir.x; out[1] = g.dir.y; out[2] = g.dir.z; out[3] = g.g; out[4] = g.ok ? 1.0 : 0.0;
+}
 
 }  // extern "C"

@@ -67,6 +67,15 @@ class Scene:
     start_region: int = 0        # region just below the array face
     meshes: list = dataclasses.field(default_factory=list)   # closed triangle meshes (Mesh)
     mesh_q: Optional[np.ndarray] = None   # (n_meshes, n_basis) displacement coefficients [m]
+    plane_rough: Optional[np.ndarray] = None    # (Pl,) GGX roughness (Eq. GGX_PDF); None: 0
+    sphere_rough: Optional[np.ndarray] = None   # (S,) GGX roughness; None: 0
+
+    def roughness(self) -> np.ndarray:
+        """Roughness of every plane, then sphere, then mesh (theta's order)."""
+        rp = np.zeros(self.n_planes) if self.plane_rough is None else np.asarray(self.plane_rough, np.float64)
+        rs = np.zeros(self.n_spheres) if self.sphere_rough is None else np.asarray(self.sphere_rough, np.float64)
+        rm = np.array([getattr(m, "rough", 0.0) for m in self.meshes], dtype=np.float64)
+        return np.concatenate([rp.reshape(-1), rs.reshape(-1), rm])
 
     @property
     def n_meshes(self) -> int:
@@ -94,27 +103,46 @@ class Scene:
         return int(self.spheres.shape[0])
 
     @property
+    def n_surfaces(self) -> int:
+        return self.n_planes + self.n_spheres + self.n_meshes
+
+    @property
+    def rough_offset(self) -> int:
+        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres
+
+    @property
     def n_params(self) -> int:
-        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres + self.n_meshes * self.n_basis
+        return self.rough_offset + self.n_surfaces + self.n_meshes * self.n_basis
 
     def theta(self) -> np.ndarray:
+        """[(c, Z, alpha) per region, plane depths, (x, y, z, r) per sphere,
+        roughness per plane, sphere and mesh, mesh basis coefficients]."""
         return np.concatenate([self.regions.reshape(-1), self.planes.reshape(-1),
-                               self.spheres.reshape(-1), self.q().reshape(-1)]).astype(np.float64)
+                               self.spheres.reshape(-1), self.roughness(),
+                               self.q().reshape(-1)]).astype(np.float64)
 
     def with_theta(self, theta: np.ndarray) -> "Scene":
         theta = np.asarray(theta, dtype=np.float64)
         assert theta.shape == (self.n_params,)
-        r, p, s = self.n_regions, self.n_planes, self.n_spheres
-        o = 3 * r + p + 4 * s
+        r, p, s, m = self.n_regions, self.n_planes, self.n_spheres, self.n_meshes
+        o = self.rough_offset
+        rough = theta[o:o + p + s + m]
+        meshes = [dataclasses.replace(mm, rough=float(rough[p + s + k])) for k, mm in enumerate(self.meshes)]
         return dataclasses.replace(
             self,
             regions=theta[:3 * r].reshape(r, 3).copy(),
             planes=theta[3 * r:3 * r + p].copy(),
             spheres=theta[3 * r + p:o].reshape(s, 4).copy(),
-            mesh_q=theta[o:].reshape(self.n_meshes, self.n_basis).copy() if self.meshes else None)
+            plane_rough=rough[:p].copy(), sphere_rough=rough[p:p + s].copy(), meshes=meshes,
+            mesh_q=theta[o + p + s + m:].reshape(m, self.n_basis).copy() if self.meshes else None)
 
     def idx_mesh(self, m: int, j: int) -> int:
-        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres + m * self.n_basis + j
+        return self.rough_offset + self.n_surfaces + m * self.n_basis + j
+
+    def idx_rough(self, kind: str, k: int) -> int:
+        """Roughness of plane / sphere / mesh k."""
+        base = {"plane": 0, "sphere": self.n_planes, "mesh": self.n_planes + self.n_spheres}[kind]
+        return self.rough_offset + base + k
 
     # index helpers for the flat parameter vector
     def idx_region(self, k: int, which: str) -> int:
@@ -243,6 +271,20 @@ def layered_phantom(seed: int = 1, rays_per_tx: int = 1 << 20, n_tx: int = 11) -
                     rays_per_elem=rays_per_tx // probe.n_elem, max_bounces=8)
 
 
+ROUGH_STREAM_TAG = 4
+
+
+def rough_layered_phantom(seed: int = 1, rays_per_tx: int = 1 << 20, n_tx: int = 11) -> Workload:
+    """The layered phantom with rough interfaces (Eq. GGX_PDF): plane
+    roughness U[0.02, 0.15], sphere roughness U[0.1, 0.4], seeded."""
+    wl = layered_phantom(seed, rays_per_tx, n_tx)
+    rng = np.random.Generator(np.random.Philox(key=[seed, ROUGH_STREAM_TAG]))
+    sc = wl.scene
+    scene = dataclasses.replace(sc, plane_rough=rng.uniform(0.02, 0.15, sc.n_planes),
+                                sphere_rough=rng.uniform(0.1, 0.4, sc.n_spheres))
+    return wl.replace(name="rough_layered_phantom", scene=scene)
+
+
 def perturbed_indices(scene: Scene) -> List[int]:
     """The 34 perturbed parameters: (c, Z, alpha) of every non-water region, then
     every sphere's depth and radius."""
@@ -363,6 +405,7 @@ class Mesh:
     region_in: int
     region_out: int
     kd: float
+    rough: float = 0.0        # GGX roughness (Eq. GGX_PDF)
 
 
 def _orient_outward(v, f, inside_point):

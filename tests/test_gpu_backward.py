@@ -183,7 +183,7 @@ def test_full_chain_gradient_against_oracle(L, ctx):
     loss = float(((B - Bref) ** 2).mean())
     assert loss == pytest.approx(ref["loss"], rel=1e-3)
     compare_grads(g.cpu().numpy(), ref["g_theta"], wl.scene.theta(), "full chain (34 perturbed)", idx)
-    compare_grads(g.cpu().numpy(), ref["g_theta"], wl.scene.theta(), "full chain (all 50)")
+    compare_grads(g.cpu().numpy(), ref["g_theta"], wl.scene.theta(), f"full chain (all {wl.scene.n_params})")
 
 
 def test_autograd_matches_explicit_chain(L, ctx):

@@ -88,7 +88,7 @@ def test_planar_echo_oblique_steering(deg):
     wl = W.two_layer(rays_per_elem=1 << 10)
     th = math.radians(deg)
     d = 20e-3
-    sc = wl.scene.with_theta(np.r_[wl.scene.regions.reshape(-1), [d]])
+    sc = wl.scene.with_theta(np.r_[wl.scene.regions.reshape(-1), [d], [0.0]])   # depth, roughness
     p = wl.probe
     tr = oracle.trace(sc, p, [th], [3], 11, wl.rays_per_elem, 4)
     n = p.n_elem * wl.rays_per_elem

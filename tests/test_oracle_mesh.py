@@ -78,7 +78,11 @@ def test_box_mesh_equals_two_planes():
     ga = oracle.trace(planes, p, wl.angles, wl.tx_ids, 1, 64, 5, g_h=g_h).g_theta
     gb = oracle.trace(box, p, wl.angles, wl.tx_ids, 1, 64, 5, g_h=g_h).g_theta
     assert np.allclose(gb[:6], ga[:6], rtol=1e-9, atol=1e-12 * np.abs(ga).max())
-    assert gb[6] == pytest.approx(-ga[6], rel=1e-9)
+    assert gb[box.idx_mesh(0, 0)] == pytest.approx(-ga[planes.idx_plane(0)], rel=1e-9)
+    # one roughness for both faces of the box: the sum of the two planes' roughness gradients
+    g_rho = ga[planes.idx_rough("plane", 0)] + ga[planes.idx_rough("plane", 1)]
+    assert abs(g_rho) > 1e-6 * np.abs(ga).max()
+    assert gb[box.idx_rough("mesh", 0)] == pytest.approx(g_rho, rel=1e-9)
 
 
 def test_mesh_displacement_gradient_matches_finite_differences():
