@@ -24,8 +24,10 @@
  *      iq        float  [n_x][n_z][2]  (real, imaginary)
  *      bmode     float  [n_x][n_z]     (dB, in [-dr_db, 0])
  *      theta     double [n_params]: (c, Z, alpha) per region, then plane
- *                depths, then (cx, cy, cz, r) per sphere, then the
- *                displacement coefficients q[mesh][j] of the meshes
+ *                depths, then (cx, cy, cz, r) per sphere, then the GGX
+ *                roughness of every plane, every sphere and every mesh
+ *                (>= 0; 0 is a mirror), then the displacement coefficients
+ *                q[mesh][j] of the meshes
  */
 #ifndef USRT_H
 #define USRT_H
@@ -68,6 +70,11 @@ typedef struct us_probe_desc {
  * {region above, region below}; sphere_regions[k] and mesh_regions[m] =
  * {inside, outside}; kd = fraction of the reflected energy scattered into the
  * Lambertian lobe; start_region = region at the array face. Host arrays.
+ * Roughness rho (Eq. GGX_PDF): the specular share (1 - kd) of the reflection
+ * is mirrored about a microfacet normal drawn from the GGX distribution with
+ * density D(m) (n.m), weighted by the Smith-masked microfacet estimator
+ * G1(i) G1(o) |i.m| / ((n.i) (n.m)); a glossy path reaches the elements
+ * directly (no secondary ray), a reflection below the surface ends it.
  *
  * Meshes (n_meshes = 0: none, and the mesh pointers may be NULL): the
  * vertices of all meshes are concatenated in mesh order ([n_vertices][3]
@@ -131,7 +138,7 @@ int us_scene_destroy(us_scene* scene);
 int us_scene_set_params(us_scene* scene, const double* theta_dev, int32_t n_params, void* stream);
 
 /* Forward transport, Sec. 2.3 (emission, traversal with Snell reflection /
- * refraction / Lambertian backscatter, attenuation, receiver-directed
+ * refraction / Lambertian backscatter / GGX glossy reflection, attenuation, receiver-directed
  * secondary rays, time-of-flight deposit with a linear tent, Eq. axial_sig
  * pulse filter). Traces rays [ray_begin, ray_begin + ray_count) of each of
  * the n_tx transmits (ray id = element * rays_per_elem + j, Philox4x64-10

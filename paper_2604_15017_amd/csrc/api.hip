@@ -207,8 +207,14 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_CHECK(d->n_vertices >= 3 && d->n_vertices < (1L << 30), "us_scene_upload: n_vertices must be in [3, 2^30)");
     US_CHECK(d->n_triangles >= 1 && d->n_triangles < (1L << 27), "us_scene_upload: n_triangles must be in [1, 2^27)");
   }
-  const int q_offset = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
+  // theta = [regions, plane depths, spheres, roughness (planes, spheres,
+  // meshes), mesh basis coefficients]
+  const int rough_offset = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
+  const int q_offset = rough_offset + d->n_planes + d->n_spheres + nm;
   const int np = q_offset + (nm > 0 ? nm * d->n_basis : 0);
+  for (int k = 0; k < d->n_planes + d->n_spheres + nm; ++k)
+    US_CHECK(d->theta[rough_offset + k] >= 0 && std::isfinite(d->theta[rough_offset + k]),
+             "us_scene_upload: roughness must be finite and >= 0");
   for (int r = 0; r < d->n_regions; ++r)
     US_CHECK(d->theta[3 * r] > 0 && d->theta[3 * r + 1] > 0 && d->theta[3 * r + 2] >= 0,
              "us_scene_upload: region needs c > 0, Z > 0, alpha >= 0");

@@ -125,6 +125,7 @@ struct SceneLDS {
   int sreg[kMaxSpheres][2];
   int mreg[kMaxMeshes][2];
   double mkd[kMaxMeshes];
+  double prho[kMaxPlanes], srho[kMaxSpheres], mrho[kMaxMeshes];   // GGX roughness
   int n_planes, n_spheres, n_meshes, start_region, stack_cap;
   bool any_diffuse;
   const BvhNode* nodes;
@@ -162,6 +163,14 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
     s.mreg[i][0] = v.mesh_regions[2 * i];
     s.mreg[i][1] = v.mesh_regions[2 * i + 1];
     s.mkd[i] = v.mesh_kd[i];
+  }
+  // roughness follows the spheres: planes, spheres, meshes
+  const int orh = os + 4 * v.n_spheres;
+  for (int i = t; i < v.n_planes + v.n_spheres + v.n_meshes; i += blockDim.x) {
+    const double r = v.theta[orh + i];
+    if (i < v.n_planes) s.prho[i] = r;
+    else if (i < v.n_planes + v.n_spheres) s.srho[i - v.n_planes] = r;
+    else s.mrho[i - v.n_planes - v.n_spheres] = r;
   }
   if (t == 0) {
     s.n_planes = v.n_planes;

@@ -141,7 +141,7 @@ __device__ __forceinline__ d3 tri_normal(const SceneLDS& s, int i) {
   return nu * (1.0 / sqrt(dot(nu, nu)));
 }
 
-struct Surface { d3 n; int other; double kd; };
+struct Surface { d3 n; int other; double kd, rho; };
 
 __device__ __forceinline__ Surface surface_of(const SceneLDS& s, const Hit& h, d3 x, int region) {
   Surface f;
@@ -149,16 +149,19 @@ __device__ __forceinline__ Surface surface_of(const SceneLDS& s, const Hit& h, d
     f.n = d3{0.0, 0.0, 1.0};
     f.other = region == s.pr[h.index][0] ? s.pr[h.index][1] : s.pr[h.index][0];
     f.kd = s.pkd[h.index];
+    f.rho = s.prho[h.index];
   } else if (h.kind == kHitSphere) {
     const double ir = 1.0 / s.sr[h.index];
     f.n = d3{(x.x - s.sx[h.index]) * ir, (x.y - s.sy[h.index]) * ir, (x.z - s.sz[h.index]) * ir};
     f.other = region == s.sreg[h.index][0] ? s.sreg[h.index][1] : s.sreg[h.index][0];
     f.kd = s.skd[h.index];
+    f.rho = s.srho[h.index];
   } else {
     const int m = s.tri[h.index].w;
     f.n = tri_normal(s, h.index);
     f.other = region == s.mreg[m][0] ? s.mreg[m][1] : s.mreg[m][0];
     f.kd = s.mkd[m];
+    f.rho = s.mrho[m];
   }
   return f;
 }
@@ -192,6 +195,63 @@ __device__ __forceinline__ Coef coefficients(d3 d, d3 n, double c1, double Z1, d
   f.At = 2.0 * zi * inv;
   f.RE = f.Ar * f.Ar;
   return f;
+}
+
+// Orthonormal frame (b1, b2, n) about a unit normal n, branch-free form of
+// Duff et al. (JCGT 2017); directions l = (lx, ly, lz) in it map to
+// lx b1 + ly b2 + lz n.
+struct Frame { d3 b1, b2; };
+__device__ __forceinline__ Frame frame_of(d3 n) {
+  const double sg = n.z >= 0.0 ? 1.0 : -1.0;
+  const double aa = -1.0 / (sg + n.z);
+  const double bb = n.x * n.y * aa;
+  return Frame{d3{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x}, d3{bb, sg + n.y * n.y * aa, -n.y}};
+}
+
+// Transposed Jacobian of lx b1(n) + ly b2(n) + lz n with respect to n,
+// applied to v (the frame depends on n through b1, b2).
+__device__ __forceinline__ d3 frame_vjp(d3 n, double lx, double ly, double lz, d3 v) {
+  const double sg = n.z >= 0.0 ? 1.0 : -1.0;
+  const double aa = -1.0 / (sg + n.z);
+  const double a2 = aa * aa;
+  const double j_xx = lx * 2.0 * sg * n.x * aa + ly * n.y * aa + lz;
+  const double j_xy = ly * n.x * aa;
+  const double j_xz = lx * sg * n.x * n.x * a2 + ly * n.x * n.y * a2;
+  const double j_yx = lx * sg * n.y * aa;
+  const double j_yy = lx * sg * n.x * aa + ly * 2.0 * n.y * aa + lz;
+  const double j_yz = lx * sg * n.x * n.y * a2 + ly * n.y * n.y * a2;
+  const double j_zx = -lx * sg, j_zy = -ly, j_zz = lz;
+  return d3{v.x * j_xx + v.y * j_yx + v.z * j_zx, v.x * j_xy + v.y * j_yy + v.z * j_zy,
+            v.x * j_xz + v.y * j_yz + v.z * j_zz};
+}
+
+// Smith masking of one direction for GGX roughness rho at cosine c > 0.
+__device__ __forceinline__ double smith_g1(double c, double rho) {
+  return 2.0 * c / (c + sqrt(rho * rho + (1.0 - rho * rho) * c * c));
+}
+
+// Rough specular reflection (Eq. GGX_PDF): the specular share is mirrored
+// about a microfacet normal m drawn with density D(m) (n.m) (tan theta_m =
+// rho sqrt(u1 / (1 - u1)), azimuth 2 pi u2 in the frame about n_r); the
+// weight takes the microfacet estimator factor
+//   g = G1(n.i) G1(n.o) |i.m| / ((n.i) (n.m)),
+// i = -d. A facet turned away from i, or an o below the surface, ends the
+// path (ok = false). rho = 0 gives m = n_r.
+struct Glossy { d3 dir; double g; bool ok; };
+__device__ __forceinline__ Glossy glossy_reflect(d3 d, const Coef& f, double rho, double u1, double u2) {
+  const Frame fr = frame_of(f.nr);
+  const double th = rho * sqrt(u1 / (1.0 - u1));
+  const double ch = 1.0 / sqrt(1.0 + th * th);
+  const double sh = th * ch;
+  const double phi = 2.0 * kPi * u2;
+  const d3 m = fr.b1 * (sh * cos(phi)) + fr.b2 * (sh * sin(phi)) + f.nr * ch;
+  Glossy o;
+  const double wh = dot(d, m);
+  o.dir = d - m * (2.0 * wh);
+  const double co = dot(f.nr, o.dir);
+  o.ok = wh < 0.0 && co > 0.0;
+  o.g = o.ok ? smith_g1(f.ci, rho) * smith_g1(co, rho) * (-wh) / (f.ci * ch) : 0.0;
+  return o;
 }
 
 __device__ __forceinline__ double elem_x(const ProbeView& p, int e) {

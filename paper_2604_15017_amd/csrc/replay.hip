@@ -49,7 +49,7 @@ __device__ __forceinline__ void grad_flush(const double* gsh, int n_grad, int co
 // Per-block gradient accumulator over the flat parameter vector.
 struct GradAcc {
   double* g;
-  int n_regions, n_planes;
+  int n_regions, n_planes, n_spheres;
   double np_per_m;
   const double* vnormal;
   double* vadj;                   // per-vertex adjoint along the displacement direction (HBM)
@@ -66,6 +66,13 @@ struct GradAcc {
   // v is the adjoint of the amplitude attenuation a [Np/m]; a = alpha * np_per_m
   __device__ void a(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 2], v * np_per_m); }
   __device__ void plane(int k, double v) { if (v != 0.0) atomicAdd(&g[3 * n_regions + k], v); }
+  // roughness of plane / sphere k or of mesh k (hit kind decides)
+  __device__ void rough(int kind, int k, double v) {
+    if (v == 0.0) return;
+    const int base = 3 * n_regions + n_planes + 4 * n_spheres;
+    const int j = kind == kHitPlane ? k : (kind == kHitSphere ? n_planes + k : n_planes + n_spheres + k);
+    atomicAdd(&g[base + j], v);
+  }
   __device__ void sphere(int k, d3 cbar, double rbar) {
     double* s = g + 3 * n_regions + n_planes + 4 * k;
     if (cbar.x != 0.0) atomicAdd(s + 0, cbar.x);
@@ -86,6 +93,16 @@ __device__ __forceinline__ void tri_nu_backward(const SceneLDS& S, int i, d3 nub
   G.mesh_vertex(tv.x, tv.w, p0b_extra - e1b - e2b);
   G.mesh_vertex(tv.y, tv.w, e1b);
   G.mesh_vertex(tv.z, tv.w, e2b);
+}
+
+// Adjoint of G1(c, rho) (Smith masking for GGX): adds gbar dG1/dc to *cbar
+// and gbar dG1/drho to *rhobar.
+__device__ __forceinline__ void smith_g1_vjp(double c, double rho, double gbar, double* cbar, double* rhobar) {
+  const double s = sqrt(rho * rho + (1.0 - rho * rho) * c * c);
+  const double den = c + s;
+  const double inv2 = 1.0 / (den * den);
+  *cbar += gbar * 2.0 * (s - c * (1.0 - rho * rho) * c / s) * inv2;
+  *rhobar += gbar * (-2.0 * c * (rho * (1.0 - c * c) / s)) * inv2;
 }
 
 // d/dc of the receive directivity (Eq. cutoff) at cosine c; zero outside the ramp.
@@ -463,9 +480,17 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
         w = st.watt;
         const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
         const double p_spec = (1.0 - st.sf.kd) * st.f.RE;
+        bool alive = true;
         if (v.u0 < p_spec) {
-          d = d + st.f.nr * (2.0 * st.f.ci);
-          w *= st.f.Ar / st.f.RE;
+          if (st.sf.rho > 0.0) {
+            const Glossy gl = glossy_reflect(d, st.f, st.sf.rho, v.u1, v.u2);
+            d = gl.dir;
+            w *= st.f.Ar / st.f.RE * gl.g;
+            alive = gl.ok;
+          } else {
+            d = d + st.f.nr * (2.0 * st.f.ci);
+            w *= st.f.Ar / st.f.RE;
+          }
           delta = true;
         } else if (v.u0 < st.f.RE) {
           const d3 nn = st.f.nr;
@@ -487,7 +512,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
         }
         o = st.x;
         a.stk.last[ci] = k;
-        keep = true;
+        keep = alive;
         diffuse = st.sf.kd > 0.0;
       }
     }
@@ -533,7 +558,7 @@ __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
   int* leg_h = (int*)(legs + kLegCache * blockDim.x) + threadIdx.x;
   int* stk = leg_h + kLegCache * blockDim.x;
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
-            a.scene.np_per_m, a.scene.vnormal, a.vadj};
+            a.scene.n_spheres, a.scene.np_per_m, a.scene.vnormal, a.vadj};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
@@ -570,7 +595,7 @@ __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
 // Phase 3 (one thread per ray): the reverse sweep over the kept steps, with
 // the secondary-ray adjoints of phase 2 added at their interactions; no
 // intersection queries.
-__global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_replay_reverse(ReplayArgs a, long n) {
   if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
   extern __shared__ double gsh[];      // gradient sums, kGradCopies copies
@@ -578,7 +603,7 @@ __global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
   grad_clear(gsh, a.n_grad, a.grad_copies);
   __syncthreads();
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
-            a.scene.np_per_m, a.scene.vnormal, a.vadj};
+            a.scene.n_spheres, a.scene.np_per_m, a.scene.vnormal, a.vadj};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -630,30 +655,51 @@ __global__ __launch_bounds__(256) void k_replay_reverse(ReplayArgs a, long n) {
         d3 nrb{0, 0, 0};
         double cib = 0.0, ctb = 0.0, etab = 0.0, Ab = 0.0;
         const double p_spec = (1.0 - sf.kd) * f.RE;
-        if (v.u0 < p_spec) {          // d' = d + 2 ci nr, w' = watt Ar / R_E
-          d0b = d0b + db;
-          cib += 2.0 * dot(db, f.nr);
-          nrb = nrb + db * (2.0 * f.ci);
-          wattb += wb * f.Ar / f.RE;
-          Ab += wb * watt / f.RE;
-        } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
+        if (v.u0 < p_spec) {
+          // d' = d - 2 (d.m) m about the GGX microfacet m(n_r, rho), w' = watt
+          // Ar / R_E g. Taken in this form also at rho = 0, where the forward
+          // mirrored about n_r: the values agree and dL/drho is kept.
           const d3 nn = f.nr;
-          const double sg = nn.z >= 0.0 ? 1.0 : -1.0;
-          const double aa = -1.0 / (sg + nn.z);
+          const Frame fr = frame_of(nn);
+          const double rho = sf.rho;
+          const double kap = sqrt(v.u1 / (1.0 - v.u1));
+          const double th = rho * kap;
+          const double lz = 1.0 / sqrt(1.0 + th * th);
+          const double sh = th * lz;
+          const double phi = 2.0 * kPi * v.u2, cph = cos(phi), sph = sin(phi);
+          const double lx = sh * cph, ly = sh * sph;
+          const d3 m = fr.b1 * lx + fr.b2 * ly + nn * lz;
+          const double wh = dot(d0, m);
+          const d3 dout = d0 - m * (2.0 * wh);
+          const double co = dot(nn, dout);
+          if (wh < 0.0 && co > 0.0) {   // else the path ended here: nothing flows back
+            const double g1i = smith_g1(f.ci, rho), g1o = smith_g1(co, rho);
+            const double q = f.ci * lz, g = g1i * g1o * (-wh) / q;
+            wattb += wb * f.Ar / f.RE * g;
+            Ab += wb * watt / f.RE * g;
+            const double gb = wb * watt * f.Ar / f.RE;
+            double rho_b = 0.0, co_b = 0.0, lz_b = -gb * g / lz;
+            cib += -gb * g / f.ci;
+            smith_g1_vjp(f.ci, rho, gb * g1o * (-wh) / q, &cib, &rho_b);
+            smith_g1_vjp(co, rho, gb * g1i * (-wh) / q, &co_b, &rho_b);
+            const double im_b = gb * g1i * g1o / q;            // of -wh
+            const d3 ob = db + nn * co_b;                      // co = n_r . d'
+            nrb = nrb + dout * co_b;
+            d0b = d0b + ob;
+            const double wh_b = -2.0 * dot(m, ob) - im_b;
+            const d3 mb = ob * (-2.0 * wh) + d0 * wh_b;
+            d0b = d0b + m * wh_b;
+            nrb = nrb + frame_vjp(nn, lx, ly, lz, mb);
+            lz_b += dot(nn, mb);
+            const double sh_b = dot(fr.b1, mb) * cph + dot(fr.b2, mb) * sph;
+            const double lz3 = lz * lz * lz;
+            rho_b += sh_b * kap * lz3 - lz_b * rho * kap * kap * lz3;
+            G.rough(h.kind, h.kind == kHitMesh ? S.tri[h.index].w : h.index, rho_b);
+          }
+        } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
           const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
           const double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(1.0 - v.u2);
-          const double a2 = aa * aa;
-          // Jacobian of d' with respect to (nx, ny, nz), applied transposed to db
-          const double j_xx = lx * 2.0 * sg * nn.x * aa + ly * nn.y * aa + lz;
-          const double j_xy = ly * nn.x * aa;
-          const double j_xz = lx * sg * nn.x * nn.x * a2 + ly * nn.x * nn.y * a2;
-          const double j_yx = lx * sg * nn.y * aa;
-          const double j_yy = lx * sg * nn.x * aa + ly * 2.0 * nn.y * aa + lz;
-          const double j_yz = lx * sg * nn.x * nn.y * a2 + ly * nn.y * nn.y * a2;
-          const double j_zx = -lx * sg, j_zy = -ly, j_zz = lz;
-          nrb.x += db.x * j_xx + db.y * j_yx + db.z * j_zx;
-          nrb.y += db.x * j_xy + db.y * j_yy + db.z * j_zy;
-          nrb.z += db.x * j_xz + db.y * j_yz + db.z * j_zz;
+          nrb = nrb + frame_vjp(f.nr, lx, ly, lz, db);
           wattb += wb * f.Ar / f.RE;
           Ab += wb * watt / f.RE;
         } else {                      // d' = eta d + (eta ci - ct) nr, w' = watt At / (1 - R_E)

@@ -142,10 +142,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
           // branch on the energy split; weight times coefficient / probability
           const double p_spec = (1.0 - sf.kd) * f.RE;
           uint32_t branch;
+          bool alive = true;
           if (v.u0 < p_spec) {
-            d = d + f.nr * (2.0 * f.ci);
-            w *= f.Ar / f.RE;
-            delta = true; branch = 0;
+            if (sf.rho > 0.0) {   // glossy about a GGX microfacet; deposits like a mirror path
+              const Glossy gl = glossy_reflect(d, f, sf.rho, v.u1, v.u2);
+              d = gl.dir;
+              w *= f.Ar / f.RE * gl.g;
+              alive = gl.ok;
+            } else {
+              d = d + f.nr * (2.0 * f.ci);
+              w *= f.Ar / f.RE;
+            }
+            delta = true; branch = alive ? 0 : 3;
           } else if (v.u0 < f.RE) {
             // cosine lobe about n_r in the frame of Duff et al. (JCGT 2017)
             const d3 n = f.nr;
@@ -167,7 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             delta = true; branch = 2;
           }
           if (kAudit) hsum += event_mix(kEvBranch, k, branch | (f.tir ? 0x10u : 0u));
-          keep = true;
+          keep = alive;
         }
       }
       if (kAudit && hsum) atomicAdd(a.hash + (long)(a.tx_base + txl) * a.ray_count + (rid - a.ray_begin), (unsigned long long)hsum);

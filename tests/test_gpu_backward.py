@@ -114,8 +114,23 @@ def test_vjp_diffuse_spheres(L, ctx):
 
 
 def test_vjp_layered_phantom(L, ctx):
+    """Mirror interfaces: the forward reflects about n, and dL/drho at zero
+    roughness is still the glossy lobe's, as in the oracle."""
     wl = W.layered_phantom().replace(rays_per_elem=64)
-    vjp_parity(L, ctx, wl, "layered phantom")
+    g, ref = vjp_parity(L, ctx, wl, "layered phantom")
+    assert ref[wl.scene.idx_rough("plane", 0)] != 0.0
+
+
+def test_vjp_rough_layered_phantom(L, ctx):
+    """Roughness gradients through the glossy lobe (Eq. GGX_PDF): the sampled
+    microfacet, the Smith factor and the reflected direction, together with
+    every other parameter."""
+    wl = W.rough_layered_phantom().replace(rays_per_elem=96)
+    g, ref = vjp_parity(L, ctx, wl, "rough layered phantom")
+    sc = wl.scene
+    rough = [sc.idx_rough("plane", j) for j in range(sc.n_planes)] + \
+            [sc.idx_rough("sphere", j) for j in range(sc.n_spheres)]
+    assert np.count_nonzero(ref[rough]) >= 6
 
 
 def test_vjp_ray_subsets_add_up(L, ctx):

@@ -79,6 +79,16 @@ def test_layered_phantom_reduced_rays(L, ctx):
     check_transport(L, ctx, wl.replace(rays_per_elem=128))
 
 
+def test_rough_layered_phantom(L, ctx):
+    """Rough planes and spheres (Eq. GGX_PDF): glossy reflections, the paths
+    they end, and their direct deposits."""
+    check_transport(L, ctx, W.rough_layered_phantom().replace(rays_per_elem=128))
+
+
+def test_rough_layered_phantom_full_size(L, ctx):
+    check_transport(L, ctx, W.rough_layered_phantom())
+
+
 def test_layered_phantom_full_size(L, ctx):
     """The benchmark workload itself: 11 transmits x 2^20 rays, 8 bounces."""
     check_transport(L, ctx, W.layered_phantom())
