@@ -51,13 +51,15 @@ def kernel_bytes(name, wl, counts, n_px):
         "das_adjoint": 8 * row_samples + 8 * n_px,
         "bmode_vjp": 28 * n_px,
         "image_loss": 12 * n_px,
-        # replay: the forward phase writes one 80-byte step record per primary
-        # segment and queues the diffuse interactions; the secondary phase
-        # reads a step record, dL/dh at its deposit and writes 72 bytes of
-        # adjoints; the reverse phase reads the step records and those adjoints
-        "replay_forward": 80 * seg_p + 8 * sec,
-        "replay_secondary": (80 + 8 + 72) * sec,
-        "replay_reverse": 80 * seg_p + 72 * sec + 8 * (dep - sec),
+        # replay: the forward phase moves the live rays through the queues as
+        # the bounce kernel does, writes one 80-byte step record per primary
+        # segment and a 4-byte queue entry per diffuse interaction; the
+        # secondary phase reads the entry, the step record and dL/dh at its
+        # deposit and writes 80 bytes of adjoints; the reverse phase reads the
+        # step records, those adjoints and dL/dh at the array hits
+        "replay_forward": 2 * state * (seg_p - rays) + 80 * seg_p + 4 * sec,
+        "replay_secondary": (4 + 80 + 8 + 80) * sec,
+        "replay_reverse": 80 * seg_p + 80 * sec + 8 * (dep - sec),
         "analytic": 12 * row_samples,
         "das": 8 * row_samples + 8 * n_px,
         "bmode": 20 * n_px,
@@ -111,7 +113,7 @@ def cpu_baseline(wl):
 
 def inverse_leg(ctx, steps, warmup):
     """Algorithm opt on the layered phantom: the 34 perturbed parameters free
-    within +-10 % (material and geometry learning-rate groups), the other 16
+    within +-10 % (material and geometry learning-rate groups), the others
     fixed, three micro-batches of transmits (4, 4, 3 plane waves), MSE against
     the image of the seeded +-5 % target; iterations per second."""
     import numpy as np
@@ -306,6 +308,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-anatomy", action="store_true")
+    ap.add_argument("--no-inverse", action="store_true", help="skip the inverse-loop leg")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-backward", action="store_true",
                     help="forward legs only (for short profiler runs)")
@@ -393,7 +396,7 @@ def main():
                 "gradient_parameters": a["n_params"], "loss": a["loss"],
                 "kernels": a["fb_kernels"]},
         }
-    if not args.no_backward:
+    if not args.no_backward and not args.no_inverse:
         out["inverse"] = inverse_leg(ctx, args.steps, args.warmup)
         print(f"inverse loop: {out['inverse']['ms_per_iteration']:.3f} ms/iteration", file=sys.stderr,
               flush=True)

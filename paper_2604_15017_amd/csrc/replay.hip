@@ -765,14 +765,21 @@ __global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__
   if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(g_q + blockIdx.x, red[0]);
 }
 
-// g_theta[j] += sum of the kMaxReplayBlocks partial rows, one thread per entry.
+// g_theta[j] += sum of the kMaxReplayBlocks partial rows: one block per
+// entry j, each thread a strided share of the rows, then a tree in LDS.
 __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ g_part, int n_grad,
                                                      double* __restrict__ g_theta) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n_grad) return;
+  const int j = blockIdx.x;
   double v = 0.0;
-  for (int b = 0; b < kMaxReplayBlocks; ++b) v += g_part[(long)b * n_grad + j];
-  g_theta[j] += v;
+  for (int b = threadIdx.x; b < kMaxReplayBlocks; b += blockDim.x) v += g_part[(long)b * n_grad + j];
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) g_theta[j] += red[0];
 }
 
 namespace {
@@ -803,8 +810,7 @@ void launch_replay_prefix(const ReplayArgs& a, hipStream_t s) {
 }
 
 void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, hipStream_t s) {
-  if (n_grad > 0)
-    hipLaunchKernelGGL(k_grad_reduce, dim3((n_grad + 255) / 256), dim3(256), 0, s, g_part, n_grad, g_theta);
+  if (n_grad > 0) hipLaunchKernelGGL(k_grad_reduce, dim3(n_grad), dim3(256), 0, s, g_part, n_grad, g_theta);
 }
 
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s) {

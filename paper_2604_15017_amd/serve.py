@@ -26,6 +26,12 @@ from typing import Callable, Dict, List, Optional
 import numpy as np
 
 
+# The replay workspace of a gradient request is sized for chunks of this many
+# rays (some 5 GB at twelve interactions): a whole-frame chunk would save a few
+# launches but reserve up to 20 GB per request in flight.
+REPLAY_CHUNK_RAYS = 1 << 21
+
+
 @dataclasses.dataclass
 class Request:
     rid: int
@@ -193,8 +199,9 @@ class GpuExecutor:
             s.update({"b_ref": 4 * g.n_px, "g_b": 4 * g.n_px, "g_iq": 8 * g.n_px, "g_rf": 4 * rows,
                       "loss": 8, "g_theta": 8 * scene.n_params,
                       "ws_beam_vjp": L.load().us_beamform_vjp_workspace_size(probe.handle, n_tx),
-                      "ws_replay": L.us_simulate_rf_vjp_workspace_size(scene, probe, n_tx, wl.rays_per_tx,
-                                                                       wl.max_bounces)})
+                      "ws_replay": L.us_simulate_rf_vjp_workspace_size(
+                          scene, probe, n_tx, min(wl.rays_per_tx, max(1, REPLAY_CHUNK_RAYS // n_tx)),
+                          wl.max_bounces)})
         return s
 
     def bytes_needed(self, req: Request) -> int:
