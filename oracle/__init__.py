@@ -57,7 +57,9 @@ class _Scene(ctypes.Structure):
                 ("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
                 ("vrest", ctypes.c_void_p), ("vnormal", ctypes.c_void_p), ("vbasis", ctypes.c_void_p),
                 ("vmesh", ctypes.c_void_p), ("tris", ctypes.c_void_p), ("tmesh", ctypes.c_void_p),
-                ("mesh_bruteforce", ctypes.c_int)]
+                ("mesh_bruteforce", ctypes.c_int),
+                ("n_cylinders", ctypes.c_int), ("cylinder_regions", ctypes.c_void_p),
+                ("cylinder_kd", ctypes.c_void_p)]
 
 
 class _Probe(ctypes.Structure):
@@ -153,9 +155,12 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
            estimator with its sampling density held fixed need this.
     scene.meshes (optional): closed triangle meshes with attributes vertices,
            triangles, normals, basis, region_in, region_out, kd.
+    scene.cylinders (optional): (C, 3) axes x, z and radii of cylinders along
+           y, with cylinder_regions (C, 2) inside / outside and cylinder_kd.
     theta layout: (c, Z, alpha) per region, plane depths, (x, y, z, r) per
-           sphere, GGX roughness per plane, per sphere and per mesh, then the
-           mesh displacement coefficients [mesh][basis].
+           sphere, (x, z, R) per cylinder, GGX roughness per plane, sphere,
+           cylinder and mesh, then the mesh displacement coefficients
+           [mesh][basis].
     mesh_bruteforce: test every triangle instead of walking the hierarchy.
     """
     lib = _load()
@@ -165,7 +170,13 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
     sr = np.ascontiguousarray(scene.sphere_regions, dtype=np.int32).reshape(-1)
     sk = np.ascontiguousarray(scene.sphere_kd, dtype=np.float64)
     meshes = list(getattr(scene, "meshes", []) or [])
-    keep = [pr, pk, sr, sk]
+    cyl = np.ascontiguousarray(getattr(scene, "cylinders", np.zeros((0, 3))), dtype=np.float64).reshape(-1, 3)
+    cr = np.ascontiguousarray(getattr(scene, "cylinder_regions", np.zeros((0, 2))), dtype=np.int32).reshape(-1)
+    ck = np.ascontiguousarray(getattr(scene, "cylinder_kd", np.zeros(0)), dtype=np.float64).reshape(-1)
+    n_c = cyl.shape[0]
+    if cr.shape[0] != 2 * n_c or ck.shape[0] != n_c:
+        raise ValueError("cylinder arrays disagree")
+    keep = [pr, pk, sr, sk, cr, ck]
     if meshes:
         vs, ns, bs, vm, ts, tm, off = [], [], [], [], [], [], 0
         for k, mm in enumerate(meshes):
@@ -186,12 +197,13 @@ def trace(scene, probe, angles, tx_ids, seed: int, rays_per_elem: int, max_bounc
     n_m = len(meshes)
     n_b = int(meshes[0].basis.shape[1]) if meshes else 0
     n_exp = (3 * scene.regions.shape[0] + 2 * scene.planes.shape[0] + 5 * scene.spheres.shape[0]
-             + n_m + n_m * n_b)
+             + 4 * n_c + n_m + n_m * n_b)
     if th.shape != (n_exp,):
         raise ValueError(f"theta has {th.shape} entries, the scene needs {n_exp}")
     sd = _Scene(int(scene.regions.shape[0]), int(scene.planes.shape[0]),
                 int(scene.spheres.shape[0]), _ptr(pr), _ptr(pk), _ptr(sr), _ptr(sk),
-                int(scene.start_region), *mesh_fields, 1 if mesh_bruteforce else 0)
+                int(scene.start_region), *mesh_fields, 1 if mesh_bruteforce else 0,
+                n_c, _ptr(cr) if n_c else None, _ptr(ck) if n_c else None)
     pd = _probe_struct(probe)
     ang = np.ascontiguousarray(angles, dtype=np.float64)
     ids = np.ascontiguousarray(tx_ids, dtype=np.uint32)

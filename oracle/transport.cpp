@@ -174,6 +174,10 @@ struct OrSceneDesc {
   const int32_t* tris;            // [T][3]
   const int32_t* tmesh;           // [T]
   int mesh_bruteforce;            // test hook: 1 = test every triangle instead of the BVH
+  // cylinders along y: (x - cx)^2 + (z - cz)^2 = R^2 for every y
+  int n_cylinders;
+  const int32_t* cylinder_regions;  // [n_cylinders][2]: inside, outside
+  const double* cylinder_kd;        // [n_cylinders]
 };
 
 struct OrProbeDesc {
@@ -212,7 +216,7 @@ namespace {
 constexpr double TMIN = 1e-6;   // reading: self-intersection guard of 1 um
 constexpr double PI = 3.14159265358979323846;
 
-enum HitKind { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_ARRAY = 3, HIT_MESH = 4 };
+enum HitKind { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_ARRAY = 3, HIT_MESH = 4, HIT_CYLINDER = 5 };
 
 // Bounding-volume hierarchy over the mesh triangles (median split along the
 // longest axis of the centroids, at most 4 triangles per leaf). It only
@@ -274,7 +278,8 @@ struct Model {
   std::vector<T> c, Z, a;               // per region: speed, impedance, amplitude attenuation [Np/m]
   std::vector<T> pz;                    // plane depths
   std::vector<V3<T>> sc; std::vector<T> sr;  // sphere centres, radii
-  std::vector<T> rho_p, rho_s, rho_m;   // GGX roughness of planes, spheres, meshes
+  std::vector<T> ccx, ccz, cr;          // cylinder axes (x, z) and radii
+  std::vector<T> rho_p, rho_s, rho_c, rho_m;   // GGX roughness of planes, spheres, cylinders, meshes
   std::vector<T> q;                     // mesh displacement coefficients [n_meshes][n_basis]
   std::vector<double> vpos;             // current vertex positions (values) [V][3]
   Bvh bvh;
@@ -398,6 +403,20 @@ Hit<T> closest_hit(const Model<T>& m, const V3<T>& o, const V3<T>& w, bool with_
     T t = val(t1) > TMIN ? t1 : t2;
     if (val(t) > TMIN && val(t) < best_t) { best = {HIT_SPHERE, k, t}; best_t = val(t); }
   }
+  // cylinder: |(o + t w - c) projected on the x-z plane| = R, a t^2 + 2 b t + cc = 0
+  for (int k = 0; k < m.sd->n_cylinders; ++k) {
+    T ox = o.x - m.ccx[k], oz = o.z - m.ccz[k];
+    T a = w.x * w.x + w.z * w.z;
+    if (val(a) <= 0.0) continue;            // parallel to the axis
+    T b = ox * w.x + oz * w.z;
+    T cc = ox * ox + oz * oz - m.cr[k] * m.cr[k];
+    T disc = b * b - a * cc;
+    if (val(disc) < 0) continue;
+    T sq = sqrt(disc);
+    T t1 = (-b - sq) / a, t2 = (-b + sq) / a;
+    T t = val(t1) > TMIN ? t1 : t2;
+    if (val(t) > TMIN && val(t) < best_t) { best = {HIT_CYLINDER, k, t}; best_t = val(t); }
+  }
   if (m.sd->n_meshes > 0) {
     double ov[3] = {val(o.x), val(o.y), val(o.z)}, wv[3] = {val(w.x), val(w.y), val(w.z)};
     double bt = best_t;
@@ -434,6 +453,13 @@ void surface_at(const Model<T>& m, const Hit<T>& h, const V3<T>& x, int region,
     *other = region == sr[0] ? sr[1] : sr[0];
     *kd = m.sd->sphere_kd[h.index];
     if (rho) *rho = m.rho_s[h.index];
+  } else if (h.kind == HIT_CYLINDER) {
+    T inv_r = 1.0 / m.cr[h.index];
+    *n = {(x.x - m.ccx[h.index]) * inv_r, T(0.0), (x.z - m.ccz[h.index]) * inv_r};
+    const int32_t* cr = m.sd->cylinder_regions + 2 * h.index;
+    *other = region == cr[0] ? cr[1] : cr[0];
+    *kd = m.sd->cylinder_kd[h.index];
+    if (rho) *rho = m.rho_c[h.index];
   } else {   // mesh triangle: flat face normal
     V3<T> zero{T(0.0), T(0.0), T(1.0)};
     tri_geometry(m, h.index, x, zero, (T*)nullptr, n);
@@ -768,10 +794,16 @@ void build_model(Model<T>& m, const OrSceneDesc* sd, const OrProbeDesc* pd, cons
     m.sr.push_back(th[off + 4 * s + 3]);
   }
   off += 4 * sd->n_spheres;
+  for (int c = 0; c < sd->n_cylinders; ++c) {
+    m.ccx.push_back(th[off + 3 * c]); m.ccz.push_back(th[off + 3 * c + 1]); m.cr.push_back(th[off + 3 * c + 2]);
+  }
+  off += 3 * sd->n_cylinders;
   for (int p = 0; p < sd->n_planes; ++p) m.rho_p.push_back(th[off + p]);
   off += sd->n_planes;
   for (int s = 0; s < sd->n_spheres; ++s) m.rho_s.push_back(th[off + s]);
   off += sd->n_spheres;
+  for (int c = 0; c < sd->n_cylinders; ++c) m.rho_c.push_back(th[off + c]);
+  off += sd->n_cylinders;
   for (int j = 0; j < sd->n_meshes; ++j) m.rho_m.push_back(th[off + j]);
   off += sd->n_meshes;
   if (sd->n_meshes > 0) {
@@ -786,10 +818,11 @@ void build_model(Model<T>& m, const OrSceneDesc* sd, const OrProbeDesc* pd, cons
 }
 
 // theta = [(c, Z, alpha) per region, plane depths, (x, y, z, r) per sphere,
-//          roughness per plane, per sphere, per mesh, mesh basis coefficients]
+//          (x, z, R) per cylinder, roughness per plane, sphere, cylinder and
+//          mesh, mesh basis coefficients]
 int n_params_of(const OrSceneDesc* sd) {
-  return 3 * sd->n_regions + sd->n_planes + 4 * sd->n_spheres +
-         (sd->n_planes + sd->n_spheres + sd->n_meshes) + sd->n_meshes * sd->n_basis;
+  return 3 * sd->n_regions + sd->n_planes + 4 * sd->n_spheres + 3 * sd->n_cylinders +
+         (sd->n_planes + sd->n_spheres + sd->n_cylinders + sd->n_meshes) + sd->n_meshes * sd->n_basis;
 }
 
 struct Result {

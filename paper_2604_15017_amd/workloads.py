@@ -69,13 +69,23 @@ class Scene:
     mesh_q: Optional[np.ndarray] = None   # (n_meshes, n_basis) displacement coefficients [m]
     plane_rough: Optional[np.ndarray] = None    # (Pl,) GGX roughness (Eq. GGX_PDF); None: 0
     sphere_rough: Optional[np.ndarray] = None   # (S,) GGX roughness; None: 0
+    # cylinders along y (the elevation axis): axis at (x, z), radius R
+    cylinders: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3)))   # (C, 3) x, z, R [m]
+    cylinder_regions: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    cylinder_kd: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros(0))
+    cylinder_rough: Optional[np.ndarray] = None  # (C,) GGX roughness; None: 0
+
+    @property
+    def n_cylinders(self) -> int:
+        return int(np.asarray(self.cylinders).reshape(-1, 3).shape[0])
 
     def roughness(self) -> np.ndarray:
-        """Roughness of every plane, then sphere, then mesh (theta's order)."""
-        rp = np.zeros(self.n_planes) if self.plane_rough is None else np.asarray(self.plane_rough, np.float64)
-        rs = np.zeros(self.n_spheres) if self.sphere_rough is None else np.asarray(self.sphere_rough, np.float64)
+        """Roughness of every plane, sphere, cylinder, then mesh (theta's order)."""
+        def arr(x, n):
+            return np.zeros(n) if x is None else np.asarray(x, np.float64).reshape(-1)
         rm = np.array([getattr(m, "rough", 0.0) for m in self.meshes], dtype=np.float64)
-        return np.concatenate([rp.reshape(-1), rs.reshape(-1), rm])
+        return np.concatenate([arr(self.plane_rough, self.n_planes), arr(self.sphere_rough, self.n_spheres),
+                               arr(self.cylinder_rough, self.n_cylinders), rm])
 
     @property
     def n_meshes(self) -> int:
@@ -104,11 +114,11 @@ class Scene:
 
     @property
     def n_surfaces(self) -> int:
-        return self.n_planes + self.n_spheres + self.n_meshes
+        return self.n_planes + self.n_spheres + self.n_cylinders + self.n_meshes
 
     @property
     def rough_offset(self) -> int:
-        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres
+        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres + 3 * self.n_cylinders
 
     @property
     def n_params(self) -> int:
@@ -116,33 +126,42 @@ class Scene:
 
     def theta(self) -> np.ndarray:
         """[(c, Z, alpha) per region, plane depths, (x, y, z, r) per sphere,
-        roughness per plane, sphere and mesh, mesh basis coefficients]."""
+        (x, z, R) per cylinder, roughness per plane, sphere, cylinder and
+        mesh, mesh basis coefficients]."""
         return np.concatenate([self.regions.reshape(-1), self.planes.reshape(-1),
-                               self.spheres.reshape(-1), self.roughness(),
-                               self.q().reshape(-1)]).astype(np.float64)
+                               self.spheres.reshape(-1), np.asarray(self.cylinders, np.float64).reshape(-1),
+                               self.roughness(), self.q().reshape(-1)]).astype(np.float64)
 
     def with_theta(self, theta: np.ndarray) -> "Scene":
         theta = np.asarray(theta, dtype=np.float64)
         assert theta.shape == (self.n_params,)
-        r, p, s, m = self.n_regions, self.n_planes, self.n_spheres, self.n_meshes
+        r, p, s, c, m = self.n_regions, self.n_planes, self.n_spheres, self.n_cylinders, self.n_meshes
+        os_ = 3 * r + p
+        oc = os_ + 4 * s
         o = self.rough_offset
-        rough = theta[o:o + p + s + m]
-        meshes = [dataclasses.replace(mm, rough=float(rough[p + s + k])) for k, mm in enumerate(self.meshes)]
+        rough = theta[o:o + p + s + c + m]
+        meshes = [dataclasses.replace(mm, rough=float(rough[p + s + c + k])) for k, mm in enumerate(self.meshes)]
         return dataclasses.replace(
             self,
             regions=theta[:3 * r].reshape(r, 3).copy(),
-            planes=theta[3 * r:3 * r + p].copy(),
-            spheres=theta[3 * r + p:o].reshape(s, 4).copy(),
-            plane_rough=rough[:p].copy(), sphere_rough=rough[p:p + s].copy(), meshes=meshes,
-            mesh_q=theta[o + p + s + m:].reshape(m, self.n_basis).copy() if self.meshes else None)
+            planes=theta[3 * r:os_].copy(),
+            spheres=theta[os_:oc].reshape(s, 4).copy(),
+            cylinders=theta[oc:o].reshape(c, 3).copy(),
+            plane_rough=rough[:p].copy(), sphere_rough=rough[p:p + s].copy(),
+            cylinder_rough=rough[p + s:p + s + c].copy(), meshes=meshes,
+            mesh_q=theta[o + p + s + c + m:].reshape(m, self.n_basis).copy() if self.meshes else None)
 
     def idx_mesh(self, m: int, j: int) -> int:
         return self.rough_offset + self.n_surfaces + m * self.n_basis + j
 
     def idx_rough(self, kind: str, k: int) -> int:
-        """Roughness of plane / sphere / mesh k."""
-        base = {"plane": 0, "sphere": self.n_planes, "mesh": self.n_planes + self.n_spheres}[kind]
+        """Roughness of plane / sphere / cylinder / mesh k."""
+        base = {"plane": 0, "sphere": self.n_planes, "cylinder": self.n_planes + self.n_spheres,
+                "mesh": self.n_planes + self.n_spheres + self.n_cylinders}[kind]
         return self.rough_offset + base + k
+
+    def idx_cylinder(self, k: int, which: str) -> int:
+        return 3 * self.n_regions + self.n_planes + 4 * self.n_spheres + 3 * k + {"x": 0, "z": 1, "R": 2}[which]
 
     # index helpers for the flat parameter vector
     def idx_region(self, k: int, which: str) -> int:
@@ -269,6 +288,28 @@ def layered_phantom(seed: int = 1, rays_per_tx: int = 1 << 20, n_tx: int = 11) -
     return Workload("layered_phantom", _layered_scene(seed), probe, angles,
                     np.arange(n_tx, dtype=np.uint32), grid, seed=0,
                     rays_per_elem=rays_per_tx // probe.n_elem, max_bounces=8)
+
+
+def cylinder_phantom(radius: float = 5e-3, depth: float = 15e-3, Z: float = 1.7, rough: float = 0.15,
+                     kd: float = 0.1, rays_per_tx: int = 1 << 20, n_tx: int = 5) -> Workload:
+    """The hollow-cylinder scene of the paper's forward check and its
+    simulated-reference inversion: a cylindrical interface of radius 5 mm
+    along the elevation axis, its axis 15 mm below the array (reading), water
+    outside and a tissue-like medium of impedance Z inside (1540 m/s,
+    0.5 dB/cm/MHz), GGX roughness 0.15 and a Lambertian share 0.1; the
+    128-element probe of the layered phantom, 5 plane waves over [-10, 10]
+    degrees, 128 x 256 pixels over +-12.8 mm x [0, 30] mm."""
+    scene = Scene(
+        regions=np.array([_water(), [1540.0, Z, 0.5]], dtype=np.float64),
+        planes=np.zeros(0), plane_regions=np.zeros((0, 2), dtype=np.int32), plane_kd=np.zeros(0),
+        spheres=np.zeros((0, 4)), sphere_regions=np.zeros((0, 2), dtype=np.int32), sphere_kd=np.zeros(0),
+        cylinders=np.array([[0.0, depth, radius]]), cylinder_regions=np.array([[1, 0]], dtype=np.int32),
+        cylinder_kd=np.array([kd]), cylinder_rough=np.array([rough]))
+    probe = layered_probe()
+    angles = np.radians(np.linspace(-10.0, 10.0, n_tx))
+    grid = Grid.span(128, 256, -12.8e-3, 12.8e-3, 0.0, 30e-3)
+    return Workload("cylinder_phantom", scene, probe, angles, np.arange(n_tx, dtype=np.uint32), grid,
+                    seed=0, rays_per_elem=rays_per_tx // probe.n_elem, max_bounces=8)
 
 
 ROUGH_STREAM_TAG = 4
