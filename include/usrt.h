@@ -24,10 +24,10 @@
  *      iq        float  [n_x][n_z][2]  (real, imaginary)
  *      bmode     float  [n_x][n_z]     (dB, in [-dr_db, 0])
  *      theta     double [n_params]: (c, Z, alpha) per region, then plane
- *                depths, then (cx, cy, cz, r) per sphere, then the GGX
- *                roughness of every plane, every sphere and every mesh
- *                (>= 0; 0 is a mirror), then the displacement coefficients
- *                q[mesh][j] of the meshes
+ *                depths, then (cx, cy, cz, r) per sphere, then (cx, cz, R)
+ *                per cylinder, then the GGX roughness of every plane,
+ *                sphere, cylinder and mesh (>= 0; 0 is a mirror), then the
+ *                displacement coefficients q[mesh][j] of the meshes
  */
 #ifndef USRT_H
 #define USRT_H
@@ -64,8 +64,10 @@ typedef struct us_probe_desc {
   double c_ref, alpha_main, alpha_cut;
 } us_probe_desc;
 
-/* Scene of homogeneous regions bounded by planes z = d, spheres and closed
- * triangle meshes (Sec. 2.3.2; meshes as in the anatomy scenes of Sec. 4).
+/* Scene of homogeneous regions bounded by planes z = d, spheres, cylinders
+ * along the elevation axis y ((x - cx)^2 + (z - cz)^2 = R^2, the hollow
+ * cylinder of the paper's forward check and inversions) and closed triangle
+ * meshes (Sec. 2.3.2; meshes as in the anatomy scenes of Sec. 4).
  * theta holds the continuous parameters (layout above); plane_regions[k] =
  * {region above, region below}; sphere_regions[k] and mesh_regions[m] =
  * {inside, outside}; kd = fraction of the reflected energy scattered into the
@@ -104,6 +106,9 @@ typedef struct us_scene_desc {
   const int32_t* vmesh;          /* [n_vertices] */
   const int32_t* triangles;      /* [n_triangles][3] */
   const int32_t* tmesh;          /* [n_triangles] */
+  int32_t n_cylinders;           /* at most 16; axis along y through (x, z) of theta */
+  const int32_t* cylinder_regions;   /* [n_cylinders][2]: inside, outside */
+  const double* cylinder_kd;         /* [n_cylinders] */
 } us_scene_desc;
 
 /* One plane-wave transmit: steering angle and the id that seeds its rays. */

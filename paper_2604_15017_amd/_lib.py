@@ -45,7 +45,9 @@ class us_scene_desc(ctypes.Structure):
                 ("n_vertices", ctypes.c_int64), ("n_triangles", ctypes.c_int64),
                 ("vertices", ctypes.c_void_p), ("vnormal", ctypes.c_void_p),
                 ("vbasis", ctypes.c_void_p), ("vmesh", ctypes.c_void_p),
-                ("triangles", ctypes.c_void_p), ("tmesh", ctypes.c_void_p)]
+                ("triangles", ctypes.c_void_p), ("tmesh", ctypes.c_void_p),
+                ("n_cylinders", ctypes.c_int32), ("cylinder_regions", ctypes.c_void_p),
+                ("cylinder_kd", ctypes.c_void_p)]
 
 
 class us_tx_desc(ctypes.Structure):
@@ -198,6 +200,14 @@ class Scene:
         d = us_scene_desc(int(s.regions.shape[0]), int(s.planes.shape[0]),
                           int(s.spheres.shape[0]), th.ctypes.data, pr.ctypes.data, pk.ctypes.data,
                           sr.ctypes.data, sk.ctypes.data, int(s.start_region))
+        n_c = int(getattr(s, "n_cylinders", 0))
+        if n_c:
+            cr = np.ascontiguousarray(s.cylinder_regions, dtype=np.int32).reshape(-1)
+            ck = np.ascontiguousarray(s.cylinder_kd, dtype=np.float64).reshape(-1)
+            if cr.shape[0] != 2 * n_c or ck.shape[0] != n_c:
+                raise ValueError("cylinder arrays disagree")
+            d.n_cylinders, d.cylinder_regions, d.cylinder_kd = n_c, cr.ctypes.data, ck.ctypes.data
+            self._keep = (cr, ck)
         meshes = list(getattr(s, "meshes", None) or [])
         if meshes:
             # concatenate the meshes: global vertex ids, owning mesh per vertex / triangle

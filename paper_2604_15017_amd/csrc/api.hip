@@ -107,6 +107,9 @@ struct us_scene {
   double* plane_kd;
   int* sphere_regions;
   double* sphere_kd;
+  int n_cylinders;
+  int* cylinder_regions;
+  double* cylinder_kd;
   // meshes
   int n_meshes, n_basis, q_offset, stack_cap;
   int* mesh_regions;
@@ -196,6 +199,9 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
   US_CHECK(d->n_spheres >= 0 && d->n_spheres <= kMaxSpheres, "us_scene_upload: at most 32 spheres");
   US_CHECK(d->n_planes == 0 || (d->plane_regions && d->plane_kd), "us_scene_upload: plane arrays missing");
   US_CHECK(d->n_spheres == 0 || (d->sphere_regions && d->sphere_kd), "us_scene_upload: sphere arrays missing");
+  US_CHECK(d->n_cylinders >= 0 && d->n_cylinders <= kMaxCylinders, "us_scene_upload: at most 16 cylinders");
+  US_CHECK(d->n_cylinders == 0 || (d->cylinder_regions && d->cylinder_kd),
+           "us_scene_upload: cylinder arrays missing");
   US_CHECK(d->start_region >= 0 && d->start_region < d->n_regions, "us_scene_upload: start_region out of range");
   US_CHECK(d->n_meshes >= 0 && d->n_meshes <= kMaxMeshes, "us_scene_upload: at most 32 meshes");
   const int nm = d->n_meshes;
@@ -207,12 +213,14 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_CHECK(d->n_vertices >= 3 && d->n_vertices < (1L << 30), "us_scene_upload: n_vertices must be in [3, 2^30)");
     US_CHECK(d->n_triangles >= 1 && d->n_triangles < (1L << 27), "us_scene_upload: n_triangles must be in [1, 2^27)");
   }
-  // theta = [regions, plane depths, spheres, roughness (planes, spheres,
-  // meshes), mesh basis coefficients]
-  const int rough_offset = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
-  const int q_offset = rough_offset + d->n_planes + d->n_spheres + nm;
+  // theta = [regions, plane depths, spheres, cylinders, roughness (planes,
+  // spheres, cylinders, meshes), mesh basis coefficients]
+  const int nc = d->n_cylinders;
+  const int cyl_offset = 3 * d->n_regions + d->n_planes + 4 * d->n_spheres;
+  const int rough_offset = cyl_offset + 3 * nc;
+  const int q_offset = rough_offset + d->n_planes + d->n_spheres + nc + nm;
   const int np = q_offset + (nm > 0 ? nm * d->n_basis : 0);
-  for (int k = 0; k < d->n_planes + d->n_spheres + nm; ++k)
+  for (int k = 0; k < d->n_planes + d->n_spheres + nc + nm; ++k)
     US_CHECK(d->theta[rough_offset + k] >= 0 && std::isfinite(d->theta[rough_offset + k]),
              "us_scene_upload: roughness must be finite and >= 0");
   for (int r = 0; r < d->n_regions; ++r)
@@ -231,6 +239,14 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_CHECK(d->sphere_kd[k] >= 0 && d->sphere_kd[k] <= 1, "us_scene_upload: kd must be in [0, 1]");
     US_CHECK(d->theta[3 * d->n_regions + d->n_planes + 4 * k + 3] > 0, "us_scene_upload: sphere radius must be positive");
     diffuse |= d->sphere_kd[k] > 0;
+  }
+  for (int k = 0; k < nc; ++k) {
+    for (int j = 0; j < 2; ++j)
+      US_CHECK(d->cylinder_regions[2 * k + j] >= 0 && d->cylinder_regions[2 * k + j] < d->n_regions,
+               "us_scene_upload: cylinder region out of range");
+    US_CHECK(d->cylinder_kd[k] >= 0 && d->cylinder_kd[k] <= 1, "us_scene_upload: kd must be in [0, 1]");
+    US_CHECK(d->theta[cyl_offset + 3 * k + 2] > 0, "us_scene_upload: cylinder radius must be positive");
+    diffuse |= d->cylinder_kd[k] > 0;
   }
   MeshHierarchy H;
   const long nv = nm > 0 ? (long)d->n_vertices : 0, nt = nm > 0 ? (long)d->n_triangles : 0;
@@ -272,6 +288,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
   us_scene* s = new us_scene{};
   s->ctx = ctx;
   s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
+  s->n_cylinders = nc;
   s->start_region = d->start_region; s->n_params = np; s->any_diffuse = diffuse;
   s->n_meshes = nm; s->n_basis = nb; s->q_offset = q_offset; s->stack_cap = nm > 0 ? H.depth : 0;
   bool ok = hipMalloc(&s->theta, np * sizeof(double)) == hipSuccess &&
@@ -279,6 +296,8 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
             hipMalloc(&s->plane_kd, (d->n_planes + 1) * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->sphere_regions, (2 * d->n_spheres + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc(&s->sphere_kd, (d->n_spheres + 1) * sizeof(double)) == hipSuccess &&
+            hipMalloc(&s->cylinder_regions, (2 * nc + 1) * sizeof(int)) == hipSuccess &&
+            hipMalloc(&s->cylinder_kd, (nc + 1) * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->mesh_regions, (2 * nm + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc(&s->mesh_kd, (nm + 1) * sizeof(double)) == hipSuccess;
   MeshDevice& md = s->mesh;
@@ -330,6 +349,10 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_HIP(hipMemcpy(s->sphere_regions, d->sphere_regions, 2 * d->n_spheres * sizeof(int), hipMemcpyHostToDevice));
     US_HIP(hipMemcpy(s->sphere_kd, d->sphere_kd, d->n_spheres * sizeof(double), hipMemcpyHostToDevice));
   }
+  if (nc) {
+    US_HIP(hipMemcpy(s->cylinder_regions, d->cylinder_regions, 2 * nc * sizeof(int), hipMemcpyHostToDevice));
+    US_HIP(hipMemcpy(s->cylinder_kd, d->cylinder_kd, nc * sizeof(double), hipMemcpyHostToDevice));
+  }
   if (nm > 0) {
     launch_mesh_refit(md, s->theta + q_offset, nullptr);
     US_HIP(hipGetLastError());
@@ -348,6 +371,8 @@ int us_scene_destroy(us_scene* s) {
   (void)hipFree(s->plane_kd);
   (void)hipFree(s->sphere_regions);
   (void)hipFree(s->sphere_kd);
+  (void)hipFree(s->cylinder_regions);
+  (void)hipFree(s->cylinder_kd);
   (void)hipFree(s->mesh_regions);
   (void)hipFree(s->mesh_kd);
   (void)hipFree(s->tri_orig);
@@ -388,6 +413,9 @@ SceneView scene_view(const us_scene* s, const us_probe* p) {
   v.plane_kd = s->plane_kd;
   v.sphere_regions = s->sphere_regions;
   v.sphere_kd = s->sphere_kd;
+  v.n_cylinders = s->n_cylinders;
+  v.cylinder_regions = s->cylinder_regions;
+  v.cylinder_kd = s->cylinder_kd;
   v.n_regions = s->n_regions;
   v.n_planes = s->n_planes;
   v.n_spheres = s->n_spheres;

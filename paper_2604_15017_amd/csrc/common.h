@@ -12,6 +12,7 @@ constexpr int kMaxPlanes = 16;
 constexpr int kMaxSpheres = 32;
 constexpr int kMaxTxPerLaunch = 64;
 constexpr int kMaxMeshes = 32;
+constexpr int kMaxCylinders = 16;
 constexpr int kMaxBvhDepth = 38;        // inner levels of the hierarchy; the walk's LDS
                                         // stack holds at most one entry per inner level
 constexpr double kTMin = 1e-6;          // self-intersection guard [m]
@@ -62,7 +63,7 @@ __device__ __forceinline__ uint64_t event_mix(uint32_t tag, uint32_t k, uint32_t
   return z ^ (z >> 31);
 }
 enum : uint32_t { kEvHit = 1, kEvArray = 2, kEvBranch = 3, kEvNee = 4 };
-enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3, kHitMesh = 4 };
+enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3, kHitMesh = 4, kHitCylinder = 5 };
 
 // Inner node of the bounding-volume hierarchy (64 B): the fp32 boxes of both
 // children (rounded outward) and the child references. A reference c >= 0 is
@@ -102,6 +103,10 @@ struct SceneView {
   const double* sphere_kd;
   int n_regions, n_planes, n_spheres, start_region;
   double np_per_m;       // amplitude attenuation [Np/m] per dB/cm/MHz at f0
+  // cylinders along y: (x - cx)^2 + (z - cz)^2 = R^2
+  int n_cylinders;
+  const int* cylinder_regions;   // [n_cylinders][2]: inside, outside
+  const double* cylinder_kd;
   // triangle meshes (all null / zero without meshes)
   int n_meshes, n_basis;
   int stack_cap;               // LDS stack entries per thread (>= inner levels)
@@ -125,8 +130,10 @@ struct SceneLDS {
   int sreg[kMaxSpheres][2];
   int mreg[kMaxMeshes][2];
   double mkd[kMaxMeshes];
-  double prho[kMaxPlanes], srho[kMaxSpheres], mrho[kMaxMeshes];   // GGX roughness
-  int n_planes, n_spheres, n_meshes, start_region, stack_cap;
+  double cx[kMaxCylinders], cz[kMaxCylinders], cr[kMaxCylinders], ckd[kMaxCylinders];
+  int creg[kMaxCylinders][2];
+  double prho[kMaxPlanes], srho[kMaxSpheres], crho[kMaxCylinders], mrho[kMaxMeshes];   // GGX roughness
+  int n_planes, n_spheres, n_cylinders, n_meshes, start_region, stack_cap;
   bool any_diffuse;
   const BvhNode* nodes;
   const TriRec* trec;
@@ -164,23 +171,36 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
     s.mreg[i][1] = v.mesh_regions[2 * i + 1];
     s.mkd[i] = v.mesh_kd[i];
   }
-  // roughness follows the spheres: planes, spheres, meshes
-  const int orh = os + 4 * v.n_spheres;
-  for (int i = t; i < v.n_planes + v.n_spheres + v.n_meshes; i += blockDim.x) {
+  const int oc = os + 4 * v.n_spheres;
+  for (int i = t; i < v.n_cylinders; i += blockDim.x) {
+    s.cx[i] = v.theta[oc + 3 * i];
+    s.cz[i] = v.theta[oc + 3 * i + 1];
+    s.cr[i] = v.theta[oc + 3 * i + 2];
+    s.ckd[i] = v.cylinder_kd[i];
+    s.creg[i][0] = v.cylinder_regions[2 * i];
+    s.creg[i][1] = v.cylinder_regions[2 * i + 1];
+  }
+  // roughness follows the cylinders: planes, spheres, cylinders, meshes
+  const int orh = oc + 3 * v.n_cylinders;
+  const int n1 = v.n_planes, n2 = n1 + v.n_spheres, n3 = n2 + v.n_cylinders;
+  for (int i = t; i < n3 + v.n_meshes; i += blockDim.x) {
     const double r = v.theta[orh + i];
-    if (i < v.n_planes) s.prho[i] = r;
-    else if (i < v.n_planes + v.n_spheres) s.srho[i - v.n_planes] = r;
-    else s.mrho[i - v.n_planes - v.n_spheres] = r;
+    if (i < n1) s.prho[i] = r;
+    else if (i < n2) s.srho[i - n1] = r;
+    else if (i < n3) s.crho[i - n2] = r;
+    else s.mrho[i - n3] = r;
   }
   if (t == 0) {
     s.n_planes = v.n_planes;
     s.n_spheres = v.n_spheres;
+    s.n_cylinders = v.n_cylinders;
     s.n_meshes = v.n_meshes;
     s.stack_cap = v.stack_cap;
     s.start_region = v.start_region;
     bool d = false;
     for (int i = 0; i < v.n_planes; ++i) d |= v.plane_kd[i] > 0.0;
     for (int i = 0; i < v.n_spheres; ++i) d |= v.sphere_kd[i] > 0.0;
+    for (int i = 0; i < v.n_cylinders; ++i) d |= v.cylinder_kd[i] > 0.0;
     for (int i = 0; i < v.n_meshes; ++i) d |= v.mesh_kd[i] > 0.0;
     s.any_diffuse = d;
     s.nodes = v.nodes;

@@ -118,6 +118,20 @@ __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool w
     const double t = t1 > kTMin ? t1 : -b + q;
     if (t > kTMin && t < best) { best = t; h = Hit{kHitSphere, k, t}; }
   }
+  // cylinders along y: a t^2 + 2 b t + cc = 0 in the x-z plane
+  const double ca = d.x * d.x + d.z * d.z;
+  if (ca > 0.0) {
+    for (int k = 0; k < s.n_cylinders; ++k) {
+      const double ox = o.x - s.cx[k], oz = o.z - s.cz[k];
+      const double b = ox * d.x + oz * d.z;
+      const double disc = b * b - ca * (ox * ox + oz * oz - s.cr[k] * s.cr[k]);
+      if (disc < 0.0) continue;
+      const double q = sqrt(disc);
+      const double t1 = (-b - q) / ca;
+      const double t = t1 > kTMin ? t1 : (-b + q) / ca;
+      if (t > kTMin && t < best) { best = t; h = Hit{kHitCylinder, k, t}; }
+    }
+  }
   if (s.n_meshes > 0) {
     int tri = -1;
     mesh_closest(s, o, d, best, tri, stk);
@@ -131,7 +145,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool w
 // that needs more is treated as blocked).
 constexpr int kMeshLegs = 16;
 __device__ __forceinline__ int max_legs(const SceneLDS& s) {
-  return s.n_planes + 2 * s.n_spheres + kMeshLegs * s.n_meshes + 1;
+  return s.n_planes + 2 * s.n_spheres + 2 * s.n_cylinders + kMeshLegs * s.n_meshes + 1;
 }
 
 // Unit face normal of leaf-order triangle i, from the current geometry.
@@ -156,6 +170,12 @@ __device__ __forceinline__ Surface surface_of(const SceneLDS& s, const Hit& h, d
     f.other = region == s.sreg[h.index][0] ? s.sreg[h.index][1] : s.sreg[h.index][0];
     f.kd = s.skd[h.index];
     f.rho = s.srho[h.index];
+  } else if (h.kind == kHitCylinder) {
+    const double ir = 1.0 / s.cr[h.index];
+    f.n = d3{(x.x - s.cx[h.index]) * ir, 0.0, (x.z - s.cz[h.index]) * ir};
+    f.other = region == s.creg[h.index][0] ? s.creg[h.index][1] : s.creg[h.index][0];
+    f.kd = s.ckd[h.index];
+    f.rho = s.crho[h.index];
   } else {
     const int m = s.tri[h.index].w;
     f.n = tri_normal(s, h.index);

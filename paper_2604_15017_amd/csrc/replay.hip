@@ -49,7 +49,7 @@ __device__ __forceinline__ void grad_flush(const double* gsh, int n_grad, int co
 // Per-block gradient accumulator over the flat parameter vector.
 struct GradAcc {
   double* g;
-  int n_regions, n_planes, n_spheres;
+  int n_regions, n_planes, n_spheres, n_cylinders;
   double np_per_m;
   const double* vnormal;
   double* vadj;                   // per-vertex adjoint along the displacement direction (HBM)
@@ -66,12 +66,21 @@ struct GradAcc {
   // v is the adjoint of the amplitude attenuation a [Np/m]; a = alpha * np_per_m
   __device__ void a(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 2], v * np_per_m); }
   __device__ void plane(int k, double v) { if (v != 0.0) atomicAdd(&g[3 * n_regions + k], v); }
-  // roughness of plane / sphere k or of mesh k (hit kind decides)
+  // roughness of plane / sphere / cylinder k or of mesh k (hit kind decides)
   __device__ void rough(int kind, int k, double v) {
     if (v == 0.0) return;
-    const int base = 3 * n_regions + n_planes + 4 * n_spheres;
-    const int j = kind == kHitPlane ? k : (kind == kHitSphere ? n_planes + k : n_planes + n_spheres + k);
+    const int base = 3 * n_regions + n_planes + 4 * n_spheres + 3 * n_cylinders;
+    const int j = kind == kHitPlane ? k
+                : kind == kHitSphere ? n_planes + k
+                : kind == kHitCylinder ? n_planes + n_spheres + k
+                : n_planes + n_spheres + n_cylinders + k;
     atomicAdd(&g[base + j], v);
+  }
+  __device__ void cylinder(int k, double xbar, double zbar, double rbar) {
+    double* s = g + 3 * n_regions + n_planes + 4 * n_spheres + 3 * k;
+    if (xbar != 0.0) atomicAdd(s + 0, xbar);
+    if (zbar != 0.0) atomicAdd(s + 1, zbar);
+    if (rbar != 0.0) atomicAdd(s + 2, rbar);
   }
   __device__ void sphere(int k, d3 cbar, double rbar) {
     double* s = g + 3 * n_regions + n_planes + 4 * k;
@@ -152,6 +161,24 @@ __device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, i
     if (kind == kHitPlane) G.plane(idx, sbar * inv);
     obar.z -= sbar * inv;
     dbar.z -= sbar * s * inv;
+  } else if (kind == kHitCylinder) {
+    // s = (-b + sig q) / a, q = sqrt(b^2 - a cc), a = dx^2 + dz^2,
+    // b = ox dx + oz dz, cc = ox^2 + oz^2 - R^2 in the x-z plane
+    const double ox = o.x - S.cx[idx], oz = o.z - S.cz[idx];
+    const double a = d.x * d.x + d.z * d.z;
+    const double b = ox * d.x + oz * d.z;
+    const double cc = ox * ox + oz * oz - S.cr[idx] * S.cr[idx];
+    const double q = sqrt(fmax(b * b - a * cc, 0.0));
+    if (q == 0.0) return;   // tangent ray: measure zero
+    const double bbar = sbar * (-1.0 + sig * b / q) / a;
+    const double ccbar = sbar * (-sig / (2.0 * q));
+    const double abar = -sbar * (sig * cc / (2.0 * q) + s) / a;
+    const double oxbar = bbar * d.x + 2.0 * ccbar * ox, ozbar = bbar * d.z + 2.0 * ccbar * oz;
+    dbar.x += bbar * ox + 2.0 * abar * d.x;
+    dbar.z += bbar * oz + 2.0 * abar * d.z;
+    obar.x += oxbar;
+    obar.z += ozbar;
+    G.cylinder(idx, -oxbar, -ozbar, -2.0 * ccbar * S.cr[idx]);
   } else {
     const d3 oc{o.x - S.sx[idx], o.y - S.sy[idx], o.z - S.sz[idx]};
     const double b = dot(oc, d);
@@ -165,6 +192,15 @@ __device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, i
     obar = obar + ocbar;
     G.sphere(idx, -ocbar, -2.0 * ccbar * S.sr[idx]);
   }
+}
+
+// Root sign of the primary intersection with cylinder idx, as the forward chose it.
+__device__ __forceinline__ double cylinder_root(const SceneLDS& S, int idx, d3 o, d3 d) {
+  const double ox = o.x - S.cx[idx], oz = o.z - S.cz[idx];
+  const double a = d.x * d.x + d.z * d.z;
+  const double b = ox * d.x + oz * d.z;
+  const double disc = b * b - a * (ox * ox + oz * oz - S.cr[idx] * S.cr[idx]);
+  return ((-b - sqrt(disc)) / a > kTMin) ? -1.0 : 1.0;
 }
 
 // Root sign of the primary intersection, as the forward chose it.
@@ -186,6 +222,14 @@ __device__ __forceinline__ void normal_backward(const SceneLDS& S, int kind, int
     const d3 nu = cross(vtx(S.vcur, tv.y) - p0, vtx(S.vcur, tv.z) - p0);
     const d3 nub = (nbar - n * dot(nbar, n)) * (1.0 / sqrt(dot(nu, nu)));
     tri_nu_backward(S, idx, nub, d3{0, 0, 0}, G);
+    return;
+  }
+  if (kind == kHitCylinder) {   // n = ((x - cx) / R, 0, (z - cz) / R)
+    const double ir = 1.0 / S.cr[idx];
+    const double tx = nbar.x * ir, tz = nbar.z * ir;
+    xbar.x += tx;
+    xbar.z += tz;
+    G.cylinder(idx, -tx, -tz, -(nbar.x * n.x + nbar.z * n.z) * ir);
     return;
   }
   if (kind != kHitSphere) return;
@@ -355,6 +399,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
       // s_j as a function of (x, we): entering a sphere takes the near root
       double sig = -1.0;
       if (h.kind == kHitSphere) sig = (reg == S.sreg[h.index][1]) ? -1.0 : 1.0;
+      if (h.kind == kHitCylinder) sig = (reg == S.creg[h.index][1]) ? -1.0 : 1.0;
       distance_backward(S, h.kind, h.index, sig, x, we, s_cum, sbar, xb, webar, C.G);
       reg = other;
     }
@@ -558,7 +603,7 @@ __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
   int* leg_h = (int*)(legs + kLegCache * blockDim.x) + threadIdx.x;
   int* stk = leg_h + kLegCache * blockDim.x;
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
-            a.scene.n_spheres, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+            a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal, a.vadj};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
@@ -603,7 +648,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   grad_clear(gsh, a.n_grad, a.grad_copies);
   __syncthreads();
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
-            a.scene.n_spheres, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+            a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal, a.vadj};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -733,7 +778,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       G.a(reg, -wattb * watt * L);
       d3 o0b = xb;
       d0b = d0b + xb * L;
-      const double sig = h.kind == kHitSphere ? primary_root(S, h.index, o0, d0) : -1.0;
+      const double sig = h.kind == kHitSphere     ? primary_root(S, h.index, o0, d0)
+                       : h.kind == kHitCylinder ? cylinder_root(S, h.index, o0, d0)
+                                                : -1.0;
       distance_backward(S, h.kind, h.index, sig, o0, d0, L, Lb, o0b, d0b, G);
       ob = o0b;
       db = d0b;

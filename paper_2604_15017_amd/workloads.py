@@ -297,15 +297,16 @@ def cylinder_phantom(radius: float = 5e-3, depth: float = 15e-3, Z: float = 1.7,
     along the elevation axis, its axis 15 mm below the array (reading), water
     outside and a tissue-like medium of impedance Z inside (1540 m/s,
     0.5 dB/cm/MHz), GGX roughness 0.15 and a Lambertian share 0.1; the
-    128-element probe of the layered phantom, 5 plane waves over [-10, 10]
-    degrees, 128 x 256 pixels over +-12.8 mm x [0, 30] mm."""
+    128-element probe of the layered phantom with its delays at the water
+    speed, 5 plane waves over [-10, 10] degrees, 128 x 256 pixels over
+    +-12.8 mm x [0, 30] mm."""
     scene = Scene(
         regions=np.array([_water(), [1540.0, Z, 0.5]], dtype=np.float64),
         planes=np.zeros(0), plane_regions=np.zeros((0, 2), dtype=np.int32), plane_kd=np.zeros(0),
         spheres=np.zeros((0, 4)), sphere_regions=np.zeros((0, 2), dtype=np.int32), sphere_kd=np.zeros(0),
         cylinders=np.array([[0.0, depth, radius]]), cylinder_regions=np.array([[1, 0]], dtype=np.int32),
         cylinder_kd=np.array([kd]), cylinder_rough=np.array([rough]))
-    probe = layered_probe()
+    probe = dataclasses.replace(layered_probe(), c_ref=1480.0)   # delays at the water speed
     angles = np.radians(np.linspace(-10.0, 10.0, n_tx))
     grid = Grid.span(128, 256, -12.8e-3, 12.8e-3, 0.0, 30e-3)
     return Workload("cylinder_phantom", scene, probe, angles, np.arange(n_tx, dtype=np.uint32), grid,

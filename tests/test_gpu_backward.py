@@ -133,6 +133,17 @@ def test_vjp_rough_layered_phantom(L, ctx):
     assert np.count_nonzero(ref[rough]) >= 6
 
 
+def test_vjp_cylinder_phantom(L, ctx):
+    """Cylinder axis, radius and roughness through primary hits, crossings of
+    secondary rays and both roots of the circle."""
+    wl = W.cylinder_phantom().replace(rays_per_elem=128)
+    g, ref = vjp_parity(L, ctx, wl, "cylinder phantom")
+    sc = wl.scene
+    for j in (sc.idx_cylinder(0, "x"), sc.idx_cylinder(0, "z"), sc.idx_cylinder(0, "R"),
+              sc.idx_rough("cylinder", 0)):
+        assert ref[j] != 0.0
+
+
 def test_vjp_ray_subsets_add_up(L, ctx):
     import torch
     wl = W.layered_phantom().replace(rays_per_elem=32, angles=np.radians([-3.0]),

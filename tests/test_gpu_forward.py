@@ -89,6 +89,41 @@ def test_rough_layered_phantom_full_size(L, ctx):
     check_transport(L, ctx, W.rough_layered_phantom())
 
 
+def test_cylinder_phantom_full_size(L, ctx):
+    """The hollow cylinder (radius, axis, roughness, Lambertian share): 5 x 2^20 rays."""
+    check_transport(L, ctx, W.cylinder_phantom())
+
+
+def test_cylinder_walls_in_the_bmode_image(L, ctx):
+    """The paper's forward check: in the B-mode image of the hollow cylinder
+    (R = 5 mm, axis 15 mm deep) the brightest pixel of the central columns is
+    the near wall at z_c - R, and the far wall, seen through the cylinder's
+    medium with the delays of the water speed, at z_c - R + 2 R c_water / c_in;
+    the measured diameter (c_in / c_water times the wall distance) is 2 R to
+    within a pixel."""
+    import torch
+    wl = W.cylinder_phantom()
+    sc, g = wl.scene, wl.grid
+    _, zc, R = sc.cylinders[0]
+    c_w, c_in = sc.regions[0, 0], sc.regions[1, 0]
+    scene, probe = L.Scene(ctx, sc), L.Probe(ctx, wl.probe)
+    rf = L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces)
+    iq = L.us_beamform(ctx, probe, wl.grid, wl.angles, wl.tx_ids, rf)
+    B = L.us_bmode(ctx, iq, wl.dr_db)
+    torch.cuda.synchronize()
+    B = B.cpu().numpy()
+    x = g.x0 + g.dx * np.arange(g.n_x)
+    z = g.z0 + g.dz * np.arange(g.n_z)
+    col = B[np.abs(x) < 0.5e-3].max(axis=0)          # central columns, per depth
+    z_near = z[np.argmax(np.where(z < zc, col, -np.inf))]
+    z_far = z[np.argmax(np.where(z > zc, col, -np.inf))]
+    print(f"near wall {z_near * 1e3:.3f} mm (expected {(zc - R) * 1e3:.3f}), far wall {z_far * 1e3:.3f} mm "
+          f"(expected {(zc - R + 2 * R * c_w / c_in) * 1e3:.3f}), peaks {col.max():.1f} dB", flush=True)
+    assert abs(z_near - (zc - R)) <= 1.5 * g.dz
+    assert abs(z_far - (zc - R + 2 * R * c_w / c_in)) <= 2.5 * g.dz
+    assert abs((z_far - z_near) * c_in / c_w - 2 * R) <= 3 * g.dz
+
+
 def test_layered_phantom_full_size(L, ctx):
     """The benchmark workload itself: 11 transmits x 2^20 rays, 8 bounces."""
     check_transport(L, ctx, W.layered_phantom())
