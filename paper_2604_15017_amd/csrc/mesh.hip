@@ -35,7 +35,7 @@ struct TmpNode {
   int depth = 0;
 };
 
-constexpr int kLeafMax = 4;
+constexpr int kLeafMax = 2;
 constexpr int kBins = 16;
 
 struct Builder {
