@@ -2,6 +2,8 @@
 // of every RF channel (FFT in LDS), plane-wave delay-and-sum (Eq. das),
 // envelope and log compression, and the adjoints of all three (Eq.
 // das_adjoint as a per-sample gather, no atomics).
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace usrt {
@@ -471,6 +473,56 @@ __global__ __launch_bounds__(256) void k_das_adjoint(const float2* __restrict__ 
   }
 }
 
+// Adjoint of DAS for one RF row (transmit, element), column by column: the
+// block's threads take the pixels of one column (coalesced reads of dL/dI)
+// and add each pixel's two tent weights into the row's accumulators in LDS.
+// Down a column kappa grows by more than two samples per pixel (checked by
+// the launcher: dz fs / c_ref cos(theta) > 2 and z0 >= 0), so the pixels of
+// one column touch disjoint sample pairs and need no atomics; a barrier
+// separates the columns. Every sample then sums its contributions in column
+// order, as the per-sample gather does.
+__global__ __launch_bounds__(256) void k_das_adjoint_cols(const float2* __restrict__ giq,
+                                                          float2* __restrict__ gA, ProbeView p,
+                                                          GridView g, TxTable tx, int tx_base) {
+  const int txl = blockIdx.x / p.n_elem;
+  const int e = blockIdx.x % p.n_elem;
+  extern __shared__ float2 acc_row[];   // [n_t]
+  for (int k = threadIdx.x; k < p.n_t; k += blockDim.x) acc_row[k] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  const double sa = tx.sin_a[txl], ca = tx.cos_a[txl];
+  const double s_per_m = p.fs / p.c_ref;
+  const double xe = ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
+  for (int a = 0; a < g.n_x; ++a) {
+    const double x = g.x0 + a * g.dx;
+    const double dx = x - xe;
+    const float2* col = giq + (long)a * g.n_z;
+    for (int b = threadIdx.x; b < g.n_z; b += blockDim.x) {
+      const double z = g.z0 + b * g.dz;
+      const double kap = (x * sa + z * ca + sqrt(dx * dx + z * z)) * s_per_m;
+      const double k0d = floor(kap);
+      if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
+      const int k0 = (int)k0d;
+      const float f = (float)(kap - k0d);
+      const float2 gv = col[b];
+      if (k0 >= 0) {
+        float2 v = acc_row[k0];
+        v.x = fmaf(1.0f - f, gv.x, v.x);
+        v.y = fmaf(1.0f - f, gv.y, v.y);
+        acc_row[k0] = v;
+      }
+      if (k0 + 1 < p.n_t) {
+        float2 v = acc_row[k0 + 1];
+        v.x = fmaf(f, gv.x, v.x);
+        v.y = fmaf(f, gv.y, v.y);
+        acc_row[k0 + 1] = v;
+      }
+    }
+    __syncthreads();
+  }
+  float2* row = gA + ((long)(tx_base + txl) * p.n_elem + e) * p.n_t;
+  for (int k = threadIdx.x; k < p.n_t; k += blockDim.x) row[k] = acc_row[k];
+}
+
 // L = (1/n) sum [l1 |d| + l2 d^2], d = B - R; dL/dB = (l1 sign(d) + 2 l2 d) / n.
 __global__ __launch_bounds__(256) void k_image_loss(const float* __restrict__ b,
                                                     const float* __restrict__ ref, long n,
@@ -571,6 +623,17 @@ void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long*
 void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, const GridView& g,
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s) {
   const dim3 grid((unsigned)(n_tx_group * p.n_elem)), block(256);
+  // column kernel when a column's pixels cannot share a tent sample: kappa
+  // grows by at least dz fs / c_ref cos(theta) per pixel for z >= 0
+  double ca_min = 1.0;
+  for (int i = 0; i < n_tx_group; ++i) ca_min = std::min(ca_min, tx.cos_a[i]);
+  const bool cols_ok = g.z0 >= 0.0 && g.dz * p.fs / p.c_ref * ca_min > 2.0 + 1e-9 &&
+                       (size_t)p.n_t * sizeof(float2) <= 64 * 1024;
+  if (cols_ok) {
+    hipLaunchKernelGGL(k_das_adjoint_cols, grid, block, (size_t)p.n_t * sizeof(float2), s, g_iq, g_A, p, g,
+                       tx, tx_base);
+    return;
+  }
   const int per_thread = (p.n_t + 255) / 256;
   const int k_s = per_thread <= 8 ? 8 : (per_thread <= 16 ? 16 : 32);
   const size_t lds = (size_t)k_s * 256 * sizeof(float2);   // 64 KB at most

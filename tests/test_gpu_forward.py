@@ -326,20 +326,24 @@ def test_bmode_vjp_against_oracle(L, ctx):
     assert rel_l2(gc, ref) <= 1e-4
 
 
-@pytest.mark.parametrize("case", ["layered_3tx", "two_layer_40tx_ragged"])
+@pytest.mark.parametrize("case", ["layered_3tx", "two_layer_40tx_ragged", "fine_grid_gather"])
 def test_beamform_vjp_against_oracle(L, ctx, case):
-    """Transposed DAS + analytic VJP. The second case (40 transmits) makes the
-    windowed adjoint shrink its sample windows to fit LDS, on a ragged grid
-    that starts below the array."""
+    """Transposed DAS + analytic VJP. The first two cases take the column
+    kernel (pixels of a column more than two samples apart), the second with
+    40 transmits on a ragged grid starting 2 mm below the array; the third,
+    with 0.03 mm pixels (under one sample apart), the per-sample gather."""
     import torch
     rng = np.random.default_rng(1)
     if case == "layered_3tx":
         wl = W.layered_phantom().replace(angles=np.radians([-10.0, 2.0, 10.0]),
                                          tx_ids=np.arange(3, dtype=np.uint32))
-    else:
+    elif case == "two_layer_40tx_ragged":
         wl = W.two_layer().replace(angles=np.radians(np.linspace(-12.0, 12.0, 40)),
                                    tx_ids=np.arange(40, dtype=np.uint32),
                                    grid=W.Grid(101, 173, -15e-3, 0.3e-3, 2.0e-3, 0.2e-3))
+    else:
+        wl = W.layered_phantom().replace(angles=np.radians([-7.0, 4.0]), tx_ids=np.arange(2, dtype=np.uint32),
+                                         grid=W.Grid(61, 301, -6e-3, 0.2e-3, 18e-3, 0.03e-3))
     gI = rng.standard_normal((wl.grid.n_x, wl.grid.n_z)) + 1j * rng.standard_normal((wl.grid.n_x, wl.grid.n_z))
     ref = oracle.analytic_vjp(oracle.das_vjp(gI, wl.probe, wl.grid, wl.angles, wl.probe.n_t))
     probe = L.Probe(ctx, wl.probe)
