@@ -86,8 +86,9 @@ typedef struct us_probe_desc {
  * three vertices of that mesh). Vertex v moves along its unit direction
  * vnormal[v] by sum_j q[vmesh[v]][j] vbasis[v][j]; faces are flat. At most
  * 32 meshes and 2^27 - 1 triangles; zero-area triangles are rejected. The library builds a
- * bounding-volume hierarchy on upload (rejected with US_EINVAL if deeper than
- * 38 levels) and refits it on every us_scene_set_params. */
+ * 4-wide bounding-volume hierarchy on upload (rejected with US_EINVAL if too
+ * deep: its binary form over 38 levels, or over 20 levels of 4-wide nodes)
+ * and refits it on every us_scene_set_params. */
 typedef struct us_scene_desc {
   int32_t n_regions, n_planes, n_spheres;
   const double* theta;

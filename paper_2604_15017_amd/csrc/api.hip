@@ -282,7 +282,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
       US_CHECK(cx * cx + cy * cy + cz * cz > 0.0, "us_scene_upload: zero-area triangle");
     }
     US_CHECK(build_mesh_bvh(d->vertices, nv, d->triangles, d->tmesh, nt, H) == 0,
-             "us_scene_upload: mesh hierarchy deeper than 38 levels (degenerate triangle set)");
+             "us_scene_upload: mesh hierarchy too deep (degenerate triangle set)");
   }
   US_HIP(hipSetDevice(ctx->device));
   us_scene* s = new us_scene{};
@@ -290,7 +290,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
   s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
   s->n_cylinders = nc;
   s->start_region = d->start_region; s->n_params = np; s->any_diffuse = diffuse;
-  s->n_meshes = nm; s->n_basis = nb; s->q_offset = q_offset; s->stack_cap = nm > 0 ? H.depth : 0;
+  s->n_meshes = nm; s->n_basis = nb; s->q_offset = q_offset; s->stack_cap = nm > 0 ? 3 * H.depth : 0;
   bool ok = hipMalloc(&s->theta, np * sizeof(double)) == hipSuccess &&
             hipMalloc(&s->plane_regions, (2 * d->n_planes + 1) * sizeof(int)) == hipSuccess &&
             hipMalloc(&s->plane_kd, (d->n_planes + 1) * sizeof(double)) == hipSuccess &&

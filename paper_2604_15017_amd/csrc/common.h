@@ -13,8 +13,8 @@ constexpr int kMaxSpheres = 32;
 constexpr int kMaxTxPerLaunch = 64;
 constexpr int kMaxMeshes = 32;
 constexpr int kMaxCylinders = 16;
-constexpr int kMaxBvhDepth = 38;        // inner levels of the hierarchy; the walk's LDS
-                                        // stack holds at most one entry per inner level
+constexpr int kMaxBvhDepth = 38;        // levels of the binary tree the hierarchy is built as
+constexpr int kMaxBvhStack = 60;        // LDS stack entries of the 4-wide walk: three per level
 constexpr double kTMin = 1e-6;          // self-intersection guard [m]
 constexpr double kPi = 3.14159265358979323846;
 
@@ -65,15 +65,19 @@ __device__ __forceinline__ uint64_t event_mix(uint32_t tag, uint32_t k, uint32_t
 enum : uint32_t { kEvHit = 1, kEvArray = 2, kEvBranch = 3, kEvNee = 4 };
 enum : int { kHitNone = 0, kHitPlane = 1, kHitSphere = 2, kHitArray = 3, kHitMesh = 4, kHitCylinder = 5 };
 
-// Inner node of the bounding-volume hierarchy (64 B): the fp32 boxes of both
-// children (rounded outward) and the child references. A reference c >= 0 is
-// an inner node; c < 0 is a leaf holding the n = (~c) & 15 triangles starting
-// at (~c) >> 4 in leaf order (n = 0: empty).
-struct BvhNode {
-  float lo_l[3], hi_l[3];
-  float lo_r[3], hi_r[3];
-  int left, right, pad0, pad1;
+// Inner node of the 4-wide bounding-volume hierarchy (128 B): the fp32 boxes
+// of up to four children (rounded outward), one coordinate per 16-byte row,
+// and the child references. A reference c >= 0 is an inner node; c < 0 is a
+// leaf holding the n = (~c) & 15 triangles starting at (~c) >> 4 in leaf
+// order; an unused slot is the empty leaf ~0 with a point box far away.
+struct alignas(16) BvhNode {
+  float lox[4], loy[4], loz[4], hix[4], hiy[4], hiz[4];
+  int child[4];
+  int pad[4];
 };
+static_assert(sizeof(BvhNode) == 128, "hierarchy node layout");
+constexpr int kEmptyChild = ~0;
+constexpr float kFarBox = 1e30f;
 constexpr int kLeafCap = 15;
 
 // Leaf-order triangle as the walk reads it: p0 and the edges p1 - p0,
@@ -109,7 +113,7 @@ struct SceneView {
   const double* cylinder_kd;
   // triangle meshes (all null / zero without meshes)
   int n_meshes, n_basis;
-  int stack_cap;               // LDS stack entries per thread (>= inner levels)
+  int stack_cap;               // LDS stack entries per thread (3 per inner level)
   const int* mesh_regions;     // [n_meshes][2]: inside, outside
   const double* mesh_kd;       // [n_meshes]
   const BvhNode* nodes;

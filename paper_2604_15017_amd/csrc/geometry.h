@@ -46,12 +46,13 @@ __device__ __forceinline__ double rec_distance(const TriRec& r, d3 o, d3 d) {
   return dot(e2, qv) * inv;
 }
 
-// Closest triangle in (kTMin, best) by walking the hierarchy near child
-// first. One step handles one inner node (both child boxes tested against the
-// ray in fp32; the farther of two hit children is pushed) or one leaf (its
-// triangles intersected in fp64). The stack lives in LDS, interleaved across
-// the block's threads (entry i of this thread at stk[i * blockDim.x]); it
-// holds at most one entry per inner level.
+// Closest triangle in (kTMin, best) by walking the 4-wide hierarchy near
+// child first. One step handles one inner node (its four child boxes tested
+// against the ray in fp32, the hit children ordered by entry distance: the
+// nearest is visited next, the others pushed farthest first) or one leaf
+// (its triangles intersected in fp64). The stack lives in LDS, interleaved
+// across the block's threads (entry i of this thread at stk[i * blockDim.x]);
+// it holds at most three entries per inner level.
 __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, double& best, int& best_tri,
                                              int* stk) {
   constexpr float kPad = 1e-6f;
@@ -65,18 +66,31 @@ __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, doub
     if (cur >= 0) {
       const BvhNode n = s.nodes[cur];
       const float lim = (float)best * 1.0001f + kPad;
-      float tl, tr;
-      const bool hl = slab(n.lo_l, n.hi_l, ox, oy, oz, ix, iy, iz, lim, &tl);
-      const bool hr = slab(n.lo_r, n.hi_r, ox, oy, oz, ix, iy, iz, lim, &tr);
-      if (hl && hr) {
-        const bool left_first = tl <= tr;
-        // the build bounds the inner depth by stack_cap, so the push always fits
-        if (sp < s.stack_cap) { stk[sp * step] = left_first ? n.right : n.left; ++sp; }
-        cur = left_first ? n.left : n.right;
+      float t[4];
+      int r[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float lo[3] = {n.lox[j], n.loy[j], n.loz[j]}, hi[3] = {n.hix[j], n.hiy[j], n.hiz[j]};
+        float tj;
+        t[j] = slab(lo, hi, ox, oy, oz, ix, iy, iz, lim, &tj) ? tj : INFINITY;
+        r[j] = n.child[j];
+      }
+      // sort the four (distance, child) pairs: a five-exchange network
+#define USRT_CX(a, b)                                                      \
+      if (t[b] < t[a]) {                                                   \
+        const float tt = t[a]; t[a] = t[b]; t[b] = tt;                     \
+        const int rr = r[a]; r[a] = r[b]; r[b] = rr;                       \
+      }
+      USRT_CX(0, 1) USRT_CX(2, 3) USRT_CX(0, 2) USRT_CX(1, 3) USRT_CX(1, 2)
+#undef USRT_CX
+      if (t[0] != INFINITY) {
+        // the build bounds the depth by stack_cap / 3, so the pushes always fit
+        if (t[3] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[3]; ++sp; }
+        if (t[2] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[2]; ++sp; }
+        if (t[1] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[1]; ++sp; }
+        cur = r[0];
         continue;
       }
-      if (hl) { cur = n.left; continue; }
-      if (hr) { cur = n.right; continue; }
     } else {
       const int first = (~cur) >> 4, cnt = (~cur) & 15;
       for (int i = first; i < first + cnt; ++i) {

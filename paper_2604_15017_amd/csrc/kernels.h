@@ -127,10 +127,11 @@ struct MeshHierarchy {
   std::vector<int4> tri;
   std::vector<int> tri_orig;
   std::vector<int> level_begin;   // inner nodes of depth l: [level_begin[l], level_begin[l + 1])
-  int depth = 0;                  // number of inner levels
+  int depth = 0;                  // number of inner levels of the 4-wide tree
 };
-// Returns 0, or -1 if the tree would exceed kMaxBvhDepth (or a leaf at that
-// depth would hold more than kLeafCap triangles).
+// Returns 0, or -1 if the binary tree would exceed kMaxBvhDepth (or a leaf at
+// that depth would hold more than kLeafCap triangles), or the 4-wide walk
+// would need more than kMaxBvhStack stack entries.
 int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
                    const int32_t* tmesh, long n_tri, MeshHierarchy& out);
 

@@ -1,9 +1,11 @@
 // Closed triangle meshes (the anatomy scenes of Sec. 4): bounding-volume
-// hierarchy built once on the host from the rest shape (binned surface-area
-// heuristic), then refitted on the device whenever the displacement
-// coefficients change, so that the topology stays fixed and only the boxes
-// move. Nodes are numbered breadth first: the nodes of one depth form a
-// contiguous range and a refit is one launch per depth, deepest first.
+// hierarchy built once on the host from the rest shape (binary tree by the
+// binned surface-area heuristic, collapsed to 4-wide nodes by pulling up the
+// grandchildren of the largest inner children), then refitted on the device
+// whenever the displacement coefficients change, so that the topology stays
+// fixed and only the boxes move. Nodes are numbered breadth first: the nodes
+// of one depth form a contiguous range and a refit is one launch per depth,
+// deepest first.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -32,6 +34,14 @@ struct Box {
 struct TmpNode {
   int left = -1, right = -1;   // children (temporary numbering), -1 for a leaf
   int first = 0, count = 0;    // leaf range in the permutation
+  int depth = 0;
+  double area = 0.0;           // surface area of the node's box
+};
+
+// 4-wide node before numbering: binary-tree ids of its children.
+struct Wide {
+  int slot[4];
+  int n = 0;
   int depth = 0;
 };
 
@@ -116,6 +126,7 @@ struct Builder {
     max_depth_seen = std::max(max_depth_seen, depth);
     Box bounds;
     for (int i = first; i < first + count; ++i) bounds.add(tbox[perm[i]]);
+    nodes[id].area = bounds.area();
     bool halve = false;
     const int nl = split(first, count, bounds, depth, &halve);
     if (halve) {
@@ -162,46 +173,66 @@ int build_mesh_bvh(const double* vertices, long n_vertices, const int32_t* tris,
   b.build(0, (int)n_tri, 0);
   if (b.max_depth_seen > kMaxBvhDepth || b.too_deep) return -1;
 
-  // inner nodes in breadth-first order, so that every depth is a contiguous
-  // range; leaves become references held by their parents
+  // collapse to 4-wide nodes: a node takes its two children, then repeatedly
+  // replaces its inner child of largest area by that child's two children
   std::vector<TmpNode>& T = b.nodes;
-  std::vector<int> order;   // temporary ids of the inner nodes, breadth first
-  if (T[0].left < 0) {      // a single leaf: wrap it in a root with an empty sibling
-    TmpNode empty;
-    empty.first = 0; empty.count = 0; empty.depth = 1;
-    T[0].depth = 1;
-    TmpNode root;
-    root.left = 0; root.right = (int)T.size() + 1; root.depth = 0;
-    T.push_back(root);
-    T.push_back(empty);
-    order.push_back((int)T.size() - 2);
-  } else {
-    order.push_back(0);
+  std::vector<Wide> W;
+  auto leaf_ref = [&](int id) { return ~((T[id].first << 4) | T[id].count); };
+  auto make_wide = [&](int bin, int depth) {
+    Wide w;
+    w.depth = depth;
+    if (T[bin].left < 0) {          // a single leaf as the whole tree
+      w.slot[0] = bin;
+      w.n = 1;
+    } else {
+      w.slot[0] = T[bin].left;
+      w.slot[1] = T[bin].right;
+      w.n = 2;
+      while (w.n < 4) {
+        int best = -1;
+        for (int j = 0; j < w.n; ++j)
+          if (T[w.slot[j]].left >= 0 && (best < 0 || T[w.slot[j]].area > T[w.slot[best]].area)) best = j;
+        if (best < 0) break;
+        const int x = w.slot[best];
+        w.slot[best] = T[x].left;
+        w.slot[w.n++] = T[x].right;
+      }
+    }
+    W.push_back(w);
+    return (int)W.size() - 1;
+  };
+  make_wide(0, 0);
+  // breadth first: the children of node i are created while node i is read
+  std::vector<int> wchild;   // per wide node, 4 entries: wide id of an inner slot, or -1
+  for (size_t i = 0; i < W.size(); ++i) {
+    for (int j = 0; j < 4; ++j) wchild.push_back(-1);
+    for (int j = 0; j < W[i].n; ++j) {
+      const int x = W[i].slot[j];
+      if (T[x].left >= 0) {
+        const int w = make_wide(x, W[i].depth + 1);
+        wchild[4 * i + j] = w;
+      }
+    }
   }
-  std::vector<int> newid(T.size(), -1);
-  for (size_t head = 0; head < order.size(); ++head) {
-    const TmpNode& t = T[order[head]];
-    newid[order[head]] = (int)head;
-    if (T[t.left].left >= 0) order.push_back(t.left);
-    if (T[t.right].left >= 0) order.push_back(t.right);
-  }
-  const int n = (int)order.size();
+  // breadth-first numbering (creation order is already breadth first)
+  const int n = (int)W.size();
   out.level_begin.assign(1, 0);
   for (int i = 1; i < n; ++i)
-    if (T[order[i]].depth != T[order[i - 1]].depth) out.level_begin.push_back(i);
+    if (W[i].depth != W[i - 1].depth) out.level_begin.push_back(i);
   out.level_begin.push_back(n);
   out.nodes.resize(n);
   for (int k = 0; k < n; ++k) {
-    const TmpNode& t = T[order[k]];
     BvhNode& nd = out.nodes[k];
-    for (int j = 0; j < 3; ++j) { nd.lo_l[j] = nd.hi_l[j] = nd.lo_r[j] = nd.hi_r[j] = 0.0f; }
-    nd.pad0 = nd.pad1 = 0;
-    const TmpNode& l = T[t.left];
-    const TmpNode& r = T[t.right];
-    nd.left = l.left >= 0 ? newid[t.left] : ~((l.first << 4) | l.count);
-    nd.right = r.left >= 0 ? newid[t.right] : ~((r.first << 4) | r.count);
+    for (int j = 0; j < 4; ++j) {
+      nd.lox[j] = nd.loy[j] = nd.loz[j] = nd.hix[j] = nd.hiy[j] = nd.hiz[j] = kFarBox;
+      nd.pad[j] = 0;
+      if (j >= W[k].n) nd.child[j] = kEmptyChild;
+      else if (wchild[4 * k + j] >= 0) nd.child[j] = wchild[4 * k + j];
+      else nd.child[j] = leaf_ref(W[k].slot[j]);
+    }
   }
-  out.depth = (int)out.level_begin.size() - 1;   // inner levels = stack entries needed
+  out.depth = (int)out.level_begin.size() - 1;
+  if (3 * out.depth > kMaxBvhStack) return -1;
   out.tri.resize(n_tri);
   out.tri_orig.resize(n_tri);
   for (long i = 0; i < n_tri; ++i) {
@@ -245,9 +276,18 @@ __device__ __forceinline__ float round_up(double x) {
 // level and are already refitted.
 __device__ __forceinline__ void child_box(const BvhNode* nodes, int ref, const int4* tri,
                                           const double* vcur, float* lo, float* hi) {
-  if (ref >= 0) {
+  if (ref == kEmptyChild) {   // unused slot: a point far away
+    for (int k = 0; k < 3; ++k) lo[k] = hi[k] = kFarBox;
+    return;
+  }
+  if (ref >= 0) {   // union of the used slots of an inner child (refitted one level deeper)
     const BvhNode c = nodes[ref];
-    for (int k = 0; k < 3; ++k) { lo[k] = fminf(c.lo_l[k], c.lo_r[k]); hi[k] = fmaxf(c.hi_l[k], c.hi_r[k]); }
+    for (int k = 0; k < 3; ++k) { lo[k] = INFINITY; hi[k] = -INFINITY; }
+    for (int j = 0; j < 4; ++j) {
+      if (c.child[j] == kEmptyChild) continue;
+      lo[0] = fminf(lo[0], c.lox[j]); lo[1] = fminf(lo[1], c.loy[j]); lo[2] = fminf(lo[2], c.loz[j]);
+      hi[0] = fmaxf(hi[0], c.hix[j]); hi[1] = fmaxf(hi[1], c.hiy[j]); hi[2] = fmaxf(hi[2], c.hiz[j]);
+    }
     return;
   }
   double l[3] = {INFINITY, INFINITY, INFINITY}, h[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -271,8 +311,12 @@ __global__ __launch_bounds__(256) void k_refit(BvhNode* __restrict__ nodes, int 
   const int i = begin + (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (i >= end) return;
   BvhNode nd = nodes[i];
-  child_box(nodes, nd.left, tri, vcur, nd.lo_l, nd.hi_l);
-  child_box(nodes, nd.right, tri, vcur, nd.lo_r, nd.hi_r);
+  for (int j = 0; j < 4; ++j) {
+    float lo[3], hi[3];
+    child_box(nodes, nd.child[j], tri, vcur, lo, hi);
+    nd.lox[j] = lo[0]; nd.loy[j] = lo[1]; nd.loz[j] = lo[2];
+    nd.hix[j] = hi[0]; nd.hiy[j] = hi[1]; nd.hiz[j] = hi[2];
+  }
   nodes[i] = nd;
 }
 
