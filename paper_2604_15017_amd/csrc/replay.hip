@@ -93,6 +93,13 @@ struct GradAcc {
 
 __device__ __forceinline__ d3 operator-(d3 a) { return {-a.x, -a.y, -a.z}; }
 
+// Adjoints of one crossing's triangle collected from its distance and its
+// normal, so that the three vertices take one atomic update each.
+struct TriAdj {
+  d3 nub{0, 0, 0};    // adjoint of nu = (p1 - p0) x (p2 - p0)
+  d3 p0b{0, 0, 0};    // direct adjoint of p0
+};
+
 // Adjoint through nu = (p1 - p0) x (p2 - p0) into the three vertices.
 __device__ __forceinline__ void tri_nu_backward(const SceneLDS& S, int i, d3 nub, d3 p0b_extra,
                                                 GradAcc& G) {
@@ -143,7 +150,7 @@ __device__ __forceinline__ void tent_adjoint(const float* row, int n_t, double f
 // s = -b + sig sqrt(b^2 - cc), b = (o - C).d, cc = |o - C|^2 - R^2.
 __device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, int idx, double sig,
                                                   d3 o, d3 d, double s, double sbar, d3& obar,
-                                                  d3& dbar, GradAcc& G) {
+                                                  d3& dbar, GradAcc& G, TriAdj& ta) {
   if (sbar == 0.0) return;
   if (kind == kHitMesh) {   // s = nu.(p0 - o) / nu.d
     const int4 tv = S.tri[idx];
@@ -153,7 +160,8 @@ __device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, i
     const double numb = sbar / den, denb = -sbar * s / den;
     obar = obar - nu * numb;
     dbar = dbar + nu * denb;
-    tri_nu_backward(S, idx, (p0 - o) * numb + d * denb, nu * numb, G);
+    ta.nub = ta.nub + (p0 - o) * numb + d * denb;
+    ta.p0b = ta.p0b + nu * numb;
     return;
   }
   if (kind == kHitPlane || kind == kHitArray) {
@@ -215,13 +223,12 @@ __device__ __forceinline__ double primary_root(const SceneLDS& S, int idx, d3 o,
 // Adjoint of the geometric normal at x on the hit surface (plane: constant;
 // sphere: n = (x - C) / R). nbar is the adjoint of n; adds to xbar.
 __device__ __forceinline__ void normal_backward(const SceneLDS& S, int kind, int idx, d3 n,
-                                                d3 nbar, d3& xbar, GradAcc& G) {
+                                                d3 nbar, d3& xbar, GradAcc& G, TriAdj& ta) {
   if (kind == kHitMesh) {   // n = nu / |nu|
     const int4 tv = S.tri[idx];
     const d3 p0 = vtx(S.vcur, tv.x);
     const d3 nu = cross(vtx(S.vcur, tv.y) - p0, vtx(S.vcur, tv.z) - p0);
-    const d3 nub = (nbar - n * dot(nbar, n)) * (1.0 / sqrt(dot(nu, nu)));
-    tri_nu_backward(S, idx, nub, d3{0, 0, 0}, G);
+    ta.nub = ta.nub + (nbar - n * dot(nbar, n)) * (1.0 / sqrt(dot(nu, nu)));
     return;
   }
   if (kind == kHitCylinder) {   // n = ((x - cx) / R, 0, (z - cz) / R)
@@ -391,7 +398,8 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
       webar = webar - g.nr * cibar;
       const double sgn = dot(sf.n, we) > 0.0 ? -1.0 : 1.0;
       d3 pbar{0, 0, 0};
-      normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, pbar, C.G);
+      TriAdj ta;
+      normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, pbar, C.G, ta);
       // p_j = x + we s_j
       xb = xb + pbar;
       webar = webar + pbar * s_cum;
@@ -400,7 +408,8 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
       double sig = -1.0;
       if (h.kind == kHitSphere) sig = (reg == S.sreg[h.index][1]) ? -1.0 : 1.0;
       if (h.kind == kHitCylinder) sig = (reg == S.creg[h.index][1]) ? -1.0 : 1.0;
-      distance_backward(S, h.kind, h.index, sig, x, we, s_cum, sbar, xb, webar, C.G);
+      distance_backward(S, h.kind, h.index, sig, x, we, s_cum, sbar, xb, webar, C.G, ta);
+      if (h.kind == kHitMesh) tri_nu_backward(S, h.index, ta.nub, ta.p0b, C.G);
       reg = other;
     }
   }
@@ -674,6 +683,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       const double watt = st.watt;
       const d3 x = st.x;
       d3 xb{0, 0, 0}, d0b{0, 0, 0};
+      TriAdj ta;   // the hit triangle's adjoints from the normal and the distance
       double tpb = 0.0, wattb = 0.0;
       if (h.kind == kHitArray) {
         const double half = 0.5 * (double)P.n_elem * P.pitch;
@@ -770,7 +780,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
         nrb = nrb - d0 * cib;
         d0b = d0b - f.nr * cib;
         const double sgn = dot(sf.n, d0) > 0.0 ? -1.0 : 1.0;
-        normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, xb, G);
+        normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, xb, G, ta);
       }
       // t' = t + L / c, w_att = w exp(-a L), x = o + d L, L = distance(o, d)
       const double Lb = tpb / c1 - wattb * watt * ar + dot(xb, d0);
@@ -781,7 +791,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       const double sig = h.kind == kHitSphere     ? primary_root(S, h.index, o0, d0)
                        : h.kind == kHitCylinder ? cylinder_root(S, h.index, o0, d0)
                                                 : -1.0;
-      distance_backward(S, h.kind, h.index, sig, o0, d0, L, Lb, o0b, d0b, G);
+      distance_backward(S, h.kind, h.index, sig, o0, d0, L, Lb, o0b, d0b, G, ta);
+      if (h.kind == kHitMesh) tri_nu_backward(S, h.index, ta.nub, ta.p0b, G);
       ob = o0b;
       db = d0b;
       tb = tpb;
