@@ -496,6 +496,9 @@ void carve_queues(Carver& c, long cap, RayQueue* q0, RayQueue* q1, SecondaryQueu
 // chunks that the per-step launches stay long.
 constexpr long kReplayChunk = 1L << 23;
 
+// Vertex adjoints per copy, rounded up to 256 bytes.
+long vadj_stride(const us_scene* scene) { return ((long)scene->mesh.n_vertices + 32) & ~31L; }
+
 // Workspace of the replay backward for chunks of `cap` rays: dL/dh, the mesh
 // vertex adjoints, the per-block gradient rows, the step records, the queue
 // of diffuse interactions with its step offsets, the per-step counts and the
@@ -507,7 +510,7 @@ size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_
   Carver c{base};
   float* g = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   if (gh) *gh = g;
-  double* va = c.take<double>((size_t)scene->mesh.n_vertices + 1);
+  double* va = c.take<double>((size_t)kVadjCopies * vadj_stride(scene));
   if (vadj) *vadj = va;
   double* gp = c.take<double>((size_t)kMaxReplayBlocks * scene->q_offset);
   if (g_part) *g_part = gp;
@@ -863,7 +866,8 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   RayQueue q0, q1;
   replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &a.vadj, &a.g_part,
                &q0, &q1, &a.counts);
-  if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2 * scene->mesh.n_vertices, 0u, s);
+  a.vadj_stride = vadj_stride(scene);
+  if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2L * kVadjCopies * a.vadj_stride, 0u, s);
   launch_fill_u32((uint32_t*)a.g_part, 2L * kMaxReplayBlocks * scene->q_offset, 0u, s);
   {
     Timed tm(ctx, "pulse_adjoint", s);
@@ -915,7 +919,7 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   launch_grad_reduce(a.g_part, a.n_grad, g_theta_dev, s);
   if (scene->n_meshes > 0) {
     Timed tm(ctx, "basis_gather", s);
-    launch_basis_gather(a.vadj, scene->mesh.vbasis, scene->mesh.vbeg, scene->n_meshes, scene->n_basis,
+    launch_basis_gather(a.vadj, a.vadj_stride, scene->mesh.vbasis, scene->mesh.vbeg, scene->n_meshes, scene->n_basis,
                         g_theta_dev + scene->q_offset, s);
   }
   US_HIP(hipGetLastError());

@@ -92,7 +92,8 @@ struct ReplayArgs {
   int grad_copies;        // interleaved LDS copies of those sums (power of two, <= 16)
   const float* gh;        // dL/dh [n_tx][n_elem][n_t]
   double* g_part;         // [kMaxReplayBlocks][n_grad] per-block partial sums (zeroed per call)
-  double* vadj;           // [n_vertices] mesh vertex adjoints along vnormal (zeroed per call)
+  double* vadj;           // [kVadjCopies][vadj_stride] mesh vertex adjoints along vnormal (zeroed per call)
+  long vadj_stride;
   ReplayStack stk;
   RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
   unsigned long long* counts;   // [max_bounces + 2]: survivors of step k | diffuse interactions << 32
@@ -109,8 +110,12 @@ void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t 
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
 // g_theta[j] += sum over b of g_part[b * n_grad + j], j < n_grad.
 void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, hipStream_t s);
-// g_q[m * n_basis + j] += sum_{v in mesh m} vadj[v] vbasis[v][j].
-void launch_basis_gather(const double* vadj, const double* vbasis, const long* vbeg, int n_meshes,
+// Copies of the vertex adjoints: block b adds into copy b % kVadjCopies, so
+// that (with blocks dealt round-robin to the eight XCDs) the atomics of one
+// XCD meet in its own L2; the copies are summed by the basis projection.
+constexpr int kVadjCopies = 8;
+// g_q[m * n_basis + j] += sum_{v in mesh m} sum_c vadj[c * stride + v] vbasis[v][j].
+void launch_basis_gather(const double* vadj, long stride, const double* vbasis, const long* vbeg, int n_meshes,
                          int n_basis, double* g_q, hipStream_t s);
 
 // ---------------------------------------------------------------- inverse loop

@@ -612,7 +612,8 @@ __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
   int* leg_h = (int*)(legs + kLegCache * blockDim.x) + threadIdx.x;
   int* stk = leg_h + kLegCache * blockDim.x;
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
-            a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+            a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
+            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
@@ -657,7 +658,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   grad_clear(gsh, a.n_grad, a.grad_copies);
   __syncthreads();
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
-            a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal, a.vadj};
+            a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
+            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -803,16 +805,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
 }
 
-// g_theta[q(m, j)] += sum over the vertices v of mesh m of vadj[v] phi_j(v):
-// one block per (mesh, basis function), vertices of mesh m in [vbeg[m], vbeg[m + 1]).
-__global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__ vadj,
+// g_theta[q(m, j)] += sum over the vertices v of mesh m of vadj[v] phi_j(v),
+// vadj[v] summed over its copies: one block per (mesh, basis function),
+// vertices of mesh m in [vbeg[m], vbeg[m + 1]).
+__global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__ vadj, long stride,
                                                       const double* __restrict__ vbasis,
                                                       const long* __restrict__ vbeg, int n_basis,
                                                       double* __restrict__ g_q) {
   const int m = blockIdx.x / n_basis, j = blockIdx.x % n_basis;
   double acc = 0.0;
-  for (long v = vbeg[m] + threadIdx.x; v < vbeg[m + 1]; v += blockDim.x)
-    acc += vadj[v] * vbasis[v * n_basis + j];
+  for (long v = vbeg[m] + threadIdx.x; v < vbeg[m + 1]; v += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < kVadjCopies; ++c) s += vadj[c * stride + v];
+    acc += s * vbasis[v * n_basis + j];
+  }
   __shared__ double red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -875,11 +881,11 @@ void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a), s, a, n);
 }
 
-void launch_basis_gather(const double* vadj, const double* vbasis, const long* vbeg, int n_meshes,
+void launch_basis_gather(const double* vadj, long stride, const double* vbasis, const long* vbeg, int n_meshes,
                          int n_basis, double* g_q, hipStream_t s) {
   if (n_meshes > 0 && n_basis > 0)
-    hipLaunchKernelGGL(k_basis_gather, dim3(n_meshes * n_basis), dim3(256), 0, s, vadj, vbasis, vbeg,
-                       n_basis, g_q);
+    hipLaunchKernelGGL(k_basis_gather, dim3(n_meshes * n_basis), dim3(256), 0, s, vadj, stride, vbasis,
+                       vbeg, n_basis, g_q);
 }
 
 }  // namespace usrt
