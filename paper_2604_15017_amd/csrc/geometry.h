@@ -107,6 +107,8 @@ __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, doub
 // Closest surface along o + t d with kTMin < t < tmax among the planes, the
 // spheres, the meshes and, when `with_array` and the ray moves up, the array
 // face z = 0.
+// kMeshes = false compiles the hierarchy walk out (scenes without meshes).
+template <bool kMeshes = true>
 __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool with_array,
                                            int* stk, double tmax = INFINITY) {
   Hit h{kHitNone, -1, 0.0};
@@ -146,7 +148,7 @@ __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool w
       if (t > kTMin && t < best) { best = t; h = Hit{kHitCylinder, k, t}; }
     }
   }
-  if (s.n_meshes > 0) {
+  if (kMeshes && s.n_meshes > 0) {
     int tri = -1;
     mesh_closest(s, o, d, best, tri, stk);
     if (tri >= 0) h = Hit{kHitMesh, tri, best};

@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* 
 // One thread per pixel, reading the two samples of every (element,
 // transmit) pair straight from HBM through the caches; used for grids too
 // small to fill the chip with pixel tiles. Same sums in the same order as
-// k_das_tiled.
+// k_das_tiled, with the sample index formed in fp64 throughout.
 __global__ __launch_bounds__(256) void k_das_gather(const float2* __restrict__ A, float2* __restrict__ iq,
                                                     ProbeView p, GridView g, TxTable tx, int n_tx,
                                                     int tx_base, int accumulate) {
@@ -234,26 +234,63 @@ __global__ __launch_bounds__(256) void k_das_gather(const float2* __restrict__ A
   iq[px] = acc;
 }
 
-// One block per tile of kDasTx x kDasTz pixels. The (element, transmit)
-// pairs are taken kDasPairs at a time, element-major like the plain sum: for
-// each pair the window of samples any pixel of the tile can touch is bounded
-// from the tile's corners (the transmit term is linear in x and z; the
-// receive distance lies between the distance from the element to the tile
-// and to its farthest corner), that window of the pair's analytic signal is
-// loaded into LDS with coalesced reads, and every pixel interpolates from it.
-// A window wider than kDasSpan is read from HBM instead.
+// One block per tile of kDasTx x kDasTz pixels, the (element, transmit) pairs
+// taken element-major like the plain sum, kDasGroup at a time, in a two-stage
+// pipeline: while the pixels interpolate group g from LDS, each thread holds
+// its share of group g + 1's sample windows in registers (loads in flight),
+// and the window bounds of group g + 2 are formed; one barrier per group.
+// A pair's window is the range of samples any pixel of the tile can touch:
+// the transmit term is linear in x and z, the receive distance lies between
+// the distance from the element to the tile and to its farthest corner
+// (fp64, one sample of slack on each side). A window wider than kDasSpan is
+// read from HBM instead.
+//
+// Sample index: fs (x sin th + z cos th + r) / c_ref near 4000 needs more than
+// fp32 (2.4e-4 samples of rounding, 2e-4 rad of phase at 5 MHz / 40 MHz), but
+// only a few terms need fp64: the transmit term at the tile origin and the
+// receive term per (pixel, element) are formed in fp64 and split into an
+// integer and an fp32 fraction; the transmit term's change across the tile
+// (at most tens of samples) is added in fp32. The index is then off by a few
+// 1e-6 samples at most, and each pair costs fp32 and integer work only.
 constexpr int kDasTx = 16, kDasTz = 16;      // 256 threads, z fastest
-constexpr int kDasPairs = 8;
-constexpr int kDasSpan = 256;
-constexpr long kDasMinTiles = 1024;          // below this the grid cannot fill the chip: gather
+constexpr int kDasThreads = kDasTx * kDasTz;
+constexpr int kDasGroup = 16;                // pairs per pipeline stage
+constexpr int kDasBatch = 8;                 // pairs whose samples are read together
+constexpr int kDasSpan = 144;                // window samples per pair in LDS (four blocks per CU)
+constexpr int kDasStage = kDasGroup * kDasSpan / kDasThreads;   // staged samples per thread
+static_assert(kDasGroup * kDasSpan % kDasThreads == 0, "window stage must split evenly");
+static_assert(kDasGroup <= kDasThreads && kMaxTxPerLaunch <= kDasThreads, "one thread per bound");
+constexpr long kDasMinTiles = 64;            // below this the grid cannot fill the chip: gather
 
-__global__ __launch_bounds__(256) void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq,
-                                                   ProbeView p, GridView g, TxTable tx, int n_tx,
-                                                   int tx_base, int accumulate, int tiles_z) {
-  __shared__ float2 seg[kDasPairs][kDasSpan];
-  __shared__ int seg_lo[kDasPairs], seg_n[kDasPairs];
+struct DasWindow { long row; int lo, n; };   // channel offset in A, first sample, length
+struct TxSplit { int ib; float fb, da, db; };   // transmit term at the tile origin, steps per pixel
+
+__device__ __forceinline__ DasWindow das_window(const ProbeView& p, const TxTable& tx, int n_tx, int tx_base,
+                                                int q, double xa, double xb, double za, double zb) {
+  const double s_per_m = p.fs / p.c_ref;
+  const int e = q / n_tx, i = q % n_tx;
+  const double xe = ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
+  const double sa = tx.sin_a[i], ca = tx.cos_a[i];
+  const double l1 = xa * sa + za * ca, l2 = xb * sa + za * ca, l3 = xa * sa + zb * ca, l4 = xb * sa + zb * ca;
+  const double lmin = fmin(fmin(l1, l2), fmin(l3, l4)), lmax = fmax(fmax(l1, l2), fmax(l3, l4));
+  const double dx_near = xe < xa ? xa - xe : (xe > xb ? xe - xb : 0.0);
+  const double dx_far = fmax(fabs(xe - xa), fabs(xe - xb));
+  const double rmin = sqrt(dx_near * dx_near + za * za), rmax = sqrt(dx_far * dx_far + zb * zb);
+  const double klo = floor((lmin + rmin) * s_per_m) - 1.0, khi = floor((lmax + rmax) * s_per_m) + 2.0;
+  const double lo = fmax(klo, -1.0), hi = fmin(khi, (double)p.n_t);   // samples [lo, hi]
+  return DasWindow{((long)(tx_base + i) * p.n_elem + e) * p.n_t, (int)lo, hi >= lo ? (int)(hi - lo) + 1 : 0};
+}
+
+__global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq,
+                                                           ProbeView p, GridView g, TxTable tx, int n_tx,
+                                                           int tx_base, int accumulate, int tiles_z) {
+  __shared__ float2 win[2][kDasGroup * kDasSpan];
+  __shared__ DasWindow wb[3][kDasGroup];
+  __shared__ int wide[3];   // the group has a window wider than kDasSpan (or is partial)
+  __shared__ TxSplit ts[kMaxTxPerLaunch];
   const int a0 = (blockIdx.x / tiles_z) * kDasTx, b0 = (blockIdx.x % tiles_z) * kDasTz;
-  const int a = a0 + (int)threadIdx.x / kDasTz, b = b0 + (int)threadIdx.x % kDasTz;
+  const int ia = (int)threadIdx.x / kDasTz, ib = (int)threadIdx.x % kDasTz;
+  const int a = a0 + ia, b = b0 + ib;
   const bool inside = a < g.n_x && b < g.n_z;
   const long px = (long)a * g.n_z + b;
   const double x = g.x0 + a * g.dx, z = g.z0 + b * g.dz;
@@ -262,65 +299,127 @@ __global__ __launch_bounds__(256) void k_das_tiled(const float2* __restrict__ A,
   const double za = g.z0 + b0 * g.dz, zb = g.z0 + (min(b0 + kDasTz, g.n_z) - 1) * g.dz;
   const double s_per_m = p.fs / p.c_ref;
   const double half = 0.5 * (double)(p.n_elem - 1);
-  float2 acc = (accumulate && inside) ? iq[px] : make_float2(0.0f, 0.0f);
   const int n_pairs = p.n_elem * n_tx;
-  int krx_e = -1;
-  double krx = 0.0;
-  for (int q0 = 0; q0 < n_pairs; q0 += kDasPairs) {
-    const int nq = min(kDasPairs, n_pairs - q0);
-    if ((int)threadIdx.x < nq) {
-      const int q = q0 + threadIdx.x, e = q / n_tx, i = q % n_tx;
-      const double xe = ((double)e - half) * p.pitch;
-      const double sa = tx.sin_a[i], ca = tx.cos_a[i];
-      const double l1 = xa * sa + za * ca, l2 = xb * sa + za * ca, l3 = xa * sa + zb * ca, l4 = xb * sa + zb * ca;
-      const double lmin = fmin(fmin(l1, l2), fmin(l3, l4)), lmax = fmax(fmax(l1, l2), fmax(l3, l4));
-      const double dx_near = xe < xa ? xa - xe : (xe > xb ? xe - xb : 0.0);
-      const double dx_far = fmax(fabs(xe - xa), fabs(xe - xb));
-      const double rmin = sqrt(dx_near * dx_near + za * za), rmax = sqrt(dx_far * dx_far + zb * zb);
-      const double klo = floor((lmin + rmin) * s_per_m) - 1.0, khi = floor((lmax + rmax) * s_per_m) + 2.0;
-      const double lo = fmax(klo, -1.0), hi = fmin(khi, (double)p.n_t);   // samples [lo, hi]
-      seg_lo[threadIdx.x] = (int)lo;
-      seg_n[threadIdx.x] = hi >= lo ? (int)(hi - lo) + 1 : 0;
+  const int n_groups = (n_pairs + kDasGroup - 1) / kDasGroup;
+  if ((int)threadIdx.x < n_tx) {
+    const int i = threadIdx.x;
+    const double kt = (xa * tx.sin_a[i] + za * tx.cos_a[i]) * s_per_m;
+    const double fl = floor(kt);
+    ts[i] = TxSplit{(int)fl, (float)(kt - fl), (float)(g.dx * tx.sin_a[i] * s_per_m),
+                    (float)(g.dz * tx.cos_a[i] * s_per_m)};
+  }
+  auto bounds = [&](int grp, int buf) {
+    const int q = grp * kDasGroup + (int)threadIdx.x;
+    if ((int)threadIdx.x < kDasGroup) {
+      const DasWindow w = q < n_pairs ? das_window(p, tx, n_tx, tx_base, q, xa, xb, za, zb) : DasWindow{0, 0, 0};
+      wb[buf][threadIdx.x] = w;
+      const unsigned long long m = __ballot(q >= n_pairs || w.n > kDasSpan);   // lanes 0..15 of wave 0
+      if (threadIdx.x == 0) wide[buf] = m != 0ull;
     }
-    __syncthreads();
-    for (int j = 0; j < nq; ++j) {
-      const int n = seg_n[j];
-      if (n > kDasSpan) continue;   // read from HBM below
-      const int q = q0 + j;
-      const float2* row = A + ((long)(tx_base + q % n_tx) * p.n_elem + q / n_tx) * p.n_t;
-      for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const int k = seg_lo[j] + t;
-        seg[j][t] = (k >= 0 && k < p.n_t) ? row[k] : make_float2(0.0f, 0.0f);
+  };
+  float2 st[kDasStage];
+  auto load = [&](const DasWindow* w) {
+#pragma unroll
+    for (int r = 0; r < kDasStage; ++r) {
+      const int f = r * kDasThreads + (int)threadIdx.x;
+      const int j = f / kDasSpan, t = f - j * kDasSpan;
+      const DasWindow ww = w[j];
+      const int k = ww.lo + t;
+      st[r] = (t < ww.n && ww.n <= kDasSpan && k >= 0 && k < p.n_t) ? A[ww.row + k] : make_float2(0.0f, 0.0f);
+    }
+  };
+  auto store = [&](float2* dst) {
+#pragma unroll
+    for (int r = 0; r < kDasStage; ++r) dst[r * kDasThreads + threadIdx.x] = st[r];
+  };
+
+  bounds(0, 0);
+  if (n_groups > 1) bounds(1, 1);
+  __syncthreads();
+  load(wb[0]);
+  store(win[0]);
+  __syncthreads();
+
+  float2 acc = (accumulate && inside) ? iq[px] : make_float2(0.0f, 0.0f);
+  const float fa = (float)ia, fz = (float)ib;
+  int e = 0, i = 0, rx_e = -1, rx_i = 0;
+  float rx_f = 0.0f;
+  for (int grp = 0; grp < n_groups; ++grp) {
+    const int cur = grp & 1;
+    const DasWindow* wc = wb[grp % 3];
+    if (grp + 1 < n_groups) load(wb[(grp + 1) % 3]);          // in flight during the sums below
+    if (grp + 2 < n_groups) bounds(grp + 2, (grp + 2) % 3);
+    const int nq = min(kDasGroup, n_pairs - grp * kDasGroup);
+    if (!wide[grp % 3]) {
+      // whole group, every window in LDS: all indices first, then the reads
+      // and sums without branches (out-of-range samples weigh zero)
+#pragma unroll 1
+      for (int j0 = 0; j0 < kDasGroup; j0 += kDasBatch) {
+        int kk[kDasBatch];
+        float fk[kDasBatch];
+#pragma unroll
+        for (int j = 0; j < kDasBatch; ++j) {
+          if (e != rx_e) {
+            const double dxe = x - ((double)e - half) * p.pitch;
+            const double krx = sqrt(dxe * dxe + z * z) * s_per_m;
+            const double fl = floor(krx);
+            rx_i = (int)fl;
+            rx_f = (float)(krx - fl);
+            rx_e = e;
+          }
+          const TxSplit T = ts[i];
+          const float sf = (T.fb + rx_f) + fmaf(fa, T.da, fz * T.db);
+          const float fl = floorf(sf);
+          kk[j] = T.ib + rx_i + (int)fl;
+          fk[j] = sf - fl;
+          if (++i == n_tx) { i = 0; ++e; }
+        }
+#pragma unroll
+        for (int j = 0; j < kDasBatch; ++j) {
+          const DasWindow w = wc[j0 + j];
+          const int k0 = kk[j];
+          const bool ok = inside && k0 >= -1 && k0 < p.n_t && w.n >= 2;
+          const int o = (j0 + j) * kDasSpan + min(max(k0 - w.lo, 0), max(w.n - 2, 0));
+          const float2 v0 = win[cur][o], v1 = win[cur][o + 1];
+          const float f1 = ok ? fk[j] : 0.0f, f0 = ok ? 1.0f - fk[j] : 0.0f;
+          acc.x += f0 * v0.x + f1 * v1.x;
+          acc.y += f0 * v0.y + f1 * v1.y;
+        }
       }
-    }
-    __syncthreads();
-    if (inside) {
-      for (int j = 0; j < nq; ++j) {
-        const int q = q0 + j, e = q / n_tx, i = q % n_tx;
-        if (e != krx_e) {   // receive delay once per element
+    } else for (int j = 0; j < nq; ++j) {
+      if (inside) {
+        if (e != rx_e) {   // receive term once per element: integer + fraction
           const double dxe = x - ((double)e - half) * p.pitch;
-          krx = sqrt(dxe * dxe + z * z) * s_per_m;
-          krx_e = e;
+          const double krx = sqrt(dxe * dxe + z * z) * s_per_m;
+          const double fl = floor(krx);
+          rx_i = (int)fl;
+          rx_f = (float)(krx - fl);
+          rx_e = e;
         }
-        const double k = (x * tx.sin_a[i] + z * tx.cos_a[i]) * s_per_m + krx;
-        const double k0d = floor(k);
-        if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
-        const int k0 = (int)k0d;
-        const float f = (float)(k - k0d);
-        float2 v0, v1;
-        if (seg_n[j] <= kDasSpan) {
-          const int o = k0 - seg_lo[j];   // within [0, n - 2] by the window bound
-          v0 = seg[j][o];
-          v1 = seg[j][o + 1];
-        } else {
-          const float2* row = A + ((long)(tx_base + i) * p.n_elem + e) * p.n_t;
-          v0 = k0 >= 0 ? row[k0] : make_float2(0.0f, 0.0f);
-          v1 = k0 + 1 < p.n_t ? row[k0 + 1] : make_float2(0.0f, 0.0f);
+        const TxSplit T = ts[i];
+        const float sf = (T.fb + rx_f) + fmaf(fa, T.da, fz * T.db);
+        const float fl = floorf(sf);
+        const int k0 = T.ib + rx_i + (int)fl;
+        const float f = sf - fl;
+        const DasWindow w = wc[j];
+        if (k0 >= -1 && k0 < p.n_t && w.n >= 2) {
+          float2 v0, v1;
+          if (w.n <= kDasSpan) {
+            const int o = min(max(k0 - w.lo, 0), w.n - 2);   // within [0, n - 2] by the window bound
+            v0 = win[cur][j * kDasSpan + o];
+            v1 = win[cur][j * kDasSpan + o + 1];
+          } else {
+            const float2* row = A + w.row;
+            v0 = k0 >= 0 ? row[k0] : make_float2(0.0f, 0.0f);
+            v1 = k0 + 1 < p.n_t ? row[k0 + 1] : make_float2(0.0f, 0.0f);
+          }
+          acc.x += (1.0f - f) * v0.x + f * v1.x;
+          acc.y += (1.0f - f) * v0.y + f * v1.y;
         }
-        acc.x += (1.0f - f) * v0.x + f * v1.x;
-        acc.y += (1.0f - f) * v0.y + f * v1.y;
       }
+      if (++i == n_tx) { i = 0; ++e; }
     }
+    if (grp + 1 < n_groups) store(win[cur ^ 1]);
     __syncthreads();
   }
   if (inside) iq[px] = acc;

@@ -292,6 +292,7 @@ struct ReplayCtx {
 
 // Secondary ray of interaction k at x (weight watt, time tp, interface f):
 // adds its adjoints to xbar, nrbar, Arbar, wattbar, tpbar and the parameters.
+template <bool kMeshes>
 __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f, double kd,
                                    double watt, double tp, int e2, d3& xbar, d3& nrbar,
                                    double& Arbar, double& wattbar, double& tpbar) {
@@ -320,7 +321,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
     bool reached = false;
     const int step = blockDim.x;
     for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false, C.stk, remaining);
+      const Hit h = closest_hit<kMeshes>(S, p, we, false, C.stk, remaining);
       if (h.kind == kHitNone || h.t >= remaining) {
         tof += remaining / S.c[reg];
         rest *= exp(-(S.a[reg] * remaining));
@@ -369,7 +370,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
           h = Hit{kHitNone, -1, 0.0};
         }
       } else {
-        h = closest_hit(S, p, we, false, C.stk, remaining);
+        h = closest_hit<kMeshes>(S, p, we, false, C.stk, remaining);
       }
       if (h.kind == kHitNone || h.t >= remaining) {
         const double ell = remaining;   // = r - s_J
@@ -470,7 +471,8 @@ __device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t,
 // keeping the state before it and the surface it hits in the step record of
 // their chunk index; the survivors are compacted into the next queue and
 // every interaction on a diffuse surface is queued for phase 2.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+template <bool kMeshes>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 3 : 4, 8)))
 void k_replay_forward(ReplayArgs a, int k, long n) {
   const long n_in = k == 1 ? n : (long)(uint32_t)a.counts[k - 1];   // survivors of step k - 1
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
@@ -519,7 +521,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
         delta = (m >> 8) & 1u;
       }
       const long at = (long)(k - 1) * cap + ci;
-      const Hit h = closest_hit(S, o, d, true, stk);
+      const Hit h = closest_hit<kMeshes>(S, o, d, true, stk);
       a.stk.rec[at] = StepRec{o.x, o.y, o.z, d.x, d.y, d.z, t, w, h.t,
                               (uint32_t)region | ((uint32_t)delta << 8) | ((uint32_t)h.kind << 12),
                               h.index};
@@ -598,6 +600,7 @@ __global__ void k_replay_prefix(ReplayArgs a) {
   }
 }
 
+template <bool kMeshes>
 __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
   const int B = a.max_bounces;
   const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
@@ -640,7 +643,7 @@ __global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
     ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
     d3 xb{0, 0, 0}, nrb{0, 0, 0};
     double Ab = 0.0, wb = 0.0, tb = 0.0;
-    secondary_backward(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb);
+    secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb);
     a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
   }
   __syncthreads();
@@ -860,12 +863,14 @@ size_t grad_lds(const ReplayArgs& a) {
 }  // namespace
 
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_replay_forward, dim3(replay_grid(n)), dim3(256), stack_lds(a), s, a, k, n);
+  const auto kern = a.scene.n_meshes > 0 ? k_replay_forward<true> : k_replay_forward<false>;
+  hipLaunchKernelGGL(kern, dim3(replay_grid(n)), dim3(256), stack_lds(a), s, a, k, n);
 }
 
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s) {
   const size_t legs = (size_t)kLegCache * 256 * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL(k_replay_secondary, dim3(replay_grid(max_entries)), dim3(256),
+  const auto kern = a.scene.n_meshes > 0 ? k_replay_secondary<true> : k_replay_secondary<false>;
+  hipLaunchKernelGGL(kern, dim3(replay_grid(max_entries)), dim3(256),
                      grad_lds(a) + legs + stack_lds(a), s, a);
 }
 

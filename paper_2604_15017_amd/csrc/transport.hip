@@ -36,7 +36,7 @@ __device__ __forceinline__ void flush_counters(unsigned long long* g, unsigned l
 }  // namespace
 
 // One interaction step for every live ray (k = 1 fuses the emission).
-template <bool kAudit>
+template <bool kAudit, bool kMeshes>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_bounce(TraceArgs a, int k) {
   const long n_in = k == 1 ? a.n_chunk : (long)(uint32_t)a.counts[k - 1];
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     uint64_t hsum = 0;
 
     if (active) {
-      const Hit h = closest_hit(S, o, d, true, stk);
+      const Hit h = closest_hit<kMeshes>(S, o, d, true, stk);
       ++n_seg;
       if (kAudit) hsum += event_mix(kEvHit, k, ((uint32_t)h.kind << 24) | ((uint32_t)(hit_id(S, h) + 1) & 0xFFFFFFu));
       if (h.kind != kHitNone) {
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 // element centre through every crossed interface (transmission coefficient
 // each, zero on total internal reflection), attenuation and travel time per
 // medium, then the deposit.
-template <bool kAudit>
+template <bool kAudit, bool kMeshes>
 __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
   const long n_in = (long)(a.counts[k] >> 32);
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
     bool blocked = true;
     const int legs = max_legs(S);
     for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit(S, p, we, false, stk, remaining);
+      const Hit h = closest_hit<kMeshes>(S, p, we, false, stk, remaining);
       ++n_seg;
       if (h.kind == kHitNone || h.t >= remaining) {
         tof += remaining / S.c[reg];
@@ -366,14 +366,18 @@ static size_t stack_bytes(const TraceArgs& a) {
 
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {
   const dim3 grid(grid_for(max_rays, 256, kMaxBlocks)), block(256);
-  if (audit) hipLaunchKernelGGL(k_bounce<true>, grid, block, stack_bytes(a), s, a, k);
-  else hipLaunchKernelGGL(k_bounce<false>, grid, block, stack_bytes(a), s, a, k);
+  const bool m = a.scene.n_meshes > 0;
+  const auto kern = audit ? (m ? k_bounce<true, true> : k_bounce<true, false>)
+                          : (m ? k_bounce<false, true> : k_bounce<false, false>);
+  hipLaunchKernelGGL(kern, grid, block, stack_bytes(a), s, a, k);
 }
 
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s) {
   const dim3 grid(grid_for(max_rays, 256, kMaxBlocks)), block(256);
-  if (audit) hipLaunchKernelGGL(k_secondary<true>, grid, block, stack_bytes(a), s, a, k);
-  else hipLaunchKernelGGL(k_secondary<false>, grid, block, stack_bytes(a), s, a, k);
+  const bool m = a.scene.n_meshes > 0;
+  const auto kern = audit ? (m ? k_secondary<true, true> : k_secondary<true, false>)
+                          : (m ? k_secondary<false, true> : k_secondary<false, false>);
+  hipLaunchKernelGGL(kern, grid, block, stack_bytes(a), s, a, k);
 }
 
 int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,
