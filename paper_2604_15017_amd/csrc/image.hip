@@ -572,54 +572,101 @@ __global__ __launch_bounds__(256) void k_das_adjoint(const float2* __restrict__ 
   }
 }
 
-// Adjoint of DAS for one RF row (transmit, element), column by column: the
-// block's threads take the pixels of one column (coalesced reads of dL/dI)
-// and add each pixel's two tent weights into the row's accumulators in LDS.
+// Square root of s to about 1e-14 relative: the fp32 root refined by one
+// Newton step whose residual s - r0^2 is formed in fp64 (a handful of
+// instructions against the fp64 root's iteration).
+__device__ __forceinline__ double sqrt_newton(double s) {
+  if (!(s > 1e-30)) return sqrt(s);
+  const float r0 = __builtin_amdgcn_sqrtf((float)s);
+  const double r0d = (double)r0;
+  return r0d + (double)((float)fma(-r0d, r0d, s) * (0.5f * __builtin_amdgcn_rcpf(r0)));
+}
+
+// Adjoint of DAS for kT RF rows of one element (kT transmits), column by
+// column: the block's threads take the pixels of one column (coalesced reads
+// of dL/dI, the next column's prefetched into registers while this one is
+// summed) and add each pixel's two tent weights into the rows' accumulators
+// in LDS. The receive distance of a pixel is formed once for the kT rows.
 // Down a column kappa grows by more than two samples per pixel (checked by
 // the launcher: dz fs / c_ref cos(theta) > 2 and z0 >= 0), so the pixels of
-// one column touch disjoint sample pairs and need no atomics; a barrier
-// separates the columns. Every sample then sums its contributions in column
-// order, as the per-sample gather does.
-__global__ __launch_bounds__(256) void k_das_adjoint_cols(const float2* __restrict__ giq,
-                                                          float2* __restrict__ gA, ProbeView p,
-                                                          GridView g, TxTable tx, int tx_base) {
-  const int txl = blockIdx.x / p.n_elem;
-  const int e = blockIdx.x % p.n_elem;
-  extern __shared__ float2 acc_row[];   // [n_t]
-  for (int k = threadIdx.x; k < p.n_t; k += blockDim.x) acc_row[k] = make_float2(0.0f, 0.0f);
+// one column touch disjoint sample pairs of a row and need no atomics; a
+// barrier separates the columns. Every sample then sums its contributions in
+// column order, as the per-sample gather does.
+constexpr int kAdjThreads = 512;
+constexpr int kAdjMaxR = 4;   // pixels per thread and column: n_z <= 2048
+
+template <int kT>
+__global__ __launch_bounds__(kAdjThreads) void k_das_adjoint_cols(const float2* __restrict__ giq,
+                                                                  float2* __restrict__ gA, ProbeView p,
+                                                                  GridView g, TxTable tx, int n_tx,
+                                                                  int tx_base) {
+  const int groups = (n_tx + kT - 1) / kT;
+  const int e = blockIdx.x / groups, i0 = (blockIdx.x % groups) * kT;
+  const int nt = min(kT, n_tx - i0);
+  extern __shared__ float2 acc_row[];   // [kT][n_t]
+  for (int k = threadIdx.x; k < kT * p.n_t; k += blockDim.x) acc_row[k] = make_float2(0.0f, 0.0f);
   __syncthreads();
-  const double sa = tx.sin_a[txl], ca = tx.cos_a[txl];
+  double sa[kT], ca[kT];
+#pragma unroll
+  for (int t = 0; t < kT; ++t) {
+    const int i = i0 + min(t, nt - 1);
+    sa[t] = tx.sin_a[i];
+    ca[t] = tx.cos_a[i];
+  }
   const double s_per_m = p.fs / p.c_ref;
   const double xe = ((double)e - 0.5 * (double)(p.n_elem - 1)) * p.pitch;
+  float2 cur[kAdjMaxR], nxt[kAdjMaxR];
+  auto fetch = [&](int a, float2* v) {
+    const float2* col = giq + (long)a * g.n_z;
+#pragma unroll
+    for (int r = 0; r < kAdjMaxR; ++r) {
+      const int b = (int)threadIdx.x + r * kAdjThreads;
+      v[r] = b < g.n_z ? col[b] : make_float2(0.0f, 0.0f);
+    }
+  };
+  fetch(0, cur);
   for (int a = 0; a < g.n_x; ++a) {
+    if (a + 1 < g.n_x) fetch(a + 1, nxt);
     const double x = g.x0 + a * g.dx;
     const double dx = x - xe;
-    const float2* col = giq + (long)a * g.n_z;
-    for (int b = threadIdx.x; b < g.n_z; b += blockDim.x) {
+#pragma unroll
+    for (int r = 0; r < kAdjMaxR; ++r) {
+      const int b = (int)threadIdx.x + r * kAdjThreads;
+      if (b >= g.n_z) continue;
       const double z = g.z0 + b * g.dz;
-      const double kap = (x * sa + z * ca + sqrt(dx * dx + z * z)) * s_per_m;
-      const double k0d = floor(kap);
-      if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
-      const int k0 = (int)k0d;
-      const float f = (float)(kap - k0d);
-      const float2 gv = col[b];
-      if (k0 >= 0) {
-        float2 v = acc_row[k0];
-        v.x = fmaf(1.0f - f, gv.x, v.x);
-        v.y = fmaf(1.0f - f, gv.y, v.y);
-        acc_row[k0] = v;
-      }
-      if (k0 + 1 < p.n_t) {
-        float2 v = acc_row[k0 + 1];
-        v.x = fmaf(f, gv.x, v.x);
-        v.y = fmaf(f, gv.y, v.y);
-        acc_row[k0 + 1] = v;
+      const double rx = sqrt_newton(dx * dx + z * z);
+      const float2 gv = cur[r];
+#pragma unroll
+      for (int t = 0; t < kT; ++t) {
+        if (t >= nt) continue;
+        float2* acc = acc_row + t * p.n_t;
+        const double kap = (x * sa[t] + z * ca[t] + rx) * s_per_m;
+        const double k0d = floor(kap);
+        if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
+        const int k0 = (int)k0d;
+        const float f = (float)(kap - k0d);
+        if (k0 >= 0) {
+          float2 v = acc[k0];
+          v.x = fmaf(1.0f - f, gv.x, v.x);
+          v.y = fmaf(1.0f - f, gv.y, v.y);
+          acc[k0] = v;
+        }
+        if (k0 + 1 < p.n_t) {
+          float2 v = acc[k0 + 1];
+          v.x = fmaf(f, gv.x, v.x);
+          v.y = fmaf(f, gv.y, v.y);
+          acc[k0 + 1] = v;
+        }
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kAdjMaxR; ++r) cur[r] = nxt[r];
   }
-  float2* row = gA + ((long)(tx_base + txl) * p.n_elem + e) * p.n_t;
-  for (int k = threadIdx.x; k < p.n_t; k += blockDim.x) row[k] = acc_row[k];
+  for (int t = 0; t < nt; ++t) {
+    float2* row = gA + ((long)(tx_base + i0 + t) * p.n_elem + e) * p.n_t;
+    for (int k = threadIdx.x; k < p.n_t; k += blockDim.x) row[k] = acc_row[t * p.n_t + k];
+  }
 }
 
 // L = (1/n) sum [l1 |d| + l2 d^2], d = B - R; dL/dB = (l1 sign(d) + 2 l2 d) / n.
@@ -719,6 +766,8 @@ void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long*
   hipLaunchKernelGGL(k_bmode_vjp_fix, dim3(1), dim3(1), 0, s, iq, key, sum, g_iq);
 }
 
+constexpr size_t kAdjLds = 64 * 1024;   // accumulator rows per column-kernel block
+
 void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, const GridView& g,
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s) {
   const dim3 grid((unsigned)(n_tx_group * p.n_elem)), block(256);
@@ -727,10 +776,19 @@ void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, con
   double ca_min = 1.0;
   for (int i = 0; i < n_tx_group; ++i) ca_min = std::min(ca_min, tx.cos_a[i]);
   const bool cols_ok = g.z0 >= 0.0 && g.dz * p.fs / p.c_ref * ca_min > 2.0 + 1e-9 &&
-                       (size_t)p.n_t * sizeof(float2) <= 64 * 1024;
+                       g.n_z <= kAdjThreads * kAdjMaxR && (size_t)p.n_t * sizeof(float2) <= kAdjLds;
   if (cols_ok) {
-    hipLaunchKernelGGL(k_das_adjoint_cols, grid, block, (size_t)p.n_t * sizeof(float2), s, g_iq, g_A, p, g,
-                       tx, tx_base);
+    // as many transmits per block as the LDS budget holds
+    const size_t row = (size_t)p.n_t * sizeof(float2);
+    const int kt = 4 * row <= kAdjLds ? 4 : (2 * row <= kAdjLds ? 2 : 1);
+    const int groups = (n_tx_group + kt - 1) / kt;
+    const dim3 cgrid((unsigned)(groups * p.n_elem)), cblock(kAdjThreads);
+    if (kt == 4)
+      hipLaunchKernelGGL(k_das_adjoint_cols<4>, cgrid, cblock, 4 * row, s, g_iq, g_A, p, g, tx, n_tx_group, tx_base);
+    else if (kt == 2)
+      hipLaunchKernelGGL(k_das_adjoint_cols<2>, cgrid, cblock, 2 * row, s, g_iq, g_A, p, g, tx, n_tx_group, tx_base);
+    else
+      hipLaunchKernelGGL(k_das_adjoint_cols<1>, cgrid, cblock, row, s, g_iq, g_A, p, g, tx, n_tx_group, tx_base);
     return;
   }
   const int per_thread = (p.n_t + 255) / 256;
