@@ -603,18 +603,13 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   a.dep.key = c.take<uint32_t>((size_t)kDepositsPerRay * cap);
   a.dep.w = c.take<float2>((size_t)kDepositsPerRay * cap);
   a.dep_count = counts + max_bounces + 4;
-  // the binned order is written over the first ray queue, which is dead by
-  // then (72 bytes per ray hold the 2 x 12 bytes per ray)
-  DepositList sorted{};
-  {
-    char* dead = reinterpret_cast<char*>(q0.ox);
-    const size_t key_bytes = align_up((size_t)kDepositsPerRay * cap * sizeof(uint32_t));
-    sorted.key = reinterpret_cast<uint32_t*>(dead);
-    sorted.w = reinterpret_cast<float2*>(dead + key_bytes);
-    US_CHECK(key_bytes + (size_t)kDepositsPerRay * cap * sizeof(float2) <=
-                 (size_t)(reinterpret_cast<char*>(q1.ox) - dead),
-             "us_simulate_rf: internal workspace layout");
-  }
+  // the binned order (16-byte records: key, two tent weights) is written
+  // over the first ray queue, which is dead by then (72 bytes per ray hold
+  // the 2 x 16 bytes per ray)
+  uint4* sorted = reinterpret_cast<uint4*>(q0.ox);
+  US_CHECK((size_t)kDepositsPerRay * cap * sizeof(uint4) <=
+               (size_t)(reinterpret_cast<char*>(q1.ox) - reinterpret_cast<char*>(q0.ox)),
+           "us_simulate_rf: internal workspace layout");
   a.scene = scene_view(scene, probe);
   a.probe = probe->pv;
   a.seed = seed;

@@ -166,8 +166,8 @@ void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s);
 // LDS and adds the tile to h.
 size_t splat_scratch_bytes(int n_rows);
 void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_count, long shard_cap,
-                      int n_rows, const DepositList& sorted, void* scratch, hipStream_t s);
-void launch_splat_accumulate(const DepositList& sorted, const void* scratch, uint32_t row0, int n_rows,
+                      int n_rows, uint4* sorted, void* scratch, hipStream_t s);
+void launch_splat_accumulate(const uint4* sorted, const void* scratch, uint32_t row0, int n_rows,
                              int n_t, float* h, hipStream_t s);
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);

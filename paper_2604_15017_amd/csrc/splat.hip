@@ -2,7 +2,9 @@
 // linear tent of the path contributions, Sec. 2.3.4): the secondary-ray kernel
 // records each deposit (row and bin in one key, the two tent weights); here
 // the records are grouped by RF row with a counting sort whose per-block
-// histograms and cursors live in LDS, and then one block per row and time tile
+// histograms and cursors live in LDS (each moved record is one 16-byte store:
+// the scattered stores, not the arithmetic, bound this pass), and then one
+// block per row and time tile
 // sums its deposits in an LDS copy of the tile (LDS atomics) and adds the tile
 // to the histogram in HBM with plain coalesced accesses. Global atomics are
 // left to deposits that did not fit the record buffer.
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_dep_rowscan(int n_rows, BinScratch bs)
 
 __global__ __launch_bounds__(kBinThreads) void k_dep_scatter(DepositList dep, const unsigned long long* count,
                                                              long shard_cap, int n_rows, BinScratch bs,
-                                                             DepositList sorted) {
+                                                             uint4* __restrict__ sorted) {
   __shared__ uint32_t cur[kMaxBinRows];
   for (int r = threadIdx.x; r < n_rows; r += blockDim.x)
     cur[r] = bs.row_begin[r] + bs.hist[(long)r * kBinBlocks + blockIdx.x];
@@ -117,14 +119,14 @@ __global__ __launch_bounds__(kBinThreads) void k_dep_scatter(DepositList dep, co
   for (long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
     const uint32_t k = dep.key[i];
     const uint32_t pos = atomicAdd(&cur[k >> kDepBinBits], 1u);
-    sorted.key[pos] = k;
-    sorted.w[pos] = dep.w[i];
+    const float2 w = dep.w[i];
+    sorted[pos] = make_uint4(k, __float_as_uint(w.x), __float_as_uint(w.y), 0u);   // one 16-byte store
   }
 }
 
 // Block (row, tile): the row's deposits summed into an LDS tile of samples
 // [t0, t0 + kAccTile), then added to h.
-__global__ __launch_bounds__(512) void k_dep_accumulate(DepositList sorted, BinScratch bs, uint32_t row0,
+__global__ __launch_bounds__(512) void k_dep_accumulate(const uint4* __restrict__ sorted, BinScratch bs, uint32_t row0,
                                                         int n_t, int tiles, float* __restrict__ h) {
   __shared__ float acc[kAccTile];
   const int r = blockIdx.x / tiles, tile = blockIdx.x % tiles;
@@ -135,8 +137,9 @@ __global__ __launch_bounds__(512) void k_dep_accumulate(DepositList sorted, BinS
   __syncthreads();
   const uint32_t mask = (1u << kDepBinBits) - 1u;
   for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-    const int j0 = (int)(sorted.key[i] & mask) - 1;   // bin of w0; w1 goes to j0 + 1
-    const float2 w = sorted.w[i];
+    const uint4 rec = sorted[i];
+    const int j0 = (int)(rec.x & mask) - 1;   // bin of w0; w1 goes to j0 + 1
+    const float2 w = make_float2(__uint_as_float(rec.y), __uint_as_float(rec.z));
     const int j = j0 - t0;
     if (j0 >= 0 && j >= 0 && j < len) atomicAdd(&acc[j], w.x);
     if (j0 + 1 < n_t && j + 1 >= 0 && j + 1 < len) atomicAdd(&acc[j + 1], w.y);
@@ -157,7 +160,7 @@ size_t splat_scratch_bytes(int n_rows) {
 }
 
 void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_count, long shard_cap,
-                      int n_rows, const DepositList& sorted, void* scratch, hipStream_t s) {
+                      int n_rows, uint4* sorted, void* scratch, hipStream_t s) {
   const BinScratch bs = carve(scratch, n_rows);
   hipLaunchKernelGGL(k_dep_count, dim3(kBinBlocks), dim3(kBinThreads), 0, s, dep.key, shard_count, shard_cap,
                      n_rows, bs);
@@ -167,7 +170,7 @@ void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_co
                      n_rows, bs, sorted);
 }
 
-void launch_splat_accumulate(const DepositList& sorted, const void* scratch, uint32_t row0, int n_rows,
+void launch_splat_accumulate(const uint4* sorted, const void* scratch, uint32_t row0, int n_rows,
                              int n_t, float* h, hipStream_t s) {
   const BinScratch bs = carve(const_cast<void*>(scratch), n_rows);
   const int tiles = (n_t + kAccTile - 1) / kAccTile;
