@@ -630,7 +630,9 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
     a.tx_base = t0;
     const long total = (long)ng * ray_count;
     const int n_rows = ng * pd.n_elem;
-    a.dep_cap = (bin_scratch && n_rows <= rows) ? kDepositsPerRay * cap : 0;   // split in kDepShards
+    // deposits are binned (kDepShards shards of records) except on mesh scenes,
+    // whose walk-bound secondary kernel hides global atomics into h
+    a.dep_cap = (bin_scratch && n_rows <= rows && scene->n_meshes == 0) ? kDepositsPerRay * cap : 0;
     a.dep.row0 = (uint32_t)t0 * (uint32_t)pd.n_elem;
     for (long g0 = 0; g0 < total; g0 += cap) {
       const long n = std::min(cap, total - g0);
