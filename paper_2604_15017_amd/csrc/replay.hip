@@ -850,10 +850,12 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
 }
 
 namespace {
-unsigned replay_grid(long n) {
+unsigned replay_grid(long n, long cap = kMaxReplayBlocks) {
   const long b = (n + 255) / 256;
-  return (unsigned)(b < 1 ? 1 : (b > kMaxReplayBlocks ? kMaxReplayBlocks : b));
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
+// the forward phase keeps no gradient rows, so its grid may be larger
+constexpr long kMaxReplayForwardBlocks = 8192;
 size_t stack_lds(const ReplayArgs& a) {
   return a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0;
 }
@@ -864,7 +866,7 @@ size_t grad_lds(const ReplayArgs& a) {
 
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s) {
   const auto kern = a.scene.n_meshes > 0 ? k_replay_forward<true> : k_replay_forward<false>;
-  hipLaunchKernelGGL(kern, dim3(replay_grid(n)), dim3(256), stack_lds(a), s, a, k, n);
+  hipLaunchKernelGGL(kern, dim3(replay_grid(n, kMaxReplayForwardBlocks)), dim3(256), stack_lds(a), s, a, k, n);
 }
 
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s) {

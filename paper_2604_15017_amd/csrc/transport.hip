@@ -358,7 +358,7 @@ void launch_fill_u32(uint32_t* p, long n, uint32_t v, hipStream_t s) {
 }
 
 // Grids are capped at a few blocks per compute unit; the kernels loop.
-constexpr int kMaxBlocks = 2048;
+constexpr int kMaxBlocks = 8192;
 
 static size_t stack_bytes(const TraceArgs& a) {
   return a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0;
