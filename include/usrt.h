@@ -127,7 +127,11 @@ typedef struct us_grid_desc {
 /* Last error message of the calling thread ("" if none). */
 const char* us_last_error(void);
 
-/* Context bound to one HIP device. */
+/* Context bound to one HIP device. Probes and scenes keep their device and
+ * may be destroyed before or after their context (compute calls need it
+ * alive). Every call that launches work makes the context's device current
+ * and first clears the HIP runtime's last-error state of the calling thread,
+ * so that it reports only its own launch failures. */
 int us_create(int device, us_ctx** out);
 int us_destroy(us_ctx* ctx);
 

@@ -90,6 +90,7 @@ struct Timed {
 
 struct us_probe {
   us_ctx* ctx;
+  int device;   // kept for destroy, which must not read the context
   us_probe_desc d;
   ProbeView pv;
   int M;
@@ -100,6 +101,7 @@ struct us_probe {
 
 struct us_scene {
   us_ctx* ctx;
+  int device;   // kept for destroy, which must not read the context
   int n_regions, n_planes, n_spheres, start_region, n_params;
   bool any_diffuse;
   double* theta;
@@ -118,6 +120,15 @@ struct us_scene {
   MeshDevice mesh;   // owns vrest, vnormal, vbasis, vmesh, vcur, nodes, tri
 };
 
+// Makes the device current and clears the runtime's last error, so that a
+// failure left by an unrelated earlier HIP call of this thread (the caller's,
+// or a destroy's) is not reported as this call's.
+static hipError_t bind_device(int device) {
+  const hipError_t e = hipSetDevice(device);
+  (void)hipGetLastError();
+  return e;
+}
+
 extern "C" {
 
 const char* us_last_error(void) { return g_err.c_str(); }
@@ -127,7 +138,7 @@ int us_create(int device, us_ctx** out) {
   int n = 0;
   US_HIP(hipGetDeviceCount(&n));
   US_CHECK(device >= 0 && device < n, "us_create: no such device");
-  US_HIP(hipSetDevice(device));
+  US_HIP(bind_device(device));
   *out = new us_ctx{device};
   return US_OK;
 }
@@ -154,9 +165,10 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
     taps[m + M] = (float)(std::sin(2.0 * M_PI * d->f0 * t) * std::exp(-t * t / sigma));
   }
   for (int i = 0; i < 2 * M + 1; ++i) rev[i] = taps[2 * M - i];
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   us_probe* p = new us_probe{};
   p->ctx = ctx;
+  p->device = ctx->device;
   p->d = *d;
   p->M = M;
   p->pv = ProbeView{d->n_elem, d->n_t, d->pitch, d->elem_width, d->elem_height, d->f0, d->fs,
@@ -184,7 +196,7 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
 
 int us_probe_destroy(us_probe* p) {
   if (!p) return US_OK;
-  (void)hipSetDevice(p->ctx->device);
+  (void)hipSetDevice(p->device);
   (void)hipFree(p->taps);
   (void)hipFree(p->taps_rev);
   (void)hipFree(p->twiddle);
@@ -284,9 +296,10 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_CHECK(build_mesh_bvh(d->vertices, nv, d->triangles, d->tmesh, nt, H) == 0,
              "us_scene_upload: mesh hierarchy too deep (degenerate triangle set)");
   }
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   us_scene* s = new us_scene{};
   s->ctx = ctx;
+  s->device = ctx->device;
   s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
   s->n_cylinders = nc;
   s->start_region = d->start_region; s->n_params = np; s->any_diffuse = diffuse;
@@ -365,7 +378,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
 
 int us_scene_destroy(us_scene* s) {
   if (!s) return US_OK;
-  (void)hipSetDevice(s->ctx->device);
+  (void)hipSetDevice(s->device);
   (void)hipFree(s->theta);
   (void)hipFree(s->plane_regions);
   (void)hipFree(s->plane_kd);
@@ -392,7 +405,7 @@ int us_scene_destroy(us_scene* s) {
 int us_scene_set_params(us_scene* s, const double* theta_dev, int32_t n_params, void* stream) {
   US_CHECK(s && theta_dev, "us_scene_set_params: NULL argument");
   US_CHECK(n_params == s->n_params, "us_scene_set_params: n_params does not match the scene");
-  US_HIP(hipSetDevice(s->ctx->device));
+  US_HIP(bind_device(s->ctx->device));
   US_HIP(hipMemcpyAsync(s->theta, theta_dev, n_params * sizeof(double), hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));
   if (s->n_meshes > 0) {
@@ -589,7 +602,7 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   }
   if (cap < std::min<int64_t>(256, (int64_t)n_tx * ray_count) || (ray_count > 0 && cap < 1))
     return fail(US_ETOOBIG, "us_simulate_rf: workspace too small (see us_simulate_rf_workspace_size)");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const us_probe_desc& pd = probe->d;
   Carver c{(char*)ws_dev};
@@ -709,7 +722,7 @@ int us_beamform(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, co
   if (rc) return rc;
   if (ws_bytes < us_beamform_workspace_size(probe, n_tx))
     return fail(US_ETOOBIG, "us_beamform: workspace too small");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   float2* A = (float2*)ws_dev;
   const long rows = (long)n_tx * probe->d.n_elem;
@@ -741,7 +754,7 @@ int us_bmode(us_ctx* ctx, const float* iq_dev, int64_t n_px, float dr_db, float*
   US_CHECK(n_px >= 1 && n_px < (int64_t(1) << 32) - 1, "us_bmode: n_px out of range");
   US_CHECK(dr_db > 0, "us_bmode: dr_db must be positive");
   if (ws_bytes < us_bmode_workspace_size(n_px)) return fail(US_ETOOBIG, "us_bmode: workspace too small");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* key = (unsigned long long*)ws_dev;
   launch_fill_u32((uint32_t*)key, 2, 0u, s);
@@ -760,7 +773,7 @@ int us_bmode_vjp(us_ctx* ctx, const float* iq_dev, const float* g_bmode_dev, int
   US_CHECK(n_px >= 1 && n_px < (int64_t(1) << 32) - 1, "us_bmode_vjp: n_px out of range");
   US_CHECK(dr_db > 0, "us_bmode_vjp: dr_db must be positive");
   if (ws_bytes < us_bmode_workspace_size(n_px)) return fail(US_ETOOBIG, "us_bmode_vjp: workspace too small");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* key = (unsigned long long*)ws_dev;
   double* sum = (double*)((char*)ws_dev + kAlign);
@@ -788,7 +801,7 @@ int us_image_loss(us_ctx* ctx, const float* bmode_dev, const float* ref_dev, int
   US_CHECK(ctx && bmode_dev && ref_dev && loss_dev, "us_image_loss: NULL argument");
   US_CHECK(n_px >= 1, "us_image_loss: n_px must be >= 1");
   US_CHECK(lambda1 >= 0 && lambda2 >= 0, "us_image_loss: weights must be non-negative");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   Timed tm(ctx, "image_loss", s);
   launch_fill_u32((uint32_t*)loss_dev, 2, 0u, s);
@@ -809,7 +822,7 @@ int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid
   if (rc) return rc;
   if (ws_bytes < us_beamform_vjp_workspace_size(probe, n_tx))
     return fail(US_ETOOBIG, "us_beamform_vjp: workspace too small");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   float2* gA = (float2*)ws_dev;
   const GridView g = grid_view(grid);
@@ -855,7 +868,7 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
     if (replay_bytes(scene, n_tx, probe, max_bounces, mid) <= ws_bytes) lo = mid; else hi = mid - 1;
   }
   const long cap = lo;
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const us_probe_desc& pd = probe->d;
   ReplayArgs a{};
@@ -931,7 +944,7 @@ int us_param_map(us_ctx* ctx, const double* u_dev, const double* lo_dev, const d
                  int32_t n, double* theta_dev, void* stream) {
   US_CHECK(ctx && u_dev && lo_dev && hi_dev && theta_dev, "us_param_map: NULL argument");
   US_CHECK(n >= 1, "us_param_map: n must be >= 1");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   Timed tm(ctx, "param_map", (hipStream_t)stream);
   launch_param_map(u_dev, lo_dev, hi_dev, n, theta_dev, (hipStream_t)stream);
   US_HIP(hipGetLastError());
@@ -948,7 +961,7 @@ int us_adam_step(us_ctx* ctx, double* u_dev, double* m_dev, double* v_dev,
   US_CHECK(step >= 1, "us_adam_step: step counts from 1");
   US_CHECK(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0,
            "us_adam_step: need 0 <= beta1, beta2 < 1 and eps > 0");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   Timed tm(ctx, "adam_step", (hipStream_t)stream);
   launch_adam(u_dev, m_dev, v_dev, g_theta_dev, lo_dev, hi_dev, lr_dev, n, step, beta1, beta2, eps,
               max_norm, (hipStream_t)stream);
@@ -966,7 +979,7 @@ int us_profile_read(us_ctx* ctx, int32_t max_kernels, char* names, double* total
                     int64_t* launches, int32_t* n_kernels) {
   US_CHECK(ctx && n_kernels && (max_kernels == 0 || (names && total_ms && launches)),
            "us_profile_read: NULL argument");
-  US_HIP(hipSetDevice(ctx->device));
+  US_HIP(bind_device(ctx->device));
   ProfileLog& L = ctx->prof;
   for (auto& p : L.pending) {
     US_HIP(hipEventSynchronize(p.b));

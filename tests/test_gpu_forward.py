@@ -221,6 +221,27 @@ def test_invalid_arguments_are_rejected(L, ctx):
         L.Scene(ctx, bad)
 
 
+def test_handles_destroyed_after_their_context(L, ctx):
+    """A garbage collector may finalize a context before its probe and scene
+    (objects in a reference cycle, such as the locals a caught exception's
+    traceback keeps). Destroying them afterwards must neither read the freed
+    context nor leave a HIP error that a later call on another context would
+    report as its own."""
+    wl = W.two_layer(rays_per_elem=4)
+    lib = L.load()
+    for _ in range(3):
+        c2 = L.Context(0)
+        probe, scene = L.Probe(c2, wl.probe), L.Scene(c2, wl.scene)
+        assert lib.us_destroy(c2.handle) == L.US_OK
+        c2.handle = None
+        assert lib.us_probe_destroy(probe.handle) == L.US_OK
+        probe.handle = None
+        assert lib.us_scene_destroy(scene.handle) == L.US_OK
+        scene.handle = None
+    g = gpu_trace(L, ctx, wl)   # checks the runtime's last error after its launches
+    assert np.isfinite(g["rf"]).all() and g["counters"][0] > 0
+
+
 # ------------------------------------------------------------------ image chain
 def _gpu_image(L, ctx, wl, rf_np):
     import torch
