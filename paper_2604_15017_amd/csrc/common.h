@@ -128,6 +128,7 @@ struct SceneView {
 // Per-block copy of the scene in LDS.
 struct SceneLDS {
   double c[kMaxRegions], Z[kMaxRegions], a[kMaxRegions];
+  double ic[kMaxRegions];   // 1 / c: travel time per metre
   double pd[kMaxPlanes], pkd[kMaxPlanes];
   int pr[kMaxPlanes][2];
   double sx[kMaxSpheres], sy[kMaxSpheres], sz[kMaxSpheres], sr[kMaxSpheres], skd[kMaxSpheres];
@@ -151,6 +152,7 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
   const int nr = v.n_regions;
   for (int i = t; i < nr; i += blockDim.x) {
     s.c[i] = v.theta[3 * i];
+    s.ic[i] = 1.0 / v.theta[3 * i];
     s.Z[i] = v.theta[3 * i + 1];
     s.a[i] = v.theta[3 * i + 2] * v.np_per_m;
   }

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
       ++n_seg;
       if (kAudit) hsum += event_mix(kEvHit, k, ((uint32_t)h.kind << 24) | ((uint32_t)(hit_id(S, h) + 1) & 0xFFFFFFu));
       if (h.kind != kHitNone) {
-        t += h.t / S.c[region];
+        t += h.t * S.ic[region];
         w *= exp(-(S.a[region] * h.t));
         x = o + d * h.t;
         if (h.kind == kHitArray) {
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 // each, zero on total internal reflection), attenuation and travel time per
 // medium, then the deposit.
 template <bool kAudit, bool kMeshes>
-__global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4 : 5, 8))) void k_secondary(TraceArgs a, int k) {
   const long n_in = (long)(a.counts[k] >> 32);
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
     const double r = sqrt(dot(dv, dv));
     const d3 we = dv * (1.0 / r);
     d3 p = x;
-    double remaining = r;
+    double remaining = r, att = 0.0;   // att: sum of alpha times length over the legs
     uint32_t crossings = 0;
     bool blocked = true;
     const int legs = max_legs(S);
@@ -236,13 +236,13 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
       const Hit h = closest_hit<kMeshes>(S, p, we, false, stk, remaining);
       ++n_seg;
       if (h.kind == kHitNone || h.t >= remaining) {
-        tof += remaining / S.c[reg];
-        amp *= exp(-(S.a[reg] * remaining));
+        tof += remaining * S.ic[reg];
+        att += S.a[reg] * remaining;
         blocked = false;
         break;
       }
-      tof += h.t / S.c[reg];
-      amp *= exp(-(S.a[reg] * h.t));
+      tof += h.t * S.ic[reg];
+      att += S.a[reg] * h.t;
       remaining -= h.t;
       p = p + we * h.t;
       const Surface sf = surface_of(S, h, p, reg);
@@ -256,6 +256,7 @@ __global__ __launch_bounds__(256) void k_secondary(TraceArgs a, int k) {
     bool rec = false;
     if (!blocked) {
       ++n_dep;
+      amp *= exp(-att);   // the attenuation of all legs at once
       rec = make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, tof, amp, &dp);
     }
     // record for the binned splat (one atomic per wave on this block's shard
