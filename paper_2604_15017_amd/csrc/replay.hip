@@ -312,7 +312,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
                       (double)P.n_elem * fd;
   // pass 1: the march as the forward did it
   const int legs = max_legs(S);
-  double tof = tp, rest = 1.0;
+  double tof = tp, rest = 1.0, att = 0.0;   // rest: transmissions, then times e^-att
   int n_cross = 0;
   {
     d3 p = x;
@@ -323,8 +323,8 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
     for (int leg = 0; leg < legs; ++leg) {
       const Hit h = closest_hit<kMeshes>(S, p, we, false, C.stk, remaining);
       if (h.kind == kHitNone || h.t >= remaining) {
-        tof += remaining / S.c[reg];
-        rest *= exp(-(S.a[reg] * remaining));
+        tof += remaining * S.ic[reg];
+        att += S.a[reg] * remaining;
         reached = true;
         break;
       }
@@ -333,8 +333,8 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
         C.leg_h[leg * step] = (h.kind << 28) | h.index;
       }
       ++n_cross;
-      tof += h.t / S.c[reg];
-      rest *= exp(-(S.a[reg] * h.t));
+      tof += h.t * S.ic[reg];
+      att += S.a[reg] * h.t;
       remaining -= h.t;
       p = p + we * h.t;
       const Surface sf = surface_of(S, h, p, reg);
@@ -344,6 +344,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
       reg = sf.other;
     }
     if (!reached) return;   // the forward dropped this deposit
+    rest *= exp(-att);      // the attenuation of all legs at once, as the forward
   }
   const double amp = amp0 * rest;
   double GA, GT;
@@ -601,7 +602,7 @@ __global__ void k_replay_prefix(ReplayArgs a) {
 }
 
 template <bool kMeshes>
-__global__ __launch_bounds__(256) void k_replay_secondary(ReplayArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2 : 3, 8))) void k_replay_secondary(ReplayArgs a) {
   const int B = a.max_bounces;
   const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
   if ((long)blockIdx.x * blockDim.x >= n_q) return;
