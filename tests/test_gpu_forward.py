@@ -322,6 +322,55 @@ def test_tiled_and_gather_beamformers_on_a_large_grid(L, ctx):
     assert rel_l2(win, small) <= 1e-6
 
 
+def _window_widths(p, g, angles, tile=16):
+    """Sample-window lengths of every (tile, element, transmit) of a tiled
+    beamformer with the conservative bound of the tile's corners (the
+    transmit term's extremes plus the receive distance's, one sample of slack
+    on each side), computed here from the geometry alone."""
+    spm = p.fs / p.c_ref
+    out = []
+    for a0 in range(0, g.n_x, tile):
+        for b0 in range(0, g.n_z, tile):
+            xa, xb = g.x0 + a0 * g.dx, g.x0 + (min(a0 + tile, g.n_x) - 1) * g.dx
+            za, zb = g.z0 + b0 * g.dz, g.z0 + (min(b0 + tile, g.n_z) - 1) * g.dz
+            xe = (np.arange(p.n_elem) - 0.5 * (p.n_elem - 1)) * p.pitch
+            near = np.where(xe < xa, xa - xe, np.where(xe > xb, xe - xb, 0.0))
+            far = np.maximum(np.abs(xe - xa), np.abs(xe - xb))
+            for th in angles:
+                l = [xa * np.sin(th) + za * np.cos(th), xb * np.sin(th) + za * np.cos(th),
+                     xa * np.sin(th) + zb * np.cos(th), xb * np.sin(th) + zb * np.cos(th)]
+                lo = np.floor((min(l) + np.hypot(near, za)) * spm) - 1
+                hi = np.floor((max(l) + np.hypot(far, zb)) * spm) + 2
+                out.append(hi - lo + 1)
+    return np.concatenate(out)
+
+
+def test_tiled_beamformer_wide_windows_and_ragged_groups(L, ctx):
+    """127 elements x 5 transmits (635 pairs: the last group of 16 is partial)
+    on a 128 x 160 grid of 0.12 mm rows, so that about 40 % of the tile
+    windows exceed the 144 samples held in LDS and are read from HBM while the
+    rest come from LDS; seeded random channels against the oracle's fp64
+    delay-and-sum."""
+    import dataclasses
+    wl = W.two_layer()
+    p = dataclasses.replace(wl.probe, n_elem=127)
+    g = W.Grid.span(128, 160, -12e-3, 12e-3, 2e-3, 2e-3 + 160 * 0.12e-3)
+    angles = np.radians([-8.0, -4.0, 0.0, 4.0, 8.0])
+    wl = wl.replace(probe=p, grid=g, angles=angles, tx_ids=np.arange(5, dtype=np.uint32))
+    widths = _window_widths(p, g, angles)
+    assert (widths > 144).any() and (widths <= 144).any(), (widths.min(), widths.max())
+    assert (p.n_elem * len(angles)) % 16 != 0 and (g.n_x // 16) * (g.n_z // 16) >= 64
+    rng = np.random.default_rng(21)
+    k = np.exp(-0.5 * (np.arange(-12, 13) / 4.0) ** 2)
+    rf = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), -1,
+                             rng.standard_normal((5, p.n_elem, p.n_t))).astype(np.float32)
+    I = oracle.das(oracle.analytic(rf.astype(np.float64)), p, g, angles)
+    Ig, _ = _gpu_image(L, ctx, wl, rf)
+    rel = rel_l2(Ig, I)
+    print(f"wide windows {np.mean(widths > 144):.2f} of tile pairs: iq rel-L2 {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
 def test_end_to_end_bmode_full_size(L, ctx):
     wl = W.two_layer()
     out = oracle.render(wl)
