@@ -38,13 +38,22 @@ def kernel_bytes(name, wl, counts, n_px):
     seg_p, seg_s, dep, inter, sec = counts
     row_samples = wl.n_tx * p.n_elem * p.n_t
     state = 8 * 8 + 2 * 4          # ray state in the queue [B]
+    has_meshes = len(getattr(wl.scene, "meshes", ()) or ()) > 0
     sec_rec = 5 * 8 + 3 * 4        # secondary-ray record [B]
     return {
         # every primary segment after the first reads a queued state, every
         # surviving ray writes one, every diffuse hit writes a secondary record
         "bounce": 2 * state * (seg_p - rays) + sec_rec * sec,
-        # each secondary record is read once; each deposit updates two fp32 bins
-        "secondary": sec_rec * sec + 8 * dep,
+        # each secondary record is read once; each deposit writes a 12-byte
+        # record for the binned splat (scenes with meshes: two fp32 bins)
+        "secondary": sec_rec * sec + (8 if has_meshes else 12) * dep,
+        # binned splat (scenes without meshes): the counting pass reads each
+        # record's 4-byte key, the scatter reads the 12-byte record and writes
+        # it as 16 bytes; the accumulation reads the 16 bytes and updates every
+        # RF bin once. `dep` also counts the few array hits that the bounce
+        # kernel adds directly, so these are upper bounds on the records.
+        "splat_bin": None if has_meshes else (4 + 12 + 16) * dep,
+        "splat_accumulate": None if has_meshes else 16 * dep + 8 * row_samples,
         "pulse": 8 * row_samples,
         "pulse_adjoint": 8 * row_samples,
         "analytic_adjoint": 12 * row_samples,
