@@ -276,8 +276,12 @@ __device__ __forceinline__ DasWindow das_window(const ProbeView& p, const TxTabl
   const double dx_near = xe < xa ? xa - xe : (xe > xb ? xe - xb : 0.0);
   const double dx_far = fmax(fabs(xe - xa), fabs(xe - xb));
   const double rmin = sqrt(dx_near * dx_near + za * za), rmax = sqrt(dx_far * dx_far + zb * zb);
+  // samples [klo, khi], not clipped to the record: the loader fills samples
+  // outside [0, n_t) with zeros, so a tap reads its two samples from the
+  // window and taps beyond the record add zero, as the plain sum skips them
+  // (the limits below only keep far-off windows finite; they come out wide)
   const double klo = floor((lmin + rmin) * s_per_m) - 1.0, khi = floor((lmax + rmax) * s_per_m) + 2.0;
-  const double lo = fmax(klo, -1.0), hi = fmin(khi, (double)p.n_t);   // samples [lo, hi]
+  const double lo = fmax(klo, -2.0 * kDasSpan), hi = fmin(khi, (double)p.n_t + 2.0 * kDasSpan);
   return DasWindow{((long)(tx_base + i) * p.n_elem + e) * p.n_t, (int)lo, hi >= lo ? (int)(hi - lo) + 1 : 0};
 }
 
@@ -286,7 +290,7 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
                                                            int tx_base, int accumulate, int tiles_z) {
   __shared__ float2 win[2][kDasGroup * kDasSpan];
   __shared__ DasWindow wb[3][kDasGroup];
-  __shared__ int wide[3];   // the group has a window wider than kDasSpan (or is partial)
+  __shared__ int wide[3];   // the group is partial or has a window wider than kDasSpan or under 2
   __shared__ TxSplit ts[kMaxTxPerLaunch];
   const int a0 = (blockIdx.x / tiles_z) * kDasTx, b0 = (blockIdx.x % tiles_z) * kDasTz;
   const int ia = (int)threadIdx.x / kDasTz, ib = (int)threadIdx.x % kDasTz;
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
     if ((int)threadIdx.x < kDasGroup) {
       const DasWindow w = q < n_pairs ? das_window(p, tx, n_tx, tx_base, q, xa, xb, za, zb) : DasWindow{0, 0, 0};
       wb[buf][threadIdx.x] = w;
-      const unsigned long long m = __ballot(q >= n_pairs || w.n > kDasSpan);   // lanes 0..15 of wave 0
+      const unsigned long long m = __ballot(q >= n_pairs || w.n > kDasSpan || w.n < 2);   // lanes 0..15 of wave 0
       if (threadIdx.x == 0) wide[buf] = m != 0ull;
     }
   };
@@ -352,7 +356,7 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
     const int nq = min(kDasGroup, n_pairs - grp * kDasGroup);
     if (!wide[grp % 3]) {
       // whole group, every window in LDS: all indices first, then the reads
-      // and sums without branches (out-of-range samples weigh zero)
+      // and sums without branches (samples outside the record are zeros)
 #pragma unroll 1
       for (int j0 = 0; j0 < kDasGroup; j0 += kDasBatch) {
         int kk[kDasBatch];
@@ -377,13 +381,12 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
 #pragma unroll
         for (int j = 0; j < kDasBatch; ++j) {
           const DasWindow w = wc[j0 + j];
-          const int k0 = kk[j];
-          const bool ok = inside && k0 >= -1 && k0 < p.n_t && w.n >= 2;
-          const int o = (j0 + j) * kDasSpan + min(max(k0 - w.lo, 0), max(w.n - 2, 0));
+          // within [0, n - 2] by the window bound (n >= 2 in this path);
+          // clamped so that a read never leaves the pair's window
+          const int o = (j0 + j) * kDasSpan + min(max(kk[j] - w.lo, 0), w.n - 2);
           const float2 v0 = win[cur][o], v1 = win[cur][o + 1];
-          const float f1 = ok ? fk[j] : 0.0f, f0 = ok ? 1.0f - fk[j] : 0.0f;
-          acc.x += f0 * v0.x + f1 * v1.x;
-          acc.y += f0 * v0.y + f1 * v1.y;
+          acc.x += fmaf(fk[j], v1.x - v0.x, v0.x);
+          acc.y += fmaf(fk[j], v1.y - v0.y, v0.y);
         }
       }
     } else for (int j = 0; j < nq; ++j) {
