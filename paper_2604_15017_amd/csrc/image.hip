@@ -261,6 +261,7 @@ constexpr int kDasStage = kDasGroup * kDasSpan / kDasThreads;   // staged sample
 static_assert(kDasGroup * kDasSpan % kDasThreads == 0, "window stage must split evenly");
 static_assert(kDasGroup <= kDasThreads && kMaxTxPerLaunch <= kDasThreads, "one thread per bound");
 constexpr long kDasMinTiles = 64;            // below this the grid cannot fill the chip: gather
+constexpr long kDasSliceTiles = 1024;        // below this a tile's pairs are split over two slices
 
 struct DasWindow { long row; int lo, n; };   // channel offset in A, first sample, length
 struct TxSplit { int ib; float fb, da, db; };   // transmit term at the tile origin, steps per pixel
@@ -285,15 +286,19 @@ __device__ __forceinline__ DasWindow das_window(const ProbeView& p, const TxTabl
   return DasWindow{((long)(tx_base + i) * p.n_elem + e) * p.n_t, (int)lo, hi >= lo ? (int)(hi - lo) + 1 : 0};
 }
 
-__global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq,
-                                                           ProbeView p, GridView g, TxTable tx, int n_tx,
-                                                           int tx_base, int accumulate, int tiles_z) {
-  __shared__ float2 win[2][kDasGroup * kDasSpan];
-  __shared__ DasWindow wb[3][kDasGroup];
-  __shared__ int wide[3];   // the group is partial or has a window wider than kDasSpan or under 2
+template <int kS>
+__global__ __launch_bounds__(kDasThreads * kS) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq, ProbeView p, GridView g, TxTable tx,
+                 int n_tx, int tx_base, int accumulate, int tiles_z) {
+  __shared__ float2 win[kS][2][kDasGroup * kDasSpan];
+  __shared__ DasWindow wb[kS][3][kDasGroup];
+  __shared__ int wide[kS][3];   // the group is partial or has a window wider than kDasSpan or under 2
   __shared__ TxSplit ts[kMaxTxPerLaunch];
+  // kS slices of kDasThreads threads share the tile: slice sl takes the
+  // sl-th run of pair groups, and the partial sums are added in slice order
+  const int sl = (int)threadIdx.x / kDasThreads, tid = (int)threadIdx.x % kDasThreads;
   const int a0 = (blockIdx.x / tiles_z) * kDasTx, b0 = (blockIdx.x % tiles_z) * kDasTz;
-  const int ia = (int)threadIdx.x / kDasTz, ib = (int)threadIdx.x % kDasTz;
+  const int ia = tid / kDasTz, ib = tid % kDasTz;
   const int a = a0 + ia, b = b0 + ib;
   const bool inside = a < g.n_x && b < g.n_z;
   const long px = (long)a * g.n_z + b;
@@ -305,6 +310,10 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
   const double half = 0.5 * (double)(p.n_elem - 1);
   const int n_pairs = p.n_elem * n_tx;
   const int n_groups = (n_pairs + kDasGroup - 1) / kDasGroup;
+  // groups per slice (the same loop count for all), first group, end of pairs
+  const int per = kS == 1 ? n_groups : (n_groups + kS - 1) / kS;
+  const int g0 = kS == 1 ? 0 : sl * per;
+  const int q_end = kS == 1 ? n_pairs : min(n_pairs, (g0 + per) * kDasGroup);
   if ((int)threadIdx.x < n_tx) {
     const int i = threadIdx.x;
     const double kt = (xa * tx.sin_a[i] + za * tx.cos_a[i]) * s_per_m;
@@ -312,20 +321,20 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
     ts[i] = TxSplit{(int)fl, (float)(kt - fl), (float)(g.dx * tx.sin_a[i] * s_per_m),
                     (float)(g.dz * tx.cos_a[i] * s_per_m)};
   }
-  auto bounds = [&](int grp, int buf) {
-    const int q = grp * kDasGroup + (int)threadIdx.x;
-    if ((int)threadIdx.x < kDasGroup) {
-      const DasWindow w = q < n_pairs ? das_window(p, tx, n_tx, tx_base, q, xa, xb, za, zb) : DasWindow{0, 0, 0};
-      wb[buf][threadIdx.x] = w;
-      const unsigned long long m = __ballot(q >= n_pairs || w.n > kDasSpan || w.n < 2);   // lanes 0..15 of wave 0
-      if (threadIdx.x == 0) wide[buf] = m != 0ull;
+  auto bounds = [&](int grp, int buf) {   // grp: the slice's own group index
+    const int q = (g0 + grp) * kDasGroup + tid;
+    if (tid < kDasGroup) {
+      const DasWindow w = q < q_end ? das_window(p, tx, n_tx, tx_base, q, xa, xb, za, zb) : DasWindow{0, 0, 0};
+      wb[sl][buf][tid] = w;
+      const unsigned long long m = __ballot(q >= q_end || w.n > kDasSpan || w.n < 2);   // the slice's lanes 0..15
+      if (tid == 0) wide[sl][buf] = m != 0ull;
     }
   };
   float2 st[kDasStage];
   auto load = [&](const DasWindow* w) {
 #pragma unroll
     for (int r = 0; r < kDasStage; ++r) {
-      const int f = r * kDasThreads + (int)threadIdx.x;
+      const int f = r * kDasThreads + tid;
       const int j = f / kDasSpan, t = f - j * kDasSpan;
       const DasWindow ww = w[j];
       const int k = ww.lo + t;
@@ -334,27 +343,29 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
   };
   auto store = [&](float2* dst) {
 #pragma unroll
-    for (int r = 0; r < kDasStage; ++r) dst[r * kDasThreads + threadIdx.x] = st[r];
+    for (int r = 0; r < kDasStage; ++r) dst[r * kDasThreads + tid] = st[r];
   };
 
   bounds(0, 0);
-  if (n_groups > 1) bounds(1, 1);
+  if (per > 1) bounds(1, 1);
   __syncthreads();
-  load(wb[0]);
-  store(win[0]);
+  load(wb[sl][0]);
+  store(win[sl][0]);
   __syncthreads();
 
-  float2 acc = (accumulate && inside) ? iq[px] : make_float2(0.0f, 0.0f);
+  float2 acc = (accumulate && inside && sl == 0) ? iq[px] : make_float2(0.0f, 0.0f);
   const float fa = (float)ia, fz = (float)ib;
-  int e = 0, i = 0, rx_e = -1, rx_i = 0;
+  const int q_first = min(g0 * kDasGroup, n_pairs);
+  int e = q_first / n_tx, i = q_first % n_tx, rx_e = -1, rx_i = 0;
   float rx_f = 0.0f;
-  for (int grp = 0; grp < n_groups; ++grp) {
+  for (int grp = 0; grp < per; ++grp) {
     const int cur = grp & 1;
-    const DasWindow* wc = wb[grp % 3];
-    if (grp + 1 < n_groups) load(wb[(grp + 1) % 3]);          // in flight during the sums below
-    if (grp + 2 < n_groups) bounds(grp + 2, (grp + 2) % 3);
-    const int nq = min(kDasGroup, n_pairs - grp * kDasGroup);
-    if (!wide[grp % 3]) {
+    const DasWindow* wc = wb[sl][grp % 3];
+    if (grp + 1 < per) load(wb[sl][(grp + 1) % 3]);          // in flight during the sums below
+    if (grp + 2 < per) bounds(grp + 2, (grp + 2) % 3);
+    const int nq = min(kDasGroup, q_end - (g0 + grp) * kDasGroup);
+    const float2* wcur = win[sl][cur];
+    if (!wide[sl][grp % 3]) {
       // whole group, every window in LDS: all indices first, then the reads
       // and sums without branches (samples outside the record are zeros)
 #pragma unroll 1
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
           // within [0, n - 2] by the window bound (n >= 2 in this path);
           // clamped so that a read never leaves the pair's window
           const int o = (j0 + j) * kDasSpan + min(max(kk[j] - w.lo, 0), w.n - 2);
-          const float2 v0 = win[cur][o], v1 = win[cur][o + 1];
+          const float2 v0 = wcur[o], v1 = wcur[o + 1];
           acc.x += fmaf(fk[j], v1.x - v0.x, v0.x);
           acc.y += fmaf(fk[j], v1.y - v0.y, v0.y);
         }
@@ -409,8 +420,8 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
           float2 v0, v1;
           if (w.n <= kDasSpan) {
             const int o = min(max(k0 - w.lo, 0), w.n - 2);   // within [0, n - 2] by the window bound
-            v0 = win[cur][j * kDasSpan + o];
-            v1 = win[cur][j * kDasSpan + o + 1];
+            v0 = wcur[j * kDasSpan + o];
+            v1 = wcur[j * kDasSpan + o + 1];
           } else {
             const float2* row = A + w.row;
             v0 = k0 >= 0 ? row[k0] : make_float2(0.0f, 0.0f);
@@ -422,10 +433,24 @@ __global__ __launch_bounds__(kDasThreads) __attribute__((amdgpu_waves_per_eu(4, 
       }
       if (++i == n_tx) { i = 0; ++e; }
     }
-    if (grp + 1 < n_groups) store(win[cur ^ 1]);
+    if (grp + 1 < per) store(win[sl][cur ^ 1]);
     __syncthreads();
   }
-  if (inside) iq[px] = acc;
+  if (kS > 1) {   // slice partial sums, added in slice order (the loop ended with a barrier)
+    float2* part = &win[0][0][0];
+    if (sl > 0) part[(sl - 1) * kDasThreads + tid] = acc;
+    __syncthreads();
+    if (sl == 0) {
+      for (int t = 1; t < kS; ++t) {
+        const float2 v = part[(t - 1) * kDasThreads + tid];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+      if (inside) iq[px] = acc;
+    }
+  } else if (inside) {
+    iq[px] = acc;
+  }
 }
 
 // Frame maximum of |I|^2 with the first index among equals, packed as
@@ -738,8 +763,14 @@ void launch_das(const float2* A, float2* iq, const ProbeView& p, const GridView&
   const int tiles_x = (g.n_x + kDasTx - 1) / kDasTx, tiles_z = (g.n_z + kDasTz - 1) / kDasTz;
   const long tiles = (long)tiles_x * tiles_z;
   if (tiles >= kDasMinTiles) {
-    hipLaunchKernelGGL(k_das_tiled, dim3((unsigned)tiles), dim3(kDasTx * kDasTz), 0, s, A, iq, p, g, tx,
-                       n_tx_group, tx_base, accumulate ? 1 : 0, tiles_z);
+    // grids of fewer than 1024 tiles split each tile's pairs over two slices
+    // of one block, so that the chip still holds four waves per SIMD
+    if (tiles < kDasSliceTiles)
+      hipLaunchKernelGGL(k_das_tiled<2>, dim3((unsigned)tiles), dim3(2 * kDasThreads), 0, s, A, iq, p, g, tx,
+                         n_tx_group, tx_base, accumulate ? 1 : 0, tiles_z);
+    else
+      hipLaunchKernelGGL(k_das_tiled<1>, dim3((unsigned)tiles), dim3(kDasThreads), 0, s, A, iq, p, g, tx,
+                         n_tx_group, tx_base, accumulate ? 1 : 0, tiles_z);
   } else {
     const long n_px = (long)g.n_x * g.n_z;
     hipLaunchKernelGGL(k_das_gather, dim3((unsigned)((n_px + 255) / 256)), dim3(256), 0, s, A, iq, p, g, tx,
