@@ -197,14 +197,13 @@ __global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* 
   fft_pass_bits<kIoLds, kOut>(bits[n_pass - 1], x, nullptr, dst, n, L, lo, hi);
 }
 
-// Delay-and-sum, one pixel per thread, threads along z. The fractional
-// sample index is formed in fp64 (an fp32 index near 4000 carries 2.4e-4
-// samples of rounding, i.e. 2e-4 rad of phase per tap at 5 MHz / 40 MHz);
-// interpolation and accumulation are fp32.
-// One thread per pixel, reading the two samples of every (element,
-// transmit) pair straight from HBM through the caches; used for grids too
-// small to fill the chip with pixel tiles. Same sums in the same order as
-// k_das_tiled, with the sample index formed in fp64 throughout.
+// Delay-and-sum, one pixel per thread, threads along z, reading the two
+// samples of every (element, transmit) pair straight from HBM through the
+// caches; used for grids too small to fill the chip with pixel tiles. The
+// fractional sample index is formed in fp64 (an fp32 index near 4000 carries
+// 2.4e-4 samples of rounding, i.e. 2e-4 rad of phase per tap at 5 MHz /
+// 40 MHz); interpolation and accumulation are fp32, in the element-major pair
+// order of the plain sum.
 __global__ __launch_bounds__(256) void k_das_gather(const float2* __restrict__ A, float2* __restrict__ iq,
                                                     ProbeView p, GridView g, TxTable tx, int n_tx,
                                                     int tx_base, int accumulate) {
