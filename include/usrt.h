@@ -205,8 +205,11 @@ int us_image_loss(us_ctx* ctx, const float* bmode_dev, const float* ref_dev, int
 int us_bmode_vjp(us_ctx* ctx, const float* iq_dev, const float* g_bmode_dev, int64_t n_px,
                  float dr_db, float* g_iq_dev, void* ws_dev, size_t ws_bytes, void* stream);
 /* g_rf = adjoint of us_beamform (Eq. das_adjoint, then the self-adjoint
- * analytic-signal map, real part). Computed per RF sample as a gather over
- * the pixels that interpolate from it; no atomics.
+ * analytic-signal map, real part). Computed per RF row in LDS, the image
+ * walked column by column (a column's pixels touch disjoint sample pairs
+ * when the grid's rows are more than two samples apart), else per RF sample
+ * as a gather over the pixels that interpolate from it; no atomics either
+ * way, so the result does not depend on scheduling.
  *   g_iq_dev in: float [n_x][n_z][2]; g_rf_dev out: float [n_tx][n_elem][n_t] */
 size_t us_beamform_vjp_workspace_size(const us_probe* probe, int32_t n_tx);
 int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
