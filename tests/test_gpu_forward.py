@@ -371,6 +371,27 @@ def test_tiled_beamformer_wide_windows_and_ragged_groups(L, ctx):
     assert rel <= 1e-5
 
 
+def test_beamform_more_transmits_than_one_launch(L, ctx):
+    """70 transmits: the library beamforms them in two launches (64, then 6,
+    the second adding into the image) with the two-slice tiled kernel
+    (64 tiles); seeded random channels against the oracle."""
+    import dataclasses
+    wl = W.two_layer()
+    p = dataclasses.replace(wl.probe, n_elem=48)
+    g = W.Grid.span(128, 128, -6e-3, 6e-3, 4e-3, 4e-3 + 128 * 0.12e-3)
+    angles = np.radians(np.linspace(-12.0, 12.0, 70))
+    wl = wl.replace(probe=p, grid=g, angles=angles, tx_ids=np.arange(70, dtype=np.uint32))
+    rng = np.random.default_rng(5)
+    k = np.exp(-0.5 * (np.arange(-12, 13) / 4.0) ** 2)
+    rf = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), -1,
+                             rng.standard_normal((70, p.n_elem, p.n_t))).astype(np.float32)
+    I = oracle.das(oracle.analytic(rf.astype(np.float64)), p, g, angles)
+    Ig, _ = _gpu_image(L, ctx, wl, rf)
+    rel = rel_l2(Ig, I)
+    print(f"70 transmits: iq rel-L2 {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+
+
 def test_end_to_end_bmode_full_size(L, ctx):
     wl = W.two_layer()
     out = oracle.render(wl)
