@@ -107,20 +107,97 @@ __global__ __launch_bounds__(1024) void k_dep_rowscan(int n_rows, BinScratch bs)
   if (threadIdx.x == 1023) bs.row_begin[n_rows] = part[1023];
 }
 
+// Records move in chunks of kScatChunk: each chunk is counted and ranked per
+// row in LDS, the counts are scanned into staging offsets, the records are
+// staged in row order with their final position in the spare word, and then
+// written out by consecutive threads, so that a row's run of the chunk leaves
+// as contiguous 16-byte stores instead of scattered ones.
+constexpr int kScatChunk = 4 * kBinThreads;
+constexpr int kRowsPerThread = kMaxBinRows / kBinThreads;
+static_assert(kMaxBinRows % kBinThreads == 0, "rows per thread");
+
 __global__ __launch_bounds__(kBinThreads) void k_dep_scatter(DepositList dep, const unsigned long long* count,
                                                              long shard_cap, int n_rows, BinScratch bs,
                                                              uint4* __restrict__ sorted) {
-  __shared__ uint32_t cur[kMaxBinRows];
-  for (int r = threadIdx.x; r < n_rows; r += blockDim.x)
+  __shared__ uint32_t cur[kMaxBinRows];   // next position of each row in this block's range
+  __shared__ uint32_t off[kMaxBinRows];   // the chunk's count, then staging start, per row
+  __shared__ uint4 stage[kScatChunk];
+  __shared__ uint32_t wsum[kBinThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r = tid; r < n_rows; r += blockDim.x)
     cur[r] = bs.row_begin[r] + bs.hist[(long)r * kBinBlocks + blockIdx.x];
-  __syncthreads();
   long b0, b1;
   block_range(count, shard_cap, &b0, &b1);
-  for (long i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-    const uint32_t k = dep.key[i];
-    const uint32_t pos = atomicAdd(&cur[k >> kDepBinBits], 1u);
-    const float2 w = dep.w[i];
-    sorted[pos] = make_uint4(k, __float_as_uint(w.x), __float_as_uint(w.y), 0u);   // one 16-byte store
+  const int R = (n_rows + kBinThreads - 1) / kBinThreads;   // rows owned per thread (<= kRowsPerThread)
+  for (long c0 = b0; c0 < b1; c0 += kScatChunk) {
+    const int nc = (int)min((long)kScatChunk, b1 - c0);
+    for (int r = tid; r < n_rows; r += blockDim.x) off[r] = 0u;
+    __syncthreads();
+    uint32_t key[4], rank[4];
+    float2 w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = u * kBinThreads + tid;
+      if (j < nc) {
+        key[u] = dep.key[c0 + j];
+        w[u] = dep.w[c0 + j];
+        rank[u] = atomicAdd(&off[key[u] >> kDepBinBits], 1u);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the counts over the rows (thread t owns rows t R ..)
+    uint32_t c[kRowsPerThread];
+    uint32_t tsum = 0;
+#pragma unroll
+    for (int j = 0; j < kRowsPerThread; ++j) {
+      const int r = tid * R + j;
+      c[j] = (j < R && r < n_rows) ? off[r] : 0u;
+      tsum += c[j];
+    }
+    uint32_t incl = tsum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int v = 0; v < kBinThreads / 64; ++v) {
+        const uint32_t x = wsum[v];
+        wsum[v] = run;
+        run += x;
+      }
+    }
+    __syncthreads();
+    uint32_t at = wsum[wave] + incl - tsum;
+#pragma unroll
+    for (int j = 0; j < kRowsPerThread; ++j) {
+      const int r = tid * R + j;
+      if (j < R && r < n_rows) { off[r] = at; at += c[j]; }
+    }
+    __syncthreads();
+    // stage in row order, the final position in the spare word
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u * kBinThreads + tid < nc) {
+        const uint32_t row = key[u] >> kDepBinBits;
+        stage[off[row] + rank[u]] = make_uint4(key[u], __float_as_uint(w[u].x), __float_as_uint(w[u].y),
+                                               cur[row] + rank[u]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRowsPerThread; ++j) {
+      const int r = tid * R + j;
+      if (j < R && r < n_rows) cur[r] += c[j];
+    }
+    for (int j = tid; j < nc; j += kBinThreads) {
+      const uint4 v = stage[j];
+      sorted[v.w] = make_uint4(v.x, v.y, v.z, 0u);
+    }
+    __syncthreads();
   }
 }
 
