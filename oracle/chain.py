@@ -33,7 +33,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["pulse_taps", "pulse", "pulse_vjp", "analytic", "analytic_vjp", "das_index", "das",
-           "das_vjp", "bmode", "bmode_vjp", "mse", "mse_grad", "simulate_rf", "render",
+           "das_vjp", "das_acq_vjp", "bmode", "bmode_vjp", "mse", "mse_grad", "simulate_rf", "render",
            "grad_theta", "analytic_multiplier"]
 
 LOG_SCALE = 20.0 / math.log(10.0)
@@ -147,6 +147,43 @@ def das_vjp(g_I: np.ndarray, probe, grid, angles, n_t: int) -> np.ndarray:
                 g_A[i, e] += np.bincount(idx[ok], weights=(wgt[ok] * gr[ok].real), minlength=n_t) \
                     + 1j * np.bincount(idx[ok], weights=(wgt[ok] * gr[ok].imag), minlength=n_t)
     return g_A
+
+
+def das_acq_vjp(A: np.ndarray, g_I: np.ndarray, probe, grid, angles):
+    """Gradient of L = Re sum conj(g_I) I with respect to the acquisition
+    parameters of Eq. das at fixed analytic signal A: each transmit's steering
+    angle, the beamforming speed of sound c_ref and the element pitch.
+
+    I depends on them only through the fractional sample index k = fs tau, and
+    the linear interpolation lerp(A, k) has slope A[k0 + 1] - A[k0] in k on
+    each sample interval, so dL/dk = Re(conj(g_I) (A[k0 + 1] - A[k0])). With
+    k = fs ((x sin th + z cos th) + r_e) / c_ref, r_e = |(x, z) - (x_e, 0)| and
+    x_e = (e - (N - 1)/2) pitch:
+        dk/dth    = fs (x cos th - z sin th) / c_ref
+        dk/dc_ref = -k / c_ref
+        dk/dpitch = -fs (x - x_e) (e - (N - 1)/2) / (r_e c_ref).
+    Returns (g_angles [n_tx], g_c_ref, g_pitch)."""
+    n_t = A.shape[-1]
+    X, Z = _pixels(grid)
+    half = 0.5 * (probe.n_elem - 1)
+    g_th = np.zeros(len(angles))
+    g_c = 0.0
+    g_p = 0.0
+    for i, th in enumerate(angles):
+        dk_dth = probe.fs * (X * math.cos(th) - Z * math.sin(th)) / probe.c_ref
+        for e in range(probe.n_elem):
+            k = das_index(probe, grid, th, e)
+            k0 = np.floor(k).astype(np.int64)
+            row = A[i, e]
+            v0 = np.where((k0 >= 0) & (k0 < n_t), row[np.clip(k0, 0, n_t - 1)], 0.0)
+            v1 = np.where((k0 + 1 >= 0) & (k0 + 1 < n_t), row[np.clip(k0 + 1, 0, n_t - 1)], 0.0)
+            dL_dk = (np.conj(g_I) * (v1 - v0)).real
+            xe = (e - half) * probe.pitch
+            r = np.sqrt((X - xe) ** 2 + Z ** 2)
+            g_th[i] += float(np.sum(dL_dk * dk_dth))
+            g_c += float(np.sum(dL_dk * (-k / probe.c_ref)))
+            g_p += float(np.sum(dL_dk * (-probe.fs * (X - xe) * (e - half) / (r * probe.c_ref))))
+    return g_th, g_c, g_p
 
 
 # ---------------------------------------------------------------- B-mode

@@ -138,3 +138,45 @@ def test_nee_matches_bsdf_sampling_in_expectation():
     assert abs(tot_nee.sum() - tot_bsdf.sum()) < 4 * math.sqrt(np.sum(se ** 2)) + 2e-3 * tot_nee.sum()
     # arrival times: both spread over the same window
     assert abs(np.average(nee.t, weights=nee.a) - np.average(bsdf.t, weights=bsdf.a)) < 0.1e-6
+
+
+def test_das_acquisition_gradients_match_finite_differences():
+    """dL/d(angles, c_ref, pitch) of L = Re <g, I> at fixed analytic signal,
+    against central differences of the oracle's delay-and-sum with the
+    parameter moved (Eq. das; I is piecewise linear in each sample index,
+    and a step of 1e-7 relative crosses a sample boundary at too few pixels
+    to matter)."""
+    import dataclasses
+    rng = np.random.default_rng(17)
+    wl = W.two_layer()
+    p = dataclasses.replace(wl.probe, n_elem=12, n_t=1024)
+    g = W.Grid.span(10, 14, -3e-3, 3e-3, 8e-3, 14e-3)
+    angles = np.radians([-7.0, 2.0, 9.0])
+    k = np.exp(-0.5 * (np.arange(-9, 10) / 3.0) ** 2)
+    rf = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), -1,
+                             rng.standard_normal((3, p.n_elem, p.n_t)))
+    A = oracle.analytic(rf)
+    g_I = rng.standard_normal((g.n_x, g.n_z)) + 1j * rng.standard_normal((g.n_x, g.n_z))
+    g_th, g_c, g_p = oracle.das_acq_vjp(A, g_I, p, g, angles)
+
+    def L(probe, ang):
+        return _real_inner(g_I, oracle.das(A, probe, g, ang))
+
+    fd_th = []
+    for i in range(len(angles)):
+        h = 1e-7
+        ap, am = angles.copy(), angles.copy()
+        ap[i] += h
+        am[i] -= h
+        fd_th.append((L(p, ap) - L(p, am)) / (2 * h))
+    hc = 1e-7 * p.c_ref
+    fd_c = (L(dataclasses.replace(p, c_ref=p.c_ref + hc), angles)
+            - L(dataclasses.replace(p, c_ref=p.c_ref - hc), angles)) / (2 * hc)
+    hp = 1e-7 * p.pitch
+    fd_p = (L(dataclasses.replace(p, pitch=p.pitch + hp), angles)
+            - L(dataclasses.replace(p, pitch=p.pitch - hp), angles)) / (2 * hp)
+    got = np.array([*g_th, g_c, g_p])
+    want = np.array([*fd_th, fd_c, fd_p])
+    print("acquisition gradients", got, "finite differences", want)
+    assert np.all(np.abs(got) > 0)
+    assert np.allclose(got, want, rtol=2e-4, atol=0.0)
