@@ -215,6 +215,21 @@ size_t us_beamform_vjp_workspace_size(const us_probe* probe, int32_t n_tx);
 int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
                     const us_tx_desc* tx, int32_t n_tx, const float* g_iq_dev, float* g_rf_dev,
                     void* ws_dev, size_t ws_bytes, void* stream);
+/* Gradients of Re<g_iq, I>, I the image us_beamform forms from rf_dev, with
+ * respect to the acquisition parameters of Eq. das at fixed RF: the steering
+ * angle of each transmit (radians), the speed of sound c_ref of the delays
+ * (m/s) and the element pitch (m). I depends on them only through the
+ * fractional sample index fs tau, and the linear interpolation's slope in it
+ * is A[k0 + 1] - A[k0] (A the analytic signal). Sums in fp64 in a fixed
+ * order (the result does not depend on scheduling).
+ *   rf_dev in: float [n_tx][n_elem][n_t]; g_iq_dev in: float [n_x][n_z][2]
+ *   g_acq_dev out: double [n_tx + 2] (overwritten): d/d angle of each
+ *   transmit, then d/d c_ref, then d/d pitch
+ * The workspace depends on the grid (partial sums per tile of 256 pixels). */
+size_t us_beamform_acq_vjp_workspace_size(const us_probe* probe, const us_grid_desc* grid, int32_t n_tx);
+int us_beamform_acq_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
+                        const us_tx_desc* tx, int32_t n_tx, const float* rf_dev, const float* g_iq_dev,
+                        double* g_acq_dev, void* ws_dev, size_t ws_bytes, void* stream);
 /* g_theta += (d rf / d theta)^T g_rf at fixed ray realizations (Sec. 3.2,
  * Eq. chain_rule): the paths of the same rays as us_simulate_rf are replayed
  * from their Philox counters (nothing stored between the calls); discrete

@@ -81,6 +81,8 @@ _SIGNATURES = {
     "us_bmode_vjp": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_float, vp, vp, sz, vp]),
     "us_beamform_vjp_workspace_size": (sz, [vp, i32]),
     "us_beamform_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
+    "us_beamform_acq_vjp_workspace_size": (sz, [vp, vp, i32]),
+    "us_beamform_acq_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, vp, sz, vp]),
     "us_simulate_rf_vjp_workspace_size": (sz, [vp, vp, i32, i64, i32]),
     "us_simulate_rf_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                           vp, sz, vp]),
@@ -292,6 +294,24 @@ def us_beamform(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, iq=None, w
                               _ptr(iq), _ptr(workspace), workspace.numel(), _stream(stream)),
            "us_beamform")
     return iq
+
+
+def us_beamform_acq_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, g_iq, out=None,
+                        workspace=None, stream=None):
+    """d Re<g_iq, I> / d (steering angle of each transmit, c_ref, pitch) as a
+    float64 device tensor [n_tx + 2]."""
+    torch = _torch()
+    tx, n_tx = _tx_array(angles, tx_ids)
+    g = _grid(grid)
+    if out is None:
+        out = torch.empty(n_tx + 2, dtype=torch.float64, device=ctx.torch_device)
+    if workspace is None:
+        workspace = _workspace(load().us_beamform_acq_vjp_workspace_size(probe.handle, ctypes.byref(g), n_tx),
+                               ctx.torch_device)
+    _check(load().us_beamform_acq_vjp(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf), _ptr(g_iq),
+                                      _ptr(out), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "us_beamform_acq_vjp")
+    return out
 
 
 def us_bmode(ctx: Context, iq, dr_db: float, out=None, workspace=None, stream=None):

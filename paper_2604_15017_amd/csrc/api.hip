@@ -843,6 +843,44 @@ int us_beamform_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid
   return US_OK;
 }
 
+size_t us_beamform_acq_vjp_workspace_size(const us_probe* probe, const us_grid_desc* grid, int32_t n_tx) {
+  if (!probe || !grid || n_tx < 1 || grid->n_x < 1 || grid->n_z < 1) return 0;
+  const long tiles = das_acq_tiles(grid_view(grid));
+  return us_beamform_workspace_size(probe, n_tx) +
+         align_up((size_t)std::min(n_tx, kMaxTxPerLaunch) * tiles * 3 * sizeof(double));
+}
+
+int us_beamform_acq_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx,
+                        int32_t n_tx, const float* rf_dev, const float* g_iq_dev, double* g_acq_dev,
+                        void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && rf_dev && g_iq_dev && g_acq_dev && ws_dev, "us_beamform_acq_vjp: NULL argument");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  if (ws_bytes < us_beamform_acq_vjp_workspace_size(probe, grid, n_tx))
+    return fail(US_ETOOBIG, "us_beamform_acq_vjp: workspace too small");
+  US_HIP(bind_device(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  float2* A = (float2*)ws_dev;
+  double* part = (double*)((char*)ws_dev + us_beamform_workspace_size(probe, n_tx));
+  const long rows = (long)n_tx * probe->d.n_elem;
+  {
+    Timed tm(ctx, "analytic", s);
+    if (launch_analytic(rf_dev, A, probe->twiddle, probe->d.n_t, rows, s))
+      return fail(US_EINVAL, "us_beamform_acq_vjp: unsupported n_t");
+  }
+  launch_fill_u32((uint32_t*)g_acq_dev, 2L * (n_tx + 2), 0u, s);
+  const GridView g = grid_view(grid);
+  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    TxTable tt;
+    fill_tx(tt, tx, t0, ng);
+    Timed tm(ctx, "das_acq", s);
+    launch_das_acq(A, (const float2*)g_iq_dev, probe->pv, g, tt, ng, t0, n_tx, part, g_acq_dev, s);
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
 size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* probe,
                                          int32_t n_tx, int64_t ray_count, int32_t max_bounces) {
   if (!scene || !probe || n_tx < 1 || ray_count < 0 || max_bounces < 0) return 0;

@@ -696,6 +696,94 @@ __global__ __launch_bounds__(kAdjThreads) void k_das_adjoint_cols(const float2* 
   }
 }
 
+// Gradients of Re<g, I> with respect to the acquisition parameters of Eq.
+// das (the steering angle of each transmit, c_ref, the pitch) at fixed
+// analytic signal. I depends on them only through the fractional sample index
+// k = fs tau, and the interpolation's slope in k is A[k0 + 1] - A[k0]; with
+// k = fs ((x sin th + z cos th) + r_e) / c_ref and x_e = (e - (N - 1)/2) pitch:
+// dk/dth = fs (x cos th - z sin th) / c_ref, dk/dc_ref = -k / c_ref,
+// dk/dpitch = -fs (x - x_e) (e - (N - 1)/2) / (r_e c_ref). Block (tile of
+// kAcqThreads pixels, transmit): each thread sums over the elements for its
+// pixel in fp64, the block reduces its three sums in a fixed order into one
+// partial row per tile.
+constexpr int kAcqThreads = 256;
+
+__global__ __launch_bounds__(kAcqThreads) void k_das_acq(const float2* __restrict__ A,
+                                                         const float2* __restrict__ giq, ProbeView p,
+                                                         GridView g, TxTable tx, int tx_base,
+                                                         double* __restrict__ part) {
+  __shared__ double red[3][kAcqThreads];
+  const int i = blockIdx.y, tid = threadIdx.x;
+  const long n_px = (long)g.n_x * g.n_z;
+  const long px = (long)blockIdx.x * kAcqThreads + tid;
+  double s_th = 0.0, s_c = 0.0, s_p = 0.0;
+  if (px < n_px) {
+    const int a = (int)(px / g.n_z), b = (int)(px % g.n_z);
+    const double x = g.x0 + a * g.dx, z = g.z0 + b * g.dz;
+    const double s_per_m = p.fs / p.c_ref;
+    const double sa = tx.sin_a[i], ca = tx.cos_a[i];
+    const double kt = (x * sa + z * ca) * s_per_m;
+    const double dk_dth = (x * ca - z * sa) * s_per_m;
+    const double half = 0.5 * (double)(p.n_elem - 1);
+    const float2 gv = giq[px];
+    const float2* rows = A + (long)(tx_base + i) * p.n_elem * p.n_t;
+    for (int e = 0; e < p.n_elem; ++e) {
+      const double de = (double)e - half;
+      const double dxe = x - de * p.pitch;
+      const double r = sqrt(dxe * dxe + z * z);
+      const double k = kt + r * s_per_m;
+      const double k0d = floor(k);
+      if (!(k0d >= -1.0 && k0d < (double)p.n_t)) continue;
+      const int k0 = (int)k0d;
+      const float2* row = rows + (long)e * p.n_t;
+      const float2 v0 = k0 >= 0 ? row[k0] : make_float2(0.0f, 0.0f);
+      const float2 v1 = k0 + 1 < p.n_t ? row[k0 + 1] : make_float2(0.0f, 0.0f);
+      const double dl = (double)gv.x * ((double)v1.x - (double)v0.x) + (double)gv.y * ((double)v1.y - (double)v0.y);
+      s_th += dl * dk_dth;
+      s_c -= dl * k;
+      s_p -= dl * dxe * de / r;
+    }
+    s_c /= p.c_ref;
+    s_p *= s_per_m;
+  }
+  red[0][tid] = s_th;
+  red[1][tid] = s_c;
+  red[2][tid] = s_p;
+  __syncthreads();
+  for (int off = kAcqThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      red[0][tid] += red[0][tid + off];
+      red[1][tid] += red[1][tid + off];
+      red[2][tid] += red[2][tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid < 3) part[((long)i * gridDim.x + blockIdx.x) * 3 + tid] = red[tid][0];
+}
+
+// Block j adds, in a fixed order, the partial rows of output j of one launch
+// group into out: j < n_tx the angle of transmit tx_base + j, then c_ref and
+// the pitch (summed over the group's transmits too).
+__global__ __launch_bounds__(256) void k_acq_reduce(const double* __restrict__ part, int n_tx, int n_tiles,
+                                                    int tx_base, int n_tx_total, double* __restrict__ out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  double v = 0.0;
+  if (j < n_tx) {
+    for (int t = tid; t < n_tiles; t += 256) v += part[((long)j * n_tiles + t) * 3];
+  } else {
+    const int c = j - n_tx + 1;
+    for (long q = tid; q < (long)n_tx * n_tiles; q += 256) v += part[q * 3 + c];
+  }
+  red[tid] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  if (tid == 0) out[j < n_tx ? tx_base + j : n_tx_total + (j - n_tx)] += red[0];
+}
+
 // L = (1/n) sum [l1 |d| + l2 d^2], d = B - R; dL/dB = (l1 sign(d) + 2 l2 d) / n.
 __global__ __launch_bounds__(256) void k_image_loss(const float* __restrict__ b,
                                                     const float* __restrict__ ref, long n,
@@ -833,6 +921,17 @@ void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, con
     hipLaunchKernelGGL(k_das_adjoint<16>, grid, block, lds, s, g_iq, g_A, p, g, tx, tx_base);
   else
     hipLaunchKernelGGL(k_das_adjoint<32>, grid, block, lds, s, g_iq, g_A, p, g, tx, tx_base);
+}
+
+long das_acq_tiles(const GridView& g) { return ((long)g.n_x * g.n_z + kAcqThreads - 1) / kAcqThreads; }
+
+void launch_das_acq(const float2* A, const float2* g_iq, const ProbeView& p, const GridView& g, const TxTable& tx,
+                    int n_tx_group, int tx_base, int n_tx_total, double* part, double* out, hipStream_t s) {
+  const long tiles = das_acq_tiles(g);
+  hipLaunchKernelGGL(k_das_acq, dim3((unsigned)tiles, (unsigned)n_tx_group), dim3(kAcqThreads), 0, s, A, g_iq,
+                     p, g, tx, tx_base, part);
+  hipLaunchKernelGGL(k_acq_reduce, dim3((unsigned)(n_tx_group + 2)), dim3(256), 0, s, part, n_tx_group,
+                     (int)tiles, tx_base, n_tx_total, out);
 }
 
 int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps_reversed, int M, int n_t,

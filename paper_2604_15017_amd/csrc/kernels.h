@@ -191,6 +191,13 @@ void launch_bmode_vjp(const float2* iq, const float* g_b, long n_px, float dr_db
                       const unsigned long long* key, double* sum, float2* g_iq, hipStream_t s);
 void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long* key,
                           const double* sum, float2* g_iq, hipStream_t s);
+// Gradients of the image with respect to the acquisition parameters (the
+// steering angles, c_ref, the pitch): per-tile partial rows in part
+// ([n_tx_group][das_acq_tiles][3] doubles), then added into out[n_tx_total + 2]
+// (angles at tx_base.., c_ref, pitch), which the caller zeroes first.
+long das_acq_tiles(const GridView& g);
+void launch_das_acq(const float2* A, const float2* g_iq, const ProbeView& p, const GridView& g, const TxTable& tx,
+                    int n_tx_group, int tx_base, int n_tx_total, double* part, double* out, hipStream_t s);
 void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, const GridView& g,
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s);
 int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddle, int n_t,

@@ -392,6 +392,36 @@ def test_beamform_more_transmits_than_one_launch(L, ctx):
     assert rel <= 1e-5
 
 
+@pytest.mark.parametrize("case", ["two_layer_3tx", "layered_full_grid"])
+def test_beamform_acquisition_gradients_against_oracle(L, ctx, case):
+    """d Re<g, I> / d (steering angle of each transmit, c_ref, pitch) from the
+    library against the oracle's on the same RF and image gradient (the oracle
+    forms the analytic signal in fp64, the library in fp32): within the
+    gradient tolerance, 1e-3 relative per parameter."""
+    import torch
+    if case == "two_layer_3tx":
+        wl = W.two_layer().replace(angles=np.radians([-6.0, 0.0, 5.0]), tx_ids=np.arange(3, dtype=np.uint32))
+    else:
+        wl = W.layered_phantom()
+    p, g, angles = wl.probe, wl.grid, wl.angles
+    rng = np.random.default_rng(31)
+    k = np.exp(-0.5 * (np.arange(-12, 13) / 4.0) ** 2)
+    rf = np.apply_along_axis(lambda r: np.convolve(r, k, mode="same"), -1,
+                             rng.standard_normal((len(angles), p.n_elem, p.n_t))).astype(np.float32)
+    g_I = (rng.standard_normal((g.n_x, g.n_z)) + 1j * rng.standard_normal((g.n_x, g.n_z))).astype(np.complex64)
+    ref = oracle.das_acq_vjp(oracle.analytic(rf.astype(np.float64)), g_I.astype(np.complex128), p, g, angles)
+    ref = np.array([*ref[0], ref[1], ref[2]])
+    probe = L.Probe(ctx, p)
+    giq = torch.tensor(np.stack([g_I.real, g_I.imag], -1), dtype=torch.float32, device="cuda")
+    got = L.us_beamform_acq_vjp(ctx, probe, g, angles, wl.tx_ids, torch.tensor(rf, device="cuda"), giq)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    rel = np.abs(got - ref) / np.abs(ref)
+    print(f"{case}: acquisition gradients worst relative error {rel.max():.2e} "
+          f"(angles {rel[:-2].max():.2e}, c_ref {rel[-2]:.2e}, pitch {rel[-1]:.2e})", flush=True)
+    assert np.all(rel <= 1e-3)
+
+
 def test_end_to_end_bmode_full_size(L, ctx):
     wl = W.two_layer()
     out = oracle.render(wl)
