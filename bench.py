@@ -157,6 +157,50 @@ def inverse_leg(ctx, steps, warmup):
             "loss_first": losses[0], "loss_last": losses[-1], "iterations": len(losses)}
 
 
+def acquisition_leg(ctx, steps, warmup):
+    """Gradients of the image with respect to the acquisition parameters (the
+    11 steering angles, c_ref, pitch) on the layered frame's RF and grid, from
+    seeded channels and a seeded image gradient: ms per call, and the DAS
+    kernel's rate in taps (pixel x element x transmit) per second."""
+    import ctypes
+    import numpy as np
+    import torch
+    from paper_2604_15017_amd import _lib as L
+    from paper_2604_15017_amd import workloads as W
+    wl = W.layered_phantom()
+    p, g = wl.probe, wl.grid
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    rf = torch.randn((wl.n_tx, p.n_elem, p.n_t), dtype=torch.float32, device="cuda", generator=gen)
+    g_iq = torch.randn((g.n_x, g.n_z, 2), dtype=torch.float32, device="cuda", generator=gen)
+    probe = L.Probe(ctx, p)
+    out = torch.empty(wl.n_tx + 2, dtype=torch.float64, device="cuda")
+    gd = L._grid(g)
+    ws = L._workspace(L.load().us_beamform_acq_vjp_workspace_size(probe.handle, ctypes.byref(gd), wl.n_tx),
+                      ctx.torch_device)
+    f = lambda: L.us_beamform_acq_vjp(ctx, probe, g, wl.angles, wl.tx_ids, rf, g_iq, out=out, workspace=ws)
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    L.us_profile_enable(ctx, True)
+    L.us_profile_read(ctx)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        f()
+    end.record()
+    torch.cuda.synchronize()
+    prof = L.us_profile_read(ctx)
+    L.us_profile_enable(ctx, False)
+    ms = start.elapsed_time(end) / steps
+    taps = g.n_px * p.n_elem * wl.n_tx
+    das_ms = prof["das_acq"][0] / steps if "das_acq" in prof else float("nan")
+    return {"workload": f"layered_phantom grid {g.n_x} x {g.n_z}, {wl.n_tx} transmits x {p.n_elem} elements, "
+                        f"d/d (steering angles, c_ref, pitch) of Re<g, I>",
+            "ms_per_call": round(ms, 4), "das_acq_ms": round(das_ms, 4),
+            "taps_per_s": taps / (das_ms * 1e-3) if das_ms == das_ms else None,
+            "finite": bool(np.isfinite(out.cpu().numpy()).all())}
+
+
 def serving(ctx, n_requests):
     """Serving stream: Poisson arrivals at 80 % of the measured one-at-a-time
     throughput, scenes 40/40/20 from the two-layer, layered-phantom and mesh
@@ -409,6 +453,8 @@ def main():
         out["inverse"] = inverse_leg(ctx, args.steps, args.warmup)
         print(f"inverse loop: {out['inverse']['ms_per_iteration']:.3f} ms/iteration", file=sys.stderr,
               flush=True)
+    if not args.no_backward:
+        out["acquisition_gradients"] = acquisition_leg(ctx, args.steps, args.warmup)
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
