@@ -242,6 +242,22 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
                        int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
                        const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
                        void* stream);
+/* us_simulate_rf_vjp, and also the gradient of the same contraction with
+ * respect to the acquisition parameters, at the same fixed ray realizations:
+ * the steering angle of each transmit (emission direction, emission delay
+ * x sin th / c_ref, weight cos th / rays_per_elem), c_ref (emission delay)
+ * and the pitch (element centres of the emission origins and of the
+ * receiver-directed rays' targets). Which element an array hit lands on is
+ * piecewise constant in the pitch and not differentiated. The workspace is
+ * that of us_simulate_rf_vjp.
+ *   g_acq_dev in/out: double [n_tx + 2], accumulated: d/d angle of each
+ *   transmit, then d/d c_ref, then d/d pitch (summed with atomics per block,
+ *   so they vary in their last bits between runs) */
+int us_simulate_rf_vjp_acq(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
+                           const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                           int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
+                           const float* g_rf_dev, double* g_theta_dev, double* g_acq_dev, void* ws_dev,
+                           size_t ws_bytes, void* stream);
 
 /* Inverse loop (Sec. "Parameterization and constraints", Sec. "Optimization
  * procedure", Algorithm opt). All arrays are device doubles of length n.

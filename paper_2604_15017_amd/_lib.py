@@ -86,6 +86,7 @@ _SIGNATURES = {
     "us_simulate_rf_vjp_workspace_size": (sz, [vp, vp, i32, i64, i32]),
     "us_simulate_rf_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                           vp, sz, vp]),
+    "us_simulate_rf_vjp_acq": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp, vp, vp, sz, vp]),
     "us_image_loss_workspace_size": (sz, [i64]),
     "us_image_loss": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp,
                                      vp, sz, vp]),
@@ -379,7 +380,9 @@ def us_simulate_rf_vjp_workspace_size(scene: Scene, probe: Probe, n_tx: int, ray
 def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, seed: int,
                        rays_per_elem: int, max_bounces: int, g_rf, g_theta=None,
                        ray_begin: int = 0, ray_count: Optional[int] = None, workspace=None,
-                       stream=None):
+                       stream=None, g_acq=None):
+    """g_theta += (d rf / d theta)^T g_rf; with g_acq (float64 [n_tx + 2]) also
+    the acquisition parameters (steering angles, c_ref, pitch), accumulated."""
     torch = _torch()
     p = probe.desc
     tx, n_tx = _tx_array(angles, tx_ids)
@@ -390,10 +393,17 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
     if workspace is None:
         workspace = _workspace(us_simulate_rf_vjp_workspace_size(scene, probe, n_tx, ray_count,
                                                                  max_bounces), ctx.torch_device)
-    _check(load().us_simulate_rf_vjp(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
-                                     int(rays_per_elem), int(ray_begin), int(ray_count),
-                                     int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(workspace),
-                                     workspace.numel(), _stream(stream)), "us_simulate_rf_vjp")
+    if g_acq is None:
+        _check(load().us_simulate_rf_vjp(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
+                                         int(rays_per_elem), int(ray_begin), int(ray_count),
+                                         int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(workspace),
+                                         workspace.numel(), _stream(stream)), "us_simulate_rf_vjp")
+    else:
+        _check(load().us_simulate_rf_vjp_acq(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
+                                             int(rays_per_elem), int(ray_begin), int(ray_count),
+                                             int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(g_acq),
+                                             _ptr(workspace), workspace.numel(), _stream(stream)),
+               "us_simulate_rf_vjp_acq")
     return g_theta
 
 

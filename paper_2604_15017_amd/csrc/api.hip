@@ -889,11 +889,16 @@ size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* 
   return replay_bytes(scene, n_tx, probe, max_bounces, cap);
 }
 
-int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
-                       const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
-                       int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
-                       const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
-                       void* stream) {
+}  // extern "C"
+
+namespace {
+
+// The replay backward; g_acq_dev (may be null) also receives the adjoints of
+// the acquisition parameters.
+int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
+                    int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin, int64_t ray_count,
+                    int32_t max_bounces, const float* g_rf_dev, double* g_theta_dev, double* g_acq_dev,
+                    void* ws_dev, size_t ws_bytes, void* stream) {
   US_CHECK(ctx && g_rf_dev && g_theta_dev && ws_dev, "us_simulate_rf_vjp: NULL argument");
   int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
@@ -936,6 +941,8 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
     a.grad_copies >>= 1;
   a.gh = gh;
   a.cap = cap;
+  a.g_acq = g_acq_dev;
+  a.n_tx_total = n_tx;
   for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
     const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
     fill_tx(a.tx, tx, t0, ng);
@@ -974,9 +981,28 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
   return US_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 extern "C" {
+
+int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
+                       const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                       int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
+                       const float* g_rf_dev, double* g_theta_dev, void* ws_dev, size_t ws_bytes,
+                       void* stream) {
+  return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
+                         g_rf_dev, g_theta_dev, nullptr, ws_dev, ws_bytes, stream);
+}
+
+int us_simulate_rf_vjp_acq(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
+                           const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                           int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
+                           const float* g_rf_dev, double* g_theta_dev, double* g_acq_dev, void* ws_dev,
+                           size_t ws_bytes, void* stream) {
+  US_CHECK(g_acq_dev, "us_simulate_rf_vjp_acq: NULL g_acq");
+  return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
+                         g_rf_dev, g_theta_dev, g_acq_dev, ws_dev, ws_bytes, stream);
+}
 
 int us_param_map(us_ctx* ctx, const double* u_dev, const double* lo_dev, const double* hi_dev,
                  int32_t n, double* theta_dev, void* stream) {

@@ -97,6 +97,11 @@ struct ReplayArgs {
   ReplayStack stk;
   RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
   unsigned long long* counts;   // [max_bounces + 2]: survivors of step k | diffuse interactions << 32
+  // optional (null): d/d steering angle of each transmit (tx_base + local
+  // index), then d/d c_ref, then d/d pitch, accumulated; n_tx_total entries
+  // of angles precede the two
+  double* g_acq;
+  int n_tx_total;
 };
 // The three phases of the replay over chunk rays [0, n): the forward phase
 // once per step k = 1..max_bounces + 1 (queues swapped in between), the

@@ -295,7 +295,7 @@ struct ReplayCtx {
 template <bool kMeshes>
 __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f, double kd,
                                    double watt, double tp, int e2, d3& xbar, d3& nrbar,
-                                   double& Arbar, double& wattbar, double& tpbar) {
+                                   double& Arbar, double& wattbar, double& tpbar, double& xebar) {
   const SceneLDS& S = C.S;
   const ProbeView& P = C.P;
   const double xe = ((double)e2 - 0.5 * (double)(P.n_elem - 1)) * P.pitch;
@@ -430,6 +430,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   // we = dv / r, r = |dv|, dv = y - x
   const d3 dvbar = (webar - we * dot(webar, we)) * (1.0 / r) + we * rbar;
   xbar = xbar + xb - dvbar;
+  xebar += dvbar.x;   // the element centre y = (x_e, 0, 0) enters as dv = y - x
 }
 
 // Ray of chunk slot i: transmit (local index) and ray id.
@@ -601,15 +602,32 @@ __global__ void k_replay_prefix(ReplayArgs a) {
   }
 }
 
+// Acquisition-parameter adjoints of one block (the steering angles of the
+// launch group's transmits, then c_ref and the pitch), summed in LDS and added
+// to a.g_acq once per block. The order of those global additions varies from
+// run to run, so these sums vary in their last bits.
+__device__ __forceinline__ void acq_clear(double* acq) {
+  for (int j = threadIdx.x; j < kMaxTxPerLaunch + 2; j += blockDim.x) acq[j] = 0.0;
+}
+__device__ __forceinline__ void acq_flush(const ReplayArgs& a, const double* acq) {
+  if (!a.g_acq) return;
+  for (int j = threadIdx.x; j < a.tx.n + 2; j += blockDim.x) {
+    const double v = acq[j];
+    if (v != 0.0) atomicAdd(&a.g_acq[j < a.tx.n ? a.tx_base + j : a.n_tx_total + (j - a.tx.n)], v);
+  }
+}
+
 template <bool kMeshes>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2 : 3, 8))) void k_replay_secondary(ReplayArgs a) {
   const int B = a.max_bounces;
   const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
   if ((long)blockIdx.x * blockDim.x >= n_q) return;
   __shared__ SceneLDS S;
+  __shared__ double acq[kMaxTxPerLaunch + 2];
   extern __shared__ double gsh[];      // gradient sums (kGradCopies copies), crossing caches, hierarchy stacks
   load_scene(S, a.scene);
   grad_clear(gsh, a.n_grad, a.grad_copies);
+  acq_clear(acq);
   __syncthreads();
   double* legs = gsh + a.grad_copies * grad_stride(a.n_grad);
   double* leg_t = legs + threadIdx.x;
@@ -643,12 +661,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
     const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
     ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
     d3 xb{0, 0, 0}, nrb{0, 0, 0};
-    double Ab = 0.0, wb = 0.0, tb = 0.0;
-    secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb);
+    double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0;
+    secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb);
     a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
+    // x_e = (e - (N - 1)/2) pitch
+    if (a.g_acq && xeb != 0.0) atomicAdd(&acq[a.tx.n + 1], xeb * ((double)e2 - 0.5 * (double)(P.n_elem - 1)));
   }
   __syncthreads();
   grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
+  acq_flush(a, acq);
 }
 
 // Phase 3 (one thread per ray): the reverse sweep over the kept steps, with
@@ -657,9 +678,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_replay_reverse(ReplayArgs a, long n) {
   if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
+  __shared__ double acq[kMaxTxPerLaunch + 2];
   extern __shared__ double gsh[];      // gradient sums, kGradCopies copies
   load_scene(S, a.scene);
   grad_clear(gsh, a.n_grad, a.grad_copies);
+  acq_clear(acq);
   __syncthreads();
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
@@ -804,9 +827,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       tb = tpb;
       wb = wattb * st.E;
     }
+    if (a.g_acq) {
+      // the emitted state: o = (x_e + (u0 - 1/2) w_el, (u1 - 1/2) h_el, 0),
+      // d = (sin th, 0, cos th), t = o_x sin th / c_ref, w = cos th / n, with
+      // x_e = (e - (N - 1)/2) pitch
+      const int e = (int)(rid / (uint32_t)a.rays_per_elem);
+      const Draw u = draw(a.seed, rid, tx_id, 0);
+      const double de = (double)e - 0.5 * (double)(P.n_elem - 1);
+      const double ox = elem_x(P, e) + (u.u0 - 0.5) * P.elem_w;
+      const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
+      const double thb = db.x * ca - db.z * sa + tb * ox * ca / P.c_ref - wb * sa / (double)a.rays_per_elem;
+      atomicAdd(&acq[txl], thb);
+      atomicAdd(&acq[a.tx.n], -tb * ox * sa / (P.c_ref * P.c_ref));
+      atomicAdd(&acq[a.tx.n + 1], (ob.x + tb * sa / P.c_ref) * de);
+    }
   }
   __syncthreads();
   grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
+  acq_flush(a, acq);
 }
 
 // g_theta[q(m, j)] += sum over the vertices v of mesh m of vadj[v] phi_j(v),

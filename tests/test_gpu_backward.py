@@ -271,3 +271,54 @@ def test_full_size_gradient_on_ray_sample(L, ctx):
                       ray_begin=begin, ray_count=count, g_h=g_h,
                       grad_params=list(range(wl.scene.n_params)))
     compare_grads(g.cpu().numpy(), tr.g_theta, wl.scene.theta(), "full size, ray sample")
+
+
+def test_vjp_acquisition_parameters(L, ctx):
+    """Steering angles, c_ref and pitch through the transport (emission
+    direction, delay and weight; the emission origins and the receiver-directed
+    rays' target elements) from us_simulate_rf_vjp_acq, against central
+    differences of the oracle's transport at fixed branch probabilities. The RF
+    gradient is the same for every element of a transmit, so that an array hit
+    moving to a neighbouring element under a pitch step changes nothing."""
+    import dataclasses
+    import torch
+    wl = W.layered_phantom().replace(rays_per_elem=48, angles=np.radians([-6.0, 0.0, 5.0]),
+                                     tx_ids=np.arange(3, dtype=np.uint32))
+    p = wl.probe
+    g_t = smooth_field((wl.n_tx, 1, p.n_t), 5)
+    g_rf = np.ascontiguousarray(np.broadcast_to(g_t, (wl.n_tx, p.n_elem, p.n_t))).astype(np.float32)
+    _, s = oracle.pulse_taps(p.f0, p.n_cycles, p.fs)
+    g_h = oracle.pulse_vjp(g_rf.astype(np.float64), s)
+    theta = wl.scene.theta()
+    probs = oracle.trace(wl.scene, p, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                         theta=theta, record_probs=True).probs
+
+    def Lf(probe, angles):
+        tr = oracle.trace(wl.scene, probe, angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                          theta=theta, probs=probs)
+        return float(np.sum(g_h * tr.splat(wl.n_tx, p.n_elem, p.n_t, p.fs)))
+
+    fd = []
+    for i in range(wl.n_tx):
+        h = 1e-7
+        ap, am = wl.angles.copy(), wl.angles.copy()
+        ap[i] += h
+        am[i] -= h
+        fd.append((Lf(p, ap) - Lf(p, am)) / (2 * h))
+    hc = 1e-7 * p.c_ref
+    fd.append((Lf(dataclasses.replace(p, c_ref=p.c_ref + hc), wl.angles)
+               - Lf(dataclasses.replace(p, c_ref=p.c_ref - hc), wl.angles)) / (2 * hc))
+    hp = 1e-7 * p.pitch
+    fd.append((Lf(dataclasses.replace(p, pitch=p.pitch + hp), wl.angles)
+               - Lf(dataclasses.replace(p, pitch=p.pitch - hp), wl.angles)) / (2 * hp))
+    fd = np.array(fd)
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, p)
+    g_acq = torch.zeros(wl.n_tx + 2, dtype=torch.float64, device="cuda")
+    L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                         torch.tensor(g_rf, device="cuda"), g_acq=g_acq)
+    torch.cuda.synchronize()
+    got = g_acq.cpu().numpy()
+    rel = np.abs(got - fd) / np.abs(fd)
+    print(f"acquisition parameters: gpu {got}, finite differences {fd}, relative error {rel}", flush=True)
+    assert np.all(np.abs(fd) > 0)
+    assert np.all(rel <= 1e-3)
