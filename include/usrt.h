@@ -246,13 +246,15 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
  * respect to the acquisition parameters, at the same fixed ray realizations:
  * the steering angle of each transmit (emission direction, emission delay
  * x sin th / c_ref, weight cos th / rays_per_elem), c_ref (emission delay)
- * and the pitch (element centres of the emission origins and of the
- * receiver-directed rays' targets). Which element an array hit lands on is
- * piecewise constant in the pitch and not differentiated. The workspace is
- * that of us_simulate_rf_vjp.
- *   g_acq_dev in/out: double [n_tx + 2], accumulated: d/d angle of each
- *   transmit, then d/d c_ref, then d/d pitch (summed with atomics per block,
- *   so they vary in their last bits between runs) */
+ * the pitch (element centres of the emission origins and of the
+ * receiver-directed rays' targets) and the centre frequency f0 (the pulse of
+ * Eq. axial_sig, carrier and envelope width n_cycles / f0, and the amplitude
+ * attenuation alpha f0 of every region; the tap count M is held fixed). Which
+ * element an array hit lands on is piecewise constant in the pitch and not
+ * differentiated. The workspace is that of us_simulate_rf_vjp.
+ *   g_acq_dev in/out: double [n_tx + 3], accumulated: d/d angle of each
+ *   transmit, then d/d c_ref, d/d pitch and d/d f0 (summed with atomics per
+ *   block, so they vary in their last bits between runs) */
 int us_simulate_rf_vjp_acq(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
                            const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
                            int64_t ray_begin, int64_t ray_count, int32_t max_bounces,

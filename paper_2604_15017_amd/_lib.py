@@ -381,8 +381,8 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
                        rays_per_elem: int, max_bounces: int, g_rf, g_theta=None,
                        ray_begin: int = 0, ray_count: Optional[int] = None, workspace=None,
                        stream=None, g_acq=None):
-    """g_theta += (d rf / d theta)^T g_rf; with g_acq (float64 [n_tx + 2]) also
-    the acquisition parameters (steering angles, c_ref, pitch), accumulated."""
+    """g_theta += (d rf / d theta)^T g_rf; with g_acq (float64 [n_tx + 3]) also
+    the acquisition parameters (steering angles, c_ref, pitch, f0), accumulated."""
     torch = _torch()
     p = probe.desc
     tx, n_tx = _tx_array(angles, tx_ids)
@@ -399,6 +399,8 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
                                          int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(workspace),
                                          workspace.numel(), _stream(stream)), "us_simulate_rf_vjp")
     else:
+        if g_acq.dtype != torch.float64 or g_acq.numel() != n_tx + 3 or not g_acq.is_contiguous():
+            raise ValueError(f"g_acq must be a contiguous float64 tensor of {n_tx + 3} entries")
         _check(load().us_simulate_rf_vjp_acq(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
                                              int(rays_per_elem), int(ray_begin), int(ray_count),
                                              int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(g_acq),

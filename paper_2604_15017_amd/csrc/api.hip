@@ -96,6 +96,7 @@ struct us_probe {
   int M;
   float* taps;          // s[m], m = -M..M
   float* taps_rev;      // s[-m]
+  float* dtaps_rev;     // d s[-m] / d f0
   float2* twiddle;      // exp(-2 pi i j / n_t), j < n_t / 2 (power-of-two n_t only)
 };
 
@@ -159,10 +160,13 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
   const double sigma = std::pow(d->n_cycles / (2.0 * d->f0), 2) / std::log(2.0);
   const int M = (int)std::ceil(d->fs * std::sqrt(sigma * std::log(1e7)));
   US_CHECK(M >= 0 && M <= 511, "us_probe_upload: pulse longer than 1023 taps");
-  std::vector<float> taps(2 * M + 1), rev(2 * M + 1);
+  std::vector<float> taps(2 * M + 1), rev(2 * M + 1), drev(2 * M + 1);
   for (int m = -M; m <= M; ++m) {
     const double t = m / d->fs;
-    taps[m + M] = (float)(std::sin(2.0 * M_PI * d->f0 * t) * std::exp(-t * t / sigma));
+    const double env = std::exp(-t * t / sigma), w = 2.0 * M_PI * d->f0 * t;
+    taps[m + M] = (float)(std::sin(w) * env);
+    // sigma scales as 1 / f0^2, so d env / d f0 = -env 2 t^2 / (sigma f0)
+    drev[M - m] = (float)(2.0 * M_PI * t * std::cos(w) * env - std::sin(w) * env * 2.0 * t * t / (sigma * d->f0));
   }
   for (int i = 0; i < 2 * M + 1; ++i) rev[i] = taps[2 * M - i];
   US_HIP(bind_device(ctx->device));
@@ -176,12 +180,14 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
   const bool pow2 = (d->n_t & (d->n_t - 1)) == 0;
   if (hipMalloc(&p->taps, taps.size() * sizeof(float)) != hipSuccess ||
       hipMalloc(&p->taps_rev, rev.size() * sizeof(float)) != hipSuccess ||
+      hipMalloc(&p->dtaps_rev, drev.size() * sizeof(float)) != hipSuccess ||
       (pow2 && hipMalloc(&p->twiddle, (d->n_t / 2) * sizeof(float2)) != hipSuccess)) {
     us_probe_destroy(p);
     return fail(US_ENOMEM, "us_probe_upload: hipMalloc failed");
   }
   US_HIP(hipMemcpy(p->taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice));
   US_HIP(hipMemcpy(p->taps_rev, rev.data(), rev.size() * sizeof(float), hipMemcpyHostToDevice));
+  US_HIP(hipMemcpy(p->dtaps_rev, drev.data(), drev.size() * sizeof(float), hipMemcpyHostToDevice));
   if (pow2) {
     std::vector<float2> tw(d->n_t / 2);
     for (int j = 0; j < d->n_t / 2; ++j) {
@@ -199,6 +205,7 @@ int us_probe_destroy(us_probe* p) {
   (void)hipSetDevice(p->device);
   (void)hipFree(p->taps);
   (void)hipFree(p->taps_rev);
+  (void)hipFree(p->dtaps_rev);
   (void)hipFree(p->twiddle);
   delete p;
   return US_OK;
@@ -518,11 +525,13 @@ long vadj_stride(const us_scene* scene) { return ((long)scene->mesh.n_vertices +
 // two live-ray queues.
 size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_bounces, long cap,
                     ReplayStack* k = nullptr, char* base = nullptr, float** gh = nullptr,
-                    double** vadj = nullptr, double** g_part = nullptr, RayQueue* q0 = nullptr,
+                    float** gh_f0 = nullptr, double** vadj = nullptr, double** g_part = nullptr, RayQueue* q0 = nullptr,
                     RayQueue* q1 = nullptr, unsigned long long** counts = nullptr) {
   Carver c{base};
   float* g = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   if (gh) *gh = g;
+  float* gf = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
+  if (gh_f0) *gh_f0 = gf;
   double* va = c.take<double>((size_t)kVadjCopies * vadj_stride(scene));
   if (vadj) *vadj = va;
   double* gp = c.take<double>((size_t)kMaxReplayBlocks * scene->q_offset);
@@ -916,8 +925,9 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   const us_probe_desc& pd = probe->d;
   ReplayArgs a{};
   float* gh = nullptr;
+  float* gh_f0 = nullptr;
   RayQueue q0, q1;
-  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &a.vadj, &a.g_part,
+  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &a.vadj, &a.g_part,
                &q0, &q1, &a.counts);
   a.vadj_stride = vadj_stride(scene);
   if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2L * kVadjCopies * a.vadj_stride, 0u, s);
@@ -925,6 +935,10 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   {
     Timed tm(ctx, "pulse_adjoint", s);
     if (launch_pulse_adjoint(g_rf_dev, gh, probe->taps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
+      return fail(US_EINVAL, "us_simulate_rf_vjp: pulse too long");
+    // with g_acq, also the rows of dL/dh for the pulse's derivative in f0
+    if (g_acq_dev &&
+        launch_pulse_adjoint(g_rf_dev, gh_f0, probe->dtaps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
       return fail(US_EINVAL, "us_simulate_rf_vjp: pulse too long");
   }
   a.scene = scene_view(scene, probe);
@@ -942,6 +956,7 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   a.gh = gh;
   a.cap = cap;
   a.g_acq = g_acq_dev;
+  a.gh_f0 = g_acq_dev ? gh_f0 : nullptr;
   a.n_tx_total = n_tx;
   for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
     const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
@@ -971,7 +986,10 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
       }
     }
   }
-  launch_grad_reduce(a.g_part, a.n_grad, g_theta_dev, s);
+  // f0 also scales every region's amplitude attenuation a_r = alpha_r np_per_m,
+  // so the reduce adds sum_r alpha_r dL/dalpha_r / f0 to the f0 entry
+  launch_grad_reduce(a.g_part, a.n_grad, g_theta_dev, g_acq_dev ? g_acq_dev + n_tx + 2 : nullptr,
+                     a.scene.theta, scene->n_regions, 1.0 / pd.f0, s);
   if (scene->n_meshes > 0) {
     Timed tm(ctx, "basis_gather", s);
     launch_basis_gather(a.vadj, a.vadj_stride, scene->mesh.vbasis, scene->mesh.vbeg, scene->n_meshes, scene->n_basis,

@@ -98,9 +98,13 @@ struct ReplayArgs {
   RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
   unsigned long long* counts;   // [max_bounces + 2]: survivors of step k | diffuse interactions << 32
   // optional (null): d/d steering angle of each transmit (tx_base + local
-  // index), then d/d c_ref, then d/d pitch, accumulated; n_tx_total entries
-  // of angles precede the two
+  // index), then d/d c_ref, d/d pitch and d/d f0, accumulated; n_tx_total
+  // entries of angles precede the three. With g_acq, gh_f0 holds the rows of
+  // dL/dh for the pulse's derivative in f0 (the f0 entry gets each deposit's
+  // amplitude times gh_f0 at its time; the attenuation's share of d/d f0 is
+  // added by launch_grad_reduce)
   double* g_acq;
+  const float* gh_f0;
   int n_tx_total;
 };
 // The three phases of the replay over chunk rays [0, n): the forward phase
@@ -114,7 +118,10 @@ void launch_replay_prefix(const ReplayArgs& a, hipStream_t s);
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s);
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
 // g_theta[j] += sum over b of g_part[b * n_grad + j], j < n_grad.
-void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, hipStream_t s);
+// g_theta += the per-block rows of g_part; with g_f0 (may be null) also
+// *g_f0 += sum_r theta[3 r + 2] (row sum)[3 r + 2] * inv_f0 over r < n_regions.
+void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, double* g_f0, const double* theta,
+                        int n_regions, double inv_f0, hipStream_t s);
 // Copies of the vertex adjoints: block b adds into copy b % kVadjCopies, so
 // that (with blocks dealt round-robin to the eight XCDs) the atomics of one
 // XCD meet in its own L2; the copies are summed by the basis projection.

@@ -283,6 +283,7 @@ struct ReplayCtx {
   const SceneLDS& S;
   const ProbeView& P;
   const float* gh;      // dL/dh rows [n_tx][n_elem][n_t]
+  const float* ghf;     // the same for the pulse's derivative in f0, or null
   long row_base;        // (tx_base + txl) * n_elem
   GradAcc& G;
   int* stk;             // this thread's hierarchy stack in LDS
@@ -291,11 +292,13 @@ struct ReplayCtx {
 };
 
 // Secondary ray of interaction k at x (weight watt, time tp, interface f):
-// adds its adjoints to xbar, nrbar, Arbar, wattbar, tpbar and the parameters.
+// adds its adjoints to xbar, nrbar, Arbar, wattbar, tpbar, the target
+// element's x (xebar), f0 through the pulse (f0bar) and the parameters.
 template <bool kMeshes>
 __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f, double kd,
                                    double watt, double tp, int e2, d3& xbar, d3& nrbar,
-                                   double& Arbar, double& wattbar, double& tpbar, double& xebar) {
+                                   double& Arbar, double& wattbar, double& tpbar, double& xebar,
+                                   double& f0bar) {
   const SceneLDS& S = C.S;
   const ProbeView& P = C.P;
   const double xe = ((double)e2 - 0.5 * (double)(P.n_elem - 1)) * P.pitch;
@@ -349,6 +352,11 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   const double amp = amp0 * rest;
   double GA, GT;
   tent_adjoint(C.gh + (C.row_base + e2) * (long)P.n_t, P.n_t, P.fs, tof, amp, &GA, &GT);
+  if (C.ghf) {
+    double gf, unused;
+    tent_adjoint(C.ghf + (C.row_base + e2) * (long)P.n_t, P.n_t, P.fs, tof, 0.0, &gf, &unused);
+    f0bar += gf * amp;
+  }
   if (GA == 0.0 && GT == 0.0) return;
   tpbar += GT;
   const double AA = GA * amp;   // adjoint of log(amplitude)
@@ -603,15 +611,15 @@ __global__ void k_replay_prefix(ReplayArgs a) {
 }
 
 // Acquisition-parameter adjoints of one block (the steering angles of the
-// launch group's transmits, then c_ref and the pitch), summed in LDS and added
+// launch group's transmits, then c_ref, the pitch and f0), summed in LDS and added
 // to a.g_acq once per block. The order of those global additions varies from
 // run to run, so these sums vary in their last bits.
 __device__ __forceinline__ void acq_clear(double* acq) {
-  for (int j = threadIdx.x; j < kMaxTxPerLaunch + 2; j += blockDim.x) acq[j] = 0.0;
+  for (int j = threadIdx.x; j < kMaxTxPerLaunch + 3; j += blockDim.x) acq[j] = 0.0;
 }
 __device__ __forceinline__ void acq_flush(const ReplayArgs& a, const double* acq) {
   if (!a.g_acq) return;
-  for (int j = threadIdx.x; j < a.tx.n + 2; j += blockDim.x) {
+  for (int j = threadIdx.x; j < a.tx.n + 3; j += blockDim.x) {
     const double v = acq[j];
     if (v != 0.0) atomicAdd(&a.g_acq[j < a.tx.n ? a.tx_base + j : a.n_tx_total + (j - a.tx.n)], v);
   }
@@ -623,7 +631,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
   const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
   if ((long)blockIdx.x * blockDim.x >= n_q) return;
   __shared__ SceneLDS S;
-  __shared__ double acq[kMaxTxPerLaunch + 2];
+  __shared__ double acq[kMaxTxPerLaunch + 3];
   extern __shared__ double gsh[];      // gradient sums (kGradCopies copies), crossing caches, hierarchy stacks
   load_scene(S, a.scene);
   grad_clear(gsh, a.n_grad, a.grad_copies);
@@ -659,13 +667,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
     const Step st = step_at(S, o, d, R.t, R.w, reg, h);
     const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
     const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
-    ReplayCtx C{S, P, a.gh, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
+    ReplayCtx C{S, P, a.gh, a.gh_f0, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
     d3 xb{0, 0, 0}, nrb{0, 0, 0};
-    double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0;
-    secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb);
+    double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0, f0b = 0.0;
+    secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb, f0b);
     a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
     // x_e = (e - (N - 1)/2) pitch
     if (a.g_acq && xeb != 0.0) atomicAdd(&acq[a.tx.n + 1], xeb * ((double)e2 - 0.5 * (double)(P.n_elem - 1)));
+    if (a.g_acq && f0b != 0.0) atomicAdd(&acq[a.tx.n + 2], f0b);
   }
   __syncthreads();
   grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
@@ -678,7 +687,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_replay_reverse(ReplayArgs a, long n) {
   if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
-  __shared__ double acq[kMaxTxPerLaunch + 2];
+  __shared__ double acq[kMaxTxPerLaunch + 3];
   extern __shared__ double gsh[];      // gradient sums, kGradCopies copies
   load_scene(S, a.scene);
   grad_clear(gsh, a.n_grad, a.grad_copies);
@@ -723,6 +732,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
           if (fd > 0.0) {
             double ga, gt;
             tent_adjoint(a.gh + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, watt * fd, &ga, &gt);
+            if (a.gh_f0) {
+              double gf, unused;
+              tent_adjoint(a.gh_f0 + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, 0.0, &gf, &unused);
+              if (gf != 0.0) atomicAdd(&acq[a.tx.n + 2], gf * watt * fd);
+            }
             wattb += ga * fd;
             d0b.z -= ga * watt * rx_directivity_deriv(P, -d0.z);
             tpb += gt;
@@ -874,7 +888,9 @@ __global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__
 // g_theta[j] += sum of the kMaxReplayBlocks partial rows: one block per
 // entry j, each thread a strided share of the rows, then a tree in LDS.
 __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ g_part, int n_grad,
-                                                     double* __restrict__ g_theta) {
+                                                     double* __restrict__ g_theta, double* g_f0,
+                                                     const double* __restrict__ theta, int n_regions,
+                                                     double inv_f0) {
   const int j = blockIdx.x;
   double v = 0.0;
   for (int b = threadIdx.x; b < kMaxReplayBlocks; b += blockDim.x) v += g_part[(long)b * n_grad + j];
@@ -885,7 +901,11 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) g_theta[j] += red[0];
+  if (threadIdx.x == 0) {
+    g_theta[j] += red[0];
+    // the amplitude attenuation alpha_j np_per_m grows in proportion to f0
+    if (g_f0 && j < 3 * n_regions && j % 3 == 2 && red[0] != 0.0) atomicAdd(g_f0, red[0] * theta[j] * inv_f0);
+  }
 }
 
 namespace {
@@ -919,8 +939,10 @@ void launch_replay_prefix(const ReplayArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_prefix, dim3(1), dim3(64), 0, s, a);
 }
 
-void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, hipStream_t s) {
-  if (n_grad > 0) hipLaunchKernelGGL(k_grad_reduce, dim3(n_grad), dim3(256), 0, s, g_part, n_grad, g_theta);
+void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, double* g_f0, const double* theta,
+                        int n_regions, double inv_f0, hipStream_t s) {
+  if (n_grad > 0) hipLaunchKernelGGL(k_grad_reduce, dim3(n_grad), dim3(256), 0, s, g_part, n_grad, g_theta, g_f0, theta,
+                                    n_regions, inv_f0);
 }
 
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s) {

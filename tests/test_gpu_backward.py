@@ -276,10 +276,12 @@ def test_full_size_gradient_on_ray_sample(L, ctx):
 def test_vjp_acquisition_parameters(L, ctx):
     """Steering angles, c_ref and pitch through the transport (emission
     direction, delay and weight; the emission origins and the receiver-directed
-    rays' target elements) from us_simulate_rf_vjp_acq, against central
-    differences of the oracle's transport at fixed branch probabilities. The RF
-    gradient is the same for every element of a transmit, so that an array hit
-    moving to a neighbouring element under a pitch step changes nothing."""
+    rays' target elements) and f0 through the pulse (carrier and envelope
+    width) and every region's attenuation, from us_simulate_rf_vjp_acq, against
+    central differences of the oracle's transport and pulse at fixed branch
+    probabilities. The RF gradient is the same for every element of a
+    transmit, so that an array hit moving to a neighbouring element under a
+    pitch step changes nothing."""
     import dataclasses
     import torch
     wl = W.layered_phantom().replace(rays_per_elem=48, angles=np.radians([-6.0, 0.0, 5.0]),
@@ -311,9 +313,21 @@ def test_vjp_acquisition_parameters(L, ctx):
     hp = 1e-7 * p.pitch
     fd.append((Lf(dataclasses.replace(p, pitch=p.pitch + hp), wl.angles)
                - Lf(dataclasses.replace(p, pitch=p.pitch - hp), wl.angles)) / (2 * hp))
+
+    def Lf0(f0):
+        q = dataclasses.replace(p, f0=f0)
+        tr = oracle.trace(wl.scene, q, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                          theta=theta, probs=probs)
+        _, sq = oracle.pulse_taps(f0, p.n_cycles, p.fs)
+        assert sq.shape == s.shape   # the tap count M is held fixed
+        return float(np.sum(g_rf * oracle.pulse(tr.splat(wl.n_tx, p.n_elem, p.n_t, p.fs), sq)))
+
+    hf = 1e-7 * p.f0
+    fd.append((Lf0(p.f0 + hf) - Lf0(p.f0 - hf)) / (2 * hf))
     fd = np.array(fd)
+    assert np.any(wl.scene.theta()[2:3 * wl.scene.n_regions:3] > 0)   # attenuation takes part in d/d f0
     scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, p)
-    g_acq = torch.zeros(wl.n_tx + 2, dtype=torch.float64, device="cuda")
+    g_acq = torch.zeros(wl.n_tx + 3, dtype=torch.float64, device="cuda")
     L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
                          torch.tensor(g_rf, device="cuda"), g_acq=g_acq)
     torch.cuda.synchronize()
