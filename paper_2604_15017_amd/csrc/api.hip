@@ -88,6 +88,15 @@ struct Timed {
 
 }  // namespace
 
+// Destroys a half-built handle when an upload returns early (the US_HIP
+// checks of its copies); release() hands the finished handle to the caller.
+template <class T, int (*Destroy)(T*)>
+struct UploadGuard {
+  T* h;
+  ~UploadGuard() { if (h) Destroy(h); }
+  T* release() { T* t = h; h = nullptr; return t; }
+};
+
 struct us_probe {
   us_ctx* ctx;
   int device;   // kept for destroy, which must not read the context
@@ -171,6 +180,7 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
   for (int i = 0; i < 2 * M + 1; ++i) rev[i] = taps[2 * M - i];
   US_HIP(bind_device(ctx->device));
   us_probe* p = new us_probe{};
+  UploadGuard<us_probe, us_probe_destroy> guard{p};
   p->ctx = ctx;
   p->device = ctx->device;
   p->d = *d;
@@ -181,10 +191,8 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
   if (hipMalloc(&p->taps, taps.size() * sizeof(float)) != hipSuccess ||
       hipMalloc(&p->taps_rev, rev.size() * sizeof(float)) != hipSuccess ||
       hipMalloc(&p->dtaps_rev, drev.size() * sizeof(float)) != hipSuccess ||
-      (pow2 && hipMalloc(&p->twiddle, (d->n_t / 2) * sizeof(float2)) != hipSuccess)) {
-    us_probe_destroy(p);
+      (pow2 && hipMalloc(&p->twiddle, (d->n_t / 2) * sizeof(float2)) != hipSuccess))
     return fail(US_ENOMEM, "us_probe_upload: hipMalloc failed");
-  }
   US_HIP(hipMemcpy(p->taps, taps.data(), taps.size() * sizeof(float), hipMemcpyHostToDevice));
   US_HIP(hipMemcpy(p->taps_rev, rev.data(), rev.size() * sizeof(float), hipMemcpyHostToDevice));
   US_HIP(hipMemcpy(p->dtaps_rev, drev.data(), drev.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -196,7 +204,7 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
     }
     US_HIP(hipMemcpy(p->twiddle, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
   }
-  *out = p;
+  *out = guard.release();
   return US_OK;
 }
 
@@ -305,6 +313,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
   }
   US_HIP(bind_device(ctx->device));
   us_scene* s = new us_scene{};
+  UploadGuard<us_scene, us_scene_destroy> guard{s};
   s->ctx = ctx;
   s->device = ctx->device;
   s->n_regions = d->n_regions; s->n_planes = d->n_planes; s->n_spheres = d->n_spheres;
@@ -341,10 +350,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     md.vrest = vrest; md.vnormal = vnormal; md.vbasis = vbasis; md.vmesh = vmesh; md.tri = tri;
     md.vbeg = vbeg;
   }
-  if (!ok) {
-    us_scene_destroy(s);
-    return fail(US_ENOMEM, "us_scene_upload: hipMalloc failed");
-  }
+  if (!ok) return fail(US_ENOMEM, "us_scene_upload: hipMalloc failed");
   if (nm > 0) {
     US_HIP(hipMemcpy(s->mesh_regions, d->mesh_regions, 2 * nm * sizeof(int), hipMemcpyHostToDevice));
     US_HIP(hipMemcpy(s->mesh_kd, d->mesh_kd, nm * sizeof(double), hipMemcpyHostToDevice));
@@ -378,7 +384,7 @@ int us_scene_upload(us_ctx* ctx, const us_scene_desc* d, us_scene** out, int32_t
     US_HIP(hipGetLastError());
     US_HIP(hipDeviceSynchronize());
   }
-  *out = s;
+  *out = guard.release();
   if (n_params) *n_params = np;
   return US_OK;
 }
