@@ -10,9 +10,18 @@ memory, the current stream and the graph bookkeeping.
 
 Fixed ray realisations (common random numbers): the seed and ray range are
 attributes of the Renderer, constants of the differentiation.
+
+Acquisition parameters: SimulateRF and Beamform also take an optional vector
+acq = (steering angle of each transmit [rad], c_ref [m/s], pitch [m], f0 [Hz])
+(Renderer.acquisition() gives the current one). Passed with requires_grad, it
+receives the transport's gradient (us_simulate_rf_vjp_acq: emission, element
+centres, pulse and the f0-scaled attenuation) and the image chain's
+(us_beamform_acq_vjp: the delays of Eq. das, which do not depend on f0). A
+changed c_ref, pitch or f0 uploads a new probe; the element width stays.
 """
 from __future__ import annotations
 
+import dataclasses
 from typing import Optional
 
 import numpy as np
@@ -43,26 +52,52 @@ class Renderer:
         self.ws_bmode = L._workspace(L.load().us_bmode_workspace_size(wl.grid.n_px), dev)
         self.theta0 = torch.tensor(wl.scene.theta(), dtype=torch.float64, device=dev)
 
-    # -- the three differentiable stages
-    def simulate_rf(self, theta: torch.Tensor) -> torch.Tensor:
-        return SimulateRF.apply(theta, self)
+    # -- acquisition parameters
+    def acquisition(self) -> torch.Tensor:
+        """(steering angle of each transmit, c_ref, pitch, f0) as float64 [n_tx + 3]."""
+        return torch.tensor(self._acquisition_host(), dtype=torch.float64, device=self.ctx.torch_device)
 
-    def beamform(self, rf: torch.Tensor) -> torch.Tensor:
-        return Beamform.apply(rf, self)
+    def _acquisition_host(self) -> np.ndarray:
+        p = self.wl.probe
+        return np.concatenate([np.asarray(self.wl.angles, dtype=np.float64), [p.c_ref, p.pitch, p.f0]])
+
+    def set_acquisition(self, acq) -> None:
+        """Use these acquisition parameters from now on (uploads a new probe when
+        c_ref, pitch or f0 change)."""
+        a = acq.detach().to("cpu", torch.float64).numpy() if isinstance(acq, torch.Tensor) \
+            else np.asarray(acq, dtype=np.float64)
+        n = self.wl.n_tx
+        if a.shape != (n + 3,):
+            raise ValueError(f"acq must hold {n + 3} values (n_tx angles, c_ref, pitch, f0)")
+        p = self.wl.probe
+        q = dataclasses.replace(p, c_ref=float(a[n]), pitch=float(a[n + 1]), f0=float(a[n + 2]))
+        if (q.c_ref, q.pitch, q.f0) != (p.c_ref, p.pitch, p.f0):
+            self.probe = L.Probe(self.ctx, q)
+        self.wl = self.wl.replace(angles=a[:n].copy(), probe=q)
+
+    # -- the three differentiable stages
+    def simulate_rf(self, theta: torch.Tensor, acq: Optional[torch.Tensor] = None) -> torch.Tensor:
+        return SimulateRF.apply(theta, acq, self)
+
+    def beamform(self, rf: torch.Tensor, acq: Optional[torch.Tensor] = None) -> torch.Tensor:
+        return Beamform.apply(rf, acq, self)
 
     def bmode(self, iq: torch.Tensor) -> torch.Tensor:
         return BMode.apply(iq, self)
 
-    def render(self, theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def render(self, theta: Optional[torch.Tensor] = None, acq: Optional[torch.Tensor] = None) -> torch.Tensor:
         theta = self.theta0 if theta is None else theta
-        return self.bmode(self.beamform(self.simulate_rf(theta)))
+        return self.bmode(self.beamform(self.simulate_rf(theta, acq), acq))
 
 
 class SimulateRF(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, theta: torch.Tensor, r: Renderer):
+    def forward(fctx, theta: torch.Tensor, acq: Optional[torch.Tensor], r: Renderer):
         theta = theta.detach().to(torch.float64).contiguous()
         r.scene.set_params(theta)
+        if acq is not None:
+            r.set_acquisition(acq)
+        fctx.acq = r._acquisition_host()
         wl = r.wl
         rf = L.us_simulate_rf(r.ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
                               wl.rays_per_elem, wl.max_bounces, ray_begin=r.ray_begin,
@@ -75,32 +110,47 @@ class SimulateRF(torch.autograd.Function):
     def backward(fctx, g_rf: torch.Tensor):
         r = fctx.r
         (theta,) = fctx.saved_tensors
-        wl = r.wl
         r.scene.set_params(theta)           # the parameters this forward ran with
+        r.set_acquisition(fctx.acq)
+        wl = r.wl
+        g_acq = None
+        if fctx.needs_input_grad[1]:
+            g_acq = torch.zeros(wl.n_tx + 3, dtype=torch.float64, device=r.ctx.torch_device)
         g_theta = L.us_simulate_rf_vjp(r.ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
                                        wl.rays_per_elem, wl.max_bounces,
                                        g_rf.to(torch.float32).contiguous(),
                                        ray_begin=r.ray_begin, ray_count=r.ray_count,
-                                       workspace=r.ws_replay)
-        return g_theta, None
+                                       workspace=r.ws_replay, g_acq=g_acq)
+        return g_theta, g_acq, None
 
 
 class Beamform(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, rf: torch.Tensor, r: Renderer):
+    def forward(fctx, rf: torch.Tensor, acq: Optional[torch.Tensor], r: Renderer):
+        if acq is not None:
+            r.set_acquisition(acq)
+        fctx.acq = r._acquisition_host()
         wl = r.wl
-        iq = L.us_beamform(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids,
-                           rf.detach().to(torch.float32).contiguous(), workspace=r.ws_beam)
+        rf = rf.detach().to(torch.float32).contiguous()
+        iq = L.us_beamform(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids, rf, workspace=r.ws_beam)
         fctx.r = r
+        fctx.save_for_backward(rf)
         return iq
 
     @staticmethod
     def backward(fctx, g_iq: torch.Tensor):
         r = fctx.r
+        (rf,) = fctx.saved_tensors
+        r.set_acquisition(fctx.acq)
         wl = r.wl
-        g_rf = L.us_beamform_vjp(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids,
-                                 g_iq.to(torch.float32).contiguous(), workspace=r.ws_beam_vjp)
-        return g_rf, None
+        g_iq = g_iq.to(torch.float32).contiguous()
+        g_rf = L.us_beamform_vjp(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids, g_iq,
+                                 workspace=r.ws_beam_vjp)
+        g_acq = None
+        if fctx.needs_input_grad[1]:
+            g = L.us_beamform_acq_vjp(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids, rf, g_iq)
+            g_acq = torch.cat([g, g.new_zeros(1)])   # the delays do not depend on f0
+        return g_rf, g_acq, None
 
 
 class BMode(torch.autograd.Function):

@@ -243,6 +243,51 @@ def test_autograd_matches_explicit_chain(L, ctx):
     assert np.allclose(a, e, rtol=1e-9, atol=1e-12 * np.abs(e).max())
 
 
+def test_autograd_acquisition_parameters(L, ctx):
+    """The acquisition vector (angles, c_ref, pitch, f0) through the Functions:
+    a changed vector renders as a Renderer built with those values, and its
+    gradient is the sum of the transport's (us_simulate_rf_vjp_acq) and the
+    image chain's (us_beamform_acq_vjp, nothing for f0) on the same forward
+    tensors, up to the order of the replay's fp64 atomic additions."""
+    import dataclasses
+    import torch
+    from paper_2604_15017_amd import autograd as A
+    wl = W.layered_phantom().replace(rays_per_elem=32, angles=np.radians([-8.0, 0.0, 8.0]),
+                                     tx_ids=np.arange(3, dtype=np.uint32))
+    n = wl.n_tx
+    r = A.Renderer(wl, ctx)
+    acq = r.acquisition().cpu().numpy()
+    a2 = acq + np.concatenate([np.full(n, 0.01), acq[n:] * np.array([0.01, 0.02, 0.03])])
+    acq2 = torch.tensor(a2, dtype=torch.float64, device="cuda", requires_grad=True)
+    theta = r.theta0.clone()
+    rf = r.simulate_rf(theta, acq2)
+    iq = r.beamform(rf, acq2)
+    b = r.bmode(iq)
+    wl2 = wl.replace(angles=a2[:n].copy(), probe=dataclasses.replace(wl.probe, c_ref=float(a2[n]),
+                                                                    pitch=float(a2[n + 1]), f0=float(a2[n + 2])))
+    with torch.no_grad():
+        b_direct = A.Renderer(wl2, ctx).render(theta)
+    torch.cuda.synchronize()
+    diff = float((b.detach() - b_direct).abs().max())
+    print(f"B-mode against a renderer built with the changed acquisition: max {diff:.2e} dB", flush=True)
+    assert diff <= 0.05
+    g_b = torch.tensor(smooth_field(tuple(b.shape), 13).astype(np.float32), device="cuda")
+    (b * g_b).sum().backward()
+    torch.cuda.synchronize()
+    g_iq = L.us_bmode_vjp(ctx, iq.detach(), g_b, wl.dr_db)
+    g_rf = L.us_beamform_vjp(ctx, r.probe, wl2.grid, wl2.angles, wl2.tx_ids, g_iq)
+    g_img = L.us_beamform_acq_vjp(ctx, r.probe, wl2.grid, wl2.angles, wl2.tx_ids, rf.detach(), g_iq)
+    g_tr = torch.zeros(n + 3, dtype=torch.float64, device="cuda")
+    L.us_simulate_rf_vjp(ctx, r.scene, r.probe, wl2.angles, wl2.tx_ids, wl2.seed, wl2.rays_per_elem,
+                         wl2.max_bounces, g_rf, g_acq=g_tr)
+    torch.cuda.synchronize()
+    exp = g_tr.cpu().numpy() + np.concatenate([g_img.cpu().numpy(), [0.0]])
+    got = acq2.grad.cpu().numpy()
+    print(f"acquisition gradient through autograd {got}, explicit chain {exp}", flush=True)
+    assert np.all(exp != 0.0)
+    assert np.all(np.abs(got - exp) <= 1e-9 * np.abs(exp))
+
+
 def test_full_size_gradient_on_ray_sample(L, ctx):
     """The forward+backward workload at full size (11 x 2^20 rays): dL/drf from
     the full-size image chain on the GPU; the transport VJP of a sampled ray
