@@ -243,6 +243,39 @@ def test_autograd_matches_explicit_chain(L, ctx):
     assert np.allclose(a, e, rtol=1e-9, atol=1e-12 * np.abs(e).max())
 
 
+def test_vjp_acquisition_parameters_over_launch_groups(L, ctx):
+    """70 transmits run as launch groups of 64 and 6: one call's gradients (the
+    angles at their transmit's index, c_ref, pitch and f0 after them, and
+    theta) equal the sums of 70 single-transmit calls, whose rays are the same
+    (the ray counters hold the transmit id)."""
+    import torch
+    n = 70
+    wl = W.layered_phantom().replace(rays_per_elem=2, angles=np.radians(np.linspace(-10.0, 10.0, n)),
+                                     tx_ids=np.arange(n, dtype=np.uint32))
+    p = wl.probe
+    g_rf = torch.tensor(smooth_field((n, p.n_elem, p.n_t), 21).astype(np.float32), device="cuda")
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, p)
+    g_acq = torch.zeros(n + 3, dtype=torch.float64, device="cuda")
+    g_theta = L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                                   wl.max_bounces, g_rf, g_acq=g_acq)
+    exp_acq = np.zeros(n + 3)
+    exp_theta = torch.zeros_like(g_theta)
+    for i in range(n):
+        g1 = torch.zeros(4, dtype=torch.float64, device="cuda")
+        L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles[i:i + 1], wl.tx_ids[i:i + 1], wl.seed,
+                             wl.rays_per_elem, wl.max_bounces, g_rf[i:i + 1].contiguous(), g_theta=exp_theta,
+                             g_acq=g1)
+        g1 = g1.cpu().numpy()
+        exp_acq[i] = g1[0]
+        exp_acq[n:] += g1[1:]
+    torch.cuda.synchronize()
+    got = g_acq.cpu().numpy()
+    assert np.count_nonzero(exp_acq[:n]) >= n - 2 and np.count_nonzero(exp_acq[n:]) == 3
+    assert np.all(np.abs(got - exp_acq) <= 1e-9 * np.abs(exp_acq))
+    e = exp_theta.cpu().numpy()
+    assert np.allclose(g_theta.cpu().numpy(), e, rtol=1e-9, atol=1e-12 * np.abs(e).max())
+
+
 def test_autograd_acquisition_parameters(L, ctx):
     """The acquisition vector (angles, c_ref, pitch, f0) through the Functions:
     a changed vector renders as a Renderer built with those values, and its
