@@ -206,3 +206,65 @@ def test_mesh_vjp_displaced_specular(L, ctx):
 def test_anatomy_phantom_vjp_ray_sample(L, ctx):
     wl = W.anatomy_phantom()
     mesh_vjp(L, ctx, wl, "anatomy phantom VJP sample", ray_begin=300_001, ray_count=3000)
+
+
+def acquisition_fd(wl, g_rf, rel):
+    """Central differences of <g_rf, rf> in (angles, c_ref, pitch, f0) through the
+    oracle's transport and pulse at the branch probabilities of the unperturbed
+    run; relative step `rel`."""
+    import dataclasses
+    p = wl.probe
+    theta = wl.scene.theta()
+    probs = oracle.trace(wl.scene, p, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                         theta=theta, record_probs=True).probs
+    n_taps = oracle.pulse_taps(p.f0, p.n_cycles, p.fs)[1].shape
+
+    def L_(probe, angles):
+        tr = oracle.trace(wl.scene, probe, angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                          theta=theta, probs=probs)
+        _, s = oracle.pulse_taps(probe.f0, probe.n_cycles, probe.fs)
+        assert s.shape == n_taps
+        return float(np.sum(g_rf * oracle.pulse(tr.splat(wl.n_tx, p.n_elem, p.n_t, p.fs), s)))
+
+    fd = []
+    for i in range(wl.n_tx):
+        ap, am = wl.angles.copy(), wl.angles.copy()
+        ap[i] += rel
+        am[i] -= rel
+        fd.append((L_(p, ap) - L_(p, am)) / (2 * rel))
+    for field in ("c_ref", "pitch", "f0"):
+        h = rel * getattr(p, field)
+        v = getattr(p, field)
+        fd.append((L_(dataclasses.replace(p, **{field: v + h}), wl.angles)
+                   - L_(dataclasses.replace(p, **{field: v - h}), wl.angles)) / (2 * h))
+    return np.array(fd)
+
+
+def test_mesh_vjp_acquisition_parameters(L, ctx):
+    """us_simulate_rf_vjp_acq on the blob + tube mesh scene (the mesh instances
+    of the replay kernels): angles, c_ref, pitch and f0 against central
+    differences of the oracle at fixed branch probabilities, with an RF
+    gradient equal across elements (a pitch step then moves no array hit's
+    contribution). On flat-faced meshes a step can carry a ray across a
+    triangle edge or a silhouette, where the path jumps and a central
+    difference is no derivative; the ray seed is one whose differences at
+    steps 1e-7 and 1e-8 agree (asserted), so no such crossing lies inside."""
+    import torch
+    wl = small_anatomy(rays_per_elem=24).replace(seed=12)
+    p = wl.probe
+    g_t = smooth_field((wl.n_tx, 1, p.n_t), 17)
+    g_rf = np.ascontiguousarray(np.broadcast_to(g_t, (wl.n_tx, p.n_elem, p.n_t))).astype(np.float32)
+    fd = acquisition_fd(wl, g_rf, 1e-7)
+    fd_small = acquisition_fd(wl, g_rf, 1e-8)
+    assert np.all(np.abs(fd - fd_small) <= 1e-5 * np.abs(fd))
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, p)
+    g_acq = torch.zeros(wl.n_tx + 3, dtype=torch.float64, device="cuda")
+    L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                         torch.tensor(g_rf, device="cuda"), g_acq=g_acq)
+    torch.cuda.synchronize()
+    got = g_acq.cpu().numpy()
+    rel = np.abs(got - fd) / np.abs(fd)
+    print(f"mesh scene acquisition parameters: gpu {got}, finite differences {fd}, relative error {rel}",
+          flush=True)
+    assert np.all(np.abs(fd) > 0)
+    assert np.all(rel <= 1e-3)
