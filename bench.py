@@ -161,7 +161,9 @@ def acquisition_leg(ctx, steps, warmup):
     """Gradients of the image with respect to the acquisition parameters (the
     11 steering angles, c_ref, pitch) on the layered frame's RF and grid, from
     seeded channels and a seeded image gradient: ms per call, and the DAS
-    kernel's rate in taps (pixel x element x transmit) per second."""
+    kernel's rate in taps (pixel x element x transmit) per second. Then the
+    transport VJP of the whole layered frame from a seeded dL/drf, timed
+    without and with the acquisition adjoints (angles, c_ref, pitch, f0)."""
     import ctypes
     import numpy as np
     import torch
@@ -194,11 +196,40 @@ def acquisition_leg(ctx, steps, warmup):
     ms = start.elapsed_time(end) / steps
     taps = g.n_px * p.n_elem * wl.n_tx
     das_ms = prof["das_acq"][0] / steps if "das_acq" in prof else float("nan")
+    # through the transport: the replay VJP of the whole frame with and without
+    # the acquisition adjoints (angles, c_ref, pitch, f0), seeded dL/drf
+    scene = L.Scene(ctx, wl.scene)
+    g_rf = torch.randn((wl.n_tx, p.n_elem, p.n_t), dtype=torch.float32, device="cuda", generator=gen)
+    ws_r = L._workspace(L.us_simulate_rf_vjp_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx,
+                                                            wl.max_bounces), ctx.torch_device)
+    g_theta = torch.zeros(scene.n_params, dtype=torch.float64, device="cuda")
+    g_acq = torch.zeros(wl.n_tx + 3, dtype=torch.float64, device="cuda")
+
+    def vjp(acq):
+        L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                             wl.max_bounces, g_rf, g_theta=g_theta, workspace=ws_r,
+                             g_acq=g_acq if acq else None)
+    replay_ms = {}
+    for acq in (False, True):
+        vjp(acq)
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(max(1, steps // 4)):
+            vjp(acq)
+        end.record()
+        torch.cuda.synchronize()
+        replay_ms[acq] = start.elapsed_time(end) / max(1, steps // 4)
+    acq_finite = bool(np.isfinite(g_acq.cpu().numpy()).all())
+    del ws_r
+    torch.cuda.empty_cache()
     return {"workload": f"layered_phantom grid {g.n_x} x {g.n_z}, {wl.n_tx} transmits x {p.n_elem} elements, "
-                        f"d/d (steering angles, c_ref, pitch) of Re<g, I>",
+                        f"d/d (steering angles, c_ref, pitch) of Re<g, I>; transport VJP of the frame "
+                        f"({wl.n_tx} x {wl.rays_per_tx} rays) with d/d (angles, c_ref, pitch, f0)",
             "ms_per_call": round(ms, 4), "das_acq_ms": round(das_ms, 4),
             "taps_per_s": taps / (das_ms * 1e-3) if das_ms == das_ms else None,
-            "finite": bool(np.isfinite(out.cpu().numpy()).all())}
+            "transport_vjp_ms": round(replay_ms[False], 3),
+            "transport_vjp_with_acquisition_ms": round(replay_ms[True], 3),
+            "finite": bool(np.isfinite(out.cpu().numpy()).all()) and acq_finite}
 
 
 def serving(ctx, n_requests):
