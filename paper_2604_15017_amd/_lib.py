@@ -144,6 +144,19 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _expect(t, n: int, dtype, name: str):
+    """Raise unless `t` is a contiguous device tensor of `n` elements of `dtype`:
+    the library reads and writes exactly that many through the raw pointer."""
+    if t is None:
+        raise ValueError(f"{name}: missing")
+    if t.dtype != dtype or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {n} elements "
+                         f"(got {t.dtype}, {t.numel()} elements, contiguous={t.is_contiguous()})")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    return t
+
+
 def _workspace(nbytes: int, device):
     torch = _torch()
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -267,6 +280,7 @@ def us_simulate_rf(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, see
         ray_count = int(p.n_elem) * int(rays_per_elem) - ray_begin
     if rf is None:
         rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
+    _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
     if workspace is None:
         workspace = _workspace(us_simulate_rf_workspace_size(scene, probe, n_tx, ray_count,
                                                              max_bounces), ctx.torch_device)
@@ -289,6 +303,9 @@ def us_beamform(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, iq=None, w
     g = _grid(grid)
     if iq is None:
         iq = torch.empty((g.n_x, g.n_z, 2), dtype=torch.float32, device=ctx.torch_device)
+    p = probe.desc
+    _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
+    _expect(iq, 2 * g.n_x * g.n_z, torch.float32, "iq")
     if workspace is None:
         workspace = _workspace(load().us_beamform_workspace_size(probe.handle, n_tx), ctx.torch_device)
     _check(load().us_beamform(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf),
@@ -306,6 +323,10 @@ def us_beamform_acq_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, g_
     g = _grid(grid)
     if out is None:
         out = torch.empty(n_tx + 2, dtype=torch.float64, device=ctx.torch_device)
+    p = probe.desc
+    _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
+    _expect(g_iq, 2 * g.n_x * g.n_z, torch.float32, "g_iq")
+    _expect(out, n_tx + 2, torch.float64, "out")
     if workspace is None:
         workspace = _workspace(load().us_beamform_acq_vjp_workspace_size(probe.handle, ctypes.byref(g), n_tx),
                                ctx.torch_device)
@@ -318,8 +339,10 @@ def us_beamform_acq_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, g_
 def us_bmode(ctx: Context, iq, dr_db: float, out=None, workspace=None, stream=None):
     torch = _torch()
     n_px = iq.numel() // 2
+    _expect(iq, 2 * n_px, torch.float32, "iq")
     if out is None:
         out = torch.empty(iq.shape[:-1], dtype=torch.float32, device=ctx.torch_device)
+    _expect(out, n_px, torch.float32, "bmode")
     if workspace is None:
         workspace = _workspace(load().us_bmode_workspace_size(n_px), ctx.torch_device)
     _check(load().us_bmode(ctx.handle, _ptr(iq), n_px, float(dr_db), _ptr(out), _ptr(workspace),
@@ -336,6 +359,11 @@ def us_image_loss(ctx: Context, bmode, ref, lambda1: float = 0.0, lambda2: float
         loss = torch.empty(1, dtype=torch.float64, device=ctx.torch_device)
     if want_grad and g_bmode is None:
         g_bmode = torch.empty_like(bmode)
+    _expect(bmode, n_px, torch.float32, "bmode")
+    _expect(ref, n_px, torch.float32, "ref")
+    _expect(loss, 1, torch.float64, "loss")
+    if want_grad:
+        _expect(g_bmode, n_px, torch.float32, "g_bmode")
     _check(load().us_image_loss(ctx.handle, _ptr(bmode), _ptr(ref), n_px, float(lambda1),
                                 float(lambda2), _ptr(loss), _ptr(g_bmode if want_grad else None),
                                 ctypes.c_void_p(0), 0, _stream(stream)), "us_image_loss")
@@ -347,6 +375,9 @@ def us_bmode_vjp(ctx: Context, iq, g_bmode, dr_db: float, g_iq=None, workspace=N
     n_px = iq.numel() // 2
     if g_iq is None:
         g_iq = torch.empty_like(iq)
+    _expect(iq, 2 * n_px, torch.float32, "iq")
+    _expect(g_bmode, n_px, torch.float32, "g_bmode")
+    _expect(g_iq, 2 * n_px, torch.float32, "g_iq")
     if workspace is None:
         workspace = _workspace(load().us_bmode_workspace_size(n_px), ctx.torch_device)
     _check(load().us_bmode_vjp(ctx.handle, _ptr(iq), _ptr(g_bmode), n_px, float(dr_db), _ptr(g_iq),
@@ -362,6 +393,8 @@ def us_beamform_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, g_iq, g_rf
     p = probe.desc
     if g_rf is None:
         g_rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
+    _expect(g_iq, 2 * g.n_x * g.n_z, torch.float32, "g_iq")
+    _expect(g_rf, n_tx * p.n_elem * p.n_t, torch.float32, "g_rf")
     if workspace is None:
         workspace = _workspace(load().us_beamform_vjp_workspace_size(probe.handle, n_tx),
                                ctx.torch_device)
@@ -390,6 +423,8 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
         ray_count = int(p.n_elem) * int(rays_per_elem) - ray_begin
     if g_theta is None:
         g_theta = torch.zeros(scene.n_params, dtype=torch.float64, device=ctx.torch_device)
+    _expect(g_rf, n_tx * p.n_elem * p.n_t, torch.float32, "g_rf")
+    _expect(g_theta, scene.n_params, torch.float64, "g_theta")
     if workspace is None:
         workspace = _workspace(us_simulate_rf_vjp_workspace_size(scene, probe, n_tx, ray_count,
                                                                  max_bounces), ctx.torch_device)
@@ -399,8 +434,7 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
                                          int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(workspace),
                                          workspace.numel(), _stream(stream)), "us_simulate_rf_vjp")
     else:
-        if g_acq.dtype != torch.float64 or g_acq.numel() != n_tx + 3 or not g_acq.is_contiguous():
-            raise ValueError(f"g_acq must be a contiguous float64 tensor of {n_tx + 3} entries")
+        _expect(g_acq, n_tx + 3, torch.float64, "g_acq")
         _check(load().us_simulate_rf_vjp_acq(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
                                              int(rays_per_elem), int(ray_begin), int(ray_count),
                                              int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(g_acq),

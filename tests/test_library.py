@@ -33,3 +33,20 @@ def test_binding_fails_loudly_without_gpu():
         pytest.skip("libusrt.so not built")
     with pytest.raises(Exception):
         L.Context(0)
+
+
+def test_binding_rejects_tensors_the_library_would_overrun():
+    """The binding checks each caller tensor's dtype, element count, layout
+    and device before handing its raw pointer to the library."""
+    import torch
+    from paper_2604_15017_amd import _lib
+    with pytest.raises(ValueError, match="elements"):
+        _lib._expect(torch.zeros(5, dtype=torch.float64), 6, torch.float64, "out")
+    with pytest.raises(ValueError, match="float32"):
+        _lib._expect(torch.zeros(6, dtype=torch.float64), 6, torch.float32, "rf")
+    with pytest.raises(ValueError, match="contiguous"):
+        _lib._expect(torch.zeros(4, 6, dtype=torch.float32).t(), 24, torch.float32, "rf")
+    with pytest.raises(ValueError, match="GPU"):
+        _lib._expect(torch.zeros(6, dtype=torch.float32), 6, torch.float32, "rf")
+    with pytest.raises(ValueError, match="missing"):
+        _lib._expect(None, 6, torch.float32, "g_iq")
