@@ -1,16 +1,18 @@
 """Benchmark of the hot path on one MI355X.
 
-One step = one B-mode frame of the layered phantom (11 plane waves x 2^20
-rays, 8 interactions, 128 elements x 4096 samples, 256 x 512 pixels): transport
-and RF synthesis, beamforming, envelope and log compression, all through the
-C-ABI with inputs and buffers resident in HBM. The same protocol is repeated
-for forward + backward, and for the triangle-mesh anatomy phantom (200k
-triangles, 21 x 798,912 rays, 12 interactions), reported beside it, followed
-by iterations of the inverse loop and the serving stream. Prints one JSON line with the
-throughput in ray-segments/s (a segment is one closest-hit query, primary or
-secondary), frames/s, per-kernel timings from HIP events recorded on the
-launch stream inside the timed region, the roofline of the dominant kernel and
-the FP64 oracle timed on the host cores as a reported baseline.
+One step = one B-mode frame of the triangle-mesh anatomy phantom (200,192
+triangles in four nested closed meshes, 21 plane waves x 798,912 rays, 12
+interactions, 192 elements x 8192 samples, 512 x 1024 pixels): transport and
+RF synthesis, beamforming, envelope and log compression, all through the C-ABI
+with inputs and buffers resident in HBM. The same protocol is repeated for
+forward + backward (gradient of every parameter), then for the layered phantom
+(11 plane waves x 2^20 rays, 8 interactions, 128 x 4096 samples, 256 x 512
+pixels), followed by iterations of the inverse loop, the acquisition gradients
+and the serving stream. Prints one JSON line with the throughput in
+ray-segments/s (a segment is one closest-hit query, primary or secondary),
+frames/s, per-kernel timings from HIP events recorded on the launch stream
+inside the timed region, the roofline of the dominant kernel and the FP64
+oracle timed on the host cores as a reported baseline.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--no-cpu-baseline]
 """
@@ -75,12 +77,13 @@ def kernel_bytes(name, wl, counts, n_px):
     }.get(name)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, summary):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the
-    summary is missing or the kernel sources changed since it was taken."""
+    summary profiles/`summary` (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
+    None when the summary is missing or the kernel sources changed since it
+    was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "transport_layered_phantom_hbm_traffic.md")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         text = open(path).read()
     except OSError:
@@ -106,18 +109,29 @@ def measured_traffic(kernel):
     return vals.get(kernel)
 
 
-def cpu_baseline(wl):
-    """The FP64 oracle on the host cores: the transport of one whole frame
-    (every ray of every transmit; a few seconds of CPU work), segments/s."""
+def cpu_baseline(wl, ray_count=None):
+    """The FP64 oracle on the host cores, segments/s of its transport (no
+    image chain). With ray_count, a labelled sample: that many consecutive rays
+    of every transmit, centred on the middle of the array (the oracle builds
+    its own hierarchy first, which is timed too); else the whole frame."""
     import oracle
     cores = len(os.sched_getaffinity(0))
+    total = wl.probe.n_elem * wl.rays_per_elem
+    if ray_count is None or ray_count >= total:
+        begin, count = 0, total
+    else:
+        begin, count = total // 2 - ray_count // 2, ray_count
     t0 = time.perf_counter()
     tr = oracle.trace(wl.scene, wl.probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
-                      wl.max_bounces, n_threads=cores)
+                      wl.max_bounces, ray_begin=begin, ray_count=count, n_threads=cores)
     dt = time.perf_counter() - t0
+    what = ("one whole frame" if count == total else
+            f"rays [{begin}, {begin + count}) of each transmit ({wl.n_tx} x {count} = {wl.n_tx * count} rays "
+            f"of the frame's {wl.n_tx * total}; elements {begin // wl.rays_per_elem}-"
+            f"{(begin + count - 1) // wl.rays_per_elem} of {wl.probe.n_elem})")
     return {"value": tr.segments / dt, "unit": "ray-segments/s", "cores": cores, "kind": "oracle",
-            "sample": f"one whole frame: {wl.n_tx} x {wl.rays_per_tx} rays, FP64 transport "
-                      f"(no image chain), {tr.segments} segments in {dt:.2f} s"}
+            "sample": f"{what}: FP64 transport, {wl.max_bounces} interactions, {tr.segments} segments in "
+                      f"{dt:.2f} s"}
 
 
 def inverse_leg(ctx, steps, warmup):
@@ -263,6 +277,7 @@ def serving(ctx, n_requests):
     srv.run(len(batch))
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
+    plain_segs = sum(r.segments for r in srv.results.values() if r.ok)
     print(f"serving: plain closed loop {plain_s:.2f} s", file=sys.stderr, flush=True)
     # the same closed loop with eight overlapping slots
     ex8 = S.GpuExecutor(ctx, n_slots=8)
@@ -273,6 +288,7 @@ def serving(ctx, n_requests):
     srv.run(len(batch))
     torch.cuda.synchronize()
     batched_s = time.perf_counter() - t0
+    batched_segs = sum(r.segments for r in srv.results.values() if r.ok)
     print(f"serving: batched closed loop {batched_s:.2f} s", file=sys.stderr, flush=True)
     rate = 0.8 * len(batch) / plain_s
     offsets = S.poisson_arrivals(len(batch), rate, seed=4)
@@ -280,7 +296,10 @@ def serving(ctx, n_requests):
            "arrival_rate_hz": round(rate, 2),
            "plain_closed_loop_s": round(plain_s, 3),
            "batched_closed_loop_s": round(batched_s, 3),
-           "closed_loop_speedup": round(plain_s / batched_s, 3)}
+           "closed_loop_speedup": round(plain_s / batched_s, 3),
+           # capacity: every request queued at once, segments of all requests / wall time
+           "plain_capacity_segments_per_s": plain_segs / plain_s,
+           "batched_capacity_segments_per_s": batched_segs / batched_s}
     for name, slots in (("plain_one_at_a_time", 1), ("continuous_batching", 8)):
         ex = ex1 if slots == 1 else ex8
         srv = S.Server(ex, n_slots=slots, mem_cap_bytes=200 * 10**9)
@@ -384,14 +403,46 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
             "loss": float(loss.item()) if backward else None}
 
 
+SEGMENT_BYTES = 120   # per transport segment: queued ray state in and out plus the hit record
+
+
+def transport_roofline(name, prof, counts, steps, traffic_file):
+    """Roofline of transport kernel `name` ("bounce" or "secondary"): its
+    segments per launch (primary closest-hit queries for the bounce, receiver
+    legs for the secondary rays) times SEGMENT_BYTES, divided by the launch's
+    average duration from the HIP events recorded on the launch stream."""
+    ms, launches = prof[name]
+    per_step = launches // steps
+    segs = counts[0] if name == "bounce" else counts[1]
+    bytes_per_launch = SEGMENT_BYTES * segs / max(1, per_step)
+    avg_s = ms * 1e-3 / max(1, launches)
+    achieved = bytes_per_launch / avg_s / 1e9
+    traffic = measured_traffic(name, traffic_file)
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": int(traffic) if traffic is not None else None,
+            "bytes_per_launch": int(bytes_per_launch), "segments_per_launch": int(segs / max(1, per_step)),
+            "avg_launch_us": round(avg_s * 1e6, 2)}
+
+
+def frame_summary(r, wl, steps):
+    counts = r["counts"]
+    return {"ms_per_step": round(r["fwd_ms"], 4), "frames_per_s": round(1e3 / r["fwd_ms"], 2),
+            "ray_segments_per_s": r["segments"] / (r["fwd_ms"] * 1e-3),
+            "segments_per_frame": r["segments"],
+            "frame_counts": {"primary_segments": counts[0], "secondary_segments": counts[1],
+                             "deposits": counts[2], "interactions": counts[3], "secondary_rays": counts[4]},
+            "kernels": r["kernels"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-anatomy", action="store_true")
+    ap.add_argument("--no-layered", action="store_true", help="skip the layered-phantom legs")
     ap.add_argument("--no-inverse", action="store_true", help="skip the inverse-loop leg")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-backward", action="store_true",
@@ -414,82 +465,76 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    wl = W.layered_phantom()
-    p, g = wl.probe, wl.grid
-    r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup,
+
+    # headline: the triangle-mesh anatomy phantom (the largest single-GPU workload)
+    wa = W.anatomy_phantom()
+    a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup,
                    backward=not args.no_backward)
-    counts, segments, prof = r["counts"], r["segments"], r["prof"]
-    ms_per_step = r["fwd_ms"]
-    print(f"layered phantom: forward {ms_per_step:.3f} ms/frame, forward+backward "
-          f"{r['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
-
-    dom = max(prof, key=lambda k: prof[k][0])
-    dom_ms = prof[dom][0] / args.steps
-    dom_bytes = kernel_bytes(dom, wl, counts, g.n_px)
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    launches = prof[dom][1] // args.steps
-    traffic = measured_traffic(dom)
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": int(traffic) if traffic is not None else None,
-                "bytes_per_launch": int(dom_bytes / max(1, launches)),
-                "avg_launch_us": round(1e3 * dom_ms / max(1, launches), 2)}
-
+    print(f"anatomy phantom: forward {a['fwd_ms']:.3f} ms/frame, forward+backward "
+          f"{a['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
+    prof, counts = a["prof"], a["counts"]
+    transport = [k for k in ("bounce", "secondary") if k in prof]
+    dom = max(transport, key=lambda k: prof[k][0])
+    roofline = transport_roofline(dom, prof, counts, args.steps, "transport_anatomy_phantom_hbm_traffic.md")
+    p, g = wa.probe, wa.grid
+    fs = frame_summary(a, wa, args.steps)
+    n_tri = sum(len(m.triangles) for m in wa.scene.meshes)
     out = {
         "metric": "ray-segments/s and B-mode frames/s (fwd, fwd+bwd)",
-        "value": segments / (ms_per_step * 1e-3),
+        "value": fs["ray_segments_per_s"],
         "unit": "ray-segments/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": fs["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 transport + f32 image chain",
         "data": "synthetic",
-        "config": {"workload": "layered_phantom", "n_tx": wl.n_tx, "rays_per_tx": wl.rays_per_tx,
-                   "max_bounces": wl.max_bounces, "n_elem": p.n_elem, "n_t": p.n_t,
-                   "grid": [g.n_x, g.n_z], "pass": "forward"},
-        "frames_per_s": round(1e3 / ms_per_step, 2),
-        "segments_per_frame": segments,
-        "frame_counts": {"primary_segments": counts[0], "secondary_segments": counts[1],
-                         "deposits": counts[2], "interactions": counts[3], "secondary_rays": counts[4]},
-        "kernels": r["kernels"],
+        "config": {"workload": "anatomy_phantom", "triangles": n_tri, "meshes": len(wa.scene.meshes),
+                   "n_tx": wa.n_tx, "rays_per_tx": wa.rays_per_tx, "max_bounces": wa.max_bounces,
+                   "n_elem": p.n_elem, "n_t": p.n_t, "grid": [g.n_x, g.n_z], "pass": "forward"},
+        "frames_per_s": fs["frames_per_s"],
+        "segments_per_frame": fs["segments_per_frame"],
+        "frame_counts": fs["frame_counts"],
+        "kernels": fs["kernels"],
         "roofline": roofline,
+        "roofline_bounce": transport_roofline("bounce", prof, counts, args.steps,
+                                              "transport_anatomy_phantom_hbm_traffic.md"),
         "fwd_bwd": None if args.no_backward else {
-            "workload": "layered_phantom forward + backward, B-mode MSE vs +-5 % target, "
-                        f"gradient of all {r['n_params']} parameters",
-            "ms_per_step": round(r["fb_ms"], 4), "frames_per_s": round(1e3 / r["fb_ms"], 2),
-            "ray_segments_per_s": segments / (r["fb_ms"] * 1e-3),
-            "loss": r["loss"], "kernels": r["fb_kernels"]},
+            "workload": f"anatomy_phantom forward + backward, B-mode MSE vs the perturbed target, "
+                        f"gradient of all {a['n_params']} parameters",
+            "ms_per_step": round(a["fb_ms"], 4), "frames_per_s": round(1e3 / a["fb_ms"], 2),
+            "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
+            "loss": a["loss"], "kernels": a["fb_kernels"]},
     }
-    if not args.no_anatomy:
-        wa = W.anatomy_phantom()
-        a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup,
+    if not args.no_layered:
+        wl = W.layered_phantom()
+        r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup,
                        backward=not args.no_backward)
-        print(f"anatomy phantom: forward {a['fwd_ms']:.3f} ms/frame, forward+backward "
-              f"{a['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
-        out["anatomy"] = {
-            "workload": f"anatomy_phantom: {sum(len(m.triangles) for m in wa.scene.meshes)} triangles "
-                        f"in {len(wa.scene.meshes)} closed meshes, {wa.n_tx} x {wa.rays_per_tx} rays, "
-                        f"{wa.max_bounces} interactions, {wa.probe.n_elem} x {wa.probe.n_t} samples, "
-                        f"{wa.grid.n_x} x {wa.grid.n_z} pixels",
-            "forward": {"ms_per_step": round(a["fwd_ms"], 4), "frames_per_s": round(1e3 / a["fwd_ms"], 2),
-                        "ray_segments_per_s": a["segments"] / (a["fwd_ms"] * 1e-3),
-                        "segments_per_frame": a["segments"], "kernels": a["kernels"]},
-            "fwd_bwd": None if args.no_backward else {
-                "ms_per_step": round(a["fb_ms"], 4), "frames_per_s": round(1e3 / a["fb_ms"], 2),
-                "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
-                "gradient_parameters": a["n_params"], "loss": a["loss"],
-                "kernels": a["fb_kernels"]},
-        }
+        print(f"layered phantom: forward {r['fwd_ms']:.3f} ms/frame, forward+backward "
+              f"{r['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
+        lay = frame_summary(r, wl, args.steps)
+        lay["workload"] = (f"layered_phantom: {wl.n_tx} x {wl.rays_per_tx} rays, {wl.max_bounces} interactions, "
+                           f"{wl.probe.n_elem} x {wl.probe.n_t} samples, {wl.grid.n_x} x {wl.grid.n_z} pixels")
+        lay["roofline"] = transport_roofline("bounce", r["prof"], r["counts"], args.steps,
+                                             "transport_layered_phantom_hbm_traffic.md")
+        if not args.no_backward:
+            lay["fwd_bwd"] = {"ms_per_step": round(r["fb_ms"], 4), "frames_per_s": round(1e3 / r["fb_ms"], 2),
+                              "ray_segments_per_s": r["segments"] / (r["fb_ms"] * 1e-3),
+                              "gradient_parameters": r["n_params"], "loss": r["loss"],
+                              "kernels": r["fb_kernels"]}
+        out["layered_phantom"] = lay
     if not args.no_backward and not args.no_inverse:
         out["inverse"] = inverse_leg(ctx, args.steps, args.warmup)
         print(f"inverse loop: {out['inverse']['ms_per_iteration']:.3f} ms/iteration", file=sys.stderr,
               flush=True)
-    if not args.no_backward:
+    if not args.no_backward and not args.no_layered:
         out["acquisition_gradients"] = acquisition_leg(ctx, args.steps, args.warmup)
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        # 2^16 rays of each of the 21 transmits: 1,376,256 of the frame's 16,777,152
+        out["cpu_baseline"] = cpu_baseline(wa, ray_count=1 << 16)
+        if "layered_phantom" in out:
+            out["layered_phantom"]["cpu_baseline"] = cpu_baseline(W.layered_phantom())
     print(json.dumps(out), flush=True)
 
 

@@ -162,9 +162,18 @@ def _workspace(nbytes: int, device):
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
 
 
+def _expect_ws(ws, name: str = "workspace"):
+    """A caller workspace is a contiguous uint8 device tensor: its element
+    count is passed to the library as its size in bytes."""
+    import torch
+    return _expect(ws, ws.numel() if ws is not None else 0, torch.uint8, name)
+
+
 def _tx_array(angles, tx_ids):
     angles = np.asarray(angles, dtype=np.float64).reshape(-1)
-    ids = np.asarray(tx_ids if tx_ids is not None else np.arange(len(angles)), dtype=np.uint32)
+    ids = np.asarray(tx_ids if tx_ids is not None else np.arange(len(angles)), dtype=np.uint32).reshape(-1)
+    if ids.shape[0] != angles.shape[0]:
+        raise ValueError(f"tx_ids has {ids.shape[0]} entries for {angles.shape[0]} steering angles")
     arr = (us_tx_desc * len(angles))()
     for i, (a, k) in enumerate(zip(angles, ids)):
         arr[i].angle = float(a)
@@ -253,7 +262,8 @@ class Scene:
         self.ctx, self.handle, self.n_params, self.desc = ctx, h, n.value, s
 
     def set_params(self, theta_dev, stream=None):
-        """us_scene_set_params from a float64 device tensor."""
+        """us_scene_set_params from a float64 device tensor of n_params entries."""
+        _expect(theta_dev, self.n_params, _torch().float64, "theta")
         _check(load().us_scene_set_params(self.handle, _ptr(theta_dev), int(theta_dev.numel()),
                                           _stream(stream)), "us_scene_set_params")
 
@@ -281,9 +291,14 @@ def us_simulate_rf(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, see
     if rf is None:
         rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
     _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
+    if counters is not None:
+        _expect(counters, 5, torch.int64, "counters")
+    if ray_hash is not None:
+        _expect(ray_hash, n_tx * int(ray_count), torch.int64, "ray_hash")
     if workspace is None:
         workspace = _workspace(us_simulate_rf_workspace_size(scene, probe, n_tx, ray_count,
                                                              max_bounces), ctx.torch_device)
+    _expect_ws(workspace)
     _check(load().us_simulate_rf(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
                                  int(rays_per_elem), int(ray_begin), int(ray_count),
                                  int(max_bounces), _ptr(rf), _ptr(counters), _ptr(ray_hash),
@@ -308,6 +323,7 @@ def us_beamform(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, iq=None, w
     _expect(iq, 2 * g.n_x * g.n_z, torch.float32, "iq")
     if workspace is None:
         workspace = _workspace(load().us_beamform_workspace_size(probe.handle, n_tx), ctx.torch_device)
+    _expect_ws(workspace)
     _check(load().us_beamform(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf),
                               _ptr(iq), _ptr(workspace), workspace.numel(), _stream(stream)),
            "us_beamform")
@@ -330,6 +346,7 @@ def us_beamform_acq_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, g_
     if workspace is None:
         workspace = _workspace(load().us_beamform_acq_vjp_workspace_size(probe.handle, ctypes.byref(g), n_tx),
                                ctx.torch_device)
+    _expect_ws(workspace)
     _check(load().us_beamform_acq_vjp(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf), _ptr(g_iq),
                                       _ptr(out), _ptr(workspace), workspace.numel(), _stream(stream)),
            "us_beamform_acq_vjp")
@@ -345,6 +362,7 @@ def us_bmode(ctx: Context, iq, dr_db: float, out=None, workspace=None, stream=No
     _expect(out, n_px, torch.float32, "bmode")
     if workspace is None:
         workspace = _workspace(load().us_bmode_workspace_size(n_px), ctx.torch_device)
+    _expect_ws(workspace)
     _check(load().us_bmode(ctx.handle, _ptr(iq), n_px, float(dr_db), _ptr(out), _ptr(workspace),
                            workspace.numel(), _stream(stream)), "us_bmode")
     return out
@@ -380,6 +398,7 @@ def us_bmode_vjp(ctx: Context, iq, g_bmode, dr_db: float, g_iq=None, workspace=N
     _expect(g_iq, 2 * n_px, torch.float32, "g_iq")
     if workspace is None:
         workspace = _workspace(load().us_bmode_workspace_size(n_px), ctx.torch_device)
+    _expect_ws(workspace)
     _check(load().us_bmode_vjp(ctx.handle, _ptr(iq), _ptr(g_bmode), n_px, float(dr_db), _ptr(g_iq),
                                _ptr(workspace), workspace.numel(), _stream(stream)), "us_bmode_vjp")
     return g_iq
@@ -398,6 +417,7 @@ def us_beamform_vjp(ctx: Context, probe: Probe, grid, angles, tx_ids, g_iq, g_rf
     if workspace is None:
         workspace = _workspace(load().us_beamform_vjp_workspace_size(probe.handle, n_tx),
                                ctx.torch_device)
+    _expect_ws(workspace)
     _check(load().us_beamform_vjp(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(g_iq),
                                   _ptr(g_rf), _ptr(workspace), workspace.numel(), _stream(stream)),
            "us_beamform_vjp")
@@ -428,6 +448,7 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
     if workspace is None:
         workspace = _workspace(us_simulate_rf_vjp_workspace_size(scene, probe, n_tx, ray_count,
                                                                  max_bounces), ctx.torch_device)
+    _expect_ws(workspace)
     if g_acq is None:
         _check(load().us_simulate_rf_vjp(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
                                          int(rays_per_elem), int(ray_begin), int(ray_count),
@@ -449,6 +470,8 @@ def us_param_map(ctx: Context, u, lo, hi, theta=None, stream=None):
     n = u.numel()
     if theta is None:
         theta = torch.empty(n, dtype=torch.float64, device=ctx.torch_device)
+    for t, name in ((u, "u"), (lo, "lo"), (hi, "hi"), (theta, "theta")):
+        _expect(t, n, torch.float64, name)
     _check(load().us_param_map(ctx.handle, _ptr(u), _ptr(lo), _ptr(hi), n, _ptr(theta),
                                _stream(stream)), "us_param_map")
     return theta
@@ -457,6 +480,10 @@ def us_param_map(ctx: Context, u, lo, hi, theta=None, stream=None):
 def us_adam_step(ctx: Context, u, m, v, g_theta, lo, hi, lr, step: int, beta1: float = 0.9,
                  beta2: float = 0.999, eps: float = 1e-8, max_norm: float = 0.0, stream=None):
     """One Adam step on u (float64 device tensors, updated in place with m, v)."""
+    torch = _torch()
+    n = u.numel()
+    for t, name in ((u, "u"), (m, "m"), (v, "v"), (g_theta, "g_theta"), (lo, "lo"), (hi, "hi"), (lr, "lr")):
+        _expect(t, n, torch.float64, name)
     _check(load().us_adam_step(ctx.handle, _ptr(u), _ptr(m), _ptr(v), _ptr(g_theta), _ptr(lo),
                                _ptr(hi), _ptr(lr), u.numel(), int(step), float(beta1),
                                float(beta2), float(eps), float(max_norm), _stream(stream)),

@@ -37,7 +37,10 @@ class Request:
     rid: int
     workload: object                  # workloads.Workload
     want_grad: bool = False
-    b_ref: Optional[np.ndarray] = None   # reference image for the gradient's loss
+    # reference image of the gradient's loss: a float32 device tensor
+    # [n_x][n_z] (build_requests makes it one), or a host array that launch()
+    # stages through pinned memory without blocking
+    b_ref: Optional[object] = None
     arrival: float = 0.0
 
 
@@ -194,7 +197,7 @@ class GpuExecutor:
         s = {"rf": 4 * rows, "iq": 8 * g.n_px, "bmode": 4 * g.n_px,
              "ws_trace": L.us_simulate_rf_workspace_size(scene, probe, n_tx, wl.rays_per_tx, wl.max_bounces),
              "ws_beam": L.load().us_beamform_workspace_size(probe.handle, n_tx),
-             "ws_bmode": L.load().us_bmode_workspace_size(g.n_px), "counters": 64}
+             "ws_bmode": L.load().us_bmode_workspace_size(g.n_px), "counters": 40}
         if req.want_grad:
             s.update({"b_ref": 4 * g.n_px, "g_b": 4 * g.n_px, "g_iq": 8 * g.n_px, "g_rf": 4 * rows,
                       "loss": 8, "g_theta": 8 * scene.n_params,
@@ -217,7 +220,7 @@ class GpuExecutor:
         sz = self.sizes(req)
         with torch.cuda.stream(st):
             t = {}
-            t["counters"] = torch.zeros(8, dtype=torch.int64, device=dev)
+            t["counters"] = torch.zeros(5, dtype=torch.int64, device=dev)
             t["rf"] = torch.empty((wl.n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=dev)
             t["iq"] = torch.empty((g.n_x, g.n_z, 2), dtype=torch.float32, device=dev)
             t["bmode"] = torch.empty((g.n_x, g.n_z), dtype=torch.float32, device=dev)
@@ -230,7 +233,7 @@ class GpuExecutor:
                           workspace=t["ws_beam"], stream=st)
             L.us_bmode(self.ctx, t["iq"], wl.dr_db, out=t["bmode"], workspace=t["ws_bmode"], stream=st)
             if req.want_grad:
-                t["b_ref"] = torch.as_tensor(np.ascontiguousarray(req.b_ref, dtype=np.float32)).to(dev, non_blocking=False)
+                t["b_ref"] = self._device_ref(req.b_ref, t)
                 t["loss"] = torch.empty(1, dtype=torch.float64, device=dev)
                 t["g_b"] = torch.empty_like(t["bmode"])
                 t["g_iq"] = torch.empty_like(t["iq"])
@@ -250,6 +253,19 @@ class GpuExecutor:
             ev = torch.cuda.Event()
             ev.record(st)
         return (t, ev)
+
+    def _device_ref(self, b_ref, t):
+        """The reference image on the device without a host-blocking copy:
+        a device tensor is used as it is; a host array is copied into pinned
+        memory and sent with an asynchronous copy on the current (slot)
+        stream, its pinned buffer kept in the request's handle until the
+        request completes."""
+        torch = self.torch
+        if isinstance(b_ref, torch.Tensor) and b_ref.is_cuda:
+            return b_ref
+        host = torch.from_numpy(np.ascontiguousarray(b_ref, dtype=np.float32)).pin_memory()
+        t["b_ref_host"] = host
+        return host.to(self.ctx.torch_device, non_blocking=True)
 
     def done(self, handle) -> bool:
         return handle[1].query()
@@ -289,9 +305,10 @@ def replay_stream(server: Server, requests: List[Request], offsets: np.ndarray):
     return [server.results[r.rid] for r in requests]
 
 
-def reference_image(ex: GpuExecutor, wl, target_scene) -> np.ndarray:
+def reference_image(ex: GpuExecutor, wl, target_scene):
     """B-mode of `target_scene` under workload `wl` (the reference image of a
-    gradient request), rendered through the library on the default stream."""
+    gradient request), rendered through the library on the default stream;
+    a float32 device tensor [n_x][n_z] that stays resident."""
     L, torch = ex.L, ex.torch
     scene = L.Scene(ex.ctx, target_scene)
     _, probe = ex.resident(wl)
@@ -300,7 +317,7 @@ def reference_image(ex: GpuExecutor, wl, target_scene) -> np.ndarray:
     iq = L.us_beamform(ex.ctx, probe, wl.grid, wl.angles, wl.tx_ids, rf)
     b = L.us_bmode(ex.ctx, iq, wl.dr_db)
     torch.cuda.synchronize()
-    return b.cpu().numpy()
+    return b
 
 
 def build_requests(ex: GpuExecutor, specs) -> List[Request]:

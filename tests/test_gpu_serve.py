@@ -45,3 +45,36 @@ def test_results_alone_equal_results_in_mix():
             assert np.abs(ga - gm).max() <= 1e-3 * np.abs(ga).max()
     st = S.latency_stats(list(mix.results.values()))
     assert st["completed"] == len(reqs)
+
+
+def test_launch_enqueues_without_blocking_the_host():
+    """launch() of a gradient request only enqueues work on its slot's stream:
+    with torch's synchronisation check set to raise, neither a device-resident
+    reference image nor a host one (staged through pinned memory) makes the
+    serving thread wait for the device."""
+    import torch
+    from paper_2604_15017_amd import _lib as L
+    from paper_2604_15017_amd import serve as S
+    ctx = L.Context(0)
+    specs = [sp for sp in W.serving_requests(40, seed=11, min_log2_rays=14, max_log2_rays=16)
+             if sp.want_grad][:2]
+    assert len(specs) == 2
+    ex = S.GpuExecutor(ctx, n_slots=2)
+    reqs = S.build_requests(ex, specs)
+    for slot, r in enumerate(reqs):   # scenes, probes and each stream's allocator blocks in place
+        h = ex.launch(r, slot)
+        torch.cuda.synchronize()
+        ex.finish(r, h)
+    torch.cuda.synchronize()
+    host_ref = S.Request(reqs[1].rid, reqs[1].workload, True, reqs[1].b_ref.cpu().numpy())
+    handles = []
+    torch.cuda.set_sync_debug_mode("error")
+    try:
+        handles.append((reqs[0], ex.launch(reqs[0], 0)))
+        handles.append((host_ref, ex.launch(host_ref, 1)))
+    finally:
+        torch.cuda.set_sync_debug_mode(0)
+    torch.cuda.synchronize()
+    for r, h in handles:
+        res = ex.finish(r, h)
+        assert res.ok and np.isfinite(res.loss) and res.segments > 0

@@ -50,3 +50,21 @@ def test_binding_rejects_tensors_the_library_would_overrun():
         _lib._expect(torch.zeros(6, dtype=torch.float32), 6, torch.float32, "rf")
     with pytest.raises(ValueError, match="missing"):
         _lib._expect(None, 6, torch.float32, "g_iq")
+
+
+def test_binding_rejects_mismatched_transmits_and_workspaces():
+    """Every steering angle needs its transmit id (each id selects the Philox
+    stream of its transmit), and a workspace is a uint8 device buffer whose
+    element count the library takes as its size in bytes."""
+    import torch
+    from paper_2604_15017_amd import _lib
+    arr, n = _lib._tx_array([0.0, 0.1], [3, 4])
+    assert n == 2 and arr[1].id == 4 and abs(arr[1].angle - 0.1) < 1e-15
+    with pytest.raises(ValueError, match="tx_ids"):
+        _lib._tx_array([0.0, 0.1, 0.2], [0, 1])
+    with pytest.raises(ValueError, match="uint8"):
+        _lib._expect_ws(torch.zeros(16, dtype=torch.float32))
+    with pytest.raises(ValueError, match="GPU"):
+        _lib._expect_ws(torch.zeros(16, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="missing"):
+        _lib._expect_ws(None)
