@@ -16,6 +16,10 @@ constexpr int kMaxCylinders = 16;
 constexpr int kMaxBvhDepth = 38;        // levels of the binary tree the hierarchy is built as
 constexpr int kMaxBvhStack = 60;        // LDS stack entries of the 4-wide walk: three per level
 constexpr double kTMin = 1e-6;          // self-intersection guard [m]
+// Outward padding of the hierarchy's fp32 boxes [m]: it covers the rounding of
+// a ray's origin, inverse direction and slab distances to fp32 (a few nm at
+// the scenes' scale), so the fp32 box tests never miss a box the fp64 ray enters.
+constexpr float kBoxPad = 1e-6f;
 constexpr double kPi = 3.14159265358979323846;
 
 // ---------------------------------------------------------------------------
@@ -331,6 +335,65 @@ __device__ __forceinline__ bool make_deposit(uint32_t row, int n_t, double fs, d
   d->w0 = (float)(a * (1.0 - f));
   d->w1 = (float)(a * f);
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Order-independent sums of fp64 values. A value v is cut at fixed binary
+// boundaries: with its leading bit in window b (windows of 32 bits, window b
+// holding multiples of 2^(32 b + kSumBase)), the integer pieces hi and lo of
+// v / 2^(32 (b - 1) + kSumBase), truncated towards zero (at least 33
+// significant bits kept), are added to the int64 words b and b - 1 of the
+// accumulator. Integer addition is associative, so the total is the same
+// whatever order the threads add in. Each word takes 2^31 pieces before it
+// could overflow. Values below 2^(kSumBase + 32) are dropped; a value above
+// the last window increments the overflow word, and the total then reads NaN.
+// ---------------------------------------------------------------------------
+constexpr int kSumBins = 10;                  // windows: 2^-168 .. 2^120
+constexpr int kSumBase = -200;
+constexpr int kSumWords = kSumBins + 1;       // the windows, then the overflow count
+
+struct SumPieces { int b; unsigned long long hi, lo; bool over; };
+
+__device__ __forceinline__ bool sum_pieces(double v, SumPieces* p) {
+  if (v == 0.0) return false;
+  const double a = fabs(v);
+  int e;
+  frexp(a, &e);                               // a in [2^(e-1), 2^e)
+  const int b = (e - 1 - kSumBase) >> 5;      // window of the leading bit
+  if (b < 1) return false;                    // below the first window: dropped
+  if (!(b < kSumBins)) {                      // beyond the last window (or not finite)
+    p->over = true;
+    return true;
+  }
+  const double scaled = ldexp(a, -(32 * (b - 1) + kSumBase));   // in [2^32, 2^64)
+  const unsigned long long u = (unsigned long long)scaled;
+  unsigned long long hi = u >> 32, lo = u & 0xFFFFFFFFull;
+  if (v < 0.0) { hi = 0ull - hi; lo = 0ull - lo; }
+  p->b = b;
+  p->hi = hi;
+  p->lo = lo;
+  p->over = false;
+  return true;
+}
+
+// Adds v to the accumulator acc[kSumWords] (LDS or global memory).
+__device__ __forceinline__ void sum_add(unsigned long long* acc, double v) {
+  SumPieces p;
+  if (!sum_pieces(v, &p)) return;
+  if (p.over) { atomicAdd(acc + kSumBins, 1ull); return; }
+  atomicAdd(acc + p.b, p.hi);
+  if (p.lo) atomicAdd(acc + p.b - 1, p.lo);
+}
+
+// The accumulated total: the windows added in a fixed order.
+__device__ __forceinline__ double sum_value(const unsigned long long* acc) {
+  if (acc[kSumBins]) return __builtin_nan("");
+  double r = 0.0;
+  for (int b = 0; b < kSumBins; ++b) {
+    const long long w = (long long)acc[b];
+    if (w) r += ldexp((double)w, 32 * b + kSumBase);
+  }
+  return r;
 }
 
 // Recorded deposits, structure of arrays: key = (row - row0) << kDepBinBits |

@@ -15,18 +15,33 @@ __device__ __forceinline__ d3 cross(d3 a, d3 b) {
   return d3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
-// Ray against one fp32 child box padded by kPad (absorbs the rounding of the
-// ray to fp32); entry distance in *t0, culled beyond lim.
-__device__ __forceinline__ bool slab(const float* lo, const float* hi, float ox, float oy, float oz,
+// Ray against one fp32 child box (already padded outward by kBoxPad by the
+// refit, which absorbs the rounding of the ray to fp32): with oi = o * (1/d)
+// per axis, the slab distances are lo * (1/d) - oi, one fused multiply-add
+// each; entry distance in *t0, culled beyond lim.
+__device__ __forceinline__ bool slab(const float* lo, const float* hi, float oix, float oiy, float oiz,
                                      float ix, float iy, float iz, float lim, float* t0) {
-  constexpr float kPad = 1e-6f;
-  const float ax = (lo[0] - kPad - ox) * ix, bx = (hi[0] + kPad - ox) * ix;
-  const float ay = (lo[1] - kPad - oy) * iy, by = (hi[1] + kPad - oy) * iy;
-  const float az = (lo[2] - kPad - oz) * iz, bz = (hi[2] + kPad - oz) * iz;
+  const float ax = fmaf(lo[0], ix, -oix), bx = fmaf(hi[0], ix, -oix);
+  const float ay = fmaf(lo[1], iy, -oiy), by = fmaf(hi[1], iy, -oiy);
+  const float az = fmaf(lo[2], iz, -oiz), bz = fmaf(hi[2], iz, -oiz);
   const float tmin = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
   const float tmax = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
   *t0 = tmin;
   return tmin <= tmax && tmin <= lim;
+}
+
+// The ray in the form the slab tests take: 1/d per axis (clamped away from
+// infinity) and o * (1/d), in fp32.
+struct SlabRay { float ix, iy, iz, oix, oiy, oiz; };
+__device__ __forceinline__ SlabRay slab_ray(d3 o, d3 d) {
+  SlabRay r;
+  r.ix = fabs(d.x) > 1e-30 ? (float)(1.0 / d.x) : copysignf(1e30f, (float)d.x);
+  r.iy = fabs(d.y) > 1e-30 ? (float)(1.0 / d.y) : copysignf(1e30f, (float)d.y);
+  r.iz = fabs(d.z) > 1e-30 ? (float)(1.0 / d.z) : copysignf(1e30f, (float)d.z);
+  r.oix = (float)o.x * r.ix;
+  r.oiy = (float)o.y * r.iy;
+  r.oiz = (float)o.z * r.iz;
+  return r;
 }
 
 // Moller-Trumbore in fp64 on a leaf-order triangle record, edges included;
@@ -46,6 +61,25 @@ __device__ __forceinline__ double rec_distance(const TriRec& r, d3 o, d3 d) {
   return dot(e2, qv) * inv;
 }
 
+// Four child boxes of node n against the ray, culled beyond lim, sorted by
+// entry distance (a five-exchange network); misses get INFINITY.
+__device__ __forceinline__ void node_children(const BvhNode& n, const SlabRay& q, float lim, float* t, int* r) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float lo[3] = {n.lox[j], n.loy[j], n.loz[j]}, hi[3] = {n.hix[j], n.hiy[j], n.hiz[j]};
+    float tj;
+    t[j] = slab(lo, hi, q.oix, q.oiy, q.oiz, q.ix, q.iy, q.iz, lim, &tj) ? tj : INFINITY;
+    r[j] = n.child[j];
+  }
+#define USRT_CX(a, b)                                                      \
+  if (t[b] < t[a]) {                                                       \
+    const float tt = t[a]; t[a] = t[b]; t[b] = tt;                         \
+    const int rr = r[a]; r[a] = r[b]; r[b] = rr;                           \
+  }
+  USRT_CX(0, 1) USRT_CX(2, 3) USRT_CX(0, 2) USRT_CX(1, 3) USRT_CX(1, 2)
+#undef USRT_CX
+}
+
 // Closest triangle in (kTMin, best) by walking the 4-wide hierarchy near
 // child first. One step handles one inner node (its four child boxes tested
 // against the ray in fp32, the hit children ordered by entry distance: the
@@ -55,34 +89,15 @@ __device__ __forceinline__ double rec_distance(const TriRec& r, d3 o, d3 d) {
 // it holds at most three entries per inner level.
 __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, double& best, int& best_tri,
                                              int* stk) {
-  constexpr float kPad = 1e-6f;
-  const float ox = (float)o.x, oy = (float)o.y, oz = (float)o.z;
-  const float ix = fabs(d.x) > 1e-30 ? (float)(1.0 / d.x) : copysignf(1e30f, (float)d.x);
-  const float iy = fabs(d.y) > 1e-30 ? (float)(1.0 / d.y) : copysignf(1e30f, (float)d.y);
-  const float iz = fabs(d.z) > 1e-30 ? (float)(1.0 / d.z) : copysignf(1e30f, (float)d.z);
+  const SlabRay q = slab_ray(o, d);
   const int step = blockDim.x;
   int sp = 0, cur = 0;
   for (;;) {
     if (cur >= 0) {
-      const BvhNode n = s.nodes[cur];
-      const float lim = (float)best * 1.0001f + kPad;
+      const float lim = (float)best * 1.0001f + kBoxPad;
       float t[4];
       int r[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float lo[3] = {n.lox[j], n.loy[j], n.loz[j]}, hi[3] = {n.hix[j], n.hiy[j], n.hiz[j]};
-        float tj;
-        t[j] = slab(lo, hi, ox, oy, oz, ix, iy, iz, lim, &tj) ? tj : INFINITY;
-        r[j] = n.child[j];
-      }
-      // sort the four (distance, child) pairs: a five-exchange network
-#define USRT_CX(a, b)                                                      \
-      if (t[b] < t[a]) {                                                   \
-        const float tt = t[a]; t[a] = t[b]; t[b] = tt;                     \
-        const int rr = r[a]; r[a] = r[b]; r[b] = rr;                       \
-      }
-      USRT_CX(0, 1) USRT_CX(2, 3) USRT_CX(0, 2) USRT_CX(1, 3) USRT_CX(1, 2)
-#undef USRT_CX
+      node_children(s.nodes[cur], q, lim, t, r);
       if (t[0] != INFINITY) {
         // the build bounds the depth by stack_cap / 3, so the pushes always fit
         if (t[3] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[3]; ++sp; }
@@ -162,6 +177,112 @@ __device__ __forceinline__ Hit closest_hit(const SceneLDS& s, d3 o, d3 d, bool w
 constexpr int kMeshLegs = 16;
 __device__ __forceinline__ int max_legs(const SceneLDS& s) {
   return s.n_planes + 2 * s.n_spheres + 2 * s.n_cylinders + kMeshLegs * s.n_meshes + 1;
+}
+
+// Crossings of a straight segment x + s w, nearest first. A receiver segment
+// is walked once for several crossings instead of once per leg: the walk keeps
+// the kSegHits nearest surfaces with lo + kTMin < s < hi (every plane,
+// sphere and cylinder crossing and every triangle hit) and culls boxes beyond
+// the farthest kept one once the list is full. A full list may have dropped
+// farther crossings; the caller then walks again from its last crossing.
+// With lo the last crossing taken, a leg from it needs s > lo + kTMin, the
+// same guard a per-leg closest-hit query from that point applies.
+constexpr int kSegHits = 4;
+struct SegHits {
+  double s[kSegHits];
+  int h[kSegHits];   // kind << 28 | index
+  int n;
+};
+
+__device__ __forceinline__ void seg_insert(SegHits& L, double s, int h) {
+  if (L.n == kSegHits && !(s < L.s[kSegHits - 1])) return;
+  double cs = s;
+  int ch = h;
+#pragma unroll
+  for (int j = 0; j < kSegHits; ++j) {
+    if (j < L.n) {
+      if (cs < L.s[j]) {
+        const double ts = L.s[j]; L.s[j] = cs; cs = ts;
+        const int th = L.h[j]; L.h[j] = ch; ch = th;
+      }
+    } else if (j == L.n) {
+      L.s[j] = cs;
+      L.h[j] = ch;
+    }
+  }
+  L.n = L.n < kSegHits ? L.n + 1 : kSegHits;
+}
+
+__device__ __forceinline__ double seg_cull(const SegHits& L, double hi) {
+  return L.n == kSegHits ? L.s[kSegHits - 1] : hi;
+}
+
+template <bool kMeshes>
+__device__ __forceinline__ SegHits segment_hits(const SceneLDS& s, d3 x, d3 w, double lo, double hi,
+                                                int* stk) {
+  SegHits L;
+  L.n = 0;
+  const double smin = lo + kTMin;
+  if (w.z != 0.0) {
+    const double inv = 1.0 / w.z;
+    for (int k = 0; k < s.n_planes; ++k) {
+      const double t = (s.pd[k] - x.z) * inv;
+      if (t > smin && t < hi) seg_insert(L, t, (kHitPlane << 28) | k);
+    }
+  }
+  for (int k = 0; k < s.n_spheres; ++k) {
+    const d3 oc{x.x - s.sx[k], x.y - s.sy[k], x.z - s.sz[k]};
+    const double b = dot(oc, w);
+    const double disc = b * b - (dot(oc, oc) - s.sr[k] * s.sr[k]);
+    if (disc < 0.0) continue;
+    const double q = sqrt(disc);
+    const double t1 = -b - q, t2 = -b + q;
+    if (t1 > smin && t1 < hi) seg_insert(L, t1, (kHitSphere << 28) | k);
+    if (t2 > smin && t2 < hi) seg_insert(L, t2, (kHitSphere << 28) | k);
+  }
+  const double ca = w.x * w.x + w.z * w.z;
+  if (ca > 0.0) {
+    for (int k = 0; k < s.n_cylinders; ++k) {
+      const double ox = x.x - s.cx[k], oz = x.z - s.cz[k];
+      const double b = ox * w.x + oz * w.z;
+      const double disc = b * b - ca * (ox * ox + oz * oz - s.cr[k] * s.cr[k]);
+      if (disc < 0.0) continue;
+      const double q = sqrt(disc);
+      const double t1 = (-b - q) / ca, t2 = (-b + q) / ca;
+      if (t1 > smin && t1 < hi) seg_insert(L, t1, (kHitCylinder << 28) | k);
+      if (t2 > smin && t2 < hi) seg_insert(L, t2, (kHitCylinder << 28) | k);
+    }
+  }
+  if (kMeshes && s.n_meshes > 0) {
+    const SlabRay q = slab_ray(x, w);
+    const int step = blockDim.x;
+    int sp = 0, cur = 0;
+    for (;;) {
+      if (cur >= 0) {
+        const float lim = (float)seg_cull(L, hi) * 1.0001f + kBoxPad;
+        float t[4];
+        int r[4];
+        node_children(s.nodes[cur], q, lim, t, r);
+        if (t[0] != INFINITY) {
+          if (t[3] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[3]; ++sp; }
+          if (t[2] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[2]; ++sp; }
+          if (t[1] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[1]; ++sp; }
+          cur = r[0];
+          continue;
+        }
+      } else {
+        const int first = (~cur) >> 4, cnt = (~cur) & 15;
+        for (int i = first; i < first + cnt; ++i) {
+          const double t = rec_distance(s.trec[i], x, w);
+          if (t > smin && t < seg_cull(L, hi)) seg_insert(L, t, (kHitMesh << 28) | i);
+        }
+      }
+      if (sp == 0) break;
+      --sp;
+      cur = stk[sp * step];
+    }
+  }
+  return L;
 }
 
 // Unit face normal of leaf-order triangle i, from the current geometry.
@@ -288,6 +409,69 @@ __device__ __forceinline__ Glossy glossy_reflect(d3 d, const Coef& f, double rho
   o.ok = wh < 0.0 && co > 0.0;
   o.g = o.ok ? smith_g1(f.ci, rho) * smith_g1(co, rho) * (-wh) / (f.ci * ch) : 0.0;
   return o;
+}
+
+// Entry j of a crossing list (selects, so the list stays in registers).
+__device__ __forceinline__ void seg_get(const SegHits& L, int j, double* s, int* h) {
+  double sv = L.s[0];
+  int hv = L.h[0];
+#pragma unroll
+  for (int i = 1; i < kSegHits; ++i)
+    if (j == i) { sv = L.s[i]; hv = L.h[i]; }
+  *s = sv;
+  *h = hv;
+}
+
+// Straight march of a receiver segment from x along the unit direction w to
+// the point at distance r, starting in region reg: every crossed interface
+// in order (pressure transmission coefficient each, blocked on total
+// internal reflection), the travel time and the attenuation exponent summed
+// over the legs. on_cross(j, s_j, hit word, surface, coefficients) sees
+// crossing j (from 0) at distance s_j from x before its transmission is
+// applied. A segment with max_legs(s) crossings or more is blocked.
+struct March {
+  double tof;     // tof0 + sum over legs of length / c
+  double att;     // sum over legs of a * length
+  double trans;   // product of the transmission coefficients
+  int crossings;
+  bool reached;
+};
+
+template <bool kMeshes, class OnCross>
+__device__ __forceinline__ March receiver_march(const SceneLDS& S, d3 x, d3 w, double r, int reg,
+                                                double tof0, int* stk, OnCross on_cross) {
+  March m{tof0, 0.0, 1.0, 0, false};
+  const int legs = max_legs(S);
+  double lo = 0.0;   // distance of the last crossing taken
+  for (;;) {
+    const SegHits L = segment_hits<kMeshes>(S, x, w, lo, r, stk);
+    for (int j = 0; j < L.n; ++j) {
+      double sj;
+      int hw;
+      seg_get(L, j, &sj, &hw);
+      if (!(sj > lo + kTMin)) continue;   // the surface point just crossed (a shared edge)
+      const double ell = sj - lo;
+      m.tof += ell * S.ic[reg];
+      m.att += S.a[reg] * ell;
+      lo = sj;
+      const Hit h{hw >> 28, hw & 0x0FFFFFFF, sj};
+      const d3 p = x + w * sj;
+      const Surface sf = surface_of(S, h, p, reg);
+      const Coef g = coefficients(w, sf.n, S.c[reg], S.Z[reg], S.c[sf.other], S.Z[sf.other]);
+      on_cross(m.crossings, sj, hw, sf, g);
+      ++m.crossings;
+      if (g.tir) return m;
+      m.trans *= g.At;
+      reg = sf.other;
+      if (m.crossings >= legs) return m;
+    }
+    if (L.n < kSegHits) break;   // every crossing up to r was in the list
+  }
+  const double ell = r - lo;
+  m.tof += ell * S.ic[reg];
+  m.att += S.a[reg] * ell;
+  m.reached = true;
+  return m;
 }
 
 __device__ __forceinline__ double elem_x(const ProbeView& p, int e) {

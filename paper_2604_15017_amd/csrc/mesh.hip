@@ -271,7 +271,8 @@ __device__ __forceinline__ float round_up(double x) {
 }
 
 // Child boxes of the inner nodes [begin, end) of one depth: a leaf child's
-// from its triangles' current vertices (fp64, rounded outward to fp32), an
+// from its triangles' current vertices (fp64, padded by kBoxPad and rounded
+// outward to fp32), an
 // inner child's as the union of its own two boxes, which belong to a deeper
 // level and are already refitted.
 __device__ __forceinline__ void child_box(const BvhNode* nodes, int ref, const int4* tri,
@@ -302,7 +303,10 @@ __device__ __forceinline__ void child_box(const BvhNode* nodes, int ref, const i
         h[k] = fmax(h[k], c);
       }
   }
-  for (int k = 0; k < 3; ++k) { lo[k] = round_down(l[k]); hi[k] = round_up(h[k]); }
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = round_down(l[k] - (double)kBoxPad);
+    hi[k] = round_up(h[k] + (double)kBoxPad);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_refit(BvhNode* __restrict__ nodes, int begin, int end,

@@ -275,8 +275,8 @@ __device__ __forceinline__ double interface_backward(const Coef& f, double eta, 
 }
 
 // Crossings of a receiver segment remembered between the two passes of its
-// adjoint (in LDS, interleaved across the block's threads); further
-// crossings are found again.
+// adjoint (their distance from the segment's start and hit word, in LDS,
+// interleaved across the block's threads); further crossings are found again.
 constexpr int kLegCache = 8;
 
 struct ReplayCtx {
@@ -287,7 +287,7 @@ struct ReplayCtx {
   long row_base;        // (tx_base + txl) * n_elem
   GradAcc& G;
   int* stk;             // this thread's hierarchy stack in LDS
-  double* leg_t;        // this thread's crossing cache in LDS: distance ...
+  double* leg_t;        // this thread's crossing cache in LDS: distance from x ...
   int* leg_h;           // ... and kind << 28 | index
 };
 
@@ -313,42 +313,19 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   const double K = (kd / kPi) * P.elem_w * P.elem_h * (double)P.n_elem;
   const double amp0 = watt * f.Ar * (kd / kPi) * co * (P.elem_w * P.elem_h * cel / (r * r)) *
                       (double)P.n_elem * fd;
-  // pass 1: the march as the forward did it
-  const int legs = max_legs(S);
-  double tof = tp, rest = 1.0, att = 0.0;   // rest: transmissions, then times e^-att
-  int n_cross = 0;
-  {
-    d3 p = x;
-    double remaining = r;
-    int reg = region;
-    bool reached = false;
-    const int step = blockDim.x;
-    for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit<kMeshes>(S, p, we, false, C.stk, remaining);
-      if (h.kind == kHitNone || h.t >= remaining) {
-        tof += remaining * S.ic[reg];
-        att += S.a[reg] * remaining;
-        reached = true;
-        break;
-      }
-      if (leg < kLegCache) {
-        C.leg_t[leg * step] = h.t;
-        C.leg_h[leg * step] = (h.kind << 28) | h.index;
-      }
-      ++n_cross;
-      tof += h.t * S.ic[reg];
-      att += S.a[reg] * h.t;
-      remaining -= h.t;
-      p = p + we * h.t;
-      const Surface sf = surface_of(S, h, p, reg);
-      const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[sf.other], S.Z[sf.other]);
-      if (g.tir) return;   // blocked: no deposit
-      rest *= g.At;
-      reg = sf.other;
-    }
-    if (!reached) return;   // the forward dropped this deposit
-    rest *= exp(-att);      // the attenuation of all legs at once, as the forward
-  }
+  // pass 1: the march as the forward did it, its crossings cached in LDS
+  const int step = blockDim.x;
+  const March mr = receiver_march<kMeshes>(
+      S, x, we, r, region, tp, C.stk, [&](int j, double sj, int hw, const Surface&, const Coef&) {
+        if (j < kLegCache) {
+          C.leg_t[j * step] = sj;
+          C.leg_h[j * step] = hw;
+        }
+      });
+  if (!mr.reached) return;   // blocked: the forward dropped this deposit
+  const int n_cross = mr.crossings;
+  const double tof = mr.tof;
+  const double rest = mr.trans * exp(-mr.att);   // the attenuation of all legs at once, as the forward
   const double amp = amp0 * rest;
   double GA, GT;
   tent_adjoint(C.gh + (C.row_base + e2) * (long)P.n_t, P.n_t, P.fs, tof, amp, &GA, &GT);
@@ -364,36 +341,33 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   d3 webar{0, 0, 0}, xb{0, 0, 0};
   double rbar = 0.0;
   {
-    d3 p = x;
-    double remaining = r, s_cum = 0.0;
     int reg = region;
-    const int step = blockDim.x;
-    for (int leg = 0; leg < legs; ++leg) {
-      // the crossings of pass 1 in order, then the final stretch to the element
-      Hit h;
-      if (leg < kLegCache) {
-        if (leg < n_cross) {
-          const int id = C.leg_h[leg * step];
-          h = Hit{id >> 28, id & 0x0FFFFFFF, C.leg_t[leg * step]};
-        } else {
-          h = Hit{kHitNone, -1, 0.0};
-        }
-      } else {
-        h = closest_hit<kMeshes>(S, p, we, false, C.stk, remaining);
-      }
-      if (h.kind == kHitNone || h.t >= remaining) {
-        const double ell = remaining;   // = r - s_J
+    double s_prev = 0.0;
+    for (int leg = 0;; ++leg) {
+      if (leg == n_cross) {   // the final stretch to the element
+        const double ell = r - s_prev;
         C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
         C.G.a(reg, -AA * ell);
         rbar += GT / S.c[reg] - AA * S.a[reg];
         break;
       }
-      const double ell = h.t;
+      // crossing `leg`: cached by pass 1, or the nearest beyond the previous one
+      double sj;
+      int hw;
+      if (leg < kLegCache) {
+        sj = C.leg_t[leg * step];
+        hw = C.leg_h[leg * step];
+      } else {
+        const SegHits L = segment_hits<kMeshes>(S, x, we, s_prev, r, C.stk);
+        sj = L.s[0];
+        hw = L.h[0];
+      }
+      const Hit h{hw >> 28, hw & 0x0FFFFFFF, sj};
+      const double ell = sj - s_prev;
       C.G.c(reg, -GT * ell / (S.c[reg] * S.c[reg]));
       C.G.a(reg, -AA * ell);
-      s_cum += ell;
-      remaining -= ell;
-      p = p + we * ell;
+      s_prev = sj;
+      const d3 p = x + we * sj;
       const Surface sf = surface_of(S, h, p, reg);
       const int other = sf.other;
       const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[other], S.Z[other]);
@@ -412,13 +386,13 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
       normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, pbar, C.G, ta);
       // p_j = x + we s_j
       xb = xb + pbar;
-      webar = webar + pbar * s_cum;
+      webar = webar + pbar * sj;
       sbar += dot(pbar, we);
       // s_j as a function of (x, we): entering a sphere takes the near root
       double sig = -1.0;
       if (h.kind == kHitSphere) sig = (reg == S.sreg[h.index][1]) ? -1.0 : 1.0;
       if (h.kind == kHitCylinder) sig = (reg == S.creg[h.index][1]) ? -1.0 : 1.0;
-      distance_backward(S, h.kind, h.index, sig, x, we, s_cum, sbar, xb, webar, C.G, ta);
+      distance_backward(S, h.kind, h.index, sig, x, we, sj, sbar, xb, webar, C.G, ta);
       if (h.kind == kHitMesh) tri_nu_backward(S, h.index, ta.nub, ta.p0b, C.G);
       reg = other;
     }

@@ -205,7 +205,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 // Receiver-directed secondary rays spawned at interaction k: straight to the
 // element centre through every crossed interface (transmission coefficient
 // each, zero on total internal reflection), attenuation and travel time per
-// medium, then the deposit.
+// medium, then the deposit. The crossings of a segment come from one
+// hierarchy walk that keeps the nearest few (receiver_march).
 template <bool kAudit, bool kMeshes>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4 : 5, 8))) void k_secondary(TraceArgs a, int k) {
   const long n_in = (long)(a.counts[k] >> 32);
@@ -221,42 +222,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
     const d3 x{a.nee.x[i], a.nee.y[i], a.nee.z[i]};
     double tof = a.nee.t[i], amp = a.nee.amp[i];
     const uint32_t meta = a.nee.meta[i], txk = a.nee.txk[i];
-    int reg = meta & 0xFF;
+    const int reg = meta & 0xFF;
     const int e2 = (int)(meta >> 8);
     const int txl = (int)(txk & 0xFFFF);
     const d3 dv = d3{elem_x(P, e2), 0.0, 0.0} - x;
     const double r = sqrt(dot(dv, dv));
     const d3 we = dv * (1.0 / r);
-    d3 p = x;
-    double remaining = r, att = 0.0;   // att: sum of alpha times length over the legs
-    uint32_t crossings = 0;
-    bool blocked = true;
-    const int legs = max_legs(S);
-    for (int leg = 0; leg < legs; ++leg) {
-      const Hit h = closest_hit<kMeshes>(S, p, we, false, stk, remaining);
-      ++n_seg;
-      if (h.kind == kHitNone || h.t >= remaining) {
-        tof += remaining * S.ic[reg];
-        att += S.a[reg] * remaining;
-        blocked = false;
-        break;
-      }
-      tof += h.t * S.ic[reg];
-      att += S.a[reg] * h.t;
-      remaining -= h.t;
-      p = p + we * h.t;
-      const Surface sf = surface_of(S, h, p, reg);
-      const Coef g = coefficients(we, sf.n, S.c[reg], S.Z[reg], S.c[sf.other], S.Z[sf.other]);
-      ++crossings;
-      if (g.tir) break;
-      amp *= g.At;
-      reg = sf.other;
-    }
+    const March mr = receiver_march<kMeshes>(S, x, we, r, reg, tof, stk,
+                                             [](int, double, int, const Surface&, const Coef&) {});
+    n_seg += mr.reached ? mr.crossings + 1 : mr.crossings;   // one segment per leg
+    const uint32_t crossings = (uint32_t)mr.crossings;
+    const bool blocked = !mr.reached;
+    tof = mr.tof;
+    amp *= mr.trans;
     Deposit dp;
     bool rec = false;
     if (!blocked) {
       ++n_dep;
-      amp *= exp(-att);   // the attenuation of all legs at once
+      amp *= exp(-mr.att);   // the attenuation of all legs at once
       rec = make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, tof, amp, &dp);
     }
     // record for the binned splat (one atomic per wave on this block's shard
