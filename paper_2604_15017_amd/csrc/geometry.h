@@ -80,21 +80,25 @@ __device__ __forceinline__ void node_children(const BvhNode& n, const SlabRay& q
 #undef USRT_CX
 }
 
-// Closest triangle in (kTMin, best) by walking the 4-wide hierarchy near
-// child first. One step handles one inner node (its four child boxes tested
-// against the ray in fp32, the hit children ordered by entry distance: the
-// nearest is visited next, the others pushed farthest first) or one leaf
-// (its triangles intersected in fp64). The stack lives in LDS, interleaved
-// across the block's threads (entry i of this thread at stk[i * blockDim.x]);
-// it holds at most three entries per inner level.
-__device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, double& best, int& best_tri,
-                                             int* stk) {
-  const SlabRay q = slab_ray(o, d);
+// Walk of the 4-wide hierarchy near child first. An inner node's four child
+// boxes are tested against the ray in fp32 and the hit children ordered by
+// entry distance: the nearest is visited next, the others pushed farthest
+// first. The stack lives in LDS, interleaved across the block's threads
+// (entry i of this thread at stk[i * blockDim.x]); it holds at most three
+// entries per inner level. The walk alternates two phases so that the lanes
+// of a wave run one kind of work at a time (Aila and Laine, HPG 2009): inner
+// nodes until every lane holds a leaf (a lane that meets a leaf sets it aside
+// and keeps walking), then the leaves. cull() is the distance beyond which
+// boxes are skipped; leaf(first, count) tests a leaf's triangles.
+constexpr int kWalkDone = 0x7FFFFFFF;
+
+template <class Cull, class Leaf>
+__device__ __forceinline__ void walk4(const SceneLDS& s, const SlabRay& q, int* stk, Cull cull, Leaf leaf) {
   const int step = blockDim.x;
-  int sp = 0, cur = 0;
+  int sp = 0, cur = 0, pend = 0;   // pend: a leaf set aside (leaf references are negative), 0 if none
   for (;;) {
-    if (cur >= 0) {
-      const float lim = (float)best * 1.0001f + kBoxPad;
+    while ((unsigned)cur < (unsigned)kWalkDone) {   // an inner node
+      const float lim = cull() * 1.0001f + kBoxPad;
       float t[4];
       int r[4];
       node_children(s.nodes[cur], q, lim, t, r);
@@ -104,19 +108,36 @@ __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, doub
         if (t[2] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[2]; ++sp; }
         if (t[1] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[1]; ++sp; }
         cur = r[0];
-        continue;
+      } else {
+        cur = sp > 0 ? stk[--sp * step] : kWalkDone;
       }
-    } else {
-      const int first = (~cur) >> 4, cnt = (~cur) & 15;
-      for (int i = first; i < first + cnt; ++i) {
-        const double t = rec_distance(s.trec[i], o, d);
-        if (t > kTMin && t < best) { best = t; best_tri = i; }
+      if (cur < 0 && pend == 0) {   // set the leaf aside and walk on
+        pend = cur;
+        cur = sp > 0 ? stk[--sp * step] : kWalkDone;
+      }
+      if (__all(pend != 0)) break;
+    }
+    while (pend != 0) {
+      leaf((~pend) >> 4, (~pend) & 15);
+      pend = 0;
+      if (cur < 0) {   // the next reference is a leaf too
+        pend = cur;
+        cur = sp > 0 ? stk[--sp * step] : kWalkDone;
       }
     }
-    if (sp == 0) break;
-    --sp;
-    cur = stk[sp * step];
+    if (cur == kWalkDone) break;
   }
+}
+
+// Closest triangle in (kTMin, best): best and best_tri updated.
+__device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, double& best, int& best_tri,
+                                             int* stk) {
+  walk4(s, slab_ray(o, d), stk, [&]() { return (float)best; }, [&](int first, int cnt) {
+    for (int i = first; i < first + cnt; ++i) {
+      const double t = rec_distance(s.trec[i], o, d);
+      if (t > kTMin && t < best) { best = t; best_tri = i; }
+    }
+  });
 }
 
 // Closest surface along o + t d with kTMin < t < tmax among the planes, the
@@ -254,33 +275,12 @@ __device__ __forceinline__ SegHits segment_hits(const SceneLDS& s, d3 x, d3 w, d
     }
   }
   if (kMeshes && s.n_meshes > 0) {
-    const SlabRay q = slab_ray(x, w);
-    const int step = blockDim.x;
-    int sp = 0, cur = 0;
-    for (;;) {
-      if (cur >= 0) {
-        const float lim = (float)seg_cull(L, hi) * 1.0001f + kBoxPad;
-        float t[4];
-        int r[4];
-        node_children(s.nodes[cur], q, lim, t, r);
-        if (t[0] != INFINITY) {
-          if (t[3] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[3]; ++sp; }
-          if (t[2] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[2]; ++sp; }
-          if (t[1] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[1]; ++sp; }
-          cur = r[0];
-          continue;
-        }
-      } else {
-        const int first = (~cur) >> 4, cnt = (~cur) & 15;
-        for (int i = first; i < first + cnt; ++i) {
-          const double t = rec_distance(s.trec[i], x, w);
-          if (t > smin && t < seg_cull(L, hi)) seg_insert(L, t, (kHitMesh << 28) | i);
-        }
+    walk4(s, slab_ray(x, w), stk, [&]() { return (float)seg_cull(L, hi); }, [&](int first, int cnt) {
+      for (int i = first; i < first + cnt; ++i) {
+        const double t = rec_distance(s.trec[i], x, w);
+        if (t > smin && t < seg_cull(L, hi)) seg_insert(L, t, (kHitMesh << 28) | i);
       }
-      if (sp == 0) break;
-      --sp;
-      cur = stk[sp * step];
-    }
+    });
   }
   return L;
 }
