@@ -14,6 +14,10 @@ absolute 1e-9 for zero parameters): small enough that hardly any discrete
 choice (element under a returning ray, sphere hit or miss) flips and hardly any
 deposit crosses a sample boundary, large enough that FP64 cancellation stays
 far below the tolerance."""
+import dataclasses
+import multiprocessing as mp
+import os
+
 import numpy as np
 import pytest
 
@@ -94,3 +98,79 @@ def test_full_chain_gradient_matches_finite_differences():
         # kept small enough that no deposit crosses a sample boundary
         fd = _fd(L, theta, j, rel=1e-8)
         assert abs(fd - ad[j]) * unit[j] <= 1e-3 * abs(ad[j]) * unit[j] + 1e-6 * scale, (j, fd, ad[j])
+
+
+def _sweep_loss(args):
+    """B-mode MSE of the sweep's reduced phantom at theta (one FD evaluation,
+    single-threaded transport so that several run side by side)."""
+    wl, theta, probs, B_ref = args
+    return oracle.mse(oracle.render(wl, theta=theta, probs=probs, n_threads=1)["B"], B_ref)
+
+
+def test_fd_step_sweep_of_the_layered_image_loss():
+    """The forward+backward workload's own check on a reduced copy of its scene
+    (the layered phantom: its 34 perturbed parameters, the B-mode MSE in dB
+    against the image of the seeded +-5 % target; the 128 elements, two plane
+    waves, 16 rays per element, a 32 x 64 grid): dual-number gradients against central
+    differences at relative steps 1e-2 .. 1e-9, at fixed branch
+    probabilities, the paper's AD-versus-FD comparison. Every parameter whose
+    sensitivity (|dL/dtheta| |theta|) reaches 1e-3 of the largest agrees to
+    1e-3 relative at its best step, the others to 1e-6 of the largest
+    sensitivity; the table printed gives the error at each step, the
+    workload's stated step 1e-4 among them (there sound-speed and geometry
+    moves shift path times by a fraction of a sample and cross the tent's
+    kinks, so the error there is larger than at the best step). A large step
+    can also send a ray along a path it did not take at theta, whose branch
+    probabilities were never recorded: that difference reads NaN and counts
+    as no agreement at that step. Most of the deep layers' and the spheres'
+    parameters barely move this small image (sensitivities near 1e-11 of the
+    largest: their echoes lie below the 60 dB range or are missed by so few
+    rays), and the 1e-6 bound is all the differences can resolve there."""
+    base = W.layered_phantom()
+    probe = dataclasses.replace(base.probe, n_elem=128)
+    wl = base.replace(probe=probe, rays_per_elem=16, angles=np.radians([-6.0, 6.0]),
+                      tx_ids=np.arange(2, dtype=np.uint32),
+                      grid=W.Grid.span(32, 64, -19.2e-3, 19.2e-3, 0.0, 60e-3))
+    target = W.layered_phantom_target(wl)
+    B_ref = oracle.render(wl, theta=target.theta())["B"]
+    theta = wl.scene.theta()
+    idx = list(W.perturbed_indices(wl.scene))
+    ad = oracle.grad_theta(wl, B_ref, theta=theta, grad_params=idx)["g_theta"]
+    probs = oracle.render(wl, theta=theta, record_probs=True)["trace"].probs
+    steps = [1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9]
+    jobs = []
+    for j in idx:
+        for rel in steps:
+            h = rel * abs(theta[j])
+            tp, tm = theta.copy(), theta.copy()
+            tp[j] += h
+            tm[j] -= h
+            jobs += [(wl, tp, probs, B_ref), (wl, tm, probs, B_ref)]
+    with mp.get_context("fork").Pool(min(8, len(os.sched_getaffinity(0)))) as pool:
+        vals = pool.map(_sweep_loss, jobs, chunksize=4)
+    unit = np.abs(theta)                       # sensitivities per relative change
+    sens = np.abs(ad[idx]) * unit[idx]
+    k = 0
+    rows = []
+    for n, j in enumerate(idx):
+        errs = []
+        for rel in steps:
+            h = rel * abs(theta[j])
+            fd = (vals[k] - vals[k + 1]) / (2 * h)
+            k += 2
+            errs.append(abs(fd - ad[j]) / max(abs(ad[j]), 1e-300))
+        errs = [e if np.isfinite(e) else np.inf for e in errs]
+        rows.append(errs)
+        if sens[n] >= 1e-3 * sens.max():
+            assert min(errs) <= 1e-3, (j, errs)
+        else:
+            assert min(errs) * sens[n] <= 1e-6 * sens.max(), (j, errs)
+    print("parameter  |AD| x |theta|  |FD - AD| / |AD| at relative steps " + " ".join(f"{s:.0e}" for s in steps))
+    for n, j in enumerate(idx):
+        print(f"{j:9d}  {sens[n]:.3e}  " + " ".join(f"{e:.1e}" for e in rows[n]), flush=True)
+    at_1e4 = np.array([r[2] for n, r in enumerate(rows) if sens[n] >= 1e-3 * sens.max()])
+    best = np.array([min(r) for n, r in enumerate(rows) if sens[n] >= 1e-3 * sens.max()])
+    print(f"{len(at_1e4)} sensitive parameters: at h = 1e-4 median {np.median(at_1e4):.1e}, "
+          f"{np.sum(at_1e4 <= 1e-3)} within 1e-3; at the best step worst {best.max():.1e}", flush=True)
+
+
