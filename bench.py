@@ -56,7 +56,11 @@ def kernel_bytes(name, wl, counts, n_px):
         # kernel adds directly, so these are upper bounds on the records.
         "splat_bin": None if has_meshes else (4 + 12 + 16) * dep,
         "splat_accumulate": None if has_meshes else 16 * dep + 8 * row_samples,
-        "pulse": 8 * row_samples,
+        # the last chunk's deposits (16-byte records), the fixed-point row of
+        # direct deposits read, the RF written
+        "splat_pulse": None if has_meshes else 16 * dep + (8 + 4) * row_samples,
+        # the fixed-point histogram read, the RF written
+        "pulse": 12 * row_samples,
         "pulse_adjoint": 8 * row_samples,
         "analytic_adjoint": 12 * row_samples,
         "das_adjoint": 8 * row_samples + 8 * n_px,
@@ -348,6 +352,7 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
                                                             wl.max_bounces), dev)
     ws_bv = L._workspace(L.load().us_beamform_vjp_workspace_size(probe.handle, wl.n_tx), dev)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
+    ws_l = L._workspace(L.load().us_image_loss_workspace_size(g.n_px), dev)
     g_b = torch.empty_like(bm)
     g_iq = torch.empty_like(iq)
     g_rf = torch.empty_like(rf)
@@ -355,7 +360,7 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
 
     def step_fb():
         step()
-        L.us_image_loss(ctx, bm, b_ref, 0.0, 1.0, loss=loss, g_bmode=g_b, stream=stream)
+        L.us_image_loss(ctx, bm, b_ref, 0.0, 1.0, loss=loss, g_bmode=g_b, workspace=ws_l, stream=stream)
         L.us_bmode_vjp(ctx, iq, g_b, wl.dr_db, g_iq=g_iq, workspace=ws_m, stream=stream)
         L.us_beamform_vjp(ctx, probe, g, wl.angles, wl.tx_ids, g_iq, g_rf=g_rf, workspace=ws_bv,
                           stream=stream)

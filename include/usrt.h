@@ -191,8 +191,11 @@ int us_bmode(us_ctx* ctx, const float* iq_dev, int64_t n_px, float dr_db, float*
 /* Image-space loss (Sec. 3.5, Eq. weighted_l1_l2_loss):
  * L = (1/n_px) sum_u [lambda1 |B_u - R_u| + lambda2 (B_u - R_u)^2]; the mean
  * squared error is lambda1 = 0, lambda2 = 1.
- *   loss_dev out: double [1] (overwritten)
- *   g_bmode_dev optional out (NULL): float [n_px], dL/dB (sign(0) = 0) */
+ *   loss_dev out: double [1] (overwritten); summed in integer windows, so
+ *     the value does not depend on the order in which blocks finish
+ *   g_bmode_dev optional out (NULL): float [n_px], dL/dB (sign(0) = 0)
+ *   ws_dev: device workspace of us_image_loss_workspace_size(n_px) bytes
+ *     (US_ETOOBIG if smaller, US_EINVAL if NULL) */
 size_t us_image_loss_workspace_size(int64_t n_px);
 int us_image_loss(us_ctx* ctx, const float* bmode_dev, const float* ref_dev, int64_t n_px,
                   double lambda1, double lambda2, double* loss_dev, float* g_bmode_dev,

@@ -369,10 +369,13 @@ def us_bmode(ctx: Context, iq, dr_db: float, out=None, workspace=None, stream=No
 
 
 def us_image_loss(ctx: Context, bmode, ref, lambda1: float = 0.0, lambda2: float = 1.0,
-                  loss=None, g_bmode=None, want_grad: bool = True, stream=None):
+                  loss=None, g_bmode=None, want_grad: bool = True, workspace=None, stream=None):
     """Returns (loss as a 1-element float64 device tensor, dL/dB or None)."""
     torch = _torch()
     n_px = bmode.numel()
+    if workspace is None:
+        workspace = _workspace(load().us_image_loss_workspace_size(n_px), ctx.torch_device)
+    _expect_ws(workspace)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=ctx.torch_device)
     if want_grad and g_bmode is None:
@@ -384,7 +387,7 @@ def us_image_loss(ctx: Context, bmode, ref, lambda1: float = 0.0, lambda2: float
         _expect(g_bmode, n_px, torch.float32, "g_bmode")
     _check(load().us_image_loss(ctx.handle, _ptr(bmode), _ptr(ref), n_px, float(lambda1),
                                 float(lambda2), _ptr(loss), _ptr(g_bmode if want_grad else None),
-                                ctypes.c_void_p(0), 0, _stream(stream)), "us_image_loss")
+                                _ptr(workspace), workspace.numel(), _stream(stream)), "us_image_loss")
     return loss, (g_bmode if want_grad else None)
 
 

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "fir.h"
 #include "kernels.h"
 
 using namespace usrt;
@@ -492,8 +493,8 @@ int bin_rows(int n_tx, const us_probe* p) {
 
 size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {
   Carver c{nullptr};
-  c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
-  c.take<unsigned long long>((size_t)max_bounces + 4 + kDepShards);
+  c.take<long long>((size_t)n_tx * p->d.n_elem * p->d.n_t);
+  c.take<unsigned long long>((size_t)max_bounces + 5 + kDepShards);
   const int rows = bin_rows(n_tx, p);
   if (rows > 0) c.take<char>(splat_scratch_bytes(rows));
   return c.off;
@@ -525,23 +526,33 @@ constexpr long kReplayChunk = 1L << 23;
 // Vertex adjoints per copy, rounded up to 256 bytes.
 long vadj_stride(const us_scene* scene) { return ((long)scene->mesh.n_vertices + 32) & ~31L; }
 
-// Workspace of the replay backward for chunks of `cap` rays: dL/dh, the mesh
-// vertex adjoints, the per-block gradient rows, the step records, the queue
-// of diffuse interactions with its step offsets, the per-step counts and the
-// two live-ray queues.
+// Workspace of the replay backward for chunks of `cap` rays: dL/dh (and its
+// f0 rows), the accumulators of the gradient, of the acquisition parameters
+// and of the mesh vertex adjoints with the vertex totals, the step records,
+// the queue of diffuse interactions with its step offsets, the per-step
+// counts and the two live-ray queues.
+struct ReplaySums {
+  unsigned long long* g_sum = nullptr;
+  unsigned long long* acq_sum = nullptr;
+  unsigned long long* vadj = nullptr;
+  double* vval = nullptr;
+};
+
 size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_bounces, long cap,
                     ReplayStack* k = nullptr, char* base = nullptr, float** gh = nullptr,
-                    float** gh_f0 = nullptr, double** vadj = nullptr, double** g_part = nullptr, RayQueue* q0 = nullptr,
+                    float** gh_f0 = nullptr, ReplaySums* sums = nullptr, RayQueue* q0 = nullptr,
                     RayQueue* q1 = nullptr, unsigned long long** counts = nullptr) {
   Carver c{base};
   float* g = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   if (gh) *gh = g;
   float* gf = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   if (gh_f0) *gh_f0 = gf;
-  double* va = c.take<double>((size_t)kVadjCopies * vadj_stride(scene));
-  if (vadj) *vadj = va;
-  double* gp = c.take<double>((size_t)kMaxReplayBlocks * scene->q_offset);
-  if (g_part) *g_part = gp;
+  ReplaySums tmp_sums;
+  ReplaySums& sm = sums ? *sums : tmp_sums;
+  sm.g_sum = c.take<unsigned long long>((size_t)std::max(1, scene->q_offset) * kSumWords);
+  sm.acq_sum = c.take<unsigned long long>((size_t)(n_tx + 3) * kSumWords);
+  sm.vadj = c.take<unsigned long long>((size_t)kVadjCopies * vadj_stride(scene) * kSumWords);
+  sm.vval = c.take<double>((size_t)vadj_stride(scene));
   ReplayStack tmp;
   ReplayStack& r = k ? *k : tmp;
   const size_t n = (size_t)cap * (max_bounces + 1);
@@ -621,8 +632,9 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   hipStream_t s = (hipStream_t)stream;
   const us_probe_desc& pd = probe->d;
   Carver c{(char*)ws_dev};
-  float* h = c.take<float>((size_t)n_tx * pd.n_elem * pd.n_t);
-  unsigned long long* counts = c.take<unsigned long long>((size_t)max_bounces + 4 + kDepShards);
+  long long* h = c.take<long long>((size_t)n_tx * pd.n_elem * pd.n_t);
+  // per-bounce counts, the deposit-shard counts, the histogram's overflow count
+  unsigned long long* counts = c.take<unsigned long long>((size_t)max_bounces + 5 + kDepShards);
   const int rows = bin_rows(n_tx, probe);
   void* bin_scratch = rows > 0 ? (void*)c.take<char>(splat_scratch_bytes(rows)) : nullptr;
   TraceArgs a{};
@@ -647,12 +659,16 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   a.ray_count = ray_count;
   a.counts = counts;
   a.h = h;
+  a.hist_scale = hist_scale(rays_per_elem);
+  a.hist_over = counts + max_bounces + 4 + kDepShards;
   a.counters = (unsigned long long*)counters_dev;
   a.hash = (unsigned long long*)ray_hash_dev;
   const bool audit = ray_hash_dev != nullptr;
-  launch_fill_u32((uint32_t*)h, (long)n_tx * pd.n_elem * pd.n_t, 0u, s);
+  launch_fill_u32((uint32_t*)h, 2L * n_tx * pd.n_elem * pd.n_t, 0u, s);
+  launch_fill_u32((uint32_t*)a.hist_over, 2, 0u, s);
   if (audit) launch_fill_u32((uint32_t*)ray_hash_dev, 2L * n_tx * ray_count, 0u, s);
-  for (int t0 = 0; t0 < n_tx && ray_count > 0; t0 += kMaxTxPerLaunch) {
+  if (probe->M > kMaxTaps - 1) return fail(US_EINVAL, "us_simulate_rf: pulse too long");
+  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
     const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
     fill_tx(a.tx, tx, t0, ng);
     a.tx_base = t0;
@@ -662,6 +678,7 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
     // whose walk-bound secondary kernel hides global atomics into h
     a.dep_cap = (bin_scratch && n_rows <= rows && scene->n_meshes == 0) ? kDepositsPerRay * cap : 0;
     a.dep.row0 = (uint32_t)t0 * (uint32_t)pd.n_elem;
+    bool filtered = false;   // the group's RF rows are written
     for (long g0 = 0; g0 < total; g0 += cap) {
       const long n = std::min(cap, total - g0);
       a.g0 = g0;
@@ -685,15 +702,25 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
           Timed tm(ctx, "splat_bin", s);
           launch_splat_bin(a.dep, a.dep_count, a.dep_cap / kDepShards, n_rows, sorted, bin_scratch, s);
         }
-        Timed tm(ctx, "splat_accumulate", s);
-        launch_splat_accumulate(sorted, bin_scratch, a.dep.row0, n_rows, pd.n_t, h, s);
+        // the group's last chunk: its deposits, the row of h and the pulse in
+        // one pass; earlier chunks add their deposits to h
+        if (g0 + n >= total) {
+          Timed tm(ctx, "splat_pulse", s);
+          filtered = launch_splat_pulse(sorted, bin_scratch, a.dep.row0, n_rows, pd.n_t, h, a.hist_scale,
+                                        a.hist_over, probe->taps, probe->M, rf_dev, s) == 0;
+        }
+        if (!filtered) {
+          Timed tm(ctx, "splat_accumulate", s);
+          launch_splat_accumulate(sorted, bin_scratch, a.dep.row0, n_rows, pd.n_t, h, a.hist_scale, a.hist_over, s);
+        }
       }
     }
-  }
-  {
-    Timed tm(ctx, "pulse", s);
-    if (launch_pulse(h, rf_dev, probe->taps, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
-      return fail(US_EINVAL, "us_simulate_rf: pulse too long");
+    if (!filtered) {
+      const long r0 = (long)t0 * pd.n_elem;
+      Timed tm(ctx, "pulse", s);
+      launch_pulse_fixed(h + r0 * pd.n_t, a.hist_scale, a.hist_over, rf_dev + r0 * pd.n_t, probe->taps, probe->M,
+                         pd.n_t, n_rows, s);
+    }
   }
   US_HIP(hipGetLastError());
   return US_OK;
@@ -791,9 +818,10 @@ int us_bmode_vjp(us_ctx* ctx, const float* iq_dev, const float* g_bmode_dev, int
   US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   unsigned long long* key = (unsigned long long*)ws_dev;
-  double* sum = (double*)((char*)ws_dev + kAlign);
+  unsigned long long* sum = (unsigned long long*)((char*)ws_dev + kAlign);
+  static_assert(kSumWords * 8 <= kAlign, "bmode workspace layout");
   launch_fill_u32((uint32_t*)key, 2, 0u, s);
-  launch_fill_u32((uint32_t*)sum, 2, 0u, s);
+  launch_fill_u32((uint32_t*)sum, 2 * kSumWords, 0u, s);
   {
     Timed tm(ctx, "bmode_vjp", s);
     launch_env_max((const float2*)iq_dev, n_px, key, s);
@@ -812,15 +840,17 @@ size_t us_image_loss_workspace_size(int64_t n_px) {
 int us_image_loss(us_ctx* ctx, const float* bmode_dev, const float* ref_dev, int64_t n_px,
                   double lambda1, double lambda2, double* loss_dev, float* g_bmode_dev,
                   void* ws_dev, size_t ws_bytes, void* stream) {
-  (void)ws_dev; (void)ws_bytes;
-  US_CHECK(ctx && bmode_dev && ref_dev && loss_dev, "us_image_loss: NULL argument");
+  US_CHECK(ctx && bmode_dev && ref_dev && loss_dev && ws_dev, "us_image_loss: NULL argument");
+  if (ws_bytes < us_image_loss_workspace_size(n_px)) return fail(US_ETOOBIG, "us_image_loss: workspace too small");
   US_CHECK(n_px >= 1, "us_image_loss: n_px must be >= 1");
   US_CHECK(lambda1 >= 0 && lambda2 >= 0, "us_image_loss: weights must be non-negative");
   US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   Timed tm(ctx, "image_loss", s);
-  launch_fill_u32((uint32_t*)loss_dev, 2, 0u, s);
-  launch_image_loss(bmode_dev, ref_dev, n_px, lambda1, lambda2, loss_dev, g_bmode_dev, s);
+  unsigned long long* acc = (unsigned long long*)ws_dev;
+  static_assert(kSumWords * 8 <= kAlign, "loss workspace layout");
+  launch_fill_u32((uint32_t*)acc, 2 * kSumWords, 0u, s);
+  launch_image_loss(bmode_dev, ref_dev, n_px, lambda1, lambda2, acc, loss_dev, g_bmode_dev, s);
   US_HIP(hipGetLastError());
   return US_OK;
 }
@@ -933,11 +963,16 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   float* gh = nullptr;
   float* gh_f0 = nullptr;
   RayQueue q0, q1;
-  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &a.vadj, &a.g_part,
-               &q0, &q1, &a.counts);
+  ReplaySums sums;
+  replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &sums, &q0, &q1,
+               &a.counts);
+  a.vadj = sums.vadj;
+  a.g_sum = sums.g_sum;
+  a.acq_sum = sums.acq_sum;
   a.vadj_stride = vadj_stride(scene);
-  if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2L * kVadjCopies * a.vadj_stride, 0u, s);
-  launch_fill_u32((uint32_t*)a.g_part, 2L * kMaxReplayBlocks * scene->q_offset, 0u, s);
+  if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2L * kVadjCopies * a.vadj_stride * kSumWords, 0u, s);
+  launch_fill_u32((uint32_t*)a.g_sum, 2L * std::max(1, scene->q_offset) * kSumWords, 0u, s);
+  if (g_acq_dev) launch_fill_u32((uint32_t*)a.acq_sum, 2L * (n_tx + 3) * kSumWords, 0u, s);
   {
     Timed tm(ctx, "pulse_adjoint", s);
     if (launch_pulse_adjoint(g_rf_dev, gh, probe->taps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
@@ -956,9 +991,7 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   a.ray_count = ray_count;
   a.n_params = scene->n_params;
   a.n_grad = scene->q_offset;
-  a.grad_copies = 16;   // keep the copies within 16 KB of LDS
-  while (a.grad_copies > 1 && (size_t)a.grad_copies * ((a.n_grad + 1) & ~1) * sizeof(double) > 16384)
-    a.grad_copies >>= 1;
+  a.grad_copies = 1;   // each launcher sets the copies its kernel's LDS allows
   a.gh = gh;
   a.cap = cap;
   a.g_acq = g_acq_dev;
@@ -993,13 +1026,13 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
     }
   }
   // f0 also scales every region's amplitude attenuation a_r = alpha_r np_per_m,
-  // so the reduce adds sum_r alpha_r dL/dalpha_r / f0 to the f0 entry
-  launch_grad_reduce(a.g_part, a.n_grad, g_theta_dev, g_acq_dev ? g_acq_dev + n_tx + 2 : nullptr,
-                     a.scene.theta, scene->n_regions, 1.0 / pd.f0, s);
+  // so the f0 entry takes sum_r alpha_r dL/dalpha_r / f0 besides
+  launch_grad_finish(a.g_sum, a.n_grad, g_theta_dev, a.acq_sum, n_tx + 3, g_acq_dev, n_tx + 2, a.scene.theta,
+                     scene->n_regions, 1.0 / pd.f0, s);
   if (scene->n_meshes > 0) {
     Timed tm(ctx, "basis_gather", s);
-    launch_basis_gather(a.vadj, a.vadj_stride, scene->mesh.vbasis, scene->mesh.vbeg, scene->n_meshes, scene->n_basis,
-                        g_theta_dev + scene->q_offset, s);
+    launch_basis_gather(a.vadj, a.vadj_stride, scene->mesh.n_vertices, sums.vval, scene->mesh.vbasis,
+                        scene->mesh.vbeg, scene->n_meshes, scene->n_basis, g_theta_dev + scene->q_offset, s);
   }
   US_HIP(hipGetLastError());
   return US_OK;

@@ -354,7 +354,7 @@ constexpr int kSumWords = kSumBins + 1;       // the windows, then the overflow 
 
 struct SumPieces { int b; unsigned long long hi, lo; bool over; };
 
-__device__ __forceinline__ bool sum_pieces(double v, SumPieces* p) {
+__host__ __device__ __forceinline__ bool sum_pieces(double v, SumPieces* p) {
   if (v == 0.0) return false;
   const double a = fabs(v);
   int e;
@@ -386,7 +386,7 @@ __device__ __forceinline__ void sum_add(unsigned long long* acc, double v) {
 }
 
 // The accumulated total: the windows added in a fixed order.
-__device__ __forceinline__ double sum_value(const unsigned long long* acc) {
+__host__ __device__ __forceinline__ double sum_value(const unsigned long long* acc) {
   if (acc[kSumBins]) return __builtin_nan("");
   double r = 0.0;
   for (int b = 0; b < kSumBins; ++b) {
@@ -408,11 +408,38 @@ struct DepositList {
   uint32_t row0;
 };
 
-// Adds a deposit straight into the histogram with global atomics.
-__device__ __forceinline__ void add_deposit(float* h, int n_t, const Deposit& d) {
-  float* r = h + (long)d.row * n_t;
-  if (d.j0 >= 0) unsafeAtomicAdd(r + d.j0, d.w0);
-  if (d.j0 + 1 < n_t) unsafeAtomicAdd(r + d.j0 + 1, d.w1);
+// The deposit histogram is fixed point: a bin holds an int64 count of units
+// of 1/scale, so that sums of deposits added by many threads in any order
+// are the same integers. A tent weight is rounded to fp32 first and then to
+// the nearest unit (the same rounding whether it is recorded for the binned
+// splat or added at once). hist_scale puts the weight of one emitted ray,
+// 1/rays_per_elem, at 2^40 units or more (a power of two, so the read-out
+// divides exactly); a single weight beyond kHistMaxUnits units (2^12 and more
+// emitted-ray weights) is clamped and counted in the overflow word, and the
+// RF rows then read NaN.
+constexpr double kHistMaxUnits = 4503599627370496.0;   // 2^52
+
+inline double hist_scale(int rays_per_elem) {
+  int e = 0;
+  while ((1L << e) < (long)rays_per_elem) ++e;
+  return ldexp(1.0, 40 + e);
+}
+
+__device__ __forceinline__ long long hist_units(float w, double scale, unsigned long long* over) {
+  double x = (double)w * scale;
+  if (!(fabs(x) <= kHistMaxUnits)) {   // also NaN
+    atomicAdd(over, 1ull);
+    x = x > 0.0 ? kHistMaxUnits : -kHistMaxUnits;
+  }
+  return (long long)rint(x);
+}
+
+// Adds a deposit straight into the histogram with global integer atomics.
+__device__ __forceinline__ void add_deposit(long long* h, int n_t, const Deposit& d, double scale,
+                                            unsigned long long* over) {
+  unsigned long long* r = (unsigned long long*)(h + (long)d.row * n_t);
+  if (d.j0 >= 0) atomicAdd(r + d.j0, (unsigned long long)hist_units(d.w0, scale, over));
+  if (d.j0 + 1 < n_t) atomicAdd(r + d.j0 + 1, (unsigned long long)hist_units(d.w1, scale, over));
 }
 
 }  // namespace usrt

@@ -285,10 +285,18 @@ __device__ __forceinline__ DasWindow das_window(const ProbeView& p, const TxTabl
   return DasWindow{((long)(tx_base + i) * p.n_elem + e) * p.n_t, (int)lo, hi >= lo ? (int)(hi - lo) + 1 : 0};
 }
 
+// Tile order: the chip deals consecutive blocks round-robin to its kXcds
+// XCDs, each with its own L2. Block b runs tile L = (b % kXcds) per_xcd +
+// b / kXcds of the x-fastest tile order, so each XCD owns a contiguous band
+// of depths and the tiles it runs at one time are x-neighbours at the same
+// depths, which read nearly the same sample windows of every pair: the
+// windows come from HBM about once and are shared in that XCD's L2.
+constexpr int kXcds = 8;
+
 template <int kS>
 __global__ __launch_bounds__(kDasThreads * kS) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq, ProbeView p, GridView g, TxTable tx,
-                 int n_tx, int tx_base, int accumulate, int tiles_z) {
+                 int n_tx, int tx_base, int accumulate, int tiles_x, int tiles_z) {
   __shared__ float2 win[kS][2][kDasGroup * kDasSpan];
   __shared__ DasWindow wb[kS][3][kDasGroup];
   __shared__ int wide[kS][3];   // the group is partial or has a window wider than kDasSpan or under 2
@@ -296,7 +304,10 @@ void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq, ProbeVie
   // kS slices of kDasThreads threads share the tile: slice sl takes the
   // sl-th run of pair groups, and the partial sums are added in slice order
   const int sl = (int)threadIdx.x / kDasThreads, tid = (int)threadIdx.x % kDasThreads;
-  const int a0 = (blockIdx.x / tiles_z) * kDasTx, b0 = (blockIdx.x % tiles_z) * kDasTz;
+  const int n_tiles = tiles_x * tiles_z, per_xcd = (n_tiles + kXcds - 1) / kXcds;
+  const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (tile >= n_tiles) return;   // the whole block: the last band is short
+  const int a0 = (tile % tiles_x) * kDasTx, b0 = (tile / tiles_x) * kDasTz;
   const int ia = tid / kDasTz, ib = tid % kDasTz;
   const int a = a0 + ia, b = b0 + ib;
   const bool inside = a < g.n_x && b < g.n_z;
@@ -493,15 +504,25 @@ __global__ __launch_bounds__(256) void k_bmode(const float2* __restrict__ iq, lo
   }
 }
 
+// Sum of the block's per-thread values in a fixed tree (256 threads).
+__device__ __forceinline__ double block_sum256(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  return red[0];
+}
+
 // g_I = g_B (20/ln10) I / |I|^2 on unclipped pixels; the sum of g_B over
-// them feeds the normalisation term added at the arg-max pixel afterwards.
+// them (block sums added to the order-independent accumulator sum[kSumWords])
+// feeds the normalisation term added at the arg-max pixel afterwards.
 __global__ __launch_bounds__(256) void k_bmode_vjp(const float2* __restrict__ iq,
                                                    const float* __restrict__ gb, long n, float dr,
-                                                   const unsigned long long* key, double* sum,
+                                                   const unsigned long long* key, unsigned long long* sum,
                                                    float2* __restrict__ giq) {
-  __shared__ double bsum;
-  if (threadIdx.x == 0) bsum = 0.0;
-  __syncthreads();
   const float m2 = key_power(*key);
   double local = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -516,17 +537,16 @@ __global__ __launch_bounds__(256) void k_bmode_vjp(const float2* __restrict__ iq
     }
     giq[i] = gi;
   }
-  atomicAdd(&bsum, local);
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(sum, bsum);
+  const double bs = block_sum256(local);
+  if (threadIdx.x == 0) sum_add(sum, bs);
 }
 
 __global__ void k_bmode_vjp_fix(const float2* __restrict__ iq, const unsigned long long* key,
-                                const double* sum, float2* giq) {
+                                const unsigned long long* sum, float2* giq) {
   const long am = key_index(*key);
   const float m2 = key_power(*key);
   const float2 v = iq[am];
-  const float s = (float)(-kDbPerNeper * *sum / (double)m2);
+  const float s = (float)(-kDbPerNeper * sum_value(sum) / (double)m2);
   giq[am].x += s * v.x;
   giq[am].y += s * v.y;
 }
@@ -785,13 +805,12 @@ __global__ __launch_bounds__(256) void k_acq_reduce(const double* __restrict__ p
 }
 
 // L = (1/n) sum [l1 |d| + l2 d^2], d = B - R; dL/dB = (l1 sign(d) + 2 l2 d) / n.
+// Block sums go into the order-independent accumulator acc[kSumWords];
+// k_loss_finish writes the total.
 __global__ __launch_bounds__(256) void k_image_loss(const float* __restrict__ b,
                                                     const float* __restrict__ ref, long n,
-                                                    double l1, double l2, double* loss,
+                                                    double l1, double l2, unsigned long long* acc,
                                                     float* __restrict__ gb) {
-  __shared__ double bsum;
-  if (threadIdx.x == 0) bsum = 0.0;
-  __syncthreads();
   const double inv_n = 1.0 / (double)n;
   double local = 0.0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -802,10 +821,11 @@ __global__ __launch_bounds__(256) void k_image_loss(const float* __restrict__ b,
       gb[i] = (float)((l1 * sg + 2.0 * l2 * d) * inv_n);
     }
   }
-  atomicAdd(&bsum, local * inv_n);
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, bsum);
+  const double bs = block_sum256(local);
+  if (threadIdx.x == 0) sum_add(acc, bs * inv_n);
 }
+
+__global__ void k_loss_finish(const unsigned long long* acc, double* loss) { *loss = sum_value(acc); }
 
 int grid_for(long n, int per_block, int cap) {
   long gsz = (n + per_block - 1) / per_block;
@@ -852,12 +872,13 @@ void launch_das(const float2* A, float2* iq, const ProbeView& p, const GridView&
   if (tiles >= kDasMinTiles) {
     // grids of fewer than 1024 tiles split each tile's pairs over two slices
     // of one block, so that the chip still holds four waves per SIMD
+    const unsigned blocks = (unsigned)(kXcds * ((tiles + kXcds - 1) / kXcds));
     if (tiles < kDasSliceTiles)
-      hipLaunchKernelGGL(k_das_tiled<2>, dim3((unsigned)tiles), dim3(2 * kDasThreads), 0, s, A, iq, p, g, tx,
-                         n_tx_group, tx_base, accumulate ? 1 : 0, tiles_z);
+      hipLaunchKernelGGL(k_das_tiled<2>, dim3(blocks), dim3(2 * kDasThreads), 0, s, A, iq, p, g, tx,
+                         n_tx_group, tx_base, accumulate ? 1 : 0, tiles_x, tiles_z);
     else
-      hipLaunchKernelGGL(k_das_tiled<1>, dim3((unsigned)tiles), dim3(kDasThreads), 0, s, A, iq, p, g, tx,
-                         n_tx_group, tx_base, accumulate ? 1 : 0, tiles_z);
+      hipLaunchKernelGGL(k_das_tiled<1>, dim3(blocks), dim3(kDasThreads), 0, s, A, iq, p, g, tx,
+                         n_tx_group, tx_base, accumulate ? 1 : 0, tiles_x, tiles_z);
   } else {
     const long n_px = (long)g.n_x * g.n_z;
     hipLaunchKernelGGL(k_das_gather, dim3((unsigned)((n_px + 255) / 256)), dim3(256), 0, s, A, iq, p, g, tx,
@@ -876,13 +897,13 @@ void launch_bmode(const float2* iq, long n_px, float dr_db, const unsigned long 
 }
 
 void launch_bmode_vjp(const float2* iq, const float* g_b, long n_px, float dr_db,
-                      const unsigned long long* key, double* sum, float2* g_iq, hipStream_t s) {
+                      const unsigned long long* key, unsigned long long* sum, float2* g_iq, hipStream_t s) {
   hipLaunchKernelGGL(k_bmode_vjp, dim3(grid_for(n_px, 256, 1024)), dim3(256), 0, s, iq, g_b, n_px,
                      dr_db, key, sum, g_iq);
 }
 
 void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long* key,
-                          const double* sum, float2* g_iq, hipStream_t s) {
+                          const unsigned long long* sum, float2* g_iq, hipStream_t s) {
   (void)n_px;
   hipLaunchKernelGGL(k_bmode_vjp_fix, dim3(1), dim3(1), 0, s, iq, key, sum, g_iq);
 }
@@ -942,9 +963,10 @@ int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps_revers
 }  // namespace usrt
 
 namespace usrt {
-void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2, double* loss,
-                       float* gb, hipStream_t s) {
+void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2,
+                       unsigned long long* acc, double* loss, float* gb, hipStream_t s) {
   hipLaunchKernelGGL(k_image_loss, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, b, ref, n, l1, l2,
-                     loss, gb);
+                     acc, gb);
+  hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(1), 0, s, acc, loss);
 }
 }  // namespace usrt

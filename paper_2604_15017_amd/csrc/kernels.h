@@ -39,7 +39,9 @@ struct TraceArgs {
   // counts[k], k = 1..max_bounces + 1: rays alive after interaction k (low 32
   // bits) and secondary rays spawned at interaction k (high 32 bits)
   unsigned long long* counts;
-  float* h;               // deposit histogram [n_tx][n_elem][n_t]
+  long long* h;           // deposit histogram [n_tx][n_elem][n_t], units of 1 / hist_scale
+  double hist_scale;
+  unsigned long long* hist_over;   // count of clamped deposit weights
   // deposits of the secondary rays recorded for the binned splat in
   // kDepShards shards of dep_cap / kDepShards records (shard = block index
   // mod kDepShards, count dep_count[shard]); beyond a shard's capacity (or
@@ -88,22 +90,24 @@ struct ReplayArgs {
   long cap;               // chunk capacity (rays)
   int tx_base;
   int n_params;
-  int n_grad;             // leading theta entries summed in LDS (regions, planes, spheres)
-  int grad_copies;        // interleaved LDS copies of those sums (power of two, <= 16)
+  int n_grad;             // leading theta entries summed in LDS (regions, planes, spheres, cylinders, roughness)
+  int grad_copies;        // interleaved LDS copies of those sums (power of two, <= 16; set by the launchers)
   const float* gh;        // dL/dh [n_tx][n_elem][n_t]
-  double* g_part;         // [kMaxReplayBlocks][n_grad] per-block partial sums (zeroed per call)
-  double* vadj;           // [kVadjCopies][vadj_stride] mesh vertex adjoints along vnormal (zeroed per call)
+  unsigned long long* g_sum;   // [n_grad][kSumWords] accumulators of the gradient (zeroed per call)
+  unsigned long long* vadj;    // [kVadjCopies][vadj_stride][kSumWords] mesh vertex adjoints along vnormal (zeroed per call)
   long vadj_stride;
   ReplayStack stk;
   RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
   unsigned long long* counts;   // [max_bounces + 2]: survivors of step k | diffuse interactions << 32
   // optional (null): d/d steering angle of each transmit (tx_base + local
-  // index), then d/d c_ref, d/d pitch and d/d f0, accumulated; n_tx_total
-  // entries of angles precede the three. With g_acq, gh_f0 holds the rows of
-  // dL/dh for the pulse's derivative in f0 (the f0 entry gets each deposit's
-  // amplitude times gh_f0 at its time; the attenuation's share of d/d f0 is
-  // added by launch_grad_reduce)
+  // index), then d/d c_ref, d/d pitch and d/d f0, accumulated by
+  // launch_grad_finish from acq_sum ([n_tx_total + 3][kSumWords], zeroed per
+  // call); n_tx_total entries of angles precede the three. With g_acq, gh_f0
+  // holds the rows of dL/dh for the pulse's derivative in f0 (the f0 entry
+  // gets each deposit's amplitude times gh_f0 at its time; the attenuation's
+  // share of d/d f0 is added by launch_grad_finish)
   double* g_acq;
+  unsigned long long* acq_sum;
   const float* gh_f0;
   int n_tx_total;
 };
@@ -111,24 +115,27 @@ struct ReplayArgs {
 // once per step k = 1..max_bounces + 1 (queues swapped in between), the
 // prefix over the per-step interaction counts, the secondary phase, then the
 // reverse sweep. The counts must be zero before the forward step k = 1. The
-// analytic gradient collects in g_part; add it to g_theta with
-// launch_grad_reduce once all chunks are done.
+// analytic gradient collects in g_sum; add it to g_theta with
+// launch_grad_finish once all chunks are done.
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s);
 void launch_replay_prefix(const ReplayArgs& a, hipStream_t s);
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s);
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
-// g_theta[j] += sum over b of g_part[b * n_grad + j], j < n_grad.
-// g_theta += the per-block rows of g_part; with g_f0 (may be null) also
-// *g_f0 += sum_r theta[3 r + 2] (row sum)[3 r + 2] * inv_f0 over r < n_regions.
-void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, double* g_f0, const double* theta,
-                        int n_regions, double inv_f0, hipStream_t s);
+// g_theta[j] += total of g_sum entry j (j < n_grad); with g_acq, also
+// g_acq[i] += total of acq_sum entry i (i < n_acq), the f0 entry f0_at taking
+// sum_r theta[3 r + 2] (total of entry 3 r + 2) inv_f0 besides.
+void launch_grad_finish(const unsigned long long* g_sum, int n_grad, double* g_theta,
+                        const unsigned long long* acq_sum, int n_acq, double* g_acq, int f0_at,
+                        const double* theta, int n_regions, double inv_f0, hipStream_t s);
 // Copies of the vertex adjoints: block b adds into copy b % kVadjCopies, so
 // that (with blocks dealt round-robin to the eight XCDs) the atomics of one
-// XCD meet in its own L2; the copies are summed by the basis projection.
+// XCD meet in its own L2; the copies are added up by launch_basis_gather.
 constexpr int kVadjCopies = 8;
-// g_q[m * n_basis + j] += sum_{v in mesh m} sum_c vadj[c * stride + v] vbasis[v][j].
-void launch_basis_gather(const double* vadj, long stride, const double* vbasis, const long* vbeg, int n_meshes,
-                         int n_basis, double* g_q, hipStream_t s);
+// vval[v] = total of vertex v over the copies, then
+// g_q[m * n_basis + j] += sum_{v in mesh m} vval[v] vbasis[v][j].
+void launch_basis_gather(const unsigned long long* vadj, long stride, long n_vertices, double* vval,
+                         const double* vbasis, const long* vbeg, int n_meshes, int n_basis, double* g_q,
+                         hipStream_t s);
 
 // ---------------------------------------------------------------- inverse loop
 void launch_param_map(const double* u, const double* lo, const double* hi, int n, double* theta,
@@ -180,11 +187,23 @@ size_t splat_scratch_bytes(int n_rows);
 void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_count, long shard_cap,
                       int n_rows, uint4* sorted, void* scratch, hipStream_t s);
 void launch_splat_accumulate(const uint4* sorted, const void* scratch, uint32_t row0, int n_rows,
-                             int n_t, float* h, hipStream_t s);
+                             int n_t, long long* h, double hist_scale, unsigned long long* hist_over,
+                             hipStream_t s);
+// The last chunk of a transmit group, fused with the pulse: each row of h
+// (direct deposits and earlier chunks) plus the row's binned deposits, read
+// out and filtered straight into rf. Returns -1 (nothing launched) when
+// n_t > 8192 or the pulse is too long for the one-row-per-block layout.
+int launch_splat_pulse(const uint4* sorted, const void* scratch, uint32_t row0, int n_rows, int n_t,
+                       const long long* h, double hist_scale, unsigned long long* hist_over, const float* taps,
+                       int M, float* rf, hipStream_t s);
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,
                  hipStream_t s);
+// The same FIR from the fixed-point histogram: samples h / hist_scale (NaN
+// everywhere when *hist_over is nonzero).
+int launch_pulse_fixed(const long long* h, double hist_scale, const unsigned long long* hist_over, float* rf,
+                       const float* taps, int M, int n_t, long n_rows, hipStream_t s);
 
 // ---------------------------------------------------------------- image chain
 struct GridView {
@@ -199,10 +218,11 @@ void launch_das(const float2* A, float2* iq, const ProbeView& p, const GridView&
 void launch_env_max(const float2* iq, long n_px, unsigned long long* key, hipStream_t s);
 void launch_bmode(const float2* iq, long n_px, float dr_db, const unsigned long long* key,
                   float* bmode, hipStream_t s);
+// sum: an order-independent accumulator of kSumWords words, zeroed by the caller
 void launch_bmode_vjp(const float2* iq, const float* g_b, long n_px, float dr_db,
-                      const unsigned long long* key, double* sum, float2* g_iq, hipStream_t s);
+                      const unsigned long long* key, unsigned long long* sum, float2* g_iq, hipStream_t s);
 void launch_bmode_vjp_fix(const float2* iq, long n_px, const unsigned long long* key,
-                          const double* sum, float2* g_iq, hipStream_t s);
+                          const unsigned long long* sum, float2* g_iq, hipStream_t s);
 // Gradients of the image with respect to the acquisition parameters (the
 // steering angles, c_ref, the pitch): per-tile partial rows in part
 // ([n_tx_group][das_acq_tiles][3] doubles), then added into out[n_tx_total + 2]
@@ -214,8 +234,9 @@ void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, con
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s);
 int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddle, int n_t,
                             long n_rows, hipStream_t s);
-void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2, double* loss,
-                       float* gb, hipStream_t s);
+// acc: an order-independent accumulator of kSumWords words, zeroed by the caller
+void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2,
+                       unsigned long long* acc, double* loss, float* gb, hipStream_t s);
 int launch_pulse_adjoint(const float* g_rf, float* g_h, const float* taps, int M, int n_t,
                          long n_rows, hipStream_t s);
 

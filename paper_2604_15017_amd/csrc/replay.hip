@@ -13,8 +13,11 @@
 // are frozen; branch probabilities are sampling densities and carry no
 // derivative.
 //
-// Parameter adjoints are summed per block in LDS (fp64 LDS atomics) and
-// folded into a per-block row in HBM; the rows are reduced once per call.
+// Every adjoint sum (parameters, mesh vertices, acquisition parameters) is
+// kept in the order-independent integer windows of sum_add: per block in LDS,
+// then added into one global accumulator per entry, read out once per call.
+// Identical calls therefore give bitwise identical gradients whatever the
+// scheduling of the threads and their atomics.
 #include "geometry.h"
 #include "kernels.h"
 
@@ -22,72 +25,72 @@ namespace usrt {
 
 namespace {
 
-// Per-block sums of the region, plane and sphere adjoints (the first n_grad
-// entries of theta; mesh coefficients go through the per-vertex scalars) are
-// kept in LDS in grad_copies interleaved copies: a lane adds to copy
+// Per-block sums of the region, plane, sphere, cylinder and roughness
+// adjoints (the first n_grad entries of theta; mesh coefficients go through
+// the per-vertex sums) live in LDS as grad_copies interleaved copies of
+// n_grad accumulators of kSumWords words: a lane adds to copy
 // lane % grad_copies, so lanes adding to the same parameter contend at most
-// 64 / grad_copies ways. The copies are folded when the block flushes.
-__device__ __forceinline__ int grad_stride(int n_grad) { return (n_grad + 1) & ~1; }
+// 64 / grad_copies ways. The copies are added up word by word when the
+// block ends and the totals go into the global accumulators with integer
+// atomics (order-independent).
+__device__ __forceinline__ int grad_words(int n_grad) { return n_grad * kSumWords; }
 
-__device__ __forceinline__ void grad_clear(double* gsh, int n_grad, int copies) {
-  for (int j = threadIdx.x; j < copies * grad_stride(n_grad); j += blockDim.x) gsh[j] = 0.0;
+__device__ __forceinline__ void words_clear(unsigned long long* w, int n) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) w[j] = 0ull;
 }
 
-// Folds the copies into the block's own row of partial sums: one block with
-// this index runs at a time, so plain read-modify-writes suffice and no
-// global atomics contend on the few gradient entries.
-__device__ __forceinline__ void grad_flush(const double* gsh, int n_grad, int copies, double* g_part) {
-  const int st = grad_stride(n_grad);
-  double* row = g_part + (long)blockIdx.x * n_grad;
-  for (int j = threadIdx.x; j < n_grad; j += blockDim.x) {
-    double v = 0.0;
-    for (int c = 0; c < copies; ++c) v += gsh[c * st + j];
-    if (v != 0.0) row[j] += v;
+__device__ __forceinline__ void grad_flush(const unsigned long long* gsh, int n_grad, int copies,
+                                           unsigned long long* g_sum) {
+  const int n = grad_words(n_grad);
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    unsigned long long v = 0ull;
+    for (int c = 0; c < copies; ++c) v += gsh[c * n + j];
+    if (v) atomicAdd(g_sum + j, v);
   }
 }
 
 // Per-block gradient accumulator over the flat parameter vector.
 struct GradAcc {
-  double* g;
+  unsigned long long* g;          // this lane's LDS copy: [n_grad][kSumWords]
   int n_regions, n_planes, n_spheres, n_cylinders;
   double np_per_m;
   const double* vnormal;
-  double* vadj;                   // per-vertex adjoint along the displacement direction (HBM)
+  unsigned long long* vadj;       // this block's copy of the vertex sums (HBM): [vertex][kSumWords]
+  __device__ void add(int j, double v) { sum_add(g + (long)j * kSumWords, v); }
   // adjoint vbar of mesh vertex v: v = v_rest + (sum_j q_j phi_j(v)) n(v), so
   // the vertex contributes (vbar . n(v)) phi_j(v) to q_j; the scalar is summed
   // per vertex here and projected onto the basis once per call
   __device__ void mesh_vertex(int v, int m, d3 vbar) {
     (void)m;
     const double s = vbar.x * vnormal[3 * v] + vbar.y * vnormal[3 * v + 1] + vbar.z * vnormal[3 * v + 2];
-    if (s != 0.0) unsafeAtomicAdd(vadj + v, s);
+    sum_add(vadj + (long)v * kSumWords, s);
   }
-  __device__ void c(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r], v); }
-  __device__ void Z(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 1], v); }
+  __device__ void c(int r, double v) { add(3 * r, v); }
+  __device__ void Z(int r, double v) { add(3 * r + 1, v); }
   // v is the adjoint of the amplitude attenuation a [Np/m]; a = alpha * np_per_m
-  __device__ void a(int r, double v) { if (v != 0.0) atomicAdd(&g[3 * r + 2], v * np_per_m); }
-  __device__ void plane(int k, double v) { if (v != 0.0) atomicAdd(&g[3 * n_regions + k], v); }
+  __device__ void a(int r, double v) { add(3 * r + 2, v * np_per_m); }
+  __device__ void plane(int k, double v) { add(3 * n_regions + k, v); }
   // roughness of plane / sphere / cylinder k or of mesh k (hit kind decides)
   __device__ void rough(int kind, int k, double v) {
-    if (v == 0.0) return;
     const int base = 3 * n_regions + n_planes + 4 * n_spheres + 3 * n_cylinders;
     const int j = kind == kHitPlane ? k
                 : kind == kHitSphere ? n_planes + k
                 : kind == kHitCylinder ? n_planes + n_spheres + k
                 : n_planes + n_spheres + n_cylinders + k;
-    atomicAdd(&g[base + j], v);
+    add(base + j, v);
   }
   __device__ void cylinder(int k, double xbar, double zbar, double rbar) {
-    double* s = g + 3 * n_regions + n_planes + 4 * n_spheres + 3 * k;
-    if (xbar != 0.0) atomicAdd(s + 0, xbar);
-    if (zbar != 0.0) atomicAdd(s + 1, zbar);
-    if (rbar != 0.0) atomicAdd(s + 2, rbar);
+    const int j = 3 * n_regions + n_planes + 4 * n_spheres + 3 * k;
+    add(j, xbar);
+    add(j + 1, zbar);
+    add(j + 2, rbar);
   }
   __device__ void sphere(int k, d3 cbar, double rbar) {
-    double* s = g + 3 * n_regions + n_planes + 4 * k;
-    if (cbar.x != 0.0) atomicAdd(s + 0, cbar.x);
-    if (cbar.y != 0.0) atomicAdd(s + 1, cbar.y);
-    if (cbar.z != 0.0) atomicAdd(s + 2, cbar.z);
-    if (rbar != 0.0) atomicAdd(s + 3, rbar);
+    const int j = 3 * n_regions + n_planes + 4 * k;
+    add(j, cbar.x);
+    add(j + 1, cbar.y);
+    add(j + 2, cbar.z);
+    add(j + 3, rbar);
   }
 };
 
@@ -585,17 +588,18 @@ __global__ void k_replay_prefix(ReplayArgs a) {
 }
 
 // Acquisition-parameter adjoints of one block (the steering angles of the
-// launch group's transmits, then c_ref, the pitch and f0), summed in LDS and added
-// to a.g_acq once per block. The order of those global additions varies from
-// run to run, so these sums vary in their last bits.
-__device__ __forceinline__ void acq_clear(double* acq) {
-  for (int j = threadIdx.x; j < kMaxTxPerLaunch + 3; j += blockDim.x) acq[j] = 0.0;
-}
-__device__ __forceinline__ void acq_flush(const ReplayArgs& a, const double* acq) {
+// launch group's transmits, then c_ref, the pitch and f0) in LDS accumulators
+// after the gradient copies (when the call asks for them), added to the global
+// accumulators of a.acq_sum (entry tx_base + j for transmit j) once per block.
+__device__ __forceinline__ int acq_words(const ReplayArgs& a) { return a.g_acq ? (a.tx.n + 3) * kSumWords : 0; }
+
+__device__ __forceinline__ void acq_flush(const ReplayArgs& a, const unsigned long long* acq) {
   if (!a.g_acq) return;
-  for (int j = threadIdx.x; j < a.tx.n + 3; j += blockDim.x) {
-    const double v = acq[j];
-    if (v != 0.0) atomicAdd(&a.g_acq[j < a.tx.n ? a.tx_base + j : a.n_tx_total + (j - a.tx.n)], v);
+  for (int j = threadIdx.x; j < acq_words(a); j += blockDim.x) {
+    const unsigned long long v = acq[j];
+    const int e = j / kSumWords, w = j % kSumWords;
+    const int g = e < a.tx.n ? a.tx_base + e : a.n_tx_total + (e - a.tx.n);
+    if (v) atomicAdd(a.acq_sum + (long)g * kSumWords + w, v);
   }
 }
 
@@ -605,19 +609,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
   const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
   if ((long)blockIdx.x * blockDim.x >= n_q) return;
   __shared__ SceneLDS S;
-  __shared__ double acq[kMaxTxPerLaunch + 3];
-  extern __shared__ double gsh[];      // gradient sums (kGradCopies copies), crossing caches, hierarchy stacks
+  // gradient accumulators (grad_copies copies), acquisition accumulators,
+  // crossing caches, hierarchy stacks
+  extern __shared__ unsigned long long gsh[];
   load_scene(S, a.scene);
-  grad_clear(gsh, a.n_grad, a.grad_copies);
-  acq_clear(acq);
+  const int gw = a.grad_copies * grad_words(a.n_grad);
+  unsigned long long* acq = gsh + gw;
+  words_clear(gsh, gw + acq_words(a));
   __syncthreads();
-  double* legs = gsh + a.grad_copies * grad_stride(a.n_grad);
+  double* legs = (double*)(acq + acq_words(a));
   double* leg_t = legs + threadIdx.x;
   int* leg_h = (int*)(legs + kLegCache * blockDim.x) + threadIdx.x;
   int* stk = leg_h + kLegCache * blockDim.x;
-  GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
+  GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_words(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
-            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride};
+            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
@@ -647,11 +653,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
     secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb, f0b);
     a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
     // x_e = (e - (N - 1)/2) pitch
-    if (a.g_acq && xeb != 0.0) atomicAdd(&acq[a.tx.n + 1], xeb * ((double)e2 - 0.5 * (double)(P.n_elem - 1)));
-    if (a.g_acq && f0b != 0.0) atomicAdd(&acq[a.tx.n + 2], f0b);
+    if (a.g_acq) {
+      sum_add(acq + (a.tx.n + 1) * kSumWords, xeb * ((double)e2 - 0.5 * (double)(P.n_elem - 1)));
+      sum_add(acq + (a.tx.n + 2) * kSumWords, f0b);
+    }
   }
   __syncthreads();
-  grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
+  grad_flush(gsh, a.n_grad, a.grad_copies, a.g_sum);
   acq_flush(a, acq);
 }
 
@@ -661,15 +669,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_replay_reverse(ReplayArgs a, long n) {
   if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
-  __shared__ double acq[kMaxTxPerLaunch + 3];
-  extern __shared__ double gsh[];      // gradient sums, kGradCopies copies
+  extern __shared__ unsigned long long gsh[];   // gradient accumulators (grad_copies copies), acquisition accumulators
   load_scene(S, a.scene);
-  grad_clear(gsh, a.n_grad, a.grad_copies);
-  acq_clear(acq);
+  const int gw = a.grad_copies * grad_words(a.n_grad);
+  unsigned long long* acq = gsh + gw;
+  words_clear(gsh, gw + acq_words(a));
   __syncthreads();
-  GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_stride(a.n_grad), a.scene.n_regions, a.scene.n_planes,
+  GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_words(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
-            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride};
+            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -709,7 +717,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
             if (a.gh_f0) {
               double gf, unused;
               tent_adjoint(a.gh_f0 + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, 0.0, &gf, &unused);
-              if (gf != 0.0) atomicAdd(&acq[a.tx.n + 2], gf * watt * fd);
+              sum_add(acq + (a.tx.n + 2) * kSumWords, gf * watt * fd);
             }
             wattb += ga * fd;
             d0b.z -= ga * watt * rx_directivity_deriv(P, -d0.z);
@@ -825,30 +833,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
       const double ox = elem_x(P, e) + (u.u0 - 0.5) * P.elem_w;
       const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
       const double thb = db.x * ca - db.z * sa + tb * ox * ca / P.c_ref - wb * sa / (double)a.rays_per_elem;
-      atomicAdd(&acq[txl], thb);
-      atomicAdd(&acq[a.tx.n], -tb * ox * sa / (P.c_ref * P.c_ref));
-      atomicAdd(&acq[a.tx.n + 1], (ob.x + tb * sa / P.c_ref) * de);
+      sum_add(acq + txl * kSumWords, thb);
+      sum_add(acq + a.tx.n * kSumWords, -tb * ox * sa / (P.c_ref * P.c_ref));
+      sum_add(acq + (a.tx.n + 1) * kSumWords, (ob.x + tb * sa / P.c_ref) * de);
     }
   }
   __syncthreads();
-  grad_flush(gsh, a.n_grad, a.grad_copies, a.g_part);
+  grad_flush(gsh, a.n_grad, a.grad_copies, a.g_sum);
   acq_flush(a, acq);
 }
 
-// g_theta[q(m, j)] += sum over the vertices v of mesh m of vadj[v] phi_j(v),
-// vadj[v] summed over its copies: one block per (mesh, basis function),
-// vertices of mesh m in [vbeg[m], vbeg[m + 1]).
-__global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__ vadj, long stride,
+// vval[v] = the total of vertex v's adjoint sums over the kVadjCopies copies
+// (their words added first, then read out).
+__global__ __launch_bounds__(256) void k_vertex_values(const unsigned long long* __restrict__ vadj, long stride,
+                                                       long n_v, double* __restrict__ vval) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_v) return;
+  unsigned long long w[kSumWords];
+#pragma unroll
+  for (int k = 0; k < kSumWords; ++k) w[k] = 0ull;
+  for (int c = 0; c < kVadjCopies; ++c) {
+    const unsigned long long* p = vadj + ((long)c * stride + v) * kSumWords;
+#pragma unroll
+    for (int k = 0; k < kSumWords; ++k) w[k] += p[k];
+  }
+  vval[v] = sum_value(w);
+}
+
+// g_theta[q(m, j)] += sum over the vertices v of mesh m of vval[v] phi_j(v):
+// one block per (mesh, basis function), vertices of mesh m in
+// [vbeg[m], vbeg[m + 1]), summed in a fixed tree.
+__global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__ vval,
                                                       const double* __restrict__ vbasis,
                                                       const long* __restrict__ vbeg, int n_basis,
                                                       double* __restrict__ g_q) {
   const int m = blockIdx.x / n_basis, j = blockIdx.x % n_basis;
   double acc = 0.0;
-  for (long v = vbeg[m] + threadIdx.x; v < vbeg[m + 1]; v += blockDim.x) {
-    double s = 0.0;
-    for (int c = 0; c < kVadjCopies; ++c) s += vadj[c * stride + v];
-    acc += s * vbasis[v * n_basis + j];
-  }
+  for (long v = vbeg[m] + threadIdx.x; v < vbeg[m + 1]; v += blockDim.x) acc += vval[v] * vbasis[v * n_basis + j];
   __shared__ double red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -856,29 +877,31 @@ __global__ __launch_bounds__(256) void k_basis_gather(const double* __restrict__
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0] != 0.0) atomicAdd(g_q + blockIdx.x, red[0]);
+  if (threadIdx.x == 0) g_q[blockIdx.x] += red[0];   // this block is the entry's only writer
 }
 
-// g_theta[j] += sum of the kMaxReplayBlocks partial rows: one block per
-// entry j, each thread a strided share of the rows, then a tree in LDS.
-__global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ g_part, int n_grad,
-                                                     double* __restrict__ g_theta, double* g_f0,
+// g_theta[j] += the total of accumulator j, j < n_grad; with g_acq, also
+// g_acq[i] += the total of acquisition accumulator i, i < n_acq, and the f0
+// entry (index f0_at) takes sum_r theta[3 r + 2] dL/dalpha_r * inv_f0 besides
+// (every region's amplitude attenuation alpha_r np_per_m grows in proportion
+// to f0). One block; every entry is read out in a fixed order.
+__global__ __launch_bounds__(256) void k_grad_finish(const unsigned long long* __restrict__ g_sum, int n_grad,
+                                                     double* __restrict__ g_theta,
+                                                     const unsigned long long* __restrict__ acq_sum, int n_acq,
+                                                     double* __restrict__ g_acq, int f0_at,
                                                      const double* __restrict__ theta, int n_regions,
                                                      double inv_f0) {
-  const int j = blockIdx.x;
-  double v = 0.0;
-  for (int b = threadIdx.x; b < kMaxReplayBlocks; b += blockDim.x) v += g_part[(long)b * n_grad + j];
-  __shared__ double red[256];
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    g_theta[j] += red[0];
-    // the amplitude attenuation alpha_j np_per_m grows in proportion to f0
-    if (g_f0 && j < 3 * n_regions && j % 3 == 2 && red[0] != 0.0) atomicAdd(g_f0, red[0] * theta[j] * inv_f0);
+  for (int j = threadIdx.x; j < n_grad; j += blockDim.x) g_theta[j] += sum_value(g_sum + (long)j * kSumWords);
+  if (!g_acq) return;
+  for (int i = threadIdx.x; i < n_acq; i += blockDim.x) {
+    double v = sum_value(acq_sum + (long)i * kSumWords);
+    if (i == f0_at) {
+      double att = 0.0;
+      for (int r = 0; r < n_regions && 3 * r + 2 < n_grad; ++r)
+        att += sum_value(g_sum + (long)(3 * r + 2) * kSumWords) * theta[3 * r + 2];
+      v += att * inv_f0;
+    }
+    g_acq[i] += v;
   }
 }
 
@@ -887,14 +910,24 @@ unsigned replay_grid(long n, long cap = kMaxReplayBlocks) {
   const long b = (n + 255) / 256;
   return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
-// the forward phase keeps no gradient rows, so its grid may be larger
+// the forward phase keeps no gradient sums, so its grid may be larger
 constexpr long kMaxReplayForwardBlocks = 8192;
 size_t stack_lds(const ReplayArgs& a) {
   return a.scene.n_meshes > 0 ? (size_t)a.scene.stack_cap * 256 * sizeof(int) : 0;
 }
-size_t grad_lds(const ReplayArgs& a) {
-  return (size_t)a.grad_copies * ((a.n_grad + 1) & ~1) * sizeof(double);
+size_t acq_lds(const ReplayArgs& a) { return a.g_acq ? (size_t)(a.tx.n + 3) * kSumWords * 8 : 0; }
+// LDS of a block of 256 threads when `waves` of them share a SIMD: the
+// gradient copies get what the rest leaves (at most 16 copies, at least one).
+constexpr size_t kLdsPerCU = 160 * 1024;
+constexpr size_t kStaticLds = 8192;   // the scene copy and the kernels' own arrays, rounded up
+int grad_copies_for(const ReplayArgs& a, int waves, size_t other) {
+  const size_t budget = kLdsPerCU / waves;
+  const size_t per = (size_t)a.n_grad * kSumWords * 8;
+  int c = 16;
+  while (c > 1 && kStaticLds + other + c * per > budget) c >>= 1;
+  return c;
 }
+size_t grad_lds(const ReplayArgs& a) { return (size_t)a.grad_copies * a.n_grad * kSumWords * 8; }
 }  // namespace
 
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s) {
@@ -902,32 +935,40 @@ void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s) {
   hipLaunchKernelGGL(kern, dim3(replay_grid(n, kMaxReplayForwardBlocks)), dim3(256), stack_lds(a), s, a, k, n);
 }
 
-void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s) {
+void launch_replay_secondary(const ReplayArgs& a0, long max_entries, hipStream_t s) {
+  ReplayArgs a = a0;
   const size_t legs = (size_t)kLegCache * 256 * (sizeof(double) + sizeof(int));
-  const auto kern = a.scene.n_meshes > 0 ? k_replay_secondary<true> : k_replay_secondary<false>;
+  const bool m = a.scene.n_meshes > 0;
+  a.grad_copies = grad_copies_for(a, m ? 2 : 3, acq_lds(a) + legs + stack_lds(a));
+  const auto kern = m ? k_replay_secondary<true> : k_replay_secondary<false>;
   hipLaunchKernelGGL(kern, dim3(replay_grid(max_entries)), dim3(256),
-                     grad_lds(a) + legs + stack_lds(a), s, a);
+                     grad_lds(a) + acq_lds(a) + legs + stack_lds(a), s, a);
 }
 
 void launch_replay_prefix(const ReplayArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_prefix, dim3(1), dim3(64), 0, s, a);
 }
 
-void launch_grad_reduce(const double* g_part, int n_grad, double* g_theta, double* g_f0, const double* theta,
-                        int n_regions, double inv_f0, hipStream_t s) {
-  if (n_grad > 0) hipLaunchKernelGGL(k_grad_reduce, dim3(n_grad), dim3(256), 0, s, g_part, n_grad, g_theta, g_f0, theta,
-                                    n_regions, inv_f0);
+void launch_grad_finish(const unsigned long long* g_sum, int n_grad, double* g_theta,
+                        const unsigned long long* acq_sum, int n_acq, double* g_acq, int f0_at,
+                        const double* theta, int n_regions, double inv_f0, hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_finish, dim3(1), dim3(256), 0, s, g_sum, n_grad, g_theta, acq_sum, n_acq, g_acq, f0_at,
+                     theta, n_regions, inv_f0);
 }
 
-void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a), s, a, n);
+void launch_replay_reverse(const ReplayArgs& a0, long n, hipStream_t s) {
+  ReplayArgs a = a0;
+  a.grad_copies = grad_copies_for(a, 2, acq_lds(a));
+  hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a) + acq_lds(a), s, a, n);
 }
 
-void launch_basis_gather(const double* vadj, long stride, const double* vbasis, const long* vbeg, int n_meshes,
-                         int n_basis, double* g_q, hipStream_t s) {
-  if (n_meshes > 0 && n_basis > 0)
-    hipLaunchKernelGGL(k_basis_gather, dim3(n_meshes * n_basis), dim3(256), 0, s, vadj, stride, vbasis,
-                       vbeg, n_basis, g_q);
+void launch_basis_gather(const unsigned long long* vadj, long stride, long n_vertices, double* vval,
+                         const double* vbasis, const long* vbeg, int n_meshes, int n_basis, double* g_q,
+                         hipStream_t s) {
+  if (n_meshes <= 0 || n_basis <= 0 || n_vertices <= 0) return;
+  hipLaunchKernelGGL(k_vertex_values, dim3((unsigned)((n_vertices + 255) / 256)), dim3(256), 0, s, vadj, stride,
+                     n_vertices, vval);
+  hipLaunchKernelGGL(k_basis_gather, dim3(n_meshes * n_basis), dim3(256), 0, s, vval, vbasis, vbeg, n_basis, g_q);
 }
 
 }  // namespace usrt

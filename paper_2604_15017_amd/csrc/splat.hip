@@ -5,10 +5,12 @@
 // histograms and cursors live in LDS (each moved record is one 16-byte store:
 // the scattered stores, not the arithmetic, bound this pass), and then one
 // block per row and time tile
-// sums its deposits in an LDS copy of the tile (LDS atomics) and adds the tile
-// to the histogram in HBM with plain coalesced accesses. Global atomics are
+// sums its deposits in an LDS copy of the tile (fixed-point units, integer LDS
+// atomics: the order of the additions does not matter) and adds the tile to
+// the histogram in HBM with plain coalesced accesses. Global atomics are
 // left to deposits that did not fit the record buffer.
 #include "kernels.h"
+#include "fir.h"
 
 namespace usrt {
 
@@ -16,7 +18,7 @@ namespace {
 
 constexpr int kBinBlocks = 256;    // blocks of the counting and scatter passes
 constexpr int kBinThreads = 1024;
-constexpr int kAccTile = 8192;     // samples per accumulation block (32 KB of LDS)
+constexpr int kAccTile = 8192;     // samples per accumulation block (64 KB of LDS)
 
 struct BinScratch {
   uint32_t* hist;       // [n_rows][kBinBlocks]: counts, then row start + prefix over blocks
@@ -202,30 +204,96 @@ __global__ __launch_bounds__(kBinThreads) void k_dep_scatter(DepositList dep, co
 }
 
 // Block (row, tile): the row's deposits summed into an LDS tile of samples
-// [t0, t0 + kAccTile), then added to h.
+// [t0, t0 + kAccTile) in fixed-point units (integer LDS atomics), then added
+// to h.
 __global__ __launch_bounds__(512) void k_dep_accumulate(const uint4* __restrict__ sorted, BinScratch bs, uint32_t row0,
-                                                        int n_t, int tiles, float* __restrict__ h) {
-  __shared__ float acc[kAccTile];
+                                                        int n_t, int tiles, long long* __restrict__ h,
+                                                        double scale, unsigned long long* over) {
+  __shared__ unsigned long long acc[kAccTile];
   const int r = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const uint32_t i0 = bs.row_begin[r], i1 = bs.row_begin[r + 1];
   if (i0 == i1) return;   // nothing to add
   const int t0 = tile * kAccTile, len = min(kAccTile, n_t - t0);
-  for (int j = threadIdx.x; j < len; j += blockDim.x) acc[j] = 0.0f;
+  for (int j = threadIdx.x; j < len; j += blockDim.x) acc[j] = 0ull;
   __syncthreads();
   const uint32_t mask = (1u << kDepBinBits) - 1u;
   for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     const uint4 rec = sorted[i];
     const int j0 = (int)(rec.x & mask) - 1;   // bin of w0; w1 goes to j0 + 1
-    const float2 w = make_float2(__uint_as_float(rec.y), __uint_as_float(rec.z));
     const int j = j0 - t0;
-    if (j0 >= 0 && j >= 0 && j < len) atomicAdd(&acc[j], w.x);
-    if (j0 + 1 < n_t && j + 1 >= 0 && j + 1 < len) atomicAdd(&acc[j + 1], w.y);
+    if (j0 >= 0 && j >= 0 && j < len)
+      atomicAdd(&acc[j], (unsigned long long)hist_units(__uint_as_float(rec.y), scale, over));
+    if (j0 + 1 < n_t && j + 1 >= 0 && j + 1 < len)
+      atomicAdd(&acc[j + 1], (unsigned long long)hist_units(__uint_as_float(rec.z), scale, over));
   }
   __syncthreads();
-  float* out = h + (long)(row0 + r) * n_t + t0;
+  long long* out = h + (long)(row0 + r) * n_t + t0;
   for (int j = threadIdx.x; j < len; j += blockDim.x) {
-    const float v = acc[j];
-    if (v != 0.0f) out[j] += v;
+    const long long v = (long long)acc[j];
+    if (v != 0) out[j] += v;
+  }
+}
+
+// Block per RF row (n_t <= kAccTile, 1024 threads): the row of h (the
+// deposits added directly) and the row's binned deposits summed in LDS in
+// fixed-point units, then read out as fp32 into the same LDS and filtered
+// with the pulse straight into rf: the histogram row never returns to HBM.
+constexpr int kFuseThreads = 1024;
+static_assert(kFuseThreads * kPulseR >= kAccTile, "one row per block");
+
+template <bool kVec>
+__global__ __launch_bounds__(kFuseThreads) void k_splat_pulse(const uint4* __restrict__ sorted, BinScratch bs,
+                                                              uint32_t row0, int n_t, const long long* __restrict__ h,
+                                                              double scale, unsigned long long* over,
+                                                              const float* __restrict__ taps, int M,
+                                                              float* __restrict__ rf) {
+  __shared__ __align__(16) unsigned long long acc[kAccTile];   // then the fp32 input of the filter
+  __shared__ __align__(16) float c[2 * kMaxTaps];
+  __shared__ int row_over;
+  const int r = blockIdx.x;
+  const long grow = (long)row0 + r;
+  const long long* hr = h + grow * n_t;
+  for (int j = threadIdx.x; j < n_t; j += blockDim.x) acc[j] = (unsigned long long)hr[j];
+  const int T = 2 * M + 1, Tp = fir_padded(M);
+  for (int j = threadIdx.x; j < Tp; j += blockDim.x) c[j] = j < T ? taps[2 * M - j] : 0.0f;
+  if (threadIdx.x == 0) row_over = 0;
+  __syncthreads();
+  const uint32_t i0 = bs.row_begin[r], i1 = bs.row_begin[r + 1];
+  const uint32_t mask = (1u << kDepBinBits) - 1u;
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const uint4 rec = sorted[i];
+    const int j0 = (int)(rec.x & mask) - 1;   // bin of w0; w1 goes to j0 + 1
+    if (j0 >= 0) atomicAdd(&acc[j0], (unsigned long long)hist_units(__uint_as_float(rec.y), scale, over));
+    if (j0 + 1 < n_t) atomicAdd(&acc[j0 + 1], (unsigned long long)hist_units(__uint_as_float(rec.z), scale, over));
+  }
+  __syncthreads();
+  // read out: every thread takes its samples into registers before the fp32
+  // copy (x[m] = h[m - M], zero outside [0, n_t)) overwrites the LDS
+  constexpr int kPer = kAccTile / kFuseThreads;
+  const double inv = 1.0 / scale;
+  const bool bad = *over != 0ull;
+  float v[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int j = u * kFuseThreads + threadIdx.x;
+    v[u] = j < n_t ? (bad ? __builtin_nanf("") : (float)((double)(long long)acc[j] * inv)) : 0.0f;
+  }
+  __syncthreads();
+  float* x = reinterpret_cast<float*>(acc);
+  const int n_x = kFuseThreads * kPulseR + Tp;   // every input the filter reads
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int j = u * kFuseThreads + threadIdx.x;
+    if (j < n_t) x[M + j] = v[u];
+  }
+  for (int j = threadIdx.x; j < n_x; j += blockDim.x)
+    if (j < M || j >= M + n_t) x[j] = 0.0f;
+  __syncthreads();
+  const int b = threadIdx.x * kPulseR;
+  if (b < n_t) {
+    float out[kPulseR];
+    fir_block(x, c, b, Tp, out);
+    fir_store<kVec>(rf + grow * n_t, b, n_t, out);
   }
 }
 
@@ -247,12 +315,28 @@ void launch_splat_bin(const DepositList& dep, const unsigned long long* shard_co
                      n_rows, bs, sorted);
 }
 
+int launch_splat_pulse(const uint4* sorted, const void* scratch, uint32_t row0, int n_rows, int n_t,
+                       const long long* h, double hist_scale, unsigned long long* hist_over, const float* taps,
+                       int M, float* rf, hipStream_t s) {
+  if (n_t > kAccTile || M > kMaxTaps - 1 || kFuseThreads * kPulseR + fir_padded(M) > 2 * kAccTile) return -1;
+  const BinScratch bs = carve(const_cast<void*>(scratch), n_rows);
+  const bool vec = n_t % 4 == 0 && ((uintptr_t)rf & 15) == 0;
+  if (vec)
+    hipLaunchKernelGGL(k_splat_pulse<true>, dim3((unsigned)n_rows), dim3(kFuseThreads), 0, s, sorted, bs, row0, n_t,
+                       h, hist_scale, hist_over, taps, M, rf);
+  else
+    hipLaunchKernelGGL(k_splat_pulse<false>, dim3((unsigned)n_rows), dim3(kFuseThreads), 0, s, sorted, bs, row0,
+                       n_t, h, hist_scale, hist_over, taps, M, rf);
+  return 0;
+}
+
 void launch_splat_accumulate(const uint4* sorted, const void* scratch, uint32_t row0, int n_rows,
-                             int n_t, float* h, hipStream_t s) {
+                             int n_t, long long* h, double hist_scale, unsigned long long* hist_over,
+                             hipStream_t s) {
   const BinScratch bs = carve(const_cast<void*>(scratch), n_rows);
   const int tiles = (n_t + kAccTile - 1) / kAccTile;
   hipLaunchKernelGGL(k_dep_accumulate, dim3((unsigned)((long)n_rows * tiles)), dim3(512), 0, s, sorted, bs,
-                     row0, n_t, tiles, h);
+                     row0, n_t, tiles, h, hist_scale, hist_over);
 }
 
 }  // namespace usrt

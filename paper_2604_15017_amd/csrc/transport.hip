@@ -2,14 +2,16 @@
 // one launch per interaction index k, each consuming a compacted queue of
 // live rays in HBM and producing the next one, plus one launch per k for the
 // receiver-directed secondary rays spawned at diffuse-capable hits. Deposits
-// are splatted with a linear tent into an fp32 histogram h[tx][elem][sample]
-// with hardware fp32 atomics; a final FIR applies the pulse of Eq. axial_sig.
+// are splatted with a linear tent into a fixed-point histogram
+// h[tx][elem][sample] (int64 units, integer atomics: the sums do not depend on
+// the order of the additions); a final FIR applies the pulse of Eq. axial_sig.
 //
 // Precision: positions, directions, times and weights are fp64 (MI355X runs
 // fp64 vector math at half the fp32 rate). A time error dt costs 2 pi f0 dt of
 // phase, and the parity bound on RF needs dt of a few ps over paths tens of
 // millimetres long, which fp32 geometry cannot hold.
 #include "kernels.h"
+#include "fir.h"
 #include "geometry.h"
 
 namespace usrt {
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
             if (fd > 0.0) {   // few per launch: added to the histogram directly
               ++n_dep;
               if (make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e), P.n_t, P.fs, t, w * fd, &dp))
-                add_deposit(a.h, P.n_t, dp);
+                add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
             }
           } else if (kAudit) {
             hsum += event_mix(kEvArray, k, 0xFFFFFFu);
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
       a.dep.key[at] = ((dp.row - a.dep.row0) << kDepBinBits) | (uint32_t)(dp.j0 + 1);
       a.dep.w[at] = make_float2(dp.w0, dp.w1);
     } else if (rec) {
-      add_deposit(a.h, P.n_t, dp);
+      add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
     }
     if (kAudit) {
       const uint32_t word = blocked ? ((uint32_t)e2 | (3u << 16) | (crossings << 20))
@@ -266,16 +268,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
 
 // rf[row][k] = sum_{|m| <= M} h[row][k - m] s[m]  (Eq. axial_sig as a FIR on
 // the deposit histogram; h is zero outside [0, n_t)). One block computes a
-// tile of kPulseTile outputs of one row from an LDS copy of the tile + halo;
-// each thread keeps kPulseR consecutive outputs in registers and slides a
-// window of 2 kPulseR inputs over the taps, so that one LDS read feeds
-// kPulseR multiply-adds (the FIR is then bound by fp32 FMA issue, not LDS).
-constexpr int kPulseR = 8;
+// tile of kPulseTile outputs of one row from an LDS copy of the tile + halo
+// (fir_block: kPulseR outputs per thread).
 constexpr int kPulseTile = 256 * kPulseR;
-constexpr int kMaxTaps = 512;
+
+// Samples of the FIR's input: an fp32 row, or the fixed-point histogram
+// read out (units times 1 / scale, a power of two; NaN once a weight was clamped).
+struct PulseIn {
+  const float* f;
+  const long long* q;
+  double inv_scale;
+  const unsigned long long* over;
+  __device__ __forceinline__ float at(long i, bool bad) const {
+    if (f) return f[i];
+    return bad ? __builtin_nanf("") : (float)((double)q[i] * inv_scale);
+  }
+};
 
 template <bool kVec>
-__global__ __launch_bounds__(256) void k_pulse(const float* __restrict__ h, float* __restrict__ rf,
+__global__ __launch_bounds__(256) void k_pulse(PulseIn in, float* __restrict__ rf,
                                                const float* __restrict__ taps, int M, int n_t,
                                                int tiles_per_row) {
   // x[i] = h[k0 - M + i]; c[q] = s[M - q] = taps[2M - q], zero-padded to Tp
@@ -283,45 +294,20 @@ __global__ __launch_bounds__(256) void k_pulse(const float* __restrict__ h, floa
   __shared__ __align__(16) float c[2 * kMaxTaps];
   const long row = blockIdx.x / tiles_per_row;
   const int k0 = (blockIdx.x % tiles_per_row) * kPulseTile;
-  const float* hr = h + row * (long)n_t;
-  const int T = 2 * M + 1, Tp = (T + kPulseR - 1) / kPulseR * kPulseR;
+  const long r0 = row * (long)n_t;
+  const bool bad = in.over && *in.over != 0ull;
+  const int T = 2 * M + 1, Tp = fir_padded(M);
   for (int j = threadIdx.x; j < kPulseTile + Tp; j += blockDim.x) {
     const int src = k0 - M + j;
-    x[j] = (src >= 0 && src < n_t) ? hr[src] : 0.0f;
+    x[j] = (src >= 0 && src < n_t) ? in.at(r0 + src, bad) : 0.0f;
   }
   for (int j = threadIdx.x; j < Tp; j += blockDim.x) c[j] = j < T ? taps[2 * M - j] : 0.0f;
   __syncthreads();
   // output k0 + b + r = sum_q x[b + r + q] c[q]
   const int b = threadIdx.x * kPulseR;
-  float acc[kPulseR], v[2 * kPulseR];
-#pragma unroll
-  for (int r = 0; r < kPulseR; ++r) {
-    acc[r] = 0.0f;
-    v[r] = x[b + r];
-  }
-  for (int q0 = 0; q0 < Tp; q0 += kPulseR) {
-#pragma unroll
-    for (int r = 0; r < kPulseR; ++r) v[kPulseR + r] = x[b + q0 + kPulseR + r];
-#pragma unroll
-    for (int qq = 0; qq < kPulseR; ++qq) {
-      const float cq = c[q0 + qq];
-#pragma unroll
-      for (int r = 0; r < kPulseR; ++r) acc[r] = fmaf(v[r + qq], cq, acc[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < kPulseR; ++r) v[r] = v[kPulseR + r];
-  }
-  const int kk = k0 + b;
-  float* out = rf + row * (long)n_t + kk;
-  if (kVec && kk + kPulseR <= n_t) {
-#pragma unroll
-    for (int r = 0; r < kPulseR; r += 4)
-      *reinterpret_cast<float4*>(out + r) = make_float4(acc[r], acc[r + 1], acc[r + 2], acc[r + 3]);
-  } else {
-#pragma unroll
-    for (int r = 0; r < kPulseR; ++r)
-      if (kk + r < n_t) out[r] = acc[r];
-  }
+  float acc[kPulseR];
+  fir_block(x, c, b, Tp, acc);
+  fir_store<kVec>(rf + row * (long)n_t, k0 + b, n_t, acc);
 }
 
 __global__ void k_fill_u32(uint32_t* p, long n, uint32_t v) {
@@ -364,19 +350,27 @@ void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipS
   hipLaunchKernelGGL(kern, grid, block, stack_bytes(a), s, a, k);
 }
 
-int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,
-                 hipStream_t s) {
+static int pulse(const PulseIn& in, float* rf, const float* taps, int M, int n_t, long n_rows, hipStream_t s) {
   if (M > kMaxTaps - 1) return -1;
   const int tiles = (n_t + kPulseTile - 1) / kPulseTile;
   // 16-byte stores when every row starts 16-byte aligned
   const bool vec = n_t % 4 == 0 && ((uintptr_t)rf & 15) == 0;
   if (vec)
-    hipLaunchKernelGGL(k_pulse<true>, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, h, rf, taps, M,
-                       n_t, tiles);
+    hipLaunchKernelGGL(k_pulse<true>, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, in, rf, taps, M, n_t,
+                       tiles);
   else
-    hipLaunchKernelGGL(k_pulse<false>, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, h, rf, taps, M,
-                       n_t, tiles);
+    hipLaunchKernelGGL(k_pulse<false>, dim3((unsigned)(n_rows * tiles)), dim3(256), 0, s, in, rf, taps, M, n_t,
+                       tiles);
   return 0;
+}
+
+int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows, hipStream_t s) {
+  return pulse(PulseIn{h, nullptr, 0.0, nullptr}, rf, taps, M, n_t, n_rows, s);
+}
+
+int launch_pulse_fixed(const long long* h, double hist_scale, const unsigned long long* hist_over, float* rf,
+                       const float* taps, int M, int n_t, long n_rows, hipStream_t s) {
+  return pulse(PulseIn{nullptr, h, 1.0 / hist_scale, hist_over}, rf, taps, M, n_t, n_rows, s);
 }
 
 }  // namespace usrt

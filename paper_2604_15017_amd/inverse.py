@@ -74,6 +74,7 @@ class InverseLoop:
                                                                  wl.max_bounces), dev)
         self.ws_b = L._workspace(lib.us_beamform_workspace_size(self.probe.handle, n_tx), dev)
         self.ws_m = L._workspace(lib.us_bmode_workspace_size(g.n_px), dev)
+        self.ws_l = L._workspace(lib.us_image_loss_workspace_size(g.n_px), dev)
         self.ws_r = L._workspace(L.us_simulate_rf_vjp_workspace_size(self.scene, self.probe, n_tx, count,
                                                                      wl.max_bounces), dev)
         if refs is None:
@@ -109,7 +110,7 @@ class InverseLoop:
         for b, (ang, ids, rb, rc) in enumerate(self._views):
             rf = self._frame(self.scene, b)
             L.us_image_loss(self.ctx, self.bm, self.refs[b], self.l1, self.l2, loss=self.loss[b:b + 1],
-                            g_bmode=self.g_b, stream=self.stream)
+                            g_bmode=self.g_b, workspace=self.ws_l, stream=self.stream)
             L.us_bmode_vjp(self.ctx, self.iq, self.g_b, wl.dr_db, g_iq=self.g_iq, workspace=self.ws_m,
                            stream=self.stream)
             g_rf = self.g_rf[:len(ang)]

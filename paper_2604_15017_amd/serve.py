@@ -201,6 +201,7 @@ class GpuExecutor:
         if req.want_grad:
             s.update({"b_ref": 4 * g.n_px, "g_b": 4 * g.n_px, "g_iq": 8 * g.n_px, "g_rf": 4 * rows,
                       "loss": 8, "g_theta": 8 * scene.n_params,
+                      "ws_loss": L.load().us_image_loss_workspace_size(g.n_px),
                       "ws_beam_vjp": L.load().us_beamform_vjp_workspace_size(probe.handle, n_tx),
                       "ws_replay": L.us_simulate_rf_vjp_workspace_size(
                           scene, probe, n_tx, min(wl.rays_per_tx, max(1, REPLAY_CHUNK_RAYS // n_tx)),
@@ -239,10 +240,10 @@ class GpuExecutor:
                 t["g_iq"] = torch.empty_like(t["iq"])
                 t["g_rf"] = torch.empty_like(t["rf"])
                 t["g_theta"] = torch.zeros(scene.n_params, dtype=torch.float64, device=dev)
-                for k in ("ws_beam_vjp", "ws_replay"):
+                for k in ("ws_beam_vjp", "ws_replay", "ws_loss"):
                     t[k] = torch.empty(max(256, sz[k]), dtype=torch.uint8, device=dev)
                 L.us_image_loss(self.ctx, t["bmode"], t["b_ref"], 0.0, 1.0, loss=t["loss"],
-                                g_bmode=t["g_b"], stream=st)
+                                g_bmode=t["g_b"], workspace=t["ws_loss"], stream=st)
                 L.us_bmode_vjp(self.ctx, t["iq"], t["g_b"], wl.dr_db, g_iq=t["g_iq"],
                                workspace=t["ws_bmode"], stream=st)
                 L.us_beamform_vjp(self.ctx, probe, g, wl.angles, wl.tx_ids, t["g_iq"], g_rf=t["g_rf"],

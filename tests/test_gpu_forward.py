@@ -159,12 +159,13 @@ def test_small_workspace_forces_chunks(L, ctx):
                                      tx_ids=np.arange(3, dtype=np.uint32))
     scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
     need = L.us_simulate_rf_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx, wl.max_bounces)
-    hist = wl.n_tx * wl.probe.n_elem * wl.probe.n_t * 4 + 4096   # histogram + counters
+    hist = wl.n_tx * wl.probe.n_elem * wl.probe.n_t * 8 + 4096   # fixed-point histogram + counters
     small = hist + (need - hist) // 7                             # queues for ~1/7 of the rays
     ws = torch.empty(small, dtype=torch.uint8, device="cuda")
     g_small = gpu_trace(L, ctx, wl, workspace=ws)["rf"]
     g_full = gpu_trace(L, ctx, wl)["rf"]
-    assert rel_l2(g_small, g_full) <= 1e-6
+    # the same integer additions grouped by chunk: the same bits
+    assert np.array_equal(g_small, g_full)
     rf, _, _ = oracle.simulate_rf(wl)
     assert rel_l2(g_small, rf) <= RF_TOL
 
