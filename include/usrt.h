@@ -182,6 +182,21 @@ int us_beamform(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
                 const us_tx_desc* tx, int32_t n_tx, const float* rf_dev, float* iq_dev,
                 void* ws_dev, size_t ws_bytes, void* stream);
 
+/* us_beamform for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, with the analytic signal kept in a
+ * file-scope device array of the library instead of a workspace. The array
+ * holds at most 64 MiB (8,388,608 complex samples: n_tx * n_elem * n_t of
+ * them; US_ETOOBIG beyond, with nothing launched); each GPU that loads the
+ * library holds its own copy until the process ends. Allocates nothing and
+ * clears nothing (every sample it reads is written first in the same call).
+ * All calls on one GPU share its array: calls that overlap in time on one
+ * GPU (on different streams, or from different threads) race and give wrong
+ * results; serialise them. */
+int us_beamform_static(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid,
+                       const us_tx_desc* tx, int32_t n_tx, const float* rf_dev, float* iq_dev,
+                       void* stream);
+
 /* Envelope and log compression (Sec. 2.3.4, Sec. 3.1):
  * bmode = max(20 log10(|iq| / max|iq|), -dr_db). */
 size_t us_bmode_workspace_size(int64_t n_px);

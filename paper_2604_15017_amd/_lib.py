@@ -76,6 +76,7 @@ _SIGNATURES = {
                                       vp, sz, vp]),
     "us_beamform_workspace_size": (sz, [vp, i32]),
     "us_beamform": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]),
+    "us_beamform_static": (ctypes.c_int, [vp, vp, vp, vp, i32, vp, vp, vp]),
     "us_bmode_workspace_size": (sz, [i64]),
     "us_bmode": (ctypes.c_int, [vp, vp, i64, ctypes.c_float, vp, vp, sz, vp]),
     "us_bmode_vjp": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_float, vp, vp, sz, vp]),
@@ -327,6 +328,22 @@ def us_beamform(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, iq=None, w
     _check(load().us_beamform(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf),
                               _ptr(iq), _ptr(workspace), workspace.numel(), _stream(stream)),
            "us_beamform")
+    return iq
+
+
+def us_beamform_static(ctx: Context, probe: Probe, grid, angles, tx_ids, rf, iq=None, stream=None):
+    """us_beamform without a workspace (the library's static scratch; calls on
+    one GPU must not overlap)."""
+    torch = _torch()
+    tx, n_tx = _tx_array(angles, tx_ids)
+    g = _grid(grid)
+    if iq is None:
+        iq = torch.empty((g.n_x, g.n_z, 2), dtype=torch.float32, device=ctx.torch_device)
+    p = probe.desc
+    _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
+    _expect(iq, 2 * g.n_x * g.n_z, torch.float32, "iq")
+    _check(load().us_beamform_static(ctx.handle, probe.handle, ctypes.byref(g), tx, n_tx, _ptr(rf), _ptr(iq),
+                                     _stream(stream)), "us_beamform_static")
     return iq
 
 

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,21 @@ struct us_ctx {
   ProfileLog prof;
 };
 
+// Scratch of us_beamform_static, the entry point for callers that cannot
+// allocate: the analytic signal of the channels, at most kStaticScratchBytes
+// (64 MiB, 8,388,608 complex samples). Every GPU that loads the library holds
+// its own copy of the array until the process ends. In host code the array's
+// name is not a device address: us_create looks up each device's copy once
+// (hipGetSymbolAddress with that device current) and every use goes through
+// the pointer kept here.
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
 namespace {
 
 // Brackets the launches issued in its scope with events when profiling is on.
@@ -76,8 +92,9 @@ struct Timed {
   const char* name;
   hipStream_t s;
   hipEvent_t a = nullptr;
+  // a null name records nothing (the allocation-free entry point)
   Timed(us_ctx* ctx, const char* n, hipStream_t st) : log(&ctx->prof), name(n), s(st) {
-    if (log->on) { a = log->get(); (void)hipEventRecord(a, s); }
+    if (log->on && n) { a = log->get(); (void)hipEventRecord(a, s); }
   }
   ~Timed() {
     if (!a) return;
@@ -150,6 +167,14 @@ int us_create(int device, us_ctx** out) {
   US_HIP(hipGetDeviceCount(&n));
   US_CHECK(device >= 0 && device < n, "us_create: no such device");
   US_HIP(bind_device(device));
+  if (device < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      void* p = nullptr;
+      US_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      g_scratch_ptr[device] = p;
+    }
+  }
   *out = new us_ctx{device};
   return US_OK;
 }
@@ -756,6 +781,36 @@ size_t us_beamform_workspace_size(const us_probe* probe, int32_t n_tx) {
   return align_up((size_t)n_tx * probe->d.n_elem * probe->d.n_t * sizeof(float2));
 }
 
+}  // extern "C"
+
+namespace {
+
+// The launches of us_beamform with the analytic signal in A (checked by the
+// caller); `timed` brackets them with the profiling events when profiling is on.
+int beamform_launch(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx,
+                    int32_t n_tx, const float* rf_dev, float* iq_dev, float2* A, hipStream_t s, bool timed) {
+  const long rows = (long)n_tx * probe->d.n_elem;
+  {
+    Timed tm(ctx, timed ? "analytic" : nullptr, s);
+    if (launch_analytic(rf_dev, A, probe->twiddle, probe->d.n_t, rows, s))
+      return fail(US_EINVAL, "us_beamform: unsupported n_t");
+  }
+  const GridView g = grid_view(grid);
+  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    TxTable tt;
+    fill_tx(tt, tx, t0, ng);
+    Timed tm(ctx, timed ? "das" : nullptr, s);
+    launch_das(A, (float2*)iq_dev, probe->pv, g, tt, ng, t0, t0 > 0, s);
+  }
+  US_HIP(hipGetLastError());
+  return US_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int us_beamform(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx,
                 int32_t n_tx, const float* rf_dev, float* iq_dev, void* ws_dev, size_t ws_bytes,
                 void* stream) {
@@ -765,24 +820,23 @@ int us_beamform(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, co
   if (ws_bytes < us_beamform_workspace_size(probe, n_tx))
     return fail(US_ETOOBIG, "us_beamform: workspace too small");
   US_HIP(bind_device(ctx->device));
-  hipStream_t s = (hipStream_t)stream;
-  float2* A = (float2*)ws_dev;
-  const long rows = (long)n_tx * probe->d.n_elem;
-  {
-    Timed tm(ctx, "analytic", s);
-    if (launch_analytic(rf_dev, A, probe->twiddle, probe->d.n_t, rows, s))
-      return fail(US_EINVAL, "us_beamform: unsupported n_t");
-  }
-  const GridView g = grid_view(grid);
-  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
-    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
-    TxTable tt;
-    fill_tx(tt, tx, t0, ng);
-    Timed tm(ctx, "das", s);
-    launch_das(A, (float2*)iq_dev, probe->pv, g, tt, ng, t0, t0 > 0, s);
-  }
-  US_HIP(hipGetLastError());
-  return US_OK;
+  return beamform_launch(ctx, probe, grid, tx, n_tx, rf_dev, iq_dev, (float2*)ws_dev, (hipStream_t)stream, true);
+}
+
+int us_beamform_static(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx,
+                       int32_t n_tx, const float* rf_dev, float* iq_dev, void* stream) {
+  US_CHECK(ctx && rf_dev && iq_dev, "us_beamform_static: NULL argument");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  const size_t need = us_beamform_workspace_size(probe, n_tx);
+  if (need > kStaticScratchBytes)
+    return fail(US_ETOOBIG, "us_beamform_static: the analytic signal needs " + std::to_string(need) +
+                                " bytes; the static scratch holds " + std::to_string(kStaticScratchBytes) +
+                                " (use us_beamform with a workspace)");
+  void* p = ctx->device < kMaxDevices ? g_scratch_ptr[ctx->device] : nullptr;
+  US_CHECK(p != nullptr, "us_beamform_static: no static scratch on this device");
+  US_HIP(bind_device(ctx->device));
+  return beamform_launch(ctx, probe, grid, tx, n_tx, rf_dev, iq_dev, (float2*)p, (hipStream_t)stream, false);
 }
 
 size_t us_bmode_workspace_size(int64_t n_px) {
