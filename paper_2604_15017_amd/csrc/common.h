@@ -90,6 +90,26 @@ struct TriRec {
   double p0[3], e1[3], e2[3], pad;
 };
 
+// Read-only pointer into device memory in the global address space. The
+// scene's array pointers live in the per-block LDS copy of the scene; typed
+// this way, loads through them are global loads rather than flat ones (a flat
+// load also counts against the LDS wait counter, so every wait on an LDS read
+// of the walk's stack would wait for the node loads in flight as well).
+template <class T> using gptr = __attribute__((address_space(1))) const T*;
+
+// Whole-structure load through a gptr, as 16-byte vector loads.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ T gload(gptr<T> p) {
+  static_assert(sizeof(T) % 16 == 0, "16-byte pieces");
+  T out;
+  const __attribute__((address_space(1))) u32x4* q = (const __attribute__((address_space(1))) u32x4*)p;
+  u32x4* o = reinterpret_cast<u32x4*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 16); ++i) o[i] = q[i];
+  return out;
+}
+
 struct d3 { double x, y, z; };
 __device__ __forceinline__ d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
@@ -144,11 +164,11 @@ struct SceneLDS {
   double prho[kMaxPlanes], srho[kMaxSpheres], crho[kMaxCylinders], mrho[kMaxMeshes];   // GGX roughness
   int n_planes, n_spheres, n_cylinders, n_meshes, start_region, stack_cap;
   bool any_diffuse;
-  const BvhNode* nodes;
-  const TriRec* trec;
-  const int4* tri;
-  const int* tri_orig;
-  const double* vcur;
+  gptr<BvhNode> nodes;
+  gptr<TriRec> trec;
+  gptr<int4> tri;
+  gptr<int> tri_orig;
+  gptr<double> vcur;
 };
 
 __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
@@ -213,11 +233,11 @@ __device__ inline void load_scene(SceneLDS& s, const SceneView& v) {
     for (int i = 0; i < v.n_cylinders; ++i) d |= v.cylinder_kd[i] > 0.0;
     for (int i = 0; i < v.n_meshes; ++i) d |= v.mesh_kd[i] > 0.0;
     s.any_diffuse = d;
-    s.nodes = v.nodes;
-    s.trec = v.trec;
-    s.tri = v.tri;
-    s.tri_orig = v.tri_orig;
-    s.vcur = v.vcur;
+    s.nodes = (gptr<BvhNode>)v.nodes;
+    s.trec = (gptr<TriRec>)v.trec;
+    s.tri = (gptr<int4>)v.tri;
+    s.tri_orig = (gptr<int>)v.tri_orig;
+    s.vcur = (gptr<double>)v.vcur;
   }
   __syncthreads();
 }

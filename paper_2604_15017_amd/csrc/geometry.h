@@ -8,7 +8,7 @@ namespace usrt {
 
 struct Hit { int kind; int index; double t; };
 
-__device__ __forceinline__ d3 vtx(const double* v, int i) {
+__device__ __forceinline__ d3 vtx(gptr<double> v, int i) {
   return d3{v[3 * i], v[3 * i + 1], v[3 * i + 2]};
 }
 __device__ __forceinline__ d3 cross(d3 a, d3 b) {
@@ -46,7 +46,7 @@ __device__ __forceinline__ SlabRay slab_ray(d3 o, d3 d) {
 
 // Moller-Trumbore in fp64 on a leaf-order triangle record, edges included;
 // distance or -1.
-__device__ __forceinline__ double rec_distance(const TriRec& r, d3 o, d3 d) {
+__device__ __forceinline__ double rec_distance(const TriRec r, d3 o, d3 d) {
   const d3 e1{r.e1[0], r.e1[1], r.e1[2]}, e2{r.e2[0], r.e2[1], r.e2[2]};
   const d3 pv = cross(d, e2);
   const double det = dot(e1, pv);
@@ -101,7 +101,7 @@ __device__ __forceinline__ void walk4(const SceneLDS& s, const SlabRay& q, int* 
       const float lim = cull() * 1.0001f + kBoxPad;
       float t[4];
       int r[4];
-      node_children(s.nodes[cur], q, lim, t, r);
+      node_children(gload(s.nodes + cur), q, lim, t, r);
       if (t[0] != INFINITY) {
         // the build bounds the depth by stack_cap / 3, so the pushes always fit
         if (t[3] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[3]; ++sp; }
@@ -134,7 +134,7 @@ __device__ __forceinline__ void mesh_closest(const SceneLDS& s, d3 o, d3 d, doub
                                              int* stk) {
   walk4(s, slab_ray(o, d), stk, [&]() { return (float)best; }, [&](int first, int cnt) {
     for (int i = first; i < first + cnt; ++i) {
-      const double t = rec_distance(s.trec[i], o, d);
+      const double t = rec_distance(gload(s.trec + i), o, d);
       if (t > kTMin && t < best) { best = t; best_tri = i; }
     }
   });
@@ -277,7 +277,7 @@ __device__ __forceinline__ SegHits segment_hits(const SceneLDS& s, d3 x, d3 w, d
   if (kMeshes && s.n_meshes > 0) {
     walk4(s, slab_ray(x, w), stk, [&]() { return (float)seg_cull(L, hi); }, [&](int first, int cnt) {
       for (int i = first; i < first + cnt; ++i) {
-        const double t = rec_distance(s.trec[i], x, w);
+        const double t = rec_distance(gload(s.trec + i), x, w);
         if (t > smin && t < seg_cull(L, hi)) seg_insert(L, t, (kHitMesh << 28) | i);
       }
     });
@@ -287,7 +287,7 @@ __device__ __forceinline__ SegHits segment_hits(const SceneLDS& s, d3 x, d3 w, d
 
 // Unit face normal of leaf-order triangle i, from the current geometry.
 __device__ __forceinline__ d3 tri_normal(const SceneLDS& s, int i) {
-  const TriRec& r = s.trec[i];
+  const TriRec r = gload(s.trec + i);
   const d3 nu = cross(d3{r.e1[0], r.e1[1], r.e1[2]}, d3{r.e2[0], r.e2[1], r.e2[2]});
   return nu * (1.0 / sqrt(dot(nu, nu)));
 }

@@ -106,7 +106,7 @@ struct TriAdj {
 // Adjoint through nu = (p1 - p0) x (p2 - p0) into the three vertices.
 __device__ __forceinline__ void tri_nu_backward(const SceneLDS& S, int i, d3 nub, d3 p0b_extra,
                                                 GradAcc& G) {
-  const int4 tv = S.tri[i];
+  const int4 tv = gload(S.tri + i);
   const d3 p0 = vtx(S.vcur, tv.x), e1 = vtx(S.vcur, tv.y) - p0, e2 = vtx(S.vcur, tv.z) - p0;
   const d3 e1b = cross(e2, nub), e2b = cross(nub, e1);
   G.mesh_vertex(tv.x, tv.w, p0b_extra - e1b - e2b);
@@ -156,7 +156,7 @@ __device__ __forceinline__ void distance_backward(const SceneLDS& S, int kind, i
                                                   d3& dbar, GradAcc& G, TriAdj& ta) {
   if (sbar == 0.0) return;
   if (kind == kHitMesh) {   // s = nu.(p0 - o) / nu.d
-    const int4 tv = S.tri[idx];
+    const int4 tv = gload(S.tri + idx);
     const d3 p0 = vtx(S.vcur, tv.x);
     const d3 nu = cross(vtx(S.vcur, tv.y) - p0, vtx(S.vcur, tv.z) - p0);
     const double den = dot(nu, d);
@@ -228,7 +228,7 @@ __device__ __forceinline__ double primary_root(const SceneLDS& S, int idx, d3 o,
 __device__ __forceinline__ void normal_backward(const SceneLDS& S, int kind, int idx, d3 n,
                                                 d3 nbar, d3& xbar, GradAcc& G, TriAdj& ta) {
   if (kind == kHitMesh) {   // n = nu / |nu|
-    const int4 tv = S.tri[idx];
+    const int4 tv = gload(S.tri + idx);
     const d3 p0 = vtx(S.vcur, tv.x);
     const d3 nu = cross(vtx(S.vcur, tv.y) - p0, vtx(S.vcur, tv.z) - p0);
     ta.nub = ta.nub + (nbar - n * dot(nbar, n)) * (1.0 / sqrt(dot(nu, nu)));

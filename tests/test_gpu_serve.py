@@ -36,13 +36,11 @@ def test_results_alone_equal_results_in_mix():
         a, m = alone[r.rid], mix.results[r.rid]
         assert a.ok and m.ok, (a.error, m.error)
         assert a.segments == m.segments
-        ba, bm = a.bmode.cpu().numpy(), m.bmode.cpu().numpy()
-        live = (ba > -60) | (bm > -60)
-        assert np.abs(ba - bm)[live].max() <= 0.05
+        # every sum on the path is order-independent: the same bits alone and in the mix
+        assert np.array_equal(a.bmode.cpu().numpy(), m.bmode.cpu().numpy())
         if r.want_grad:
-            assert m.loss == pytest.approx(a.loss, rel=1e-4)
-            ga, gm = a.g_theta.cpu().numpy(), m.g_theta.cpu().numpy()
-            assert np.abs(ga - gm).max() <= 1e-3 * np.abs(ga).max()
+            assert m.loss == a.loss
+            assert np.array_equal(a.g_theta.cpu().numpy(), m.g_theta.cpu().numpy())
     st = S.latency_stats(list(mix.results.values()))
     assert st["completed"] == len(reqs)
 
