@@ -396,14 +396,18 @@ __host__ __device__ __forceinline__ bool sum_pieces(double v, SumPieces* p) {
   return true;
 }
 
-// Adds v to the accumulator acc[kSumWords] (LDS or global memory).
-__device__ __forceinline__ void sum_add(unsigned long long* acc, double v) {
+// Adds v to an accumulator whose kSumWords words lie `stride` words apart,
+// acc[w * stride] (LDS or global memory).
+__device__ __forceinline__ void sum_add(unsigned long long* acc, long stride, double v) {
   SumPieces p;
   if (!sum_pieces(v, &p)) return;
-  if (p.over) { atomicAdd(acc + kSumBins, 1ull); return; }
-  atomicAdd(acc + p.b, p.hi);
-  if (p.lo) atomicAdd(acc + p.b - 1, p.lo);
+  if (p.over) { atomicAdd(acc + kSumBins * stride, 1ull); return; }
+  atomicAdd(acc + p.b * stride, p.hi);
+  if (p.lo) atomicAdd(acc + (p.b - 1) * stride, p.lo);
 }
+
+// Adds v to the contiguous accumulator acc[kSumWords].
+__device__ __forceinline__ void sum_add(unsigned long long* acc, double v) { sum_add(acc, 1, v); }
 
 // The accumulated total: the windows added in a fixed order.
 __host__ __device__ __forceinline__ double sum_value(const unsigned long long* acc) {

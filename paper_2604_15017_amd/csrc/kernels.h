@@ -94,7 +94,7 @@ struct ReplayArgs {
   int grad_copies;        // interleaved LDS copies of those sums (power of two, <= 16; set by the launchers)
   const float* gh;        // dL/dh [n_tx][n_elem][n_t]
   unsigned long long* g_sum;   // [n_grad][kSumWords] accumulators of the gradient (zeroed per call)
-  unsigned long long* vadj;    // [kVadjCopies][vadj_stride][kSumWords] mesh vertex adjoints along vnormal (zeroed per call)
+  unsigned long long* vadj;    // [kVadjCopies][kSumWords][vadj_stride] mesh vertex adjoints along vnormal (zeroed per call)
   long vadj_stride;
   ReplayStack stk;
   RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
@@ -127,10 +127,16 @@ void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
 void launch_grad_finish(const unsigned long long* g_sum, int n_grad, double* g_theta,
                         const unsigned long long* acq_sum, int n_acq, double* g_acq, int f0_at,
                         const double* theta, int n_regions, double inv_f0, hipStream_t s);
-// Copies of the vertex adjoints: block b adds into copy b % kVadjCopies, so
-// that (with blocks dealt round-robin to the eight XCDs) the atomics of one
-// XCD meet in its own L2; the copies are added up by launch_basis_gather.
-constexpr int kVadjCopies = 8;
+// Copies of the vertex adjoints: block b adds into copy b % kVadjCopies.
+// Blocks are dealt round-robin to the eight XCDs, so each copy is updated
+// from one XCD (its atomics meet in that XCD's L2), and four copies per XCD
+// spread the blocks contending for a line. The copies are added up by
+// launch_basis_gather. Within a copy the sums are word-major (word w of every
+// vertex, then word w + 1): a value touches the two words of its magnitude's
+// windows, and the vertex adjoints of one call span few windows, so the lines
+// the atomics touch are those few rows of the copy rather than every vertex's
+// whole accumulator.
+constexpr int kVadjCopies = 32;
 // vval[v] = total of vertex v over the copies, then
 // g_q[m * n_basis + j] += sum_{v in mesh m} vval[v] vbasis[v][j].
 void launch_basis_gather(const unsigned long long* vadj, long stride, long n_vertices, double* vval,

@@ -55,7 +55,8 @@ struct GradAcc {
   int n_regions, n_planes, n_spheres, n_cylinders;
   double np_per_m;
   const double* vnormal;
-  unsigned long long* vadj;       // this block's copy of the vertex sums (HBM): [vertex][kSumWords]
+  unsigned long long* vadj;       // this block's copy of the vertex sums (HBM): [kSumWords][vstride]
+  long vstride;
   __device__ void add(int j, double v) { sum_add(g + (long)j * kSumWords, v); }
   // adjoint vbar of mesh vertex v: v = v_rest + (sum_j q_j phi_j(v)) n(v), so
   // the vertex contributes (vbar . n(v)) phi_j(v) to q_j; the scalar is summed
@@ -63,7 +64,7 @@ struct GradAcc {
   __device__ void mesh_vertex(int v, int m, d3 vbar) {
     (void)m;
     const double s = vbar.x * vnormal[3 * v] + vbar.y * vnormal[3 * v + 1] + vbar.z * vnormal[3 * v + 2];
-    sum_add(vadj + (long)v * kSumWords, s);
+    sum_add(vadj + v, vstride, s);
   }
   __device__ void c(int r, double v) { add(3 * r, v); }
   __device__ void Z(int r, double v) { add(3 * r + 1, v); }
@@ -623,7 +624,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
   int* stk = leg_h + kLegCache * blockDim.x;
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_words(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
-            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords};
+            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords, a.vadj_stride};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
@@ -677,7 +678,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
   __syncthreads();
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_words(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
-            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords};
+            a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords, a.vadj_stride};
   const ProbeView& P = a.probe;
   const long cap = a.cap;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -853,9 +854,9 @@ __global__ __launch_bounds__(256) void k_vertex_values(const unsigned long long*
 #pragma unroll
   for (int k = 0; k < kSumWords; ++k) w[k] = 0ull;
   for (int c = 0; c < kVadjCopies; ++c) {
-    const unsigned long long* p = vadj + ((long)c * stride + v) * kSumWords;
+    const unsigned long long* p = vadj + (long)c * stride * kSumWords + v;
 #pragma unroll
-    for (int k = 0; k < kSumWords; ++k) w[k] += p[k];
+    for (int k = 0; k < kSumWords; ++k) w[k] += p[k * stride];
   }
   vval[v] = sum_value(w);
 }
