@@ -63,6 +63,8 @@ def kernel_bytes(name, wl, counts, n_px):
         "pulse": 12 * row_samples,
         "pulse_adjoint": 8 * row_samples,
         "analytic_adjoint": 12 * row_samples,
+        # the analytic-signal gradient read, dL/dh written (dL/drf stays in LDS)
+        "analytic_pulse_adjoint": 12 * row_samples,
         "das_adjoint": 8 * row_samples + 8 * n_px,
         "bmode_vjp": 28 * n_px,
         "image_loss": 12 * n_px,
@@ -368,6 +370,18 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
         L.us_simulate_rf_vjp(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
                              wl.max_bounces, g_rf, g_theta=g_theta, workspace=ws_r, stream=stream)
 
+    # the same backward as one us_frame_vjp call (fused analytic + pulse adjoints)
+    ws_f = L._workspace(L.us_frame_vjp_workspace_size(scene, probe, g, wl.n_tx, wl.rays_per_tx,
+                                                      wl.max_bounces), dev) if backward else None
+    g_theta_f = torch.zeros_like(g_theta)
+
+    def step_fb_fused():
+        step()
+        L.us_image_loss(ctx, bm, b_ref, 0.0, 1.0, loss=loss, g_bmode=g_b, workspace=ws_l, stream=stream)
+        g_theta_f.zero_()
+        L.us_frame_vjp(ctx, scene, probe, g, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                       iq, g_b, wl.dr_db, g_theta=g_theta_f, workspace=ws_f, stream=stream)
+
     step(cnt=counters)                  # event counts of one frame (deterministic)
     torch.cuda.synchronize()
     counts = [int(v) for v in counters.cpu().numpy()]
@@ -401,10 +415,19 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
 
     fwd_ms, prof = timed(step)
     fb_ms, prof_fb = timed(step_fb) if backward else (float("nan"), {})
+    fused = None
+    if backward:
+        fused_ms, prof_fused = timed(step_fb_fused)
+        step_fb()                       # the plain chain's gradient of the same frame
+        torch.cuda.synchronize()
+        fused = {"ms_per_step": round(fused_ms, 4), "frames_per_s": round(1e3 / fused_ms, 2),
+                 "plain_ms_per_step": round(fb_ms, 4), "speedup_vs_plain": round(fb_ms / fused_ms, 4),
+                 "gradient_bitwise_equal_to_plain": bool(torch.equal(g_theta, g_theta_f)),
+                 "kernels": kernel_table(prof_fused)}
     segments = counts[0] + counts[1]
     return {"counts": counts, "segments": segments, "n_params": scene.n_params,
             "fwd_ms": fwd_ms, "prof": prof, "kernels": kernel_table(prof),
-            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb),
+            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb), "fused": fused,
             "loss": float(loss.item()) if backward else None}
 
 
@@ -476,7 +499,8 @@ def main():
     a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup,
                    backward=not args.no_backward)
     print(f"anatomy phantom: forward {a['fwd_ms']:.3f} ms/frame, forward+backward "
-          f"{a['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
+          f"{a['fb_ms']:.3f} ms/frame" + (f" ({a['fused']['ms_per_step']:.3f} fused)" if a["fused"] else ""),
+          file=sys.stderr, flush=True)
     prof, counts = a["prof"], a["counts"]
     transport = [k for k in ("bounce", "secondary") if k in prof]
     dom = max(transport, key=lambda k: prof[k][0])
@@ -509,13 +533,15 @@ def main():
             "ms_per_step": round(a["fb_ms"], 4), "frames_per_s": round(1e3 / a["fb_ms"], 2),
             "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
             "loss": a["loss"], "kernels": a["fb_kernels"]},
+        "fwd_bwd_fused": a["fused"],
     }
     if not args.no_layered:
         wl = W.layered_phantom()
         r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup,
                        backward=not args.no_backward)
         print(f"layered phantom: forward {r['fwd_ms']:.3f} ms/frame, forward+backward "
-              f"{r['fb_ms']:.3f} ms/frame", file=sys.stderr, flush=True)
+              f"{r['fb_ms']:.3f} ms/frame" + (f" ({r['fused']['ms_per_step']:.3f} fused)" if r["fused"] else ""),
+              file=sys.stderr, flush=True)
         lay = frame_summary(r, wl, args.steps)
         lay["workload"] = (f"layered_phantom: {wl.n_tx} x {wl.rays_per_tx} rays, {wl.max_bounces} interactions, "
                            f"{wl.probe.n_elem} x {wl.probe.n_t} samples, {wl.grid.n_x} x {wl.grid.n_z} pixels")
@@ -526,6 +552,7 @@ def main():
                               "ray_segments_per_s": r["segments"] / (r["fb_ms"] * 1e-3),
                               "gradient_parameters": r["n_params"], "loss": r["loss"],
                               "kernels": r["fb_kernels"]}
+            lay["fwd_bwd_fused"] = r["fused"]
         out["layered_phantom"] = lay
     if not args.no_backward and not args.no_inverse:
         out["inverse"] = inverse_leg(ctx, args.steps, args.warmup)
@@ -536,8 +563,9 @@ def main():
     if not args.no_serving:
         out["serving"] = serving(ctx, args.serve_requests)
     if not args.no_cpu_baseline:
-        # 2^16 rays of each of the 21 transmits: 1,376,256 of the frame's 16,777,152
-        out["cpu_baseline"] = cpu_baseline(wa, ray_count=1 << 16)
+        # 2^19 rays of each of the 21 transmits: 11,010,048 of the frame's 16,777,152
+        # (about 12 s on 16 host cores)
+        out["cpu_baseline"] = cpu_baseline(wa, ray_count=1 << 19)
         if "layered_phantom" in out:
             out["layered_phantom"]["cpu_baseline"] = cpu_baseline(W.layered_phantom())
     print(json.dumps(out), flush=True)

@@ -271,13 +271,34 @@ int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe
  * element an array hit lands on is piecewise constant in the pitch and not
  * differentiated. The workspace is that of us_simulate_rf_vjp.
  *   g_acq_dev in/out: double [n_tx + 3], accumulated: d/d angle of each
- *   transmit, then d/d c_ref, d/d pitch and d/d f0 (summed with atomics per
- *   block, so they vary in their last bits between runs) */
+ *   transmit, then d/d c_ref, d/d pitch and d/d f0 (summed in integer
+ *   windows, so the values do not depend on scheduling) */
 int us_simulate_rf_vjp_acq(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
                            const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
                            int64_t ray_begin, int64_t ray_count, int32_t max_bounces,
                            const float* g_rf_dev, double* g_theta_dev, double* g_acq_dev, void* ws_dev,
                            size_t ws_bytes, void* stream);
+
+/* The backward of one frame in one call, from dL/dB to g_theta (Sec. 3.2-3.3,
+ * Eq. das_adjoint, Eq. chain_rule): us_bmode_vjp, then us_beamform_vjp, then
+ * us_simulate_rf_vjp, with the image and analytic-signal gradients kept in
+ * the workspace and the analytic-signal adjoint and the pulse adjoint run as
+ * one kernel per RF row (dL/drf stays in LDS and never reaches HBM). The
+ * arithmetic is that of the three calls in the same order: g_theta is bit for
+ * bit the three-call result.
+ *   iq_dev in: float [n_x][n_z][2], the image the B-mode frame came from
+ *   (us_beamform of the same scene, probe, transmits and grid)
+ *   g_bmode_dev in: float [n_x][n_z], dL/dB; dr_db as for us_bmode
+ *   g_theta_dev in/out: double [n_params], accumulated
+ *   ws_dev: us_frame_vjp_workspace_size(...) bytes at least (US_ETOOBIG if
+ *   smaller); a larger workspace lets the replay take longer chunks of rays.
+ * Arguments are checked as for the three calls (US_EINVAL). */
+size_t us_frame_vjp_workspace_size(const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                                   int32_t n_tx, int64_t ray_count, int32_t max_bounces);
+int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                 const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                 int64_t ray_count, int32_t max_bounces, const float* iq_dev, const float* g_bmode_dev,
+                 float dr_db, double* g_theta_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Inverse loop (Sec. "Parameterization and constraints", Sec. "Optimization
  * procedure", Algorithm opt). All arrays are device doubles of length n.

@@ -88,6 +88,9 @@ _SIGNATURES = {
     "us_simulate_rf_vjp": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                           vp, sz, vp]),
     "us_simulate_rf_vjp_acq": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp, vp, vp, sz, vp]),
+    "us_frame_vjp_workspace_size": (sz, [vp, vp, vp, i32, i64, i32]),
+    "us_frame_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
+                                    ctypes.c_float, vp, vp, sz, vp]),
     "us_image_loss_workspace_size": (sz, [i64]),
     "us_image_loss": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp,
                                      vp, sz, vp]),
@@ -481,6 +484,42 @@ def us_simulate_rf_vjp(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids,
                                              int(max_bounces), _ptr(g_rf), _ptr(g_theta), _ptr(g_acq),
                                              _ptr(workspace), workspace.numel(), _stream(stream)),
                "us_simulate_rf_vjp_acq")
+    return g_theta
+
+
+def us_frame_vjp_workspace_size(scene: Scene, probe: Probe, grid, n_tx: int, ray_count: int,
+                                max_bounces: int) -> int:
+    g = _grid(grid)
+    return int(load().us_frame_vjp_workspace_size(scene.handle, probe.handle, ctypes.byref(g), n_tx, ray_count,
+                                                  max_bounces))
+
+
+def us_frame_vjp(ctx: Context, scene: Scene, probe: Probe, grid, angles, tx_ids, seed: int,
+                 rays_per_elem: int, max_bounces: int, iq, g_bmode, dr_db: float, g_theta=None,
+                 ray_begin: int = 0, ray_count: Optional[int] = None, workspace=None, stream=None):
+    """g_theta += (d bmode / d theta)^T g_bmode in one call: the B-mode, DAS,
+    analytic-signal, pulse and transport adjoints (iq: the image the B-mode
+    frame was formed from)."""
+    torch = _torch()
+    p = probe.desc
+    tx, n_tx = _tx_array(angles, tx_ids)
+    g = _grid(grid)
+    n_px = g.n_x * g.n_z
+    if ray_count is None:
+        ray_count = int(p.n_elem) * int(rays_per_elem) - ray_begin
+    if g_theta is None:
+        g_theta = torch.zeros(scene.n_params, dtype=torch.float64, device=ctx.torch_device)
+    _expect(iq, 2 * n_px, torch.float32, "iq")
+    _expect(g_bmode, n_px, torch.float32, "g_bmode")
+    _expect(g_theta, scene.n_params, torch.float64, "g_theta")
+    if workspace is None:
+        workspace = _workspace(us_frame_vjp_workspace_size(scene, probe, grid, n_tx, ray_count, max_bounces),
+                               ctx.torch_device)
+    _expect_ws(workspace)
+    _check(load().us_frame_vjp(ctx.handle, scene.handle, probe.handle, ctypes.byref(g), tx, n_tx, int(seed),
+                               int(rays_per_elem), int(ray_begin), int(ray_count), int(max_bounces), _ptr(iq),
+                               _ptr(g_bmode), float(dr_db), _ptr(g_theta), _ptr(workspace), workspace.numel(),
+                               _stream(stream)), "us_frame_vjp")
     return g_theta
 
 

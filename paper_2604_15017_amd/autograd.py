@@ -8,6 +8,12 @@ the rays from their Philox counters, us_beamform_vjp is the transposed DAS
 gather, us_bmode_vjp the log/envelope adjoint). PyTorch only supplies device
 memory, the current stream and the graph bookkeeping.
 
+Frame (Renderer.render_frame) is the same chain as one Function: its forward
+makes the three forward calls, its backward is one us_frame_vjp call, which
+takes dL/dB to the parameters with the intermediate gradients in its
+workspace (the analytic-signal and pulse adjoints fused into one kernel);
+the gradient is bit for bit that of the three-Function chain.
+
 Fixed ray realisations (common random numbers): the seed and ray range are
 attributes of the Renderer, constants of the differentiation.
 
@@ -89,6 +95,18 @@ class Renderer:
         theta = self.theta0 if theta is None else theta
         return self.bmode(self.beamform(self.simulate_rf(theta, acq), acq))
 
+    def render_frame(self, theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """theta -> B-mode as one Function whose backward is us_frame_vjp."""
+        theta = self.theta0 if theta is None else theta
+        return Frame.apply(theta, self)
+
+    def frame_workspace(self) -> torch.Tensor:
+        if getattr(self, "_ws_frame", None) is None:
+            wl = self.wl
+            self._ws_frame = L._workspace(L.us_frame_vjp_workspace_size(
+                self.scene, self.probe, wl.grid, wl.n_tx, self.ray_count, wl.max_bounces), self.ctx.torch_device)
+        return self._ws_frame
+
 
 class SimulateRF(torch.autograd.Function):
     @staticmethod
@@ -169,6 +187,34 @@ class BMode(torch.autograd.Function):
         g_iq = L.us_bmode_vjp(r.ctx, iq, g_b.to(torch.float32).contiguous(), r.wl.dr_db,
                               workspace=r.ws_bmode)
         return g_iq, None
+
+
+class Frame(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, theta: torch.Tensor, r: Renderer):
+        theta = theta.detach().to(torch.float64).contiguous()
+        r.scene.set_params(theta)
+        wl = r.wl
+        rf = L.us_simulate_rf(r.ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
+                              wl.rays_per_elem, wl.max_bounces, ray_begin=r.ray_begin,
+                              ray_count=r.ray_count, workspace=r.ws_trace)
+        iq = L.us_beamform(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids, rf, workspace=r.ws_beam)
+        b = L.us_bmode(r.ctx, iq, wl.dr_db, workspace=r.ws_bmode)
+        fctx.r = r
+        fctx.save_for_backward(theta, iq)
+        return b
+
+    @staticmethod
+    def backward(fctx, g_b: torch.Tensor):
+        r = fctx.r
+        theta, iq = fctx.saved_tensors
+        r.scene.set_params(theta)
+        wl = r.wl
+        g_theta = L.us_frame_vjp(r.ctx, r.scene, r.probe, wl.grid, wl.angles, wl.tx_ids, wl.seed,
+                                 wl.rays_per_elem, wl.max_bounces, iq, g_b.to(torch.float32).contiguous(),
+                                 wl.dr_db, ray_begin=r.ray_begin, ray_count=r.ray_count,
+                                 workspace=r.frame_workspace())
+        return g_theta, None
 
 
 class ImageLoss(torch.autograd.Function):

@@ -993,12 +993,15 @@ size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* 
 namespace {
 
 // The replay backward; g_acq_dev (may be null) also receives the adjoints of
-// the acquisition parameters.
+// the acquisition parameters. The gradient arrives as dL/drf (g_rf_dev), or,
+// with g_A_dev instead, as the gradient of the analytic signal, taken through
+// the analytic map's and the pulse's adjoints in one kernel (no g_acq then).
 int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
                     int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin, int64_t ray_count,
                     int32_t max_bounces, const float* g_rf_dev, double* g_theta_dev, double* g_acq_dev,
-                    void* ws_dev, size_t ws_bytes, void* stream) {
-  US_CHECK(ctx && g_rf_dev && g_theta_dev && ws_dev, "us_simulate_rf_vjp: NULL argument");
+                    void* ws_dev, size_t ws_bytes, void* stream, const float2* g_A_dev = nullptr) {
+  US_CHECK(ctx && (g_rf_dev || g_A_dev) && g_theta_dev && ws_dev, "us_simulate_rf_vjp: NULL argument");
+  US_CHECK(!(g_A_dev && g_acq_dev), "us_simulate_rf_vjp: acquisition gradients need dL/drf");
   int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
   // largest chunk that fits the workspace
@@ -1027,7 +1030,12 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   if (scene->n_meshes > 0) launch_fill_u32((uint32_t*)a.vadj, 2L * kVadjCopies * a.vadj_stride * kSumWords, 0u, s);
   launch_fill_u32((uint32_t*)a.g_sum, 2L * std::max(1, scene->q_offset) * kSumWords, 0u, s);
   if (g_acq_dev) launch_fill_u32((uint32_t*)a.acq_sum, 2L * (n_tx + 3) * kSumWords, 0u, s);
-  {
+  if (g_A_dev) {
+    Timed tm(ctx, "analytic_pulse_adjoint", s);
+    if (launch_analytic_pulse_adjoint(g_A_dev, gh, probe->twiddle, probe->taps_rev, probe->M, pd.n_t,
+                                      (long)n_tx * pd.n_elem, s))
+      return fail(US_EINVAL, "us_frame_vjp: unsupported n_t or pulse too long");
+  } else {
     Timed tm(ctx, "pulse_adjoint", s);
     if (launch_pulse_adjoint(g_rf_dev, gh, probe->taps_rev, probe->M, pd.n_t, (long)n_tx * pd.n_elem, s))
       return fail(US_EINVAL, "us_simulate_rf_vjp: pulse too long");
@@ -1113,6 +1121,61 @@ int us_simulate_rf_vjp_acq(us_ctx* ctx, const us_scene* scene, const us_probe* p
   US_CHECK(g_acq_dev, "us_simulate_rf_vjp_acq: NULL g_acq");
   return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
                          g_rf_dev, g_theta_dev, g_acq_dev, ws_dev, ws_bytes, stream);
+}
+
+// Workspace of us_frame_vjp: the B-mode adjoint's frame maximum and sum, the
+// image gradient, the analytic-signal gradient and the replay's workspace.
+size_t us_frame_vjp_workspace_size(const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                                   int32_t n_tx, int64_t ray_count, int32_t max_bounces) {
+  if (!scene || !probe || !grid || n_tx < 1 || grid->n_x < 1 || grid->n_z < 1) return 0;
+  const size_t replay = us_simulate_rf_vjp_workspace_size(scene, probe, n_tx, ray_count, max_bounces);
+  if (!replay) return 0;
+  const int64_t n_px = (int64_t)grid->n_x * grid->n_z;
+  return us_bmode_workspace_size(n_px) + align_up((size_t)n_px * sizeof(float2)) +
+         us_beamform_workspace_size(probe, n_tx) + replay;
+}
+
+int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                 const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                 int64_t ray_count, int32_t max_bounces, const float* iq_dev, const float* g_bmode_dev,
+                 float dr_db, double* g_theta_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && iq_dev && g_bmode_dev && g_theta_dev && ws_dev, "us_frame_vjp: NULL argument");
+  US_CHECK(dr_db > 0, "us_frame_vjp: dr_db must be positive");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
+  if (rc) return rc;
+  const size_t need = us_frame_vjp_workspace_size(scene, probe, grid, n_tx, ray_count, max_bounces);
+  if (ws_bytes < need) return fail(US_ETOOBIG, "us_frame_vjp: workspace too small");
+  US_HIP(bind_device(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n_px = (int64_t)grid->n_x * grid->n_z;
+  char* w = (char*)ws_dev;
+  unsigned long long* key = (unsigned long long*)w;
+  unsigned long long* sum = (unsigned long long*)(w + kAlign);
+  w += us_bmode_workspace_size(n_px);
+  float2* g_iq = (float2*)w;
+  w += align_up((size_t)n_px * sizeof(float2));
+  float2* gA = (float2*)w;
+  w += us_beamform_workspace_size(probe, n_tx);
+  launch_fill_u32((uint32_t*)key, 2, 0u, s);
+  launch_fill_u32((uint32_t*)sum, 2 * kSumWords, 0u, s);
+  {
+    Timed tm(ctx, "bmode_vjp", s);
+    launch_env_max((const float2*)iq_dev, n_px, key, s);
+    launch_bmode_vjp((const float2*)iq_dev, g_bmode_dev, n_px, dr_db, key, sum, g_iq, s);
+    launch_bmode_vjp_fix((const float2*)iq_dev, n_px, key, sum, g_iq, s);
+  }
+  const GridView g = grid_view(grid);
+  for (int t0 = 0; t0 < n_tx; t0 += kMaxTxPerLaunch) {
+    const int ng = std::min(kMaxTxPerLaunch, n_tx - t0);
+    TxTable tt;
+    fill_tx(tt, tx, t0, ng);
+    Timed tm(ctx, "das_adjoint", s);
+    launch_das_adjoint(g_iq, gA, probe->pv, g, tt, ng, t0, s);
+  }
+  return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
+                         nullptr, g_theta_dev, nullptr, w, ws_bytes - (size_t)(w - (char*)ws_dev), stream, gA);
 }
 
 int us_param_map(us_ctx* ctx, const double* u_dev, const double* lo_dev, const double* hi_dev,

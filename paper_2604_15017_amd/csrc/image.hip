@@ -4,6 +4,7 @@
 // das_adjoint as a per-sample gather, no atomics).
 #include <algorithm>
 
+#include "fir.h"
 #include "kernels.h"
 
 namespace usrt {
@@ -149,7 +150,7 @@ __device__ __forceinline__ void fft_pass_bits(int bits, float2* x, const void* g
 // (adjoint: T is self-adjoint, g_rf = Re(T g_A)). n = 2^logn is split into
 // two or three passes of radix <= 32, smallest first.
 template <bool kRealIn, bool kRealOut>
-__global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* out,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_analytic(const void* in, void* out,
                                                           const float2* twiddle, int n, int logn) {
   extern __shared__ float2 lds[];
   float2* lo = lds;                          // w_n^i, i < 128
@@ -195,6 +196,76 @@ __global__ __launch_bounds__(kFftThreads) void k_analytic(const void* in, void* 
     L <<= bits[p];
   }
   fft_pass_bits<kIoLds, kOut>(bits[n_pass - 1], x, nullptr, dst, n, L, lo, hi);
+}
+
+template <int R>
+__device__ __forceinline__ void fir_row(const float* rr, const float* c, int Tp, int n, float* out) {
+  for (int b = threadIdx.x * R; b < n; b += blockDim.x * R) {
+    float acc[R];
+    fir_block<R>(rr, c, b, Tp, acc);
+    fir_store<true, R>(out, b, n, acc);
+  }
+}
+
+// Adjoint of the pulse (Eq. axial_sig) after the adjoint of the analytic
+// map, per RF row: the transforms of k_analytic<false, true>, whose last pass
+// writes the row's real gradient Re(T g_A) into LDS (over the transform's
+// buffer, M zeros before it and Tp after it) instead of HBM, then the pulse
+// correlation of k_pulse from that row (taps c[q] = taps[2M - q], the same
+// fir_block sums), written as g_h. One HBM round trip of the row less than
+// the two kernels, and the same arithmetic in the same order.
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_analytic_pulse_adjoint(const float2* __restrict__ gA,
+                                                                        float* __restrict__ gh,
+                                                                        const float2* __restrict__ twiddle,
+                                                                        const float* __restrict__ taps, int M,
+                                                                        int n, int logn) {
+  extern __shared__ float2 lds[];
+  float2* lo = lds;
+  float2* hi = lds + (1 << kFftLoBits);
+  float2* x = hi + 64;
+  const long row = blockIdx.x;
+  const int half = n >> 1;
+  for (int i = threadIdx.x; i < (1 << kFftLoBits) + 64; i += blockDim.x) {
+    const bool is_lo = i < (1 << kFftLoBits);
+    const int e = is_lo ? i : (i - (1 << kFftLoBits)) << kFftLoBits;
+    float2 v = make_float2(1.0f, 0.0f);
+    if (e < n) {
+      v = twiddle[e < half ? e : e - half];
+      if (e >= half) v = make_float2(-v.x, -v.y);
+    }
+    lds[i] = v;
+  }
+  __syncthreads();
+  const int n_pass = (logn + 4) / 5;
+  int bits[3];
+  for (int p = 0, left = logn; p < n_pass; ++p) {
+    bits[p] = left / (n_pass - p);
+    left -= bits[p];
+  }
+  float* rr = reinterpret_cast<float*>(x);   // rr[M + k]: the real gradient of sample k
+  int L = 1;
+  fft_pass_bits<kIoComplexIn, kIoLds>(bits[0], x, gA + row * n, nullptr, n, L, lo, hi);
+  L <<= bits[0];
+  if (n_pass == 3) {
+    fft_pass_bits<kIoLds, kIoLds>(bits[1], x, nullptr, nullptr, n, L, lo, hi);
+    L <<= bits[1];
+  }
+  fft_pass_bits<kIoLds, kIoLdsH>(bits[n_pass - 1], x, nullptr, nullptr, n, L, lo, hi);
+  L = 1;
+  for (int p = 0; p < n_pass - 1; ++p) {
+    fft_pass_bits<kIoLds, kIoLds>(bits[p], x, nullptr, nullptr, n, L, lo, hi);
+    L <<= bits[p];
+  }
+  // the last pass reads all of x before it writes (a barrier in between)
+  fft_pass_bits<kIoLds, kIoRealOut>(bits[n_pass - 1], x, nullptr, rr + M, n, L, lo, hi);
+  const int T = 2 * M + 1, Tp = fir_padded(M);
+  float* c = rr + ((n + Tp + 3) & ~3);
+  for (int j = threadIdx.x; j < M; j += blockDim.x) rr[j] = 0.0f;
+  for (int j = M + n + threadIdx.x; j < n + Tp; j += blockDim.x) rr[j] = 0.0f;
+  for (int j = threadIdx.x; j < Tp; j += blockDim.x) c[j] = j < T ? taps[2 * M - j] : 0.0f;
+  __syncthreads();
+  float* out = gh + row * (long)n;
+  fir_row<kPulseR>(rr, c, Tp, n, out);
 }
 
 // Delay-and-sum, one pixel per thread, threads along z, reading the two
@@ -862,6 +933,20 @@ int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddl
   const size_t lds = analytic_lds(n_t);
   hipLaunchKernelGGL((k_analytic<false, true>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
                      (const void*)g_A, (void*)g_rf, twiddle, n_t, logn);
+  return 0;
+}
+
+int launch_analytic_pulse_adjoint(const float2* g_A, float* g_h, const float2* twiddle, const float* taps_reversed,
+                                  int M, int n_t, long n_rows, hipStream_t s) {
+  const int logn = log2_exact(n_t);
+  if (logn < 6 || n_t > kMaxFft || M < 0 || M > kMaxTaps - 1) return -1;
+  // the transform's buffer, or the padded real row and the taps after the twiddles
+  const int Tp = fir_padded(M);
+  const size_t fir = (size_t)((1 << kFftLoBits) + 64) * sizeof(float2) +
+                     (size_t)(((n_t + Tp + 3) & ~3) + Tp) * sizeof(float);
+  const size_t lds = std::max(analytic_lds(n_t), fir);
+  hipLaunchKernelGGL(k_analytic_pulse_adjoint, dim3((unsigned)n_rows), dim3(kFftThreads), lds, s, g_A, g_h, twiddle,
+                     taps_reversed, M, n_t, logn);
   return 0;
 }
 

@@ -240,6 +240,11 @@ void launch_das_adjoint(const float2* g_iq, float2* g_A, const ProbeView& p, con
                         const TxTable& tx, int n_tx_group, int tx_base, hipStream_t s);
 int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddle, int n_t,
                             long n_rows, hipStream_t s);
+// launch_analytic_adjoint followed by launch_pulse_adjoint with the same
+// reversed taps, in one kernel per RF row (the real row between them stays in
+// LDS): g_h = P^T Re(T g_A), bit for bit the two-launch result.
+int launch_analytic_pulse_adjoint(const float2* g_A, float* g_h, const float2* twiddle, const float* taps_reversed,
+                                  int M, int n_t, long n_rows, hipStream_t s);
 // acc: an order-independent accumulator of kSumWords words, zeroed by the caller
 void launch_image_loss(const float* b, const float* ref, long n, double l1, double l2,
                        unsigned long long* acc, double* loss, float* gb, hipStream_t s);
