@@ -516,12 +516,26 @@ int bin_rows(int n_tx, const us_probe* p) {
   return rows <= kMaxBinRows && p->d.n_t < kMaxBinSamples ? (int)rows : 0;
 }
 
+// Keys of the receiver-segment sort: target element, origin cell.
+long sort_keys(const us_probe* p) { return (long)p->d.n_elem * kSortCellsZ * kSortCellsX; }
+
+// The origin cells span twice the aperture either side of its centre and
+// the depth the record reaches at c_ref.
+SegSort seg_sort(const us_probe* p) {
+  const us_probe_desc& d = p->d;
+  const double half = 0.5 * d.n_elem * d.pitch;
+  const double depth = 0.5 * d.n_t / d.fs * d.c_ref;
+  return SegSort{(int)sort_keys(p), -2.0 * half, kSortCellsX / (4.0 * half), kSortCellsZ / depth};
+}
+
 size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {
   Carver c{nullptr};
   c.take<long long>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   c.take<unsigned long long>((size_t)max_bounces + 5 + kDepShards);
   const int rows = bin_rows(n_tx, p);
   if (rows > 0) c.take<char>(splat_scratch_bytes(rows));
+  c.take<uint32_t>((size_t)sort_keys(p));
+  c.take<uint32_t>((size_t)kSortBlocks);
   return c.off;
 }
 
@@ -537,9 +551,7 @@ void carve_ray_queue(Carver& c, long cap, RayQueue* q) {
 void carve_queues(Carver& c, long cap, RayQueue* q0, RayQueue* q1, SecondaryQueue* nq) {
   carve_ray_queue(c, cap, q0);
   carve_ray_queue(c, cap, q1);
-  nq->x = c.take<double>(cap); nq->y = c.take<double>(cap); nq->z = c.take<double>(cap);
-  nq->t = c.take<double>(cap); nq->amp = c.take<double>(cap);
-  nq->rid = c.take<uint32_t>(cap); nq->meta = c.take<uint32_t>(cap); nq->txk = c.take<uint32_t>(cap);
+  nq->rec = c.take<SecRec>(cap);
 }
 
 // Rays per chunk of the replay backward when the caller sizes the workspace
@@ -566,7 +578,8 @@ struct ReplaySums {
 size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_bounces, long cap,
                     ReplayStack* k = nullptr, char* base = nullptr, float** gh = nullptr,
                     float** gh_f0 = nullptr, ReplaySums* sums = nullptr, RayQueue* q0 = nullptr,
-                    RayQueue* q1 = nullptr, unsigned long long** counts = nullptr) {
+                    RayQueue* q1 = nullptr, unsigned long long** counts = nullptr,
+                    uint32_t** sort_count = nullptr, uint32_t** sort_part = nullptr) {
   Carver c{base};
   float* g = c.take<float>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   if (gh) *gh = g;
@@ -586,6 +599,14 @@ size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_
   r.last = c.take<int>((size_t)cap);
   r.queue = c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1));
   r.queue_begin = c.take<unsigned long long>((size_t)max_bounces + 1);
+  // receiver segments in key order (scenes with meshes and diffuse surfaces)
+  const bool sort = scene->n_meshes > 0 && scene->any_diffuse;
+  r.sort_kr = sort ? c.take<uint2>((size_t)cap * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
+  r.sort_q = sort ? c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
+  uint32_t* sc = sort ? c.take<uint32_t>((size_t)sort_keys(p) * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
+  uint32_t* sp = sort ? c.take<uint32_t>((size_t)kSortBlocks) : nullptr;
+  if (sort_count) *sort_count = sc;
+  if (sort_part) *sort_part = sp;
   unsigned long long* cn = c.take<unsigned long long>((size_t)max_bounces + 2);
   if (counts) *counts = cn;
   RayQueue ta, tb;
@@ -663,8 +684,15 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   const int rows = bin_rows(n_tx, probe);
   void* bin_scratch = rows > 0 ? (void*)c.take<char>(splat_scratch_bytes(rows)) : nullptr;
   TraceArgs a{};
+  a.sort_count = c.take<uint32_t>((size_t)sort_keys(probe));
+  a.sort_part = c.take<uint32_t>((size_t)kSortBlocks);
   carve_queues(c, cap, &a.qin, &a.qout, &a.nee);
   const RayQueue q0 = a.qin, q1 = a.qout;
+  // receiver segments marched in key order on mesh scenes (the walk is what
+  // they spend their time on); the permutation lies over the interaction's
+  // dead input queue
+  const bool sort = scene->n_meshes > 0 && scene->any_diffuse;
+  if (sort) a.sort = seg_sort(probe);
   a.dep.key = c.take<uint32_t>((size_t)kDepositsPerRay * cap);
   a.dep.w = c.take<float2>((size_t)kDepositsPerRay * cap);
   a.dep_count = counts + max_bounces + 4;
@@ -712,11 +740,17 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
       a.qin = q0;
       a.qout = q1;
       for (int k = 1; k <= max_bounces + 1; ++k) {
+        if (sort && k <= max_bounces) launch_fill_u32(a.sort_count, a.sort.keys, 0u, s);
         {
           Timed tm(ctx, "bounce", s);
           launch_bounce(a, k, n, audit, s);
         }
         if (k <= max_bounces && scene->any_diffuse) {
+          if (sort) {
+            a.sort_perm = reinterpret_cast<uint32_t*>(a.qin.ox);   // bounce k has consumed its input queue
+            Timed tm(ctx, "secondary_sort", s);
+            launch_secondary_sort(a, k, n, s);
+          }
           Timed tm(ctx, "secondary", s);
           launch_secondary(a, k, n, audit, s);
         }
@@ -1022,7 +1056,8 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   RayQueue q0, q1;
   ReplaySums sums;
   replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &sums, &q0, &q1,
-               &a.counts);
+               &a.counts, &a.sort_count, &a.sort_part);
+  if (a.sort_count) a.sort = seg_sort(probe);
   a.vadj = sums.vadj;
   a.g_sum = sums.g_sum;
   a.acq_sum = sums.acq_sum;
@@ -1068,6 +1103,7 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
       const long n = std::min(cap, n_group - g0);
       a.g0 = g0;
       launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);
+      if (a.sort.keys > 0) launch_fill_u32(a.sort_count, (long)a.sort.keys * max_bounces, 0u, s);
       {
         Timed tm(ctx, "replay_forward", s);
         for (int k = 1; k <= max_bounces + 1; ++k) {
@@ -1079,6 +1115,7 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
       {
         Timed tm(ctx, "replay_secondary", s);
         launch_replay_prefix(a, s);
+        launch_replay_sort(a, n * std::max(1, max_bounces), s);
         launch_replay_secondary(a, n * std::max(1, max_bounces), s);
       }
       {

@@ -16,13 +16,43 @@ struct RayQueue {
 constexpr size_t kRayQueueBytesPerRay = 8 * sizeof(double) + 2 * sizeof(uint32_t);
 
 // Secondary-ray queue.
-struct SecondaryQueue {
-  double *x, *y, *z, *t, *amp;
-  uint32_t* rid;
-  uint32_t* meta;   // region (8 bits) | element << 8
-  uint32_t* txk;    // transmit (local, 16 bits) | interaction index << 16
+// Receiver-directed secondary ray queued by the bounce kernel: one 64-byte
+// record (written and read as four 16-byte pieces, moved whole by the sort).
+struct alignas(16) SecRec {
+  double x, y, z, t, amp;
+  uint32_t rid;
+  uint32_t meta;   // region (8 bits) | element << 8
+  uint32_t txk;    // transmit (local, 16 bits) | interaction index << 16
+  uint32_t key;    // sort key (scenes that sort their receiver segments), else 0
+  uint32_t rank;   // the record's place among those of its key (likewise)
+  uint32_t pad;
 };
-constexpr size_t kSecondaryBytesPerRay = 5 * sizeof(double) + 3 * sizeof(uint32_t);
+static_assert(sizeof(SecRec) == 64, "secondary record layout");
+struct SecondaryQueue {
+  SecRec* rec;
+};
+constexpr size_t kSecondaryBytesPerRay = sizeof(SecRec);
+
+// Receiver segments are marched in the order of a key, so that a wave takes
+// segments that run close together through the same part of the hierarchy
+// (in queue order its 64 segments head for random elements from scattered
+// origins, and the wave waits for its longest walk): the target element, then
+// the cell of the origin on a kSortCellsZ x kSortCellsX grid over x in
+// [x0, x0 + kSortCellsX / inv_dx) and z in [0, kSortCellsZ / inv_dz) (points
+// outside go to the edge cells). keys = 0: queue order.
+constexpr int kSortCellsX = 32, kSortCellsZ = 32;
+constexpr int kSortBlocks = 256;   // tiles of the offsets' scan
+struct SegSort {
+  int keys;
+  double x0, inv_dx, inv_dz;
+  __device__ __forceinline__ uint32_t key(double x, double z, int e2) const {
+    const int cx = (int)fmin(fmax(floor((x - x0) * inv_dx), 0.0), (double)(kSortCellsX - 1));
+    const int cz = (int)fmin(fmax(floor(z * inv_dz), 0.0), (double)(kSortCellsZ - 1));
+    return ((uint32_t)e2 * kSortCellsZ + (uint32_t)cz) * kSortCellsX + (uint32_t)cx;
+  }
+};
+// count[0..n) -> its exclusive prefix sums, in place (part: kSortBlocks words).
+void launch_sort_offsets(uint32_t* count, int n, uint32_t* part, hipStream_t s);
 
 struct TraceArgs {
   SceneView scene;
@@ -51,6 +81,16 @@ struct TraceArgs {
   unsigned long long* dep_count;
   unsigned long long* counters;   // optional int64[5]
   unsigned long long* hash;       // optional [n_tx][ray_count]
+  // With sort.keys > 0 the receiver segments of each interaction are
+  // marched in key order: the bounce kernel counts the keys in
+  // sort_count[sort.keys] (zeroed before it) and keeps each record's rank
+  // among its key's; launch_secondary_sort turns the counts into offsets
+  // (sort_part: kSortBlocks words) and writes the permutation sort_perm
+  // (record index in key order, over the interaction's dead input queue).
+  SegSort sort;
+  uint32_t* sort_count;
+  uint32_t* sort_part;
+  uint32_t* sort_perm;
 };
 
 // Step record of the replay: the exact state before step k of a ray and the
@@ -76,6 +116,11 @@ struct ReplayStack {
   int* last;                                     // [cap] last step that can carry a deposit
   uint32_t* queue;          // [max_bounces][cap]: chunk rays of the diffuse interactions of step k
   unsigned long long* queue_begin;   // [max_bounces + 1]: exclusive prefix of the step sizes
+  // with ReplayArgs::sort.keys > 0: each queued interaction's (key, rank
+  // among the step's entries of that key) [max_bounces][cap], and the queue
+  // in key order within each step, indexed like queue_begin
+  uint2* sort_kr;
+  uint32_t* sort_q;
 };
 constexpr int kMaxReplayBlocks = 2048;
 struct ReplayArgs {
@@ -97,6 +142,12 @@ struct ReplayArgs {
   unsigned long long* vadj;    // [kVadjCopies][kSumWords][vadj_stride] mesh vertex adjoints along vnormal (zeroed per call)
   long vadj_stride;
   ReplayStack stk;
+  // receiver segments of the secondary phase in key order (as the forward
+  // marches them): counts per (step, key) [max_bounces][sort.keys], zeroed
+  // before the forward phase, then offsets (sort_part: kSortBlocks words)
+  SegSort sort;
+  uint32_t* sort_count;
+  uint32_t* sort_part;
   RayQueue qin, qout;     // live rays of the forward phase (rid holds the chunk index)
   unsigned long long* counts;   // [max_bounces + 2]: survivors of step k | diffuse interactions << 32
   // optional (null): d/d steering angle of each transmit (tx_base + local
@@ -120,6 +171,8 @@ struct ReplayArgs {
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s);
 void launch_replay_prefix(const ReplayArgs& a, hipStream_t s);
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s);
+// With sort.keys > 0, after the prefix: the queue in key order (stk.sort_q).
+void launch_replay_sort(const ReplayArgs& a, long max_entries, hipStream_t s);
 void launch_replay_reverse(const ReplayArgs& a, long n, hipStream_t s);
 // g_theta[j] += total of g_sum entry j (j < n_grad); with g_acq, also
 // g_acq[i] += total of acq_sum entry i (i < n_acq), the f0 entry f0_at taking
@@ -204,6 +257,9 @@ int launch_splat_pulse(const uint4* sorted, const void* scratch, uint32_t row0, 
                        int M, float* rf, hipStream_t s);
 void launch_bounce(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
 void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipStream_t s);
+// Counting sort of interaction k's receiver segments by key into sort_perm
+// (with sort_keys > 0); launch_secondary then marches them in that order.
+void launch_secondary_sort(const TraceArgs& a, int k, long max_rays, hipStream_t s);
 int launch_pulse(const float* h, float* rf, const float* taps, int M, int n_t, long n_rows,
                  hipStream_t s);
 // The same FIR from the fixed-point histogram: samples h / hist_scale (NaN

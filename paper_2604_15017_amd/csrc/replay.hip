@@ -482,6 +482,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
     uint32_t ci = 0;   // chunk index of the ray
     int region = 0;
     bool delta = true, keep = false, diffuse = false;
+    uint32_t skey = 0;   // sort key of a diffuse interaction's receiver segment
     if (active) {
       if (k == 1) {
         ci = (uint32_t)iq;
@@ -558,11 +559,19 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
         a.stk.last[ci] = k;
         keep = alive;
         diffuse = st.sf.kd > 0.0;
+        if (diffuse && a.sort.keys > 0)
+          skey = a.sort.key(st.x.x, st.x.z, min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1));
       }
     }
     const Slots sl = block_append2(keep, diffuse, &a.counts[k], scan);
     const long slot = sl.a;
-    if (sl.b >= 0) a.stk.queue[(long)(k - 1) * cap + sl.b] = ci;
+    if (sl.b >= 0) {
+      a.stk.queue[(long)(k - 1) * cap + sl.b] = ci;
+      if (a.sort.keys > 0) {
+        const uint32_t rank = atomicAdd(a.sort_count + (long)(k - 1) * a.sort.keys + skey, 1u);
+        a.stk.sort_kr[(long)(k - 1) * cap + sl.b] = make_uint2(skey, rank);
+      }
+    }
     if (slot >= 0) {
       a.qout.ox[slot] = o.x; a.qout.oy[slot] = o.y; a.qout.oz[slot] = o.z;
       a.qout.dx[slot] = d.x; a.qout.dy[slot] = d.y; a.qout.dz[slot] = d.z;
@@ -585,6 +594,23 @@ __global__ void k_replay_prefix(ReplayArgs a) {
   for (int k = 1; k <= a.max_bounces; ++k) {
     run += a.counts[k] >> 32;
     a.stk.queue_begin[k] = run;
+  }
+}
+
+// Queued interaction q (step k, slot q - queue_begin[k - 1]) to its place in
+// key order: the offset of (k, key) plus its rank.
+__global__ __launch_bounds__(256) void k_replay_sort_scatter(ReplayArgs a) {
+  const int B = a.max_bounces;
+  const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
+    int k = 1, hi = B;
+    while (k < hi) {
+      const int mid = (k + hi + 1) >> 1;
+      if ((long)a.stk.queue_begin[mid - 1] <= q) k = mid; else hi = mid - 1;
+    }
+    const long e = (long)(k - 1) * a.cap + (q - (long)a.stk.queue_begin[k - 1]);
+    const uint2 kr = a.stk.sort_kr[e];
+    a.stk.sort_q[a.sort_count[(long)(k - 1) * a.sort.keys + kr.x] + kr.y] = a.stk.queue[e];
   }
 }
 
@@ -634,7 +660,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
       const int mid = (k + hi + 1) >> 1;
       if ((long)a.stk.queue_begin[mid - 1] <= q) k = mid; else hi = mid - 1;
     }
-    const uint32_t i = a.stk.queue[(long)(k - 1) * cap + (q - (long)a.stk.queue_begin[k - 1])];
+    const uint32_t i = a.sort.keys > 0 ? a.stk.sort_q[q]
+                                       : a.stk.queue[(long)(k - 1) * cap + (q - (long)a.stk.queue_begin[k - 1])];
     const long at = (long)(k - 1) * cap + i;
     int txl;
     uint32_t rid;
@@ -948,6 +975,13 @@ void launch_replay_secondary(const ReplayArgs& a0, long max_entries, hipStream_t
 
 void launch_replay_prefix(const ReplayArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_replay_prefix, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_replay_sort(const ReplayArgs& a, long max_entries, hipStream_t s) {
+  if (a.sort.keys <= 0 || a.max_bounces <= 0) return;
+  launch_sort_offsets(a.sort_count, a.max_bounces * a.sort.keys, a.sort_part, s);
+  hipLaunchKernelGGL(k_replay_sort_scatter, dim3(replay_grid(max_entries, kMaxReplayForwardBlocks)), dim3(256), 0,
+                     s, a);
 }
 
 void launch_grad_finish(const unsigned long long* g_sum, int n_grad, double* g_theta,

@@ -194,11 +194,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     }
     const long ns = sl.b;
     if (ns >= 0) {
-      a.nee.x[ns] = x.x; a.nee.y[ns] = x.y; a.nee.z[ns] = x.z;
-      a.nee.t[ns] = t; a.nee.amp[ns] = nee_amp;
-      a.nee.rid[ns] = rid;
-      a.nee.meta[ns] = (uint32_t)incident_region | ((uint32_t)nee_e << 8);
-      a.nee.txk[ns] = (uint32_t)txl | ((uint32_t)k << 16);
+      const uint32_t meta = (uint32_t)incident_region | ((uint32_t)nee_e << 8);
+      uint32_t key = 0, rank = 0;
+      if (a.sort.keys > 0) {   // counted for the sort of the receiver segments
+        key = a.sort.key(x.x, x.z, nee_e);
+        rank = atomicAdd(a.sort_count + key, 1u);
+      }
+      a.nee.rec[ns] = SecRec{x.x, x.y, x.z, t, nee_amp, rid, meta, (uint32_t)txl | ((uint32_t)k << 16), key, rank, 0u};
     }
   }
   if (a.counters) flush_counters(a.counters, n_seg, 0, n_dep, n_int, 0);
@@ -221,9 +223,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
   unsigned long long n_seg = 0, n_dep = 0, n_rays = 0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += (long)gridDim.x * blockDim.x) {
     ++n_rays;
-    const d3 x{a.nee.x[i], a.nee.y[i], a.nee.z[i]};
-    double tof = a.nee.t[i], amp = a.nee.amp[i];
-    const uint32_t meta = a.nee.meta[i], txk = a.nee.txk[i];
+    const SecRec q = a.nee.rec[a.sort.keys > 0 ? (long)a.sort_perm[i] : i];
+    const d3 x{q.x, q.y, q.z};
+    double tof = q.t, amp = q.amp;
+    const uint32_t meta = q.meta, txk = q.txk;
     const int reg = meta & 0xFF;
     const int e2 = (int)(meta >> 8);
     const int txl = (int)(txk & 0xFFFF);
@@ -259,11 +262,70 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
     if (kAudit) {
       const uint32_t word = blocked ? ((uint32_t)e2 | (3u << 16) | (crossings << 20))
                                     : ((uint32_t)e2 | (crossings << 20));
-      atomicAdd(a.hash + (long)(a.tx_base + txl) * a.ray_count + (a.nee.rid[i] - a.ray_begin),
+      atomicAdd(a.hash + (long)(a.tx_base + txl) * a.ray_count + (q.rid - a.ray_begin),
                 (unsigned long long)event_mix(kEvNee, txk >> 16, word));
     }
   }
   if (a.counters) flush_counters(a.counters, 0, n_seg, n_dep, 0, n_rays);
+}
+
+// Exclusive scan in place over kSortBlocks contiguous tiles: tile sums, their
+// scan (one block), then each tile scanned from its offset.
+__device__ __forceinline__ uint32_t block_scan256(uint32_t v, uint32_t* total) {
+  __shared__ uint32_t part[256];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {   // inclusive Hillis-Steele scan
+    const uint32_t u = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += u;
+    __syncthreads();
+  }
+  const uint32_t r = part[threadIdx.x] - v;
+  *total = part[255];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_sort_tile_sums(const uint32_t* count, int n, uint32_t* part) {
+  const int per = (n + kSortBlocks - 1) / kSortBlocks;
+  const int b = blockIdx.x * per, e = min(n, b + per);
+  uint32_t s = 0;
+  for (int i = b + threadIdx.x; i < e; i += blockDim.x) s += count[i];
+  uint32_t tot;
+  block_scan256(s, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_sort_tile_offsets(uint32_t* part) {
+  uint32_t tot;
+  part[threadIdx.x] = block_scan256(part[threadIdx.x], &tot);   // kSortBlocks == 256
+}
+
+__global__ __launch_bounds__(256) void k_sort_tile_scan(uint32_t* count, int n, const uint32_t* part) {
+  const int per = (n + kSortBlocks - 1) / kSortBlocks;
+  const int b = blockIdx.x * per, e = min(n, b + per);
+  uint32_t base = part[blockIdx.x];
+  for (int i0 = b; i0 < e; i0 += blockDim.x) {
+    const int i = i0 + threadIdx.x;
+    const uint32_t c = i < e ? count[i] : 0u;
+    uint32_t tot;
+    const uint32_t x = block_scan256(c, &tot);
+    if (i < e) count[i] = base + x;
+    base += tot;
+  }
+}
+
+// Receiver segments of interaction k in key order: index i to its key's
+// offset plus its rank (counted by the bounce kernel as it queued the record;
+// the order within a key is the atomics' order, and nothing downstream
+// depends on it: deposits are integer sums, counters and hashes are sums).
+__global__ __launch_bounds__(256) void k_sec_scatter(TraceArgs a, int k) {
+  const long n_in = (long)(a.counts[k] >> 32);
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += (long)gridDim.x * blockDim.x) {
+    const uint2 kr = *reinterpret_cast<const uint2*>(&a.nee.rec[i].key);
+    a.sort_perm[a.sort_count[kr.x] + kr.y] = (uint32_t)i;
+  }
 }
 
 // rf[row][k] = sum_{|m| <= M} h[row][k - m] s[m]  (Eq. axial_sig as a FIR on
@@ -348,6 +410,18 @@ void launch_secondary(const TraceArgs& a, int k, long max_rays, bool audit, hipS
   const auto kern = audit ? (m ? k_secondary<true, true> : k_secondary<true, false>)
                           : (m ? k_secondary<false, true> : k_secondary<false, false>);
   hipLaunchKernelGGL(kern, grid, block, stack_bytes(a), s, a, k);
+}
+
+void launch_sort_offsets(uint32_t* count, int n, uint32_t* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_tile_sums, dim3(kSortBlocks), dim3(256), 0, s, count, n, part);
+  hipLaunchKernelGGL(k_sort_tile_offsets, dim3(1), dim3(kSortBlocks), 0, s, part);
+  hipLaunchKernelGGL(k_sort_tile_scan, dim3(kSortBlocks), dim3(256), 0, s, count, n, part);
+}
+
+void launch_secondary_sort(const TraceArgs& a, int k, long max_rays, hipStream_t s) {
+  if (a.sort.keys <= 0) return;
+  launch_sort_offsets(a.sort_count, a.sort.keys, a.sort_part, s);
+  hipLaunchKernelGGL(k_sec_scatter, dim3(grid_for(max_rays, 256, kMaxBlocks)), dim3(256), 0, s, a, k);
 }
 
 static int pulse(const PulseIn& in, float* rf, const float* taps, int M, int n_t, long n_rows, hipStream_t s) {
