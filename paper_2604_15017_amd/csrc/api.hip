@@ -516,7 +516,7 @@ int bin_rows(int n_tx, const us_probe* p) {
   return rows <= kMaxBinRows && p->d.n_t < kMaxBinSamples ? (int)rows : 0;
 }
 
-// Keys of the receiver-segment sort: target element, origin cell.
+// Keys of the receiver-segment sort: origin cell, target element.
 long sort_keys(const us_probe* p) { return (long)p->d.n_elem * kSortCellsZ * kSortCellsX; }
 
 // The origin cells span twice the aperture either side of its centre and
@@ -525,7 +525,7 @@ SegSort seg_sort(const us_probe* p) {
   const us_probe_desc& d = p->d;
   const double half = 0.5 * d.n_elem * d.pitch;
   const double depth = 0.5 * d.n_t / d.fs * d.c_ref;
-  return SegSort{(int)sort_keys(p), -2.0 * half, kSortCellsX / (4.0 * half), kSortCellsZ / depth};
+  return SegSort{(int)sort_keys(p), d.n_elem, -2.0 * half, kSortCellsX / (4.0 * half), kSortCellsZ / depth};
 }
 
 size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {

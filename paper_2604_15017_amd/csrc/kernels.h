@@ -36,19 +36,20 @@ constexpr size_t kSecondaryBytesPerRay = sizeof(SecRec);
 // Receiver segments are marched in the order of a key, so that a wave takes
 // segments that run close together through the same part of the hierarchy
 // (in queue order its 64 segments head for random elements from scattered
-// origins, and the wave waits for its longest walk): the target element, then
-// the cell of the origin on a kSortCellsZ x kSortCellsX grid over x in
-// [x0, x0 + kSortCellsX / inv_dx) and z in [0, kSortCellsZ / inv_dz) (points
-// outside go to the edge cells). keys = 0: queue order.
-constexpr int kSortCellsX = 32, kSortCellsZ = 32;
+// origins, and the wave waits for its longest walk): the cell of the origin
+// on a kSortCellsZ x kSortCellsX grid over x in [x0, x0 + kSortCellsX /
+// inv_dx) and z in [0, kSortCellsZ / inv_dz) (points outside go to the edge
+// cells), then the target element. keys = 0: queue order.
+constexpr int kSortCellsX = 64, kSortCellsZ = 64;
 constexpr int kSortBlocks = 256;   // tiles of the offsets' scan
 struct SegSort {
-  int keys;
+  int keys;               // cells x n_elem
+  int n_elem;
   double x0, inv_dx, inv_dz;
   __device__ __forceinline__ uint32_t key(double x, double z, int e2) const {
     const int cx = (int)fmin(fmax(floor((x - x0) * inv_dx), 0.0), (double)(kSortCellsX - 1));
     const int cz = (int)fmin(fmax(floor(z * inv_dz), 0.0), (double)(kSortCellsZ - 1));
-    return ((uint32_t)e2 * kSortCellsZ + (uint32_t)cz) * kSortCellsX + (uint32_t)cx;
+    return ((uint32_t)cz * kSortCellsX + (uint32_t)cx) * (uint32_t)n_elem + (uint32_t)e2;
   }
 };
 // count[0..n) -> its exclusive prefix sums, in place (part: kSortBlocks words).
