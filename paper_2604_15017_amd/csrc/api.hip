@@ -528,14 +528,19 @@ SegSort seg_sort(const us_probe* p) {
   return SegSort{(int)sort_keys(p), d.n_elem, -2.0 * half, kSortCellsX / (4.0 * half), kSortCellsZ / depth};
 }
 
-size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces) {
+// Scenes with meshes march their receiver segments in key order.
+bool sorts_segments(const us_scene* scene) { return scene->n_meshes > 0 && scene->any_diffuse; }
+
+size_t trace_fixed_bytes(int n_tx, const us_probe* p, int max_bounces, bool sorts) {
   Carver c{nullptr};
   c.take<long long>((size_t)n_tx * p->d.n_elem * p->d.n_t);
   c.take<unsigned long long>((size_t)max_bounces + 5 + kDepShards);
   const int rows = bin_rows(n_tx, p);
   if (rows > 0) c.take<char>(splat_scratch_bytes(rows));
-  c.take<uint32_t>((size_t)sort_keys(p));
-  c.take<uint32_t>((size_t)kSortBlocks);
+  if (sorts) {
+    c.take<uint32_t>((size_t)sort_keys(p));
+    c.take<uint32_t>((size_t)kSortBlocks);
+  }
   return c.off;
 }
 
@@ -600,7 +605,7 @@ size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_
   r.queue = c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1));
   r.queue_begin = c.take<unsigned long long>((size_t)max_bounces + 1);
   // receiver segments in key order (scenes with meshes and diffuse surfaces)
-  const bool sort = scene->n_meshes > 0 && scene->any_diffuse;
+  const bool sort = sorts_segments(scene);
   r.sort_kr = sort ? c.take<uint2>((size_t)cap * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
   r.sort_q = sort ? c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
   uint32_t* sc = sort ? c.take<uint32_t>((size_t)sort_keys(p) * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
@@ -651,7 +656,7 @@ size_t us_simulate_rf_workspace_size(const us_scene* scene, const us_probe* prob
   const int group = n_tx < kMaxTxPerLaunch ? n_tx : kMaxTxPerLaunch;
   long chunk = (long)std::min<int64_t>((int64_t)group * ray_count, kDefaultChunk);
   if (chunk < 256) chunk = 256;
-  return trace_fixed_bytes(n_tx, probe, max_bounces) + queue_bytes(chunk);
+  return trace_fixed_bytes(n_tx, probe, max_bounces, sorts_segments(scene)) + queue_bytes(chunk);
 }
 
 int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
@@ -661,7 +666,8 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   US_CHECK(ctx && rf_dev && ws_dev, "us_simulate_rf: NULL ctx, rf or workspace");
   int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
-  const size_t fixed = trace_fixed_bytes(n_tx, probe, max_bounces);
+  const bool sort = sorts_segments(scene);
+  const size_t fixed = trace_fixed_bytes(n_tx, probe, max_bounces, sort);
   // largest chunk whose queues fit in the workspace
   long cap = 0;
   {
@@ -684,14 +690,15 @@ int us_simulate_rf(us_ctx* ctx, const us_scene* scene, const us_probe* probe, co
   const int rows = bin_rows(n_tx, probe);
   void* bin_scratch = rows > 0 ? (void*)c.take<char>(splat_scratch_bytes(rows)) : nullptr;
   TraceArgs a{};
-  a.sort_count = c.take<uint32_t>((size_t)sort_keys(probe));
-  a.sort_part = c.take<uint32_t>((size_t)kSortBlocks);
+  if (sort) {
+    a.sort_count = c.take<uint32_t>((size_t)sort_keys(probe));
+    a.sort_part = c.take<uint32_t>((size_t)kSortBlocks);
+  }
   carve_queues(c, cap, &a.qin, &a.qout, &a.nee);
   const RayQueue q0 = a.qin, q1 = a.qout;
   // receiver segments marched in key order on mesh scenes (the walk is what
   // they spend their time on); the permutation lies over the interaction's
   // dead input queue
-  const bool sort = scene->n_meshes > 0 && scene->any_diffuse;
   if (sort) a.sort = seg_sort(probe);
   a.dep.key = c.take<uint32_t>((size_t)kDepositsPerRay * cap);
   a.dep.w = c.take<float2>((size_t)kDepositsPerRay * cap);
