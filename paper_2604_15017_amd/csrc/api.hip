@@ -604,8 +604,9 @@ size_t replay_bytes(const us_scene* scene, int n_tx, const us_probe* p, int max_
   r.last = c.take<int>((size_t)cap);
   r.queue = c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1));
   r.queue_begin = c.take<unsigned long long>((size_t)max_bounces + 1);
-  // receiver segments in key order (scenes with meshes and diffuse surfaces)
-  const bool sort = sorts_segments(scene);
+  // receiver segments in key order (scenes with meshes and diffuse surfaces;
+  // the per-step key counts are held to 2^26 words, else queue order)
+  const bool sort = sorts_segments(scene) && (long)sort_keys(p) * std::max(1, max_bounces) <= (1L << 26);
   r.sort_kr = sort ? c.take<uint2>((size_t)cap * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
   r.sort_q = sort ? c.take<uint32_t>((size_t)cap * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
   uint32_t* sc = sort ? c.take<uint32_t>((size_t)sort_keys(p) * (max_bounces > 0 ? max_bounces : 1)) : nullptr;
