@@ -6,10 +6,10 @@
 // h[tx][elem][sample] (int64 units, integer atomics: the sums do not depend on
 // the order of the additions); a final FIR applies the pulse of Eq. axial_sig.
 //
-// Precision: positions, directions, times and weights are fp64 (MI355X runs
-// fp64 vector math at half the fp32 rate). A time error dt costs 2 pi f0 dt of
-// phase, and the parity bound on RF needs dt of a few ps over paths tens of
-// millimetres long, which fp32 geometry cannot hold.
+// Precision: positions, directions, times and weights are fp64 (MI355X issues
+// an fp64 FMA at the rate of an unpacked fp32 one). A time error dt costs
+// 2 pi f0 dt of phase, and the parity bound on RF needs dt of a few ps over
+// paths tens of millimetres long, which fp32 geometry cannot hold.
 #include "kernels.h"
 #include "fir.h"
 #include "geometry.h"
