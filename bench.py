@@ -47,11 +47,12 @@ def kernel_bytes(name, wl, counts, n_px):
         # surviving ray writes one, every diffuse hit writes a secondary record
         "bounce": 2 * state * (seg_p - rays) + sec_rec * sec,
         # each secondary record is read once; each deposit writes a 12-byte
-        # record for the binned splat (scenes with meshes: two fp32 bins)
-        "secondary": sec_rec * sec + (8 if has_meshes else 12) * dep,
+        # record for the binned splat (scenes with meshes: two fp32 bins, and
+        # the record is found through a 4-byte permutation entry)
+        "secondary": (sec_rec + (4 if has_meshes else 0)) * sec + (8 if has_meshes else 12) * dep,
         # scenes with meshes: the receiver segments' counting sort reads each
-        # record's key fields (x, z, meta), then moves the 52-byte record
-        "secondary_sort": (20 + 2 * sec_rec) * sec if has_meshes else None,
+        # record's key and rank and writes its 4-byte permutation entry
+        "secondary_sort": (8 + 4) * sec if has_meshes else None,
         # binned splat (scenes without meshes): the counting pass reads each
         # record's 4-byte key, the scatter reads the 12-byte record and writes
         # it as 16 bytes; the accumulation reads the 16 bytes and updates every
