@@ -61,53 +61,66 @@ __device__ __forceinline__ double rec_distance(const TriRec r, d3 o, d3 d) {
   return dot(e2, qv) * inv;
 }
 
-// Four child boxes of node n against the ray, culled beyond lim, sorted by
-// entry distance (a five-exchange network); misses get INFINITY.
-__device__ __forceinline__ void node_children(const BvhNode& n, const SlabRay& q, float lim, float* t, int* r) {
+// Four child boxes of node n against the ray, culled beyond lim, as sort
+// keys ordered by entry distance: the distance's fp32 bits (non-negative, so
+// they order as integers) with the two low bits replaced by the child's
+// slot, sorted by a five-exchange network of integer min / max (children
+// closer than four ulps keep slot order). A missed child keys at or above
+// kMissKey, the bits of INFINITY.
+constexpr uint32_t kMissKey = 0x7F800000u;
+__device__ __forceinline__ void node_children(const BvhNode& n, const SlabRay& q, float lim, uint32_t* k) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const float lo[3] = {n.lox[j], n.loy[j], n.loz[j]}, hi[3] = {n.hix[j], n.hiy[j], n.hiz[j]};
     float tj;
-    t[j] = slab(lo, hi, q.oix, q.oiy, q.oiz, q.ix, q.iy, q.iz, lim, &tj) ? tj : INFINITY;
-    r[j] = n.child[j];
+    const float t = slab(lo, hi, q.oix, q.oiy, q.oiz, q.ix, q.iy, q.iz, lim, &tj) ? tj : INFINITY;
+    k[j] = (__float_as_uint(t) & 0x7FFFFFFCu) | (uint32_t)j;
   }
-#define USRT_CX(a, b)                                                      \
-  if (t[b] < t[a]) {                                                       \
-    const float tt = t[a]; t[a] = t[b]; t[b] = tt;                         \
-    const int rr = r[a]; r[a] = r[b]; r[b] = rr;                           \
+#define USRT_CX(a, b)                                   \
+  {                                                     \
+    const uint32_t lo_ = min(k[a], k[b]), hi_ = max(k[a], k[b]); \
+    k[a] = lo_; k[b] = hi_;                             \
   }
   USRT_CX(0, 1) USRT_CX(2, 3) USRT_CX(0, 2) USRT_CX(1, 3) USRT_CX(1, 2)
 #undef USRT_CX
+}
+
+// The child reference of a sort key.
+__device__ __forceinline__ int child_of(const BvhNode& n, uint32_t key) {
+  const bool odd = key & 1u;
+  const int c01 = odd ? n.child[1] : n.child[0], c23 = odd ? n.child[3] : n.child[2];
+  return key & 2u ? c23 : c01;
 }
 
 // Walk of the 4-wide hierarchy near child first. An inner node's four child
 // boxes are tested against the ray in fp32 and the hit children ordered by
 // entry distance: the nearest is visited next, the others pushed farthest
 // first. The stack lives in LDS, interleaved across the block's threads
-// (entry i of this thread at stk[i * blockDim.x]); it holds at most three
+// (entry i of this thread at stk[i * kWalkBlock]); it holds at most three
 // entries per inner level. The walk alternates two phases so that the lanes
 // of a wave run one kind of work at a time (Aila and Laine, HPG 2009): inner
 // nodes until every lane holds a leaf (a lane that meets a leaf sets it aside
 // and keeps walking), then the leaves. cull() is the distance beyond which
 // boxes are skipped; leaf(first, count) tests a leaf's triangles.
 constexpr int kWalkDone = 0x7FFFFFFF;
+constexpr int kWalkBlock = 256;   // threads per block of every kernel that walks (its stack LDS is sized so)
 
 template <class Cull, class Leaf>
 __device__ __forceinline__ void walk4(const SceneLDS& s, const SlabRay& q, int* stk, Cull cull, Leaf leaf) {
-  const int step = blockDim.x;
+  constexpr int step = kWalkBlock;
   int sp = 0, cur = 0, pend = 0;   // pend: a leaf set aside (leaf references are negative), 0 if none
   for (;;) {
     while ((unsigned)cur < (unsigned)kWalkDone) {   // an inner node
       const float lim = cull() * 1.0001f + kBoxPad;
-      float t[4];
-      int r[4];
-      node_children(gload(s.nodes + cur), q, lim, t, r);
-      if (t[0] != INFINITY) {
+      const BvhNode node = gload(s.nodes + cur);
+      uint32_t k[4];
+      node_children(node, q, lim, k);
+      if (k[0] < kMissKey) {
         // the build bounds the depth by stack_cap / 3, so the pushes always fit
-        if (t[3] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[3]; ++sp; }
-        if (t[2] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[2]; ++sp; }
-        if (t[1] != INFINITY && sp < s.stack_cap) { stk[sp * step] = r[1]; ++sp; }
-        cur = r[0];
+        if (k[3] < kMissKey && sp < s.stack_cap) { stk[sp * step] = child_of(node, k[3]); ++sp; }
+        if (k[2] < kMissKey && sp < s.stack_cap) { stk[sp * step] = child_of(node, k[2]); ++sp; }
+        if (k[1] < kMissKey && sp < s.stack_cap) { stk[sp * step] = child_of(node, k[1]); ++sp; }
+        cur = child_of(node, k[0]);
       } else {
         cur = sp > 0 ? stk[--sp * step] : kWalkDone;
       }
