@@ -45,16 +45,17 @@ __device__ __forceinline__ SlabRay slab_ray(d3 o, d3 d) {
 }
 
 // Moller-Trumbore in fp64 on a leaf-order triangle record, edges included;
-// distance or -1.
+// distance or -1. A zero determinant gives an infinite or NaN u, which the
+// first range test rejects (the test is written to reject NaN), so the whole
+// record is read before any branch.
 __device__ __forceinline__ double rec_distance(const TriRec r, d3 o, d3 d) {
   const d3 e1{r.e1[0], r.e1[1], r.e1[2]}, e2{r.e2[0], r.e2[1], r.e2[2]};
+  const d3 sv = o - d3{r.p0[0], r.p0[1], r.p0[2]};
   const d3 pv = cross(d, e2);
   const double det = dot(e1, pv);
-  if (det == 0.0) return -1.0;
   const double inv = 1.0 / det;
-  const d3 sv = o - d3{r.p0[0], r.p0[1], r.p0[2]};
   const double u = dot(sv, pv) * inv;
-  if (u < 0.0 || u > 1.0) return -1.0;
+  if (!(u >= 0.0 && u <= 1.0)) return -1.0;
   const d3 qv = cross(sv, e1);
   const double v = dot(d, qv) * inv;
   if (v < 0.0 || u + v > 1.0) return -1.0;
@@ -223,28 +224,25 @@ __device__ __forceinline__ int max_legs(const SceneLDS& s) {
 // same guard a per-leg closest-hit query from that point applies.
 constexpr int kSegHits = 4;
 struct SegHits {
-  double s[kSegHits];
-  int h[kSegHits];   // kind << 28 | index
+  double s[kSegHits];   // ascending; unused entries hold +infinity
+  int h[kSegHits];      // kind << 28 | index
   int n;
 };
 
+// Inserts s after the kept entries not greater than it, the last entry
+// dropping out (nothing changes when the list is full and s is not below its
+// last entry); selects only, no branches.
 __device__ __forceinline__ void seg_insert(SegHits& L, double s, int h) {
-  if (L.n == kSegHits && !(s < L.s[kSegHits - 1])) return;
-  double cs = s;
-  int ch = h;
 #pragma unroll
-  for (int j = 0; j < kSegHits; ++j) {
-    if (j < L.n) {
-      if (cs < L.s[j]) {
-        const double ts = L.s[j]; L.s[j] = cs; cs = ts;
-        const int th = L.h[j]; L.h[j] = ch; ch = th;
-      }
-    } else if (j == L.n) {
-      L.s[j] = cs;
-      L.h[j] = ch;
-    }
+  for (int j = kSegHits - 1; j > 0; --j) {
+    const bool shift = s < L.s[j - 1], here = s < L.s[j];
+    L.s[j] = shift ? L.s[j - 1] : here ? s : L.s[j];
+    L.h[j] = shift ? L.h[j - 1] : here ? h : L.h[j];
   }
-  L.n = L.n < kSegHits ? L.n + 1 : kSegHits;
+  const bool first = s < L.s[0];
+  L.s[0] = first ? s : L.s[0];
+  L.h[0] = first ? h : L.h[0];
+  L.n = min(L.n + 1, kSegHits);
 }
 
 __device__ __forceinline__ double seg_cull(const SegHits& L, double hi) {
@@ -255,6 +253,8 @@ template <bool kMeshes>
 __device__ __forceinline__ SegHits segment_hits(const SceneLDS& s, d3 x, d3 w, double lo, double hi,
                                                 int* stk) {
   SegHits L;
+#pragma unroll
+  for (int j = 0; j < kSegHits; ++j) { L.s[j] = INFINITY; L.h[j] = 0; }
   L.n = 0;
   const double smin = lo + kTMin;
   if (w.z != 0.0) {
