@@ -222,7 +222,7 @@ __device__ __forceinline__ int max_legs(const SceneLDS& s) {
 // farther crossings; the caller then walks again from its last crossing.
 // With lo the last crossing taken, a leg from it needs s > lo + kTMin, the
 // same guard a per-leg closest-hit query from that point applies.
-constexpr int kSegHits = 4;
+constexpr int kSegHits = 6;
 struct SegHits {
   double s[kSegHits];   // ascending; unused entries hold +infinity
   int h[kSegHits];      // kind << 28 | index
