@@ -45,9 +45,9 @@ __device__ __forceinline__ SlabRay slab_ray(d3 o, d3 d) {
 }
 
 // Moller-Trumbore in fp64 on a leaf-order triangle record, edges included;
-// distance or -1. A zero determinant gives an infinite or NaN u, which the
-// first range test rejects (the test is written to reject NaN), so the whole
-// record is read before any branch.
+// distance or -1. No branches: every quantity is formed and one select keeps
+// the distance (a zero determinant gives an infinite or NaN barycentric,
+// which the range tests, written to fail on NaN, reject).
 __device__ __forceinline__ double rec_distance(const TriRec r, d3 o, d3 d) {
   const d3 e1{r.e1[0], r.e1[1], r.e1[2]}, e2{r.e2[0], r.e2[1], r.e2[2]};
   const d3 sv = o - d3{r.p0[0], r.p0[1], r.p0[2]};
@@ -55,11 +55,10 @@ __device__ __forceinline__ double rec_distance(const TriRec r, d3 o, d3 d) {
   const double det = dot(e1, pv);
   const double inv = 1.0 / det;
   const double u = dot(sv, pv) * inv;
-  if (!(u >= 0.0 && u <= 1.0)) return -1.0;
   const d3 qv = cross(sv, e1);
   const double v = dot(d, qv) * inv;
-  if (v < 0.0 || u + v > 1.0) return -1.0;
-  return dot(e2, qv) * inv;
+  const double t = dot(e2, qv) * inv;
+  return (u >= 0.0 && u <= 1.0 && v >= 0.0 && u + v <= 1.0) ? t : -1.0;
 }
 
 // Four child boxes of node n against the ray, culled beyond lim, as sort
