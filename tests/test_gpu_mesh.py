@@ -139,6 +139,36 @@ def test_anatomy_phantom_ray_sample(L, ctx):
     check(L, ctx, wl, "anatomy phantom sample", ray_begin=400_003, ray_count=6000)
 
 
+def test_anatomy_phantom_full_frame(L, ctx):
+    """The headline workload as the benchmark runs it: 21 transmits x 798,912
+    rays (16,777,152) through the product kernels (no decision audit), the
+    audit kernels on the same frame, and the oracle's whole frame. The two GPU
+    runs give the same RF bit for bit (integer sums) and the same event counts;
+    the per-ray decision hashes agree with the oracle's on all but at most
+    1e-5 of the rays (then the counts must be the oracle's exactly); the RF is
+    within the tolerance."""
+    import torch
+    wl = W.anatomy_phantom()
+    scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
+    counters = torch.zeros(5, dtype=torch.int64, device="cuda")
+    rf = L.us_simulate_rf(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                          wl.max_bounces, counters=counters)
+    torch.cuda.synchronize()
+    rf, cnt = rf.cpu().numpy().astype(np.float64), counters.cpu().numpy()
+    rf_a, cnt_a, hashes = gpu_rf(L, ctx, wl)
+    assert np.array_equal(rf, rf_a) and np.array_equal(cnt, cnt_a)
+    ref, _, tr = oracle.simulate_rf(wl, want_hashes=True)
+    rel = rel_l2(rf, ref)
+    flips = int(np.count_nonzero(hashes != tr.hashes))
+    print(f"anatomy phantom, full frame: rf rel-L2 {rel:.3e}, flipped paths {flips}/{tr.hashes.size}, "
+          f"segments gpu {cnt[0] + cnt[1]} oracle {tr.segments}, deposits gpu {cnt[2]} oracle "
+          f"{tr.t.shape[0]}", flush=True)
+    assert flips / tr.hashes.size <= 1e-5
+    assert rel <= RF_TOL
+    if flips == 0:
+        assert cnt[0] + cnt[1] == tr.segments and cnt[2] == tr.t.shape[0]
+
+
 def smooth_field(shape, seed):
     rng = np.random.default_rng(seed)
     g = rng.standard_normal(shape)
