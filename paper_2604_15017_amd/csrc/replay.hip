@@ -460,7 +460,7 @@ __device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t,
 // their chunk index; the survivors are compacted into the next queue and
 // every interaction on a diffuse surface is queued for phase 2.
 template <bool kMeshes>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 3 : 4, 8)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_replay_forward(ReplayArgs a, int k, long n) {
   const long n_in = k == 1 ? n : (long)(uint32_t)a.counts[k - 1];   // survivors of step k - 1
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle

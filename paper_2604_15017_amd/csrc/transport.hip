@@ -39,7 +39,7 @@ __device__ __forceinline__ void flush_counters(unsigned long long* g, unsigned l
 
 // One interaction step for every live ray (k = 1 fuses the emission).
 template <bool kAudit, bool kMeshes>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_bounce(TraceArgs a, int k) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4 : 3, 8))) void k_bounce(TraceArgs a, int k) {
   const long n_in = k == 1 ? a.n_chunk : (long)(uint32_t)a.counts[k - 1];
   if ((long)blockIdx.x * blockDim.x >= n_in) return;   // whole block idle
   __shared__ SceneLDS S;
