@@ -374,7 +374,10 @@ void k_das_tiled(const float2* __restrict__ A, float2* __restrict__ iq, ProbeVie
   __shared__ TxSplit ts[kMaxTxPerLaunch];
   // kS slices of kDasThreads threads share the tile: slice sl takes the
   // sl-th run of pair groups, and the partial sums are added in slice order
-  const int sl = (int)threadIdx.x / kDasThreads, tid = (int)threadIdx.x % kDasThreads;
+  // the slice is uniform over each wave (kDasThreads is a multiple of 64), so
+  // the pair bookkeeping below stays in scalar registers
+  const int sl = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kDasThreads);
+  const int tid = (int)threadIdx.x % kDasThreads;
   const int n_tiles = tiles_x * tiles_z, per_xcd = (n_tiles + kXcds - 1) / kXcds;
   const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
   if (tile >= n_tiles) return;   // the whole block: the last band is short
