@@ -80,6 +80,11 @@ def kernel_bytes(name, wl, counts, n_px):
         # step records, those adjoints and dL/dh at the array hits
         "replay_forward": 2 * state * (seg_p - rays) + 80 * seg_p + 4 * sec,
         "replay_secondary": (4 + 80 + 8 + 80) * sec,
+        # a recorded forward: the replay's forward phase (array hits deposited
+        # in place), then per queued interaction its entry and step record read
+        # and the deposit made
+        "recorded_forward": 2 * state * (seg_p - rays) + 80 * seg_p + 4 * sec,
+        "recorded_deposit": (4 + 80) * sec + 8 * dep,
         "replay_reverse": 80 * seg_p + 80 * sec + 8 * (dep - sec),
         "analytic": 12 * row_samples,
         "das": 8 * row_samples + 8 * n_px,
@@ -386,6 +391,24 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
         L.us_frame_vjp(ctx, scene, probe, g, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
                        iq, g_b, wl.dr_db, g_theta=g_theta_f, workspace=ws_f, stream=stream)
 
+    # a recorded frame: the forward keeps the path records, and the one-call
+    # backward reads them instead of tracing the paths again
+    rec_bytes = L.us_recorded_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx, wl.max_bounces) \
+        if backward else 0
+    ws_rec = L._workspace(rec_bytes, dev) if rec_bytes else None
+    ws_fr = L._workspace(L.us_frame_vjp_recorded_workspace_size(probe, g, wl.n_tx), dev) if rec_bytes else None
+    g_theta_r = torch.zeros_like(g_theta)
+    rf_r = torch.empty_like(rf)
+
+    def step_fb_recorded():
+        _, rec = L.us_simulate_rf_recorded(ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                                           wl.max_bounces, rf=rf_r, workspace=ws_rec, stream=stream)
+        L.us_beamform(ctx, probe, g, wl.angles, wl.tx_ids, rf_r, iq=iq, workspace=ws_b, stream=stream)
+        L.us_bmode(ctx, iq, wl.dr_db, out=bm, workspace=ws_m, stream=stream)
+        L.us_image_loss(ctx, bm, b_ref, 0.0, 1.0, loss=loss, g_bmode=g_b, workspace=ws_l, stream=stream)
+        g_theta_r.zero_()
+        L.us_frame_vjp_recorded(ctx, rec, g, iq, g_b, wl.dr_db, g_theta=g_theta_r, workspace=ws_fr, stream=stream)
+
     step(cnt=counters)                  # event counts of one frame (deterministic)
     torch.cuda.synchronize()
     counts = [int(v) for v in counters.cpu().numpy()]
@@ -428,10 +451,24 @@ def frame_legs(ctx, wl, target, steps, warmup, backward=True):
                  "plain_ms_per_step": round(fb_ms, 4), "speedup_vs_plain": round(fb_ms / fused_ms, 4),
                  "gradient_bitwise_equal_to_plain": bool(torch.equal(g_theta, g_theta_f)),
                  "kernels": kernel_table(prof_fused)}
+    recorded = None
+    if rec_bytes:
+        rec_ms, prof_rec = timed(step_fb_recorded)
+        step_fb()
+        torch.cuda.synchronize()
+        rf_plain = rf.clone()
+        step_fb_recorded()
+        torch.cuda.synchronize()
+        recorded = {"ms_per_step": round(rec_ms, 4), "frames_per_s": round(1e3 / rec_ms, 2),
+                    "plain_ms_per_step": round(fb_ms, 4), "speedup_vs_plain": round(fb_ms / rec_ms, 4),
+                    "record_GB": round(rec_bytes / 1e9, 2),
+                    "rf_bitwise_equal_to_plain": bool(torch.equal(rf_plain, rf_r)),
+                    "gradient_bitwise_equal_to_plain": bool(torch.equal(g_theta, g_theta_r)),
+                    "kernels": kernel_table(prof_rec)}
     segments = counts[0] + counts[1]
     return {"counts": counts, "segments": segments, "n_params": scene.n_params,
             "fwd_ms": fwd_ms, "prof": prof, "kernels": kernel_table(prof),
-            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb), "fused": fused,
+            "fb_ms": fb_ms, "fb_kernels": kernel_table(prof_fb), "fused": fused, "recorded": recorded,
             "loss": float(loss.item()) if backward else None}
 
 
@@ -503,7 +540,8 @@ def main():
     a = frame_legs(ctx, wa, W.anatomy_phantom_target(wa), args.steps, args.warmup,
                    backward=not args.no_backward)
     print(f"anatomy phantom: forward {a['fwd_ms']:.3f} ms/frame, forward+backward "
-          f"{a['fb_ms']:.3f} ms/frame" + (f" ({a['fused']['ms_per_step']:.3f} fused)" if a["fused"] else ""),
+          f"{a['fb_ms']:.3f} ms/frame" + (f" ({a['fused']['ms_per_step']:.3f} fused)" if a["fused"] else "")
+          + (f" ({a['recorded']['ms_per_step']:.3f} recorded)" if a["recorded"] else ""),
           file=sys.stderr, flush=True)
     prof, counts = a["prof"], a["counts"]
     transport = [k for k in ("bounce", "secondary") if k in prof]
@@ -540,13 +578,15 @@ def main():
             "ray_segments_per_s": a["segments"] / (a["fb_ms"] * 1e-3),
             "loss": a["loss"], "kernels": a["fb_kernels"]},
         "fwd_bwd_fused": a["fused"],
+        "fwd_bwd_recorded": a["recorded"],
     }
     if not args.no_layered:
         wl = W.layered_phantom()
         r = frame_legs(ctx, wl, W.layered_phantom_target(wl), args.steps, args.warmup,
                        backward=not args.no_backward)
         print(f"layered phantom: forward {r['fwd_ms']:.3f} ms/frame, forward+backward "
-              f"{r['fb_ms']:.3f} ms/frame" + (f" ({r['fused']['ms_per_step']:.3f} fused)" if r["fused"] else ""),
+              f"{r['fb_ms']:.3f} ms/frame" + (f" ({r['fused']['ms_per_step']:.3f} fused)" if r["fused"] else "")
+              + (f" ({r['recorded']['ms_per_step']:.3f} recorded)" if r["recorded"] else ""),
               file=sys.stderr, flush=True)
         lay = frame_summary(r, wl, args.steps)
         lay["workload"] = (f"layered_phantom: {wl.n_tx} x {wl.rays_per_tx} rays, {wl.max_bounces} interactions, "
@@ -559,6 +599,7 @@ def main():
                               "gradient_parameters": r["n_params"], "loss": r["loss"],
                               "kernels": r["fb_kernels"]}
             lay["fwd_bwd_fused"] = r["fused"]
+            lay["fwd_bwd_recorded"] = r["recorded"]
         out["layered_phantom"] = lay
     if not args.no_backward and not args.no_inverse:
         out["inverse"] = inverse_leg(ctx, args.steps, args.warmup)

@@ -300,6 +300,50 @@ int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, cons
                  int64_t ray_count, int32_t max_bounces, const float* iq_dev, const float* g_bmode_dev,
                  float dr_db, double* g_theta_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Recorded frame: a forward that keeps the replay's step records for the
+ * backward that follows it (Sec. 3.2 differentiates the path of fixed random
+ * numbers; the backward of a recorded frame reads the path instead of tracing
+ * it again), trading device memory (about 1.3 KB per ray at twelve
+ * interactions) for the replay's forward phase.
+ *
+ * us_simulate_rf_recorded computes the RF of us_simulate_rf for the same
+ * arguments, bit for bit (the same fp64 path arithmetic, the same integer
+ * histogram), and leaves in ws_dev the step record of every segment, the
+ * diffuse interactions in the receiver segments' key order and the per-step
+ * counts. One launch group only (n_tx <= 64) and ray_count >= 1, all
+ * n_tx * ray_count rays in one chunk: ws_dev must hold
+ * us_recorded_workspace_size(...) bytes (US_ETOOBIG if smaller; 0 from the
+ * size function for n_tx > 64 or ray_count < 1). The scene remembers the
+ * call (workspace and arguments, host side only); us_scene_set_params on the
+ * scene invalidates the records.
+ *
+ * us_simulate_rf_vjp_recorded and us_frame_vjp_recorded then give exactly the
+ * gradient of us_simulate_rf_vjp and us_frame_vjp (bit for bit) from those
+ * records: they must be called with the same scene (parameters unchanged),
+ * probe, transmits, seed, rays per element, ray range and bounces, and the
+ * same workspace untouched since (rec_dev, rec_bytes for the frame call),
+ * else US_EINVAL before anything is launched. The records stay valid, so
+ * several backward calls may follow one forward. us_frame_vjp_recorded takes
+ * a second workspace ws_dev for the image adjoint's buffers,
+ * us_frame_vjp_recorded_workspace_size(...) bytes. Calls that share a
+ * workspace must not overlap. */
+size_t us_recorded_workspace_size(const us_scene* scene, const us_probe* probe, int32_t n_tx, int64_t ray_count,
+                                  int32_t max_bounces);
+int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
+                            int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                            int64_t ray_count, int32_t max_bounces, float* rf_dev, void* ws_dev, size_t ws_bytes,
+                            void* stream);
+int us_simulate_rf_vjp_recorded(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
+                                int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                                int64_t ray_count, int32_t max_bounces, const float* g_rf_dev, double* g_theta_dev,
+                                void* ws_dev, size_t ws_bytes, void* stream);
+size_t us_frame_vjp_recorded_workspace_size(const us_probe* probe, const us_grid_desc* grid, int32_t n_tx);
+int us_frame_vjp_recorded(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                          const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                          int64_t ray_begin, int64_t ray_count, int32_t max_bounces, const float* iq_dev,
+                          const float* g_bmode_dev, float dr_db, double* g_theta_dev, void* ws_dev,
+                          size_t ws_bytes, void* rec_dev, size_t rec_bytes, void* stream);
+
 /* Inverse loop (Sec. "Parameterization and constraints", Sec. "Optimization
  * procedure", Algorithm opt). All arrays are device doubles of length n.
  *

@@ -91,6 +91,13 @@ _SIGNATURES = {
     "us_frame_vjp_workspace_size": (sz, [vp, vp, vp, i32, i64, i32]),
     "us_frame_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                     ctypes.c_float, vp, vp, sz, vp]),
+    "us_recorded_workspace_size": (sz, [vp, vp, i32, i64, i32]),
+    "us_simulate_rf_recorded": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp, sz, vp]),
+    "us_simulate_rf_vjp_recorded": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
+                                                   vp, sz, vp]),
+    "us_frame_vjp_recorded_workspace_size": (sz, [vp, vp, i32]),
+    "us_frame_vjp_recorded": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
+                                             ctypes.c_float, vp, vp, sz, vp, sz, vp]),
     "us_image_loss_workspace_size": (sz, [i64]),
     "us_image_loss": (ctypes.c_int, [vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp,
                                      vp, sz, vp]),
@@ -520,6 +527,97 @@ def us_frame_vjp(ctx: Context, scene: Scene, probe: Probe, grid, angles, tx_ids,
                                int(rays_per_elem), int(ray_begin), int(ray_count), int(max_bounces), _ptr(iq),
                                _ptr(g_bmode), float(dr_db), _ptr(g_theta), _ptr(workspace), workspace.numel(),
                                _stream(stream)), "us_frame_vjp")
+    return g_theta
+
+
+class Recorded:
+    """One recorded forward: its workspace (the step records the backward
+    reads) and the arguments a recorded backward repeats."""
+
+    def __init__(self, scene, probe, angles, tx_ids, seed, rays_per_elem, max_bounces, ray_begin, ray_count,
+                 workspace):
+        self.scene, self.probe = scene, probe
+        self.angles, self.tx_ids = angles, tx_ids
+        self.seed, self.rays_per_elem, self.max_bounces = int(seed), int(rays_per_elem), int(max_bounces)
+        self.ray_begin, self.ray_count = int(ray_begin), int(ray_count)
+        self.workspace = workspace
+
+    def args(self):
+        tx, n_tx = _tx_array(self.angles, self.tx_ids)
+        return tx, n_tx, (self.seed, self.rays_per_elem, self.ray_begin, self.ray_count, self.max_bounces)
+
+
+def us_recorded_workspace_size(scene: Scene, probe: Probe, n_tx: int, ray_count: int, max_bounces: int) -> int:
+    return int(load().us_recorded_workspace_size(scene.handle, probe.handle, n_tx, ray_count, max_bounces))
+
+
+def us_simulate_rf_recorded(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, seed: int,
+                            rays_per_elem: int, max_bounces: int, ray_begin: int = 0,
+                            ray_count: Optional[int] = None, rf=None, workspace=None, stream=None):
+    """The RF of us_simulate_rf, keeping the path records for a recorded
+    backward; returns (rf, Recorded)."""
+    torch = _torch()
+    p = probe.desc
+    tx, n_tx = _tx_array(angles, tx_ids)
+    if ray_count is None:
+        ray_count = int(p.n_elem) * int(rays_per_elem) - ray_begin
+    if rf is None:
+        rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
+    _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
+    if workspace is None:
+        need = us_recorded_workspace_size(scene, probe, n_tx, ray_count, max_bounces)
+        if need == 0:
+            raise USError(US_EINVAL, "us_simulate_rf_recorded: at most 64 transmits and at least one ray")
+        workspace = _workspace(need, ctx.torch_device)
+    _expect_ws(workspace)
+    _check(load().us_simulate_rf_recorded(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
+                                          int(rays_per_elem), int(ray_begin), int(ray_count), int(max_bounces),
+                                          _ptr(rf), _ptr(workspace), workspace.numel(), _stream(stream)),
+           "us_simulate_rf_recorded")
+    return rf, Recorded(scene, probe, angles, tx_ids, seed, rays_per_elem, max_bounces, ray_begin, ray_count,
+                        workspace)
+
+
+def us_simulate_rf_vjp_recorded(ctx: Context, rec: Recorded, g_rf, g_theta=None, stream=None):
+    """us_simulate_rf_vjp from the records of a recorded forward."""
+    torch = _torch()
+    p = rec.probe.desc
+    tx, n_tx, (seed, rpe, rb, rc, nb) = rec.args()
+    if g_theta is None:
+        g_theta = torch.zeros(rec.scene.n_params, dtype=torch.float64, device=ctx.torch_device)
+    _expect(g_rf, n_tx * p.n_elem * p.n_t, torch.float32, "g_rf")
+    _expect(g_theta, rec.scene.n_params, torch.float64, "g_theta")
+    _check(load().us_simulate_rf_vjp_recorded(ctx.handle, rec.scene.handle, rec.probe.handle, tx, n_tx, seed, rpe,
+                                              rb, rc, nb, _ptr(g_rf), _ptr(g_theta), _ptr(rec.workspace),
+                                              rec.workspace.numel(), _stream(stream)),
+           "us_simulate_rf_vjp_recorded")
+    return g_theta
+
+
+def us_frame_vjp_recorded_workspace_size(probe: Probe, grid, n_tx: int) -> int:
+    g = _grid(grid)
+    return int(load().us_frame_vjp_recorded_workspace_size(probe.handle, ctypes.byref(g), n_tx))
+
+
+def us_frame_vjp_recorded(ctx: Context, rec: Recorded, grid, iq, g_bmode, dr_db: float, g_theta=None,
+                          workspace=None, stream=None):
+    """us_frame_vjp from the records of a recorded forward."""
+    torch = _torch()
+    tx, n_tx, (seed, rpe, rb, rc, nb) = rec.args()
+    g = _grid(grid)
+    n_px = g.n_x * g.n_z
+    if g_theta is None:
+        g_theta = torch.zeros(rec.scene.n_params, dtype=torch.float64, device=ctx.torch_device)
+    _expect(iq, 2 * n_px, torch.float32, "iq")
+    _expect(g_bmode, n_px, torch.float32, "g_bmode")
+    _expect(g_theta, rec.scene.n_params, torch.float64, "g_theta")
+    if workspace is None:
+        workspace = _workspace(us_frame_vjp_recorded_workspace_size(rec.probe, grid, n_tx), ctx.torch_device)
+    _expect_ws(workspace)
+    _check(load().us_frame_vjp_recorded(ctx.handle, rec.scene.handle, rec.probe.handle, ctypes.byref(g), tx, n_tx,
+                                        seed, rpe, rb, rc, nb, _ptr(iq), _ptr(g_bmode), float(dr_db),
+                                        _ptr(g_theta), _ptr(workspace), workspace.numel(), _ptr(rec.workspace),
+                                        rec.workspace.numel(), _stream(stream)), "us_frame_vjp_recorded")
     return g_theta
 
 

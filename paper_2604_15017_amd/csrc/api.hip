@@ -146,6 +146,19 @@ struct us_scene {
   double* mesh_kd;
   int* tri_orig;
   MeshDevice mesh;   // owns vrest, vnormal, vbasis, vmesh, vcur, nodes, tri
+  // bumped by us_scene_set_params: records of a recorded forward hold for
+  // the parameters they were made with
+  uint64_t version;
+  // the last recorded forward on this scene (workspace and arguments), which
+  // a recorded backward must match
+  struct {
+    const void* ws;
+    uint64_t version;
+    const us_probe* probe;
+    uint64_t seed, tx_hash;
+    int64_t ray_begin, ray_count;
+    int32_t rays_per_elem, max_bounces, n_tx;
+  } rec;
 };
 
 // Makes the device current and clears the runtime's last error, so that a
@@ -447,6 +460,7 @@ int us_scene_set_params(us_scene* s, const double* theta_dev, int32_t n_params, 
   US_HIP(bind_device(s->ctx->device));
   US_HIP(hipMemcpyAsync(s->theta, theta_dev, n_params * sizeof(double), hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));
+  ++s->version;
   if (s->n_meshes > 0) {
     launch_mesh_refit(s->mesh, s->theta + s->q_offset, (hipStream_t)stream);
     US_HIP(hipGetLastError());
@@ -1038,23 +1052,72 @@ namespace {
 // the acquisition parameters. The gradient arrives as dL/drf (g_rf_dev), or,
 // with g_A_dev instead, as the gradient of the analytic signal, taken through
 // the analytic map's and the pulse's adjoints in one kernel (no g_acq then).
+// Workspace of a recorded frame (one transmit group, one chunk holding all
+// n_tx * ray_count rays): the replay's, then the deposit histogram and its
+// overflow count.
+size_t recorded_bytes(const us_scene* scene, const us_probe* p, int n_tx, int64_t ray_count, int max_bounces) {
+  const long cap = (long)n_tx * ray_count;
+  return align_up(replay_bytes(scene, n_tx, p, max_bounces, cap)) +
+         align_up((size_t)n_tx * p->d.n_elem * p->d.n_t * sizeof(long long)) + kAlign;
+}
+
+// FNV-1a over the transmit table, to tell a recorded frame's transmits apart.
+uint64_t tx_hash(const us_tx_desc* tx, int n_tx) {
+  uint64_t h = 1469598103934665603ull;
+  const unsigned char* b = reinterpret_cast<const unsigned char*>(tx);
+  for (size_t i = 0; i < (size_t)n_tx * sizeof(us_tx_desc); ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+int check_recorded_shape(const us_scene* scene, const us_probe* probe, int n_tx, int64_t ray_count,
+                         int max_bounces, size_t ws_bytes) {
+  US_CHECK(n_tx <= kMaxTxPerLaunch, "recorded frame: at most 64 transmits (one launch group)");
+  US_CHECK(ray_count >= 1, "recorded frame: ray_count must be >= 1");
+  if (ws_bytes < recorded_bytes(scene, probe, n_tx, ray_count, max_bounces))
+    return fail(US_ETOOBIG, "recorded frame: workspace too small (see us_recorded_workspace_size)");
+  return US_OK;
+}
+
+int check_recorded(const us_scene* scene, const us_probe* probe, const us_tx_desc* tx, int n_tx, uint64_t seed,
+                   int rays_per_elem, int64_t ray_begin, int64_t ray_count, int max_bounces, const void* ws,
+                   size_t ws_bytes) {
+  const int rc = check_recorded_shape(scene, probe, n_tx, ray_count, max_bounces, ws_bytes);
+  if (rc) return rc;
+  const auto& r = scene->rec;
+  US_CHECK(r.ws == ws && r.version == scene->version && r.probe == probe && r.seed == seed &&
+               r.tx_hash == tx_hash(tx, n_tx) && r.ray_begin == ray_begin && r.ray_count == ray_count &&
+               r.rays_per_elem == rays_per_elem && r.max_bounces == max_bounces && r.n_tx == n_tx,
+           "recorded backward: the workspace holds no recorded forward of these arguments and parameters");
+  return US_OK;
+}
+
 int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
                     int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin, int64_t ray_count,
                     int32_t max_bounces, const float* g_rf_dev, double* g_theta_dev, double* g_acq_dev,
-                    void* ws_dev, size_t ws_bytes, void* stream, const float2* g_A_dev = nullptr) {
+                    void* ws_dev, size_t ws_bytes, void* stream, const float2* g_A_dev = nullptr,
+                    bool recorded = false) {
   US_CHECK(ctx && (g_rf_dev || g_A_dev) && g_theta_dev && ws_dev, "us_simulate_rf_vjp: NULL argument");
   US_CHECK(!(g_A_dev && g_acq_dev), "us_simulate_rf_vjp: acquisition gradients need dL/drf");
   int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
-  // largest chunk that fits the workspace
-  if (replay_bytes(scene, n_tx, probe, max_bounces, 1) > ws_bytes)
-    return fail(US_ETOOBIG, "us_simulate_rf_vjp: workspace too small");
-  long lo = 1, hi = kReplayChunk;
-  while (lo < hi) {
-    const long mid = lo + (hi - lo + 1) / 2;
-    if (replay_bytes(scene, n_tx, probe, max_bounces, mid) <= ws_bytes) lo = mid; else hi = mid - 1;
+  long cap = 0;
+  if (recorded) {
+    // the records of the whole frame, one chunk, from us_simulate_rf_recorded
+    rc = check_recorded(scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
+                        ws_dev, ws_bytes);
+    if (rc) return rc;
+    cap = (long)n_tx * ray_count;
+  } else {
+    // largest chunk that fits the workspace
+    if (replay_bytes(scene, n_tx, probe, max_bounces, 1) > ws_bytes)
+      return fail(US_ETOOBIG, "us_simulate_rf_vjp: workspace too small");
+    long lo = 1, hi = kReplayChunk;
+    while (lo < hi) {
+      const long mid = lo + (hi - lo + 1) / 2;
+      if (replay_bytes(scene, n_tx, probe, max_bounces, mid) <= ws_bytes) lo = mid; else hi = mid - 1;
+    }
+    cap = lo;
   }
-  const long cap = lo;
   US_HIP(bind_device(ctx->device));
   hipStream_t s = (hipStream_t)stream;
   const us_probe_desc& pd = probe->d;
@@ -1110,9 +1173,9 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
     for (long g0 = 0; g0 < n_group; g0 += cap) {
       const long n = std::min(cap, n_group - g0);
       a.g0 = g0;
-      launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);
-      if (a.sort.keys > 0) launch_fill_u32(a.sort_count, (long)a.sort.keys * max_bounces, 0u, s);
-      {
+      if (!recorded) {   // a recorded forward left the records, the queue and its order
+        launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);
+        if (a.sort.keys > 0) launch_fill_u32(a.sort_count, (long)a.sort.keys * max_bounces, 0u, s);
         Timed tm(ctx, "replay_forward", s);
         for (int k = 1; k <= max_bounces + 1; ++k) {
           a.qout = (k & 1) ? q0 : q1;
@@ -1122,8 +1185,10 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
       }
       {
         Timed tm(ctx, "replay_secondary", s);
-        launch_replay_prefix(a, s);
-        launch_replay_sort(a, n * std::max(1, max_bounces), s);
+        if (!recorded) {
+          launch_replay_prefix(a, s);
+          launch_replay_sort(a, n * std::max(1, max_bounces), s);
+        }
         launch_replay_secondary(a, n * std::max(1, max_bounces), s);
       }
       {
@@ -1180,22 +1245,16 @@ size_t us_frame_vjp_workspace_size(const us_scene* scene, const us_probe* probe,
          us_beamform_workspace_size(probe, n_tx) + replay;
 }
 
-int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
-                 const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
-                 int64_t ray_count, int32_t max_bounces, const float* iq_dev, const float* g_bmode_dev,
-                 float dr_db, double* g_theta_dev, void* ws_dev, size_t ws_bytes, void* stream) {
-  US_CHECK(ctx && iq_dev && g_bmode_dev && g_theta_dev && ws_dev, "us_frame_vjp: NULL argument");
-  US_CHECK(dr_db > 0, "us_frame_vjp: dr_db must be positive");
-  int rc = check_beamform(probe, grid, tx, n_tx);
-  if (rc) return rc;
-  rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
-  if (rc) return rc;
-  const size_t need = us_frame_vjp_workspace_size(scene, probe, grid, n_tx, ray_count, max_bounces);
-  if (ws_bytes < need) return fail(US_ETOOBIG, "us_frame_vjp: workspace too small");
-  US_HIP(bind_device(ctx->device));
-  hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+namespace {
+
+// The image half of the frame backward: dL/dB to dL/dA in gA (carved from w
+// after the B-mode sums and dL/dI); returns the first byte after gA.
+char* frame_image_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* grid, const us_tx_desc* tx,
+                      int32_t n_tx, const float* iq_dev, const float* g_bmode_dev, float dr_db, char* w,
+                      float2** gA_out, hipStream_t s) {
   const int64_t n_px = (int64_t)grid->n_x * grid->n_z;
-  char* w = (char*)ws_dev;
   unsigned long long* key = (unsigned long long*)w;
   unsigned long long* sum = (unsigned long long*)(w + kAlign);
   w += us_bmode_workspace_size(n_px);
@@ -1219,8 +1278,159 @@ int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, cons
     Timed tm(ctx, "das_adjoint", s);
     launch_das_adjoint(g_iq, gA, probe->pv, g, tt, ng, t0, s);
   }
+  *gA_out = gA;
+  return w;
+}
+
+size_t frame_image_bytes(const us_probe* probe, const us_grid_desc* grid, int32_t n_tx) {
+  const int64_t n_px = (int64_t)grid->n_x * grid->n_z;
+  return us_bmode_workspace_size(n_px) + align_up((size_t)n_px * sizeof(float2)) +
+         us_beamform_workspace_size(probe, n_tx);
+}
+
+}  // namespace
+
+extern "C" {
+
+int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                 const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                 int64_t ray_count, int32_t max_bounces, const float* iq_dev, const float* g_bmode_dev,
+                 float dr_db, double* g_theta_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  US_CHECK(ctx && iq_dev && g_bmode_dev && g_theta_dev && ws_dev, "us_frame_vjp: NULL argument");
+  US_CHECK(dr_db > 0, "us_frame_vjp: dr_db must be positive");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
+  if (rc) return rc;
+  const size_t need = us_frame_vjp_workspace_size(scene, probe, grid, n_tx, ray_count, max_bounces);
+  if (ws_bytes < need) return fail(US_ETOOBIG, "us_frame_vjp: workspace too small");
+  US_HIP(bind_device(ctx->device));
+  float2* gA = nullptr;
+  char* w = frame_image_vjp(ctx, probe, grid, tx, n_tx, iq_dev, g_bmode_dev, dr_db, (char*)ws_dev, &gA,
+                            (hipStream_t)stream);
   return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
                          nullptr, g_theta_dev, nullptr, w, ws_bytes - (size_t)(w - (char*)ws_dev), stream, gA);
+}
+
+size_t us_recorded_workspace_size(const us_scene* scene, const us_probe* probe, int32_t n_tx, int64_t ray_count,
+                                  int32_t max_bounces) {
+  if (!scene || !probe || n_tx < 1 || n_tx > kMaxTxPerLaunch || ray_count < 1 || max_bounces < 0) return 0;
+  return recorded_bytes(scene, probe, n_tx, ray_count, max_bounces);
+}
+
+int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
+                            int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                            int64_t ray_count, int32_t max_bounces, float* rf_dev, void* ws_dev, size_t ws_bytes,
+                            void* stream) {
+  US_CHECK(ctx && rf_dev && ws_dev, "us_simulate_rf_recorded: NULL ctx, rf or workspace");
+  int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
+  if (rc) return rc;
+  rc = check_recorded_shape(scene, probe, n_tx, ray_count, max_bounces, ws_bytes);
+  if (rc) return rc;
+  if (probe->M > kMaxTaps - 1) return fail(US_EINVAL, "us_simulate_rf_recorded: pulse too long");
+  scene->rec.ws = nullptr;   // valid again only once this call has been queued whole
+  US_HIP(bind_device(ctx->device));
+  hipStream_t s = (hipStream_t)stream;
+  const us_probe_desc& pd = probe->d;
+  const long cap = (long)n_tx * ray_count;
+  ReplayArgs a{};
+  float* gh = nullptr;
+  float* gh_f0 = nullptr;
+  RayQueue q0, q1;
+  ReplaySums sums;
+  const size_t rb = replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &sums,
+                                 &q0, &q1, &a.counts, &a.sort_count, &a.sort_part);
+  if (a.sort_count) a.sort = seg_sort(probe);
+  char* w = (char*)ws_dev + align_up(rb);
+  const long rows = (long)n_tx * pd.n_elem;
+  a.h = (long long*)w;
+  a.hist_over = (unsigned long long*)(w + align_up((size_t)rows * pd.n_t * sizeof(long long)));
+  a.hist_scale = hist_scale(rays_per_elem);
+  launch_fill_u32((uint32_t*)a.h, 2L * rows * pd.n_t, 0u, s);
+  launch_fill_u32((uint32_t*)a.hist_over, 2, 0u, s);
+  launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);
+  if (a.sort.keys > 0) launch_fill_u32(a.sort_count, (long)a.sort.keys * max_bounces, 0u, s);
+  a.scene = scene_view(scene, probe);
+  a.probe = probe->pv;
+  a.seed = seed;
+  a.rays_per_elem = rays_per_elem;
+  a.max_bounces = max_bounces;
+  a.ray_begin = ray_begin;
+  a.ray_count = ray_count;
+  a.n_params = scene->n_params;
+  a.n_grad = scene->q_offset;
+  a.grad_copies = 1;
+  a.cap = cap;
+  a.n_tx_total = n_tx;
+  fill_tx(a.tx, tx, 0, n_tx);
+  a.tx_base = 0;
+  a.g0 = 0;
+  {
+    Timed tm(ctx, "recorded_forward", s);
+    for (int k = 1; k <= max_bounces + 1; ++k) {
+      a.qout = (k & 1) ? q0 : q1;
+      a.qin = (k & 1) ? q1 : q0;
+      launch_replay_forward(a, k, cap, s);
+    }
+  }
+  {
+    Timed tm(ctx, "recorded_deposit", s);
+    launch_replay_prefix(a, s);
+    launch_replay_sort(a, cap * std::max(1, max_bounces), s);
+    if (max_bounces > 0 && scene->any_diffuse) launch_replay_deposit(a, cap * std::max(1, max_bounces), s);
+  }
+  {
+    Timed tm(ctx, "pulse", s);
+    launch_pulse_fixed(a.h, a.hist_scale, a.hist_over, rf_dev, probe->taps, probe->M, pd.n_t, (int)rows, s);
+  }
+  US_HIP(hipGetLastError());
+  scene->rec.ws = ws_dev;
+  scene->rec.version = scene->version;
+  scene->rec.probe = probe;
+  scene->rec.seed = seed;
+  scene->rec.tx_hash = tx_hash(tx, n_tx);
+  scene->rec.ray_begin = ray_begin;
+  scene->rec.ray_count = ray_count;
+  scene->rec.rays_per_elem = rays_per_elem;
+  scene->rec.max_bounces = max_bounces;
+  scene->rec.n_tx = n_tx;
+  return US_OK;
+}
+
+int us_simulate_rf_vjp_recorded(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
+                                int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
+                                int64_t ray_count, int32_t max_bounces, const float* g_rf_dev, double* g_theta_dev,
+                                void* ws_dev, size_t ws_bytes, void* stream) {
+  return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
+                         g_rf_dev, g_theta_dev, nullptr, ws_dev, ws_bytes, stream, nullptr, true);
+}
+
+size_t us_frame_vjp_recorded_workspace_size(const us_probe* probe, const us_grid_desc* grid, int32_t n_tx) {
+  if (!probe || !grid || n_tx < 1 || grid->n_x < 1 || grid->n_z < 1) return 0;
+  return frame_image_bytes(probe, grid, n_tx);
+}
+
+int us_frame_vjp_recorded(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
+                          const us_tx_desc* tx, int32_t n_tx, uint64_t seed, int32_t rays_per_elem,
+                          int64_t ray_begin, int64_t ray_count, int32_t max_bounces, const float* iq_dev,
+                          const float* g_bmode_dev, float dr_db, double* g_theta_dev, void* ws_dev,
+                          size_t ws_bytes, void* rec_dev, size_t rec_bytes, void* stream) {
+  US_CHECK(ctx && iq_dev && g_bmode_dev && g_theta_dev && ws_dev && rec_dev, "us_frame_vjp_recorded: NULL argument");
+  US_CHECK(dr_db > 0, "us_frame_vjp_recorded: dr_db must be positive");
+  int rc = check_beamform(probe, grid, tx, n_tx);
+  if (rc) return rc;
+  rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
+  if (rc) return rc;
+  if (ws_bytes < frame_image_bytes(probe, grid, n_tx))
+    return fail(US_ETOOBIG, "us_frame_vjp_recorded: workspace too small");
+  rc = check_recorded(scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces, rec_dev,
+                      rec_bytes);
+  if (rc) return rc;
+  US_HIP(bind_device(ctx->device));
+  float2* gA = nullptr;
+  frame_image_vjp(ctx, probe, grid, tx, n_tx, iq_dev, g_bmode_dev, dr_db, (char*)ws_dev, &gA, (hipStream_t)stream);
+  return simulate_rf_vjp(ctx, scene, probe, tx, n_tx, seed, rays_per_elem, ray_begin, ray_count, max_bounces,
+                         nullptr, g_theta_dev, nullptr, rec_dev, rec_bytes, stream, gA, true);
 }
 
 int us_param_map(us_ctx* ctx, const double* u_dev, const double* lo_dev, const double* hi_dev,

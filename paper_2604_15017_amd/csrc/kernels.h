@@ -162,6 +162,12 @@ struct ReplayArgs {
   unsigned long long* acq_sum;
   const float* gh_f0;
   int n_tx_total;
+  // a recorded forward (null otherwise): the forward phase adds the array
+  // hits' deposits and launch_replay_deposit the receiver segments' to h, in
+  // units of 1 / hist_scale, as the forward transport does
+  long long* h;
+  double hist_scale;
+  unsigned long long* hist_over;
 };
 // The three phases of the replay over chunk rays [0, n): the forward phase
 // once per step k = 1..max_bounces + 1 (queues swapped in between), the
@@ -170,6 +176,9 @@ struct ReplayArgs {
 // analytic gradient collects in g_sum; add it to g_theta with
 // launch_grad_finish once all chunks are done.
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s);
+// The receiver segments of the queued diffuse interactions deposited into a.h
+// (a recorded forward; after launch_replay_prefix and launch_replay_sort).
+void launch_replay_deposit(const ReplayArgs& a, long max_entries, hipStream_t s);
 void launch_replay_prefix(const ReplayArgs& a, hipStream_t s);
 void launch_replay_secondary(const ReplayArgs& a, long max_entries, hipStream_t s);
 // With sort.keys > 0, after the prefix: the queue in key order (stk.sort_q).

@@ -442,7 +442,7 @@ __device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t,
   st.h = h;
   st.L = h.t;
   st.E = exp(-(S.a[region] * h.t));
-  st.tp = t + h.t / S.c[region];
+  st.tp = t + h.t * S.ic[region];   // as the forward transport forms it
   st.watt = w * st.E;
   st.x = o + d * h.t;
   if (h.kind != kHitArray && h.kind != kHitNone) {
@@ -459,7 +459,7 @@ __device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t,
 // keeping the state before it and the surface it hits in the step record of
 // their chunk index; the survivors are compacted into the next queue and
 // every interaction on a diffuse surface is queued for phase 2.
-template <bool kMeshes>
+template <bool kMeshes, bool kDeposit>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_replay_forward(ReplayArgs a, int k, long n) {
   const long n_in = k == 1 ? n : (long)(uint32_t)a.counts[k - 1];   // survivors of step k - 1
@@ -516,6 +516,23 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
                               h.index};
       if (h.kind == kHitArray) {
         a.stk.last[ci] = k;
+        if (kDeposit) {   // a recorded forward: the array hit's deposit, as the bounce kernel makes it
+          const double th = t + h.t * S.ic[region];
+          const double wh = w * exp(-(S.a[region] * h.t));
+          const d3 x = o + d * h.t;
+          const double half = 0.5 * (double)P.n_elem * P.pitch;
+          if (delta && fabs(x.x) < half && fabs(x.y) < 0.5 * P.elem_h) {
+            int e = (int)floor((x.x + half) / P.pitch);
+            e = min(max(e, 0), P.n_elem - 1);
+            const double fd = rx_directivity(P, -d.z);
+            int txl;
+            uint32_t rid;
+            ray_of(a, ci, &txl, &rid);
+            Deposit dp;
+            if (fd > 0.0 && make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e), P.n_t, P.fs, th, wh * fd, &dp))
+              add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
+          }
+        }
       } else if (h.kind != kHitNone && k <= B) {
         int txl;
         uint32_t rid;
@@ -611,6 +628,60 @@ __global__ __launch_bounds__(256) void k_replay_sort_scatter(ReplayArgs a) {
     const long e = (long)(k - 1) * a.cap + (q - (long)a.stk.queue_begin[k - 1]);
     const uint2 kr = a.stk.sort_kr[e];
     a.stk.sort_q[a.sort_count[(long)(k - 1) * a.sort.keys + kr.x] + kr.y] = a.stk.queue[e];
+  }
+}
+
+// Receiver segments of a recorded forward (one thread per queued diffuse
+// interaction, in key order): the secondary ray rebuilt from the step record
+// and its draw, weighted as the bounce kernel weights it, marched and
+// deposited as the secondary kernel does, so that the histogram is the plain
+// forward's.
+template <bool kMeshes>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_replay_deposit(ReplayArgs a) {
+  const int B = a.max_bounces;
+  const long n_q = B > 0 ? (long)a.stk.queue_begin[B] : 0;
+  if ((long)blockIdx.x * blockDim.x >= n_q) return;
+  __shared__ SceneLDS S;
+  extern __shared__ int bvh_stack[];
+  load_scene(S, a.scene);
+  int* stk = bvh_stack + threadIdx.x;
+  const ProbeView& P = a.probe;
+  const long cap = a.cap;
+  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
+    int k = 1, hi = B;
+    while (k < hi) {
+      const int mid = (k + hi + 1) >> 1;
+      if ((long)a.stk.queue_begin[mid - 1] <= q) k = mid; else hi = mid - 1;
+    }
+    const uint32_t i = a.sort.keys > 0 ? a.stk.sort_q[q]
+                                       : a.stk.queue[(long)(k - 1) * cap + (q - (long)a.stk.queue_begin[k - 1])];
+    int txl;
+    uint32_t rid;
+    ray_of(a, i, &txl, &rid);
+    const StepRec R = a.stk.rec[(long)(k - 1) * cap + i];
+    const int reg = R.meta & 0xFF;
+    const Hit h{(int)(R.meta >> 12), R.hidx, R.L};
+    const Step st = step_at(S, d3{R.ox, R.oy, R.oz}, d3{R.dx, R.dy, R.dz}, R.t, R.w, reg, h);
+    const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
+    const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
+    const d3 dv = d3{elem_x(P, e2), 0.0, 0.0} - st.x;
+    const double r = sqrt(dot(dv, dv));
+    const d3 we = dv * (1.0 / r);
+    const double cos_o = dot(st.f.nr, we);
+    if (!(cos_o > 0.0)) continue;
+    const double cos_el = -we.z;
+    const double fd = rx_directivity(P, cos_el);
+    if (fd == 0.0) continue;
+    double amp = st.watt * st.f.Ar * (st.sf.kd / kPi) * cos_o * (P.elem_w * P.elem_h * cos_el / (r * r)) *
+                 (double)P.n_elem * fd;
+    const March mr = receiver_march<kMeshes>(S, st.x, we, r, reg, st.tp, stk,
+                                             [](int, double, int, const Surface&, const Coef&) {});
+    if (!mr.reached) continue;
+    amp *= mr.trans;
+    amp *= exp(-mr.att);
+    Deposit dp;
+    if (make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, mr.tof, amp, &dp))
+      add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
   }
 }
 
@@ -959,7 +1030,9 @@ size_t grad_lds(const ReplayArgs& a) { return (size_t)a.grad_copies * a.n_grad *
 }  // namespace
 
 void launch_replay_forward(const ReplayArgs& a, int k, long n, hipStream_t s) {
-  const auto kern = a.scene.n_meshes > 0 ? k_replay_forward<true> : k_replay_forward<false>;
+  const bool m = a.scene.n_meshes > 0;
+  const auto kern = a.h ? (m ? k_replay_forward<true, true> : k_replay_forward<false, true>)
+                        : (m ? k_replay_forward<true, false> : k_replay_forward<false, false>);
   hipLaunchKernelGGL(kern, dim3(replay_grid(n, kMaxReplayForwardBlocks)), dim3(256), stack_lds(a), s, a, k, n);
 }
 
@@ -971,6 +1044,11 @@ void launch_replay_secondary(const ReplayArgs& a0, long max_entries, hipStream_t
   const auto kern = m ? k_replay_secondary<true> : k_replay_secondary<false>;
   hipLaunchKernelGGL(kern, dim3(replay_grid(max_entries)), dim3(256),
                      grad_lds(a) + acq_lds(a) + legs + stack_lds(a), s, a);
+}
+
+void launch_replay_deposit(const ReplayArgs& a, long max_entries, hipStream_t s) {
+  const auto kern = a.scene.n_meshes > 0 ? k_replay_deposit<true> : k_replay_deposit<false>;
+  hipLaunchKernelGGL(kern, dim3(replay_grid(max_entries, kMaxReplayForwardBlocks)), dim3(256), stack_lds(a), s, a);
 }
 
 void launch_replay_prefix(const ReplayArgs& a, hipStream_t s) {
