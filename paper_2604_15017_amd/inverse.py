@@ -34,11 +34,15 @@ def unconstrained_start(theta0, lo, hi):
 class InverseLoop:
     """Optimises the scene parameters theta = lo + clip(u, 0, 1) (hi - lo);
     parameters with lo == hi stay fixed. `lr` holds one learning rate per
-    parameter (groups are runs of equal values)."""
+    parameter (groups are runs of equal values). With `recorded`, each
+    micro-batch's forward keeps its path records and the backward reads them
+    (us_simulate_rf_recorded, us_simulate_rf_vjp_recorded: the same gradient
+    bit for bit, device memory for the records of the largest micro-batch)."""
 
     def __init__(self, ctx, wl, lo, hi, lr, u0, batches: List[MicroBatch], refs=None, target=None,
                  lambda1: float = 0.0, lambda2: float = 1.0, beta1: float = 0.9,
-                 beta2: float = 0.999, eps: float = 1e-8, max_norm: float = 0.0, stream=None):
+                 beta2: float = 0.999, eps: float = 1e-8, max_norm: float = 0.0, stream=None,
+                 recorded: bool = False):
         import torch
         self.ctx, self.wl, self.batches = ctx, wl, batches
         self.l1, self.l2, self.b1, self.b2, self.eps, self.max_norm = (lambda1, lambda2, beta1, beta2,
@@ -75,23 +79,34 @@ class InverseLoop:
         self.ws_b = L._workspace(lib.us_beamform_workspace_size(self.probe.handle, n_tx), dev)
         self.ws_m = L._workspace(lib.us_bmode_workspace_size(g.n_px), dev)
         self.ws_l = L._workspace(lib.us_image_loss_workspace_size(g.n_px), dev)
-        self.ws_r = L._workspace(L.us_simulate_rf_vjp_workspace_size(self.scene, self.probe, n_tx, count,
-                                                                     wl.max_bounces), dev)
+        self.recorded = recorded
+        if recorded:
+            self.ws_rec = L._workspace(L.us_recorded_workspace_size(self.scene, self.probe, n_tx, count,
+                                                                    wl.max_bounces), dev)
+        else:
+            self.ws_r = L._workspace(L.us_simulate_rf_vjp_workspace_size(self.scene, self.probe, n_tx, count,
+                                                                         wl.max_bounces), dev)
         if refs is None:
             if target is None:
                 raise ValueError("give the reference images or a target scene")
             refs = self.render_all(target)
         self.refs = refs
 
-    def _frame(self, scene, b):
+    def _frame(self, scene, b, record=False):
         wl, (ang, ids, rb, rc) = self.wl, self._views[b]
         rf = self.rf[:len(ang)]
-        L.us_simulate_rf(self.ctx, scene, self.probe, ang, ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
-                         ray_begin=rb, ray_count=rc, rf=rf, workspace=self.ws_t, stream=self.stream)
+        rec = None
+        if record:
+            _, rec = L.us_simulate_rf_recorded(self.ctx, scene, self.probe, ang, ids, wl.seed, wl.rays_per_elem,
+                                               wl.max_bounces, ray_begin=rb, ray_count=rc, rf=rf,
+                                               workspace=self.ws_rec, stream=self.stream)
+        else:
+            L.us_simulate_rf(self.ctx, scene, self.probe, ang, ids, wl.seed, wl.rays_per_elem, wl.max_bounces,
+                             ray_begin=rb, ray_count=rc, rf=rf, workspace=self.ws_t, stream=self.stream)
         L.us_beamform(self.ctx, self.probe, wl.grid, ang, ids, rf, iq=self.iq, workspace=self.ws_b,
                       stream=self.stream)
         L.us_bmode(self.ctx, self.iq, wl.dr_db, out=self.bm, workspace=self.ws_m, stream=self.stream)
-        return rf
+        return rf, rec
 
     def render_all(self, scene_desc):
         """B-mode image of every micro-batch for a scene description."""
@@ -108,7 +123,7 @@ class InverseLoop:
         wl = self.wl
         self.g_theta.zero_()
         for b, (ang, ids, rb, rc) in enumerate(self._views):
-            rf = self._frame(self.scene, b)
+            rf, rec = self._frame(self.scene, b, record=self.recorded)
             L.us_image_loss(self.ctx, self.bm, self.refs[b], self.l1, self.l2, loss=self.loss[b:b + 1],
                             g_bmode=self.g_b, workspace=self.ws_l, stream=self.stream)
             L.us_bmode_vjp(self.ctx, self.iq, self.g_b, wl.dr_db, g_iq=self.g_iq, workspace=self.ws_m,
@@ -116,9 +131,12 @@ class InverseLoop:
             g_rf = self.g_rf[:len(ang)]
             L.us_beamform_vjp(self.ctx, self.probe, wl.grid, ang, ids, self.g_iq, g_rf=g_rf,
                               workspace=self.ws_b, stream=self.stream)
-            L.us_simulate_rf_vjp(self.ctx, self.scene, self.probe, ang, ids, wl.seed, wl.rays_per_elem,
-                                 wl.max_bounces, g_rf, g_theta=self.g_theta, ray_begin=rb, ray_count=rc,
-                                 workspace=self.ws_r, stream=self.stream)
+            if rec is not None:
+                L.us_simulate_rf_vjp_recorded(self.ctx, rec, g_rf, g_theta=self.g_theta, stream=self.stream)
+            else:
+                L.us_simulate_rf_vjp(self.ctx, self.scene, self.probe, ang, ids, wl.seed, wl.rays_per_elem,
+                                     wl.max_bounces, g_rf, g_theta=self.g_theta, ray_begin=rb, ray_count=rc,
+                                     workspace=self.ws_r, stream=self.stream)
         self.step_count += 1
         L.us_adam_step(self.ctx, self.u, self.m, self.v, self.g_theta, self.lo, self.hi, self.lr,
                        self.step_count, self.b1, self.b2, self.eps, self.max_norm, stream=self.stream)

@@ -207,9 +207,10 @@ def test_cylinder_joint_recovery(L, ctx):
 
 
 def test_inverse_runs_are_bitwise_reproducible(L, ctx):
-    """Two runs of the loop from the same start (the cylinder's three
-    parameters, ten iterations) give the same losses and the same iterates
-    bit for bit: every sum on the path is order-independent."""
+    """Runs of the loop from the same start (the cylinder's three parameters,
+    ten iterations) give the same losses and the same iterates bit for bit:
+    every sum on the path is order-independent. The third run records each
+    micro-batch's paths in its forward and differentiates from the records."""
     from paper_2604_15017_amd.inverse import InverseLoop, MicroBatch, unconstrained_start
     truth = W.cylinder_phantom()
     sc = truth.scene
@@ -221,14 +222,15 @@ def test_inverse_runs_are_bitwise_reproducible(L, ctx):
     lr = np.zeros_like(th0)
     lr[idx] = [0.003, 0.005, 0.01]
     runs = []
-    for _ in range(2):
+    for recorded in (False, False, True):
         loop = InverseLoop(ctx, truth.replace(scene=sc.with_theta(th0)), lo, hi, lr,
                            unconstrained_start(th0, lo, hi), [MicroBatch([0, 1]), MicroBatch([2, 3, 4])],
-                           target=sc, lambda1=0.2, lambda2=1.0)
+                           target=sc, lambda1=0.2, lambda2=1.0, recorded=recorded)
         losses = [float(loop.iterate().item()) for _ in range(10)]
         runs.append((losses, loop.u.cpu().numpy().copy()))
-    assert runs[0][0] == runs[1][0]
-    assert np.array_equal(runs[0][1], runs[1][1])
+    for r in runs[1:]:
+        assert r[0] == runs[0][0]
+        assert np.array_equal(r[1], runs[0][1])
 
 
 def test_speed_of_sound_recovery(L, ctx):
