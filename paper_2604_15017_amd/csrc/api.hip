@@ -225,7 +225,7 @@ int us_probe_upload(us_ctx* ctx, const us_probe_desc* d, us_probe** out) {
   p->d = *d;
   p->M = M;
   p->pv = ProbeView{d->n_elem, d->n_t, d->pitch, d->elem_width, d->elem_height, d->f0, d->fs,
-                    d->c_ref, d->alpha_main, d->alpha_cut};
+                    d->c_ref, d->alpha_main, d->alpha_cut, std::cos(d->alpha_main), std::cos(d->alpha_cut)};
   const bool pow2 = (d->n_t & (d->n_t - 1)) == 0;
   if (hipMalloc(&p->taps, taps.size() * sizeof(float)) != hipSuccess ||
       hipMalloc(&p->taps_rev, rev.size() * sizeof(float)) != hipSuccess ||

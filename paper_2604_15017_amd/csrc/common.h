@@ -120,6 +120,7 @@ __device__ __forceinline__ double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y
 struct ProbeView {
   int n_elem, n_t;
   double pitch, elem_w, elem_h, f0, fs, c_ref, alpha_m, alpha_c;
+  double cos_m, cos_c;   // cos(alpha_m), cos(alpha_c)
 };
 
 // Scene as the kernels see it (device pointers; copied to LDS per block).
@@ -250,13 +251,20 @@ struct TxTable {
 };
 
 // Receive directivity (Eq. cutoff) as a function of the cosine of the angle
-// between the element normal and the direction the wave comes from.
+// between the element normal and the direction the wave comes from: 1 up to
+// alpha_m, 0 beyond alpha_c (both tested on the cosine), linear in the angle
+// between.
+// The ramp between the two angles, out of line: inlined, the arc cosine's
+// constants were hoisted out of the transport loops and spilled, and every
+// ray reloaded them.
+__device__ __attribute__((noinline)) double rx_ramp(const ProbeView& p, double c) {
+  return (p.alpha_c - acos(c)) / (p.alpha_c - p.alpha_m);
+}
 __device__ __forceinline__ double rx_directivity(const ProbeView& p, double cos_a) {
   const double c = fmin(1.0, fmax(-1.0, cos_a));
-  const double al = acos(c);
-  if (al <= p.alpha_m) return 1.0;
-  if (al > p.alpha_c) return 0.0;
-  return (p.alpha_c - al) / (p.alpha_c - p.alpha_m);
+  if (c >= p.cos_m) return 1.0;
+  if (c < p.cos_c) return 0.0;
+  return rx_ramp(p, c);
 }
 
 // Block-aggregated append to two queues at once. Each lane with keep_a
