@@ -254,6 +254,14 @@ struct TxTable {
 // between the element normal and the direction the wave comes from: 1 up to
 // alpha_m, 0 beyond alpha_c (both tested on the cosine), linear in the angle
 // between.
+// Out-of-line arc cosine, exponential, sine and cosine for the transport and
+// replay loops: inlined, their polynomials' constants are hoisted out of the
+// loops and spilled, and every ray reloads them from scratch memory.
+struct SinCos { double s, c; };
+__device__ __attribute__((noinline)) double exp_ool(double x) { return exp(x); }
+__device__ __attribute__((noinline)) double acos_ool(double x) { return acos(x); }
+__device__ __attribute__((noinline)) SinCos sincos_ool(double x) { return SinCos{sin(x), cos(x)}; }
+
 // The ramp between the two angles, out of line: inlined, the arc cosine's
 // constants were hoisted out of the transport loops and spilled, and every
 // ray reloaded them.

@@ -413,7 +413,8 @@ __device__ __forceinline__ Glossy glossy_reflect(d3 d, const Coef& f, double rho
   const double ch = 1.0 / sqrt(1.0 + th * th);
   const double sh = th * ch;
   const double phi = 2.0 * kPi * u2;
-  const d3 m = fr.b1 * (sh * cos(phi)) + fr.b2 * (sh * sin(phi)) + f.nr * ch;
+  const SinCos sc = sincos_ool(phi);
+  const d3 m = fr.b1 * (sh * sc.c) + fr.b2 * (sh * sc.s) + f.nr * ch;
   Glossy o;
   const double wh = dot(d, m);
   o.dir = d - m * (2.0 * wh);

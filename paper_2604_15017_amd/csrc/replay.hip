@@ -128,7 +128,7 @@ __device__ __forceinline__ void smith_g1_vjp(double c, double rho, double gbar, 
 // d/dc of the receive directivity (Eq. cutoff) at cosine c; zero outside the ramp.
 __device__ __forceinline__ double rx_directivity_deriv(const ProbeView& p, double cos_a) {
   const double c = fmin(1.0, fmax(-1.0, cos_a));
-  const double al = acos(c);
+  const double al = acos_ool(c);
   if (al <= p.alpha_m || al > p.alpha_c) return 0.0;
   const double s = sqrt(fmax(0.0, 1.0 - c * c));
   return s > 0.0 ? 1.0 / ((p.alpha_c - p.alpha_m) * s) : 0.0;
@@ -329,7 +329,7 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   if (!mr.reached) return;   // blocked: the forward dropped this deposit
   const int n_cross = mr.crossings;
   const double tof = mr.tof;
-  const double rest = mr.trans * exp(-mr.att);   // the attenuation of all legs at once, as the forward
+  const double rest = mr.trans * exp_ool(-mr.att);   // the attenuation of all legs at once, as the forward
   const double amp = amp0 * rest;
   double GA, GT;
   tent_adjoint(C.gh + (C.row_base + e2) * (long)P.n_t, P.n_t, P.fs, tof, amp, &GA, &GT);
@@ -441,7 +441,7 @@ __device__ __forceinline__ Step step_at(const SceneLDS& S, d3 o, d3 d, double t,
   Step st;
   st.h = h;
   st.L = h.t;
-  st.E = exp(-(S.a[region] * h.t));
+  st.E = exp_ool(-(S.a[region] * h.t));
   st.tp = t + h.t * S.ic[region];   // as the forward transport forms it
   st.watt = w * st.E;
   st.x = o + d * h.t;
@@ -518,7 +518,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
         a.stk.last[ci] = k;
         if (kDeposit) {   // a recorded forward: the array hit's deposit, as the bounce kernel makes it
           const double th = t + h.t * S.ic[region];
-          const double wh = w * exp(-(S.a[region] * h.t));
+          const double wh = w * exp_ool(-(S.a[region] * h.t));
           const d3 x = o + d * h.t;
           const double half = 0.5 * (double)P.n_elem * P.pitch;
           if (delta && fabs(x.x) < half && fabs(x.y) < 0.5 * P.elem_h) {
@@ -562,7 +562,8 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
           const d3 b1{1.0 + sg * nn.x * nn.x * aa, sg * bb, -sg * nn.x};
           const d3 b2{bb, sg + nn.y * nn.y * aa, -nn.y};
           const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
-          d = b1 * (rr * cos(phi)) + b2 * (rr * sin(phi)) + nn * sqrt(1.0 - v.u2);
+          const SinCos sc = sincos_ool(phi);
+          d = b1 * (rr * sc.c) + b2 * (rr * sc.s) + nn * sqrt(1.0 - v.u2);
           w *= st.f.Ar / st.f.RE;
           delta = false;
         } else {
@@ -678,7 +679,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                                              [](int, double, int, const Surface&, const Coef&) {});
     if (!mr.reached) continue;
     amp *= mr.trans;
-    amp *= exp(-mr.att);
+    amp *= exp_ool(-mr.att);
     Deposit dp;
     if (make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, mr.tof, amp, &dp))
       add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
@@ -845,7 +846,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
           const double th = rho * kap;
           const double lz = 1.0 / sqrt(1.0 + th * th);
           const double sh = th * lz;
-          const double phi = 2.0 * kPi * v.u2, cph = cos(phi), sph = sin(phi);
+          const double phi = 2.0 * kPi * v.u2;
+          const SinCos scp = sincos_ool(phi);
+          const double cph = scp.c, sph = scp.s;
           const double lx = sh * cph, ly = sh * sph;
           const d3 m = fr.b1 * lx + fr.b2 * ly + nn * lz;
           const double wh = dot(d0, m);
@@ -877,7 +880,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) voi
           }
         } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
           const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
-          const double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(1.0 - v.u2);
+          const SinCos sc = sincos_ool(phi);
+          const double lx = rr * sc.c, ly = rr * sc.s, lz = sqrt(1.0 - v.u2);
           nrb = nrb + frame_vjp(f.nr, lx, ly, lz, db);
           wattb += wb * f.Ar / f.RE;
           Ab += wb * watt / f.RE;

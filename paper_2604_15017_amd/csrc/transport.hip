@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
       if (kAudit) hsum += event_mix(kEvHit, k, ((uint32_t)h.kind << 24) | ((uint32_t)(hit_id(S, h) + 1) & 0xFFFFFFu));
       if (h.kind != kHitNone) {
         t += h.t * S.ic[region];
-        w *= exp(-(S.a[region] * h.t));
+        w *= exp_ool(-(S.a[region] * h.t));
         x = o + d * h.t;
         if (h.kind == kHitArray) {
           const double half = 0.5 * (double)P.n_elem * P.pitch;
@@ -165,7 +165,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
             const d3 b1{1.0 + sg * n.x * n.x * aa, sg * bb, -sg * n.x};
             const d3 b2{bb, sg + n.y * n.y * aa, -n.y};
             const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
-            const double lx = rr * cos(phi), ly = rr * sin(phi), lz = sqrt(1.0 - v.u2);
+            const SinCos sc = sincos_ool(phi);
+            const double lx = rr * sc.c, ly = rr * sc.s, lz = sqrt(1.0 - v.u2);
             d = b1 * lx + b2 * ly + n * lz;
             w *= f.Ar / f.RE;
             delta = false; branch = 1;
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4
     bool rec = false;
     if (!blocked) {
       ++n_dep;
-      amp *= exp(-mr.att);   // the attenuation of all legs at once
+      amp *= exp_ool(-mr.att);   // the attenuation of all legs at once
       rec = make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, tof, amp, &dp);
     }
     // record for the binned splat (one atomic per wave on this block's shard
