@@ -766,7 +766,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
 // Phase 3 (one thread per ray): the reverse sweep over the kept steps, with
 // the secondary-ray adjoints of phase 2 added at their interactions; no
 // intersection queries.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_replay_reverse(ReplayArgs a, long n) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_replay_reverse(ReplayArgs a, long n) {
   if ((long)blockIdx.x * blockDim.x >= n) return;
   __shared__ SceneLDS S;
   extern __shared__ unsigned long long gsh[];   // gradient accumulators (grad_copies copies), acquisition accumulators
@@ -1075,7 +1075,7 @@ void launch_grad_finish(const unsigned long long* g_sum, int n_grad, double* g_t
 
 void launch_replay_reverse(const ReplayArgs& a0, long n, hipStream_t s) {
   ReplayArgs a = a0;
-  a.grad_copies = grad_copies_for(a, 2, acq_lds(a));
+  a.grad_copies = grad_copies_for(a, 3, acq_lds(a));
   hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a) + acq_lds(a), s, a, n);
 }
 
