@@ -12,7 +12,9 @@ Frame (Renderer.render_frame) is the same chain as one Function: its forward
 makes the three forward calls, its backward is one us_frame_vjp call, which
 takes dL/dB to the parameters with the intermediate gradients in its
 workspace (the analytic-signal and pulse adjoints fused into one kernel);
-the gradient is bit for bit that of the three-Function chain.
+the gradient is bit for bit that of the three-Function chain. With
+render_frame(theta, recorded=True) the forward keeps the path records and the
+backward reads them (us_frame_vjp_recorded), the same gradient again.
 
 Fixed ray realisations (common random numbers): the seed and ray range are
 attributes of the Renderer, constants of the differentiation.
@@ -95,10 +97,24 @@ class Renderer:
         theta = self.theta0 if theta is None else theta
         return self.bmode(self.beamform(self.simulate_rf(theta, acq), acq))
 
-    def render_frame(self, theta: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """theta -> B-mode as one Function whose backward is us_frame_vjp."""
+    def render_frame(self, theta: Optional[torch.Tensor] = None, recorded: bool = False) -> torch.Tensor:
+        """theta -> B-mode as one Function whose backward is us_frame_vjp. With
+        `recorded`, the forward keeps the path records (device memory for the
+        whole frame, one workspace per Renderer) and the backward reads them
+        (us_frame_vjp_recorded, the same gradient bit for bit); a backward
+        whose records were overwritten or whose parameters changed since
+        traces the paths again."""
         theta = self.theta0 if theta is None else theta
-        return Frame.apply(theta, self)
+        return Frame.apply(theta, self, recorded)
+
+    def record_workspace(self) -> torch.Tensor:
+        if getattr(self, "_ws_record", None) is None:
+            wl = self.wl
+            n = L.us_recorded_workspace_size(self.scene, self.probe, wl.n_tx, self.ray_count, wl.max_bounces)
+            if n == 0:
+                raise ValueError("a recorded frame takes at most 64 transmits and at least one ray")
+            self._ws_record = L._workspace(n, self.ctx.torch_device)
+        return self._ws_record
 
     def frame_workspace(self) -> torch.Tensor:
         if getattr(self, "_ws_frame", None) is None:
@@ -191,13 +207,22 @@ class BMode(torch.autograd.Function):
 
 class Frame(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, theta: torch.Tensor, r: Renderer):
+    def forward(fctx, theta: torch.Tensor, r: Renderer, recorded: bool = False):
         theta = theta.detach().to(torch.float64).contiguous()
         r.scene.set_params(theta)
         wl = r.wl
-        rf = L.us_simulate_rf(r.ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
-                              wl.rays_per_elem, wl.max_bounces, ray_begin=r.ray_begin,
-                              ray_count=r.ray_count, workspace=r.ws_trace)
+        fctx.rec = None
+        if recorded:
+            # the Renderer's one record workspace: a later recorded forward overwrites it
+            r._record_serial = getattr(r, "_record_serial", 0) + 1
+            fctx.serial = r._record_serial
+            rf, fctx.rec = L.us_simulate_rf_recorded(r.ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
+                                                     wl.rays_per_elem, wl.max_bounces, ray_begin=r.ray_begin,
+                                                     ray_count=r.ray_count, workspace=r.record_workspace())
+        else:
+            rf = L.us_simulate_rf(r.ctx, r.scene, r.probe, wl.angles, wl.tx_ids, wl.seed,
+                                  wl.rays_per_elem, wl.max_bounces, ray_begin=r.ray_begin,
+                                  ray_count=r.ray_count, workspace=r.ws_trace)
         iq = L.us_beamform(r.ctx, r.probe, wl.grid, wl.angles, wl.tx_ids, rf, workspace=r.ws_beam)
         b = L.us_bmode(r.ctx, iq, wl.dr_db, workspace=r.ws_bmode)
         fctx.r = r
@@ -208,13 +233,22 @@ class Frame(torch.autograd.Function):
     def backward(fctx, g_b: torch.Tensor):
         r = fctx.r
         theta, iq = fctx.saved_tensors
-        r.scene.set_params(theta)
         wl = r.wl
+        g_b = g_b.to(torch.float32).contiguous()
+        if fctx.rec is not None and fctx.serial == r._record_serial:
+            try:
+                # the records hold while the scene keeps this forward's parameters
+                g_theta = L.us_frame_vjp_recorded(r.ctx, fctx.rec, wl.grid, iq, g_b, wl.dr_db)
+                return g_theta, None, None
+            except L.USError as e:
+                if e.code != L.US_EINVAL:
+                    raise
+        r.scene.set_params(theta)
         g_theta = L.us_frame_vjp(r.ctx, r.scene, r.probe, wl.grid, wl.angles, wl.tx_ids, wl.seed,
-                                 wl.rays_per_elem, wl.max_bounces, iq, g_b.to(torch.float32).contiguous(),
+                                 wl.rays_per_elem, wl.max_bounces, iq, g_b,
                                  wl.dr_db, ray_begin=r.ray_begin, ray_count=r.ray_count,
                                  workspace=r.frame_workspace())
-        return g_theta, None
+        return g_theta, None, None
 
 
 class ImageLoss(torch.autograd.Function):

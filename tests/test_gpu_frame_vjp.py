@@ -98,6 +98,28 @@ def test_autograd_frame_matches_the_chain(L, ctx):
     assert torch.equal(th1.grad, th2.grad)
 
 
+def test_autograd_recorded_frame(L, ctx):
+    """render_frame(recorded=True): the gradient of the plain frame bit for bit;
+    after another recorded forward with other parameters its records are gone
+    and the backward traces the paths again, with the same gradient."""
+    import torch
+    from paper_2604_15017_amd.autograd import Renderer, mse
+    wl = W.layered_phantom(rays_per_tx=1 << 14, n_tx=4)
+    r = Renderer(wl, ctx)
+    b_ref = r.render(torch.tensor(W.layered_phantom_target(wl).theta(), device=ctx.torch_device)).detach()
+    th1 = r.theta0.clone().requires_grad_(True)
+    mse(r.render_frame(th1), b_ref, r).backward()
+    th2 = r.theta0.clone().requires_grad_(True)
+    mse(r.render_frame(th2, recorded=True), b_ref, r).backward()
+    th3 = r.theta0.clone().requires_grad_(True)
+    loss3 = mse(r.render_frame(th3, recorded=True), b_ref, r)
+    other = r.theta0.clone() * (1.0 + 1e-3)
+    r.render_frame(other, recorded=True)   # overwrites the records with other parameters
+    loss3.backward()
+    torch.cuda.synchronize()
+    assert torch.equal(th1.grad, th2.grad) and torch.equal(th1.grad, th3.grad)
+
+
 def test_workspace_too_small(L, ctx):
     import torch
     wl = W.tiny(W.two_layer(rays_per_elem=1 << 8), rays_per_elem=1 << 8)
