@@ -1054,11 +1054,34 @@ namespace {
 // the analytic map's and the pulse's adjoints in one kernel (no g_acq then).
 // Workspace of a recorded frame (one transmit group, one chunk holding all
 // n_tx * ray_count rays): the replay's, then the deposit histogram and its
-// overflow count.
-size_t recorded_bytes(const us_scene* scene, const us_probe* p, int n_tx, int64_t ray_count, int max_bounces) {
+// overflow count, then the march records of the first kMarchPerRay * rays
+// queued diffuse interactions.
+struct RecordedLayout {
+  size_t replay = 0, total = 0;
+  long long* h = nullptr;
+  unsigned long long* over = nullptr;
+  MarchRec* march = nullptr;
+  long march_cap = 0;
+};
+RecordedLayout recorded_layout(const us_scene* scene, const us_probe* p, int n_tx, int64_t ray_count,
+                               int max_bounces, char* base) {
+  RecordedLayout L;
   const long cap = (long)n_tx * ray_count;
-  return align_up(replay_bytes(scene, n_tx, p, max_bounces, cap)) +
-         align_up((size_t)n_tx * p->d.n_elem * p->d.n_t * sizeof(long long)) + kAlign;
+  L.replay = replay_bytes(scene, n_tx, p, max_bounces, cap);
+  size_t off = align_up(L.replay);
+  const size_t hbytes = (size_t)n_tx * p->d.n_elem * p->d.n_t * sizeof(long long);
+  if (base) L.h = (long long*)(base + off);
+  off += align_up(hbytes);
+  if (base) L.over = (unsigned long long*)(base + off);
+  off += kAlign;
+  L.march_cap = max_bounces > 0 && scene->any_diffuse ? kMarchPerRay * cap : 0;
+  if (base && L.march_cap) L.march = (MarchRec*)(base + off);
+  off += align_up((size_t)L.march_cap * sizeof(MarchRec));
+  L.total = off;
+  return L;
+}
+size_t recorded_bytes(const us_scene* scene, const us_probe* p, int n_tx, int64_t ray_count, int max_bounces) {
+  return recorded_layout(scene, p, n_tx, ray_count, max_bounces, nullptr).total;
 }
 
 // FNV-1a over the transmit table, to tell a recorded frame's transmits apart.
@@ -1129,6 +1152,11 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &sums, &q0, &q1,
                &a.counts, &a.sort_count, &a.sort_part);
   if (a.sort_count) a.sort = seg_sort(probe);
+  if (recorded) {   // the marches the recorded forward made
+    const RecordedLayout lay = recorded_layout(scene, probe, n_tx, ray_count, max_bounces, (char*)ws_dev);
+    a.march = lay.march;
+    a.march_cap = lay.march_cap;
+  }
   a.vadj = sums.vadj;
   a.g_sum = sums.g_sum;
   a.acq_sum = sums.acq_sum;
@@ -1341,11 +1369,14 @@ int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe,
   const size_t rb = replay_bytes(scene, n_tx, probe, max_bounces, cap, &a.stk, (char*)ws_dev, &gh, &gh_f0, &sums,
                                  &q0, &q1, &a.counts, &a.sort_count, &a.sort_part);
   if (a.sort_count) a.sort = seg_sort(probe);
-  char* w = (char*)ws_dev + align_up(rb);
+  (void)rb;
+  const RecordedLayout lay = recorded_layout(scene, probe, n_tx, ray_count, max_bounces, (char*)ws_dev);
   const long rows = (long)n_tx * pd.n_elem;
-  a.h = (long long*)w;
-  a.hist_over = (unsigned long long*)(w + align_up((size_t)rows * pd.n_t * sizeof(long long)));
+  a.h = lay.h;
+  a.hist_over = lay.over;
   a.hist_scale = hist_scale(rays_per_elem);
+  a.march = lay.march;
+  a.march_cap = lay.march_cap;
   launch_fill_u32((uint32_t*)a.h, 2L * rows * pd.n_t, 0u, s);
   launch_fill_u32((uint32_t*)a.hist_over, 2, 0u, s);
   launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);

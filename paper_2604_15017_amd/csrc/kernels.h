@@ -124,6 +124,20 @@ struct ReplayStack {
   uint32_t* sort_q;
 };
 constexpr int kMaxReplayBlocks = 2048;
+// The receiver segment of one queued diffuse interaction as a recorded
+// forward marched it: state 0 (no segment: facing away or outside the
+// directivity), 1 (blocked), 2 (reached the element), the march's sums and
+// its first kMarchLegs crossings (distance from the origin, hit word).
+constexpr int kMarchLegs = 8;
+struct alignas(16) MarchRec {
+  double tof, att, trans;
+  uint32_t n_cross, state;
+  double s[kMarchLegs];
+  int h[kMarchLegs];
+};
+static_assert(sizeof(MarchRec) == 128, "march record layout");
+constexpr long kMarchPerRay = 4;   // march records per ray of a recorded frame (more are marched again)
+
 struct ReplayArgs {
   SceneView scene;
   ProbeView probe;
@@ -168,6 +182,11 @@ struct ReplayArgs {
   long long* h;
   double hist_scale;
   unsigned long long* hist_over;
+  // a recorded frame (null otherwise): the march of queued interaction q
+  // (q < march_cap), written by launch_replay_deposit and read by the
+  // secondary phase in place of marching again
+  MarchRec* march;
+  long march_cap;
 };
 // The three phases of the replay over chunk rays [0, n): the forward phase
 // once per step k = 1..max_bounces + 1 (queues swapped in between), the

@@ -281,7 +281,7 @@ __device__ __forceinline__ double interface_backward(const Coef& f, double eta, 
 // Crossings of a receiver segment remembered between the two passes of its
 // adjoint (their distance from the segment's start and hit word, in LDS,
 // interleaved across the block's threads); further crossings are found again.
-constexpr int kLegCache = 8;
+constexpr int kLegCache = kMarchLegs;
 
 struct ReplayCtx {
   const SceneLDS& S;
@@ -293,6 +293,7 @@ struct ReplayCtx {
   int* stk;             // this thread's hierarchy stack in LDS
   double* leg_t;        // this thread's crossing cache in LDS: distance from x ...
   int* leg_h;           // ... and kind << 28 | index
+  const MarchRec* rec;  // the march as a recorded forward made it, or null
 };
 
 // Secondary ray of interaction k at x (weight watt, time tp, interface f):
@@ -318,14 +319,24 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   const double amp0 = watt * f.Ar * (kd / kPi) * co * (P.elem_w * P.elem_h * cel / (r * r)) *
                       (double)P.n_elem * fd;
   // pass 1: the march as the forward did it, its crossings cached in LDS
+  // (a recorded frame reads the march the forward made instead)
   const int step = blockDim.x;
-  const March mr = receiver_march<kMeshes>(
-      S, x, we, r, region, tp, C.stk, [&](int j, double sj, int hw, const Surface&, const Coef&) {
-        if (j < kLegCache) {
-          C.leg_t[j * step] = sj;
-          C.leg_h[j * step] = hw;
-        }
-      });
+  March mr;
+  if (C.rec) {
+    mr = March{C.rec->tof, C.rec->att, C.rec->trans, (int)C.rec->n_cross, C.rec->state == 2u};
+    for (int j = 0; j < kLegCache && j < mr.crossings; ++j) {
+      C.leg_t[j * step] = C.rec->s[j];
+      C.leg_h[j * step] = C.rec->h[j];
+    }
+  } else {
+    mr = receiver_march<kMeshes>(
+        S, x, we, r, region, tp, C.stk, [&](int j, double sj, int hw, const Surface&, const Coef&) {
+          if (j < kLegCache) {
+            C.leg_t[j * step] = sj;
+            C.leg_h[j * step] = hw;
+          }
+        });
+  }
   if (!mr.reached) return;   // blocked: the forward dropped this deposit
   const int n_cross = mr.crossings;
   const double tof = mr.tof;
@@ -668,15 +679,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const d3 dv = d3{elem_x(P, e2), 0.0, 0.0} - st.x;
     const double r = sqrt(dot(dv, dv));
     const d3 we = dv * (1.0 / r);
+    MarchRec* mrec = a.march && q < a.march_cap ? a.march + q : nullptr;
     const double cos_o = dot(st.f.nr, we);
-    if (!(cos_o > 0.0)) continue;
     const double cos_el = -we.z;
-    const double fd = rx_directivity(P, cos_el);
-    if (fd == 0.0) continue;
+    const double fd = cos_o > 0.0 ? rx_directivity(P, cos_el) : 0.0;
+    if (!(cos_o > 0.0) || fd == 0.0) {
+      if (mrec) mrec->state = 0u;
+      continue;
+    }
     double amp = st.watt * st.f.Ar * (st.sf.kd / kPi) * cos_o * (P.elem_w * P.elem_h * cos_el / (r * r)) *
                  (double)P.n_elem * fd;
     const March mr = receiver_march<kMeshes>(S, st.x, we, r, reg, st.tp, stk,
-                                             [](int, double, int, const Surface&, const Coef&) {});
+                                             [&](int j, double sj, int hw, const Surface&, const Coef&) {
+                                               if (mrec && j < kMarchLegs) {
+                                                 mrec->s[j] = sj;
+                                                 mrec->h[j] = hw;
+                                               }
+                                             });
+    if (mrec) {
+      mrec->tof = mr.tof;
+      mrec->att = mr.att;
+      mrec->trans = mr.trans;
+      mrec->n_cross = (uint32_t)mr.crossings;
+      mrec->state = mr.reached ? 2u : 1u;
+    }
     if (!mr.reached) continue;
     amp *= mr.trans;
     amp *= exp_ool(-mr.att);
@@ -747,7 +773,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
     const Step st = step_at(S, o, d, R.t, R.w, reg, h);
     const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
     const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
-    ReplayCtx C{S, P, a.gh, a.gh_f0, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h};
+    ReplayCtx C{S, P, a.gh, a.gh_f0, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h,
+                a.march && q < a.march_cap ? a.march + q : nullptr};
     d3 xb{0, 0, 0}, nrb{0, 0, 0};
     double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0, f0b = 0.0;
     secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb, f0b);
