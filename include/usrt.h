@@ -303,8 +303,9 @@ int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, cons
 /* Recorded frame: a forward that keeps the replay's step records for the
  * backward that follows it (Sec. 3.2 differentiates the path of fixed random
  * numbers; the backward of a recorded frame reads the path instead of tracing
- * it again), trading device memory (about 1.3 KB per ray at twelve
- * interactions) for the replay's forward phase.
+ * it again), trading device memory (about 3 KB per ray at twelve
+ * interactions: step records, the replay's scratch and each receiver
+ * segment's march) for the replay's forward phase and its marches.
  *
  * us_simulate_rf_recorded computes the RF of us_simulate_rf for the same
  * arguments, bit for bit (the same fp64 path arithmetic, the same integer
