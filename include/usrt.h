@@ -252,7 +252,11 @@ int us_beamform_acq_vjp(us_ctx* ctx, const us_probe* probe, const us_grid_desc* 
  * Eq. chain_rule): the paths of the same rays as us_simulate_rf are replayed
  * from their Philox counters (nothing stored between the calls); discrete
  * choices are frozen and branch probabilities are not differentiated.
- *   g_rf_dev in: float [n_tx][n_elem][n_t]; g_theta_dev in/out: double [n_params] */
+ *   g_rf_dev in: float [n_tx][n_elem][n_t]; g_theta_dev in/out: double [n_params]
+ *   ws_dev: the workspace size for the call's ray_count lets the replay take
+ *   all rays in chunks of up to 2^23; a smaller one, down to the size for
+ *   ray_count = 1 (US_ETOOBIG below it), shortens the chunks to what fits.
+ *   The result does not depend on it. */
 size_t us_simulate_rf_vjp_workspace_size(const us_scene* scene, const us_probe* probe,
                                          int32_t n_tx, int64_t ray_count, int32_t max_bounces);
 int us_simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe,
@@ -290,8 +294,10 @@ int us_simulate_rf_vjp_acq(us_ctx* ctx, const us_scene* scene, const us_probe* p
  *   (us_beamform of the same scene, probe, transmits and grid)
  *   g_bmode_dev in: float [n_x][n_z], dL/dB; dr_db as for us_bmode
  *   g_theta_dev in/out: double [n_params], accumulated
- *   ws_dev: us_frame_vjp_workspace_size(...) bytes at least (US_ETOOBIG if
- *   smaller); a larger workspace lets the replay take longer chunks of rays.
+ *   ws_dev: us_frame_vjp_workspace_size(...) bytes for the call's ray_count
+ *   let the replay take all rays in chunks of up to 2^23; a smaller
+ *   workspace, down to the size for ray_count = 1 (US_ETOOBIG below it),
+ *   shortens the chunks to what fits. The result does not depend on it.
  * Arguments are checked as for the three calls (US_EINVAL). */
 size_t us_frame_vjp_workspace_size(const us_scene* scene, const us_probe* probe, const us_grid_desc* grid,
                                    int32_t n_tx, int64_t ray_count, int32_t max_bounces);
@@ -309,7 +315,8 @@ int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, cons
  *
  * us_simulate_rf_recorded computes the RF of us_simulate_rf for the same
  * arguments, bit for bit (the same fp64 path arithmetic, the same integer
- * histogram), and leaves in ws_dev the step record of every segment, the
+ * histogram; counters_dev, optional (NULL), accumulates the same event
+ * counts), and leaves in ws_dev the step record of every segment, the
  * diffuse interactions in the receiver segments' key order and the per-step
  * counts. One launch group only (n_tx <= 64) and ray_count >= 1, all
  * n_tx * ray_count rays in one chunk: ws_dev must hold
@@ -332,8 +339,8 @@ size_t us_recorded_workspace_size(const us_scene* scene, const us_probe* probe, 
                                   int32_t max_bounces);
 int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
                             int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
-                            int64_t ray_count, int32_t max_bounces, float* rf_dev, void* ws_dev, size_t ws_bytes,
-                            void* stream);
+                            int64_t ray_count, int32_t max_bounces, float* rf_dev, int64_t* counters_dev,
+                            void* ws_dev, size_t ws_bytes, void* stream);
 int us_simulate_rf_vjp_recorded(us_ctx* ctx, const us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
                                 int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
                                 int64_t ray_count, int32_t max_bounces, const float* g_rf_dev, double* g_theta_dev,

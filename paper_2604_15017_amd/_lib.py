@@ -92,7 +92,7 @@ _SIGNATURES = {
     "us_frame_vjp": (ctypes.c_int, [vp, vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                     ctypes.c_float, vp, vp, sz, vp]),
     "us_recorded_workspace_size": (sz, [vp, vp, i32, i64, i32]),
-    "us_simulate_rf_recorded": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp, sz, vp]),
+    "us_simulate_rf_recorded": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp, vp, sz, vp]),
     "us_simulate_rf_vjp_recorded": (ctypes.c_int, [vp, vp, vp, vp, i32, u64, i32, i64, i64, i32, vp, vp,
                                                    vp, sz, vp]),
     "us_frame_vjp_recorded_workspace_size": (sz, [vp, vp, i32]),
@@ -553,9 +553,11 @@ def us_recorded_workspace_size(scene: Scene, probe: Probe, n_tx: int, ray_count:
 
 def us_simulate_rf_recorded(ctx: Context, scene: Scene, probe: Probe, angles, tx_ids, seed: int,
                             rays_per_elem: int, max_bounces: int, ray_begin: int = 0,
-                            ray_count: Optional[int] = None, rf=None, workspace=None, stream=None):
-    """The RF of us_simulate_rf, keeping the path records for a recorded
-    backward; returns (rf, Recorded)."""
+                            ray_count: Optional[int] = None, rf=None, counters=None, workspace=None,
+                            stream=None):
+    """The RF of us_simulate_rf (and its event counters, added to counters
+    when given), keeping the path records for a recorded backward; returns
+    (rf, Recorded)."""
     torch = _torch()
     p = probe.desc
     tx, n_tx = _tx_array(angles, tx_ids)
@@ -564,6 +566,8 @@ def us_simulate_rf_recorded(ctx: Context, scene: Scene, probe: Probe, angles, tx
     if rf is None:
         rf = torch.empty((n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=ctx.torch_device)
     _expect(rf, n_tx * p.n_elem * p.n_t, torch.float32, "rf")
+    if counters is not None:
+        _expect(counters, 5, torch.int64, "counters")
     if workspace is None:
         need = us_recorded_workspace_size(scene, probe, n_tx, ray_count, max_bounces)
         if need == 0:
@@ -572,7 +576,8 @@ def us_simulate_rf_recorded(ctx: Context, scene: Scene, probe: Probe, angles, tx
     _expect_ws(workspace)
     _check(load().us_simulate_rf_recorded(ctx.handle, scene.handle, probe.handle, tx, n_tx, int(seed),
                                           int(rays_per_elem), int(ray_begin), int(ray_count), int(max_bounces),
-                                          _ptr(rf), _ptr(workspace), workspace.numel(), _stream(stream)),
+                                          _ptr(rf), _ptr(counters), _ptr(workspace), workspace.numel(),
+                                          _stream(stream)),
            "us_simulate_rf_recorded")
     return rf, Recorded(scene, probe, angles, tx_ids, seed, rays_per_elem, max_bounces, ray_begin, ray_count,
                         workspace)

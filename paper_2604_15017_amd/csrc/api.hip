@@ -1330,8 +1330,9 @@ int us_frame_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, cons
   if (rc) return rc;
   rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
-  const size_t need = us_frame_vjp_workspace_size(scene, probe, grid, n_tx, ray_count, max_bounces);
-  if (ws_bytes < need) return fail(US_ETOOBIG, "us_frame_vjp: workspace too small");
+  // the image buffers and the replay of chunks of one ray at least, as us_simulate_rf_vjp
+  if (ws_bytes < frame_image_bytes(probe, grid, n_tx) + replay_bytes(scene, n_tx, probe, max_bounces, 1))
+    return fail(US_ETOOBIG, "us_frame_vjp: workspace too small");
   US_HIP(bind_device(ctx->device));
   float2* gA = nullptr;
   char* w = frame_image_vjp(ctx, probe, grid, tx, n_tx, iq_dev, g_bmode_dev, dr_db, (char*)ws_dev, &gA,
@@ -1348,8 +1349,8 @@ size_t us_recorded_workspace_size(const us_scene* scene, const us_probe* probe, 
 
 int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe, const us_tx_desc* tx,
                             int32_t n_tx, uint64_t seed, int32_t rays_per_elem, int64_t ray_begin,
-                            int64_t ray_count, int32_t max_bounces, float* rf_dev, void* ws_dev, size_t ws_bytes,
-                            void* stream) {
+                            int64_t ray_count, int32_t max_bounces, float* rf_dev, int64_t* counters_dev,
+                            void* ws_dev, size_t ws_bytes, void* stream) {
   US_CHECK(ctx && rf_dev && ws_dev, "us_simulate_rf_recorded: NULL ctx, rf or workspace");
   int rc = check_trace_args(scene, probe, tx, n_tx, rays_per_elem, ray_begin, ray_count, max_bounces);
   if (rc) return rc;
@@ -1377,6 +1378,7 @@ int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe,
   a.hist_scale = hist_scale(rays_per_elem);
   a.march = lay.march;
   a.march_cap = lay.march_cap;
+  a.counters = (unsigned long long*)counters_dev;
   launch_fill_u32((uint32_t*)a.h, 2L * rows * pd.n_t, 0u, s);
   launch_fill_u32((uint32_t*)a.hist_over, 2, 0u, s);
   launch_fill_u32((uint32_t*)a.counts, 2L * (max_bounces + 2), 0u, s);

@@ -275,6 +275,24 @@ __device__ __forceinline__ double rx_directivity(const ProbeView& p, double cos_
   return rx_ramp(p, c);
 }
 
+// Block-level reduction of the event counters into the global int64[5]:
+// primary segments, secondary segments, deposits, interactions, secondary
+// rays. Called by every thread of the block (it contains barriers).
+__device__ __forceinline__ void flush_counters(unsigned long long* g, unsigned long long c0,
+                                               unsigned long long c1, unsigned long long c2,
+                                               unsigned long long c3, unsigned long long c4) {
+  __shared__ unsigned long long acc[5];
+  if (threadIdx.x < 5) acc[threadIdx.x] = 0;
+  __syncthreads();
+  if (c0) atomicAdd(&acc[0], c0);
+  if (c1) atomicAdd(&acc[1], c1);
+  if (c2) atomicAdd(&acc[2], c2);
+  if (c3) atomicAdd(&acc[3], c3);
+  if (c4) atomicAdd(&acc[4], c4);
+  __syncthreads();
+  if (threadIdx.x < 5 && acc[threadIdx.x]) atomicAdd(&g[threadIdx.x], acc[threadIdx.x]);
+}
+
 // Block-aggregated append to two queues at once. Each lane with keep_a
 // (keep_b) receives a distinct slot in queue A (B). The two running counts
 // share one 64-bit word (A in the low half, B in the high half), so a block

@@ -187,6 +187,10 @@ struct ReplayArgs {
   // secondary phase in place of marching again
   MarchRec* march;
   long march_cap;
+  // a recorded forward, optional (null): the event counters of the forward
+  // transport (int64[5], accumulated), counted by the forward phase's
+  // deposit variant and by launch_replay_deposit
+  unsigned long long* counters;
 };
 // The three phases of the replay over chunk rays [0, n): the forward phase
 // once per step k = 1..max_bounces + 1 (queues swapped in between), the

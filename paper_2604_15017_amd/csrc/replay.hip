@@ -484,6 +484,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
   const int B = a.max_bounces;
   const long cap = a.cap;
   const long stride = (long)gridDim.x * blockDim.x;
+  uint32_t n_seg = 0, n_dep = 0, n_int = 0;   // event counters of a recorded forward
   // block-uniform loop: the queue append below synchronises the block
   for (long base = (long)blockIdx.x * blockDim.x; base < n_in; base += stride) {
     const long iq = base + threadIdx.x;
@@ -522,6 +523,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
       }
       const long at = (long)(k - 1) * cap + ci;
       const Hit h = closest_hit<kMeshes>(S, o, d, true, stk);
+      if (kDeposit) ++n_seg;
       a.stk.rec[at] = StepRec{o.x, o.y, o.z, d.x, d.y, d.z, t, w, h.t,
                               (uint32_t)region | ((uint32_t)delta << 8) | ((uint32_t)h.kind << 12),
                               h.index};
@@ -540,11 +542,13 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
             uint32_t rid;
             ray_of(a, ci, &txl, &rid);
             Deposit dp;
+            n_dep += fd > 0.0;
             if (fd > 0.0 && make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e), P.n_t, P.fs, th, wh * fd, &dp))
               add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
           }
         }
       } else if (h.kind != kHitNone && k <= B) {
+        if (kDeposit) ++n_int;
         int txl;
         uint32_t rid;
         ray_of(a, ci, &txl, &rid);
@@ -609,6 +613,7 @@ void k_replay_forward(ReplayArgs a, int k, long n) {
       a.qout.meta[slot] = (uint32_t)region | ((uint32_t)delta << 8);
     }
   }
+  if (kDeposit && a.counters) flush_counters(a.counters, n_seg, 0, n_dep, n_int, 0);
 }
 
 // Phase 2 (one thread per queued interaction): the secondary ray towards
@@ -659,6 +664,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
   int* stk = bvh_stack + threadIdx.x;
   const ProbeView& P = a.probe;
   const long cap = a.cap;
+  uint32_t n_seg = 0, n_dep = 0, n_rays = 0;   // event counters, as the secondary kernel counts them
   for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
     int k = 1, hi = B;
     while (k < hi) {
@@ -687,6 +693,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       if (mrec) mrec->state = 0u;
       continue;
     }
+    ++n_rays;
     double amp = st.watt * st.f.Ar * (st.sf.kd / kPi) * cos_o * (P.elem_w * P.elem_h * cos_el / (r * r)) *
                  (double)P.n_elem * fd;
     const March mr = receiver_march<kMeshes>(S, st.x, we, r, reg, st.tp, stk,
@@ -703,13 +710,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
       mrec->n_cross = (uint32_t)mr.crossings;
       mrec->state = mr.reached ? 2u : 1u;
     }
+    n_seg += mr.reached ? mr.crossings + 1 : mr.crossings;   // one segment per leg
     if (!mr.reached) continue;
+    ++n_dep;
     amp *= mr.trans;
     amp *= exp_ool(-mr.att);
     Deposit dp;
     if (make_deposit((uint32_t)((a.tx_base + txl) * P.n_elem + e2), P.n_t, P.fs, mr.tof, amp, &dp))
       add_deposit(a.h, P.n_t, dp, a.hist_scale, a.hist_over);
   }
+  if (a.counters) flush_counters(a.counters, 0, n_seg, n_dep, 0, n_rays);
 }
 
 // Acquisition-parameter adjoints of one block (the steering angles of the

@@ -16,27 +16,6 @@
 
 namespace usrt {
 
-namespace {
-
-// Block-level reduction of the event counters into the global int64[5]:
-// primary segments, secondary segments, deposits, interactions, secondary rays.
-__device__ __forceinline__ void flush_counters(unsigned long long* g, unsigned long long c0,
-                                               unsigned long long c1, unsigned long long c2,
-                                               unsigned long long c3, unsigned long long c4) {
-  __shared__ unsigned long long acc[5];
-  if (threadIdx.x < 5) acc[threadIdx.x] = 0;
-  __syncthreads();
-  if (c0) atomicAdd(&acc[0], c0);
-  if (c1) atomicAdd(&acc[1], c1);
-  if (c2) atomicAdd(&acc[2], c2);
-  if (c3) atomicAdd(&acc[3], c3);
-  if (c4) atomicAdd(&acc[4], c4);
-  __syncthreads();
-  if (threadIdx.x < 5 && acc[threadIdx.x]) atomicAdd(&g[threadIdx.x], acc[threadIdx.x]);
-}
-
-}  // namespace
-
 // One interaction step for every live ray (k = 1 fuses the emission).
 template <bool kAudit, bool kMeshes>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 4 : 3, 8))) void k_bounce(TraceArgs a, int k) {

@@ -6,11 +6,16 @@ slot and enough device memory are free, runs every admitted request on its
 slot's own HIP stream so that requests overlap on the device, and records per
 request the arrival, admission and completion times.
 
+Gradient requests take the whole backward in one call (us_frame_vjp). One
+whose path records fit RECORD_MAX_BYTES is rendered by the recorded forward
+and its backward reads those records instead of tracing the paths again
+(us_frame_vjp_recorded); the result is the same bits either way.
+
 Admission accounting: a request reserves the bytes of everything it
 allocates (RF, analytic-signal and queue workspaces, image buffers, and for
-gradient requests the adjoint buffers and the replay workspace), as reported
-by the library's *_workspace_size calls; a request larger than the cap is
-rejected with an error result and the loop goes on.
+gradient requests the adjoint buffers and the replay or record workspace), as
+reported by the library's *_workspace_size calls; a request larger than the
+cap is rejected with an error result and the loop goes on.
 
 The executor is pluggable: GpuExecutor calls the C-ABI; tests of admission,
 ordering, latency accounting and failure handling use a host-only executor.
@@ -30,6 +35,11 @@ import numpy as np
 # rays (some 5 GB at twelve interactions): a whole-frame chunk would save a few
 # launches but reserve up to 20 GB per request in flight.
 REPLAY_CHUNK_RAYS = 1 << 21
+
+# A gradient request records its paths (about 3 KB of device memory per ray
+# at twelve interactions) when the records take at most this many bytes:
+# some 2.8 million rays.
+RECORD_MAX_BYTES = 8 << 30
 
 
 @dataclasses.dataclass
@@ -169,10 +179,13 @@ def latency_stats(results: List[Result]) -> dict:
 class GpuExecutor:
     """Runs requests through the C-ABI on one stream per slot."""
 
-    def __init__(self, ctx=None, n_slots: int = 8):
+    def __init__(self, ctx=None, n_slots: int = 8, record_max_bytes: int = RECORD_MAX_BYTES,
+                 replay_chunk_rays: int = REPLAY_CHUNK_RAYS):
         import torch
         from . import _lib as L
         self.L, self.torch = L, torch
+        self.record_max_bytes = int(record_max_bytes)
+        self.replay_chunk_rays = int(replay_chunk_rays)
         self.ctx = ctx or L.Context(0)
         self.streams = [torch.cuda.Stream(device=self.ctx.torch_device) for _ in range(n_slots)]
         self.scenes: Dict[int, object] = {}
@@ -188,24 +201,40 @@ class GpuExecutor:
             self.probes[kp] = (self.L.Probe(self.ctx, wl.probe), wl.probe)
         return self.scenes[ks][0], self.probes[kp][0]
 
+    def record_bytes(self, req: Request) -> int:
+        """Bytes of the path records of a gradient request, 0 when it is
+        traced again in its backward (no gradient, records over the cap, or
+        more transmits than one recorded forward takes)."""
+        if not req.want_grad:
+            return 0
+        wl = req.workload
+        scene, probe = self.resident(wl)
+        n = self.L.us_recorded_workspace_size(scene, probe, wl.n_tx, wl.rays_per_tx, wl.max_bounces)
+        return n if 0 < n <= self.record_max_bytes else 0
+
     def sizes(self, req: Request) -> dict:
         wl = req.workload
         scene, probe = self.resident(wl)
         L, p, g = self.L, wl.probe, wl.grid
         n_tx = wl.n_tx
         rows = n_tx * p.n_elem * p.n_t
+        rec = self.record_bytes(req)
         s = {"rf": 4 * rows, "iq": 8 * g.n_px, "bmode": 4 * g.n_px,
-             "ws_trace": L.us_simulate_rf_workspace_size(scene, probe, n_tx, wl.rays_per_tx, wl.max_bounces),
              "ws_beam": L.load().us_beamform_workspace_size(probe.handle, n_tx),
              "ws_bmode": L.load().us_bmode_workspace_size(g.n_px), "counters": 40}
+        if rec:
+            s["ws_record"] = rec
+        else:
+            s["ws_trace"] = L.us_simulate_rf_workspace_size(scene, probe, n_tx, wl.rays_per_tx, wl.max_bounces)
         if req.want_grad:
-            s.update({"b_ref": 4 * g.n_px, "g_b": 4 * g.n_px, "g_iq": 8 * g.n_px, "g_rf": 4 * rows,
-                      "loss": 8, "g_theta": 8 * scene.n_params,
-                      "ws_loss": L.load().us_image_loss_workspace_size(g.n_px),
-                      "ws_beam_vjp": L.load().us_beamform_vjp_workspace_size(probe.handle, n_tx),
-                      "ws_replay": L.us_simulate_rf_vjp_workspace_size(
-                          scene, probe, n_tx, min(wl.rays_per_tx, max(1, REPLAY_CHUNK_RAYS // n_tx)),
-                          wl.max_bounces)})
+            s.update({"b_ref": 4 * g.n_px, "g_b": 4 * g.n_px, "loss": 8, "g_theta": 8 * scene.n_params,
+                      "ws_loss": L.load().us_image_loss_workspace_size(g.n_px)})
+            if rec:
+                s["ws_frame_vjp"] = L.us_frame_vjp_recorded_workspace_size(probe, g, n_tx)
+            else:
+                s["ws_frame_vjp"] = L.us_frame_vjp_workspace_size(
+                    scene, probe, g, n_tx, min(wl.rays_per_tx, max(1, self.replay_chunk_rays // n_tx)),
+                    wl.max_bounces)
         return s
 
     def bytes_needed(self, req: Request) -> int:
@@ -225,11 +254,18 @@ class GpuExecutor:
             t["rf"] = torch.empty((wl.n_tx, p.n_elem, p.n_t), dtype=torch.float32, device=dev)
             t["iq"] = torch.empty((g.n_x, g.n_z, 2), dtype=torch.float32, device=dev)
             t["bmode"] = torch.empty((g.n_x, g.n_z), dtype=torch.float32, device=dev)
-            for k in ("ws_trace", "ws_beam", "ws_bmode"):
-                t[k] = torch.empty(max(256, sz[k]), dtype=torch.uint8, device=dev)
-            L.us_simulate_rf(self.ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
-                             wl.max_bounces, rf=t["rf"], counters=t["counters"], workspace=t["ws_trace"],
-                             stream=st)
+            for k in ("ws_trace", "ws_record", "ws_beam", "ws_bmode", "ws_loss", "ws_frame_vjp"):
+                if k in sz:
+                    t[k] = torch.empty(max(256, sz[k]), dtype=torch.uint8, device=dev)
+            rec = None
+            if "ws_record" in sz:
+                _, rec = L.us_simulate_rf_recorded(self.ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed,
+                                                   wl.rays_per_elem, wl.max_bounces, rf=t["rf"],
+                                                   counters=t["counters"], workspace=t["ws_record"], stream=st)
+            else:
+                L.us_simulate_rf(self.ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                                 wl.max_bounces, rf=t["rf"], counters=t["counters"], workspace=t["ws_trace"],
+                                 stream=st)
             L.us_beamform(self.ctx, probe, g, wl.angles, wl.tx_ids, t["rf"], iq=t["iq"],
                           workspace=t["ws_beam"], stream=st)
             L.us_bmode(self.ctx, t["iq"], wl.dr_db, out=t["bmode"], workspace=t["ws_bmode"], stream=st)
@@ -237,20 +273,16 @@ class GpuExecutor:
                 t["b_ref"] = self._device_ref(req.b_ref, t)
                 t["loss"] = torch.empty(1, dtype=torch.float64, device=dev)
                 t["g_b"] = torch.empty_like(t["bmode"])
-                t["g_iq"] = torch.empty_like(t["iq"])
-                t["g_rf"] = torch.empty_like(t["rf"])
                 t["g_theta"] = torch.zeros(scene.n_params, dtype=torch.float64, device=dev)
-                for k in ("ws_beam_vjp", "ws_replay", "ws_loss"):
-                    t[k] = torch.empty(max(256, sz[k]), dtype=torch.uint8, device=dev)
                 L.us_image_loss(self.ctx, t["bmode"], t["b_ref"], 0.0, 1.0, loss=t["loss"],
                                 g_bmode=t["g_b"], workspace=t["ws_loss"], stream=st)
-                L.us_bmode_vjp(self.ctx, t["iq"], t["g_b"], wl.dr_db, g_iq=t["g_iq"],
-                               workspace=t["ws_bmode"], stream=st)
-                L.us_beamform_vjp(self.ctx, probe, g, wl.angles, wl.tx_ids, t["g_iq"], g_rf=t["g_rf"],
-                                  workspace=t["ws_beam_vjp"], stream=st)
-                L.us_simulate_rf_vjp(self.ctx, scene, probe, wl.angles, wl.tx_ids, wl.seed,
-                                     wl.rays_per_elem, wl.max_bounces, t["g_rf"], g_theta=t["g_theta"],
-                                     workspace=t["ws_replay"], stream=st)
+                if rec is not None:
+                    L.us_frame_vjp_recorded(self.ctx, rec, g, t["iq"], t["g_b"], wl.dr_db, g_theta=t["g_theta"],
+                                            workspace=t["ws_frame_vjp"], stream=st)
+                else:
+                    L.us_frame_vjp(self.ctx, scene, probe, g, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
+                                   wl.max_bounces, t["iq"], t["g_b"], wl.dr_db, g_theta=t["g_theta"],
+                                   workspace=t["ws_frame_vjp"], stream=st)
             ev = torch.cuda.Event()
             ev.record(st)
         return (t, ev)

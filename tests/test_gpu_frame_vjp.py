@@ -120,14 +120,24 @@ def test_autograd_recorded_frame(L, ctx):
     assert torch.equal(th1.grad, th2.grad) and torch.equal(th1.grad, th3.grad)
 
 
-def test_workspace_too_small(L, ctx):
+def test_workspace_sets_the_chunks(L, ctx):
+    """A workspace sized for fewer rays than the frame's makes the replay run
+    in shorter chunks, with the same gradient bit for bit; one holding the
+    image buffers but no replay chunk is refused."""
     import torch
     wl = W.tiny(W.two_layer(rays_per_elem=1 << 8), rays_per_elem=1 << 8)
     scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
     iq, b = frame(L, ctx, scene, probe, wl, 0, None)
     g_b = torch.ones_like(b)
-    need = L.us_frame_vjp_workspace_size(scene, probe, wl.grid, wl.n_tx, wl.rays_per_tx, wl.max_bounces)
-    ws = torch.empty(need - 1, dtype=torch.uint8, device=ctx.torch_device)
+    args = (ctx, scene, probe, wl.grid, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces, iq, g_b,
+            wl.dr_db)
+    g_full = L.us_frame_vjp(*args)
+    short = L.us_frame_vjp_workspace_size(scene, probe, wl.grid, wl.n_tx, wl.rays_per_tx // 7, wl.max_bounces)
+    assert short < L.us_frame_vjp_workspace_size(scene, probe, wl.grid, wl.n_tx, wl.rays_per_tx, wl.max_bounces)
+    g_short = L.us_frame_vjp(*args, workspace=torch.empty(short, dtype=torch.uint8, device=ctx.torch_device))
+    torch.cuda.synchronize()
+    assert torch.equal(g_full, g_short) and g_full.abs().max() > 0
+    image_only = L.us_frame_vjp_recorded_workspace_size(probe, wl.grid, wl.n_tx)
+    ws = torch.empty(image_only, dtype=torch.uint8, device=ctx.torch_device)
     with pytest.raises(L.USError, match="workspace too small"):
-        L.us_frame_vjp(ctx, scene, probe, wl.grid, wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem,
-                       wl.max_bounces, iq, g_b, wl.dr_db, workspace=ws)
+        L.us_frame_vjp(*args, workspace=ws)

@@ -36,8 +36,11 @@ def rf_and_grad(L, ctx, wl, label, ray_begin=0, ray_count=None, nonzero=True):
     import torch
     scene, probe = L.Scene(ctx, wl.scene), L.Probe(ctx, wl.probe)
     args = (wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces)
-    rf = L.us_simulate_rf(ctx, scene, probe, *args, ray_begin=ray_begin, ray_count=ray_count)
-    rf_r, rec = L.us_simulate_rf_recorded(ctx, scene, probe, *args, ray_begin=ray_begin, ray_count=ray_count)
+    c = torch.zeros(5, dtype=torch.int64, device=ctx.torch_device)
+    c_r = torch.zeros_like(c)
+    rf = L.us_simulate_rf(ctx, scene, probe, *args, ray_begin=ray_begin, ray_count=ray_count, counters=c)
+    rf_r, rec = L.us_simulate_rf_recorded(ctx, scene, probe, *args, ray_begin=ray_begin, ray_count=ray_count,
+                                          counters=c_r)
     g_rf = torch.tensor(smooth_field(tuple(rf.shape), 5), device=ctx.torch_device)
     g = L.us_simulate_rf_vjp(ctx, scene, probe, *args, g_rf, ray_begin=ray_begin, ray_count=ray_count)
     g_r = L.us_simulate_rf_vjp_recorded(ctx, rec, g_rf)
@@ -47,8 +50,10 @@ def rf_and_grad(L, ctx, wl, label, ray_begin=0, ray_count=None, nonzero=True):
     ga, gb, gc = g.cpu().numpy(), g_r.cpu().numpy(), g_r2.cpu().numpy()
     print(f"{label}: rf |max| {np.abs(a).max():.3e}, {int(np.count_nonzero(a != b))} samples differ; "
           f"|g| max {np.abs(ga).max():.3e}, {int(np.count_nonzero(ga != gb))} gradient entries differ", flush=True)
+    print(f"  counters {c.tolist()} (plain), {c_r.tolist()} (recorded)", flush=True)
     if nonzero:
         assert np.abs(a).max() > 0 and np.abs(ga).max() > 0
+    assert torch.equal(c, c_r) and int(c[0]) > 0
     assert np.array_equal(a, b)
     assert np.array_equal(ga, gb) and np.array_equal(gb, gc)
     return scene, probe, rec
@@ -88,18 +93,21 @@ def test_frame_vjp_recorded_full_anatomy_frame(L, ctx):
     args = (wl.angles, wl.tx_ids, wl.seed, wl.rays_per_elem, wl.max_bounces)
     rf_t = L.us_simulate_rf(ctx, L.Scene(ctx, target), probe, *args)
     b_ref = L.us_bmode(ctx, L.us_beamform(ctx, probe, wl.grid, wl.angles, wl.tx_ids, rf_t), wl.dr_db)
-    rf = L.us_simulate_rf(ctx, scene, probe, *args)
+    c = torch.zeros(5, dtype=torch.int64, device=ctx.torch_device)
+    c_r = torch.zeros_like(c)
+    rf = L.us_simulate_rf(ctx, scene, probe, *args, counters=c)
     iq = L.us_beamform(ctx, probe, wl.grid, wl.angles, wl.tx_ids, rf)
     _, g_b = L.us_image_loss(ctx, L.us_bmode(ctx, iq, wl.dr_db), b_ref, 0.0, 1.0)
     g = L.us_frame_vjp(ctx, scene, probe, wl.grid, *args, iq, g_b, wl.dr_db)
-    rf_r, rec = L.us_simulate_rf_recorded(ctx, scene, probe, *args)
+    rf_r, rec = L.us_simulate_rf_recorded(ctx, scene, probe, *args, counters=c_r)
     g_r = L.us_frame_vjp_recorded(ctx, rec, wl.grid, iq, g_b, wl.dr_db)
     torch.cuda.synchronize()
     a, b = rf.cpu().numpy(), rf_r.cpu().numpy()
     ga, gb = g.cpu().numpy(), g_r.cpu().numpy()
     print(f"anatomy frame: {int(np.count_nonzero(a != b))} RF samples and {int(np.count_nonzero(ga != gb))} of "
-          f"{ga.size} gradient entries differ, |g| max {np.abs(ga).max():.3e}", flush=True)
+          f"{ga.size} gradient entries differ, |g| max {np.abs(ga).max():.3e}; counters {c.tolist()}", flush=True)
     assert np.array_equal(a, b) and np.array_equal(ga, gb) and np.abs(ga).max() > 0
+    assert torch.equal(c, c_r)
 
 
 def test_recorded_backward_checks_its_records(L, ctx):

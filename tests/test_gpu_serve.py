@@ -76,3 +76,39 @@ def test_launch_enqueues_without_blocking_the_host():
     for r, h in handles:
         res = ex.finish(r, h)
         assert res.ok and np.isfinite(res.loss) and res.segments > 0
+
+
+def test_recorded_requests_equal_traced_requests():
+    """Gradient requests whose path records fit the executor's cap are
+    rendered by the recorded forward and differentiated from the records;
+    with the cap at zero every backward traces its paths again, here in
+    replay chunks of at most 2^13 rays. Both give the same bits: B-mode,
+    loss, gradient and segment counts."""
+    import torch
+    from paper_2604_15017_amd import _lib as L
+    from paper_2604_15017_amd import serve as S
+    ctx = L.Context(0)
+    specs = W.serving_requests(16, seed=5, min_log2_rays=12, max_log2_rays=18)
+    ex_rec = S.GpuExecutor(ctx, n_slots=4)
+    ex_trace = S.GpuExecutor(ctx, n_slots=4, record_max_bytes=0, replay_chunk_rays=1 << 13)
+    reqs = S.build_requests(ex_rec, specs)
+    grads = [r for r in reqs if r.want_grad]
+    assert grads and all(ex_rec.record_bytes(r) > 0 for r in grads)
+    assert all(ex_trace.record_bytes(r) == 0 for r in reqs)
+    out = []
+    for ex in (ex_rec, ex_trace):
+        srv = S.Server(ex, n_slots=4)
+        for r in reqs:
+            srv.submit(S.Request(r.rid, r.workload, r.want_grad, r.b_ref))
+        srv.run(len(reqs))
+        torch.cuda.synchronize()
+        out.append(srv.results)
+    for r in reqs:
+        a, b = out[0][r.rid], out[1][r.rid]
+        assert a.ok and b.ok, (a.error, b.error)
+        assert a.segments == b.segments > 0
+        assert np.array_equal(a.bmode.cpu().numpy(), b.bmode.cpu().numpy())
+        if r.want_grad:
+            assert a.loss == b.loss
+            ga, gb = a.g_theta.cpu().numpy(), b.g_theta.cpu().numpy()
+            assert np.abs(ga).max() > 0 and np.array_equal(ga, gb)
