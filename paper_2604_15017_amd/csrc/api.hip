@@ -1060,8 +1060,7 @@ struct RecordedLayout {
   size_t replay = 0, total = 0;
   long long* h = nullptr;
   unsigned long long* over = nullptr;
-  MarchRec* march = nullptr;
-  long march_cap = 0;
+  MarchRecs march{};
 };
 RecordedLayout recorded_layout(const us_scene* scene, const us_probe* p, int n_tx, int64_t ray_count,
                                int max_bounces, char* base) {
@@ -1074,9 +1073,21 @@ RecordedLayout recorded_layout(const us_scene* scene, const us_probe* p, int n_t
   off += align_up(hbytes);
   if (base) L.over = (unsigned long long*)(base + off);
   off += kAlign;
-  L.march_cap = max_bounces > 0 && scene->any_diffuse ? kMarchPerRay * cap : 0;
-  if (base && L.march_cap) L.march = (MarchRec*)(base + off);
-  off += align_up((size_t)L.march_cap * sizeof(MarchRec));
+  const long mc = max_bounces > 0 && scene->any_diffuse ? kMarchPerRay * cap : 0;
+  auto carve = [&](size_t bytes) {
+    char* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  if (mc) {
+    L.march.cap = base ? mc : 0;
+    L.march.tof = (double*)carve((size_t)mc * sizeof(double));
+    L.march.att = (double*)carve((size_t)mc * sizeof(double));
+    L.march.trans = (double*)carve((size_t)mc * sizeof(double));
+    L.march.nstate = (uint32_t*)carve((size_t)mc * sizeof(uint32_t));
+    L.march.s = (double*)carve((size_t)mc * kMarchLegs * sizeof(double));
+    L.march.h = (int*)carve((size_t)mc * kMarchLegs * sizeof(int));
+  }
   L.total = off;
   return L;
 }
@@ -1155,7 +1166,6 @@ int simulate_rf_vjp(us_ctx* ctx, const us_scene* scene, const us_probe* probe, c
   if (recorded) {   // the marches the recorded forward made
     const RecordedLayout lay = recorded_layout(scene, probe, n_tx, ray_count, max_bounces, (char*)ws_dev);
     a.march = lay.march;
-    a.march_cap = lay.march_cap;
   }
   a.vadj = sums.vadj;
   a.g_sum = sums.g_sum;
@@ -1377,7 +1387,6 @@ int us_simulate_rf_recorded(us_ctx* ctx, us_scene* scene, const us_probe* probe,
   a.hist_over = lay.over;
   a.hist_scale = hist_scale(rays_per_elem);
   a.march = lay.march;
-  a.march_cap = lay.march_cap;
   a.counters = (unsigned long long*)counters_dev;
   launch_fill_u32((uint32_t*)a.h, 2L * rows * pd.n_t, 0u, s);
   launch_fill_u32((uint32_t*)a.hist_over, 2, 0u, s);

@@ -124,18 +124,24 @@ struct ReplayStack {
   uint32_t* sort_q;
 };
 constexpr int kMaxReplayBlocks = 2048;
-// The receiver segment of one queued diffuse interaction as a recorded
-// forward marched it: state 0 (no segment: facing away or outside the
-// directivity), 1 (blocked), 2 (reached the element), the march's sums and
-// its first kMarchLegs crossings (distance from the origin, hit word).
+// The receiver segments of the queued diffuse interactions as a recorded
+// forward marched them, arrays over the queue index q < cap: the state with
+// the crossing count (n_cross << 2 | state; state 0: no segment, facing away
+// or outside the directivity; 1: blocked; 2: reached the element), the
+// march's sums, and its first kMarchLegs crossings (distance from the
+// origin, hit word), crossing j of entry q at [j * cap + q]. Crossings past
+// a segment's count are not written, and lanes of a wave (consecutive q)
+// touch consecutive words.
 constexpr int kMarchLegs = 8;
-struct alignas(16) MarchRec {
-  double tof, att, trans;
-  uint32_t n_cross, state;
-  double s[kMarchLegs];
-  int h[kMarchLegs];
+struct MarchRecs {
+  double* tof;
+  double* att;
+  double* trans;
+  uint32_t* nstate;
+  double* s;
+  int* h;
+  long cap;   // 0: no records
 };
-static_assert(sizeof(MarchRec) == 128, "march record layout");
 constexpr long kMarchPerRay = 4;   // march records per ray of a recorded frame (more are marched again)
 
 struct ReplayArgs {
@@ -182,11 +188,10 @@ struct ReplayArgs {
   long long* h;
   double hist_scale;
   unsigned long long* hist_over;
-  // a recorded frame (null otherwise): the march of queued interaction q
-  // (q < march_cap), written by launch_replay_deposit and read by the
+  // a recorded frame (cap 0 otherwise): the march of queued interaction q
+  // (q < march.cap), written by launch_replay_deposit and read by the
   // secondary phase in place of marching again
-  MarchRec* march;
-  long march_cap;
+  MarchRecs march;
   // a recorded forward, optional (null): the event counters of the forward
   // transport (int64[5], accumulated), counted by the forward phase's
   // deposit variant and by launch_replay_deposit

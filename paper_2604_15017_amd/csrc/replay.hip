@@ -293,7 +293,8 @@ struct ReplayCtx {
   int* stk;             // this thread's hierarchy stack in LDS
   double* leg_t;        // this thread's crossing cache in LDS: distance from x ...
   int* leg_h;           // ... and kind << 28 | index
-  const MarchRec* rec;  // the march as a recorded forward made it, or null
+  MarchRecs rec;        // the marches a recorded forward made ...
+  long rq;              // ... this one's entry, or -1 (march again)
 };
 
 // Secondary ray of interaction k at x (weight watt, time tp, interface f):
@@ -322,11 +323,14 @@ __device__ void secondary_backward(ReplayCtx& C, int region, d3 x, const Coef& f
   // (a recorded frame reads the march the forward made instead)
   const int step = blockDim.x;
   March mr;
-  if (C.rec) {
-    mr = March{C.rec->tof, C.rec->att, C.rec->trans, (int)C.rec->n_cross, C.rec->state == 2u};
+  if (C.rq >= 0) {
+    const MarchRecs& R = C.rec;
+    const long q = C.rq;
+    const uint32_t ns = R.nstate[q];
+    mr = March{R.tof[q], R.att[q], R.trans[q], (int)(ns >> 2), (ns & 3u) == 2u};
     for (int j = 0; j < kLegCache && j < mr.crossings; ++j) {
-      C.leg_t[j * step] = C.rec->s[j];
-      C.leg_h[j * step] = C.rec->h[j];
+      C.leg_t[j * step] = R.s[j * R.cap + q];
+      C.leg_h[j * step] = R.h[j * R.cap + q];
     }
   } else {
     mr = receiver_march<kMeshes>(
@@ -685,12 +689,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const d3 dv = d3{elem_x(P, e2), 0.0, 0.0} - st.x;
     const double r = sqrt(dot(dv, dv));
     const d3 we = dv * (1.0 / r);
-    MarchRec* mrec = a.march && q < a.march_cap ? a.march + q : nullptr;
+    const MarchRecs& M = a.march;
+    const bool keep = q < M.cap;   // its march is recorded
     const double cos_o = dot(st.f.nr, we);
     const double cos_el = -we.z;
     const double fd = cos_o > 0.0 ? rx_directivity(P, cos_el) : 0.0;
     if (!(cos_o > 0.0) || fd == 0.0) {
-      if (mrec) mrec->state = 0u;
+      if (keep) M.nstate[q] = 0u;
       continue;
     }
     ++n_rays;
@@ -698,17 +703,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                  (double)P.n_elem * fd;
     const March mr = receiver_march<kMeshes>(S, st.x, we, r, reg, st.tp, stk,
                                              [&](int j, double sj, int hw, const Surface&, const Coef&) {
-                                               if (mrec && j < kMarchLegs) {
-                                                 mrec->s[j] = sj;
-                                                 mrec->h[j] = hw;
+                                               if (keep && j < kMarchLegs) {
+                                                 M.s[j * M.cap + q] = sj;
+                                                 M.h[j * M.cap + q] = hw;
                                                }
                                              });
-    if (mrec) {
-      mrec->tof = mr.tof;
-      mrec->att = mr.att;
-      mrec->trans = mr.trans;
-      mrec->n_cross = (uint32_t)mr.crossings;
-      mrec->state = mr.reached ? 2u : 1u;
+    if (keep) {
+      M.tof[q] = mr.tof;
+      M.att[q] = mr.att;
+      M.trans[q] = mr.trans;
+      M.nstate[q] = (uint32_t)mr.crossings << 2 | (mr.reached ? 2u : 1u);
     }
     n_seg += mr.reached ? mr.crossings + 1 : mr.crossings;   // one segment per leg
     if (!mr.reached) continue;
@@ -784,7 +788,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
     const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
     const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
     ReplayCtx C{S, P, a.gh, a.gh_f0, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h,
-                a.march && q < a.march_cap ? a.march + q : nullptr};
+                a.march, q < a.march.cap ? q : -1L};
     d3 xb{0, 0, 0}, nrb{0, 0, 0};
     double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0, f0b = 0.0;
     secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb, f0b);
