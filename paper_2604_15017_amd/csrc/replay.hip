@@ -49,6 +49,48 @@ __device__ __forceinline__ void grad_flush(const unsigned long long* gsh, int n_
   }
 }
 
+// Mesh vertex sums staged in LDS: an open-addressing table per block, keyed
+// by (vertex, window of the value's leading bit), each entry holding the
+// two words a value adds to (window b and b - 1). The lanes of a block that
+// add to the same vertex at about the same time meet in one entry, and vh_flush adds the entries to the block's global copy at
+// points where the block is synchronised. The words are integers, so the
+// totals are those of adding every value straight to the global copy.
+// The table has 2^bits entries: 2^11 in the reverse sweep, 2^9 in the
+// secondary phase, whose crossing caches and stacks leave less LDS.
+constexpr int kVhBitsReverse = 11, kVhBitsSecondary = 9;
+constexpr uint32_t kVhEmpty = 0xFFFFFFFFu;   // vertex indices stay below 2^28
+constexpr int kVhProbes = 8;                 // entries tried before going to the global copy
+constexpr size_t vh_bytes(int bits) {
+  return ((size_t)1 << bits) * (sizeof(uint32_t) + 2 * sizeof(unsigned long long));
+}
+// Empties the table (keys [n], then words [2][n]); the caller synchronises.
+__device__ __forceinline__ void vh_clear(uint32_t* hk, unsigned long long* hw, int n) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    hk[j] = kVhEmpty;
+    hw[j] = 0ull;
+    hw[n + j] = 0ull;
+  }
+}
+// Called by every thread of the block: the table's entries added to the
+// block's vertex sums in HBM and the table emptied.
+__device__ __forceinline__ void vh_flush(uint32_t* hk, unsigned long long* hw, unsigned long long* vadj, long vstride,
+                                         int n) {
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const uint32_t key = hk[j];
+    if (key != kVhEmpty) {
+      const long v = key >> 4;
+      const int b = key & 15;
+      const unsigned long long w0 = hw[j], w1 = hw[n + j];
+      if (w0) atomicAdd(vadj + b * vstride + v, w0);
+      if (w1) atomicAdd(vadj + (b - 1) * vstride + v, w1);
+      hk[j] = kVhEmpty;
+      hw[j] = 0ull;
+      hw[n + j] = 0ull;
+    }
+  }
+  __syncthreads();
+}
 // Per-block gradient accumulator over the flat parameter vector.
 struct GradAcc {
   unsigned long long* g;          // this lane's LDS copy: [n_grad][kSumWords]
@@ -57,6 +99,9 @@ struct GradAcc {
   const double* vnormal;
   unsigned long long* vadj;       // this block's copy of the vertex sums (HBM): [kSumWords][vstride]
   long vstride;
+  uint32_t* hk = nullptr;         // optional LDS table of vertex sums (2^vh_bits keys, then twice as many words)
+  unsigned long long* hw = nullptr;
+  int vh_bits = 0;
   __device__ void add(int j, double v) { sum_add(g + (long)j * kSumWords, v); }
   // adjoint vbar of mesh vertex v: v = v_rest + (sum_j q_j phi_j(v)) n(v), so
   // the vertex contributes (vbar . n(v)) phi_j(v) to q_j; the scalar is summed
@@ -64,7 +109,32 @@ struct GradAcc {
   __device__ void mesh_vertex(int v, int m, d3 vbar) {
     (void)m;
     const double s = vbar.x * vnormal[3 * v] + vbar.y * vnormal[3 * v + 1] + vbar.z * vnormal[3 * v + 2];
-    sum_add(vadj + v, vstride, s);
+    if (!hk) {
+      sum_add(vadj + v, vstride, s);
+      return;
+    }
+    // the value's two words into its table entry (linear probing), or
+    // straight to the global copy when the entries tried are taken
+    SumPieces p;
+    if (!sum_pieces(s, &p)) return;
+    if (p.over) {
+      atomicAdd(vadj + kSumBins * vstride + v, 1ull);
+      return;
+    }
+    const uint32_t key = ((uint32_t)v << 4) | (uint32_t)p.b;
+    const uint32_t vh_n = 1u << vh_bits;
+    uint32_t slot = (key * 2654435761u) >> (32 - vh_bits);
+    for (int t = 0; t < kVhProbes; ++t) {
+      const uint32_t prev = atomicCAS(hk + slot, kVhEmpty, key);
+      if (prev == kVhEmpty || prev == key) {
+        atomicAdd(hw + slot, p.hi);
+        if (p.lo) atomicAdd(hw + vh_n + slot, p.lo);
+        return;
+      }
+      slot = (slot + 1) & (vh_n - 1);
+    }
+    atomicAdd(vadj + p.b * vstride + v, p.hi);   // the table is crowded here
+    if (p.lo) atomicAdd(vadj + (p.b - 1) * vstride + v, p.lo);
   }
   __device__ void c(int r, double v) { add(3 * r, v); }
   __device__ void Z(int r, double v) { add(3 * r + 1, v); }
@@ -756,48 +826,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kMeshes ? 2
   unsigned long long* acq = gsh + gw;
   words_clear(gsh, gw + acq_words(a));
   __syncthreads();
-  double* legs = (double*)(acq + acq_words(a));
+  constexpr int kVn = 1 << kVhBitsSecondary;
+  uint32_t* hk = (uint32_t*)(acq + acq_words(a));   // vertex sum table (mesh scenes)
+  unsigned long long* hw = (unsigned long long*)(hk + kVn);
+  if (kMeshes) {
+    vh_clear(hk, hw, kVn);
+    __syncthreads();
+  }
+  double* legs = kMeshes ? (double*)(hw + 2 * kVn) : (double*)(acq + acq_words(a));
   double* leg_t = legs + threadIdx.x;
   int* leg_h = (int*)(legs + kLegCache * blockDim.x) + threadIdx.x;
   int* stk = leg_h + kLegCache * blockDim.x;
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_words(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
             a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords, a.vadj_stride};
+  if (kMeshes) {
+    G.hk = hk;
+    G.hw = hw;
+    G.vh_bits = kVhBitsSecondary;
+  }
   const ProbeView& P = a.probe;
   const long cap = a.cap;
-  for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < n_q; q += (long)gridDim.x * blockDim.x) {
-    // the step k with queue_begin[k - 1] <= q < queue_begin[k]
-    int k = 1, hi = B;
-    while (k < hi) {
-      const int mid = (k + hi + 1) >> 1;
-      if ((long)a.stk.queue_begin[mid - 1] <= q) k = mid; else hi = mid - 1;
+  // block-uniform loop: the vertex table is flushed after each pass of the block
+  for (long qb = (long)blockIdx.x * blockDim.x; qb < n_q; qb += (long)gridDim.x * blockDim.x) {
+    const long q = qb + threadIdx.x;
+    if (q < n_q) {
+      // the step k with queue_begin[k - 1] <= q < queue_begin[k]
+      int k = 1, hi = B;
+      while (k < hi) {
+        const int mid = (k + hi + 1) >> 1;
+        if ((long)a.stk.queue_begin[mid - 1] <= q) k = mid; else hi = mid - 1;
+      }
+      const uint32_t i = a.sort.keys > 0 ? a.stk.sort_q[q]
+                                         : a.stk.queue[(long)(k - 1) * cap + (q - (long)a.stk.queue_begin[k - 1])];
+      const long at = (long)(k - 1) * cap + i;
+      int txl;
+      uint32_t rid;
+      ray_of(a, i, &txl, &rid);
+      const StepRec R = a.stk.rec[at];
+      const d3 o{R.ox, R.oy, R.oz};
+      const d3 d{R.dx, R.dy, R.dz};
+      const uint32_t meta = R.meta;
+      const int reg = meta & 0xFF;
+      const Hit h{(int)(meta >> 12), R.hidx, R.L};
+      const Step st = step_at(S, o, d, R.t, R.w, reg, h);
+      const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
+      const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
+      ReplayCtx C{S, P, a.gh, a.gh_f0, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h,
+                  a.march, q < a.march.cap ? q : -1L};
+      d3 xb{0, 0, 0}, nrb{0, 0, 0};
+      double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0, f0b = 0.0;
+      secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb, f0b);
+      a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
+      // x_e = (e - (N - 1)/2) pitch
+      if (a.g_acq) {
+        sum_add(acq + (a.tx.n + 1) * kSumWords, xeb * ((double)e2 - 0.5 * (double)(P.n_elem - 1)));
+        sum_add(acq + (a.tx.n + 2) * kSumWords, f0b);
+      }
     }
-    const uint32_t i = a.sort.keys > 0 ? a.stk.sort_q[q]
-                                       : a.stk.queue[(long)(k - 1) * cap + (q - (long)a.stk.queue_begin[k - 1])];
-    const long at = (long)(k - 1) * cap + i;
-    int txl;
-    uint32_t rid;
-    ray_of(a, i, &txl, &rid);
-    const StepRec R = a.stk.rec[at];
-    const d3 o{R.ox, R.oy, R.oz};
-    const d3 d{R.dx, R.dy, R.dz};
-    const uint32_t meta = R.meta;
-    const int reg = meta & 0xFF;
-    const Hit h{(int)(meta >> 12), R.hidx, R.L};
-    const Step st = step_at(S, o, d, R.t, R.w, reg, h);
-    const Draw v = draw(a.seed, rid, a.tx.id[txl], (uint32_t)k);
-    const int e2 = min((int)(v.u3 * (double)P.n_elem), P.n_elem - 1);
-    ReplayCtx C{S, P, a.gh, a.gh_f0, (long)(a.tx_base + txl) * P.n_elem, G, stk, leg_t, leg_h,
-                a.march, q < a.march.cap ? q : -1L};
-    d3 xb{0, 0, 0}, nrb{0, 0, 0};
-    double Ab = 0.0, wb = 0.0, tb = 0.0, xeb = 0.0, f0b = 0.0;
-    secondary_backward<kMeshes>(C, reg, st.x, st.f, st.sf.kd, st.watt, st.tp, e2, xb, nrb, Ab, wb, tb, xeb, f0b);
-    a.stk.adj[at] = StepAdj{xb.x, xb.y, xb.z, nrb.x, nrb.y, nrb.z, Ab, wb, tb, 0.0};
-    // x_e = (e - (N - 1)/2) pitch
-    if (a.g_acq) {
-      sum_add(acq + (a.tx.n + 1) * kSumWords, xeb * ((double)e2 - 0.5 * (double)(P.n_elem - 1)));
-      sum_add(acq + (a.tx.n + 2) * kSumWords, f0b);
-    }
+    if (kMeshes) vh_flush(hk, hw, G.vadj, G.vstride, kVn);
   }
   __syncthreads();
   grad_flush(gsh, a.n_grad, a.grad_copies, a.g_sum);
@@ -815,172 +902,187 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
   const int gw = a.grad_copies * grad_words(a.n_grad);
   unsigned long long* acq = gsh + gw;
   words_clear(gsh, gw + acq_words(a));
+  constexpr int kVn = 1 << kVhBitsReverse;
+  uint32_t* hk = (uint32_t*)(acq + acq_words(a));   // vertex sum table (mesh scenes)
+  unsigned long long* hw = (unsigned long long*)(hk + kVn);
+  const bool vh = a.scene.n_meshes > 0;
+  if (vh) vh_clear(hk, hw, kVn);
   __syncthreads();
   GradAcc G{gsh + (threadIdx.x % a.grad_copies) * grad_words(a.n_grad), a.scene.n_regions, a.scene.n_planes,
             a.scene.n_spheres, a.scene.n_cylinders, a.scene.np_per_m, a.scene.vnormal,
             a.vadj + (long)(blockIdx.x % kVadjCopies) * a.vadj_stride * kSumWords, a.vadj_stride};
+  if (vh) {
+    G.hk = hk;
+    G.hw = hw;
+    G.vh_bits = kVhBitsReverse;
+  }
   const ProbeView& P = a.probe;
   const long cap = a.cap;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    int txl;
-    uint32_t rid;
-    ray_of(a, i, &txl, &rid);
-    const uint32_t tx_id = a.tx.id[txl];
-    const long row_base = (long)(a.tx_base + txl) * P.n_elem;
-    d3 ob{0, 0, 0}, db{0, 0, 0};
-    double tb = 0.0, wb = 0.0;
-    for (int k = a.stk.last[i]; k >= 1; --k) {
-      const long at = (long)(k - 1) * cap + i;
-      const StepRec R = a.stk.rec[at];
-      const uint32_t meta = R.meta;
-      const d3 o0{R.ox, R.oy, R.oz};
-      const d3 d0{R.dx, R.dy, R.dz};
-      const double t0 = R.t, w0 = R.w;
-      const int reg = meta & 0xFF;
-      const bool dl = (meta >> 8) & 1u;
-      const Hit h{(int)(meta >> 12), R.hidx, R.L};
-      const Step st = step_at(S, o0, d0, t0, w0, reg, h);
-      const double L = st.L, c1 = S.c[reg], ar = S.a[reg];
-      const double watt = st.watt;
-      const d3 x = st.x;
-      d3 xb{0, 0, 0}, d0b{0, 0, 0};
-      TriAdj ta;   // the hit triangle's adjoints from the normal and the distance
-      double tpb = 0.0, wattb = 0.0;
-      if (h.kind == kHitArray) {
-        const double half = 0.5 * (double)P.n_elem * P.pitch;
-        if (dl && fabs(x.x) < half && fabs(x.y) < 0.5 * P.elem_h) {
-          int e = (int)floor((x.x + half) / P.pitch);
-          e = min(max(e, 0), P.n_elem - 1);
-          const double fd = rx_directivity(P, -d0.z);
-          if (fd > 0.0) {
-            double ga, gt;
-            tent_adjoint(a.gh + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, watt * fd, &ga, &gt);
-            if (a.gh_f0) {
-              double gf, unused;
-              tent_adjoint(a.gh_f0 + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, 0.0, &gf, &unused);
-              sum_add(acq + (a.tx.n + 2) * kSumWords, gf * watt * fd);
+  // block-uniform loop: the vertex table is flushed after each pass of the block
+  for (long base = (long)blockIdx.x * blockDim.x; base < n; base += (long)gridDim.x * blockDim.x) {
+    const long i = base + threadIdx.x;
+    if (i < n) {
+      int txl;
+      uint32_t rid;
+      ray_of(a, i, &txl, &rid);
+      const uint32_t tx_id = a.tx.id[txl];
+      const long row_base = (long)(a.tx_base + txl) * P.n_elem;
+      d3 ob{0, 0, 0}, db{0, 0, 0};
+      double tb = 0.0, wb = 0.0;
+      for (int k = a.stk.last[i]; k >= 1; --k) {
+        const long at = (long)(k - 1) * cap + i;
+        const StepRec R = a.stk.rec[at];
+        const uint32_t meta = R.meta;
+        const d3 o0{R.ox, R.oy, R.oz};
+        const d3 d0{R.dx, R.dy, R.dz};
+        const double t0 = R.t, w0 = R.w;
+        const int reg = meta & 0xFF;
+        const bool dl = (meta >> 8) & 1u;
+        const Hit h{(int)(meta >> 12), R.hidx, R.L};
+        const Step st = step_at(S, o0, d0, t0, w0, reg, h);
+        const double L = st.L, c1 = S.c[reg], ar = S.a[reg];
+        const double watt = st.watt;
+        const d3 x = st.x;
+        d3 xb{0, 0, 0}, d0b{0, 0, 0};
+        TriAdj ta;   // the hit triangle's adjoints from the normal and the distance
+        double tpb = 0.0, wattb = 0.0;
+        if (h.kind == kHitArray) {
+          const double half = 0.5 * (double)P.n_elem * P.pitch;
+          if (dl && fabs(x.x) < half && fabs(x.y) < 0.5 * P.elem_h) {
+            int e = (int)floor((x.x + half) / P.pitch);
+            e = min(max(e, 0), P.n_elem - 1);
+            const double fd = rx_directivity(P, -d0.z);
+            if (fd > 0.0) {
+              double ga, gt;
+              tent_adjoint(a.gh + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, watt * fd, &ga, &gt);
+              if (a.gh_f0) {
+                double gf, unused;
+                tent_adjoint(a.gh_f0 + (row_base + e) * (long)P.n_t, P.n_t, P.fs, st.tp, 0.0, &gf, &unused);
+                sum_add(acq + (a.tx.n + 2) * kSumWords, gf * watt * fd);
+              }
+              wattb += ga * fd;
+              d0b.z -= ga * watt * rx_directivity_deriv(P, -d0.z);
+              tpb += gt;
             }
-            wattb += ga * fd;
-            d0b.z -= ga * watt * rx_directivity_deriv(P, -d0.z);
-            tpb += gt;
           }
-        }
-      } else {
-        const Surface sf = st.sf;
-        const Coef f = st.f;
-        const int r2 = sf.other;
-        const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
-        const double eta = S.c[r2] / c1;
-        xb = ob;
-        tpb = tb;
-        d3 nrb{0, 0, 0};
-        double cib = 0.0, ctb = 0.0, etab = 0.0, Ab = 0.0;
-        const double p_spec = (1.0 - sf.kd) * f.RE;
-        if (v.u0 < p_spec) {
-          // d' = d - 2 (d.m) m about the GGX microfacet m(n_r, rho), w' = watt
-          // Ar / R_E g. Taken in this form also at rho = 0, where the forward
-          // mirrored about n_r: the values agree and dL/drho is kept.
-          const d3 nn = f.nr;
-          const Frame fr = frame_of(nn);
-          const double rho = sf.rho;
-          const double kap = sqrt(v.u1 / (1.0 - v.u1));
-          const double th = rho * kap;
-          const double lz = 1.0 / sqrt(1.0 + th * th);
-          const double sh = th * lz;
-          const double phi = 2.0 * kPi * v.u2;
-          const SinCos scp = sincos_ool(phi);
-          const double cph = scp.c, sph = scp.s;
-          const double lx = sh * cph, ly = sh * sph;
-          const d3 m = fr.b1 * lx + fr.b2 * ly + nn * lz;
-          const double wh = dot(d0, m);
-          const d3 dout = d0 - m * (2.0 * wh);
-          const double co = dot(nn, dout);
-          if (wh < 0.0 && co > 0.0) {   // else the path ended here: nothing flows back
-            const double g1i = smith_g1(f.ci, rho), g1o = smith_g1(co, rho);
-            const double q = f.ci * lz, g = g1i * g1o * (-wh) / q;
-            wattb += wb * f.Ar / f.RE * g;
-            Ab += wb * watt / f.RE * g;
-            const double gb = wb * watt * f.Ar / f.RE;
-            double rho_b = 0.0, co_b = 0.0, lz_b = -gb * g / lz;
-            cib += -gb * g / f.ci;
-            smith_g1_vjp(f.ci, rho, gb * g1o * (-wh) / q, &cib, &rho_b);
-            smith_g1_vjp(co, rho, gb * g1i * (-wh) / q, &co_b, &rho_b);
-            const double im_b = gb * g1i * g1o / q;            // of -wh
-            const d3 ob = db + nn * co_b;                      // co = n_r . d'
-            nrb = nrb + dout * co_b;
-            d0b = d0b + ob;
-            const double wh_b = -2.0 * dot(m, ob) - im_b;
-            const d3 mb = ob * (-2.0 * wh) + d0 * wh_b;
-            d0b = d0b + m * wh_b;
-            nrb = nrb + frame_vjp(nn, lx, ly, lz, mb);
-            lz_b += dot(nn, mb);
-            const double sh_b = dot(fr.b1, mb) * cph + dot(fr.b2, mb) * sph;
-            const double lz3 = lz * lz * lz;
-            rho_b += sh_b * kap * lz3 - lz_b * rho * kap * kap * lz3;
-            G.rough(h.kind, h.kind == kHitMesh ? S.tri[h.index].w : h.index, rho_b);
+        } else {
+          const Surface sf = st.sf;
+          const Coef f = st.f;
+          const int r2 = sf.other;
+          const Draw v = draw(a.seed, rid, tx_id, (uint32_t)k);
+          const double eta = S.c[r2] / c1;
+          xb = ob;
+          tpb = tb;
+          d3 nrb{0, 0, 0};
+          double cib = 0.0, ctb = 0.0, etab = 0.0, Ab = 0.0;
+          const double p_spec = (1.0 - sf.kd) * f.RE;
+          if (v.u0 < p_spec) {
+            // d' = d - 2 (d.m) m about the GGX microfacet m(n_r, rho), w' = watt
+            // Ar / R_E g. Taken in this form also at rho = 0, where the forward
+            // mirrored about n_r: the values agree and dL/drho is kept.
+            const d3 nn = f.nr;
+            const Frame fr = frame_of(nn);
+            const double rho = sf.rho;
+            const double kap = sqrt(v.u1 / (1.0 - v.u1));
+            const double th = rho * kap;
+            const double lz = 1.0 / sqrt(1.0 + th * th);
+            const double sh = th * lz;
+            const double phi = 2.0 * kPi * v.u2;
+            const SinCos scp = sincos_ool(phi);
+            const double cph = scp.c, sph = scp.s;
+            const double lx = sh * cph, ly = sh * sph;
+            const d3 m = fr.b1 * lx + fr.b2 * ly + nn * lz;
+            const double wh = dot(d0, m);
+            const d3 dout = d0 - m * (2.0 * wh);
+            const double co = dot(nn, dout);
+            if (wh < 0.0 && co > 0.0) {   // else the path ended here: nothing flows back
+              const double g1i = smith_g1(f.ci, rho), g1o = smith_g1(co, rho);
+              const double q = f.ci * lz, g = g1i * g1o * (-wh) / q;
+              wattb += wb * f.Ar / f.RE * g;
+              Ab += wb * watt / f.RE * g;
+              const double gb = wb * watt * f.Ar / f.RE;
+              double rho_b = 0.0, co_b = 0.0, lz_b = -gb * g / lz;
+              cib += -gb * g / f.ci;
+              smith_g1_vjp(f.ci, rho, gb * g1o * (-wh) / q, &cib, &rho_b);
+              smith_g1_vjp(co, rho, gb * g1i * (-wh) / q, &co_b, &rho_b);
+              const double im_b = gb * g1i * g1o / q;            // of -wh
+              const d3 ob = db + nn * co_b;                      // co = n_r . d'
+              nrb = nrb + dout * co_b;
+              d0b = d0b + ob;
+              const double wh_b = -2.0 * dot(m, ob) - im_b;
+              const d3 mb = ob * (-2.0 * wh) + d0 * wh_b;
+              d0b = d0b + m * wh_b;
+              nrb = nrb + frame_vjp(nn, lx, ly, lz, mb);
+              lz_b += dot(nn, mb);
+              const double sh_b = dot(fr.b1, mb) * cph + dot(fr.b2, mb) * sph;
+              const double lz3 = lz * lz * lz;
+              rho_b += sh_b * kap * lz3 - lz_b * rho * kap * kap * lz3;
+              G.rough(h.kind, h.kind == kHitMesh ? S.tri[h.index].w : h.index, rho_b);
+            }
+          } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
+            const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
+            const SinCos sc = sincos_ool(phi);
+            const double lx = rr * sc.c, ly = rr * sc.s, lz = sqrt(1.0 - v.u2);
+            nrb = nrb + frame_vjp(f.nr, lx, ly, lz, db);
+            wattb += wb * f.Ar / f.RE;
+            Ab += wb * watt / f.RE;
+          } else {                      // d' = eta d + (eta ci - ct) nr, w' = watt At / (1 - R_E)
+            const double dn = dot(db, f.nr);
+            d0b = d0b + db * eta;
+            etab += dot(db, d0) + f.ci * dn;
+            cib += eta * dn;
+            ctb -= dn;
+            nrb = nrb + db * (eta * f.ci - f.ct);
+            wattb += wb * f.At / (1.0 - f.RE);
+            Ab += wb * watt / (1.0 - f.RE);
           }
-        } else if (v.u0 < f.RE) {     // d' = lx b1(nr) + ly b2(nr) + lz nr
-          const double phi = 2.0 * kPi * v.u1, rr = sqrt(v.u2);
-          const SinCos sc = sincos_ool(phi);
-          const double lx = rr * sc.c, ly = rr * sc.s, lz = sqrt(1.0 - v.u2);
-          nrb = nrb + frame_vjp(f.nr, lx, ly, lz, db);
-          wattb += wb * f.Ar / f.RE;
-          Ab += wb * watt / f.RE;
-        } else {                      // d' = eta d + (eta ci - ct) nr, w' = watt At / (1 - R_E)
-          const double dn = dot(db, f.nr);
-          d0b = d0b + db * eta;
-          etab += dot(db, d0) + f.ci * dn;
-          cib += eta * dn;
-          ctb -= dn;
-          nrb = nrb + db * (eta * f.ci - f.ct);
-          wattb += wb * f.At / (1.0 - f.RE);
-          Ab += wb * watt / (1.0 - f.RE);
+          if (sf.kd > 0.0) {   // adjoints of the secondary ray's inputs (phase 2)
+            const StepAdj Q = a.stk.adj[at];
+            xb = xb + d3{Q.xb, Q.yb, Q.zb};
+            nrb = nrb + d3{Q.nxb, Q.nyb, Q.nzb};
+            Ab += Q.Ab;
+            wattb += Q.wb;
+            tpb += Q.tb;
+          }
+          cib += interface_backward(f, eta, reg, r2, S.Z[reg], S.Z[r2], c1, Ab, ctb, etab, G);
+          // ci = -nr . d
+          nrb = nrb - d0 * cib;
+          d0b = d0b - f.nr * cib;
+          const double sgn = dot(sf.n, d0) > 0.0 ? -1.0 : 1.0;
+          normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, xb, G, ta);
         }
-        if (sf.kd > 0.0) {   // adjoints of the secondary ray's inputs (phase 2)
-          const StepAdj Q = a.stk.adj[at];
-          xb = xb + d3{Q.xb, Q.yb, Q.zb};
-          nrb = nrb + d3{Q.nxb, Q.nyb, Q.nzb};
-          Ab += Q.Ab;
-          wattb += Q.wb;
-          tpb += Q.tb;
-        }
-        cib += interface_backward(f, eta, reg, r2, S.Z[reg], S.Z[r2], c1, Ab, ctb, etab, G);
-        // ci = -nr . d
-        nrb = nrb - d0 * cib;
-        d0b = d0b - f.nr * cib;
-        const double sgn = dot(sf.n, d0) > 0.0 ? -1.0 : 1.0;
-        normal_backward(S, h.kind, h.index, sf.n, nrb * sgn, xb, G, ta);
+        // t' = t + L / c, w_att = w exp(-a L), x = o + d L, L = distance(o, d)
+        const double Lb = tpb / c1 - wattb * watt * ar + dot(xb, d0);
+        G.c(reg, -tpb * L / (c1 * c1));
+        G.a(reg, -wattb * watt * L);
+        d3 o0b = xb;
+        d0b = d0b + xb * L;
+        const double sig = h.kind == kHitSphere     ? primary_root(S, h.index, o0, d0)
+                         : h.kind == kHitCylinder ? cylinder_root(S, h.index, o0, d0)
+                                                  : -1.0;
+        distance_backward(S, h.kind, h.index, sig, o0, d0, L, Lb, o0b, d0b, G, ta);
+        if (h.kind == kHitMesh) tri_nu_backward(S, h.index, ta.nub, ta.p0b, G);
+        ob = o0b;
+        db = d0b;
+        tb = tpb;
+        wb = wattb * st.E;
       }
-      // t' = t + L / c, w_att = w exp(-a L), x = o + d L, L = distance(o, d)
-      const double Lb = tpb / c1 - wattb * watt * ar + dot(xb, d0);
-      G.c(reg, -tpb * L / (c1 * c1));
-      G.a(reg, -wattb * watt * L);
-      d3 o0b = xb;
-      d0b = d0b + xb * L;
-      const double sig = h.kind == kHitSphere     ? primary_root(S, h.index, o0, d0)
-                       : h.kind == kHitCylinder ? cylinder_root(S, h.index, o0, d0)
-                                                : -1.0;
-      distance_backward(S, h.kind, h.index, sig, o0, d0, L, Lb, o0b, d0b, G, ta);
-      if (h.kind == kHitMesh) tri_nu_backward(S, h.index, ta.nub, ta.p0b, G);
-      ob = o0b;
-      db = d0b;
-      tb = tpb;
-      wb = wattb * st.E;
+      if (a.g_acq) {
+        // the emitted state: o = (x_e + (u0 - 1/2) w_el, (u1 - 1/2) h_el, 0),
+        // d = (sin th, 0, cos th), t = o_x sin th / c_ref, w = cos th / n, with
+        // x_e = (e - (N - 1)/2) pitch
+        const int e = (int)(rid / (uint32_t)a.rays_per_elem);
+        const Draw u = draw(a.seed, rid, tx_id, 0);
+        const double de = (double)e - 0.5 * (double)(P.n_elem - 1);
+        const double ox = elem_x(P, e) + (u.u0 - 0.5) * P.elem_w;
+        const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
+        const double thb = db.x * ca - db.z * sa + tb * ox * ca / P.c_ref - wb * sa / (double)a.rays_per_elem;
+        sum_add(acq + txl * kSumWords, thb);
+        sum_add(acq + a.tx.n * kSumWords, -tb * ox * sa / (P.c_ref * P.c_ref));
+        sum_add(acq + (a.tx.n + 1) * kSumWords, (ob.x + tb * sa / P.c_ref) * de);
+      }
     }
-    if (a.g_acq) {
-      // the emitted state: o = (x_e + (u0 - 1/2) w_el, (u1 - 1/2) h_el, 0),
-      // d = (sin th, 0, cos th), t = o_x sin th / c_ref, w = cos th / n, with
-      // x_e = (e - (N - 1)/2) pitch
-      const int e = (int)(rid / (uint32_t)a.rays_per_elem);
-      const Draw u = draw(a.seed, rid, tx_id, 0);
-      const double de = (double)e - 0.5 * (double)(P.n_elem - 1);
-      const double ox = elem_x(P, e) + (u.u0 - 0.5) * P.elem_w;
-      const double sa = a.tx.sin_a[txl], ca = a.tx.cos_a[txl];
-      const double thb = db.x * ca - db.z * sa + tb * ox * ca / P.c_ref - wb * sa / (double)a.rays_per_elem;
-      sum_add(acq + txl * kSumWords, thb);
-      sum_add(acq + a.tx.n * kSumWords, -tb * ox * sa / (P.c_ref * P.c_ref));
-      sum_add(acq + (a.tx.n + 1) * kSumWords, (ob.x + tb * sa / P.c_ref) * de);
-    }
+    if (vh) vh_flush(hk, hw, G.vadj, G.vstride, kVn);
   }
   __syncthreads();
   grad_flush(gsh, a.n_grad, a.grad_copies, a.g_sum);
@@ -1085,10 +1187,11 @@ void launch_replay_secondary(const ReplayArgs& a0, long max_entries, hipStream_t
   ReplayArgs a = a0;
   const size_t legs = (size_t)kLegCache * 256 * (sizeof(double) + sizeof(int));
   const bool m = a.scene.n_meshes > 0;
-  a.grad_copies = grad_copies_for(a, m ? 2 : 3, acq_lds(a) + legs + stack_lds(a));
+  const size_t vhb = m ? vh_bytes(kVhBitsSecondary) : 0;
+  a.grad_copies = grad_copies_for(a, m ? 2 : 3, acq_lds(a) + legs + stack_lds(a) + vhb);
   const auto kern = m ? k_replay_secondary<true> : k_replay_secondary<false>;
   hipLaunchKernelGGL(kern, dim3(replay_grid(max_entries)), dim3(256),
-                     grad_lds(a) + acq_lds(a) + legs + stack_lds(a), s, a);
+                     grad_lds(a) + acq_lds(a) + legs + stack_lds(a) + vhb, s, a);
 }
 
 void launch_replay_deposit(const ReplayArgs& a, long max_entries, hipStream_t s) {
@@ -1116,8 +1219,9 @@ void launch_grad_finish(const unsigned long long* g_sum, int n_grad, double* g_t
 
 void launch_replay_reverse(const ReplayArgs& a0, long n, hipStream_t s) {
   ReplayArgs a = a0;
-  a.grad_copies = grad_copies_for(a, 3, acq_lds(a));
-  hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a) + acq_lds(a), s, a, n);
+  const size_t vhb = a.scene.n_meshes > 0 ? vh_bytes(kVhBitsReverse) : 0;
+  a.grad_copies = grad_copies_for(a, 3, acq_lds(a) + vhb);
+  hipLaunchKernelGGL(k_replay_reverse, dim3(replay_grid(n)), dim3(256), grad_lds(a) + acq_lds(a) + vhb, s, a, n);
 }
 
 void launch_basis_gather(const unsigned long long* vadj, long stride, long n_vertices, double* vval,
