@@ -67,11 +67,21 @@ __device__ __forceinline__ void dft_regs(float2 (&a)[R], const float2 (&w)[R / 2
 
 enum FftIo : int {
   kIoLds,          // LDS buffer (padded)
-  kIoRealIn,       // global real row
-  kIoComplexIn,    // global complex row
-  kIoLdsH,         // LDS, multiplied by the analytic-signal mask H and conjugated
-  kIoComplexOut,   // global complex row: conj(v) / n
-  kIoRealOut       // global real row: Re(v) / n
+  kIoRealPairIn,   // two global real rows as one complex row (row 0 + i row 1)
+  kIoImagPairIn,   // the imaginary parts of two global complex rows, likewise
+  kIoLdsQ,         // LDS, times the Hilbert multiplier -i sgn(k), conjugated
+  kIoAnalyticOut,  // two global complex rows: (input row, its Hilbert transform)
+  kIoAdjointOut    // two real rows (global or LDS): Re(input row) - Hilbert transform of its Im
+};
+
+// The two rows of one transform: row 0 at in / out, row 1 n elements after
+// in and out_stride after out when two (else row 1 reads as zeros and is
+// not written).
+struct FftRows {
+  const void* in;
+  void* out;
+  long out_stride;
+  bool two;
 };
 
 // One Stockham radix-R pass (decimation in time, natural order in and out)
@@ -80,11 +90,12 @@ enum FftIo : int {
 // writes y[(j / L) L R + k + s L]. Every thread first loads all its
 // butterflies, so the pass can run in place in LDS.
 template <int R, int kSrc, int kDst>
-__device__ __forceinline__ void fft_pass(float2* x, const void* gin, void* gout, int n, int L,
-                                         const float2* lo, const float2* hi) {
+__device__ __forceinline__ void fft_pass(float2* x, const FftRows& io, int n, int L, const float2* lo,
+                                         const float2* hi) {
   constexpr int kB = 32 / R > 0 ? 32 / R : 1;   // butterflies per thread (n <= 8192, 256 threads)
   const int m = n / R, Ls = L * R, tw_step = n / Ls;
   float2 a[kB][R];
+  const int n1 = io.two ? n : 0;   // row 1, or row 0 again (read, then replaced by zeros)
 #pragma unroll
   for (int bi = 0; bi < kB; ++bi) {
     const int j = threadIdx.x + bi * kFftThreads;
@@ -92,9 +103,17 @@ __device__ __forceinline__ void fft_pass(float2* x, const void* gin, void* gout,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = j + r * m;
-        if (kSrc == kIoRealIn) a[bi][r] = make_float2(((const float*)gin)[i], 0.0f);
-        else if (kSrc == kIoComplexIn) a[bi][r] = ((const float2*)gin)[i];
-        else a[bi][r] = x[fpad(i)];
+        if (kSrc == kIoRealPairIn) {
+          const float* g = (const float*)io.in;
+          const float v1 = g[n1 + i];
+          a[bi][r] = make_float2(g[i], io.two ? v1 : 0.0f);
+        } else if (kSrc == kIoImagPairIn) {
+          const float2* g = (const float2*)io.in;
+          const float v1 = g[n1 + i].y;
+          a[bi][r] = make_float2(g[i].y, io.two ? v1 : 0.0f);
+        } else {
+          a[bi][r] = x[fpad(i)];
+        }
       }
     }
   }
@@ -114,51 +133,76 @@ __device__ __forceinline__ void fft_pass(float2* x, const void* gin, void* gout,
       }
       dft_regs<R>(a[bi], w);
       const int base = (j - k) * R + k;
+      if (kDst == kIoLds || kDst == kIoLdsQ) {
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        const int o = base + s * L;
-        const float2 v = a[bi][s];
-        if (kDst == kIoLds) {
-          x[fpad(o)] = v;
-        } else if (kDst == kIoLdsH) {
-          const float hm = (o == 0 || o == (n >> 1)) ? 1.0f : (o < (n >> 1) ? 2.0f : 0.0f);
-          x[fpad(o)] = make_float2(hm * v.x, -hm * v.y);
-        } else if (kDst == kIoComplexOut) {
-          ((float2*)gout)[o] = make_float2(v.x * inv_n, -v.y * inv_n);
-        } else {
-          ((float*)gout)[o] = v.x * inv_n;
+        for (int s = 0; s < R; ++s) {
+          const int o = base + s * L;
+          const float2 v = a[bi][s];
+          if (kDst == kIoLds) {
+            x[fpad(o)] = v;
+          } else {
+            // conj(-i sgn(o) v), sgn zero at o = 0 and o = n / 2
+            const float sg = (o == 0 || o == (n >> 1)) ? 0.0f : (o < (n >> 1) ? 1.0f : -1.0f);
+            x[fpad(o)] = make_float2(sg * v.y, sg * v.x);
+          }
+        }
+      } else {
+        // v = n conj(y) for y = Hilbert(row 0) + i Hilbert(row 1). The rows'
+        // own samples at the outputs are read eight at a time ahead of the
+        // stores (row 0 again in place of a missing row 1), so that a
+        // group's loads are in flight together.
+        constexpr int kG = R < 8 ? R : 8;
+#pragma unroll
+        for (int s0 = 0; s0 < R; s0 += kG) {
+          float g0[kG], g1[kG];
+#pragma unroll
+          for (int t = 0; t < kG; ++t) {
+            const int o = base + (s0 + t) * L;
+            if (kDst == kIoAnalyticOut) {
+              g0[t] = ((const float*)io.in)[o];
+              g1[t] = ((const float*)io.in)[n1 + o];
+            } else {
+              g0[t] = ((const float2*)io.in)[o].x;
+              g1[t] = ((const float2*)io.in)[n1 + o].x;
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < kG; ++t) {
+            const int o = base + (s0 + t) * L;
+            const float2 v = a[bi][s0 + t];
+            const float h0 = v.x * inv_n, h1 = -v.y * inv_n;
+            if (kDst == kIoAnalyticOut) {
+              float2* A = (float2*)io.out;
+              A[o] = make_float2(g0[t], h0);
+              if (io.two) A[io.out_stride + o] = make_float2(g1[t], h1);
+            } else {
+              float* gr = (float*)io.out;
+              gr[o] = g0[t] - h0;
+              if (io.two) gr[io.out_stride + o] = g1[t] - h1;
+            }
+          }
         }
       }
     }
   }
-  if (kDst == kIoLds || kDst == kIoLdsH) __syncthreads();
+  if (kDst == kIoLds || kDst == kIoLdsQ) __syncthreads();
 }
 
 template <int kSrc, int kDst>
-__device__ __forceinline__ void fft_pass_bits(int bits, float2* x, const void* gin, void* gout, int n, int L,
+__device__ __forceinline__ void fft_pass_bits(int bits, float2* x, const FftRows& io, int n, int L,
                                               const float2* lo, const float2* hi) {
   switch (bits) {   // 64 <= n <= 8192 split into two or three passes: 3 to 5 bits each
-    case 3: fft_pass<8, kSrc, kDst>(x, gin, gout, n, L, lo, hi); break;
-    case 4: fft_pass<16, kSrc, kDst>(x, gin, gout, n, L, lo, hi); break;
-    default: fft_pass<32, kSrc, kDst>(x, gin, gout, n, L, lo, hi); break;
+    case 3: fft_pass<8, kSrc, kDst>(x, io, n, L, lo, hi); break;
+    case 4: fft_pass<16, kSrc, kDst>(x, io, n, L, lo, hi); break;
+    default: fft_pass<32, kSrc, kDst>(x, io, n, L, lo, hi); break;
   }
 }
 
-// Analytic-signal map T = F^-1 diag(H) F along one row, H = 1, 2..2, 1, 0..0,
-// the inverse taken as a forward transform of the conjugate. kRealIn: input
-// row is real (forward) or complex (adjoint); kRealOut: keep the real part
-// (adjoint: T is self-adjoint, g_rf = Re(T g_A)). n = 2^logn is split into
-// two or three passes of radix <= 32, smallest first.
-template <bool kRealIn, bool kRealOut>
-__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_analytic(const void* in, void* out,
-                                                          const float2* twiddle, int n, int logn) {
-  extern __shared__ float2 lds[];
-  float2* lo = lds;                          // w_n^i, i < 128
-  float2* hi = lds + (1 << kFftLoBits);       // w_n^(128 i), i < 64
-  float2* x = hi + 64;
-  const long row = blockIdx.x;
+// The twiddle table w_n^e (two levels: lo[e & 127], hi[e >> 7]) in LDS from
+// the first half kept on the device (w_n^(e + n/2) = -w_n^e), and the pass
+// split of n = 2^logn: two or three passes of 3 to 5 bits, smallest first.
+__device__ __forceinline__ int fft_setup(float2* lds, const float2* twiddle, int n, int logn, int bits[3]) {
   const int half = n >> 1;
-  // w_n^e from the table of the first half: w_n^(e + n/2) = -w_n^e
   for (int i = threadIdx.x; i < (1 << kFftLoBits) + 64; i += blockDim.x) {
     const bool is_lo = i < (1 << kFftLoBits);
     const int e = is_lo ? i : (i - (1 << kFftLoBits)) << kFftLoBits;
@@ -171,31 +215,60 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 
   }
   __syncthreads();
   const int n_pass = (logn + 4) / 5;
-  int bits[3];
   for (int p = 0, left = logn; p < n_pass; ++p) {   // even split, smallest first
     bits[p] = left / (n_pass - p);
     left -= bits[p];
   }
-  const void* src = kRealIn ? (const void*)((const float*)in + row * n) : (const void*)((const float2*)in + row * n);
-  void* dst = kRealOut ? (void*)((float*)out + row * n) : (void*)((float2*)out + row * n);
-  constexpr int kIn = kRealIn ? kIoRealIn : kIoComplexIn;
-  constexpr int kOut = kRealOut ? kIoRealOut : kIoComplexOut;
-  // forward transform, mask and conjugate on the last write
+  return n_pass;
+}
+
+// The Hilbert transforms of the two rows of io (the multiplier -i sgn(k),
+// zero at k = 0 and n / 2): one complex transform of row 0 + i row 1, the
+// multiplier, and the inverse taken as a forward transform of the conjugate;
+// the last pass writes kOut.
+template <int kIn, int kOut>
+__device__ __forceinline__ void hilbert_pair(float2* x, const FftRows& io, int n, int n_pass, const int bits[3],
+                                             const float2* lo, const float2* hi) {
   int L = 1;
-  fft_pass_bits<kIn, kIoLds>(bits[0], x, src, nullptr, n, L, lo, hi);
+  fft_pass_bits<kIn, kIoLds>(bits[0], x, io, n, L, lo, hi);
   L <<= bits[0];
   if (n_pass == 3) {
-    fft_pass_bits<kIoLds, kIoLds>(bits[1], x, nullptr, nullptr, n, L, lo, hi);
+    fft_pass_bits<kIoLds, kIoLds>(bits[1], x, io, n, L, lo, hi);
     L <<= bits[1];
   }
-  fft_pass_bits<kIoLds, kIoLdsH>(bits[n_pass - 1], x, nullptr, nullptr, n, L, lo, hi);
-  // transform of the conjugate, conjugated and scaled on the way out
+  fft_pass_bits<kIoLds, kIoLdsQ>(bits[n_pass - 1], x, io, n, L, lo, hi);
   L = 1;
   for (int p = 0; p < n_pass - 1; ++p) {
-    fft_pass_bits<kIoLds, kIoLds>(bits[p], x, nullptr, nullptr, n, L, lo, hi);
+    fft_pass_bits<kIoLds, kIoLds>(bits[p], x, io, n, L, lo, hi);
     L <<= bits[p];
   }
-  fft_pass_bits<kIoLds, kOut>(bits[n_pass - 1], x, nullptr, dst, n, L, lo, hi);
+  // the last pass reads all of x before it writes (a barrier in between)
+  fft_pass_bits<kIoLds, kOut>(bits[n_pass - 1], x, io, n, L, lo, hi);
+}
+
+// Analytic-signal map along the rows, T = F^-1 diag(H) F with H = 1, 2..2,
+// 1, 0..0, written as A = x + i Hilbert(x) (H = 1 + sgn): the real part is
+// the row itself and the imaginary part its Hilbert transform, two rows per
+// block through one complex transform (the Hilbert transform is real, so it
+// maps row 0 + i row 1 to the two transforms). Adjoint (kAdjoint): the map
+// is real-linear from x to (Re A, Im A) and the Hilbert transform is
+// antisymmetric, so g_rf = Re(g_A) - Hilbert(Im g_A). Block b takes rows 2b
+// and 2b + 1 of n_rows.
+template <bool kAdjoint>
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_analytic(
+    const void* in, void* out, const float2* twiddle, int n, int logn, long n_rows) {
+  extern __shared__ float2 lds[];
+  float2* lo = lds;                          // w_n^i, i < 128
+  float2* hi = lds + (1 << kFftLoBits);       // w_n^(128 i), i < 64
+  float2* x = hi + 64;
+  int bits[3];
+  const int n_pass = fft_setup(lds, twiddle, n, logn, bits);
+  const long r0 = 2 * (long)blockIdx.x;
+  const FftRows io{kAdjoint ? (const void*)((const float2*)in + r0 * n) : (const void*)((const float*)in + r0 * n),
+                   kAdjoint ? (void*)((float*)out + r0 * n) : (void*)((float2*)out + r0 * n), (long)n,
+                   r0 + 1 < n_rows};
+  if (kAdjoint) hilbert_pair<kIoImagPairIn, kIoAdjointOut>(x, io, n, n_pass, bits, lo, hi);
+  else hilbert_pair<kIoRealPairIn, kIoAnalyticOut>(x, io, n, n_pass, bits, lo, hi);
 }
 
 template <int R>
@@ -207,65 +280,45 @@ __device__ __forceinline__ void fir_row(const float* rr, const float* c, int Tp,
   }
 }
 
+// Row stride of the fused pulse adjoint's two real rows in LDS: the row, M
+// zeros before it and Tp - M after it, rounded to four floats.
+__host__ __device__ __forceinline__ int fir_row_stride(int n, int Tp) { return (n + Tp + 3) & ~3; }
+
 // Adjoint of the pulse (Eq. axial_sig) after the adjoint of the analytic
-// map, per RF row: the transforms of k_analytic<false, true>, whose last pass
-// writes the row's real gradient Re(T g_A) into LDS (over the transform's
-// buffer, M zeros before it and Tp after it) instead of HBM, then the pulse
-// correlation of k_pulse from that row (taps c[q] = taps[2M - q], the same
-// fir_block sums), written as g_h. One HBM round trip of the row less than
-// the two kernels, and the same arithmetic in the same order.
-__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_analytic_pulse_adjoint(const float2* __restrict__ gA,
-                                                                        float* __restrict__ gh,
-                                                                        const float2* __restrict__ twiddle,
-                                                                        const float* __restrict__ taps, int M,
-                                                                        int n, int logn) {
+// map, for rows 2b and 2b + 1: the transforms of k_analytic<true>, whose last
+// pass writes the rows' real gradients into LDS (over the transform's
+// buffer, M zeros before each and Tp - M after) instead of HBM, then the
+// pulse correlation of k_pulse from each row (taps c[q] = taps[2M - q], the
+// same fir_block sums), written as g_h. One HBM round trip of the rows less
+// than the two kernels, and the same arithmetic in the same order.
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void k_analytic_pulse_adjoint(
+    const float2* __restrict__ gA, float* __restrict__ gh, const float2* __restrict__ twiddle,
+    const float* __restrict__ taps, int M, int n, int logn, long n_rows) {
   extern __shared__ float2 lds[];
   float2* lo = lds;
   float2* hi = lds + (1 << kFftLoBits);
   float2* x = hi + 64;
-  const long row = blockIdx.x;
-  const int half = n >> 1;
-  for (int i = threadIdx.x; i < (1 << kFftLoBits) + 64; i += blockDim.x) {
-    const bool is_lo = i < (1 << kFftLoBits);
-    const int e = is_lo ? i : (i - (1 << kFftLoBits)) << kFftLoBits;
-    float2 v = make_float2(1.0f, 0.0f);
-    if (e < n) {
-      v = twiddle[e < half ? e : e - half];
-      if (e >= half) v = make_float2(-v.x, -v.y);
-    }
-    lds[i] = v;
-  }
-  __syncthreads();
-  const int n_pass = (logn + 4) / 5;
   int bits[3];
-  for (int p = 0, left = logn; p < n_pass; ++p) {
-    bits[p] = left / (n_pass - p);
-    left -= bits[p];
+  const int n_pass = fft_setup(lds, twiddle, n, logn, bits);
+  const long r0 = 2 * (long)blockIdx.x;
+  const bool two = r0 + 1 < n_rows;
+  const int T = 2 * M + 1, Tp = fir_padded(M), stride = fir_row_stride(n, Tp);
+  float* rr = reinterpret_cast<float*>(x);   // rr[M + k], rr[stride + M + k]: sample k of the two rows
+  const FftRows io{gA + r0 * n, rr + M, (long)stride, two};
+  hilbert_pair<kIoImagPairIn, kIoAdjointOut>(x, io, n, n_pass, bits, lo, hi);
+  float* c = rr + 2 * stride;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    rr[j] = 0.0f;
+    rr[stride + j] = 0.0f;
   }
-  float* rr = reinterpret_cast<float*>(x);   // rr[M + k]: the real gradient of sample k
-  int L = 1;
-  fft_pass_bits<kIoComplexIn, kIoLds>(bits[0], x, gA + row * n, nullptr, n, L, lo, hi);
-  L <<= bits[0];
-  if (n_pass == 3) {
-    fft_pass_bits<kIoLds, kIoLds>(bits[1], x, nullptr, nullptr, n, L, lo, hi);
-    L <<= bits[1];
+  for (int j = M + n + threadIdx.x; j < n + Tp; j += blockDim.x) {
+    rr[j] = 0.0f;
+    rr[stride + j] = 0.0f;
   }
-  fft_pass_bits<kIoLds, kIoLdsH>(bits[n_pass - 1], x, nullptr, nullptr, n, L, lo, hi);
-  L = 1;
-  for (int p = 0; p < n_pass - 1; ++p) {
-    fft_pass_bits<kIoLds, kIoLds>(bits[p], x, nullptr, nullptr, n, L, lo, hi);
-    L <<= bits[p];
-  }
-  // the last pass reads all of x before it writes (a barrier in between)
-  fft_pass_bits<kIoLds, kIoRealOut>(bits[n_pass - 1], x, nullptr, rr + M, n, L, lo, hi);
-  const int T = 2 * M + 1, Tp = fir_padded(M);
-  float* c = rr + ((n + Tp + 3) & ~3);
-  for (int j = threadIdx.x; j < M; j += blockDim.x) rr[j] = 0.0f;
-  for (int j = M + n + threadIdx.x; j < n + Tp; j += blockDim.x) rr[j] = 0.0f;
   for (int j = threadIdx.x; j < Tp; j += blockDim.x) c[j] = j < T ? taps[2 * M - j] : 0.0f;
   __syncthreads();
-  float* out = gh + row * (long)n;
-  fir_row<kPulseR>(rr, c, Tp, n, out);
+  fir_row<kPulseR>(rr, c, Tp, n, gh + r0 * (long)n);
+  if (two) fir_row<kPulseR>(rr + stride, c, Tp, n, gh + (r0 + 1) * (long)n);
 }
 
 // Delay-and-sum, one pixel per thread, threads along z, reading the two
@@ -924,8 +977,8 @@ int launch_analytic(const float* rf, float2* A, const float2* twiddle, int n_t, 
   const int logn = log2_exact(n_t);
   if (logn < 6 || n_t > kMaxFft) return -1;
   const size_t lds = analytic_lds(n_t);
-  hipLaunchKernelGGL((k_analytic<true, false>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
-                     (const void*)rf, (void*)A, twiddle, n_t, logn);
+  hipLaunchKernelGGL(k_analytic<false>, dim3((unsigned)((n_rows + 1) / 2)), dim3(kFftThreads), lds, s,
+                     (const void*)rf, (void*)A, twiddle, n_t, logn, n_rows);
   return 0;
 }
 
@@ -934,8 +987,8 @@ int launch_analytic_adjoint(const float2* g_A, float* g_rf, const float2* twiddl
   const int logn = log2_exact(n_t);
   if (logn < 6 || n_t > kMaxFft) return -1;
   const size_t lds = analytic_lds(n_t);
-  hipLaunchKernelGGL((k_analytic<false, true>), dim3((unsigned)n_rows), dim3(kFftThreads), lds, s,
-                     (const void*)g_A, (void*)g_rf, twiddle, n_t, logn);
+  hipLaunchKernelGGL(k_analytic<true>, dim3((unsigned)((n_rows + 1) / 2)), dim3(kFftThreads), lds, s,
+                     (const void*)g_A, (void*)g_rf, twiddle, n_t, logn, n_rows);
   return 0;
 }
 
@@ -943,13 +996,13 @@ int launch_analytic_pulse_adjoint(const float2* g_A, float* g_h, const float2* t
                                   int M, int n_t, long n_rows, hipStream_t s) {
   const int logn = log2_exact(n_t);
   if (logn < 6 || n_t > kMaxFft || M < 0 || M > kMaxTaps - 1) return -1;
-  // the transform's buffer, or the padded real row and the taps after the twiddles
+  // the transform's buffer, or the two padded real rows and the taps after the twiddles
   const int Tp = fir_padded(M);
   const size_t fir = (size_t)((1 << kFftLoBits) + 64) * sizeof(float2) +
-                     (size_t)(((n_t + Tp + 3) & ~3) + Tp) * sizeof(float);
+                     (size_t)(2 * fir_row_stride(n_t, Tp) + Tp) * sizeof(float);
   const size_t lds = std::max(analytic_lds(n_t), fir);
-  hipLaunchKernelGGL(k_analytic_pulse_adjoint, dim3((unsigned)n_rows), dim3(kFftThreads), lds, s, g_A, g_h, twiddle,
-                     taps_reversed, M, n_t, logn);
+  hipLaunchKernelGGL(k_analytic_pulse_adjoint, dim3((unsigned)((n_rows + 1) / 2)), dim3(kFftThreads), lds, s, g_A,
+                     g_h, twiddle, taps_reversed, M, n_t, logn, n_rows);
   return 0;
 }
 
