@@ -448,15 +448,22 @@ def test_bmode_vjp_against_oracle(L, ctx):
     assert rel_l2(gc, ref) <= 1e-4
 
 
-@pytest.mark.parametrize("case", ["layered_3tx", "two_layer_40tx_ragged", "fine_grid_gather"])
+@pytest.mark.parametrize("case", ["layered_3tx", "two_layer_40tx_ragged", "fine_grid_gather", "odd_channel_count"])
 def test_beamform_vjp_against_oracle(L, ctx, case):
     """Transposed DAS + analytic VJP. The first two cases take the column
     kernel (pixels of a column more than two samples apart), the second with
     40 transmits on a ragged grid starting 2 mm below the array; the third,
-    with 0.03 mm pixels (under one sample apart), the per-sample gather."""
+    with 0.03 mm pixels (under one sample apart), the per-sample gather; the
+    fourth has 63 elements x 3 transmits, an odd number of channels, so the
+    analytic adjoint's last block transforms one channel alone."""
+    import dataclasses
     import torch
     rng = np.random.default_rng(1)
-    if case == "layered_3tx":
+    if case == "odd_channel_count":
+        base = W.two_layer()
+        wl = base.replace(probe=dataclasses.replace(base.probe, n_elem=63), angles=np.radians([-5.0, 0.0, 6.0]),
+                          tx_ids=np.arange(3, dtype=np.uint32))
+    elif case == "layered_3tx":
         wl = W.layered_phantom().replace(angles=np.radians([-10.0, 2.0, 10.0]),
                                          tx_ids=np.arange(3, dtype=np.uint32))
     elif case == "two_layer_40tx_ragged":

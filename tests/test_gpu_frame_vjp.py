@@ -78,6 +78,17 @@ def test_transform_sizes(L, ctx, n_t):
     chain_vs_fused(L, ctx, wl, target, f"two-layer, n_t = {n_t}")
 
 
+def test_odd_channel_count(L, ctx):
+    # 63 elements and one transmit: the analytic adjoint takes the channels two
+    # at a time and the last one alone, in the chain and in the fused kernel
+    import dataclasses
+    base = W.two_layer(rays_per_elem=1 << 9)
+    wl = W.tiny(base, rays_per_elem=1 << 9, n_elem=63)
+    depth = float(base.scene.planes[0])
+    target = dataclasses.replace(wl.scene, planes=np.array([1.01 * depth]))
+    chain_vs_fused(L, ctx, wl, target, "two-layer, 63 channels")
+
+
 def test_anatomy_phantom_ray_sample(L, ctx):
     wl = W.anatomy_phantom()
     chain_vs_fused(L, ctx, wl, W.anatomy_phantom_target(wl), "anatomy, 21 x 20000 rays",
